@@ -5,10 +5,17 @@ The list holds every non-excluded pair closer than r_nl = r_c + r_g
 Exceptions" paragraph). Because several lists are "correct" within rounding
 of r_nl, the inclusion test is pinned to one IEEE float32 expression:
 
-    d    = fl32(x_j - x_i)                      per dimension
-    d    = fl32(d - L) if d > L/2 ; fl32(d + L) if d < -L/2
+    s    = fl32(x_j - x_i)                                   per dimension
+    d    = s                        if -L/2 <= s <= L/2
+         = fl32(fl32(x_j - L) - x_i) if s > L/2
+         = fl32(x_j + fl32(L - x_i)) if s < -L/2
     r2   = fl32(fl32(fl32(dx*dx) + fl32(dy*dy)) + fl32(dz*dz))
     keep iff r2 < fl32(r_nl * r_nl),  r_nl = fl32(r_c + r_g)
+
+(The wrapped branches subtract the box from the coordinate that lies in the
+far half first, which is exact, so d is within half an ulp of the exact
+minimum-image displacement instead of half an ulp of L; the expression is
+antisymmetric in i, j, so the predicate is symmetric.)
 
 and a pair *interacts* iff it is listed and r2 < fl32(r_c * r_c) under the
 same expression. numpy float32 arithmetic is correctly rounded and never
@@ -35,8 +42,12 @@ def min_image_f32(xi, xj, L):
     """Per-dimension float32 minimum-image displacement x_j - x_i (one wrap)."""
     L = F32(L)
     hL = F32(L * F32(0.5))
-    d = (xj.astype(F32) - xi.astype(F32)).astype(F32)
-    d = np.where(d > hL, (d - L).astype(F32), np.where(d < -hL, (d + L).astype(F32), d))
+    xi = np.asarray(xi, F32)
+    xj = np.asarray(xj, F32)
+    s = (xj - xi).astype(F32)
+    up = ((xj - L).astype(F32) - xi).astype(F32)      # s > L/2
+    dn = (xj + (L - xi).astype(F32)).astype(F32)      # s < -L/2
+    d = np.where(s > hL, up, np.where(s < -hL, dn, s))
     return d.astype(F32)
 
 

@@ -101,3 +101,17 @@ def test_interaction_set_is_subset_with_rc():
     frac = m.mean()
     rnl = float(s.r_cut + s.r_ghost)
     assert abs(frac - (float(s.r_cut) / rnl) ** 3) < 0.08
+
+
+def test_min_image_f32_accurate_and_antisymmetric():
+    rng = np.random.default_rng(12)
+    L = np.float32(98.6)
+    xi = (rng.random(20000) * np.float64(L)).astype(np.float32)
+    xj = (rng.random(20000) * np.float64(L)).astype(np.float32)
+    d = neighbors.min_image_f32(xi, xj, L)
+    d_rev = neighbors.min_image_f32(xj, xi, L)
+    assert np.array_equal(d, -d_rev)
+    exact = xj.astype(np.float64) - xi.astype(np.float64)
+    exact = np.where(exact > L / 2, exact - np.float64(L), np.where(exact < -L / 2, exact + np.float64(L), exact))
+    err = np.abs(d.astype(np.float64) - exact)
+    assert np.all(err <= 0.5 * np.spacing(np.abs(d)) + 1e-30)
