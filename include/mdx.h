@@ -1,0 +1,246 @@
+/*
+ * mdx.h - C ABI of the MI355X (gfx950) force-evaluation library.
+ *
+ * The library evaluates the per-step forces of a periodic classical force
+ * field the way the DIMOS paper (arXiv 2503.20541) defines them:
+ *   - a cell-list Verlet neighbour list (Sec. II.A.2, "Neighborlists"),
+ *   - Lennard-Jones with Lorentz-Berthelot mixing (Eqs. 4-5, optional switch
+ *     Eq. 6) plus the real-space Ewald term (Eq. 10), exclusions removed at
+ *     list level ("Exclusions and Exceptions"), with the erf exclusion and
+ *     self (Eq. 12) corrections,
+ *   - harmonic bonds and angles (Eqs. 1-2),
+ *   - smooth particle-mesh Ewald for the reciprocal sum (Sec. II.A.2, PME
+ *     paragraph; Eq. 11 in its standard form),
+ *   - velocity Verlet (Sec. II.D.1).
+ *
+ * Conventions for every call:
+ *   - Return value: MDX_OK (0) or a negative MDX_E_* code; no call aborts or
+ *     throws across the ABI. mdx_error_string() names a code.
+ *   - "dev" pointers are device (HBM) addresses on the device that was
+ *     current at mdx_create; "host" pointers are host memory. The library
+ *     never frees or retains a caller pointer beyond the call.
+ *   - Per-atom vectors (positions, velocities, forces) are float32 structure
+ *     of arrays [3][N]: x[0..N), y[N..2N), z[2N..3N), in the caller's atom
+ *     order.
+ *   - Positions passed to any call must lie in [0, L_d) per dimension
+ *     (mdx_integrate_step keeps them there); a coordinate outside latches
+ *     MDX_FLAG_OUT_OF_BOX.
+ *   - Work is enqueued on the context's stream and is asynchronous unless a
+ *     call says "synchronising". A context is not thread-safe.
+ *   - Units are the caller's; the three unit constants in mdx_system_desc
+ *     tie them together.
+ */
+#ifndef MDX_H
+#define MDX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define MDX_OK                0
+#define MDX_E_INVALID        -1  /* bad argument or descriptor field          */
+#define MDX_E_BOX_TOO_SMALL  -2  /* r_c + r_g > L_d / 2: minimum image fails   */
+#define MDX_E_HIP            -3  /* a HIP runtime call failed                 */
+#define MDX_E_CAPACITY       -4  /* caller buffer too small (size reported)    */
+#define MDX_E_NO_LIST        -5  /* force call before mdx_build_neighbors     */
+#define MDX_E_NO_PME         -6  /* PME requested but no grid was configured  */
+#define MDX_E_OUT_OF_MEMORY  -7  /* device allocation failed                  */
+#define MDX_E_UNSUPPORTED    -8  /* option not implemented                    */
+
+/* ---- latched device flags (mdx_get_status) ----------------------------- */
+#define MDX_FLAG_NL_OVERFLOW  0x1u  /* an atom had more neighbours than capacity */
+#define MDX_FLAG_NL_STALE     0x2u  /* an atom moved > r_g/2 since the last build */
+#define MDX_FLAG_NONFINITE    0x4u  /* a non-finite energy was reduced            */
+#define MDX_FLAG_OUT_OF_BOX   0x8u  /* a coordinate outside [0, L)                */
+#define MDX_FLAG_CELL_OVERFLOW 0x10u /* a cell held more atoms than the sorter can */
+
+/* ---- energy slots (FP64) ----------------------------------------------- */
+#define MDX_ENERGY_LJ         0  /* Eq. 4 (switched by Eq. 6 if enabled)        */
+#define MDX_ENERGY_COUL_DIR   1  /* Eq. 10, minimum-image real-space term       */
+#define MDX_ENERGY_COUL_EXCL  2  /* -k_e q_i q_j erf(alpha r)/r, excluded pairs */
+#define MDX_ENERGY_COUL_SELF  3  /* Eq. 12 times k_e, + neutralising term       */
+#define MDX_ENERGY_BOND       4  /* Eq. 1                                       */
+#define MDX_ENERGY_ANGLE      5  /* Eq. 2                                       */
+#define MDX_ENERGY_COUL_REC   6  /* reciprocal sum by smooth PME                */
+#define MDX_ENERGY_KINETIC    7  /* sum m v^2 / (2 accel)                       */
+#define MDX_N_ENERGY          8
+
+typedef struct mdx_ctx mdx_ctx;
+
+/*
+ * System description (all pointers host, read during mdx_create only).
+ *
+ * Atoms: charge, mass, atom_type [n_atoms]; per-type LJ sigma/epsilon
+ * [n_types] (Lorentz-Berthelot mixing, Eq. 5). Topology index arrays use
+ * the caller's atom order: exclusions [n_exclusions][2] (any order,
+ * duplicates ignored), bonds [n_bonds][2] with bond_k, bond_r0, angles
+ * [n_angles][3] as (end, vertex, end) with angle_k, angle_theta0 (radians).
+ *
+ * r_cut: interaction cutoff r_c; r_ghost: Verlet skin r_g (the list holds
+ * pairs with r < r_c + r_g and stays valid until an atom moves > r_g / 2,
+ * Sec. II.A.2). ewald_alpha > 0 sets alpha directly; otherwise, if
+ * ewald_delta > 0, alpha = sqrt(-ln(2 delta)) / r_c (Eq. 13); if both are
+ * <= 0 there is no electrostatics. pme_grid {K_x, K_y, K_z} (0 = no PME,
+ * each in [4, 1024]); pme_order must be 4. switch_r in (0, r_c) enables
+ * the Eq. 6 switch on LJ; <= 0 is plain truncation.
+ *
+ * Units: coulomb_k = 1/(4 pi eps0); accel converts force/mass to
+ * acceleration (a = accel F / m); boltzmann is k_B (kinetic temperature).
+ *
+ * Tuning: cell_divisions m in [1, 4] (cells of edge >= (r_c + r_g)/m and a
+ * (2m+1)^3 stencil; 0 = 2); nl_capacity = neighbours per atom (0 = sized
+ * from the density with headroom); rebuild_every = steps between list
+ * rebuilds in mdx_integrate_step (0 = 10).
+ */
+typedef struct mdx_system_desc {
+  int32_t n_atoms;
+  float box[3];
+  const float* charge;
+  const float* mass;
+  const int32_t* atom_type;
+  int32_t n_types;
+  const float* type_sigma;
+  const float* type_epsilon;
+  int32_t n_exclusions;
+  const int32_t* exclusions;
+  int32_t n_bonds;
+  const int32_t* bonds;
+  const float* bond_k;
+  const float* bond_r0;
+  int32_t n_angles;
+  const int32_t* angles;
+  const float* angle_k;
+  const float* angle_theta0;
+  float r_cut;
+  float r_ghost;
+  float switch_r;
+  double ewald_delta;
+  double ewald_alpha;
+  int32_t pme_grid[3];
+  int32_t pme_order;
+  double coulomb_k;
+  double accel;
+  double boltzmann;
+  int32_t cell_divisions;
+  int32_t nl_capacity;
+  int32_t rebuild_every;
+  uint32_t reserved;
+} mdx_system_desc;
+
+/* Read-only facts about a context (mdx_get_info). */
+typedef struct mdx_info {
+  int32_t n_atoms;
+  int32_t cell_dims[3];      /* cells per dimension                       */
+  int32_t cell_divisions;
+  int32_t nl_capacity;       /* neighbours per atom the list can hold     */
+  int32_t pme_grid[3];
+  int32_t pme_brick[3];      /* grid points per PME brick                 */
+  double alpha;              /* Ewald splitting parameter in use          */
+  double r_list;             /* fl32(r_c + r_g)                           */
+  int64_t n_list_entries;    /* directed entries in the last built list   */
+  int64_t steps_taken;       /* steps integrated since creation           */
+} mdx_info;
+
+/* Names a status code; never NULL. */
+const char* mdx_error_string(int code);
+
+/*
+ * Creates a context on the current HIP device bound to `hip_stream`
+ * (a hipStream_t; NULL = the null stream). Copies what it needs from `d`
+ * and allocates all device scratch once. Errors: MDX_E_INVALID,
+ * MDX_E_BOX_TOO_SMALL (r_c + r_g > min L / 2), MDX_E_OUT_OF_MEMORY, MDX_E_HIP.
+ * On error *out is NULL.
+ */
+int mdx_create(mdx_ctx** out, const mdx_system_desc* d, void* hip_stream);
+
+/* Frees library-owned device memory; NULL is a no-op. Synchronises the stream. */
+int mdx_destroy(mdx_ctx* ctx);
+
+/* Rebinds the context to another stream (hipStream_t). */
+int mdx_set_stream(mdx_ctx* ctx, void* hip_stream);
+
+/*
+ * Builds the Verlet list (Sec. II.A.2, "Neighborlists") for dev positions
+ * pos[3][N]: bins atoms into cells, sorts them by cell (stable in atom
+ * index) and tests the (2m+1)^3 neighbouring cells of every atom with the
+ * float32 inclusion predicate
+ *     s = fl(x_j - x_i);  d = s, or fl(fl(x_j - L) - x_i) if s > L/2,
+ *     or fl(x_j + fl(L - x_i)) if s < -L/2   (per dimension);
+ *     r2 = fl(fl(fl(dx*dx) + fl(dy*dy)) + fl(dz*dz));  keep iff
+ *     r2 < fl(r_nl * r_nl), r_nl = fl(r_c + r_g), excluded pairs dropped.
+ * Also snapshots pos for the r_g/2 validity test. Synchronising only when
+ * the list overflowed: the capacity is then grown and the list rebuilt.
+ */
+int mdx_build_neighbors(mdx_ctx* ctx, const float* pos);
+
+/*
+ * Synchronising. Writes the current list as unique pairs (i, j), i < j, in
+ * caller atom indices, sorted lexicographically, into pairs_host[cap][2]
+ * and its length into *n. MDX_E_CAPACITY if cap < *n (*n still set).
+ */
+int mdx_get_neighbor_pairs(mdx_ctx* ctx, int32_t* pairs_host, int64_t cap, int64_t* n);
+
+/*
+ * Short-range forces at dev pos[3][N] from the current list: LJ + real-space
+ * Ewald over listed pairs with r2 < fl(r_c^2) (same float32 expression as
+ * the list), the erf exclusion correction (FP64), bonds and angles.
+ * force (dev [3][N]) is OVERWRITTEN. energy (dev double[6], slots
+ * MDX_ENERGY_LJ..MDX_ENERGY_ANGLE) may be NULL; with energy the variant with
+ * FP64 reductions runs. virial must be NULL (MDX_E_UNSUPPORTED otherwise).
+ * Latches MDX_FLAG_NL_STALE if an atom moved > r_g/2 since the build.
+ */
+int mdx_compute_nonbonded(mdx_ctx* ctx, const float* pos, float* force, double* energy,
+                          double* virial);
+
+/*
+ * Reciprocal-space forces by smooth PME at dev pos[3][N]: order-4 B-spline
+ * charge spreading onto the K_x x K_y x K_z grid, 3D FFT, multiplication by
+ * the influence function B(m) C(m), inverse FFT and force gather. force (dev
+ * [3][N]) is ACCUMULATED into. energy (dev double[1], MDX_ENERGY_COUL_REC)
+ * may be NULL. Needs a built list (atoms are processed in cell order).
+ * virial must be NULL.
+ */
+int mdx_compute_pme(mdx_ctx* ctx, const float* pos, float* force, double* energy,
+                    double* virial);
+
+/*
+ * Velocity Verlet (Sec. II.D.1) for n_steps >= 1 with step dt:
+ *   v += (dt/2) accel F/m;  x += dt v (wrapped into [0, L));  F = F(x);
+ *   v += (dt/2) accel F/m.
+ * pos, vel, force are dev [3][N] and are updated in place; force must hold
+ * F(pos) on entry (e.g. from mdx_compute_nonbonded + mdx_compute_pme) and
+ * holds F(pos) on exit. The list is rebuilt every rebuild_every steps and
+ * its validity (displacement < r_g/2) is tested every step. energies, if not
+ * NULL, is dev double[n_steps][MDX_N_ENERGY]: all slots after each step.
+ */
+int mdx_integrate_step(mdx_ctx* ctx, float* pos, float* vel, float* force, int32_t n_steps,
+                       float dt, double* energies);
+
+/* Synchronising. Returns the latched MDX_FLAG_* bits in *flags and clears them. */
+int mdx_get_status(mdx_ctx* ctx, uint32_t* flags);
+
+/* Fills *info (host). */
+int mdx_get_info(mdx_ctx* ctx, mdx_info* info);
+
+/* ---- diagnostics ---------------------------------------------------------
+ * Kernel timing with HIP events recorded on the context's stream around the
+ * launches of one kernel group. Groups: MDX_TIMING_PAIR (the short-range
+ * pair kernel), MDX_TIMING_PME (spread .. gather), MDX_TIMING_BUILD (list
+ * build). mdx_set_timing(ctx, 1) clears earlier records and starts
+ * recording (at most 8192 launches per group; later launches are not
+ * recorded); 0 stops. mdx_get_timing is synchronising and returns the mean
+ * duration in ms and the number of recorded launches. */
+#define MDX_TIMING_PAIR  0
+#define MDX_TIMING_PME   1
+#define MDX_TIMING_BUILD 2
+int mdx_set_timing(mdx_ctx* ctx, int enable);
+int mdx_get_timing(mdx_ctx* ctx, int group, double* mean_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MDX_H */

@@ -1,0 +1,183 @@
+// Internal declarations shared by the translation units of libmdx.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "mdx.h"
+
+namespace mdx {
+
+constexpr int kWave = 64;
+constexpr int kMaxStencil = 9;      // per-dimension stencil offsets (2m+1, m <= 4)
+constexpr int kMaxCellAtoms = 1024; // atoms one cell may hold (sort kernel limit)
+
+// Indices into the FP64 partial-sum rows written by force kernels.
+enum PartialRow { kRowLJ = 0, kRowDir, kRowExcl, kRowBond, kRowAngle, kRowRec, kRowKin, kRowCount };
+
+// Geometry of the cell grid and the float32 predicate constants.
+struct CellGrid {
+  int n[3];          // cells per dimension
+  int ncell;
+  float inv_w[3];    // n_d / L_d (float32, used only for binning)
+  float L[3];
+  float hL[3];
+  float rnl2;        // fl(r_nl * r_nl)
+  float rc2;         // fl(r_c * r_c)
+  int nofs[3];       // distinct stencil offsets per dimension
+  int ofs[3][kMaxStencil];
+};
+
+struct PmeGrid {
+  int K[3];
+  int Kxh;           // K_x / 2 + 1
+  int B[3];          // brick edge (grid points)
+  int nb[3];         // bricks per dimension
+  int nbrick;
+  float scale_hi[3]; // K_d / L_d as a float32 pair (hi + lo)
+  float scale_lo[3];
+  float disp_max;    // r_g / 2 plus margin: how far an atom may sit outside its cell
+};
+
+struct Ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int n = 0;              // atoms
+  int npad = 0;           // n rounded up to a wave multiple (ELL stride)
+  float box[3];
+  float r_cut, r_ghost, r_list, switch_r;
+  double alpha = 0.0;
+  double coulomb_k = 0.0, accel = 1.0, boltzmann = 1.0;
+  double e_self = 0.0;    // Eq. 12 + neutralising term (host FP64, fixed charges)
+  bool has_coulomb = false, has_pme = false, has_switch = false;
+  int n_types = 0, n_excl = 0, n_bonds = 0, n_angles = 0;
+  int cell_div = 2;
+  int nl_cap = 0;
+  int rebuild_every = 10;
+  int steps_since_build = -1;   // -1: no list
+  int64_t steps_taken = 0;
+  CellGrid cg{};
+  PmeGrid pg{};
+
+  // ---- per-atom parameters (caller order) ----
+  float* q = nullptr;          // charge
+  int* atype = nullptr;        // LJ type
+  float4* lj_f = nullptr;      // [T*T] (c12, c6, 12 c12, 6 c6), c_n = 4 eps sigma^n, FP32
+  double2* lj_d = nullptr;     // [T*T] (c12, c6) in FP64 for energies
+  float* hdt_scale = nullptr;  // accel / m_i  (times dt/2 at use)
+  float* mass = nullptr;
+  // exclusions per atom (CSR, caller order, both directions)
+  int* ex_start = nullptr;
+  int* ex_idx = nullptr;
+  // bonded terms and per-atom term lists (CSR)
+  int* bonds = nullptr;  float* bond_k = nullptr;  float* bond_r0 = nullptr;
+  int* angles = nullptr; float* angle_k = nullptr; float* angle_t0 = nullptr;
+  int* bt_start = nullptr; int* bt_idx = nullptr;   // bond ids per atom
+  int* at_start = nullptr; int* at_idx = nullptr;   // angle ids per atom
+
+  // ---- cell list / sorted order ----
+  int* cell_of = nullptr;      // [n] cell of each caller atom at build
+  int* cell_count = nullptr;   // [ncell]
+  int* cell_start = nullptr;   // [ncell + 1]
+  int* cell_cursor = nullptr;  // [ncell]
+  int* perm_unsorted = nullptr;// [n]
+  int* perm = nullptr;         // [n] sorted slot -> caller atom
+  int* inv_perm = nullptr;     // [n] caller atom -> sorted slot
+  int* cell_sorted = nullptr;  // [n] cell of each sorted slot
+  float4* xs = nullptr;        // [n] sorted (x, y, z, q) at the current positions
+  int* ts = nullptr;           // [n] sorted LJ type
+  float* x_build = nullptr;    // [3][n] positions at the last build (caller order)
+  int* nl_count = nullptr;     // [n] entries per sorted atom
+  int* nl = nullptr;           // [nl_cap][npad] ELL, column-major, sorted indices
+  int* nl_needed = nullptr;    // [1] max neighbours seen by the last build
+  unsigned* flags = nullptr;   // [1] latched MDX_FLAG_*
+  int* gate = nullptr;         // [1] rebuild request inside mdx_integrate_step
+
+  // ---- PME ----
+  float* grid_q = nullptr;     // [Kz][Ky][Kx] real
+  float2* grid_c = nullptr;    // [Kz][Ky][Kxh] complex
+  float* grid_phi = nullptr;   // [Kz][Ky][Kx]
+  float2* tw[3] = {nullptr, nullptr, nullptr};  // twiddles exp(-2 pi i k/K_d)
+  double* bmod[3] = {nullptr, nullptr, nullptr}; // |b_d(m)|^2
+  double* mrec[3] = {nullptr, nullptr, nullptr}; // m'_d / L_d
+  double pme_energy_scale = 0.0;                 // 1 / (pi V)
+  int* brick_cells = nullptr;  // per brick and dim: first cell and count (6 ints)
+
+  // ---- reductions ----
+  double* partials = nullptr;  // [kRowCount][max_blocks]
+  int max_blocks = 0;
+  double* energy_scratch = nullptr;   // [MDX_N_ENERGY]
+  float* force_scratch = nullptr;     // [3][n] forces inside integrate_step
+  int nb_blocks = 0;                  // blocks used by the last nonbonded launch
+  int pme_blocks = 0;
+};
+
+// ---- launchers (each returns hipError_t of the launch) ----
+hipError_t launch_fill_i32(int* p, int v, int count, hipStream_t s);
+// gate == nullptr: unconditional build; otherwise every build kernel returns
+// at once unless *gate != 0.
+hipError_t launch_build_list(Ctx& c, const float* pos, const int* gate = nullptr);
+// Copies pos into the sorted array and tests the r_g/2 validity rule. With
+// gate == nullptr a violation latches MDX_FLAG_NL_STALE; otherwise it sets
+// *gate (and force_rebuild sets it unconditionally).
+hipError_t launch_refresh_sorted(Ctx& c, const float* pos, int* gate = nullptr,
+                                 bool force_rebuild = false);
+hipError_t launch_nonbonded(Ctx& c, float* force, bool energy);
+hipError_t launch_bonded_excl(Ctx& c, const float* pos, float* force, bool energy);
+// Sums the FP64 partial rows into out[slot - slot_base] (slots MDX_ENERGY_*);
+// const_slot >= 0 also stores const_val there, zero_slot >= 0 stores 0.
+hipError_t launch_reduce_energy(Ctx& c, const int* rows, const int* nblk, int nrows, double* out,
+                                int slot_base, double const_val, int const_slot,
+                                int zero_slot = -1);
+bool pme_size_supported(int K);
+hipError_t launch_pme(Ctx& c, float* force, bool energy);
+// Also clears *gate (if not null) for the step that follows.
+hipError_t launch_kick_drift(Ctx& c, float* pos, float* vel, const float* force, float dt,
+                             int* gate = nullptr);
+hipError_t launch_kick(Ctx& c, float* vel, const float* force, float dt, bool energy);
+hipError_t launch_copy_f32(float* dst, const float* src, int count, hipStream_t s);
+
+// Device helpers shared by kernels -------------------------------------------
+
+// Accurate float32 minimum-image displacement x_j - x_i (see mdx.h); the
+// operations are not contracted so the result is the specified expression.
+__device__ __forceinline__ float min_image(float xi, float xj, float L, float hL) {
+#pragma clang fp contract(off)
+  float s = xj - xi;
+  float up = (xj - L) - xi;
+  float dn = xj + (L - xi);
+  return s > hL ? up : (s < -hL ? dn : s);
+}
+
+__device__ __forceinline__ float dist2(float dx, float dy, float dz) {
+#pragma clang fp contract(off)
+  float a = dx * dx;
+  float b = dy * dy;
+  float c = dz * dz;
+  return (a + b) + c;
+}
+
+// Wave-level sum of a double (all 64 lanes participate).
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Block-level deterministic FP64 sum (blockDim.x multiple of 64, <= 1024).
+__device__ __forceinline__ double block_sum(double v, double* lds) {
+  v = wave_sum(v);
+  int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  if (lane == 0) lds[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+    int nw = blockDim.x / kWave;
+    for (int i = 0; i < nw; ++i) r += lds[i];
+  }
+  __syncthreads();
+  return r;
+}
+
+}  // namespace mdx

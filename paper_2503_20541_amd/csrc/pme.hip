@@ -1,0 +1,513 @@
+// Smooth particle-mesh Ewald (DIMOS Sec. II.A.2, PME paragraph).
+//
+//  k_pme_spread   one workgroup per grid brick; candidate atoms come from the
+//                 cell list (cells within spline reach + r_g/2 of the brick).
+//                 Lanes first compute one atom's B-spline weights each, then
+//                 the wave walks the atoms one by one with lanes = the 4x4x4
+//                 stencil points, adding into its own LDS copy of the brick
+//                 (distinct addresses per instruction). Copies are summed in
+//                 a fixed order: atomic-free and deterministic.
+//  k_fft_rows_*   x-direction real<->half-complex transforms, P rows per block
+//  k_fft_cols     y (forward / inverse) and z (forward, influence multiply
+//                 with the FP64 energy partial, inverse) pencils
+//  k_pme_gather   one thread per atom: F = -k_e q sum grad(theta) phi
+//
+// The 1D transforms are radix-2/3/4/5/7 Stockham FFTs in LDS with a twiddle
+// table exp(-2 pi i k/N) computed on the host in double precision.
+#include "mdx_internal.h"
+
+namespace mdx {
+
+struct FftPlan {
+  int N;
+  int nst;
+  int radix[16];
+};
+
+struct PmeParams {
+  int K[3];
+  int Kxh;
+  int B[3];
+  int nb[3];
+  float s_hi[3], s_lo[3];   // K_d / L_d = s_hi + s_lo
+  float coulomb_k;
+  double exp_fac;           // pi^2 / alpha^2
+  double inv_piV;           // 1 / (pi V)
+};
+
+// Cubic B-spline weights M_4(f + t), t = 0..3, for fractional part f, and
+// their derivatives with respect to u (uniform cubic basis written out).
+__device__ __forceinline__ void spline4(float f, float th[4], float dth[4]) {
+  float g = 1.0f - f;
+  float f2 = f * f, f3 = f2 * f;
+  const float s = 1.0f / 6.0f;
+  th[0] = f3 * s;
+  th[1] = (1.0f + 3.0f * f + 3.0f * f2 - 3.0f * f3) * s;
+  th[2] = (4.0f - 6.0f * f2 + 3.0f * f3) * s;
+  th[3] = g * g * g * s;
+  dth[0] = 0.5f * f2;
+  dth[1] = 0.5f * (1.0f + 2.0f * f - 3.0f * f2);
+  dth[2] = 0.5f * (-4.0f * f + 3.0f * f2);
+  dth[3] = -0.5f * g * g;
+}
+
+// u = x K/L split into integer base k0 in [0, K) and fraction f in [0, 1),
+// with the scale carried as a float pair so f is accurate to ~1 ulp.
+__device__ __forceinline__ void grid_coord(float x, float s_hi, float s_lo, int K, int& k0,
+                                           float& f) {
+  float u = x * s_hi;
+  float kf = floorf(u);
+  f = fmaf(x, s_hi, -kf) + x * s_lo;
+  int k = (int)kf;
+  if (f < 0.f) { f += 1.0f; --k; }
+  if (f >= 1.0f) { f -= 1.0f; ++k; }
+  if (f < 0.f) f = 0.f;
+  k %= K;
+  if (k < 0) k += K;
+  k0 = k;
+}
+
+constexpr int kSpreadThreads = 256;
+constexpr int kSpreadWaves = kSpreadThreads / kWave;
+constexpr int kMaxBrick = 512;       // B_x * B_y * B_z
+constexpr int kMaxCandCells = 512;
+constexpr int kStage = 16;           // floats staged per atom
+
+__global__ void __launch_bounds__(kSpreadThreads) k_pme_spread(
+    const float4* __restrict__ xs, const int* __restrict__ cell_start,
+    const int* __restrict__ brick_cells, PmeParams pp, CellGrid cg, float* __restrict__ grid_q) {
+  __shared__ float lgrid[kSpreadWaves][kMaxBrick];
+  __shared__ float stage[kSpreadWaves][kWave * kStage];
+  __shared__ int cand_start[kMaxCandCells];
+  __shared__ int cand_off[kMaxCandCells + 1];
+
+  const int brick = blockIdx.x;
+  const int bx = brick % pp.nb[0], by = (brick / pp.nb[0]) % pp.nb[1],
+            bz = brick / (pp.nb[0] * pp.nb[1]);
+  const int g0[3] = {bx * pp.B[0], by * pp.B[1], bz * pp.B[2]};
+  int beff[3];
+  for (int d = 0; d < 3; ++d) beff[d] = min(pp.B[d], pp.K[d] - g0[d]);
+  // candidate cells: per dimension (first, count) from the host table
+  const int* bcx = brick_cells + 2 * bx;
+  const int* bcy = brick_cells + 2 * pp.nb[0] + 2 * by;
+  const int* bcz = brick_cells + 2 * (pp.nb[0] + pp.nb[1]) + 2 * bz;
+  const int ncx = bcx[1], ncy = bcy[1], ncz = bcz[1];
+  const int ncand = ncx * ncy * ncz;
+
+  for (int t = threadIdx.x; t < kSpreadWaves * kMaxBrick; t += blockDim.x)
+    (&lgrid[0][0])[t] = 0.f;
+  for (int t = threadIdx.x; t < ncand; t += blockDim.x) {
+    int ix = t % ncx, iy = (t / ncx) % ncy, iz = t / (ncx * ncy);
+    int cx = (bcx[0] + ix) % cg.n[0], cy = (bcy[0] + iy) % cg.n[1],
+        cz = (bcz[0] + iz) % cg.n[2];
+    int c = (cz * cg.n[1] + cy) * cg.n[0] + cx;
+    cand_start[t] = cell_start[c];
+    cand_off[t + 1] = cell_start[c + 1] - cell_start[c];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    cand_off[0] = 0;
+    for (int t = 0; t < ncand; ++t) {
+      acc += cand_off[t + 1];
+      cand_off[t + 1] = acc;
+    }
+  }
+  __syncthreads();
+  const int total = cand_off[ncand];
+  const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int t1 = lane >> 4, t2 = (lane >> 2) & 3, t3 = lane & 3;   // x, y, z stencil offsets
+  float* my_grid = lgrid[w];
+  float* my_stage = stage[w];
+
+  for (int ch = w; ch * kWave < total; ch += kSpreadWaves) {
+    int f = ch * kWave + lane;
+    bool touch = false;
+    if (f < total) {
+      int lo = 0, hi = ncand - 1;             // last cell with cand_off <= f
+      while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (cand_off[mid] <= f) lo = mid; else hi = mid - 1;
+      }
+      int j = cand_start[lo] + (f - cand_off[lo]);
+      float4 p = xs[j];
+      float xyz[3] = {p.x, p.y, p.z};
+      touch = true;
+      float* st = my_stage + lane * kStage;
+      for (int d = 0; d < 3; ++d) {
+        int k0;
+        float fr;
+        grid_coord(xyz[d], pp.s_hi[d], pp.s_lo[d], pp.K[d], k0, fr);
+        int delta = k0 - g0[d];
+        if (delta < 0) delta += pp.K[d];
+        touch = touch && (delta <= beff[d] + 2 || beff[d] + 3 > pp.K[d]);
+        float th[4], dth[4];
+        spline4(fr, th, dth);
+        st[4 * d + 0] = th[0];
+        st[4 * d + 1] = th[1];
+        st[4 * d + 2] = th[2];
+        st[4 * d + 3] = th[3];
+        st[12 + d] = __int_as_float(delta);
+      }
+      st[15] = p.w;
+    }
+    unsigned long long mask = __ballot(touch);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    while (mask) {
+      int m = __ffsll((long long)mask) - 1;
+      mask &= mask - 1;
+      const float* st = my_stage + m * kStage;
+      int lx = __float_as_int(st[12]) - t1;
+      int ly = __float_as_int(st[13]) - t2;
+      int lz = __float_as_int(st[14]) - t3;
+      if (lx < 0) lx += pp.K[0];
+      if (ly < 0) ly += pp.K[1];
+      if (lz < 0) lz += pp.K[2];
+      if (lx < beff[0] && ly < beff[1] && lz < beff[2]) {
+        float v = st[15] * st[t1] * st[4 + t2] * st[8 + t3];
+        atomicAdd(&my_grid[(lz * pp.B[1] + ly) * pp.B[0] + lx], v);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  __syncthreads();
+  const int nloc = beff[0] * beff[1] * beff[2];
+  for (int t = threadIdx.x; t < nloc; t += blockDim.x) {
+    int lx = t % beff[0], ly = (t / beff[0]) % beff[1], lz = t / (beff[0] * beff[1]);
+    int li = (lz * pp.B[1] + ly) * pp.B[0] + lx;
+    float s = lgrid[0][li];
+    for (int c = 1; c < kSpreadWaves; ++c) s += lgrid[c][li];
+    grid_q[((size_t)(g0[2] + lz) * pp.K[1] + (g0[1] + ly)) * pp.K[0] + g0[0] + lx] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// LDS FFT
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Twiddle exp(SIGN * 2 pi i m / N) from the forward table exp(-2 pi i m / N).
+template <int SIGN>
+__device__ __forceinline__ float2 twid(const float2* tw, int m) {
+  float2 t = tw[m];
+  if (SIGN > 0) t.y = -t.y;
+  return t;
+}
+
+template <int SIGN>
+__device__ __forceinline__ void dft_small(float2* v, int R, int N, const float2* tw) {
+  if (R == 2) {
+    float2 a = v[0], b = v[1];
+    v[0] = make_float2(a.x + b.x, a.y + b.y);
+    v[1] = make_float2(a.x - b.x, a.y - b.y);
+  } else if (R == 4) {
+    float2 a = v[0], b = v[1], c = v[2], d = v[3];
+    float2 s0 = make_float2(a.x + c.x, a.y + c.y), s1 = make_float2(a.x - c.x, a.y - c.y);
+    float2 s2 = make_float2(b.x + d.x, b.y + d.y), s3 = make_float2(b.x - d.x, b.y - d.y);
+    // SIGN * i * s3
+    float2 is3 = SIGN > 0 ? make_float2(-s3.y, s3.x) : make_float2(s3.y, -s3.x);
+    v[0] = make_float2(s0.x + s2.x, s0.y + s2.y);
+    v[2] = make_float2(s0.x - s2.x, s0.y - s2.y);
+    v[1] = make_float2(s1.x + is3.x, s1.y + is3.y);
+    v[3] = make_float2(s1.x - is3.x, s1.y - is3.y);
+  } else {
+    float2 in[7];
+    for (int r = 0; r < R; ++r) in[r] = v[r];
+    const int step = N / R;
+    for (int k = 0; k < R; ++k) {
+      float2 acc = in[0];
+      for (int r = 1; r < R; ++r) {
+        float2 wv = twid<SIGN>(tw, ((r * k) % R) * step);
+        float2 p = cmul(in[r], wv);
+        acc.x += p.x;
+        acc.y += p.y;
+      }
+      v[k] = acc;
+    }
+  }
+}
+
+// P pencils of length N stored [p][N] in a; b is scratch. Returns the buffer
+// holding the (unnormalised) transform. All threads of the block take part.
+template <int SIGN>
+__device__ float2* fft_lds(float2* a, float2* b, int P, const FftPlan& pl, const float2* tw) {
+  const int N = pl.N;
+  int Ns = 1;
+  for (int s = 0; s < pl.nst; ++s) {
+    const int R = pl.radix[s];
+    const int NR = N / R;
+    const int tstride = N / (Ns * R);
+    for (int idx = threadIdx.x; idx < P * NR; idx += blockDim.x) {
+      int p = idx / NR, j = idx - p * NR;
+      int k = j % Ns;
+      const float2* in = a + p * N;
+      float2* out = b + p * N;
+      float2 v[7];
+      v[0] = in[j];
+      for (int r = 1; r < R; ++r) v[r] = cmul(in[j + r * NR], twid<SIGN>(tw, k * r * tstride));
+      dft_small<SIGN>(v, R, N, tw);
+      int base = (j / Ns) * Ns * R + k;
+      for (int r = 0; r < R; ++r) out[base + r * Ns] = v[r];
+    }
+    __syncthreads();
+    float2* t = a;
+    a = b;
+    b = t;
+    Ns *= R;
+  }
+  return a;
+}
+
+// x-direction forward: real rows [Kz*Ky][Kx] -> half spectrum [Kz*Ky][Kxh].
+__global__ void __launch_bounds__(256) k_fft_rows_r2c(const float* __restrict__ in,
+                                                      float2* __restrict__ out, int nrows,
+                                                      int P, int Kxh, FftPlan pl,
+                                                      const float2* __restrict__ twg) {
+  extern __shared__ float2 sm[];
+  const int N = pl.N;
+  float2* tw = sm;
+  float2* a = sm + N;
+  float2* b = a + P * N;
+  for (int t = threadIdx.x; t < N; t += blockDim.x) tw[t] = twg[t];
+  const int r0 = blockIdx.x * P;
+  for (int idx = threadIdx.x; idx < P * N; idx += blockDim.x) {
+    int p = idx / N, x = idx - p * N;
+    a[idx] = (r0 + p < nrows) ? make_float2(in[(size_t)(r0 + p) * N + x], 0.f)
+                              : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  float2* res = fft_lds<-1>(a, b, P, pl, tw);
+  for (int idx = threadIdx.x; idx < P * Kxh; idx += blockDim.x) {
+    int p = idx / Kxh, k = idx - p * Kxh;
+    if (r0 + p < nrows) out[(size_t)(r0 + p) * Kxh + k] = res[p * N + k];
+  }
+}
+
+// x-direction inverse: half spectrum -> real rows (Hermitian completion).
+__global__ void __launch_bounds__(256) k_fft_rows_c2r(const float2* __restrict__ in,
+                                                      float* __restrict__ out, int nrows,
+                                                      int P, int Kxh, FftPlan pl,
+                                                      const float2* __restrict__ twg) {
+  extern __shared__ float2 sm[];
+  const int N = pl.N;
+  float2* tw = sm;
+  float2* a = sm + N;
+  float2* b = a + P * N;
+  for (int t = threadIdx.x; t < N; t += blockDim.x) tw[t] = twg[t];
+  const int r0 = blockIdx.x * P;
+  for (int idx = threadIdx.x; idx < P * N; idx += blockDim.x) {
+    int p = idx / N, k = idx - p * N;
+    float2 v = make_float2(0.f, 0.f);
+    if (r0 + p < nrows) {
+      if (k < Kxh) {
+        v = in[(size_t)(r0 + p) * Kxh + k];
+      } else {
+        v = in[(size_t)(r0 + p) * Kxh + (N - k)];
+        v.y = -v.y;
+      }
+    }
+    a[idx] = v;
+  }
+  __syncthreads();
+  float2* res = fft_lds<+1>(a, b, P, pl, tw);
+  for (int idx = threadIdx.x; idx < P * N; idx += blockDim.x) {
+    int p = idx / N, x = idx - p * N;
+    if (r0 + p < nrows) out[(size_t)(r0 + p) * N + x] = res[idx].x;
+  }
+}
+
+// Column pencils of the half spectrum. MODE 0: y forward, 1: y inverse,
+// 2: z forward, influence multiply + energy partial, z inverse.
+template <int MODE>
+__global__ void __launch_bounds__(256) k_fft_cols(float2* __restrict__ grid, PmeParams pp,
+                                                  int P, FftPlan pl,
+                                                  const float2* __restrict__ twg,
+                                                  const double* __restrict__ bmx,
+                                                  const double* __restrict__ bmy,
+                                                  const double* __restrict__ bmz,
+                                                  const double* __restrict__ mx,
+                                                  const double* __restrict__ my,
+                                                  const double* __restrict__ mz,
+                                                  double* __restrict__ partials, int pstride) {
+  extern __shared__ float2 sm[];
+  __shared__ double red[16];
+  const int N = pl.N;
+  float2* tw = sm;
+  float2* a = sm + N;
+  float2* b = a + P * N;
+  for (int t = threadIdx.x; t < N; t += blockDim.x) tw[t] = twg[t];
+  const int Kxh = pp.Kxh;
+  const int ntile = (Kxh + P - 1) / P;
+  const int outer = blockIdx.x / ntile;       // z for the y pass, ky for the z pass
+  const int kx0 = (blockIdx.x - outer * ntile) * P;
+  size_t base, stride;
+  if (MODE == 2) {
+    base = (size_t)outer * Kxh;
+    stride = (size_t)pp.K[1] * Kxh;
+  } else {
+    base = (size_t)outer * pp.K[1] * Kxh;
+    stride = Kxh;
+  }
+  for (int idx = threadIdx.x; idx < P * N; idx += blockDim.x) {
+    int i = idx / P, p = idx - i * P;
+    int kx = kx0 + p;
+    a[p * N + i] = kx < Kxh ? grid[base + i * stride + kx] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  float2* res;
+  if (MODE == 1) {
+    res = fft_lds<+1>(a, b, P, pl, tw);
+  } else {
+    res = fft_lds<-1>(a, b, P, pl, tw);
+  }
+  if (MODE == 2) {
+    // influence function G = B(m) C(m) on the half spectrum. G is formed in
+    // FP64 (its float32 value scales Q^; the FP64 value, without the
+    // constant 1/(pi V) applied in the reduction, weights |Q^|^2 for E_rec).
+    double e = 0.0;
+    const int ky = outer;
+    for (int idx = threadIdx.x; idx < P * N; idx += blockDim.x) {
+      int p = idx / N, kz = idx - p * N;
+      int kx = kx0 + p;
+      float2 v = res[idx];
+      float g = 0.f;
+      if (kx < Kxh) {
+        double msq = mx[kx] * mx[kx] + my[ky] * my[ky] + mz[kz] * mz[kz];
+        if (msq > 0.0) {
+          double gd = bmx[kx] * bmy[ky] * bmz[kz] * exp(-pp.exp_fac * msq) / msq;
+          int wgt = (kx == 0 || (2 * kx == pp.K[0])) ? 1 : 2;
+          e += (double)wgt * gd * ((double)v.x * v.x + (double)v.y * v.y);
+          g = (float)(gd * pp.inv_piV);
+        }
+      }
+      res[idx] = make_float2(v.x * g, v.y * g);
+    }
+    double s = block_sum(e, red);
+    if (threadIdx.x == 0) partials[kRowRec * pstride + blockIdx.x] = s;
+    __syncthreads();
+    float2* other = (res == a) ? b : a;
+    res = fft_lds<+1>(res, other, P, pl, tw);
+  }
+  for (int idx = threadIdx.x; idx < P * N; idx += blockDim.x) {
+    int i = idx / P, p = idx - i * P;
+    int kx = kx0 + p;
+    if (kx < Kxh) grid[base + i * stride + kx] = res[p * N + i];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_pme_gather(const float4* __restrict__ xs,
+                                                    const int* __restrict__ perm,
+                                                    const float* __restrict__ phi, int n,
+                                                    PmeParams pp, float* __restrict__ force) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  float4 p = xs[s];
+  float xyz[3] = {p.x, p.y, p.z};
+  int k0[3];
+  float th[3][4], dth[3][4];
+  for (int d = 0; d < 3; ++d) {
+    float fr;
+    grid_coord(xyz[d], pp.s_hi[d], pp.s_lo[d], pp.K[d], k0[d], fr);
+    spline4(fr, th[d], dth[d]);
+  }
+  float gx = 0.f, gy = 0.f, gz = 0.f;
+  for (int t3 = 0; t3 < 4; ++t3) {
+    int z = k0[2] - t3;
+    z += z < 0 ? pp.K[2] : 0;
+    for (int t2 = 0; t2 < 4; ++t2) {
+      int y = k0[1] - t2;
+      y += y < 0 ? pp.K[1] : 0;
+      const float* rowp = phi + ((size_t)z * pp.K[1] + y) * pp.K[0];
+      float ayz = th[1][t2] * th[2][t3];
+      float dyz = dth[1][t2] * th[2][t3];
+      float ydz = th[1][t2] * dth[2][t3];
+      for (int t1 = 0; t1 < 4; ++t1) {
+        int x = k0[0] - t1;
+        x += x < 0 ? pp.K[0] : 0;
+        float v = rowp[x];
+        gx += dth[0][t1] * ayz * v;
+        gy += th[0][t1] * dyz * v;
+        gz += th[0][t1] * ydz * v;
+      }
+    }
+  }
+  float c = -pp.coulomb_k * p.w;
+  int a = perm[s];
+  force[a] += c * gx * (pp.s_hi[0] + pp.s_lo[0]);
+  force[n + a] += c * gy * (pp.s_hi[1] + pp.s_lo[1]);
+  force[2 * n + a] += c * gz * (pp.s_hi[2] + pp.s_lo[2]);
+}
+
+// ---------------------------------------------------------------------------
+static FftPlan make_plan(int N) {
+  FftPlan p{};
+  p.N = N;
+  int m = N;
+  while (m % 4 == 0 && p.nst < 16) { p.radix[p.nst++] = 4; m /= 4; }
+  const int primes[4] = {2, 3, 5, 7};
+  for (int r : primes)
+    while (m % r == 0 && p.nst < 16) { p.radix[p.nst++] = r; m /= r; }
+  if (m != 1) p.nst = -1;
+  return p;
+}
+
+bool pme_size_supported(int K) { return K >= 4 && K <= 1024 && make_plan(K).nst > 0; }
+
+static int pencils_for(int N) {
+  int P = 2048 / N;
+  if (P > 32) P = 32;
+  if (P < 1) P = 1;
+  return P;
+}
+
+hipError_t launch_pme(Ctx& c, float* force, bool energy) {
+  (void)energy;   // the z pass always writes its energy partials
+  const PmeGrid& g = c.pg;
+  PmeParams pp;
+  for (int d = 0; d < 3; ++d) {
+    pp.K[d] = g.K[d];
+    pp.B[d] = g.B[d];
+    pp.nb[d] = g.nb[d];
+    pp.s_hi[d] = g.scale_hi[d];
+    pp.s_lo[d] = g.scale_lo[d];
+  }
+  pp.Kxh = g.Kxh;
+  pp.coulomb_k = (float)c.coulomb_k;
+  pp.exp_fac = M_PI * M_PI / (c.alpha * c.alpha);
+  pp.inv_piV = c.pme_energy_scale;
+  hipStream_t s = c.stream;
+  k_pme_spread<<<g.nbrick, kSpreadThreads, 0, s>>>(c.xs, c.cell_start, c.brick_cells, pp, c.cg,
+                                                   c.grid_q);
+  FftPlan px = make_plan(g.K[0]), py = make_plan(g.K[1]), pz = make_plan(g.K[2]);
+  const int rows = g.K[1] * g.K[2];
+  int P = pencils_for(g.K[0]);
+  size_t sh = (size_t)(g.K[0] + 2 * P * g.K[0]) * sizeof(float2);
+  k_fft_rows_r2c<<<(rows + P - 1) / P, 256, sh, s>>>(c.grid_q, c.grid_c, rows, P, g.Kxh, px,
+                                                     c.tw[0]);
+  const int Pc = 16;
+  const int ntile = (g.Kxh + Pc - 1) / Pc;
+  size_t shy = (size_t)(g.K[1] + 2 * Pc * g.K[1]) * sizeof(float2);
+  size_t shz = (size_t)(g.K[2] + 2 * Pc * g.K[2]) * sizeof(float2);
+  k_fft_cols<0><<<g.K[2] * ntile, 256, shy, s>>>(c.grid_c, pp, Pc, py, c.tw[1], c.bmod[0],
+                                                 c.bmod[1], c.bmod[2], c.mrec[0], c.mrec[1],
+                                                 c.mrec[2], c.partials, c.max_blocks);
+  k_fft_cols<2><<<g.K[1] * ntile, 256, shz, s>>>(c.grid_c, pp, Pc, pz, c.tw[2], c.bmod[0],
+                                                 c.bmod[1], c.bmod[2], c.mrec[0], c.mrec[1],
+                                                 c.mrec[2], c.partials, c.max_blocks);
+  c.pme_blocks = g.K[1] * ntile;
+  k_fft_cols<1><<<g.K[2] * ntile, 256, shy, s>>>(c.grid_c, pp, Pc, py, c.tw[1], c.bmod[0],
+                                                 c.bmod[1], c.bmod[2], c.mrec[0], c.mrec[1],
+                                                 c.mrec[2], c.partials, c.max_blocks);
+  k_fft_rows_c2r<<<(rows + P - 1) / P, 256, sh, s>>>(c.grid_c, c.grid_phi, rows, P, g.Kxh, px,
+                                                     c.tw[0]);
+  k_pme_gather<<<(c.n + 255) / 256, 256, 0, s>>>(c.xs, c.perm, c.grid_phi, c.n, pp, force);
+  return hipGetLastError();
+}
+
+}  // namespace mdx

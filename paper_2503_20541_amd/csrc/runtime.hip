@@ -1,0 +1,653 @@
+// Host runtime and C ABI (mdx.h): descriptor validation, one-time device
+// allocation, the cell/PME geometry, and the call sequences of each entry
+// point. Everything computed per step runs in the kernels of nl.hip,
+// nonbonded.hip, pme.hip and integrate.hip.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <set>
+#include <utility>
+#include <vector>
+
+#include "mdx_internal.h"
+
+struct mdx_ctx {
+  mdx::Ctx c;
+  std::vector<void*> allocs;
+  // event pairs per timing group, reused across recordings
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];
+  size_t used[3] = {0, 0, 0};
+};
+
+namespace {
+
+using mdx::Ctx;
+
+#define MDX_TRY(expr)                               \
+  do {                                              \
+    hipError_t _e = (expr);                         \
+    if (_e != hipSuccess) return MDX_E_HIP;         \
+  } while (0)
+
+template <typename T>
+int dev_alloc(mdx_ctx* x, T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, count * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return MDX_E_OUT_OF_MEMORY;
+  }
+  x->allocs.push_back(q);
+  *p = static_cast<T*>(q);
+  return MDX_OK;
+}
+
+template <typename T>
+int dev_upload(mdx_ctx* x, T** p, const std::vector<T>& h) {
+  int rc = dev_alloc(x, p, h.size());
+  if (rc != MDX_OK) return rc;
+  if (!h.empty() && hipMemcpy(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+    return MDX_E_HIP;
+  return MDX_OK;
+}
+
+void dev_free(mdx_ctx* x, void* p) {
+  if (!p) return;
+  auto it = std::find(x->allocs.begin(), x->allocs.end(), p);
+  if (it != x->allocs.end()) x->allocs.erase(it);
+  (void)hipFree(p);
+}
+
+// CSR of per-atom item lists from (atom, item) pairs.
+void build_csr(int n, const std::vector<std::pair<int, int>>& items, std::vector<int>& start,
+               std::vector<int>& idx) {
+  start.assign(n + 1, 0);
+  for (auto& p : items) start[p.first + 1]++;
+  for (int i = 0; i < n; ++i) start[i + 1] += start[i];
+  idx.assign(items.size(), 0);
+  std::vector<int> cur(start.begin(), start.end() - 1);
+  for (auto& p : items) idx[cur[p.first]++] = p.second;
+  for (int i = 0; i < n; ++i) std::sort(idx.begin() + start[i], idx.begin() + start[i + 1]);
+}
+
+// Cubic B-spline value at the integers 1, 2, 3 (uniform basis).
+double m4_at(int k) { return k == 2 ? 2.0 / 3.0 : (k == 1 || k == 3 ? 1.0 / 6.0 : 0.0); }
+
+int default_capacity(int n, const float box[3], float r_list) {
+  double V = (double)box[0] * box[1] * box[2];
+  double rho = n / V;
+  double expect = rho * 4.0 / 3.0 * M_PI * (double)r_list * r_list * r_list;
+  int cap = (int)std::ceil(1.35 * expect + 32.0);
+  cap = (cap + 15) / 16 * 16;
+  return std::min(cap, std::max(16, (n + 15) / 16 * 16));
+}
+
+int alloc_list(mdx_ctx* x, int cap) {
+  Ctx& c = x->c;
+  dev_free(x, c.nl);
+  c.nl = nullptr;
+  int rc = dev_alloc(x, &c.nl, (size_t)cap * c.npad);
+  if (rc != MDX_OK) return rc;
+  c.nl_cap = cap;
+  return MDX_OK;
+}
+
+int setup_pme(mdx_ctx* x, const mdx_system_desc* d) {
+  Ctx& c = x->c;
+  mdx::PmeGrid& g = c.pg;
+  for (int k = 0; k < 3; ++k) {
+    g.K[k] = d->pme_grid[k];
+    g.B[k] = std::min(8, g.K[k]);
+    g.nb[k] = (g.K[k] + g.B[k] - 1) / g.B[k];
+    double s = (double)g.K[k] / (double)c.box[k];
+    g.scale_hi[k] = (float)s;
+    g.scale_lo[k] = (float)(s - (double)g.scale_hi[k]);
+  }
+  g.Kxh = g.K[0] / 2 + 1;
+  g.nbrick = g.nb[0] * g.nb[1] * g.nb[2];
+  double wmin = 1e30;
+  for (int k = 0; k < 3; ++k) wmin = std::min(wmin, (double)c.box[k] / c.cg.n[k]);
+  g.disp_max = (float)(0.5 * (double)c.r_ghost * 1.001 + 1e-4 * wmin);
+
+  // candidate cells per brick and dimension: cells that can hold an atom whose
+  // spline support reaches the brick, allowing r_g/2 of motion since the build
+  std::vector<int> bc;
+  int maxc[3] = {0, 0, 0};
+  for (int k = 0; k < 3; ++k) {
+    double L = c.box[k], w = L / c.cg.n[k], h = L / g.K[k];
+    for (int b = 0; b < g.nb[k]; ++b) {
+      int g0 = b * g.B[k];
+      int beff = std::min(g.B[k], g.K[k] - g0);
+      double lo = g0 * h - g.disp_max;
+      double hi = (g0 + beff + 3) * h + g.disp_max;
+      long first = (long)std::floor(lo / w);
+      long last = (long)std::floor(hi / w);
+      long count = last - first + 1;
+      if (count >= c.cg.n[k]) {
+        first = 0;
+        count = c.cg.n[k];
+      }
+      first = ((first % c.cg.n[k]) + c.cg.n[k]) % c.cg.n[k];
+      bc.push_back((int)first);
+      bc.push_back((int)count);
+      maxc[k] = std::max(maxc[k], (int)count);
+    }
+  }
+  if ((long)maxc[0] * maxc[1] * maxc[2] > 512) return MDX_E_UNSUPPORTED;
+  int rc = dev_upload(x, &c.brick_cells, bc);
+  if (rc != MDX_OK) return rc;
+
+  for (int k = 0; k < 3; ++k) {
+    const int K = g.K[k];
+    std::vector<float2> tw(K);
+    for (int m = 0; m < K; ++m) {
+      double a = -2.0 * M_PI * m / K;
+      tw[m] = make_float2((float)std::cos(a), (float)std::sin(a));
+    }
+    std::vector<double> bm(K), mr(K);
+    for (int m = 0; m < K; ++m) {
+      std::complex<double> s(0.0, 0.0);
+      for (int t = 0; t <= 2; ++t)
+        s += m4_at(t + 1) * std::exp(std::complex<double>(0.0, 2.0 * M_PI * m * t / K));
+      bm[m] = 1.0 / std::norm(s);
+      int mp = (m <= K / 2) ? m : m - K;
+      mr[m] = (double)mp / (double)c.box[k];
+    }
+    if ((rc = dev_upload(x, &c.tw[k], tw)) != MDX_OK) return rc;
+    if ((rc = dev_upload(x, &c.bmod[k], bm)) != MDX_OK) return rc;
+    if ((rc = dev_upload(x, &c.mrec[k], mr)) != MDX_OK) return rc;
+  }
+  c.pme_energy_scale = 1.0 / (M_PI * (double)c.box[0] * c.box[1] * c.box[2]);
+  size_t ng = (size_t)g.K[0] * g.K[1] * g.K[2];
+  if ((rc = dev_alloc(x, &c.grid_q, ng)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.grid_phi, ng)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.grid_c, (size_t)g.Kxh * g.K[1] * g.K[2])) != MDX_OK) return rc;
+  return MDX_OK;
+}
+
+int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
+  Ctx& c = x->c;
+  const int n = d->n_atoms;
+  if (n <= 0 || !d->charge || !d->mass || !d->atom_type || d->n_types <= 0 || !d->type_sigma ||
+      !d->type_epsilon)
+    return MDX_E_INVALID;
+  for (int k = 0; k < 3; ++k)
+    if (!(d->box[k] > 0.f) || !std::isfinite(d->box[k])) return MDX_E_INVALID;
+  if (!(d->r_cut > 0.f) || !(d->r_ghost >= 0.f)) return MDX_E_INVALID;
+  if ((d->n_exclusions > 0 && !d->exclusions) || d->n_exclusions < 0) return MDX_E_INVALID;
+  if ((d->n_bonds > 0 && (!d->bonds || !d->bond_k || !d->bond_r0)) || d->n_bonds < 0)
+    return MDX_E_INVALID;
+  if ((d->n_angles > 0 && (!d->angles || !d->angle_k || !d->angle_theta0)) || d->n_angles < 0)
+    return MDX_E_INVALID;
+  for (int i = 0; i < n; ++i) {
+    if (d->atom_type[i] < 0 || d->atom_type[i] >= d->n_types) return MDX_E_INVALID;
+    if (!(d->mass[i] > 0.f)) return MDX_E_INVALID;
+  }
+  const int cdiv = d->cell_divisions == 0 ? 2 : d->cell_divisions;
+  if (cdiv < 1 || cdiv > 4) return MDX_E_INVALID;
+  if (d->switch_r > 0.f && !(d->switch_r < d->r_cut)) return MDX_E_INVALID;
+
+  c.n = n;
+  c.npad = (n + mdx::kWave - 1) / mdx::kWave * mdx::kWave;
+  for (int k = 0; k < 3; ++k) c.box[k] = d->box[k];
+  c.r_cut = d->r_cut;
+  c.r_ghost = d->r_ghost;
+  c.r_list = d->r_cut + d->r_ghost;   // float32 sum
+  c.switch_r = d->switch_r;
+  c.has_switch = d->switch_r > 0.f;
+  c.coulomb_k = d->coulomb_k;
+  c.accel = d->accel > 0 ? d->accel : 1.0;
+  c.boltzmann = d->boltzmann;
+  c.cell_div = cdiv;
+  c.rebuild_every = d->rebuild_every > 0 ? d->rebuild_every : 10;
+  for (int k = 0; k < 3; ++k)
+    if ((double)c.r_list > 0.5 * (double)c.box[k]) return MDX_E_BOX_TOO_SMALL;
+
+  // Ewald splitting parameter: explicit, or Eq. 13 from the tolerance.
+  if (d->ewald_alpha > 0.0) c.alpha = d->ewald_alpha;
+  else if (d->ewald_delta > 0.0) {
+    if (d->ewald_delta >= 0.5) return MDX_E_INVALID;
+    c.alpha = std::sqrt(-std::log(2.0 * d->ewald_delta)) / (double)d->r_cut;
+  } else c.alpha = 0.0;
+  bool any_q = false;
+  for (int i = 0; i < n; ++i) any_q |= d->charge[i] != 0.f;
+  c.has_coulomb = c.alpha > 0.0 && d->coulomb_k != 0.0 && any_q;
+  const bool want_pme = d->pme_grid[0] > 0 || d->pme_grid[1] > 0 || d->pme_grid[2] > 0;
+  if (want_pme) {
+    if (d->pme_order != 4 && d->pme_order != 0) return MDX_E_UNSUPPORTED;
+    for (int k = 0; k < 3; ++k)
+      if (!mdx::pme_size_supported(d->pme_grid[k])) return MDX_E_UNSUPPORTED;
+    if (!(c.alpha > 0.0)) return MDX_E_INVALID;
+  }
+  c.has_pme = want_pme && c.has_coulomb;
+
+  // ---- cell grid and predicate constants ----
+  mdx::CellGrid& g = c.cg;
+  g.ncell = 1;
+  for (int k = 0; k < 3; ++k) {
+    int nk = (int)std::floor((double)cdiv * c.box[k] / ((double)c.r_list * (1.0 + 1e-4)));
+    if (nk < 1) nk = 1;
+    g.n[k] = nk;
+    g.ncell *= nk;
+    g.L[k] = c.box[k];
+    g.hL[k] = c.box[k] * 0.5f;
+    g.inv_w[k] = (float)nk / c.box[k];
+    if (nk >= 2 * cdiv + 1) {
+      g.nofs[k] = 2 * cdiv + 1;
+      for (int o = 0; o < g.nofs[k]; ++o) g.ofs[k][o] = o - cdiv;
+    } else {
+      g.nofs[k] = nk;
+      for (int o = 0; o < nk; ++o) g.ofs[k][o] = o;
+    }
+  }
+  g.rnl2 = c.r_list * c.r_list;
+  g.rc2 = c.r_cut * c.r_cut;
+
+  // ---- per-atom parameters and the LJ type-pair table (Eqs. 4-5) ----
+  std::vector<float> q(n), am(n), ms(n);
+  std::vector<int> ty(n);
+  double q2 = 0.0, qsum = 0.0;
+  for (int i = 0; i < n; ++i) {
+    q[i] = c.has_coulomb ? d->charge[i] : 0.f;
+    ty[i] = d->atom_type[i];
+    am[i] = (float)(c.accel / (double)d->mass[i]);
+    ms[i] = d->mass[i];
+    q2 += (double)d->charge[i] * d->charge[i];
+    qsum += d->charge[i];
+  }
+  const int T = d->n_types;
+  c.n_types = T;
+  std::vector<float4> ljf((size_t)T * T);
+  std::vector<double2> ljd((size_t)T * T);
+  for (int a = 0; a < T; ++a)
+    for (int b = 0; b < T; ++b) {
+      double sig = 0.5 * ((double)d->type_sigma[a] + (double)d->type_sigma[b]);
+      double eps = std::sqrt(std::max(0.0, (double)d->type_epsilon[a] * d->type_epsilon[b]));
+      double s6 = sig * sig * sig * sig * sig * sig;
+      double c6 = 4.0 * eps * s6, c12 = 4.0 * eps * s6 * s6;
+      ljf[(size_t)a * T + b] = make_float4((float)c12, (float)c6, (float)(12.0 * c12),
+                                           (float)(6.0 * c6));
+      ljd[(size_t)a * T + b] = make_double2(c12, c6);
+    }
+  if (c.has_coulomb) {
+    double V = (double)c.box[0] * c.box[1] * c.box[2];
+    c.e_self = -c.coulomb_k * c.alpha / std::sqrt(M_PI) * q2 -
+               c.coulomb_k * M_PI * qsum * qsum / (2.0 * V * c.alpha * c.alpha);
+  }
+  int rc;
+  if ((rc = dev_upload(x, &c.q, q)) != MDX_OK) return rc;
+  if ((rc = dev_upload(x, &c.atype, ty)) != MDX_OK) return rc;
+  if ((rc = dev_upload(x, &c.lj_f, ljf)) != MDX_OK) return rc;
+  if ((rc = dev_upload(x, &c.lj_d, ljd)) != MDX_OK) return rc;
+  if ((rc = dev_upload(x, &c.hdt_scale, am)) != MDX_OK) return rc;
+  if ((rc = dev_upload(x, &c.mass, ms)) != MDX_OK) return rc;
+
+  // ---- topology ----
+  std::set<std::pair<int, int>> ex;
+  for (int e = 0; e < d->n_exclusions; ++e) {
+    int a = d->exclusions[2 * e], b = d->exclusions[2 * e + 1];
+    if (a < 0 || b < 0 || a >= n || b >= n || a == b) return MDX_E_INVALID;
+    ex.insert({std::min(a, b), std::max(a, b)});
+  }
+  std::vector<std::pair<int, int>> items;
+  for (auto& p : ex) {
+    items.push_back({p.first, p.second});
+    items.push_back({p.second, p.first});
+  }
+  std::vector<int> st, ix;
+  build_csr(n, items, st, ix);
+  c.n_excl = (int)ex.size();
+  if ((rc = dev_upload(x, &c.ex_start, st)) != MDX_OK) return rc;
+  if ((rc = dev_upload(x, &c.ex_idx, ix)) != MDX_OK) return rc;
+
+  std::vector<int> bidx(2 * d->n_bonds);
+  std::vector<float> bk(d->n_bonds), br(d->n_bonds);
+  items.clear();
+  for (int b = 0; b < d->n_bonds; ++b) {
+    int i = d->bonds[2 * b], j = d->bonds[2 * b + 1];
+    if (i < 0 || j < 0 || i >= n || j >= n || i == j) return MDX_E_INVALID;
+    bidx[2 * b] = i;
+    bidx[2 * b + 1] = j;
+    bk[b] = d->bond_k[b];
+    br[b] = d->bond_r0[b];
+    items.push_back({i, b});
+    items.push_back({j, b});
+  }
+  build_csr(n, items, st, ix);
+  c.n_bonds = d->n_bonds;
+  if ((rc = dev_upload(x, &c.bonds, bidx)) != MDX_OK) return rc;
+  if ((rc = dev_upload(x, &c.bond_k, bk)) != MDX_OK) return rc;
+  if ((rc = dev_upload(x, &c.bond_r0, br)) != MDX_OK) return rc;
+  if ((rc = dev_upload(x, &c.bt_start, st)) != MDX_OK) return rc;
+  if ((rc = dev_upload(x, &c.bt_idx, ix)) != MDX_OK) return rc;
+
+  std::vector<int> aidx(3 * d->n_angles);
+  std::vector<float> ak(d->n_angles), at(d->n_angles);
+  items.clear();
+  for (int a = 0; a < d->n_angles; ++a) {
+    int i = d->angles[3 * a], j = d->angles[3 * a + 1], l = d->angles[3 * a + 2];
+    if (i < 0 || j < 0 || l < 0 || i >= n || j >= n || l >= n || i == j || j == l || i == l)
+      return MDX_E_INVALID;
+    aidx[3 * a] = i;
+    aidx[3 * a + 1] = j;
+    aidx[3 * a + 2] = l;
+    ak[a] = d->angle_k[a];
+    at[a] = d->angle_theta0[a];
+    items.push_back({i, a});
+    items.push_back({j, a});
+    items.push_back({l, a});
+  }
+  build_csr(n, items, st, ix);
+  c.n_angles = d->n_angles;
+  if ((rc = dev_upload(x, &c.angles, aidx)) != MDX_OK) return rc;
+  if ((rc = dev_upload(x, &c.angle_k, ak)) != MDX_OK) return rc;
+  if ((rc = dev_upload(x, &c.angle_t0, at)) != MDX_OK) return rc;
+  if ((rc = dev_upload(x, &c.at_start, st)) != MDX_OK) return rc;
+  if ((rc = dev_upload(x, &c.at_idx, ix)) != MDX_OK) return rc;
+
+  // ---- cell list and neighbour list storage ----
+  if ((rc = dev_alloc(x, &c.cell_of, n)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.cell_count, g.ncell)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.cell_start, g.ncell + 1)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.cell_cursor, g.ncell)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.perm_unsorted, n)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.perm, n)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.inv_perm, n)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.cell_sorted, n)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.xs, n)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.ts, n)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.x_build, (size_t)3 * n)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.nl_count, n)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.nl_needed, 1)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.flags, 1)) != MDX_OK) return rc;
+  MDX_TRY(hipMemset(c.flags, 0, sizeof(unsigned)));
+  if ((rc = dev_alloc(x, &c.gate, 1)) != MDX_OK) return rc;
+  MDX_TRY(hipMemset(c.gate, 0, sizeof(int)));
+  int cap = d->nl_capacity > 0 ? d->nl_capacity : default_capacity(n, c.box, c.r_list);
+  if ((rc = alloc_list(x, cap)) != MDX_OK) return rc;
+
+  if (c.has_pme) {
+    if ((rc = setup_pme(x, d)) != MDX_OK) return rc;
+  }
+  // ---- reductions ----
+  int mb = (n + 255) / 256;
+  if (c.has_pme) {
+    int ntile = (c.pg.Kxh + 15) / 16;
+    mb = std::max(mb, c.pg.K[1] * ntile);
+  }
+  c.max_blocks = mb;
+  if ((rc = dev_alloc(x, &c.partials, (size_t)mdx::kRowCount * mb)) != MDX_OK) return rc;
+  MDX_TRY(hipMemset(c.partials, 0, sizeof(double) * mdx::kRowCount * mb));
+  if ((rc = dev_alloc(x, &c.energy_scratch, MDX_N_ENERGY)) != MDX_OK) return rc;
+  MDX_TRY(hipDeviceSynchronize());
+  return MDX_OK;
+}
+
+int check_ctx(mdx_ctx* x) { return x ? MDX_OK : MDX_E_INVALID; }
+
+constexpr size_t kMaxTimed = 8192;
+
+// Records an event pair around the launches made by `fn` when timing is on.
+template <typename F>
+hipError_t timed(mdx_ctx* x, int group, F&& fn) {
+  if (!x->timing || x->used[group] >= kMaxTimed) return fn();
+  auto& v = x->ev[group];
+  if (x->used[group] == v.size()) {
+    hipEvent_t a, b;
+    hipError_t e = hipEventCreate(&a);
+    if (e != hipSuccess) return e;
+    if ((e = hipEventCreate(&b)) != hipSuccess) return e;
+    v.push_back({a, b});
+  }
+  auto& p = v[x->used[group]++];
+  hipError_t e = hipEventRecord(p.first, x->c.stream);
+  if (e != hipSuccess) return e;
+  if ((e = fn()) != hipSuccess) return e;
+  return hipEventRecord(p.second, x->c.stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mdx_error_string(int code) {
+  switch (code) {
+    case MDX_OK: return "ok";
+    case MDX_E_INVALID: return "invalid argument";
+    case MDX_E_BOX_TOO_SMALL: return "box too small: r_cut + r_ghost exceeds half a box edge";
+    case MDX_E_HIP: return "HIP runtime error";
+    case MDX_E_CAPACITY: return "caller buffer too small";
+    case MDX_E_NO_LIST: return "no neighbour list: call mdx_build_neighbors first";
+    case MDX_E_NO_PME: return "PME not configured for this context";
+    case MDX_E_OUT_OF_MEMORY: return "device allocation failed";
+    case MDX_E_UNSUPPORTED: return "unsupported option";
+    default: return "unknown error";
+  }
+}
+
+int mdx_create(mdx_ctx** out, const mdx_system_desc* d, void* hip_stream) {
+  if (!out) return MDX_E_INVALID;
+  *out = nullptr;
+  if (!d) return MDX_E_INVALID;
+  mdx_ctx* x = new (std::nothrow) mdx_ctx();
+  if (!x) return MDX_E_OUT_OF_MEMORY;
+  if (hipGetDevice(&x->c.device) != hipSuccess) {
+    delete x;
+    return MDX_E_HIP;
+  }
+  x->c.stream = static_cast<hipStream_t>(hip_stream);
+  int rc = create_impl(x, d);
+  if (rc != MDX_OK) {
+    mdx_destroy(x);
+    return rc;
+  }
+  *out = x;
+  return MDX_OK;
+}
+
+int mdx_destroy(mdx_ctx* x) {
+  if (!x) return MDX_OK;
+  (void)hipStreamSynchronize(x->c.stream);
+  for (auto& v : x->ev)
+    for (auto& p : v) {
+      (void)hipEventDestroy(p.first);
+      (void)hipEventDestroy(p.second);
+    }
+  for (void* p : x->allocs) (void)hipFree(p);
+  delete x;
+  return MDX_OK;
+}
+
+int mdx_set_stream(mdx_ctx* x, void* hip_stream) {
+  if (check_ctx(x)) return MDX_E_INVALID;
+  x->c.stream = static_cast<hipStream_t>(hip_stream);
+  return MDX_OK;
+}
+
+int mdx_build_neighbors(mdx_ctx* x, const float* pos) {
+  if (check_ctx(x) || !pos) return MDX_E_INVALID;
+  Ctx& c = x->c;
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    MDX_TRY(timed(x, MDX_TIMING_BUILD, [&] { return mdx::launch_build_list(c, pos); }));
+    int needed = 0;
+    MDX_TRY(hipMemcpyAsync(&needed, c.nl_needed, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    MDX_TRY(hipStreamSynchronize(c.stream));
+    c.steps_since_build = 0;
+    if (needed <= c.nl_cap) return MDX_OK;
+    // grow, clear the overflow bit this build latched, and build again
+    int rc = alloc_list(x, (needed + needed / 8 + 16 + 15) / 16 * 16);
+    if (rc != MDX_OK) return rc;
+    unsigned fl = 0;
+    MDX_TRY(hipMemcpy(&fl, c.flags, sizeof(unsigned), hipMemcpyDeviceToHost));
+    fl &= ~MDX_FLAG_NL_OVERFLOW;
+    MDX_TRY(hipMemcpy(c.flags, &fl, sizeof(unsigned), hipMemcpyHostToDevice));
+  }
+  return MDX_E_HIP;
+}
+
+int mdx_get_neighbor_pairs(mdx_ctx* x, int32_t* pairs_host, int64_t cap, int64_t* n_out) {
+  if (check_ctx(x) || !n_out || cap < 0 || (cap > 0 && !pairs_host)) return MDX_E_INVALID;
+  Ctx& c = x->c;
+  if (c.steps_since_build < 0) return MDX_E_NO_LIST;
+  MDX_TRY(hipStreamSynchronize(c.stream));
+  const int n = c.n;
+  std::vector<int> cnt(n), perm(n), nl((size_t)c.nl_cap * c.npad);
+  MDX_TRY(hipMemcpy(cnt.data(), c.nl_count, sizeof(int) * n, hipMemcpyDeviceToHost));
+  MDX_TRY(hipMemcpy(perm.data(), c.perm, sizeof(int) * n, hipMemcpyDeviceToHost));
+  MDX_TRY(hipMemcpy(nl.data(), c.nl, sizeof(int) * nl.size(), hipMemcpyDeviceToHost));
+  std::vector<std::pair<int, int>> pairs;
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < cnt[i]; ++k) {
+      int a = perm[i], b = perm[nl[(size_t)k * c.npad + i]];
+      if (a < b) pairs.push_back({a, b});
+    }
+  std::sort(pairs.begin(), pairs.end());
+  *n_out = (int64_t)pairs.size();
+  if ((int64_t)pairs.size() > cap) return MDX_E_CAPACITY;
+  for (size_t p = 0; p < pairs.size(); ++p) {
+    pairs_host[2 * p] = pairs[p].first;
+    pairs_host[2 * p + 1] = pairs[p].second;
+  }
+  return MDX_OK;
+}
+
+int mdx_compute_nonbonded(mdx_ctx* x, const float* pos, float* force, double* energy,
+                          double* virial) {
+  if (check_ctx(x) || !pos || !force) return MDX_E_INVALID;
+  if (virial) return MDX_E_UNSUPPORTED;
+  Ctx& c = x->c;
+  if (c.steps_since_build < 0) return MDX_E_NO_LIST;
+  const bool e = energy != nullptr;
+  MDX_TRY(mdx::launch_refresh_sorted(c, pos));
+  MDX_TRY(timed(x, MDX_TIMING_PAIR, [&] { return mdx::launch_nonbonded(c, force, e); }));
+  MDX_TRY(mdx::launch_bonded_excl(c, pos, force, e));
+  if (e) {
+    const int nb = (c.n + 255) / 256;
+    int rows[5] = {mdx::kRowLJ, mdx::kRowDir, mdx::kRowExcl, mdx::kRowBond, mdx::kRowAngle};
+    int nblk[5] = {c.nb_blocks, c.nb_blocks, nb, nb, nb};
+    MDX_TRY(mdx::launch_reduce_energy(c, rows, nblk, 5, energy, 0, c.e_self,
+                                      MDX_ENERGY_COUL_SELF));
+  }
+  return MDX_OK;
+}
+
+int mdx_compute_pme(mdx_ctx* x, const float* pos, float* force, double* energy, double* virial) {
+  if (check_ctx(x) || !pos || !force) return MDX_E_INVALID;
+  if (virial) return MDX_E_UNSUPPORTED;
+  Ctx& c = x->c;
+  if (!c.has_pme) return MDX_E_NO_PME;
+  if (c.steps_since_build < 0) return MDX_E_NO_LIST;
+  MDX_TRY(mdx::launch_refresh_sorted(c, pos));
+  MDX_TRY(timed(x, MDX_TIMING_PME, [&] { return mdx::launch_pme(c, force, energy != nullptr); }));
+  if (energy) {
+    int rows[1] = {mdx::kRowRec};
+    int nblk[1] = {c.pme_blocks};
+    MDX_TRY(mdx::launch_reduce_energy(c, rows, nblk, 1, energy, MDX_ENERGY_COUL_REC, 0.0, -1));
+  }
+  return MDX_OK;
+}
+
+int mdx_integrate_step(mdx_ctx* x, float* pos, float* vel, float* force, int32_t n_steps,
+                       float dt, double* energies) {
+  if (check_ctx(x) || !pos || !vel || !force || n_steps < 1 || !(dt > 0.f)) return MDX_E_INVALID;
+  Ctx& c = x->c;
+  if (c.steps_since_build < 0) {
+    MDX_TRY(mdx::launch_build_list(c, pos));
+    c.steps_since_build = 0;
+  }
+  const int nb = (c.n + 255) / 256;
+  for (int s = 0; s < n_steps; ++s) {
+    const bool e = energies != nullptr;
+    // The list is rebuilt on the cadence, and in between whenever an atom
+    // has moved more than r_g/2 since the last build (decided on the device:
+    // the refresh kernel raises the gate, the build kernels run only if it
+    // is raised).
+    MDX_TRY(mdx::launch_kick_drift(c, pos, vel, force, dt, c.gate));
+    const bool cadence = ++c.steps_since_build >= c.rebuild_every;
+    if (cadence) c.steps_since_build = 0;
+    MDX_TRY(mdx::launch_refresh_sorted(c, pos, c.gate, cadence));
+    MDX_TRY(timed(x, MDX_TIMING_BUILD, [&] { return mdx::launch_build_list(c, pos, c.gate); }));
+    MDX_TRY(timed(x, MDX_TIMING_PAIR, [&] { return mdx::launch_nonbonded(c, force, e); }));
+    MDX_TRY(mdx::launch_bonded_excl(c, pos, force, e));
+    if (c.has_pme)
+      MDX_TRY(timed(x, MDX_TIMING_PME, [&] { return mdx::launch_pme(c, force, e); }));
+    MDX_TRY(mdx::launch_kick(c, vel, force, dt, e));
+    if (e) {
+      int rows[7] = {mdx::kRowLJ,   mdx::kRowDir,   mdx::kRowExcl, mdx::kRowBond,
+                     mdx::kRowAngle, mdx::kRowRec, mdx::kRowKin};
+      int nblk[7] = {c.nb_blocks, c.nb_blocks, nb, nb, nb, c.pme_blocks, nb};
+      int nrows = c.has_pme ? 7 : 6;
+      if (!c.has_pme) {
+        rows[5] = mdx::kRowKin;
+        nblk[5] = nb;
+      }
+      double* out = energies + (size_t)s * MDX_N_ENERGY;
+      MDX_TRY(mdx::launch_reduce_energy(c, rows, nblk, nrows, out, 0, c.e_self,
+                                        MDX_ENERGY_COUL_SELF,
+                                        c.has_pme ? -1 : MDX_ENERGY_COUL_REC));
+    }
+    c.steps_taken++;
+  }
+  return MDX_OK;
+}
+
+int mdx_get_status(mdx_ctx* x, uint32_t* flags) {
+  if (check_ctx(x) || !flags) return MDX_E_INVALID;
+  Ctx& c = x->c;
+  unsigned f = 0;
+  MDX_TRY(hipMemcpyAsync(&f, c.flags, sizeof(unsigned), hipMemcpyDeviceToHost, c.stream));
+  MDX_TRY(hipStreamSynchronize(c.stream));
+  MDX_TRY(hipMemsetAsync(c.flags, 0, sizeof(unsigned), c.stream));
+  MDX_TRY(hipStreamSynchronize(c.stream));
+  *flags = f;
+  return MDX_OK;
+}
+
+int mdx_get_info(mdx_ctx* x, mdx_info* info) {
+  if (check_ctx(x) || !info) return MDX_E_INVALID;
+  Ctx& c = x->c;
+  std::memset(info, 0, sizeof(*info));
+  info->n_atoms = c.n;
+  for (int k = 0; k < 3; ++k) {
+    info->cell_dims[k] = c.cg.n[k];
+    info->pme_grid[k] = c.has_pme ? c.pg.K[k] : 0;
+    info->pme_brick[k] = c.has_pme ? c.pg.B[k] : 0;
+  }
+  info->cell_divisions = c.cell_div;
+  info->nl_capacity = c.nl_cap;
+  info->alpha = c.alpha;
+  info->r_list = (double)c.r_list;
+  info->n_list_entries = -1;
+  info->steps_taken = c.steps_taken;
+  return MDX_OK;
+}
+
+int mdx_set_timing(mdx_ctx* x, int enable) {
+  if (check_ctx(x)) return MDX_E_INVALID;
+  x->timing = enable != 0;
+  if (x->timing)
+    for (auto& u : x->used) u = 0;
+  return MDX_OK;
+}
+
+int mdx_get_timing(mdx_ctx* x, int group, double* mean_ms, int64_t* launches) {
+  if (check_ctx(x) || group < 0 || group > 2 || !mean_ms || !launches) return MDX_E_INVALID;
+  MDX_TRY(hipStreamSynchronize(x->c.stream));
+  double tot = 0.0;
+  for (size_t k = 0; k < x->used[group]; ++k) {
+    float ms = 0.f;
+    MDX_TRY(hipEventElapsedTime(&ms, x->ev[group][k].first, x->ev[group][k].second));
+    tot += ms;
+  }
+  *launches = (int64_t)x->used[group];
+  *mean_ms = x->used[group] ? tot / (double)x->used[group] : 0.0;
+  return MDX_OK;
+}
+
+}  // extern "C"

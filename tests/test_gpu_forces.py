@@ -1,0 +1,121 @@
+"""GPU parity: short-range forces/energies and PME vs the FP64 oracle.
+
+Bars: forces within 1e-5 relative RMS (||F_gpu - F_orc|| / ||F_orc|| over all 3N
+components), energies within 1e-6 relative.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import forcefield
+from helpers import announce, gpu_context, rel_rms
+
+pytestmark = pytest.mark.gpu
+
+F_TOL = 1e-5
+E_TOL = 1e-6
+
+
+def _nonbonded_gpu(s, **kw):
+    import torch
+    with gpu_context(s, **kw) as (mdx, ctx, t):
+        mdx.build_neighbors(ctx, t["pos"])
+        mdx.compute_nonbonded(ctx, t["pos"], t["force"], t["e_nb"])
+        torch.cuda.synchronize()
+        flags = mdx.get_status(ctx)
+        return t["force"].cpu().numpy(), t["e_nb"].cpu().numpy(), flags
+
+
+@pytest.mark.parametrize("name", ["lj1k", "water375", "water9k"])
+def test_nonbonded_parity(name):
+    s = synth.config_system(name)
+    announce(f"nonbonded {name}")
+    F, E, flags = _nonbonded_gpu(s)
+    assert flags == 0
+    ref = forcefield.nonbonded_terms(s)
+    assert rel_rms(F, ref["F"]) < F_TOL
+    Eref = ref["E"]
+    scale = max(abs(Eref.sum()), 1e-30)
+    for k in range(6):
+        assert abs(E[k] - Eref[k]) <= E_TOL * max(abs(Eref[k]), scale), (k, E[k], Eref[k])
+    assert abs(E.sum() - Eref.sum()) <= E_TOL * scale
+
+
+def test_nonbonded_switched_random():
+    s = synth.random_box(2500, [13.0, 13.0, 13.0], 3.0, 0.5, 211, min_dist=0.75)
+    s.switch_r = np.float32(2.4)
+    announce("nonbonded switched random")
+    F, E, flags = _nonbonded_gpu(s)
+    ref = forcefield.nonbonded_terms(s)
+    assert rel_rms(F, ref["F"]) < F_TOL
+    assert abs(E[:4].sum() - ref["E"][:4].sum()) <= E_TOL * abs(ref["E"][:4].sum())
+
+
+def test_nonbonded_bitwise_deterministic():
+    import torch
+    s = synth.config_system("water9k")
+    announce("nonbonded determinism")
+    with gpu_context(s) as (mdx, ctx, t):
+        mdx.build_neighbors(ctx, t["pos"])
+        outs = []
+        for _ in range(2):
+            mdx.build_neighbors(ctx, t["pos"])
+            mdx.compute_nonbonded(ctx, t["pos"], t["force"], t["e_nb"])
+            mdx.compute_pme(ctx, t["pos"], t["force"], t["e_rec"])
+            torch.cuda.synchronize()
+            outs.append((t["force"].cpu().numpy().copy(), t["e_nb"].cpu().numpy().copy(),
+                         t["e_rec"].cpu().numpy().copy()))
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("name", ["water375", "water9k"])
+def test_pme_parity(name):
+    import torch
+    s = synth.config_system(name)
+    announce(f"pme {name}")
+    with gpu_context(s) as (mdx, ctx, t):
+        mdx.build_neighbors(ctx, t["pos"])
+        t["force"].zero_()
+        mdx.compute_pme(ctx, t["pos"], t["force"], t["e_rec"])
+        torch.cuda.synchronize()
+        F = t["force"].cpu().numpy()
+        E = float(t["e_rec"].cpu().numpy()[0])
+        assert mdx.get_status(ctx) == 0
+    ref = forcefield.pme_terms(s)
+    assert rel_rms(F, ref["F"]) < F_TOL
+    assert abs(E - ref["E"]) <= E_TOL * abs(ref["E"])
+
+
+def test_pme_mixed_radix_grid():
+    import torch
+    s = synth.water_box(300, 20.9, (27, 20, 25), 7.0, 1.5, 5e-4, 9, name="mixed")
+    announce("pme grid 27x20x25")
+    with gpu_context(s) as (mdx, ctx, t):
+        mdx.build_neighbors(ctx, t["pos"])
+        t["force"].zero_()
+        mdx.compute_pme(ctx, t["pos"], t["force"], t["e_rec"])
+        torch.cuda.synchronize()
+        F = t["force"].cpu().numpy()
+        E = float(t["e_rec"].cpu().numpy()[0])
+    ref = forcefield.pme_terms(s)
+    assert rel_rms(F, ref["F"]) < F_TOL
+    assert abs(E - ref["E"]) <= E_TOL * abs(ref["E"])
+
+
+def test_total_force_water9k():
+    import torch
+    s = synth.config_system("water9k")
+    announce("total force water9k")
+    with gpu_context(s) as (mdx, ctx, t):
+        mdx.build_neighbors(ctx, t["pos"])
+        mdx.compute_nonbonded(ctx, t["pos"], t["force"], t["e_nb"])
+        mdx.compute_pme(ctx, t["pos"], t["force"], t["e_rec"])
+        torch.cuda.synchronize()
+        F = t["force"].cpu().numpy()
+        E = np.concatenate([t["e_nb"].cpu().numpy(), t["e_rec"].cpu().numpy()])
+    nb = forcefield.nonbonded_terms(s)
+    rec = forcefield.pme_terms(s)
+    assert rel_rms(F, nb["F"] + rec["F"]) < F_TOL
+    Et = nb["E"].sum() + rec["E"]
+    assert abs(E.sum() - Et) <= E_TOL * abs(Et)

@@ -1,0 +1,131 @@
+"""GPU: velocity Verlet through mdx_integrate_step vs the oracle, status flags and
+error paths of the C ABI."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import forcefield, integrate
+from helpers import announce, gpu_context
+
+pytestmark = pytest.mark.gpu
+
+
+def test_lj1k_trajectory_tracks_oracle():
+    import torch
+    s = synth.config_system("lj1k")
+    n_steps = 100
+    announce("integrate lj1k 100 steps")
+    with gpu_context(s) as (mdx, ctx, t):
+        mdx.build_neighbors(ctx, t["pos"])
+        mdx.compute_nonbonded(ctx, t["pos"], t["force"])
+        en = torch.zeros((n_steps, mdx.MDX_N_ENERGY), dtype=torch.float64, device="cuda:0")
+        mdx.integrate_step(ctx, t["pos"], t["vel"], t["force"], n_steps, s.dt, en)
+        torch.cuda.synchronize()
+        x_gpu = t["pos"].cpu().numpy().astype(np.float64)
+        E = en.cpu().numpy()
+        assert mdx.get_status(ctx) == 0
+    F = lambda p: forcefield.total_forces_fp64(s, p)[1]
+    ref64 = integrate.velocity_verlet(s.pos, s.vel, s.mass, s.box, F, s.dt, n_steps, 1.0)
+    ref32 = integrate.velocity_verlet_f32(s.pos, s.vel, s.mass, s.box, F, s.dt, n_steps, 1.0)
+
+    def dev(a, b):
+        d = a - b
+        d -= s.box[:, None] * np.round(d / s.box[:, None])
+        return float(np.sqrt((d * d).mean()))
+    d_gpu = dev(x_gpu, ref64["pos"])
+    d_f32 = dev(ref32["pos"].astype(np.float64), ref64["pos"])
+    assert d_gpu <= 10 * max(d_f32, 1e-7), (d_gpu, d_f32)
+    assert np.all(np.isfinite(E))
+
+
+def test_lj_switched_energy_conservation_dt2():
+    # With the Eq. 6 switch the potential is smooth, so velocity Verlet keeps
+    # the total energy bounded with a fluctuation that scales as dt^2.
+    import torch
+    amp = []
+    for dt, n_steps in ((0.004, 200), (0.002, 400)):
+        s = synth.config_system("lj1k")
+        s.switch_r = np.float32(2.25)
+        announce(f"switched LJ dt={dt}")
+        with gpu_context(s) as (mdx, ctx, t):
+            mdx.build_neighbors(ctx, t["pos"])
+            mdx.compute_nonbonded(ctx, t["pos"], t["force"])
+            en = torch.zeros((n_steps, mdx.MDX_N_ENERGY), dtype=torch.float64, device="cuda:0")
+            mdx.integrate_step(ctx, t["pos"], t["vel"], t["force"], n_steps, dt, en)
+            torch.cuda.synchronize()
+            etot = en.cpu().numpy().sum(axis=1)
+            assert mdx.get_status(ctx) == 0
+        amp.append(etot.std())
+        assert np.abs(etot - etot.mean()).max() < 2e-3 * abs(etot.mean())
+    assert 2.5 < amp[0] / amp[1] < 6.0, amp
+
+
+def test_water9k_energy_conservation_and_no_stale():
+    import torch
+    s = synth.config_system("water9k")
+    n_steps = 50
+    announce("integrate water9k 50 steps")
+    with gpu_context(s) as (mdx, ctx, t):
+        mdx.build_neighbors(ctx, t["pos"])
+        mdx.compute_nonbonded(ctx, t["pos"], t["force"])
+        mdx.compute_pme(ctx, t["pos"], t["force"])
+        en = torch.zeros((n_steps, mdx.MDX_N_ENERGY), dtype=torch.float64, device="cuda:0")
+        mdx.integrate_step(ctx, t["pos"], t["vel"], t["force"], n_steps, 0.5, en)
+        torch.cuda.synchronize()
+        E = en.cpu().numpy()
+        assert mdx.get_status(ctx) == 0
+        x = t["pos"].cpu().numpy()
+    assert np.all((x >= 0) & (x < s.box[:, None]))
+    etot = E.sum(axis=1)
+    ke = E[:, 7]
+    assert np.abs(etot - etot[0]).max() < 0.02 * ke.mean()
+
+
+def test_stale_flag_trips_on_large_displacement():
+    import torch
+    s = synth.config_system("water375")
+    announce("stale flag")
+    with gpu_context(s) as (mdx, ctx, t):
+        mdx.build_neighbors(ctx, t["pos"])
+        mdx.compute_nonbonded(ctx, t["pos"], t["force"])
+        assert mdx.get_status(ctx) == 0
+        moved = t["pos"].clone()
+        moved[0, 7] = (moved[0, 7] + 0.51 * float(s.r_ghost)) % float(s.box[0])
+        mdx.compute_nonbonded(ctx, moved, t["force"])
+        assert mdx.get_status(ctx) & mdx.MDX_FLAG_NL_STALE
+        moved[0, 7] = t["pos"][0, 7] + 0.3 * float(s.r_ghost)
+        mdx.compute_nonbonded(ctx, moved, t["force"])
+        assert mdx.get_status(ctx) & mdx.MDX_FLAG_NL_STALE == 0
+        bad = t["pos"].clone()
+        bad[1, 3] = float(s.box[1]) + 0.5
+        mdx.compute_nonbonded(ctx, bad, t["force"])
+        assert mdx.get_status(ctx) & mdx.MDX_FLAG_OUT_OF_BOX
+
+
+def test_error_codes():
+    import paper_2503_20541_amd as mdx
+    s = synth.config_system("water375")
+    desc, keep = mdx.desc_from_system(s, r_cut=7.0)       # r_nl = 8.5 > L/2
+    with pytest.raises(mdx.MdxError) as e:
+        mdx.create(desc)
+    assert e.value.code == mdx.MDX_E_BOX_TOO_SMALL
+    desc, keep = mdx.desc_from_system(s, pme_grid=(16, 16, 11))   # 11 is prime
+    with pytest.raises(mdx.MdxError) as e:
+        mdx.create(desc)
+    assert e.value.code == mdx.MDX_E_UNSUPPORTED
+    desc, keep = mdx.desc_from_system(s)
+    ctx = mdx.create(desc)
+    try:
+        import torch
+        pos = torch.from_numpy(s.pos).cuda()
+        f = torch.zeros_like(pos)
+        with pytest.raises(mdx.MdxError) as e:
+            mdx.compute_nonbonded(ctx, pos, f)
+        assert e.value.code == mdx.MDX_E_NO_LIST
+        mdx.build_neighbors(ctx, pos)
+        v = torch.zeros(9, dtype=torch.float64, device="cuda:0")
+        with pytest.raises(mdx.MdxError) as e:
+            mdx.compute_nonbonded(ctx, pos, f, None, v)
+        assert e.value.code == mdx.MDX_E_UNSUPPORTED
+    finally:
+        mdx.destroy(ctx)

@@ -1,0 +1,97 @@
+"""GPU parity: Verlet list from the HIP cell-list build vs the oracle (bit-exact)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import neighbors
+from helpers import announce, gpu_context
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_pairs(s):
+    return neighbors.tree_pairs(s.pos, s.box, s.r_cut, s.r_ghost, s.exclusions)
+
+
+@pytest.mark.parametrize("name", ["lj1k", "water375", "water9k"])
+def test_list_exact(name):
+    s = synth.config_system(name)
+    announce(f"list {name} N={s.n_atoms}")
+    with gpu_context(s) as (mdx, ctx, t):
+        mdx.build_neighbors(ctx, t["pos"])
+        got = mdx.get_neighbor_pairs(ctx)
+        assert mdx.get_status(ctx) == 0
+    ref = _oracle_pairs(s)
+    assert got.shape == ref.shape
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("m", [1, 2, 3])
+def test_list_invariant_to_cell_width(m):
+    s = synth.random_box(3000, [14.0, 15.0, 16.0], 2.5, 0.5, 77, n_excl_per_atom=2)
+    announce(f"list cell_divisions={m}")
+    with gpu_context(s, cell_divisions=m) as (mdx, ctx, t):
+        mdx.build_neighbors(ctx, t["pos"])
+        got = mdx.get_neighbor_pairs(ctx)
+    assert np.array_equal(got, _oracle_pairs(s))
+
+
+@pytest.mark.parametrize("seed,n,box,rc,rg", [
+    (101, 500, [6.0, 6.0, 6.0], 2.0, 0.5),     # 2-3 cells per dimension: stencil wraps onto itself
+    (102, 1, [5.0, 5.0, 5.0], 1.0, 0.2),       # a single atom: empty list
+    (103, 2000, [20.0, 9.0, 30.0], 3.0, 1.4),  # anisotropic box, ragged cells
+    (104, 4097, [12.0, 12.0, 12.0], 2.2, 0.3), # ragged final wave
+])
+def test_list_edge_cases(seed, n, box, rc, rg):
+    s = synth.random_box(n, box, rc, rg, seed, n_excl_per_atom=1)
+    announce(f"list edge seed={seed} n={n}")
+    with gpu_context(s) as (mdx, ctx, t):
+        mdx.build_neighbors(ctx, t["pos"])
+        got = mdx.get_neighbor_pairs(ctx)
+    assert np.array_equal(got, _oracle_pairs(s))
+
+
+def test_list_relabelling_and_capacity_growth():
+    s = synth.random_box(1500, [10.0, 10.0, 10.0], 2.4, 0.4, 55, n_excl_per_atom=1)
+    perm = np.random.default_rng(1).permutation(s.n_atoms)
+    inv = np.argsort(perm)
+    s2 = s.copy()
+    s2.pos = np.ascontiguousarray(s.pos[:, perm])
+    s2.atom_type = s.atom_type[perm]
+    s2.charge = s.charge[perm]
+    s2.mass = s.mass[perm]
+    s2.vel = np.ascontiguousarray(s.vel[:, perm])
+    s2.exclusions = inv[s.exclusions].astype(np.int32)
+    announce("list relabelled, capacity 16 (forces regrowth)")
+    with gpu_context(s2, nl_capacity=16) as (mdx, ctx, t):
+        mdx.build_neighbors(ctx, t["pos"])
+        got = mdx.get_neighbor_pairs(ctx)
+        assert mdx.get_info(ctx).nl_capacity > 16
+        assert mdx.get_status(ctx) & mdx.MDX_FLAG_NL_OVERFLOW == 0
+    mapped = np.sort(perm[got], axis=1)
+    mapped = mapped[np.lexsort((mapped[:, 1], mapped[:, 0]))]
+    assert np.array_equal(mapped, _oracle_pairs(s))
+
+
+def test_list_water96k_sampled_rows():
+    s = synth.config_system("water96k")
+    announce("list water96k")
+    with gpu_context(s) as (mdx, ctx, t):
+        mdx.build_neighbors(ctx, t["pos"])
+        got = mdx.get_neighbor_pairs(ctx)
+        assert mdx.get_status(ctx) == 0
+    rng = np.random.default_rng(3)
+    sample = rng.choice(s.n_atoms, 300, replace=False)
+    first, second = got[:, 0], got[:, 1]
+    order2 = np.argsort(second, kind="stable")
+    s2 = second[order2]
+    for i in sample:
+        a = got[np.searchsorted(first, i):np.searchsorted(first, i, "right"), 1]
+        b = got[order2[np.searchsorted(s2, i):np.searchsorted(s2, i, "right")], 0]
+        row = np.sort(np.concatenate([a, b]))
+        ref = neighbors.neighbors_of(s.pos, s.box, s.r_cut, s.r_ghost, int(i), s.exclusions)
+        assert np.array_equal(row, ref), i
+    # density check on the total: pairs within r_nl of a uniform liquid
+    rnl = float(np.float32(s.r_cut + s.r_ghost))
+    expect = 0.5 * s.n_atoms * (s.n_atoms / np.prod(s.box.astype(float))) * 4 / 3 * np.pi * rnl ** 3
+    assert abs(len(got) / expect - 1.0) < 0.02
