@@ -11,23 +11,21 @@
 namespace mdx {
 
 constexpr int kWave = 64;
-constexpr int kMaxStencil = 9;      // per-dimension stencil offsets (2m+1, m <= 4)
-constexpr int kMaxCellAtoms = 1024; // atoms one cell may hold (sort kernel limit)
+constexpr int kClusterSize = 4;     // atoms per cluster (slots per tile side)
 
 // Indices into the FP64 partial-sum rows written by force kernels.
 enum PartialRow { kRowLJ = 0, kRowDir, kRowExcl, kRowBond, kRowAngle, kRowRec, kRowKin, kRowCount };
 
-// Geometry of the cell grid and the float32 predicate constants.
+// Geometry of the x-y column grid and the float32 predicate constants.
 struct CellGrid {
-  int n[3];          // cells per dimension
-  int ncell;
+  int n[3];          // columns along x and y (n[2] = 1)
+  int ncell;         // columns
   float inv_w[3];    // n_d / L_d (float32, used only for binning)
   float L[3];
   float hL[3];
   float rnl2;        // fl(r_nl * r_nl)
   float rc2;         // fl(r_c * r_c)
-  int nofs[3];       // distinct stencil offsets per dimension
-  int ofs[3][kMaxStencil];
+  float r_search;    // cluster-box distance below which a tile is tested
 };
 
 struct PmeGrid {
@@ -54,7 +52,7 @@ struct Ctx {
   bool has_coulomb = false, has_pme = false, has_switch = false;
   int n_types = 0, n_excl = 0, n_bonds = 0, n_angles = 0;
   int cell_div = 2;
-  int nl_cap = 0;
+  int nl_cap = 0;               // tiles per i-cluster
   int rebuild_every = 10;
   int steps_since_build = -1;   // -1: no list
   int64_t steps_taken = 0;
@@ -77,21 +75,27 @@ struct Ctx {
   int* bt_start = nullptr; int* bt_idx = nullptr;   // bond ids per atom
   int* at_start = nullptr; int* at_idx = nullptr;   // angle ids per atom
 
-  // ---- cell list / sorted order ----
-  int* cell_of = nullptr;      // [n] cell of each caller atom at build
-  int* cell_count = nullptr;   // [ncell]
-  int* cell_start = nullptr;   // [ncell + 1]
-  int* cell_cursor = nullptr;  // [ncell]
+  // ---- column sort / cluster slots ----
+  int max_slots = 0;           // n + (kClusterSize - 1) * columns, a bound on the slots
+  int max_clusters = 0;
+  int* cell_of = nullptr;      // [n] column of each caller atom at build
+  int* cell_count = nullptr;   // [ncol] atoms per column
+  int* cell_start = nullptr;   // [ncol + 1] first atom (unpadded) of each column
+  int* cell_cursor = nullptr;  // [ncol]
+  int* slot_start = nullptr;   // [ncol + 1] first slot of each column (padded to clusters)
+  int* meta = nullptr;         // [2] slots, clusters of the last build
   int* perm_unsorted = nullptr;// [n]
-  int* perm = nullptr;         // [n] sorted slot -> caller atom
-  int* inv_perm = nullptr;     // [n] caller atom -> sorted slot
-  int* cell_sorted = nullptr;  // [n] cell of each sorted slot
-  float4* xs = nullptr;        // [n] sorted (x, y, z, q) at the current positions
-  int* ts = nullptr;           // [n] sorted LJ type
+  int* perm = nullptr;         // [max_slots] slot -> caller atom, -1 for padding
+  int* inv_perm = nullptr;     // [n] caller atom -> slot
+  float4* xs = nullptr;        // [max_slots] (x, y, z, q) at the current positions
+  int* ts = nullptr;           // [max_slots] LJ type
+  float* zb = nullptr;         // [max_slots] z at the last build (sorted within a column)
+  float4* box_lo = nullptr;    // [max_clusters] cluster box (w = real atoms)
+  float4* box_hi = nullptr;
   float* x_build = nullptr;    // [3][n] positions at the last build (caller order)
-  int* nl_count = nullptr;     // [n] entries per sorted atom
-  int* nl = nullptr;           // [nl_cap][npad] ELL, column-major, sorted indices
-  int* nl_needed = nullptr;    // [1] max neighbours seen by the last build
+  uint2* tiles = nullptr;      // [max_clusters][nl_cap] (j-cluster, 16-bit pair mask)
+  int* tile_count = nullptr;   // [max_clusters]
+  int* nl_needed = nullptr;    // [1] max tiles one cluster needed in the last build
   unsigned* flags = nullptr;   // [1] latched MDX_FLAG_*
   int* gate = nullptr;         // [1] rebuild request inside mdx_integrate_step
 
@@ -103,7 +107,8 @@ struct Ctx {
   double* bmod[3] = {nullptr, nullptr, nullptr}; // |b_d(m)|^2
   double* mrec[3] = {nullptr, nullptr, nullptr}; // m'_d / L_d
   double pme_energy_scale = 0.0;                 // 1 / (pi V)
-  int* brick_cells = nullptr;  // per brick and dim: first cell and count (6 ints)
+  int* brick_cols = nullptr;   // per brick index along x, y: first column, count
+  float* brick_z = nullptr;    // per brick index along z: z range [lo, hi) of atoms that reach it
 
   // ---- reductions ----
   double* partials = nullptr;  // [kRowCount][max_blocks]

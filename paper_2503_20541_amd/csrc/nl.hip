@@ -1,11 +1,20 @@
-// Cell-list Verlet neighbour list (DIMOS Sec. II.A.2, "Neighborlists").
+// Cluster-pair Verlet list (DIMOS Sec. II.A.2, "Neighborlists").
 //
-// Build = bin atoms into cells of edge >= r_nl / m -> counting sort by cell
-// (histogram, one-block scan, scatter, per-cell rank sort by caller index so
-// the order is a pure function of (cell, atom index)) -> per-atom search of
-// the (2m+1)^3 stencil with the float32 predicate of mdx.h. The list is a
-// full (both directions) ELL array nl[k * npad + i] of sorted slot indices,
-// so the k-th entries of 64 consecutive atoms are one coalesced 256-byte row.
+// The list holds every non-excluded pair closer than r_nl = r_c + r_g. It is
+// stored as tiles of 4-atom clusters: atoms are binned into x-y columns
+// (edge ~ the cube holding four atoms), sorted by z inside each column (ties
+// by atom index) and cut into consecutive clusters of four slots (the last
+// cluster of a column is padded with empty slots). For every i-cluster the
+// list keeps the j-clusters whose bounding boxes come closer than r_nl, each
+// with a 16-bit mask whose bit 4*a + b says that slot pair (a, b) passes the
+// float32 inclusion predicate of mdx.h and is not excluded. The set bits are
+// exactly the atom-pair list (both directions), so the exported list is the
+// definition's, while the force kernel streams whole 4x4 tiles.
+//
+// Build kernels (all gated: with a gate they return unless it is raised):
+//   k_prepare -> k_bin (column of every atom, counts) -> k_scan (atom and
+//   padded-slot offsets per column) -> k_scatter -> k_col_sort (rank by z,
+//   write slot data) -> k_cluster_box -> k_tile_search (one wave per i-cluster).
 #include "mdx_internal.h"
 
 namespace mdx {
@@ -15,20 +24,9 @@ __global__ void k_fill_i32(int* __restrict__ p, int v, int count) {
   if (i < count) p[i] = v;
 }
 
-__global__ void k_copy_f32(float* __restrict__ d, const float* __restrict__ s, int count) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) d[i] = s[i];
-}
-
 hipError_t launch_fill_i32(int* p, int v, int count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   k_fill_i32<<<(count + 255) / 256, 256, 0, s>>>(p, v, count);
-  return hipGetLastError();
-}
-
-hipError_t launch_copy_f32(float* dst, const float* src, int count, hipStream_t s) {
-  if (count <= 0) return hipSuccess;
-  k_copy_f32<<<(count + 255) / 256, 256, 0, s>>>(dst, src, count);
   return hipGetLastError();
 }
 
@@ -40,17 +38,17 @@ __device__ __forceinline__ int bin_coord(float x, float inv_w, int n) {
 
 __device__ __forceinline__ bool gated_off(const int* gate) { return gate && *gate == 0; }
 
-__global__ void k_prepare(const int* __restrict__ gate, int* __restrict__ cell_count, int ncell,
+__global__ void k_prepare(const int* __restrict__ gate, int* __restrict__ col_count, int ncol,
                           int* __restrict__ nl_needed) {
   if (gated_off(gate)) return;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < ncell) cell_count[i] = 0;
+  if (i < ncol) col_count[i] = 0;
   if (i == 0) *nl_needed = 0;
 }
 
-// Bin every caller atom, count atoms per cell, snapshot the build positions.
+// Column of every caller atom, atoms per column, build-position snapshot.
 __global__ void k_bin(const int* __restrict__ gate, const float* __restrict__ pos, int n,
-                      CellGrid cg, int* __restrict__ cell_of, int* __restrict__ cell_count,
+                      CellGrid cg, int* __restrict__ col_of, int* __restrict__ col_count,
                       float* __restrict__ x_build, unsigned* __restrict__ flags) {
   if (gated_off(gate)) return;
   int a = blockIdx.x * blockDim.x + threadIdx.x;
@@ -60,165 +58,318 @@ __global__ void k_bin(const int* __restrict__ gate, const float* __restrict__ po
   if (!inside) atomicOr(flags, MDX_FLAG_OUT_OF_BOX);
   int cx = bin_coord(x, cg.inv_w[0], cg.n[0]);
   int cy = bin_coord(y, cg.inv_w[1], cg.n[1]);
-  int cz = bin_coord(z, cg.inv_w[2], cg.n[2]);
-  int c = (cz * cg.n[1] + cy) * cg.n[0] + cx;
-  cell_of[a] = c;
-  atomicAdd(&cell_count[c], 1);
+  int c = cy * cg.n[0] + cx;
+  col_of[a] = c;
+  atomicAdd(&col_count[c], 1);
   x_build[a] = x;
   x_build[n + a] = y;
   x_build[2 * n + a] = z;
 }
 
-// Exclusive scan of the cell counts in one 1024-thread block: each thread
-// sums a contiguous chunk, a wave-level shuffle scan combines the chunk sums.
+// Exclusive scans of the column counts (atoms) and of the counts rounded up
+// to whole clusters (slots), in one 1024-thread block; a wave-level shuffle
+// scan combines per-thread chunk sums. meta[0] = slots, meta[1] = clusters.
 __global__ void __launch_bounds__(1024) k_scan(const int* __restrict__ gate,
-                                               const int* __restrict__ count, int ncell,
-                                               int* __restrict__ start, int* __restrict__ cursor) {
+                                               const int* __restrict__ count, int ncol,
+                                               int* __restrict__ start, int* __restrict__ cursor,
+                                               int* __restrict__ slot_start,
+                                               int* __restrict__ meta) {
   if (gated_off(gate)) return;
-  __shared__ int wave_tot[16];
+  __shared__ int wave_tot[2][16];
   int t = threadIdx.x;
-  int chunk = (ncell + blockDim.x - 1) / blockDim.x;
-  int b = t * chunk, e = min(b + chunk, ncell);
-  int s = 0;
-  for (int i = b; i < e; ++i) s += count[i];
-  // inclusive scan of s across the wave
+  int chunk = (ncol + blockDim.x - 1) / blockDim.x;
+  int b = t * chunk, e = min(b + chunk, ncol);
+  int s = 0, sp = 0;
+  for (int i = b; i < e; ++i) {
+    s += count[i];
+    sp += (count[i] + kClusterSize - 1) / kClusterSize * kClusterSize;
+  }
   int lane = t & (kWave - 1), w = t / kWave;
-  int v = s;
+  int v = s, vp = sp;
   for (int o = 1; o < kWave; o <<= 1) {
     int u = __shfl_up(v, o, kWave);
-    if (lane >= o) v += u;
-  }
-  if (lane == kWave - 1) wave_tot[w] = v;
-  __syncthreads();
-  if (t == 0) {
-    int acc = 0;
-    for (int i = 0; i < (int)(blockDim.x / kWave); ++i) {
-      int tmp = wave_tot[i];
-      wave_tot[i] = acc;
-      acc += tmp;
+    int up = __shfl_up(vp, o, kWave);
+    if (lane >= o) {
+      v += u;
+      vp += up;
     }
   }
+  if (lane == kWave - 1) {
+    wave_tot[0][w] = v;
+    wave_tot[1][w] = vp;
+  }
   __syncthreads();
-  int run = wave_tot[w] + v - s;   // exclusive prefix of this thread's chunk
+  if (t == 0) {
+    int acc = 0, accp = 0;
+    for (int i = 0; i < (int)(blockDim.x / kWave); ++i) {
+      int tmp = wave_tot[0][i], tmpp = wave_tot[1][i];
+      wave_tot[0][i] = acc;
+      wave_tot[1][i] = accp;
+      acc += tmp;
+      accp += tmpp;
+    }
+    start[ncol] = acc;
+    slot_start[ncol] = accp;
+    meta[0] = accp;
+    meta[1] = accp / kClusterSize;
+  }
+  __syncthreads();
+  int run = wave_tot[0][w] + v - s;
+  int runp = wave_tot[1][w] + vp - sp;
   for (int i = b; i < e; ++i) {
     start[i] = run;
     cursor[i] = run;
+    slot_start[i] = runp;
     run += count[i];
+    runp += (count[i] + kClusterSize - 1) / kClusterSize * kClusterSize;
   }
-  if (e == ncell && b < e) start[ncell] = run;
-  if (ncell == 0 && t == 0) start[0] = 0;
 }
 
-__global__ void k_scatter(const int* __restrict__ gate, const int* __restrict__ cell_of, int n,
+__global__ void k_scatter(const int* __restrict__ gate, const int* __restrict__ col_of, int n,
                           int* __restrict__ cursor, int* __restrict__ perm_unsorted) {
   if (gated_off(gate)) return;
   int a = blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= n) return;
-  int slot = atomicAdd(&cursor[cell_of[a]], 1);
+  int slot = atomicAdd(&cursor[col_of[a]], 1);
   perm_unsorted[slot] = a;
 }
 
-// One wave per cell: rank every atom of the cell by caller index (stable
-// order independent of the scatter's atomic order), then write the sorted
-// slot data.
-__global__ void k_cell_sort(const int* __restrict__ gate, const int* __restrict__ cell_start,
-                            int ncell, const int* __restrict__ perm_unsorted,
-                            const float* __restrict__ pos, int n, const float* __restrict__ q,
-                            const int* __restrict__ atype, int* __restrict__ perm,
-                            int* __restrict__ inv_perm, int* __restrict__ cell_sorted,
-                            float4* __restrict__ xs, int* __restrict__ ts) {
+// One wave per column: rank its atoms by (build z, atom index) - an order
+// that does not depend on the scatter's atomic order - and write the slot
+// data; padding slots of the column's last cluster are emptied.
+__global__ void k_col_sort(const int* __restrict__ gate, const int* __restrict__ col_start,
+                           const int* __restrict__ slot_start, int ncol,
+                           const int* __restrict__ perm_unsorted, const float* __restrict__ pos,
+                           int n, const float* __restrict__ q, const int* __restrict__ atype,
+                           int* __restrict__ perm, int* __restrict__ inv_perm,
+                           float4* __restrict__ xs, int* __restrict__ ts,
+                           float* __restrict__ zb) {
   if (gated_off(gate)) return;
   int c = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   int lane = threadIdx.x & (kWave - 1);
-  if (c >= ncell) return;
-  int b = cell_start[c], e = cell_start[c + 1];
+  if (c >= ncol) return;
+  int b = col_start[c], e = col_start[c + 1];
   int cnt = e - b;
+  int sb = slot_start[c], se = slot_start[c + 1];
   for (int p = lane; p < cnt; p += kWave) {
     int v = perm_unsorted[b + p];
+    float zv = pos[2 * n + v];
     int rank = 0;
-    for (int k = 0; k < cnt; ++k) rank += perm_unsorted[b + k] < v ? 1 : 0;
-    int s = b + rank;
+    for (int k = 0; k < cnt; ++k) {
+      int u = perm_unsorted[b + k];
+      float zu = pos[2 * n + u];
+      rank += (zu < zv || (zu == zv && u < v)) ? 1 : 0;
+    }
+    int s = sb + rank;
     perm[s] = v;
     inv_perm[v] = s;
-    cell_sorted[s] = c;
-    xs[s] = make_float4(pos[v], pos[n + v], pos[2 * n + v], q[v]);
+    xs[s] = make_float4(pos[v], pos[n + v], zv, q[v]);
     ts[s] = atype[v];
+    zb[s] = zv;
+  }
+  for (int s = sb + cnt + lane; s < se; s += kWave) {
+    perm[s] = -1;
+    xs[s] = make_float4(0.f, 0.f, 0.f, 0.f);
+    ts[s] = 0;
+    zb[s] = 3.0e38f;
   }
 }
 
-// Stencil search: one thread per sorted atom i.
-__global__ void __launch_bounds__(256) k_nl_search(
-    const int* __restrict__ gate, const float4* __restrict__ xs, const int* __restrict__ cell_sorted,
-    const int* __restrict__ cell_start, const int* __restrict__ perm,
-    const int* __restrict__ ex_start, const int* __restrict__ ex_idx, int n, int npad, int cap,
-    CellGrid cg, int* __restrict__ nl, int* __restrict__ nl_count, int* __restrict__ nl_needed,
+// Bounding box of every cluster's real atoms at the build positions.
+__global__ void k_cluster_box(const int* __restrict__ gate, const int* __restrict__ meta,
+                              const float4* __restrict__ xs, const int* __restrict__ perm,
+                              float4* __restrict__ box_lo, float4* __restrict__ box_hi) {
+  if (gated_off(gate)) return;
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= meta[1]) return;
+  float lx = 3e38f, ly = 3e38f, lz = 3e38f, hx = -3e38f, hy = -3e38f, hz = -3e38f;
+  int nvalid = 0;
+  for (int k = 0; k < kClusterSize; ++k) {
+    int s = c * kClusterSize + k;
+    if (perm[s] < 0) continue;
+    float4 p = xs[s];
+    lx = fminf(lx, p.x); ly = fminf(ly, p.y); lz = fminf(lz, p.z);
+    hx = fmaxf(hx, p.x); hy = fmaxf(hy, p.y); hz = fmaxf(hz, p.z);
+    ++nvalid;
+  }
+  box_lo[c] = make_float4(lx, ly, lz, (float)nvalid);
+  box_hi[c] = make_float4(hx, hy, hz, 0.f);
+}
+
+// Periodic gap between two intervals along one axis (0 if they overlap).
+__device__ __forceinline__ float axis_gap(float alo, float ahi, float blo, float bhi, float L) {
+  float ca = 0.5f * (alo + ahi), cb = 0.5f * (blo + bhi);
+  float d = fabsf(cb - ca);
+  d = fminf(d, L - d);
+  return fmaxf(0.f, d - 0.5f * (ahi - alo) - 0.5f * (bhi - blo));
+}
+
+constexpr int kSearchCand = 1024;   // bbox-passing j-clusters one i-cluster may have
+constexpr int kSearchCols = 64;     // candidate columns handled per chunk
+
+// One wave per i-cluster: (1) enumerate the j-clusters of the columns within
+// reach and keep those whose boxes come closer than r_nl (+ margin); (2) test
+// the 16 slot pairs of four candidate tiles at once (one lane per pair) with
+// the exact predicate and the exclusions; tiles with a non-empty mask are
+// appended to the i-cluster's list in enumeration order.
+__global__ void __launch_bounds__(256) k_tile_search(
+    const int* __restrict__ gate, const int* __restrict__ meta, const float4* __restrict__ xs,
+    const int* __restrict__ perm, const float4* __restrict__ box_lo,
+    const float4* __restrict__ box_hi, const int* __restrict__ slot_start,
+    const int* __restrict__ ex_start, const int* __restrict__ ex_idx, CellGrid cg, int cap,
+    uint2* __restrict__ tiles, int* __restrict__ tile_count, int* __restrict__ nl_needed,
     unsigned* __restrict__ flags) {
   if (gated_off(gate)) return;
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  float4 pi = xs[i];
-  int ci = cell_sorted[i];
-  int cx = ci % cg.n[0], cy = (ci / cg.n[0]) % cg.n[1], cz = ci / (cg.n[0] * cg.n[1]);
-  int a = perm[i];
-  int eb = ex_start[a], ee = ex_start[a + 1];
-  int cnt = 0;
-  for (int oz = 0; oz < cg.nofs[2]; ++oz) {
-    int z = cz + cg.ofs[2][oz];
-    z += z < 0 ? cg.n[2] : 0;
-    z -= z >= cg.n[2] ? cg.n[2] : 0;
-    for (int oy = 0; oy < cg.nofs[1]; ++oy) {
-      int y = cy + cg.ofs[1][oy];
-      y += y < 0 ? cg.n[1] : 0;
-      y -= y >= cg.n[1] ? cg.n[1] : 0;
-      int row = (z * cg.n[1] + y) * cg.n[0];
-      for (int ox = 0; ox < cg.nofs[0]; ++ox) {
-        int x = cx + cg.ofs[0][ox];
-        x += x < 0 ? cg.n[0] : 0;
-        x -= x >= cg.n[0] ? cg.n[0] : 0;
-        int c = row + x;
-        int jb = cell_start[c], je = cell_start[c + 1];
-        for (int j = jb; j < je; ++j) {
-          if (j == i) continue;
-          float4 pj = xs[j];
-          float dx = min_image(pi.x, pj.x, cg.L[0], cg.hL[0]);
-          float dy = min_image(pi.y, pj.y, cg.L[1], cg.hL[1]);
-          float dz = min_image(pi.z, pj.z, cg.L[2], cg.hL[2]);
-          float r2 = dist2(dx, dy, dz);
-          if (r2 < cg.rnl2) {
-            bool excluded = false;
-            if (ee > eb) {
-              int bj = perm[j];
-              for (int k = eb; k < ee; ++k) excluded |= (ex_idx[k] == bj);
-            }
-            if (!excluded) {
-              if (cnt < cap) nl[(size_t)cnt * npad + i] = j;
-              ++cnt;
-            }
+  __shared__ int cand[4][kSearchCand];
+  __shared__ int col_first[4][kSearchCols + 1];
+  __shared__ int col_pre[4][kSearchCols + 1];
+  const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int ic = blockIdx.x * 4 + w;
+  const int nclu = meta[1];
+  if (ic >= nclu) return;
+  const float4 ilo = box_lo[ic], ihi = box_hi[ic];
+  int* mycand = cand[w];
+  int ncand = 0;
+  bool overflow = false;
+  if (ilo.w > 0.f) {
+    const float reach = cg.r_search;
+    // column ranges (periodic) that can hold a box within reach
+    int cx0 = (int)floorf((ilo.x - reach) * cg.inv_w[0]);
+    int cx1 = (int)floorf((ihi.x + reach) * cg.inv_w[0]);
+    int cy0 = (int)floorf((ilo.y - reach) * cg.inv_w[1]);
+    int cy1 = (int)floorf((ihi.y + reach) * cg.inv_w[1]);
+    int nx = min(cx1 - cx0 + 1, cg.n[0]);
+    int ny = min(cy1 - cy0 + 1, cg.n[1]);
+    if (nx == cg.n[0]) cx0 = 0;
+    if (ny == cg.n[1]) cy0 = 0;
+    const int ncols = nx * ny;
+    const float reach2 = reach * reach;
+    for (int c0 = 0; c0 < ncols; c0 += kSearchCols) {
+      const int nc = min(kSearchCols, ncols - c0);
+      int cnt = 0, first = 0;
+      if (lane < nc) {
+        int t = c0 + lane;
+        int x = cx0 + t % nx, y = cy0 + t / nx;
+        x %= cg.n[0]; x += x < 0 ? cg.n[0] : 0;
+        y %= cg.n[1]; y += y < 0 ? cg.n[1] : 0;
+        int col = y * cg.n[0] + x;
+        first = slot_start[col] / kClusterSize;
+        cnt = slot_start[col + 1] / kClusterSize - first;
+      }
+      // inclusive scan of the cluster counts over the chunk
+      int v = cnt;
+      for (int o = 1; o < kWave; o <<= 1) {
+        int u = __shfl_up(v, o, kWave);
+        if (lane >= o) v += u;
+      }
+      if (lane < nc) {
+        col_first[w][lane] = first;
+        col_pre[w][lane + 1] = v;
+      }
+      if (lane == 0) col_pre[w][0] = 0;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const int total = __shfl(v, nc - 1, kWave);
+      for (int f0 = 0; f0 < total; f0 += kWave) {
+        int f = f0 + lane;
+        bool pass = false;
+        int jc = 0;
+        if (f < total) {
+          int lo = 0, hi = nc - 1;
+          while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (col_pre[w][mid] <= f) lo = mid; else hi = mid - 1;
           }
+          jc = col_first[w][lo] + (f - col_pre[w][lo]);
+          float4 jlo = box_lo[jc], jhi = box_hi[jc];
+          if (jlo.w > 0.f) {
+            float gx = axis_gap(ilo.x, ihi.x, jlo.x, jhi.x, cg.L[0]);
+            float gy = axis_gap(ilo.y, ihi.y, jlo.y, jhi.y, cg.L[1]);
+            float gz = axis_gap(ilo.z, ihi.z, jlo.z, jhi.z, cg.L[2]);
+            pass = gx * gx + gy * gy + gz * gz < reach2;
+          }
+        }
+        unsigned long long m = __ballot(pass);
+        int before = __popcll(m & ((1ull << lane) - 1ull));
+        if (pass) {
+          int slot = ncand + before;
+          if (slot < kSearchCand) mycand[slot] = jc;
+        }
+        ncand += __popcll(m);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (ncand > kSearchCand) {
+      overflow = true;
+      ncand = kSearchCand;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+  // (2) masks: lane = (tile t of 4, i slot a, j slot b)
+  const int t = lane >> 4, a = (lane >> 2) & 3, b = lane & 3;
+  const int si = ic * kClusterSize + a;
+  const int ai = perm[si];
+  const float4 pi = xs[si];
+  const int eb = ai >= 0 ? ex_start[ai] : 0, ee = ai >= 0 ? ex_start[ai + 1] : 0;
+  int count = 0;
+  for (int g = 0; g < ncand; g += 4) {
+    unsigned bit = 0;
+    int jc = -1;
+    if (g + t < ncand) {
+      jc = mycand[g + t];
+      const int sj = jc * kClusterSize + b;
+      const int aj = perm[sj];
+      if (ai >= 0 && aj >= 0 && sj != si) {
+        const float4 pj = xs[sj];
+        float dx = min_image(pi.x, pj.x, cg.L[0], cg.hL[0]);
+        float dy = min_image(pi.y, pj.y, cg.L[1], cg.hL[1]);
+        float dz = min_image(pi.z, pj.z, cg.L[2], cg.hL[2]);
+        if (dist2(dx, dy, dz) < cg.rnl2) {
+          bool excluded = false;
+          for (int k = eb; k < ee; ++k) excluded |= (ex_idx[k] == aj);
+          bit = excluded ? 0u : 1u;
         }
       }
     }
+    unsigned long long m = __ballot(bit != 0);
+    // 16-bit mask of tile t: bits of lanes 16t .. 16t+15, bit index 4a + b
+    unsigned mask = (unsigned)((m >> (16 * t)) & 0xffffull);
+    unsigned long long nonempty = __ballot(b == 0 && a == 0 && mask != 0);
+    int before = __popcll(nonempty & ((1ull << lane) - 1ull));
+    if (a == 0 && b == 0 && mask != 0) {
+      int k = count + before;
+      if (k < cap) tiles[(size_t)ic * cap + k] = make_uint2((unsigned)jc, mask);
+    }
+    count += __popcll(nonempty);
   }
-  nl_count[i] = cnt < cap ? cnt : cap;
-  if (cnt > cap) {
-    atomicOr(flags, MDX_FLAG_NL_OVERFLOW);
+  if (lane == 0) {
+    tile_count[ic] = count < cap ? count : cap;
+    if (count > cap) atomicOr(flags, MDX_FLAG_NL_OVERFLOW);
+    if (overflow) atomicOr(flags, MDX_FLAG_CELL_OVERFLOW);
+    atomicMax(nl_needed, count);
   }
-  atomicMax(nl_needed, cnt);
 }
 
-// Copy the current positions into the sorted float4 array and test the
-// list's validity: an atom that moved more than r_g/2 since the build
-// invalidates the list (Sec. II.A.2). Without a gate this latches
-// NL_STALE; with one it requests a rebuild before the forces are taken.
+// Copy the current positions into the slot array and test the list's
+// validity: an atom that moved more than r_g/2 since the build invalidates
+// the list (Sec. II.A.2). Without a gate this latches NL_STALE; with one it
+// requests a rebuild before the forces are taken.
 __global__ void k_refresh(const float* __restrict__ pos, const int* __restrict__ perm,
-                          const float* __restrict__ q, const float* __restrict__ x_build, int n,
-                          CellGrid cg, float half_skin2, float4* __restrict__ xs,
-                          unsigned* __restrict__ flags, int* __restrict__ gate,
-                          int force_rebuild) {
+                          const float* __restrict__ q, const float* __restrict__ x_build,
+                          const int* __restrict__ meta, int n, CellGrid cg, float half_skin2,
+                          float4* __restrict__ xs, unsigned* __restrict__ flags,
+                          int* __restrict__ gate, int force_rebuild) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (gate && force_rebuild && s == 0) *gate = 1;
-  if (s >= n) return;
+  if (s >= meta[0]) return;
   int a = perm[s];
+  if (a < 0) return;
   float x = pos[a], y = pos[n + a], z = pos[2 * n + a];
   xs[s] = make_float4(x, y, z, q[a]);
   bool inside = x >= 0.f && x < cg.L[0] && y >= 0.f && y < cg.L[1] && z >= 0.f && z < cg.L[2];
@@ -239,25 +390,28 @@ hipError_t launch_build_list(Ctx& c, const float* pos, const int* gate) {
   hipStream_t s = c.stream;
   const int n = c.n;
   const int nb = (n + 255) / 256;
-  const int ncell = c.cg.ncell;
-  k_prepare<<<(ncell + 255) / 256, 256, 0, s>>>(gate, c.cell_count, ncell, c.nl_needed);
+  const int ncol = c.cg.ncell;
+  k_prepare<<<(ncol + 255) / 256, 256, 0, s>>>(gate, c.cell_count, ncol, c.nl_needed);
   k_bin<<<nb, 256, 0, s>>>(gate, pos, n, c.cg, c.cell_of, c.cell_count, c.x_build, c.flags);
-  k_scan<<<1, 1024, 0, s>>>(gate, c.cell_count, ncell, c.cell_start, c.cell_cursor);
+  k_scan<<<1, 1024, 0, s>>>(gate, c.cell_count, ncol, c.cell_start, c.cell_cursor, c.slot_start,
+                            c.meta);
   k_scatter<<<nb, 256, 0, s>>>(gate, c.cell_of, n, c.cell_cursor, c.perm_unsorted);
-  k_cell_sort<<<(ncell + 3) / 4, 256, 0, s>>>(gate, c.cell_start, ncell, c.perm_unsorted, pos, n,
-                                              c.q, c.atype, c.perm, c.inv_perm, c.cell_sorted,
-                                              c.xs, c.ts);
-  k_nl_search<<<nb, 256, 0, s>>>(gate, c.xs, c.cell_sorted, c.cell_start, c.perm, c.ex_start,
-                                 c.ex_idx, n, c.npad, c.nl_cap, c.cg, c.nl, c.nl_count,
-                                 c.nl_needed, c.flags);
+  k_col_sort<<<(ncol + 3) / 4, 256, 0, s>>>(gate, c.cell_start, c.slot_start, ncol,
+                                            c.perm_unsorted, pos, n, c.q, c.atype, c.perm,
+                                            c.inv_perm, c.xs, c.ts, c.zb);
+  k_cluster_box<<<(c.max_clusters + 255) / 256, 256, 0, s>>>(gate, c.meta, c.xs, c.perm,
+                                                             c.box_lo, c.box_hi);
+  k_tile_search<<<(c.max_clusters + 3) / 4, 256, 0, s>>>(
+      gate, c.meta, c.xs, c.perm, c.box_lo, c.box_hi, c.slot_start, c.ex_start, c.ex_idx, c.cg,
+      c.nl_cap, c.tiles, c.tile_count, c.nl_needed, c.flags);
   return hipGetLastError();
 }
 
 hipError_t launch_refresh_sorted(Ctx& c, const float* pos, int* gate, bool force_rebuild) {
-  const int n = c.n;
   float h = 0.5f * c.r_ghost;
-  k_refresh<<<(n + 255) / 256, 256, 0, c.stream>>>(pos, c.perm, c.q, c.x_build, n, c.cg, h * h,
-                                                   c.xs, c.flags, gate, force_rebuild ? 1 : 0);
+  k_refresh<<<(c.max_slots + 255) / 256, 256, 0, c.stream>>>(pos, c.perm, c.q, c.x_build, c.meta,
+                                                             c.n, c.cg, h * h, c.xs, c.flags,
+                                                             gate, force_rebuild ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -1,10 +1,14 @@
 // Short-range forces (DIMOS Sec. II.A.1-2).
 //
-// k_pair: one lane per cell-sorted atom i walks its full Verlet row (Eqs. 4-5
-//   LJ with Lorentz-Berthelot mixing, optional Eq. 6 switch, and the
-//   minimum-image real-space Ewald term of Eq. 10). Every pair is evaluated
-//   from both ends, so each lane owns its force outright: no atomics, and the
-//   result is bitwise reproducible. Energies are accumulated per lane in FP64.
+// k_pair: one wave per 4-atom i-cluster streams its list of 4x4 cluster
+//   tiles four at a time: lane = (i slot, tile, j slot), i.e. the wave's four
+//   16-lane rows each hold one i atom against 16 j atoms. Per pair: LJ
+//   (Eqs. 4-5, type-pair table, optional Eq. 6 switch) + the minimum-image
+//   real-space Ewald term (Eq. 10) for pairs whose mask bit is set and with
+//   r2 < fl(r_c^2). A group of tiles with no such pair is skipped after the
+//   distance test. The list holds both directions of every pair, so each
+//   row only accumulates its own i force: a 16-lane row reduction at the end,
+//   no atomics, bitwise reproducible. Energies accumulate per lane in FP64.
 // k_bonded_excl: one thread per caller atom for the terms that involve it:
 //   the FP64 erf exclusion correction and FP32 harmonic bonds/angles (Eqs. 1-2).
 //   Each term's energy is booked once, by a designated member atom.
@@ -30,32 +34,41 @@ struct PairParams {
 template <bool ENERGY, bool COUL, bool SWITCH>
 __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
                                               const int* __restrict__ ts,
-                                              const int* __restrict__ nl_count,
-                                              const int* __restrict__ nl, int n, int npad,
+                                              const uint2* __restrict__ tiles,
+                                              const int* __restrict__ tile_count,
+                                              const int* __restrict__ meta, int cap,
                                               PairParams pp, const float4* __restrict__ lj_f,
                                               const double2* __restrict__ lj_d,
-                                              const int* __restrict__ perm,
+                                              const int* __restrict__ perm, int n,
                                               float* __restrict__ force,
                                               double* __restrict__ partials, int pstride) {
   __shared__ double red[16];
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  bool active = i < n;
+  const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int ic = blockIdx.x * 4 + w;
+  const bool active = ic < meta[1];
+  const int ia = lane >> 4, tt = (lane >> 2) & 3, jb = lane & 3;
+  const int si = ic * kClusterSize + ia;
+  const unsigned bitpos = (unsigned)(ia * kClusterSize + jb);
   float fx = 0.f, fy = 0.f, fz = 0.f;
   double e_lj = 0.0, e_c = 0.0;
   if (active) {
-    float4 pi = xs[i];
-    const int trow = ts[i] * pp.ntypes;
-    int cnt = nl_count[i];
-    const int* row = nl + i;
-    for (int k = 0; k < cnt; ++k) {
-      int j = row[(size_t)k * npad];
-      float4 pj = xs[j];
+    const float4 pi = xs[si];
+    const int trow = ts[si] * pp.ntypes;
+    const int cnt = tile_count[ic];
+    const uint2* tl = tiles + (size_t)ic * cap;
+    for (int g = 0; g < cnt; g += 4) {
+      uint2 e = (g + tt < cnt) ? tl[g + tt] : make_uint2(0u, 0u);
+      const bool on = (e.y >> bitpos) & 1u;
+      const int sj = (int)e.x * kClusterSize + jb;
+      const float4 pj = xs[sj];
       float dx = min_image(pi.x, pj.x, pp.L[0], pp.hL[0]);
       float dy = min_image(pi.y, pj.y, pp.L[1], pp.hL[1]);
       float dz = min_image(pi.z, pj.z, pp.L[2], pp.hL[2]);
       float r2 = dist2(dx, dy, dz);
-      if (r2 < pp.rc2) {
-        const int tp = trow + ts[j];
+      const bool in = on && r2 < pp.rc2;
+      if (__ballot(in) == 0ull) continue;
+      if (in) {
+        const int tp = trow + ts[sj];
         float4 lj = lj_f[tp];             // c12, c6, 12 c12, 6 c6
         float rinv2 = 1.0f / r2;
         float r6 = rinv2 * rinv2 * rinv2;
@@ -95,10 +108,20 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
         }
       }
     }
-    int a = perm[i];
-    force[a] = fx;
-    force[n + a] = fy;
-    force[2 * n + a] = fz;
+  }
+  // sum the i force over the 16 lanes of the row
+  for (int o = 8; o >= 1; o >>= 1) {
+    fx += __shfl_xor(fx, o, kWave);
+    fy += __shfl_xor(fy, o, kWave);
+    fz += __shfl_xor(fz, o, kWave);
+  }
+  if (active && (lane & 15) == 0) {
+    int a = perm[si];
+    if (a >= 0) {
+      force[a] = fx;
+      force[n + a] = fy;
+      force[2 * n + a] = fz;
+    }
   }
   if (ENERGY) {
     // every pair was visited from both ends
@@ -273,11 +296,11 @@ hipError_t launch_nonbonded(Ctx& c, float* force, bool energy) {
   pp.r_s = c.switch_r;
   pp.r_c = c.r_cut;
   pp.inv_sw = c.has_switch ? 1.0f / (c.r_cut - c.switch_r) : 0.f;
-  const int nb = (c.n + 255) / 256;
+  const int nb = (c.max_clusters + 3) / 4;
   c.nb_blocks = nb;
-#define MDX_PAIR(E, C, S)                                                                   \
-  k_pair<E, C, S><<<nb, 256, 0, c.stream>>>(c.xs, c.ts, c.nl_count, c.nl, c.n, c.npad, pp, \
-                                             c.lj_f, c.lj_d, c.perm, force, c.partials,      \
+#define MDX_PAIR(E, C, S)                                                                       \
+  k_pair<E, C, S><<<nb, 256, 0, c.stream>>>(c.xs, c.ts, c.tiles, c.tile_count, c.meta, c.nl_cap, \
+                                             pp, c.lj_f, c.lj_d, c.perm, c.n, force, c.partials, \
                                              c.max_blocks)
   bool C = c.has_coulomb, S = c.has_switch;
   if (energy) {

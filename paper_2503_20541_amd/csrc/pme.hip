@@ -1,7 +1,9 @@
 // Smooth particle-mesh Ewald (DIMOS Sec. II.A.2, PME paragraph).
 //
 //  k_pme_spread   one workgroup per grid brick; candidate atoms come from the
-//                 cell list (cells within spline reach + r_g/2 of the brick).
+//                 column sort: columns within spline reach + r_g/2 of the
+//                 brick, and in each the slots whose build z is in reach
+//                 (binary search, the column is sorted by build z).
 //                 Lanes first compute one atom's B-spline weights each, then
 //                 the wave walks the atoms one by one with lanes = the 4x4x4
 //                 stencil points, adding into its own LDS copy of the brick
@@ -73,9 +75,19 @@ constexpr int kMaxBrick = 512;       // B_x * B_y * B_z
 constexpr int kMaxCandCells = 512;
 constexpr int kStage = 16;           // floats staged per atom
 
+__device__ __forceinline__ int lower_bound_f(const float* __restrict__ a, int lo, int hi, float v) {
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (a[mid] < v) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
 __global__ void __launch_bounds__(kSpreadThreads) k_pme_spread(
-    const float4* __restrict__ xs, const int* __restrict__ cell_start,
-    const int* __restrict__ brick_cells, PmeParams pp, CellGrid cg, float* __restrict__ grid_q) {
+    const float4* __restrict__ xs, const int* __restrict__ slot_start,
+    const int* __restrict__ col_count, const float* __restrict__ zb,
+    const int* __restrict__ brick_cols, const float* __restrict__ brick_z, PmeParams pp,
+    CellGrid cg, float* __restrict__ grid_q) {
   __shared__ float lgrid[kSpreadWaves][kMaxBrick];
   __shared__ float stage[kSpreadWaves][kWave * kStage];
   __shared__ int cand_start[kMaxCandCells];
@@ -87,22 +99,37 @@ __global__ void __launch_bounds__(kSpreadThreads) k_pme_spread(
   const int g0[3] = {bx * pp.B[0], by * pp.B[1], bz * pp.B[2]};
   int beff[3];
   for (int d = 0; d < 3; ++d) beff[d] = min(pp.B[d], pp.K[d] - g0[d]);
-  // candidate cells: per dimension (first, count) from the host table
-  const int* bcx = brick_cells + 2 * bx;
-  const int* bcy = brick_cells + 2 * pp.nb[0] + 2 * by;
-  const int* bcz = brick_cells + 2 * (pp.nb[0] + pp.nb[1]) + 2 * bz;
-  const int ncx = bcx[1], ncy = bcy[1], ncz = bcz[1];
-  const int ncand = ncx * ncy * ncz;
+  // candidate columns (first, count along x and y) and the z reach
+  const int* bcx = brick_cols + 2 * bx;
+  const int* bcy = brick_cols + 2 * pp.nb[0] + 2 * by;
+  const float zlo = brick_z[2 * bz], zhi = brick_z[2 * bz + 1];
+  const float Lz = cg.L[2];
+  const int ncx = bcx[1], ncy = bcy[1];
+  const int ncol = ncx * ncy;
+  const int ncand = 2 * ncol;    // up to two z segments per column (periodic wrap)
 
   for (int t = threadIdx.x; t < kSpreadWaves * kMaxBrick; t += blockDim.x)
     (&lgrid[0][0])[t] = 0.f;
-  for (int t = threadIdx.x; t < ncand; t += blockDim.x) {
-    int ix = t % ncx, iy = (t / ncx) % ncy, iz = t / (ncx * ncy);
-    int cx = (bcx[0] + ix) % cg.n[0], cy = (bcy[0] + iy) % cg.n[1],
-        cz = (bcz[0] + iz) % cg.n[2];
-    int c = (cz * cg.n[1] + cy) * cg.n[0] + cx;
-    cand_start[t] = cell_start[c];
-    cand_off[t + 1] = cell_start[c + 1] - cell_start[c];
+  for (int t = threadIdx.x; t < ncol; t += blockDim.x) {
+    int cx = (bcx[0] + t % ncx) % cg.n[0], cy = (bcy[0] + t / ncx) % cg.n[1];
+    int col = cy * cg.n[0] + cx;
+    int sb = slot_start[col], se = sb + col_count[col];
+    float a0 = zlo, b0 = zhi, a1 = 0.f, b1 = 0.f;
+    if (zlo < 0.f) {
+      a0 = 0.f; b0 = zhi; a1 = zlo + Lz; b1 = Lz;
+    } else if (zhi > Lz) {
+      a0 = zlo; b0 = Lz; a1 = 0.f; b1 = zhi - Lz;
+    }
+    int s0 = lower_bound_f(zb, sb, se, a0), e0 = lower_bound_f(zb, sb, se, b0);
+    int s1 = sb, e1 = sb;
+    if (b1 > a1) {
+      s1 = lower_bound_f(zb, sb, se, a1);
+      e1 = lower_bound_f(zb, sb, se, b1);
+    }
+    cand_start[2 * t] = s0;
+    cand_off[2 * t + 1] = max(0, e0 - s0);
+    cand_start[2 * t + 1] = s1;
+    cand_off[2 * t + 2] = max(0, e1 - s1);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -401,12 +428,16 @@ __global__ void __launch_bounds__(256) k_fft_cols(float2* __restrict__ grid, Pme
   }
 }
 
+// One thread per slot (padding slots return): F = -k_e q grad(theta) . phi.
 __global__ void __launch_bounds__(256) k_pme_gather(const float4* __restrict__ xs,
                                                     const int* __restrict__ perm,
+                                                    const int* __restrict__ meta,
                                                     const float* __restrict__ phi, int n,
                                                     PmeParams pp, float* __restrict__ force) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n) return;
+  if (s >= meta[0]) return;
+  const int a = perm[s];
+  if (a < 0) return;
   float4 p = xs[s];
   float xyz[3] = {p.x, p.y, p.z};
   int k0[3];
@@ -438,7 +469,6 @@ __global__ void __launch_bounds__(256) k_pme_gather(const float4* __restrict__ x
     }
   }
   float c = -pp.coulomb_k * p.w;
-  int a = perm[s];
   force[a] += c * gx * (pp.s_hi[0] + pp.s_lo[0]);
   force[n + a] += c * gy * (pp.s_hi[1] + pp.s_lo[1]);
   force[2 * n + a] += c * gz * (pp.s_hi[2] + pp.s_lo[2]);
@@ -482,8 +512,8 @@ hipError_t launch_pme(Ctx& c, float* force, bool energy) {
   pp.exp_fac = M_PI * M_PI / (c.alpha * c.alpha);
   pp.inv_piV = c.pme_energy_scale;
   hipStream_t s = c.stream;
-  k_pme_spread<<<g.nbrick, kSpreadThreads, 0, s>>>(c.xs, c.cell_start, c.brick_cells, pp, c.cg,
-                                                   c.grid_q);
+  k_pme_spread<<<g.nbrick, kSpreadThreads, 0, s>>>(c.xs, c.slot_start, c.cell_count, c.zb,
+                                                   c.brick_cols, c.brick_z, pp, c.cg, c.grid_q);
   FftPlan px = make_plan(g.K[0]), py = make_plan(g.K[1]), pz = make_plan(g.K[2]);
   const int rows = g.K[1] * g.K[2];
   int P = pencils_for(g.K[0]);
@@ -506,7 +536,8 @@ hipError_t launch_pme(Ctx& c, float* force, bool energy) {
                                                  c.mrec[2], c.partials, c.max_blocks);
   k_fft_rows_c2r<<<(rows + P - 1) / P, 256, sh, s>>>(c.grid_c, c.grid_phi, rows, P, g.Kxh, px,
                                                      c.tw[0]);
-  k_pme_gather<<<(c.n + 255) / 256, 256, 0, s>>>(c.xs, c.perm, c.grid_phi, c.n, pp, force);
+  k_pme_gather<<<(c.max_slots + 255) / 256, 256, 0, s>>>(c.xs, c.perm, c.meta, c.grid_phi, c.n,
+                                                          pp, force);
   return hipGetLastError();
 }
 

@@ -79,20 +79,23 @@ void build_csr(int n, const std::vector<std::pair<int, int>>& items, std::vector
 // Cubic B-spline value at the integers 1, 2, 3 (uniform basis).
 double m4_at(int k) { return k == 2 ? 2.0 / 3.0 : (k == 1 || k == 3 ? 1.0 / 6.0 : 0.0); }
 
-int default_capacity(int n, const float box[3], float r_list) {
+// Tiles per i-cluster: clusters whose boxes lie within r_list of a box of
+// edge ~a, with headroom.
+int default_capacity(int n, const float box[3], float r_list, double a, int max_clusters) {
   double V = (double)box[0] * box[1] * box[2];
   double rho = n / V;
-  double expect = rho * 4.0 / 3.0 * M_PI * (double)r_list * r_list * r_list;
-  int cap = (int)std::ceil(1.35 * expect + 32.0);
+  double r = (double)r_list + a;
+  double expect = rho * 4.0 / 3.0 * M_PI * r * r * r / mdx::kClusterSize;
+  int cap = (int)std::ceil(1.5 * expect + 16.0);
   cap = (cap + 15) / 16 * 16;
-  return std::min(cap, std::max(16, (n + 15) / 16 * 16));
+  return std::max(16, std::min(cap, (max_clusters + 15) / 16 * 16));
 }
 
 int alloc_list(mdx_ctx* x, int cap) {
   Ctx& c = x->c;
-  dev_free(x, c.nl);
-  c.nl = nullptr;
-  int rc = dev_alloc(x, &c.nl, (size_t)cap * c.npad);
+  dev_free(x, c.tiles);
+  c.tiles = nullptr;
+  int rc = dev_alloc(x, &c.tiles, (size_t)cap * c.max_clusters);
   if (rc != MDX_OK) return rc;
   c.nl_cap = cap;
   return MDX_OK;
@@ -111,37 +114,48 @@ int setup_pme(mdx_ctx* x, const mdx_system_desc* d) {
   }
   g.Kxh = g.K[0] / 2 + 1;
   g.nbrick = g.nb[0] * g.nb[1] * g.nb[2];
-  double wmin = 1e30;
-  for (int k = 0; k < 3; ++k) wmin = std::min(wmin, (double)c.box[k] / c.cg.n[k]);
-  g.disp_max = (float)(0.5 * (double)c.r_ghost * 1.001 + 1e-4 * wmin);
+  g.disp_max = (float)(0.5 * (double)c.r_ghost * 1.001 + 1e-3);
 
-  // candidate cells per brick and dimension: cells that can hold an atom whose
-  // spline support reaches the brick, allowing r_g/2 of motion since the build
+  // Per brick index: the columns (along x and y) and the build-z range that can
+  // hold an atom whose spline support reaches the brick, allowing r_g/2 of
+  // motion since the build.
   std::vector<int> bc;
-  int maxc[3] = {0, 0, 0};
+  std::vector<float> bz;
+  int maxc[2] = {0, 0};
   for (int k = 0; k < 3; ++k) {
-    double L = c.box[k], w = L / c.cg.n[k], h = L / g.K[k];
+    double L = c.box[k], h = L / g.K[k];
     for (int b = 0; b < g.nb[k]; ++b) {
       int g0 = b * g.B[k];
       int beff = std::min(g.B[k], g.K[k] - g0);
       double lo = g0 * h - g.disp_max;
       double hi = (g0 + beff + 3) * h + g.disp_max;
-      long first = (long)std::floor(lo / w);
-      long last = (long)std::floor(hi / w);
-      long count = last - first + 1;
-      if (count >= c.cg.n[k]) {
-        first = 0;
-        count = c.cg.n[k];
+      if (k < 2) {
+        double w = L / c.cg.n[k];
+        long first = (long)std::floor(lo / w);
+        long last = (long)std::floor(hi / w);
+        long count = last - first + 1;
+        if (count >= c.cg.n[k]) {
+          first = 0;
+          count = c.cg.n[k];
+        }
+        first = ((first % c.cg.n[k]) + c.cg.n[k]) % c.cg.n[k];
+        bc.push_back((int)first);
+        bc.push_back((int)count);
+        maxc[k] = std::max(maxc[k], (int)count);
+      } else {
+        if (hi - lo >= L) {
+          lo = 0.0;
+          hi = L;
+        }
+        bz.push_back((float)lo);
+        bz.push_back((float)hi);
       }
-      first = ((first % c.cg.n[k]) + c.cg.n[k]) % c.cg.n[k];
-      bc.push_back((int)first);
-      bc.push_back((int)count);
-      maxc[k] = std::max(maxc[k], (int)count);
     }
   }
-  if ((long)maxc[0] * maxc[1] * maxc[2] > 512) return MDX_E_UNSUPPORTED;
-  int rc = dev_upload(x, &c.brick_cells, bc);
+  if ((long)maxc[0] * maxc[1] > 256) return MDX_E_UNSUPPORTED;
+  int rc = dev_upload(x, &c.brick_cols, bc);
   if (rc != MDX_OK) return rc;
+  if ((rc = dev_upload(x, &c.brick_z, bz)) != MDX_OK) return rc;
 
   for (int k = 0; k < 3; ++k) {
     const int K = g.K[k];
@@ -194,7 +208,6 @@ int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
   if (d->switch_r > 0.f && !(d->switch_r < d->r_cut)) return MDX_E_INVALID;
 
   c.n = n;
-  c.npad = (n + mdx::kWave - 1) / mdx::kWave * mdx::kWave;
   for (int k = 0; k < 3; ++k) c.box[k] = d->box[k];
   c.r_cut = d->r_cut;
   c.r_ghost = d->r_ghost;
@@ -227,27 +240,29 @@ int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
   }
   c.has_pme = want_pme && c.has_coulomb;
 
-  // ---- cell grid and predicate constants ----
+  // ---- column grid and predicate constants ----
+  // Columns of edge ~ the cube that holds one cluster of atoms (scaled by
+  // 2/cell_divisions); the list does not depend on this choice.
   mdx::CellGrid& g = c.cg;
+  const double rho = n / ((double)c.box[0] * c.box[1] * c.box[2]);
+  const double a_clu = std::cbrt(mdx::kClusterSize / rho);
+  const double wcol = a_clu * 2.0 / cdiv;
   g.ncell = 1;
   for (int k = 0; k < 3; ++k) {
-    int nk = (int)std::floor((double)cdiv * c.box[k] / ((double)c.r_list * (1.0 + 1e-4)));
-    if (nk < 1) nk = 1;
+    int nk = k < 2 ? (int)std::floor((double)c.box[k] / wcol) : 1;
+    nk = std::max(1, std::min(nk, 4096));
     g.n[k] = nk;
     g.ncell *= nk;
     g.L[k] = c.box[k];
     g.hL[k] = c.box[k] * 0.5f;
     g.inv_w[k] = (float)nk / c.box[k];
-    if (nk >= 2 * cdiv + 1) {
-      g.nofs[k] = 2 * cdiv + 1;
-      for (int o = 0; o < g.nofs[k]; ++o) g.ofs[k][o] = o - cdiv;
-    } else {
-      g.nofs[k] = nk;
-      for (int o = 0; o < nk; ++o) g.ofs[k][o] = o;
-    }
   }
   g.rnl2 = c.r_list * c.r_list;
   g.rc2 = c.r_cut * c.r_cut;
+  g.r_search = c.r_list * 1.001f + 1e-4f;
+  c.max_slots = n + (mdx::kClusterSize - 1) * g.ncell;
+  c.max_slots = (c.max_slots + mdx::kClusterSize - 1) / mdx::kClusterSize * mdx::kClusterSize;
+  c.max_clusters = c.max_slots / mdx::kClusterSize;
 
   // ---- per-atom parameters and the LJ type-pair table (Eqs. 4-5) ----
   std::vector<float> q(n), am(n), ms(n);
@@ -351,32 +366,39 @@ int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
   if ((rc = dev_upload(x, &c.at_start, st)) != MDX_OK) return rc;
   if ((rc = dev_upload(x, &c.at_idx, ix)) != MDX_OK) return rc;
 
-  // ---- cell list and neighbour list storage ----
+  // ---- column sort, cluster slots and tile list storage ----
+  const int ncol = g.ncell;
   if ((rc = dev_alloc(x, &c.cell_of, n)) != MDX_OK) return rc;
-  if ((rc = dev_alloc(x, &c.cell_count, g.ncell)) != MDX_OK) return rc;
-  if ((rc = dev_alloc(x, &c.cell_start, g.ncell + 1)) != MDX_OK) return rc;
-  if ((rc = dev_alloc(x, &c.cell_cursor, g.ncell)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.cell_count, ncol)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.cell_start, ncol + 1)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.cell_cursor, ncol)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.slot_start, ncol + 1)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.meta, 2)) != MDX_OK) return rc;
+  MDX_TRY(hipMemset(c.meta, 0, 2 * sizeof(int)));
   if ((rc = dev_alloc(x, &c.perm_unsorted, n)) != MDX_OK) return rc;
-  if ((rc = dev_alloc(x, &c.perm, n)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.perm, c.max_slots)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.inv_perm, n)) != MDX_OK) return rc;
-  if ((rc = dev_alloc(x, &c.cell_sorted, n)) != MDX_OK) return rc;
-  if ((rc = dev_alloc(x, &c.xs, n)) != MDX_OK) return rc;
-  if ((rc = dev_alloc(x, &c.ts, n)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.xs, c.max_slots)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.ts, c.max_slots)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.zb, c.max_slots)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.box_lo, c.max_clusters)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.box_hi, c.max_clusters)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.x_build, (size_t)3 * n)) != MDX_OK) return rc;
-  if ((rc = dev_alloc(x, &c.nl_count, n)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.tile_count, c.max_clusters)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.nl_needed, 1)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.flags, 1)) != MDX_OK) return rc;
   MDX_TRY(hipMemset(c.flags, 0, sizeof(unsigned)));
   if ((rc = dev_alloc(x, &c.gate, 1)) != MDX_OK) return rc;
   MDX_TRY(hipMemset(c.gate, 0, sizeof(int)));
-  int cap = d->nl_capacity > 0 ? d->nl_capacity : default_capacity(n, c.box, c.r_list);
+  int cap = d->nl_capacity > 0 ? d->nl_capacity
+                               : default_capacity(n, c.box, c.r_list, a_clu, c.max_clusters);
   if ((rc = alloc_list(x, cap)) != MDX_OK) return rc;
 
   if (c.has_pme) {
     if ((rc = setup_pme(x, d)) != MDX_OK) return rc;
   }
   // ---- reductions ----
-  int mb = (n + 255) / 256;
+  int mb = std::max((n + 255) / 256, (c.max_clusters + 3) / 4);
   if (c.has_pme) {
     int ntile = (c.pg.Kxh + 15) / 16;
     mb = std::max(mb, c.pg.K[1] * ntile);
@@ -479,6 +501,9 @@ int mdx_build_neighbors(mdx_ctx* x, const float* pos) {
     MDX_TRY(hipMemcpyAsync(&needed, c.nl_needed, sizeof(int), hipMemcpyDeviceToHost, c.stream));
     MDX_TRY(hipStreamSynchronize(c.stream));
     c.steps_since_build = 0;
+    unsigned fl0 = 0;
+    MDX_TRY(hipMemcpy(&fl0, c.flags, sizeof(unsigned), hipMemcpyDeviceToHost));
+    if (fl0 & MDX_FLAG_CELL_OVERFLOW) return MDX_E_UNSUPPORTED;
     if (needed <= c.nl_cap) return MDX_OK;
     // grow, clear the overflow bit this build latched, and build again
     int rc = alloc_list(x, (needed + needed / 8 + 16 + 15) / 16 * 16);
@@ -496,16 +521,26 @@ int mdx_get_neighbor_pairs(mdx_ctx* x, int32_t* pairs_host, int64_t cap, int64_t
   Ctx& c = x->c;
   if (c.steps_since_build < 0) return MDX_E_NO_LIST;
   MDX_TRY(hipStreamSynchronize(c.stream));
-  const int n = c.n;
-  std::vector<int> cnt(n), perm(n), nl((size_t)c.nl_cap * c.npad);
-  MDX_TRY(hipMemcpy(cnt.data(), c.nl_count, sizeof(int) * n, hipMemcpyDeviceToHost));
-  MDX_TRY(hipMemcpy(perm.data(), c.perm, sizeof(int) * n, hipMemcpyDeviceToHost));
-  MDX_TRY(hipMemcpy(nl.data(), c.nl, sizeof(int) * nl.size(), hipMemcpyDeviceToHost));
+  int meta[2];
+  MDX_TRY(hipMemcpy(meta, c.meta, sizeof(meta), hipMemcpyDeviceToHost));
+  const int nslot = meta[0], nclu = meta[1];
+  std::vector<int> perm(nslot), cnt(nclu);
+  std::vector<uint2> tl((size_t)nclu * c.nl_cap);
+  if (nslot > 0) {
+    MDX_TRY(hipMemcpy(perm.data(), c.perm, sizeof(int) * nslot, hipMemcpyDeviceToHost));
+    MDX_TRY(hipMemcpy(cnt.data(), c.tile_count, sizeof(int) * nclu, hipMemcpyDeviceToHost));
+    MDX_TRY(hipMemcpy(tl.data(), c.tiles, sizeof(uint2) * tl.size(), hipMemcpyDeviceToHost));
+  }
   std::vector<std::pair<int, int>> pairs;
-  for (int i = 0; i < n; ++i)
-    for (int k = 0; k < cnt[i]; ++k) {
-      int a = perm[i], b = perm[nl[(size_t)k * c.npad + i]];
-      if (a < b) pairs.push_back({a, b});
+  for (int ic = 0; ic < nclu; ++ic)
+    for (int k = 0; k < cnt[ic]; ++k) {
+      const uint2 e = tl[(size_t)ic * c.nl_cap + k];
+      for (int bit = 0; bit < 16; ++bit) {
+        if (!((e.y >> bit) & 1u)) continue;
+        int a = perm[ic * mdx::kClusterSize + bit / 4];
+        int b = perm[(int)e.x * mdx::kClusterSize + bit % 4];
+        if (a < b) pairs.push_back({a, b});
+      }
     }
   std::sort(pairs.begin(), pairs.end());
   *n_out = (int64_t)pairs.size();
