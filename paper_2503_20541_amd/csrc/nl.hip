@@ -38,6 +38,26 @@ __device__ __forceinline__ int bin_coord(float x, float inv_w, int n) {
 
 __device__ __forceinline__ bool gated_off(const int* gate) { return gate && *gate == 0; }
 
+// atomicAdd(&ctr[key], 1) for every active lane, aggregated over the lanes of
+// the wave that share a key (one atomic per distinct key); returns the value
+// this lane would have seen (leader's old value + rank among equal keys).
+__device__ __forceinline__ int wave_aggregated_inc(int* __restrict__ ctr, int key, bool active) {
+  const int lane = threadIdx.x & (kWave - 1);
+  unsigned long long todo = __ballot(active);
+  int result = 0;
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const int lkey = __shfl(key, leader, kWave);
+    const unsigned long long same = __ballot(active && key == lkey);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&ctr[lkey], __popcll(same));
+    base = __shfl(base, leader, kWave);
+    if (active && key == lkey) result = base + __popcll(same & ((1ull << lane) - 1ull));
+    todo &= ~same;
+  }
+  return result;
+}
+
 __global__ void k_prepare(const int* __restrict__ gate, int* __restrict__ col_count, int ncol,
                           int* __restrict__ nl_needed) {
   if (gated_off(gate)) return;
@@ -52,18 +72,21 @@ __global__ void k_bin(const int* __restrict__ gate, const float* __restrict__ po
                       float* __restrict__ x_build, unsigned* __restrict__ flags) {
   if (gated_off(gate)) return;
   int a = blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= n) return;
-  float x = pos[a], y = pos[n + a], z = pos[2 * n + a];
-  bool inside = x >= 0.f && x < cg.L[0] && y >= 0.f && y < cg.L[1] && z >= 0.f && z < cg.L[2];
-  if (!inside) atomicOr(flags, MDX_FLAG_OUT_OF_BOX);
-  int cx = bin_coord(x, cg.inv_w[0], cg.n[0]);
-  int cy = bin_coord(y, cg.inv_w[1], cg.n[1]);
-  int c = cy * cg.n[0] + cx;
-  col_of[a] = c;
-  atomicAdd(&col_count[c], 1);
-  x_build[a] = x;
-  x_build[n + a] = y;
-  x_build[2 * n + a] = z;
+  const bool active = a < n;
+  int c = 0;
+  if (active) {
+    float x = pos[a], y = pos[n + a], z = pos[2 * n + a];
+    bool inside = x >= 0.f && x < cg.L[0] && y >= 0.f && y < cg.L[1] && z >= 0.f && z < cg.L[2];
+    if (!inside) atomicOr(flags, MDX_FLAG_OUT_OF_BOX);
+    int cx = bin_coord(x, cg.inv_w[0], cg.n[0]);
+    int cy = bin_coord(y, cg.inv_w[1], cg.n[1]);
+    c = cy * cg.n[0] + cx;
+    col_of[a] = c;
+    x_build[a] = x;
+    x_build[n + a] = y;
+    x_build[2 * n + a] = z;
+  }
+  (void)wave_aggregated_inc(col_count, c, active);
 }
 
 // Exclusive scans of the column counts (atoms) and of the counts rounded up
@@ -129,36 +152,65 @@ __global__ void k_scatter(const int* __restrict__ gate, const int* __restrict__ 
                           int* __restrict__ cursor, int* __restrict__ perm_unsorted) {
   if (gated_off(gate)) return;
   int a = blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= n) return;
-  int slot = atomicAdd(&cursor[col_of[a]], 1);
-  perm_unsorted[slot] = a;
+  const bool active = a < n;
+  const int c = active ? col_of[a] : 0;
+  const int slot = wave_aggregated_inc(cursor, c, active);
+  if (active) perm_unsorted[slot] = a;
 }
 
 // One wave per column: rank its atoms by (build z, atom index) - an order
 // that does not depend on the scatter's atomic order - and write the slot
-// data; padding slots of the column's last cluster are emptied.
-__global__ void k_col_sort(const int* __restrict__ gate, const int* __restrict__ col_start,
-                           const int* __restrict__ slot_start, int ncol,
-                           const int* __restrict__ perm_unsorted, const float* __restrict__ pos,
-                           int n, const float* __restrict__ q, const int* __restrict__ atype,
-                           int* __restrict__ perm, int* __restrict__ inv_perm,
-                           float4* __restrict__ xs, int* __restrict__ ts,
-                           float* __restrict__ zb) {
+// data; padding slots of the column's last cluster are emptied. Columns of
+// up to kColStage atoms are ranked from LDS.
+constexpr int kColStage = 512;
+
+__global__ void __launch_bounds__(256) k_col_sort(
+    const int* __restrict__ gate, const int* __restrict__ col_start,
+    const int* __restrict__ slot_start, int ncol, const int* __restrict__ perm_unsorted,
+    const float* __restrict__ pos, int n, const float* __restrict__ q,
+    const int* __restrict__ atype, int* __restrict__ perm, int* __restrict__ inv_perm,
+    float4* __restrict__ xs, int* __restrict__ ts, float* __restrict__ zb) {
   if (gated_off(gate)) return;
-  int c = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  __shared__ float zst[4][kColStage];
+  __shared__ int ist[4][kColStage];
+  const int w = threadIdx.x / kWave;
+  int c = blockIdx.x * 4 + w;
   int lane = threadIdx.x & (kWave - 1);
   if (c >= ncol) return;
   int b = col_start[c], e = col_start[c + 1];
   int cnt = e - b;
   int sb = slot_start[c], se = slot_start[c + 1];
+  const bool staged = cnt <= kColStage;
+  if (staged) {
+    for (int p = lane; p < cnt; p += kWave) {
+      int v = perm_unsorted[b + p];
+      ist[w][p] = v;
+      zst[w][p] = pos[2 * n + v];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
   for (int p = lane; p < cnt; p += kWave) {
-    int v = perm_unsorted[b + p];
-    float zv = pos[2 * n + v];
+    int v;
+    float zv;
     int rank = 0;
-    for (int k = 0; k < cnt; ++k) {
-      int u = perm_unsorted[b + k];
-      float zu = pos[2 * n + u];
-      rank += (zu < zv || (zu == zv && u < v)) ? 1 : 0;
+    if (staged) {
+      v = ist[w][p];
+      zv = zst[w][p];
+      for (int k = 0; k < cnt; ++k) {
+        float zu = zst[w][k];
+        int u = ist[w][k];
+        rank += (zu < zv || (zu == zv && u < v)) ? 1 : 0;
+      }
+    } else {
+      v = perm_unsorted[b + p];
+      zv = pos[2 * n + v];
+      for (int k = 0; k < cnt; ++k) {
+        int u = perm_unsorted[b + k];
+        float zu = pos[2 * n + u];
+        rank += (zu < zv || (zu == zv && u < v)) ? 1 : 0;
+      }
     }
     int s = sb + rank;
     perm[s] = v;
@@ -205,13 +257,32 @@ __device__ __forceinline__ float axis_gap(float alo, float ahi, float blo, float
 }
 
 constexpr int kSearchCand = 1024;   // bbox-passing j-clusters one i-cluster may have
-constexpr int kSearchCols = 64;     // candidate columns handled per chunk
+constexpr int kSearchSegs = 64;     // (column, z segment) units handled per chunk
+
+// First cluster in [lo, hi) whose value v(k) >= x (v nondecreasing).
+__device__ __forceinline__ int first_ge(const float4* __restrict__ b, int lo, int hi, float x) {
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (b[mid].z < x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+// First cluster in [lo, hi) whose value v(k) > x.
+__device__ __forceinline__ int first_gt(const float4* __restrict__ b, int lo, int hi, float x) {
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (b[mid].z <= x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
 
 // One wave per i-cluster: (1) enumerate the j-clusters of the columns within
-// reach and keep those whose boxes come closer than r_nl (+ margin); (2) test
-// the 16 slot pairs of four candidate tiles at once (one lane per pair) with
-// the exact predicate and the exclusions; tiles with a non-empty mask are
-// appended to the i-cluster's list in enumeration order.
+// reach - inside a column only the z-sorted clusters that overlap the
+// i-box's z reach (one or two periodic segments, binary searches) - and keep
+// those whose boxes come closer than r_nl (+ margin); (2) test the 16 slot
+// pairs of four candidate tiles at once (one lane per pair) with the exact
+// predicate and the exclusions; tiles with a non-empty mask are appended to
+// the i-cluster's list in enumeration order.
 __global__ void __launch_bounds__(256) k_tile_search(
     const int* __restrict__ gate, const int* __restrict__ meta, const float4* __restrict__ xs,
     const int* __restrict__ perm, const float4* __restrict__ box_lo,
@@ -221,8 +292,8 @@ __global__ void __launch_bounds__(256) k_tile_search(
     unsigned* __restrict__ flags) {
   if (gated_off(gate)) return;
   __shared__ int cand[4][kSearchCand];
-  __shared__ int col_first[4][kSearchCols + 1];
-  __shared__ int col_pre[4][kSearchCols + 1];
+  __shared__ int seg_first[4][kSearchSegs];
+  __shared__ int seg_pre[4][kSearchSegs + 1];
   const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   const int ic = blockIdx.x * 4 + w;
   const int nclu = meta[1];
@@ -244,44 +315,72 @@ __global__ void __launch_bounds__(256) k_tile_search(
     if (ny == cg.n[1]) cy0 = 0;
     const int ncols = nx * ny;
     const float reach2 = reach * reach;
-    for (int c0 = 0; c0 < ncols; c0 += kSearchCols) {
-      const int nc = min(kSearchCols, ncols - c0);
+    // z reach as up to two segments inside [0, L)
+    const float Lz = cg.L[2];
+    const float margin = 1e-3f * reach;
+    float za = ilo.z - reach - margin, zb_ = ihi.z + reach + margin;
+    float sa[2], sz[2];
+    int nseg;
+    if (zb_ - za >= Lz) {
+      nseg = 1; sa[0] = -1.f; sz[0] = 2.f * Lz;
+    } else if (za < 0.f) {
+      nseg = 2; sa[0] = 0.f; sz[0] = zb_; sa[1] = za + Lz; sz[1] = 2.f * Lz;
+    } else if (zb_ >= Lz) {
+      nseg = 2; sa[0] = za; sz[0] = 2.f * Lz; sa[1] = -1.f; sz[1] = zb_ - Lz;
+    } else {
+      nseg = 1; sa[0] = za; sz[0] = zb_;
+    }
+    const int nunits = ncols * nseg;
+    for (int u0 = 0; u0 < nunits; u0 += kSearchSegs) {
+      const int nu = min(kSearchSegs, nunits - u0);
       int cnt = 0, first = 0;
-      if (lane < nc) {
-        int t = c0 + lane;
+      if (lane < nu) {
+        int u = u0 + lane;
+        int t = u / nseg, sg = u - t * nseg;
         int x = cx0 + t % nx, y = cy0 + t / nx;
         x %= cg.n[0]; x += x < 0 ? cg.n[0] : 0;
         y %= cg.n[1]; y += y < 0 ? cg.n[1] : 0;
         int col = y * cg.n[0] + x;
-        first = slot_start[col] / kClusterSize;
-        cnt = slot_start[col + 1] / kClusterSize - first;
+        int c0 = slot_start[col] / kClusterSize, c1 = slot_start[col + 1] / kClusterSize;
+        // clusters overlapping [sa, sz]: max z >= sa and min z <= sz
+        int f = first_ge(box_hi, c0, c1, sa[sg]);
+        int l = first_gt(box_lo, f, c1, sz[sg]);
+        if (sg == 1) {
+          // the two segments sit at opposite ends of the column; a cluster
+          // reaching into both is taken once, by segment 0
+          int f0 = first_ge(box_hi, c0, c1, sa[0]);
+          int l0 = first_gt(box_lo, f0, c1, sz[0]);
+          if (sa[1] > sa[0]) f = max(f, l0);
+          else l = min(l, f0);
+        }
+        first = f;
+        cnt = max(0, l - f);
       }
-      // inclusive scan of the cluster counts over the chunk
       int v = cnt;
       for (int o = 1; o < kWave; o <<= 1) {
-        int u = __shfl_up(v, o, kWave);
-        if (lane >= o) v += u;
+        int uu = __shfl_up(v, o, kWave);
+        if (lane >= o) v += uu;
       }
-      if (lane < nc) {
-        col_first[w][lane] = first;
-        col_pre[w][lane + 1] = v;
+      if (lane < nu) {
+        seg_first[w][lane] = first;
+        seg_pre[w][lane + 1] = v;
       }
-      if (lane == 0) col_pre[w][0] = 0;
+      if (lane == 0) seg_pre[w][0] = 0;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      const int total = __shfl(v, nc - 1, kWave);
+      const int total = __shfl(v, nu - 1, kWave);
       for (int f0 = 0; f0 < total; f0 += kWave) {
         int f = f0 + lane;
         bool pass = false;
         int jc = 0;
         if (f < total) {
-          int lo = 0, hi = nc - 1;
+          int lo = 0, hi = nu - 1;
           while (lo < hi) {
             int mid = (lo + hi + 1) >> 1;
-            if (col_pre[w][mid] <= f) lo = mid; else hi = mid - 1;
+            if (seg_pre[w][mid] <= f) lo = mid; else hi = mid - 1;
           }
-          jc = col_first[w][lo] + (f - col_pre[w][lo]);
+          jc = seg_first[w][lo] + (f - seg_pre[w][lo]);
           float4 jlo = box_lo[jc], jhi = box_hi[jc];
           if (jlo.w > 0.f) {
             float gx = axis_gap(ilo.x, ihi.x, jlo.x, jhi.x, cg.L[0]);

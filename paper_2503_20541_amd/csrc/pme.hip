@@ -213,13 +213,33 @@ __global__ void __launch_bounds__(kSpreadThreads) k_pme_spread(
 }
 
 // ---------------------------------------------------------------------------
-// LDS FFT
+// LDS FFT: Stockham autosort, radix 4/2/3/5 (7 by table), twiddles from a
+// host-built table exp(-2 pi i m/N). Lengths with a compiled plan (kFftSizes)
+// run a fully unrolled stage sequence with constant strides; other lengths
+// use the same stages with run-time strides.
 // ---------------------------------------------------------------------------
+struct Radices {
+  int n;
+  int r[16];
+};
+
+__host__ __device__ constexpr Radices factor_radices(int N) {
+  Radices f{};
+  int m = N;
+  while (m % 4 == 0 && f.n < 16) { f.r[f.n++] = 4; m /= 4; }
+  while (m % 2 == 0 && f.n < 16) { f.r[f.n++] = 2; m /= 2; }
+  while (m % 3 == 0 && f.n < 16) { f.r[f.n++] = 3; m /= 3; }
+  while (m % 5 == 0 && f.n < 16) { f.r[f.n++] = 5; m /= 5; }
+  while (m % 7 == 0 && f.n < 16) { f.r[f.n++] = 7; m /= 7; }
+  if (m != 1) f.n = -1;
+  return f;
+}
+
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// Twiddle exp(SIGN * 2 pi i m / N) from the forward table exp(-2 pi i m / N).
+// exp(SIGN * 2 pi i m / N) from the forward table exp(-2 pi i m / N).
 template <int SIGN>
 __device__ __forceinline__ float2 twid(const float2* tw, int m) {
   float2 t = tw[m];
@@ -227,31 +247,64 @@ __device__ __forceinline__ float2 twid(const float2* tw, int m) {
   return t;
 }
 
+// SIGN * i * z
 template <int SIGN>
-__device__ __forceinline__ void dft_small(float2* v, int R, int N, const float2* tw) {
-  if (R == 2) {
+__device__ __forceinline__ float2 mul_si(float2 z) {
+  return SIGN > 0 ? make_float2(-z.y, z.x) : make_float2(z.y, -z.x);
+}
+
+// In-register DFT of length R with kernel exp(SIGN 2 pi i r k / R).
+template <int R, int SIGN>
+__device__ __forceinline__ void dft_fixed(float2* v, const float2* tw, int N) {
+  if constexpr (R == 2) {
     float2 a = v[0], b = v[1];
     v[0] = make_float2(a.x + b.x, a.y + b.y);
     v[1] = make_float2(a.x - b.x, a.y - b.y);
-  } else if (R == 4) {
+  } else if constexpr (R == 4) {
     float2 a = v[0], b = v[1], c = v[2], d = v[3];
     float2 s0 = make_float2(a.x + c.x, a.y + c.y), s1 = make_float2(a.x - c.x, a.y - c.y);
     float2 s2 = make_float2(b.x + d.x, b.y + d.y), s3 = make_float2(b.x - d.x, b.y - d.y);
-    // SIGN * i * s3
-    float2 is3 = SIGN > 0 ? make_float2(-s3.y, s3.x) : make_float2(s3.y, -s3.x);
+    float2 is3 = mul_si<SIGN>(s3);
     v[0] = make_float2(s0.x + s2.x, s0.y + s2.y);
     v[2] = make_float2(s0.x - s2.x, s0.y - s2.y);
     v[1] = make_float2(s1.x + is3.x, s1.y + is3.y);
     v[3] = make_float2(s1.x - is3.x, s1.y - is3.y);
+  } else if constexpr (R == 3) {
+    // y1,2 = v0 - (v1+v2)/2 +- SIGN i sin(2pi/3) (v1 - v2)
+    const float s3 = 0.86602540378443865f;
+    float2 t1 = make_float2(v[1].x + v[2].x, v[1].y + v[2].y);
+    float2 t2 = make_float2(s3 * (v[1].x - v[2].x), s3 * (v[1].y - v[2].y));
+    float2 a = make_float2(v[0].x - 0.5f * t1.x, v[0].y - 0.5f * t1.y);
+    float2 b = mul_si<SIGN>(t2);
+    v[0] = make_float2(v[0].x + t1.x, v[0].y + t1.y);
+    v[1] = make_float2(a.x + b.x, a.y + b.y);
+    v[2] = make_float2(a.x - b.x, a.y - b.y);
+  } else if constexpr (R == 5) {
+    // cos/sin of 2pi/5 and 4pi/5; pairs (1,4) and (2,3) combine into
+    // a1,2 (cosine parts) and b1,2 (sine parts)
+    const float c1 = 0.30901699437494742f, c2 = -0.80901699437494742f;
+    const float s1 = 0.95105651629515357f, s2 = 0.58778525229247313f;
+    float2 t1 = make_float2(v[1].x + v[4].x, v[1].y + v[4].y);
+    float2 t2 = make_float2(v[2].x + v[3].x, v[2].y + v[3].y);
+    float2 t3 = make_float2(v[1].x - v[4].x, v[1].y - v[4].y);
+    float2 t4 = make_float2(v[2].x - v[3].x, v[2].y - v[3].y);
+    float2 a1 = make_float2(v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y);
+    float2 a2 = make_float2(v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y);
+    float2 b1 = mul_si<SIGN>(make_float2(s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y));
+    float2 b2 = mul_si<SIGN>(make_float2(s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y));
+    v[0] = make_float2(v[0].x + t1.x + t2.x, v[0].y + t1.y + t2.y);
+    v[1] = make_float2(a1.x + b1.x, a1.y + b1.y);
+    v[4] = make_float2(a1.x - b1.x, a1.y - b1.y);
+    v[2] = make_float2(a2.x + b2.x, a2.y + b2.y);
+    v[3] = make_float2(a2.x - b2.x, a2.y - b2.y);
   } else {
-    float2 in[7];
+    float2 in[R];
     for (int r = 0; r < R; ++r) in[r] = v[r];
     const int step = N / R;
     for (int k = 0; k < R; ++k) {
       float2 acc = in[0];
       for (int r = 1; r < R; ++r) {
-        float2 wv = twid<SIGN>(tw, ((r * k) % R) * step);
-        float2 p = cmul(in[r], wv);
+        float2 p = cmul(in[r], twid<SIGN>(tw, ((r * k) % R) * step));
         acc.x += p.x;
         acc.y += p.y;
       }
@@ -260,98 +313,140 @@ __device__ __forceinline__ void dft_small(float2* v, int R, int N, const float2*
   }
 }
 
-// P pencils of length N stored [p][N] in a; b is scratch. Returns the buffer
-// holding the (unnormalised) transform. All threads of the block take part.
+// One Stockham stage on P pencils stored with stride SP: radix R, NS points
+// already combined. All threads of the block take part.
+template <int R, int SIGN>
+__device__ __forceinline__ void fft_stage(const float2* __restrict__ a, float2* __restrict__ b,
+                                          int N, int SP, int NS, int P, const float2* tw) {
+  const int NR = N / R;
+  const int ts = N / (NS * R);
+  for (int idx = threadIdx.x; idx < P * NR; idx += blockDim.x) {
+    const int p = idx / NR, j = idx - p * NR;
+    const int k = j % NS;
+    const float2* in = a + p * SP;
+    float2* out = b + p * SP;
+    float2 v[R];
+    v[0] = in[j];
+#pragma unroll
+    for (int r = 1; r < R; ++r) v[r] = cmul(in[j + r * NR], twid<SIGN>(tw, k * r * ts));
+    dft_fixed<R, SIGN>(v, tw, N);
+    const int base = (j / NS) * NS * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) out[base + r * NS] = v[r];
+  }
+  __syncthreads();
+}
+
+// Compiled plan: stage S of length N (constant strides, unrolled sequence).
+template <int N, int SIGN, int S, int NS>
+__device__ __forceinline__ float2* fft_ct(float2* a, float2* b, int SP, int P, const float2* tw) {
+  constexpr Radices f = factor_radices(N);
+  if constexpr (S >= f.n) {
+    return a;
+  } else {
+    constexpr int R = f.r[S];
+    fft_stage<R, SIGN>(a, b, N, SP, NS, P, tw);
+    return fft_ct<N, SIGN, S + 1, NS * R>(b, a, SP, P, tw);
+  }
+}
+
+// Run-time plan for lengths without a compiled one.
 template <int SIGN>
-__device__ float2* fft_lds(float2* a, float2* b, int P, const FftPlan& pl, const float2* tw) {
-  const int N = pl.N;
-  int Ns = 1;
+__device__ float2* fft_rt(float2* a, float2* b, int SP, int P, const FftPlan& pl,
+                          const float2* tw) {
+  int NS = 1;
   for (int s = 0; s < pl.nst; ++s) {
     const int R = pl.radix[s];
-    const int NR = N / R;
-    const int tstride = N / (Ns * R);
-    for (int idx = threadIdx.x; idx < P * NR; idx += blockDim.x) {
-      int p = idx / NR, j = idx - p * NR;
-      int k = j % Ns;
-      const float2* in = a + p * N;
-      float2* out = b + p * N;
-      float2 v[7];
-      v[0] = in[j];
-      for (int r = 1; r < R; ++r) v[r] = cmul(in[j + r * NR], twid<SIGN>(tw, k * r * tstride));
-      dft_small<SIGN>(v, R, N, tw);
-      int base = (j / Ns) * Ns * R + k;
-      for (int r = 0; r < R; ++r) out[base + r * Ns] = v[r];
+    switch (R) {
+      case 4: fft_stage<4, SIGN>(a, b, pl.N, SP, NS, P, tw); break;
+      case 2: fft_stage<2, SIGN>(a, b, pl.N, SP, NS, P, tw); break;
+      case 3: fft_stage<3, SIGN>(a, b, pl.N, SP, NS, P, tw); break;
+      case 5: fft_stage<5, SIGN>(a, b, pl.N, SP, NS, P, tw); break;
+      default: fft_stage<7, SIGN>(a, b, pl.N, SP, NS, P, tw); break;
     }
-    __syncthreads();
     float2* t = a;
     a = b;
     b = t;
-    Ns *= R;
+    NS *= R;
   }
   return a;
 }
 
+template <int N, int SIGN>
+__device__ __forceinline__ float2* fft_any(float2* a, float2* b, int SP, int P, const FftPlan& pl,
+                                           const float2* tw) {
+  if constexpr (N > 0) {
+    return fft_ct<N, SIGN, 0, 1>(a, b, SP, P, tw);
+  } else {
+    return fft_rt<SIGN>(a, b, SP, P, pl, tw);
+  }
+}
+
 // x-direction forward: real rows [Kz*Ky][Kx] -> half spectrum [Kz*Ky][Kxh].
+template <int N>
 __global__ void __launch_bounds__(256) k_fft_rows_r2c(const float* __restrict__ in,
                                                       float2* __restrict__ out, int nrows,
                                                       int P, int Kxh, FftPlan pl,
                                                       const float2* __restrict__ twg) {
   extern __shared__ float2 sm[];
-  const int N = pl.N;
+  const int L = N > 0 ? N : pl.N;
   float2* tw = sm;
-  float2* a = sm + N;
-  float2* b = a + P * N;
-  for (int t = threadIdx.x; t < N; t += blockDim.x) tw[t] = twg[t];
+  float2* a = sm + L;
+  float2* b = a + P * L;
+  for (int t = threadIdx.x; t < L; t += blockDim.x) tw[t] = twg[t];
   const int r0 = blockIdx.x * P;
-  for (int idx = threadIdx.x; idx < P * N; idx += blockDim.x) {
-    int p = idx / N, x = idx - p * N;
-    a[idx] = (r0 + p < nrows) ? make_float2(in[(size_t)(r0 + p) * N + x], 0.f)
+  for (int idx = threadIdx.x; idx < P * L; idx += blockDim.x) {
+    int p = idx / L, x = idx - p * L;
+    a[idx] = (r0 + p < nrows) ? make_float2(in[(size_t)(r0 + p) * L + x], 0.f)
                               : make_float2(0.f, 0.f);
   }
   __syncthreads();
-  float2* res = fft_lds<-1>(a, b, P, pl, tw);
+  float2* res = fft_any<N, -1>(a, b, L, P, pl, tw);
   for (int idx = threadIdx.x; idx < P * Kxh; idx += blockDim.x) {
     int p = idx / Kxh, k = idx - p * Kxh;
-    if (r0 + p < nrows) out[(size_t)(r0 + p) * Kxh + k] = res[p * N + k];
+    if (r0 + p < nrows) out[(size_t)(r0 + p) * Kxh + k] = res[p * L + k];
   }
 }
 
 // x-direction inverse: half spectrum -> real rows (Hermitian completion).
+template <int N>
 __global__ void __launch_bounds__(256) k_fft_rows_c2r(const float2* __restrict__ in,
                                                       float* __restrict__ out, int nrows,
                                                       int P, int Kxh, FftPlan pl,
                                                       const float2* __restrict__ twg) {
   extern __shared__ float2 sm[];
-  const int N = pl.N;
+  const int L = N > 0 ? N : pl.N;
   float2* tw = sm;
-  float2* a = sm + N;
-  float2* b = a + P * N;
-  for (int t = threadIdx.x; t < N; t += blockDim.x) tw[t] = twg[t];
+  float2* a = sm + L;
+  float2* b = a + P * L;
+  for (int t = threadIdx.x; t < L; t += blockDim.x) tw[t] = twg[t];
   const int r0 = blockIdx.x * P;
-  for (int idx = threadIdx.x; idx < P * N; idx += blockDim.x) {
-    int p = idx / N, k = idx - p * N;
+  for (int idx = threadIdx.x; idx < P * L; idx += blockDim.x) {
+    int p = idx / L, k = idx - p * L;
     float2 v = make_float2(0.f, 0.f);
     if (r0 + p < nrows) {
       if (k < Kxh) {
         v = in[(size_t)(r0 + p) * Kxh + k];
       } else {
-        v = in[(size_t)(r0 + p) * Kxh + (N - k)];
+        v = in[(size_t)(r0 + p) * Kxh + (L - k)];
         v.y = -v.y;
       }
     }
     a[idx] = v;
   }
   __syncthreads();
-  float2* res = fft_lds<+1>(a, b, P, pl, tw);
-  for (int idx = threadIdx.x; idx < P * N; idx += blockDim.x) {
-    int p = idx / N, x = idx - p * N;
-    if (r0 + p < nrows) out[(size_t)(r0 + p) * N + x] = res[idx].x;
+  float2* res = fft_any<N, +1>(a, b, L, P, pl, tw);
+  for (int idx = threadIdx.x; idx < P * L; idx += blockDim.x) {
+    int p = idx / L, x = idx - p * L;
+    if (r0 + p < nrows) out[(size_t)(r0 + p) * L + x] = res[idx].x;
   }
 }
 
-// Column pencils of the half spectrum. MODE 0: y forward, 1: y inverse,
-// 2: z forward, influence multiply + energy partial, z inverse.
-template <int MODE>
+// Column pencils of the half spectrum, P consecutive kx per block, stored in
+// LDS with an odd stride (L + 1) so the transposing load is conflict-free.
+// MODE 0: y forward, 1: y inverse, 2: z forward, influence multiply + energy
+// partial, z inverse.
+template <int N, int MODE>
 __global__ void __launch_bounds__(256) k_fft_cols(float2* __restrict__ grid, PmeParams pp,
                                                   int P, FftPlan pl,
                                                   const float2* __restrict__ twg,
@@ -364,11 +459,12 @@ __global__ void __launch_bounds__(256) k_fft_cols(float2* __restrict__ grid, Pme
                                                   double* __restrict__ partials, int pstride) {
   extern __shared__ float2 sm[];
   __shared__ double red[16];
-  const int N = pl.N;
+  const int L = N > 0 ? N : pl.N;
+  const int SP = L + 1;
   float2* tw = sm;
-  float2* a = sm + N;
-  float2* b = a + P * N;
-  for (int t = threadIdx.x; t < N; t += blockDim.x) tw[t] = twg[t];
+  float2* a = sm + L;
+  float2* b = a + P * SP;
+  for (int t = threadIdx.x; t < L; t += blockDim.x) tw[t] = twg[t];
   const int Kxh = pp.Kxh;
   const int ntile = (Kxh + P - 1) / P;
   const int outer = blockIdx.x / ntile;       // z for the y pass, ky for the z pass
@@ -381,17 +477,17 @@ __global__ void __launch_bounds__(256) k_fft_cols(float2* __restrict__ grid, Pme
     base = (size_t)outer * pp.K[1] * Kxh;
     stride = Kxh;
   }
-  for (int idx = threadIdx.x; idx < P * N; idx += blockDim.x) {
+  for (int idx = threadIdx.x; idx < P * L; idx += blockDim.x) {
     int i = idx / P, p = idx - i * P;
     int kx = kx0 + p;
-    a[p * N + i] = kx < Kxh ? grid[base + i * stride + kx] : make_float2(0.f, 0.f);
+    a[p * SP + i] = kx < Kxh ? grid[base + i * stride + kx] : make_float2(0.f, 0.f);
   }
   __syncthreads();
   float2* res;
   if (MODE == 1) {
-    res = fft_lds<+1>(a, b, P, pl, tw);
+    res = fft_any<N, +1>(a, b, SP, P, pl, tw);
   } else {
-    res = fft_lds<-1>(a, b, P, pl, tw);
+    res = fft_any<N, -1>(a, b, SP, P, pl, tw);
   }
   if (MODE == 2) {
     // influence function G = B(m) C(m) on the half spectrum. G is formed in
@@ -399,10 +495,10 @@ __global__ void __launch_bounds__(256) k_fft_cols(float2* __restrict__ grid, Pme
     // constant 1/(pi V) applied in the reduction, weights |Q^|^2 for E_rec).
     double e = 0.0;
     const int ky = outer;
-    for (int idx = threadIdx.x; idx < P * N; idx += blockDim.x) {
-      int p = idx / N, kz = idx - p * N;
+    for (int idx = threadIdx.x; idx < P * L; idx += blockDim.x) {
+      int p = idx / L, kz = idx - p * L;
       int kx = kx0 + p;
-      float2 v = res[idx];
+      float2 v = res[p * SP + kz];
       float g = 0.f;
       if (kx < Kxh) {
         double msq = mx[kx] * mx[kx] + my[ky] * my[ky] + mz[kz] * mz[kz];
@@ -413,18 +509,18 @@ __global__ void __launch_bounds__(256) k_fft_cols(float2* __restrict__ grid, Pme
           g = (float)(gd * pp.inv_piV);
         }
       }
-      res[idx] = make_float2(v.x * g, v.y * g);
+      res[p * SP + kz] = make_float2(v.x * g, v.y * g);
     }
     double s = block_sum(e, red);
     if (threadIdx.x == 0) partials[kRowRec * pstride + blockIdx.x] = s;
     __syncthreads();
     float2* other = (res == a) ? b : a;
-    res = fft_lds<+1>(res, other, P, pl, tw);
+    res = fft_any<N, +1>(res, other, SP, P, pl, tw);
   }
-  for (int idx = threadIdx.x; idx < P * N; idx += blockDim.x) {
+  for (int idx = threadIdx.x; idx < P * L; idx += blockDim.x) {
     int i = idx / P, p = idx - i * P;
     int kx = kx0 + p;
-    if (kx < Kxh) grid[base + i * stride + kx] = res[p * N + i];
+    if (kx < Kxh) grid[base + i * stride + kx] = res[p * SP + i];
   }
 }
 
@@ -477,13 +573,10 @@ __global__ void __launch_bounds__(256) k_pme_gather(const float4* __restrict__ x
 // ---------------------------------------------------------------------------
 static FftPlan make_plan(int N) {
   FftPlan p{};
+  Radices f = factor_radices(N);
   p.N = N;
-  int m = N;
-  while (m % 4 == 0 && p.nst < 16) { p.radix[p.nst++] = 4; m /= 4; }
-  const int primes[4] = {2, 3, 5, 7};
-  for (int r : primes)
-    while (m % r == 0 && p.nst < 16) { p.radix[p.nst++] = r; m /= r; }
-  if (m != 1) p.nst = -1;
+  p.nst = f.n;
+  for (int s = 0; s < 16; ++s) p.radix[s] = f.r[s];
   return p;
 }
 
@@ -494,6 +587,56 @@ static int pencils_for(int N) {
   if (P > 32) P = 32;
   if (P < 1) P = 1;
   return P;
+}
+
+// Lengths with a compiled FFT plan; others take the run-time plan.
+#define MDX_FFT_SIZES(X) X(32) X(48) X(64) X(96) X(100) X(128)
+
+template <int N>
+static void launch_rows_r2c(int blocks, size_t sh, hipStream_t s, const float* in, float2* out,
+                            int rows, int P, int Kxh, const FftPlan& pl, const float2* tw) {
+  k_fft_rows_r2c<N><<<blocks, 256, sh, s>>>(in, out, rows, P, Kxh, pl, tw);
+}
+template <int N>
+static void launch_rows_c2r(int blocks, size_t sh, hipStream_t s, const float2* in, float* out,
+                            int rows, int P, int Kxh, const FftPlan& pl, const float2* tw) {
+  k_fft_rows_c2r<N><<<blocks, 256, sh, s>>>(in, out, rows, P, Kxh, pl, tw);
+}
+template <int N, int MODE>
+static void launch_cols(int blocks, size_t sh, hipStream_t s, Ctx& c, const PmeParams& pp, int P,
+                        const FftPlan& pl, const float2* tw) {
+  k_fft_cols<N, MODE><<<blocks, 256, sh, s>>>(c.grid_c, pp, P, pl, tw, c.bmod[0], c.bmod[1],
+                                               c.bmod[2], c.mrec[0], c.mrec[1], c.mrec[2],
+                                               c.partials, c.max_blocks);
+}
+
+static void rows_r2c(int N, int blocks, size_t sh, hipStream_t s, const float* in, float2* out,
+                     int rows, int P, int Kxh, const FftPlan& pl, const float2* tw) {
+  switch (N) {
+#define X(n) case n: launch_rows_r2c<n>(blocks, sh, s, in, out, rows, P, Kxh, pl, tw); return;
+    MDX_FFT_SIZES(X)
+#undef X
+    default: launch_rows_r2c<0>(blocks, sh, s, in, out, rows, P, Kxh, pl, tw);
+  }
+}
+static void rows_c2r(int N, int blocks, size_t sh, hipStream_t s, const float2* in, float* out,
+                     int rows, int P, int Kxh, const FftPlan& pl, const float2* tw) {
+  switch (N) {
+#define X(n) case n: launch_rows_c2r<n>(blocks, sh, s, in, out, rows, P, Kxh, pl, tw); return;
+    MDX_FFT_SIZES(X)
+#undef X
+    default: launch_rows_c2r<0>(blocks, sh, s, in, out, rows, P, Kxh, pl, tw);
+  }
+}
+template <int MODE>
+static void cols(int N, int blocks, size_t sh, hipStream_t s, Ctx& c, const PmeParams& pp, int P,
+                 const FftPlan& pl, const float2* tw) {
+  switch (N) {
+#define X(n) case n: launch_cols<n, MODE>(blocks, sh, s, c, pp, P, pl, tw); return;
+    MDX_FFT_SIZES(X)
+#undef X
+    default: launch_cols<0, MODE>(blocks, sh, s, c, pp, P, pl, tw);
+  }
 }
 
 hipError_t launch_pme(Ctx& c, float* force, bool energy) {
@@ -516,26 +659,19 @@ hipError_t launch_pme(Ctx& c, float* force, bool energy) {
                                                    c.brick_cols, c.brick_z, pp, c.cg, c.grid_q);
   FftPlan px = make_plan(g.K[0]), py = make_plan(g.K[1]), pz = make_plan(g.K[2]);
   const int rows = g.K[1] * g.K[2];
-  int P = pencils_for(g.K[0]);
-  size_t sh = (size_t)(g.K[0] + 2 * P * g.K[0]) * sizeof(float2);
-  k_fft_rows_r2c<<<(rows + P - 1) / P, 256, sh, s>>>(c.grid_q, c.grid_c, rows, P, g.Kxh, px,
-                                                     c.tw[0]);
+  const int P = pencils_for(g.K[0]);
+  const size_t sh = (size_t)(g.K[0] + 2 * P * g.K[0]) * sizeof(float2);
+  const int rblocks = (rows + P - 1) / P;
+  rows_r2c(g.K[0], rblocks, sh, s, c.grid_q, c.grid_c, rows, P, g.Kxh, px, c.tw[0]);
   const int Pc = 16;
   const int ntile = (g.Kxh + Pc - 1) / Pc;
-  size_t shy = (size_t)(g.K[1] + 2 * Pc * g.K[1]) * sizeof(float2);
-  size_t shz = (size_t)(g.K[2] + 2 * Pc * g.K[2]) * sizeof(float2);
-  k_fft_cols<0><<<g.K[2] * ntile, 256, shy, s>>>(c.grid_c, pp, Pc, py, c.tw[1], c.bmod[0],
-                                                 c.bmod[1], c.bmod[2], c.mrec[0], c.mrec[1],
-                                                 c.mrec[2], c.partials, c.max_blocks);
-  k_fft_cols<2><<<g.K[1] * ntile, 256, shz, s>>>(c.grid_c, pp, Pc, pz, c.tw[2], c.bmod[0],
-                                                 c.bmod[1], c.bmod[2], c.mrec[0], c.mrec[1],
-                                                 c.mrec[2], c.partials, c.max_blocks);
+  const size_t shy = (size_t)(g.K[1] + 2 * Pc * (g.K[1] + 1)) * sizeof(float2);
+  const size_t shz = (size_t)(g.K[2] + 2 * Pc * (g.K[2] + 1)) * sizeof(float2);
+  cols<0>(g.K[1], g.K[2] * ntile, shy, s, c, pp, Pc, py, c.tw[1]);
+  cols<2>(g.K[2], g.K[1] * ntile, shz, s, c, pp, Pc, pz, c.tw[2]);
   c.pme_blocks = g.K[1] * ntile;
-  k_fft_cols<1><<<g.K[2] * ntile, 256, shy, s>>>(c.grid_c, pp, Pc, py, c.tw[1], c.bmod[0],
-                                                 c.bmod[1], c.bmod[2], c.mrec[0], c.mrec[1],
-                                                 c.mrec[2], c.partials, c.max_blocks);
-  k_fft_rows_c2r<<<(rows + P - 1) / P, 256, sh, s>>>(c.grid_c, c.grid_phi, rows, P, g.Kxh, px,
-                                                     c.tw[0]);
+  cols<1>(g.K[1], g.K[2] * ntile, shy, s, c, pp, Pc, py, c.tw[1]);
+  rows_c2r(g.K[0], rblocks, sh, s, c.grid_c, c.grid_phi, rows, P, g.Kxh, px, c.tw[0]);
   k_pme_gather<<<(c.max_slots + 255) / 256, 256, 0, s>>>(c.xs, c.perm, c.meta, c.grid_phi, c.n,
                                                           pp, force);
   return hipGetLastError();
