@@ -153,7 +153,19 @@ __device__ __forceinline__ float min_image(float xi, float xj, float L, float hL
   float s = xj - xi;
   float up = (xj - L) - xi;
   float dn = xj + (L - xi);
-  return s > hL ? up : (s < -hL ? dn : s);
+  float d = s > hL ? up : s;
+  return s < -hL ? dn : d;
+}
+
+// The same expression with L - x_i supplied by the caller (hoisted out of a
+// loop over j); every operand is computed, so it compiles to selects.
+__device__ __forceinline__ float min_image_h(float xi, float Lmxi, float xj, float L, float hL) {
+#pragma clang fp contract(off)
+  float s = xj - xi;
+  float up = (xj - L) - xi;
+  float dn = xj + Lmxi;
+  float d = s > hL ? up : s;
+  return s < -hL ? dn : d;
 }
 
 __device__ __forceinline__ float dist2(float dx, float dy, float dz) {

@@ -447,8 +447,12 @@ __global__ void __launch_bounds__(256) k_tile_search(
     }
     count += __popcll(nonempty);
   }
+  // pad the list to whole groups of four tiles with empty tiles (mask 0)
+  const int kept = count < cap ? count : cap;
+  const int padded = min((kept + 3) & ~3, cap);
+  if (lane < padded - kept) tiles[(size_t)ic * cap + kept + lane] = make_uint2(0u, 0u);
   if (lane == 0) {
-    tile_count[ic] = count < cap ? count : cap;
+    tile_count[ic] = padded;
     if (count > cap) atomicOr(flags, MDX_FLAG_NL_OVERFLOW);
     if (overflow) atomicOr(flags, MDX_FLAG_CELL_OVERFLOW);
     atomicMax(nl_needed, count);

@@ -76,24 +76,29 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
   double e_lj = 0.0, e_c = 0.0;
   if (active) {
     const float4 pi = xs[si];
+    const float lmx = pp.L[0] - pi.x, lmy = pp.L[1] - pi.y, lmz = pp.L[2] - pi.z;
     const int trow = ts[si] * pp.ntypes;
     const int cnt = tile_count[ic];
     const uint2* tl = tiles + (size_t)ic * cap;
+    // lists are padded to groups of four; the prefetch of the next group is
+    // clamped into the list's allocation and only used while g < cnt
+    uint2 e_next = tl[tt];
     for (int g = 0; g < cnt; g += 4) {
-      uint2 e = (g + tt < cnt) ? tl[g + tt] : make_uint2(0u, 0u);
+      const uint2 e = e_next;
+      e_next = tl[min(g + 4 + tt, cap - 1)];
       const bool on = (e.y >> bitpos) & 1u;
       const int sj = (int)e.x * kClusterSize + jb;
       const float4 pj = xs[sj];
-      float dx = min_image(pi.x, pj.x, pp.L[0], pp.hL[0]);
-      float dy = min_image(pi.y, pj.y, pp.L[1], pp.hL[1]);
-      float dz = min_image(pi.z, pj.z, pp.L[2], pp.hL[2]);
+      float dx = min_image_h(pi.x, lmx, pj.x, pp.L[0], pp.hL[0]);
+      float dy = min_image_h(pi.y, lmy, pj.y, pp.L[1], pp.hL[1]);
+      float dz = min_image_h(pi.z, lmz, pj.z, pp.L[2], pp.hL[2]);
       float r2 = dist2(dx, dy, dz);
       const bool in = on && r2 < pp.rc2;
       if (__ballot(in) == 0ull) continue;
       if (in) {
         const int tp = trow + ts[sj];
         float4 lj = lj_f[tp];             // c12, c6, 12 c12, 6 c6
-        const float rinv = rsqrtf(r2);
+        const float rinv = __builtin_amdgcn_rsqf(r2);   // r2 is never denormal here
         const float rinv2 = rinv * rinv;
         float r6 = rinv2 * rinv2 * rinv2;
         float f_over_r = r6 * (lj.z * r6 - lj.w) * rinv2;
@@ -113,7 +118,9 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
         if (COUL) {
           float r = r2 * rinv;
           float ar = fmaf(pp.alpha_hi, r, pp.alpha_lo * r);
-          float ex = expf(-ar * ar);
+          // exp(-x^2) as 2^(-x^2 log2 e) on the transcendental unit; the
+          // energies on measurement steps are evaluated separately in FP64
+          float ex = __builtin_amdgcn_exp2f(-ar * ar * 1.44269504088896341f);
           ec = erfc_scaled(ar) * ex;
           f_over_r += pp.coulomb_k * (pi.w * pj.w) * (ec * rinv + pp.two_a_sqrtpi * ex) * rinv2;
         }

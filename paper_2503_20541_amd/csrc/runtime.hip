@@ -93,6 +93,7 @@ int default_capacity(int n, const float box[3], float r_list, double a, int max_
 
 int alloc_list(mdx_ctx* x, int cap) {
   Ctx& c = x->c;
+  cap = std::max(4, (cap + 3) / 4 * 4);   // lists are padded to groups of four tiles
   dev_free(x, c.tiles);
   c.tiles = nullptr;
   int rc = dev_alloc(x, &c.tiles, (size_t)cap * c.max_clusters);
