@@ -41,7 +41,12 @@ def parse():
     p.add_argument("--steps", type=int, default=1000)
     p.add_argument("--warmup", type=int, default=100)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--equilibrate", type=int, default=0,
+                   help="steps of velocity-rescaled equilibration to 300 K before the warm-up")
     p.add_argument("--cpu-only", action="store_true", help=argparse.SUPPRESS)
+    p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                   help="only copy a MIB-sized float32 buffer 10 times (calibrates the "
+                        "FETCH_SIZE / WRITE_SIZE counters against known traffic) and exit")
     return p.parse_args()
 
 
@@ -49,6 +54,14 @@ def pair_counts():
     path = os.path.join(ROOT, "tests", "golden", "pair_counts.json")
     with open(path) as f:
         return json.load(f)[WORKLOAD]
+
+
+def temperature(sys_, vel):
+    """Instantaneous temperature from the device velocities (3N degrees of freedom)."""
+    import torch
+    m = torch.from_numpy(sys_.mass.astype("float64")).to(vel.device)
+    ke = 0.5 * float((m[None, :] * vel.double() ** 2).sum()) / float(sys_.accel)
+    return 2.0 * ke / (3 * sys_.n_atoms * float(sys_.boltzmann))
 
 
 def cpu_baseline(sys_):
@@ -81,8 +94,24 @@ def cpu_baseline(sys_):
                 pair_interactions_per_s=nb["n_interacting"] / t_step)
 
 
+def copy_probe(mib):
+    """A plain device-to-device copy of known size (reads and writes mib MiB
+    per launch), used to scale the hardware byte counters."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(10):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_MiB": mib, "launches": 10}), flush=True)
+
+
 def main():
     args = parse()
+    if args.copy_probe > 0:
+        copy_probe(args.copy_probe)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the hot path runs on a single MI355X)", file=sys.stderr)
@@ -116,10 +145,22 @@ def main():
         mdx.build_neighbors(ctx, pos)
         mdx.compute_nonbonded(ctx, pos, force)
         mdx.compute_pme(ctx, pos, force)
+        # The synthetic lattice start is far from equilibrium and heats up as
+        # its potential energy relaxes; optionally bring it to 300 K first by
+        # rescaling the velocities every 100 steps (input preparation, not
+        # timed).
+        done = 0
+        while done < args.equilibrate:
+            k = min(100, args.equilibrate - done)
+            mdx.integrate_step(ctx, pos, vel, force, k, s.dt)
+            vel.mul_((300.0 / temperature(s, vel)) ** 0.5)
+            done += k
         if args.warmup > 0:
             mdx.integrate_step(ctx, pos, vel, force, args.warmup, s.dt)
         torch.cuda.synchronize()
         flags0 = mdx.get_status(ctx)
+        t_start = temperature(s, vel)
+        builds0 = mdx.get_info(ctx).n_builds
         mdx.set_timing(ctx, True)
         start = torch.cuda.Event(enable_timing=True)
         stop = torch.cuda.Event(enable_timing=True)
@@ -133,6 +174,9 @@ def main():
         pme_ms, pme_n = mdx.get_timing(ctx, mdx.MDX_TIMING_PME)
         build_ms, build_n = mdx.get_timing(ctx, mdx.MDX_TIMING_BUILD)
         mdx.set_timing(ctx, False)
+        info = mdx.get_info(ctx)
+        builds = info.n_builds - builds0
+        t_end = temperature(s, vel)
         flags = mdx.get_status(ctx) | flags0
         ok = bool(torch.isfinite(pos).all() and torch.isfinite(vel).all())
         mdx.destroy(ctx)
@@ -147,6 +191,9 @@ def main():
             "value": round(ns_day, 3), "ms_per_step": round(ms_step, 5),
             "pair_interactions_per_s": counts["interacting_pairs"] * steps_per_s,
             "status_flags": flags, "finite": ok,
+            "equilibration_steps": args.equilibrate,
+            "list_builds": builds, "temperature_K": [round(t_start, 1), round(t_end, 1)],
+            "list_tiles": info.n_list_tiles, "list_entries": info.n_list_entries,
             "kernel_ms": {"pair": round(pair_ms, 5), "pme": round(pme_ms, 5),
                           "build_gated": round(build_ms, 5)},
             "roofline": {"bound": "alu", "achieved": round(achieved, 3),

@@ -55,7 +55,8 @@ extern "C" {
 #define MDX_FLAG_NL_STALE     0x2u  /* an atom moved > r_g/2 since the last build */
 #define MDX_FLAG_NONFINITE    0x4u  /* a non-finite energy was reduced            */
 #define MDX_FLAG_OUT_OF_BOX   0x8u  /* a coordinate outside [0, L)                */
-#define MDX_FLAG_CELL_OVERFLOW 0x10u /* a cell held more atoms than the sorter can */
+#define MDX_FLAG_CELL_OVERFLOW 0x10u /* a cluster had more candidate clusters than
+                                        the search holds (list incomplete)   */
 
 /* ---- energy slots (FP64) ----------------------------------------------- */
 #define MDX_ENERGY_LJ         0  /* Eq. 4 (switched by Eq. 6 if enabled)        */
@@ -90,11 +91,22 @@ typedef struct mdx_ctx mdx_ctx;
  * Units: coulomb_k = 1/(4 pi eps0); accel converts force/mass to
  * acceleration (a = accel F / m); boltzmann is k_B (kinetic temperature).
  *
- * Tuning: cell_divisions m in [1, 4] (cells of edge >= (r_c + r_g)/m and a
- * (2m+1)^3 stencil; 0 = 2); nl_capacity = neighbours per atom (0 = sized
- * from the density with headroom); rebuild_every = steps between list
- * rebuilds in mdx_integrate_step (0 = 10).
+ * Tuning: cell_divisions m in [1, 4] (x-y columns of edge 2/m times the
+ * edge of the cube that holds four atoms at the mean density; 0 = 2; the
+ * list does not depend on it); nl_capacity = 4x4 cluster tiles per
+ * cluster (0 = sized from the density with headroom; grown on overflow by
+ * mdx_build_neighbors); rebuild_every = steps between list rebuilds in
+ * mdx_integrate_step (0 = 10).
+ *
+ * options: MDX_OPT_* bits (0 = defaults). By default every pair is listed
+ * from both ends and each end accumulates its own force: no atomics,
+ * bitwise-reproducible forces. MDX_OPT_HALF_LIST lists each pair once and
+ * applies its force to both atoms (Newton's third law) with float atomics
+ * into a per-atom accumulator: half the pair arithmetic and list memory,
+ * forces that can differ in the last bits from run to run. Energies are
+ * reproducible in both modes.
  */
+#define MDX_OPT_HALF_LIST 1u
 typedef struct mdx_system_desc {
   int32_t n_atoms;
   float box[3];
@@ -127,7 +139,7 @@ typedef struct mdx_system_desc {
   int32_t cell_divisions;
   int32_t nl_capacity;
   int32_t rebuild_every;
-  uint32_t reserved;
+  uint32_t options;
 } mdx_system_desc;
 
 /* Read-only facts about a context (mdx_get_info). */
@@ -140,8 +152,15 @@ typedef struct mdx_info {
   int32_t pme_brick[3];      /* grid points per PME brick                 */
   double alpha;              /* Ewald splitting parameter in use          */
   double r_list;             /* fl32(r_c + r_g)                           */
-  int64_t n_list_entries;    /* directed entries in the last built list   */
+  int64_t n_list_entries;    /* entries in the last built list: twice the
+                                pairs (full list) or the pairs (half list);
+                                -1 before the first build                 */
   int64_t steps_taken;       /* steps integrated since creation           */
+  int64_t n_builds;          /* list builds so far: explicit builds plus
+                                the rebuilds inside mdx_integrate_step    */
+  int64_t n_list_tiles;      /* 4x4 cluster tiles in the last built list,
+                                with the padding to groups of four (-1
+                                before the first build)                   */
 } mdx_info;
 
 /* Names a status code; never NULL. */
@@ -164,8 +183,9 @@ int mdx_set_stream(mdx_ctx* ctx, void* hip_stream);
 
 /*
  * Builds the Verlet list (Sec. II.A.2, "Neighborlists") for dev positions
- * pos[3][N]: bins atoms into cells, sorts them by cell (stable in atom
- * index) and tests the (2m+1)^3 neighbouring cells of every atom with the
+ * pos[3][N]: bins atoms into x-y columns, sorts each column by z (ties by
+ * atom index), cuts it into 4-atom clusters, and tests every atom pair of
+ * the cluster pairs whose bounding boxes come closer than r_nl with the
  * float32 inclusion predicate
  *     s = fl(x_j - x_i);  d = s, or fl(fl(x_j - L) - x_i) if s > L/2,
  *     or fl(x_j + fl(L - x_i)) if s < -L/2   (per dimension);
@@ -212,8 +232,14 @@ int mdx_compute_pme(mdx_ctx* ctx, const float* pos, float* force, double* energy
  *   v += (dt/2) accel F/m.
  * pos, vel, force are dev [3][N] and are updated in place; force must hold
  * F(pos) on entry (e.g. from mdx_compute_nonbonded + mdx_compute_pme) and
- * holds F(pos) on exit. The list is rebuilt every rebuild_every steps and
- * its validity (displacement < r_g/2) is tested every step. energies, if not
+ * holds F(pos) on exit. The list is rebuilt every rebuild_every steps, and
+ * also on any step where an atom has moved more than r_g/2 since the last
+ * build (tested every step on the device; no host synchronisation). The
+ * number of builds is reported by mdx_get_info. Inside a step the PME
+ * potential (spread, FFTs) runs on a library-owned second stream,
+ * concurrently with the pair kernel; it is forked from and joined back into
+ * the context's stream, so the call is ordered on that stream like any
+ * other work. energies, if not
  * NULL, is dev double[n_steps][MDX_N_ENERGY]: all slots after each step.
  */
 int mdx_integrate_step(mdx_ctx* ctx, float* pos, float* vel, float* force, int32_t n_steps,
@@ -222,14 +248,16 @@ int mdx_integrate_step(mdx_ctx* ctx, float* pos, float* vel, float* force, int32
 /* Synchronising. Returns the latched MDX_FLAG_* bits in *flags and clears them. */
 int mdx_get_status(mdx_ctx* ctx, uint32_t* flags);
 
-/* Fills *info (host). */
+/* Fills *info (host). Synchronising once a list exists: the list is copied
+ * to the host to count its entries. */
 int mdx_get_info(mdx_ctx* ctx, mdx_info* info);
 
 /* ---- diagnostics ---------------------------------------------------------
  * Kernel timing with HIP events recorded on the context's stream around the
  * launches of one kernel group. Groups: MDX_TIMING_PAIR (the short-range
- * pair kernel), MDX_TIMING_PME (spread .. gather), MDX_TIMING_BUILD (list
- * build). mdx_set_timing(ctx, 1) clears earlier records and starts
+ * pair kernel), MDX_TIMING_PME (spread .. gather in mdx_compute_pme; spread
+ * .. last FFT pass, on the second stream, in mdx_integrate_step, where it
+ * overlaps the pair kernel), MDX_TIMING_BUILD (list build). mdx_set_timing(ctx, 1) clears earlier records and starts
  * recording (at most 8192 launches per group; later launches are not
  * recorded); 0 stops. mdx_get_timing is synchronising and returns the mean
  * duration in ms and the number of recorded launches. */

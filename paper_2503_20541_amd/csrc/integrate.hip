@@ -1,6 +1,11 @@
 // Velocity Verlet (DIMOS Sec. II.D.1): the half kick + drift of steps 1-2 and
 // the closing half kick of step 5, with positions wrapped back into [0, L).
-#include "mdx_internal.h"
+//
+// k_begin_step / k_finish_step: the updates fused, per slot, with the
+//   neighbour-list refresh and validity test (begin) and with the PME force
+//   interpolation, the bonded and exclusion terms and the kinetic energy
+//   (finish); mdx_integrate_step uses these.
+#include "atom_terms.h"
 
 namespace mdx {
 
@@ -14,69 +19,123 @@ __device__ __forceinline__ float wrap_box(float x, float L) {
   return x;
 }
 
-__global__ void __launch_bounds__(256) k_kick_drift(float* __restrict__ pos,
-                                                    float* __restrict__ vel,
-                                                    const float* __restrict__ force,
-                                                    const float* __restrict__ acc_over_m, int n,
-                                                    float half_dt, float dt, float Lx, float Ly,
-                                                    float Lz, int* __restrict__ gate) {
-  int a = blockIdx.x * blockDim.x + threadIdx.x;
-  if (gate && a == 0) *gate = 0;
-  if (a >= n) return;
-  float h = half_dt * acc_over_m[a];
-  float L[3] = {Lx, Ly, Lz};
-  for (int d = 0; d < 3; ++d) {
-    size_t k = (size_t)d * n + a;
-    float v = vel[k] + h * force[k];
-    vel[k] = v;
-    pos[k] = wrap_box(pos[k] + dt * v, L[d]);
+// Opening half of a step for every slot: v += (dt/2) a, x += dt v (wrapped),
+// slot position refreshed, r_g/2 validity test (raises gate_now). Thread 0
+// clears the gate of the following step (nothing else touches it here) and
+// raises gate_now on a cadence rebuild.
+__global__ void __launch_bounds__(256) k_begin_step(
+    float* __restrict__ pos, float* __restrict__ vel, const float* __restrict__ force,
+    const float* __restrict__ acc_over_m, const int* __restrict__ perm,
+    const float* __restrict__ q, const float* __restrict__ x_build, const int* __restrict__ meta,
+    int n, CellGrid cg, float half_dt, float dt, float half_skin2, float4* __restrict__ xs,
+    unsigned* __restrict__ flags, int* __restrict__ gate_now, int* __restrict__ gate_next,
+    int force_rebuild) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s == 0) {
+    *gate_next = 0;
+    if (force_rebuild) *gate_now = 1;
   }
+  if (s >= meta[0]) return;
+  const int a = perm[s];
+  if (a < 0) return;
+  const float h = half_dt * acc_over_m[a];
+  float x[3];
+  for (int d = 0; d < 3; ++d) {
+    const size_t k = (size_t)d * n + a;
+    const float v = vel[k] + h * force[k];
+    vel[k] = v;
+    x[d] = wrap_box(pos[k] + dt * v, cg.L[d]);
+    pos[k] = x[d];
+  }
+  xs[s] = make_float4(x[0], x[1], x[2], q[a]);
+  const float dx = min_image(x_build[a], x[0], cg.L[0], cg.hL[0]);
+  const float dy = min_image(x_build[n + a], x[1], cg.L[1], cg.hL[1]);
+  const float dz = min_image(x_build[2 * n + a], x[2], cg.L[2], cg.hL[2]);
+  if (dist2(dx, dy, dz) > half_skin2) atomicOr(gate_now, 1);
 }
 
-template <bool ENERGY>
-__global__ void __launch_bounds__(256) k_kick(float* __restrict__ vel,
-                                              const float* __restrict__ force,
-                                              const float* __restrict__ acc_over_m,
-                                              const float* __restrict__ mass, int n,
-                                              float half_dt, double inv_2acc,
-                                              double* __restrict__ partials, int pstride) {
+// Closing half of a step for every slot: the total force on the atom is the
+// pair force accumulated in the slot array (which is cleared for the next
+// evaluation), plus the PME interpolation and the bonded / exclusion terms;
+// it is stored and applied as v += (dt/2) a. FP64 energy partials
+// (exclusion, bond, angle, kinetic) per block.
+template <bool ENERGY, bool COUL, bool PME>
+__global__ void __launch_bounds__(256) k_finish_step(
+    const float4* __restrict__ xs, const int* __restrict__ perm, const int* __restrict__ meta,
+    const float* __restrict__ phi, PmeParams pp, const float* __restrict__ pos, int n,
+    BondedParams bp, Topology tp, float* __restrict__ fslot, int fstride,
+    float* __restrict__ force, float* __restrict__ vel,
+    const float* __restrict__ acc_over_m, const float* __restrict__ mass, float half_dt,
+    double inv_2acc, double* __restrict__ partials, int pstride) {
   __shared__ double red[16];
-  int a = blockIdx.x * blockDim.x + threadIdx.x;
-  double ke = 0.0;
-  if (a < n) {
-    float h = half_dt * acc_over_m[a];
-    double v2 = 0.0;
-    for (int d = 0; d < 3; ++d) {
-      size_t k = (size_t)d * n + a;
-      float v = vel[k] + h * force[k];
-      vel[k] = v;
-      v2 += (double)v * (double)v;
-    }
-    ke = (double)mass[a] * v2 * inv_2acc;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  double e_ex = 0.0, e_b = 0.0, e_a = 0.0, ke = 0.0;
+  const int a = s < meta[0] ? perm[s] : -1;
+  if (a >= 0) {
+    float fx = fslot[s], fy = fslot[fstride + s], fz = fslot[2 * fstride + s];
+    fslot[s] = 0.f;
+    fslot[fstride + s] = 0.f;
+    fslot[2 * fstride + s] = 0.f;
+    if (PME) pme_gather_atom(xs[s], phi, pp, fx, fy, fz);
+    bonded_excl_atom<ENERGY, COUL>(a, pos, n, bp, tp, fx, fy, fz, e_ex, e_b, e_a);
+    force[a] = fx;
+    force[n + a] = fy;
+    force[2 * n + a] = fz;
+    const float h = half_dt * acc_over_m[a];
+    const float v0 = vel[a] + h * fx, v1 = vel[n + a] + h * fy, v2 = vel[2 * n + a] + h * fz;
+    vel[a] = v0;
+    vel[n + a] = v1;
+    vel[2 * n + a] = v2;
+    if (ENERGY)
+      ke = (double)mass[a] * ((double)v0 * v0 + (double)v1 * v1 + (double)v2 * v2) * inv_2acc;
   }
   if (ENERGY) {
-    double s = block_sum(ke, red);
-    if (threadIdx.x == 0) partials[kRowKin * pstride + blockIdx.x] = s;
+    double s1 = block_sum(e_ex, red);
+    double s2 = block_sum(e_b, red);
+    double s3 = block_sum(e_a, red);
+    double s4 = block_sum(ke, red);
+    if (threadIdx.x == 0) {
+      partials[kRowExcl * pstride + blockIdx.x] = s1;
+      partials[kRowBond * pstride + blockIdx.x] = s2;
+      partials[kRowAngle * pstride + blockIdx.x] = s3;
+      partials[kRowKin * pstride + blockIdx.x] = s4;
+    }
   }
 }
 
-hipError_t launch_kick_drift(Ctx& c, float* pos, float* vel, const float* force, float dt,
-                             int* gate) {
-  k_kick_drift<<<(c.n + 255) / 256, 256, 0, c.stream>>>(pos, vel, force, c.hdt_scale, c.n,
-                                                        0.5f * dt, dt, c.box[0], c.box[1],
-                                                        c.box[2], gate);
+hipError_t launch_begin_step(Ctx& c, float* pos, float* vel, const float* force, float dt,
+                             int* gate_now, int* gate_next, bool force_rebuild) {
+  const float h = 0.5f * c.r_ghost;
+  k_begin_step<<<(c.max_slots + 255) / 256, 256, 0, c.stream>>>(
+      pos, vel, force, c.hdt_scale, c.perm, c.q, c.x_build, c.meta, c.n, c.cg, 0.5f * dt, dt,
+      h * h, c.xs, c.flags, gate_now, gate_next, force_rebuild ? 1 : 0);
   return hipGetLastError();
 }
 
-hipError_t launch_kick(Ctx& c, float* vel, const float* force, float dt, bool energy) {
-  const int nb = (c.n + 255) / 256;
-  double inv_2acc = 0.5 / c.accel;
-  if (energy)
-    k_kick<true><<<nb, 256, 0, c.stream>>>(vel, force, c.hdt_scale, c.mass, c.n, 0.5f * dt,
-                                           inv_2acc, c.partials, c.max_blocks);
-  else
-    k_kick<false><<<nb, 256, 0, c.stream>>>(vel, force, c.hdt_scale, c.mass, c.n, 0.5f * dt,
-                                            inv_2acc, c.partials, c.max_blocks);
+hipError_t launch_finish_step(Ctx& c, const float* pos, float* vel, float* force, float dt,
+                              bool energy) {
+  const int nb = (c.max_slots + 255) / 256;
+  const PmeParams pp = c.has_pme ? make_pme_params(c) : PmeParams{};
+  const BondedParams bp = make_bonded_params(c);
+  const Topology tp = make_topology(c);
+  const double inv_2acc = 0.5 / c.accel;
+  c.finish_blocks = nb;
+#define MDX_FIN(E, C, P)                                                                      \
+  k_finish_step<E, C, P><<<nb, 256, 0, c.stream>>>(c.xs, c.perm, c.meta, c.grid_phi, pp, pos, \
+                                                    c.n, bp, tp, c.fslot, c.max_slots, force, \
+                                                    vel, c.hdt_scale, c.mass, 0.5f * dt,      \
+                                                    inv_2acc, c.partials, c.max_blocks)
+  const bool C = c.has_coulomb, P = c.has_pme;
+  if (energy) {
+    if (C && P) MDX_FIN(true, true, true);
+    else if (C) MDX_FIN(true, true, false);
+    else MDX_FIN(true, false, false);
+  } else {
+    if (C && P) MDX_FIN(false, true, true);
+    else if (C) MDX_FIN(false, true, false);
+    else MDX_FIN(false, false, false);
+  }
+#undef MDX_FIN
   return hipGetLastError();
 }
 

@@ -50,6 +50,7 @@ struct Ctx {
   double coulomb_k = 0.0, accel = 1.0, boltzmann = 1.0;
   double e_self = 0.0;    // Eq. 12 + neutralising term (host FP64, fixed charges)
   bool has_coulomb = false, has_pme = false, has_switch = false;
+  bool half_list = false;      // each pair once, float atomics (MDX_OPT_HALF_LIST)
   int n_types = 0, n_excl = 0, n_bonds = 0, n_angles = 0;
   int cell_div = 2;
   int nl_cap = 0;               // tiles per i-cluster
@@ -83,11 +84,13 @@ struct Ctx {
   int* cell_start = nullptr;   // [ncol + 1] first atom (unpadded) of each column
   int* cell_cursor = nullptr;  // [ncol]
   int* slot_start = nullptr;   // [ncol + 1] first slot of each column (padded to clusters)
-  int* meta = nullptr;         // [2] slots, clusters of the last build
+  int* meta = nullptr;         // [3] slots, clusters of the last build; builds so far
   int* perm_unsorted = nullptr;// [n]
   int* perm = nullptr;         // [max_slots] slot -> caller atom, -1 for padding
   int* inv_perm = nullptr;     // [n] caller atom -> slot
   float4* xs = nullptr;        // [max_slots] (x, y, z, q) at the current positions
+  float* fslot = nullptr;      // [3][max_slots] pair forces by slot; all zero between
+                               // a force evaluation's consumer and the next pair kernel
   int* ts = nullptr;           // [max_slots] LJ type
   float* zb = nullptr;         // [max_slots] z at the last build (sorted within a column)
   float4* box_lo = nullptr;    // [max_clusters] cluster box (w = real atoms)
@@ -97,7 +100,7 @@ struct Ctx {
   int* tile_count = nullptr;   // [max_clusters]
   int* nl_needed = nullptr;    // [1] max tiles one cluster needed in the last build
   unsigned* flags = nullptr;   // [1] latched MDX_FLAG_*
-  int* gate = nullptr;         // [1] rebuild request inside mdx_integrate_step
+  int* gate = nullptr;         // [2] rebuild requests inside mdx_integrate_step (step parity)
 
   // ---- PME ----
   float* grid_q = nullptr;     // [Kz][Ky][Kx] real
@@ -109,6 +112,8 @@ struct Ctx {
   double pme_energy_scale = 0.0;                 // 1 / (pi V)
   int* brick_cols = nullptr;   // per brick index along x, y: first column, count
   float* brick_z = nullptr;    // per brick index along z: z range [lo, hi) of atoms that reach it
+  int4* brick_zr = nullptr;    // [brick layers along z][columns] (first slot, count) of the two
+                               // periodic segments of the column inside that z range (per build)
 
   // ---- reductions ----
   double* partials = nullptr;  // [kRowCount][max_blocks]
@@ -117,6 +122,7 @@ struct Ctx {
   float* force_scratch = nullptr;     // [3][n] forces inside integrate_step
   int nb_blocks = 0;                  // blocks used by the last nonbonded launch
   int pme_blocks = 0;
+  int finish_blocks = 0;              // blocks of the fused closing kernel
 };
 
 // ---- launchers (each returns hipError_t of the launch) ----
@@ -124,12 +130,10 @@ hipError_t launch_fill_i32(int* p, int v, int count, hipStream_t s);
 // gate == nullptr: unconditional build; otherwise every build kernel returns
 // at once unless *gate != 0.
 hipError_t launch_build_list(Ctx& c, const float* pos, const int* gate = nullptr);
-// Copies pos into the sorted array and tests the r_g/2 validity rule. With
-// gate == nullptr a violation latches MDX_FLAG_NL_STALE; otherwise it sets
-// *gate (and force_rebuild sets it unconditionally).
-hipError_t launch_refresh_sorted(Ctx& c, const float* pos, int* gate = nullptr,
-                                 bool force_rebuild = false);
-hipError_t launch_nonbonded(Ctx& c, float* force, bool energy);
+// Copies pos into the slot array and tests the r_g/2 validity rule; a
+// violation latches MDX_FLAG_NL_STALE.
+hipError_t launch_refresh_sorted(Ctx& c, const float* pos);
+hipError_t launch_nonbonded(Ctx& c, bool energy);
 hipError_t launch_bonded_excl(Ctx& c, const float* pos, float* force, bool energy);
 // Sums the FP64 partial rows into out[slot - slot_base] (slots MDX_ENERGY_*);
 // const_slot >= 0 also stores const_val there, zero_slot >= 0 stores 0.
@@ -138,16 +142,27 @@ hipError_t launch_reduce_energy(Ctx& c, const int* rows, const int* nblk, int nr
                                 int zero_slot = -1);
 bool pme_size_supported(int K);
 hipError_t launch_pme(Ctx& c, float* force, bool energy);
-// Also clears *gate (if not null) for the step that follows.
-hipError_t launch_kick_drift(Ctx& c, float* pos, float* vel, const float* force, float dt,
-                             int* gate = nullptr);
-hipError_t launch_kick(Ctx& c, float* vel, const float* force, float dt, bool energy);
-hipError_t launch_copy_f32(float* dst, const float* src, int count, hipStream_t s);
+// Fused per-slot step kernels used by mdx_integrate_step.
+hipError_t launch_begin_step(Ctx& c, float* pos, float* vel, const float* force, float dt,
+                             int* gate_now, int* gate_next, bool force_rebuild);
+hipError_t launch_finish_step(Ctx& c, const float* pos, float* vel, float* force, float dt,
+                              bool energy);
+// Spread + FFT passes only (the potential grid), for the fused closing kernel.
+hipError_t launch_pme_potential(Ctx& c, hipStream_t s);
 
 // Device helpers shared by kernels -------------------------------------------
 
 // Accurate float32 minimum-image displacement x_j - x_i (see mdx.h); the
 // operations are not contracted so the result is the specified expression.
+// First index in [lo, hi) with a[index] >= v (a nondecreasing).
+__device__ __forceinline__ int lower_bound_f(const float* __restrict__ a, int lo, int hi, float v) {
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (a[mid] < v) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
 __device__ __forceinline__ float min_image(float xi, float xj, float L, float hL) {
 #pragma clang fp contract(off)
   float s = xj - xi;

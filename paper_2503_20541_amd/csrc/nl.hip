@@ -7,14 +7,19 @@
 // cluster of a column is padded with empty slots). For every i-cluster the
 // list keeps the j-clusters whose bounding boxes come closer than r_nl, each
 // with a 16-bit mask whose bit 4*a + b says that slot pair (a, b) passes the
-// float32 inclusion predicate of mdx.h and is not excluded. The set bits are
-// exactly the atom-pair list (both directions), so the exported list is the
+// float32 inclusion predicate of mdx.h and is not excluded. By default every
+// pair is held from both ends (full list). With a half list every unordered
+// pair is held once (Newton's third law: the force kernel applies each pair
+// force to both atoms): a pair of distinct clusters is listed by one of the
+// two, chosen by index parity, and a cluster's own tile keeps the slot pairs
+// a < b. The set bits are exactly the pair list, so the exported list is the
 // definition's, while the force kernel streams whole 4x4 tiles.
 //
 // Build kernels (all gated: with a gate they return unless it is raised):
-//   k_prepare -> k_bin (column of every atom, counts) -> k_scan (atom and
+//   k_bin (column of every atom, counts) -> k_scan (atom and
 //   padded-slot offsets per column) -> k_scatter -> k_col_sort (rank by z,
-//   write slot data) -> k_cluster_box -> k_tile_search (one wave per i-cluster).
+//   write slot data) -> k_cluster_box (also the PME spreading's column
+//   ranges) -> k_tile_search (one wave per i-cluster).
 #include "mdx_internal.h"
 
 namespace mdx {
@@ -58,14 +63,6 @@ __device__ __forceinline__ int wave_aggregated_inc(int* __restrict__ ctr, int ke
   return result;
 }
 
-__global__ void k_prepare(const int* __restrict__ gate, int* __restrict__ col_count, int ncol,
-                          int* __restrict__ nl_needed) {
-  if (gated_off(gate)) return;
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < ncol) col_count[i] = 0;
-  if (i == 0) *nl_needed = 0;
-}
-
 // Column of every caller atom, atoms per column, build-position snapshot.
 __global__ void k_bin(const int* __restrict__ gate, const float* __restrict__ pos, int n,
                       CellGrid cg, int* __restrict__ col_of, int* __restrict__ col_count,
@@ -91,12 +88,15 @@ __global__ void k_bin(const int* __restrict__ gate, const float* __restrict__ po
 
 // Exclusive scans of the column counts (atoms) and of the counts rounded up
 // to whole clusters (slots), in one 1024-thread block; a wave-level shuffle
-// scan combines per-thread chunk sums. meta[0] = slots, meta[1] = clusters.
+// scan combines per-thread chunk sums. meta[0] = slots, meta[1] = clusters,
+// meta[2] counts the builds. The counts are cleared once read (ready for the
+// next build's binning; they start at zero) and so is nl_needed.
 __global__ void __launch_bounds__(1024) k_scan(const int* __restrict__ gate,
-                                               const int* __restrict__ count, int ncol,
+                                               int* __restrict__ count, int ncol,
                                                int* __restrict__ start, int* __restrict__ cursor,
                                                int* __restrict__ slot_start,
-                                               int* __restrict__ meta) {
+                                               int* __restrict__ meta,
+                                               int* __restrict__ nl_needed) {
   if (gated_off(gate)) return;
   __shared__ int wave_tot[2][16];
   int t = threadIdx.x;
@@ -135,16 +135,20 @@ __global__ void __launch_bounds__(1024) k_scan(const int* __restrict__ gate,
     slot_start[ncol] = accp;
     meta[0] = accp;
     meta[1] = accp / kClusterSize;
+    meta[2] += 1;
+    *nl_needed = 0;
   }
   __syncthreads();
   int run = wave_tot[0][w] + v - s;
   int runp = wave_tot[1][w] + vp - sp;
   for (int i = b; i < e; ++i) {
+    const int ci = count[i];
     start[i] = run;
     cursor[i] = run;
     slot_start[i] = runp;
-    run += count[i];
-    runp += (count[i] + kClusterSize - 1) / kClusterSize * kClusterSize;
+    run += ci;
+    runp += (ci + kClusterSize - 1) / kClusterSize * kClusterSize;
+    count[i] = 0;
   }
 }
 
@@ -158,68 +162,64 @@ __global__ void k_scatter(const int* __restrict__ gate, const int* __restrict__ 
   if (active) perm_unsorted[slot] = a;
 }
 
-// One wave per column: rank its atoms by (build z, atom index) - an order
-// that does not depend on the scatter's atomic order - and write the slot
-// data; padding slots of the column's last cluster are emptied. Columns of
-// up to kColStage atoms are ranked from LDS.
-constexpr int kColStage = 512;
+// One workgroup per column: rank its atoms by (build z, atom index) - an
+// order that does not depend on the scatter's atomic order - and write the
+// slot data; padding slots of the column's last cluster are emptied.
+// Columns of up to kColStage atoms are ranked from LDS, larger ones from
+// global memory.
+constexpr int kColThreads = 128;
+constexpr int kColStage = 1024;
 
-__global__ void __launch_bounds__(256) k_col_sort(
+__global__ void __launch_bounds__(kColThreads) k_col_sort(
     const int* __restrict__ gate, const int* __restrict__ col_start,
     const int* __restrict__ slot_start, int ncol, const int* __restrict__ perm_unsorted,
     const float* __restrict__ pos, int n, const float* __restrict__ q,
     const int* __restrict__ atype, int* __restrict__ perm, int* __restrict__ inv_perm,
     float4* __restrict__ xs, int* __restrict__ ts, float* __restrict__ zb) {
   if (gated_off(gate)) return;
-  __shared__ float zst[4][kColStage];
-  __shared__ int ist[4][kColStage];
-  const int w = threadIdx.x / kWave;
-  int c = blockIdx.x * 4 + w;
-  int lane = threadIdx.x & (kWave - 1);
+  __shared__ float2 st[kColStage];   // (build z, atom index bits)
+  const int c = blockIdx.x;
   if (c >= ncol) return;
-  int b = col_start[c], e = col_start[c + 1];
-  int cnt = e - b;
-  int sb = slot_start[c], se = slot_start[c + 1];
+  const int b = col_start[c], e = col_start[c + 1];
+  const int cnt = e - b;
+  const int sb = slot_start[c], se = slot_start[c + 1];
   const bool staged = cnt <= kColStage;
   if (staged) {
-    for (int p = lane; p < cnt; p += kWave) {
-      int v = perm_unsorted[b + p];
-      ist[w][p] = v;
-      zst[w][p] = pos[2 * n + v];
+    for (int p = threadIdx.x; p < cnt; p += kColThreads) {
+      const int v = perm_unsorted[b + p];
+      st[p] = make_float2(pos[2 * n + v], __int_as_float(v));
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    __syncthreads();
   }
-  for (int p = lane; p < cnt; p += kWave) {
-    int v;
+  for (int p = threadIdx.x; p < cnt; p += kColThreads) {
+    int v, rank = 0;
     float zv;
-    int rank = 0;
     if (staged) {
-      v = ist[w][p];
-      zv = zst[w][p];
+      const float2 me = st[p];
+      zv = me.x;
+      v = __float_as_int(me.y);
       for (int k = 0; k < cnt; ++k) {
-        float zu = zst[w][k];
-        int u = ist[w][k];
-        rank += (zu < zv || (zu == zv && u < v)) ? 1 : 0;
+        const float2 o = st[k];
+        const int u = __float_as_int(o.y);
+        rank += (o.x < zv || (o.x == zv && u < v)) ? 1 : 0;
       }
     } else {
       v = perm_unsorted[b + p];
       zv = pos[2 * n + v];
       for (int k = 0; k < cnt; ++k) {
-        int u = perm_unsorted[b + k];
-        float zu = pos[2 * n + u];
+        const int u = perm_unsorted[b + k];
+        const float zu = pos[2 * n + u];
         rank += (zu < zv || (zu == zv && u < v)) ? 1 : 0;
       }
     }
-    int s = sb + rank;
+    const int s = sb + rank;
     perm[s] = v;
     inv_perm[v] = s;
     xs[s] = make_float4(pos[v], pos[n + v], zv, q[v]);
     ts[s] = atype[v];
     zb[s] = zv;
   }
-  for (int s = sb + cnt + lane; s < se; s += kWave) {
+  for (int s = sb + cnt + threadIdx.x; s < se; s += kColThreads) {
     perm[s] = -1;
     xs[s] = make_float4(0.f, 0.f, 0.f, 0.f);
     ts[s] = 0;
@@ -227,11 +227,51 @@ __global__ void __launch_bounds__(256) k_col_sort(
   }
 }
 
-// Bounding box of every cluster's real atoms at the build positions.
+// For the PME spreading: per (brick layer along z, column) the slots of the
+// column whose build z lies in the layer's reach [lo, hi) - one segment, or
+// two when the reach wraps around the periodic box.
+struct ZRangeArgs {
+  const float* zb;
+  const int* slot_start;
+  const int* col_start;   // atom offsets: the column's atom count is the difference
+  const float* layer_z;   // [layers][2] lo, hi
+  int layers;
+  int ncol;
+  float Lz;
+  int4* out;              // [layers][ncol] (first, count) of both segments
+};
+
+__device__ void column_zrange(int e, const ZRangeArgs& z) {
+  const int layer = e / z.ncol, col = e - layer * z.ncol;
+  const float zlo = z.layer_z[2 * layer], zhi = z.layer_z[2 * layer + 1];
+  const int sb = z.slot_start[col], se = sb + (z.col_start[col + 1] - z.col_start[col]);
+  float a0 = zlo, b0 = zhi, a1 = 0.f, b1 = 0.f;
+  if (zlo < 0.f) {
+    a0 = 0.f; b0 = zhi; a1 = zlo + z.Lz; b1 = z.Lz;
+  } else if (zhi > z.Lz) {
+    a0 = zlo; b0 = z.Lz; a1 = 0.f; b1 = zhi - z.Lz;
+  }
+  const int s0 = lower_bound_f(z.zb, sb, se, a0), e0 = lower_bound_f(z.zb, sb, se, b0);
+  int s1 = sb, e1 = sb;
+  if (b1 > a1) {
+    s1 = lower_bound_f(z.zb, sb, se, a1);
+    e1 = lower_bound_f(z.zb, sb, se, b1);
+  }
+  z.out[e] = make_int4(s0, max(0, e0 - s0), s1, max(0, e1 - s1));
+}
+
+// Bounding box of every cluster's real atoms at the build positions; blocks
+// past the cluster blocks fill the PME column ranges.
 __global__ void k_cluster_box(const int* __restrict__ gate, const int* __restrict__ meta,
                               const float4* __restrict__ xs, const int* __restrict__ perm,
-                              float4* __restrict__ box_lo, float4* __restrict__ box_hi) {
+                              float4* __restrict__ box_lo, float4* __restrict__ box_hi,
+                              int cluster_blocks, ZRangeArgs zr) {
   if (gated_off(gate)) return;
+  if ((int)blockIdx.x >= cluster_blocks) {
+    const int e = ((int)blockIdx.x - cluster_blocks) * blockDim.x + threadIdx.x;
+    if (e < zr.layers * zr.ncol) column_zrange(e, zr);
+    return;
+  }
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= meta[1]) return;
   float lx = 3e38f, ly = 3e38f, lz = 3e38f, hx = -3e38f, hy = -3e38f, hz = -3e38f;
@@ -246,6 +286,16 @@ __global__ void k_cluster_box(const int* __restrict__ gate, const int* __restric
   }
   box_lo[c] = make_float4(lx, ly, lz, (float)nvalid);
   box_hi[c] = make_float4(hx, hy, hz, 0.f);
+}
+
+// Each unordered pair of distinct clusters is listed once, from the cluster
+// that index parity designates: for ic < jc the lower index owns the pair
+// when ic + jc is even, the higher one when it is odd, so every cluster owns
+// about half of its partners on either side of its own index. A cluster's
+// pairs with itself are kept in its own tile (slot pairs a < b).
+// With a full list (half == 0) every cluster keeps all of its partners.
+__device__ __forceinline__ bool owns_pair(int ic, int jc, int half) {
+  return !half || jc == ic || ((ic < jc) != (((ic + jc) & 1) != 0));
 }
 
 // Periodic gap between two intervals along one axis (0 if they overlap).
@@ -279,15 +329,17 @@ __device__ __forceinline__ int first_gt(const float4* __restrict__ b, int lo, in
 // One wave per i-cluster: (1) enumerate the j-clusters of the columns within
 // reach - inside a column only the z-sorted clusters that overlap the
 // i-box's z reach (one or two periodic segments, binary searches) - and keep
-// those whose boxes come closer than r_nl (+ margin); (2) test the 16 slot
+// those the i-cluster owns (owns_pair) whose boxes come closer than r_nl
+// (+ margin); (2) test the 16 slot
 // pairs of four candidate tiles at once (one lane per pair) with the exact
 // predicate and the exclusions; tiles with a non-empty mask are appended to
 // the i-cluster's list in enumeration order.
 __global__ void __launch_bounds__(256) k_tile_search(
     const int* __restrict__ gate, const int* __restrict__ meta, const float4* __restrict__ xs,
-    const int* __restrict__ perm, const float4* __restrict__ box_lo,
-    const float4* __restrict__ box_hi, const int* __restrict__ slot_start,
-    const int* __restrict__ ex_start, const int* __restrict__ ex_idx, CellGrid cg, int cap,
+    const int* __restrict__ perm, const int* __restrict__ inv_perm,
+    const float4* __restrict__ box_lo, const float4* __restrict__ box_hi,
+    const int* __restrict__ slot_start, const int* __restrict__ ex_start,
+    const int* __restrict__ ex_idx, CellGrid cg, int cap, int half,
     uint2* __restrict__ tiles, int* __restrict__ tile_count, int* __restrict__ nl_needed,
     unsigned* __restrict__ flags) {
   if (gated_off(gate)) return;
@@ -382,7 +434,7 @@ __global__ void __launch_bounds__(256) k_tile_search(
           }
           jc = seg_first[w][lo] + (f - seg_pre[w][lo]);
           float4 jlo = box_lo[jc], jhi = box_hi[jc];
-          if (jlo.w > 0.f) {
+          if (jlo.w > 0.f && owns_pair(ic, jc, half)) {
             float gx = axis_gap(ilo.x, ihi.x, jlo.x, jhi.x, cg.L[0]);
             float gy = axis_gap(ilo.y, ihi.y, jlo.y, jhi.y, cg.L[1]);
             float gz = axis_gap(ilo.z, ihi.z, jlo.z, jhi.z, cg.L[2]);
@@ -410,30 +462,60 @@ __global__ void __launch_bounds__(256) k_tile_search(
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-  // (2) masks: lane = (tile t of 4, i slot a, j slot b)
+  // (2) masks: lane = (tile t of 4, i slot a, j slot b). Padding slots are
+  // the last slots of a cluster (a slot is real iff its index in the cluster
+  // is below the cluster's real-atom count). The i atom's excluded partners
+  // are held as slot indices in registers (the list walk is the fallback
+  // for atoms with more than four exclusions).
   const int t = lane >> 4, a = (lane >> 2) & 3, b = lane & 3;
   const int si = ic * kClusterSize + a;
-  const int ai = perm[si];
+  const bool ivalid = a < (int)ilo.w;
   const float4 pi = xs[si];
-  const int eb = ai >= 0 ? ex_start[ai] : 0, ee = ai >= 0 ? ex_start[ai + 1] : 0;
+  const float lmx = cg.L[0] - pi.x, lmy = cg.L[1] - pi.y, lmz = cg.L[2] - pi.z;
+  int ex0 = -1, ex1 = -1, ex2 = -1, ex3 = -1;
+  int eb = 0, ee = 0;
+  if (ivalid) {
+    const int ai = perm[si];
+    eb = ex_start[ai];
+    ee = ex_start[ai + 1];
+    const int ne = ee - eb;
+    if (ne > 0) ex0 = inv_perm[ex_idx[eb]];
+    if (ne > 1) ex1 = inv_perm[ex_idx[eb + 1]];
+    if (ne > 2) ex2 = inv_perm[ex_idx[eb + 2]];
+    if (ne > 3) ex3 = inv_perm[ex_idx[eb + 3]];
+  }
+  const bool ex_more = ee - eb > 4;
   int count = 0;
+  int jc_n = (t < ncand) ? mycand[t] : -1;
+  float nv_n = 0.f;
+  float4 pj_n = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (jc_n >= 0) {
+    nv_n = box_lo[jc_n].w;
+    pj_n = xs[jc_n * kClusterSize + b];
+  }
   for (int g = 0; g < ncand; g += 4) {
+    const int jc = jc_n;
+    const float nv = nv_n;
+    const float4 pj = pj_n;
+    jc_n = (g + 4 + t < ncand) ? mycand[g + 4 + t] : -1;
+    if (jc_n >= 0) {
+      nv_n = box_lo[jc_n].w;
+      pj_n = xs[jc_n * kClusterSize + b];
+    }
     unsigned bit = 0;
-    int jc = -1;
-    if (g + t < ncand) {
-      jc = mycand[g + t];
-      const int sj = jc * kClusterSize + b;
-      const int aj = perm[sj];
-      if (ai >= 0 && aj >= 0 && sj != si) {
-        const float4 pj = xs[sj];
-        float dx = min_image(pi.x, pj.x, cg.L[0], cg.hL[0]);
-        float dy = min_image(pi.y, pj.y, cg.L[1], cg.hL[1]);
-        float dz = min_image(pi.z, pj.z, cg.L[2], cg.hL[2]);
-        if (dist2(dx, dy, dz) < cg.rnl2) {
-          bool excluded = false;
-          for (int k = eb; k < ee; ++k) excluded |= (ex_idx[k] == aj);
-          bit = excluded ? 0u : 1u;
+    const int sj = jc * kClusterSize + b;
+    // the cluster's own tile: slot pairs a < b (half list) or a != b
+    if (jc >= 0 && ivalid && b < (int)nv && (jc != ic || b > a || (!half && b < a))) {
+      float dx = min_image_h(pi.x, lmx, pj.x, cg.L[0], cg.hL[0]);
+      float dy = min_image_h(pi.y, lmy, pj.y, cg.L[1], cg.hL[1]);
+      float dz = min_image_h(pi.z, lmz, pj.z, cg.L[2], cg.hL[2]);
+      if (dist2(dx, dy, dz) < cg.rnl2) {
+        bool excluded = sj == ex0 || sj == ex1 || sj == ex2 || sj == ex3;
+        if (ex_more && !excluded) {
+          const int aj = perm[sj];
+          for (int k = eb + 4; k < ee; ++k) excluded |= (ex_idx[k] == aj);
         }
+        bit = excluded ? 0u : 1u;
       }
     }
     unsigned long long m = __ballot(bit != 0);
@@ -461,15 +543,12 @@ __global__ void __launch_bounds__(256) k_tile_search(
 
 // Copy the current positions into the slot array and test the list's
 // validity: an atom that moved more than r_g/2 since the build invalidates
-// the list (Sec. II.A.2). Without a gate this latches NL_STALE; with one it
-// requests a rebuild before the forces are taken.
+// the list (Sec. II.A.2) and latches NL_STALE.
 __global__ void k_refresh(const float* __restrict__ pos, const int* __restrict__ perm,
                           const float* __restrict__ q, const float* __restrict__ x_build,
                           const int* __restrict__ meta, int n, CellGrid cg, float half_skin2,
-                          float4* __restrict__ xs, unsigned* __restrict__ flags,
-                          int* __restrict__ gate, int force_rebuild) {
+                          float4* __restrict__ xs, unsigned* __restrict__ flags) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (gate && force_rebuild && s == 0) *gate = 1;
   if (s >= meta[0]) return;
   int a = perm[s];
   if (a < 0) return;
@@ -479,12 +558,8 @@ __global__ void k_refresh(const float* __restrict__ pos, const int* __restrict__
   float dx = min_image(x_build[a], x, cg.L[0], cg.hL[0]);
   float dy = min_image(x_build[n + a], y, cg.L[1], cg.hL[1]);
   float dz = min_image(x_build[2 * n + a], z, cg.L[2], cg.hL[2]);
-  bool stale = dist2(dx, dy, dz) > half_skin2;
   unsigned f = 0;
-  if (stale) {
-    if (gate) atomicOr(gate, 1);
-    else f |= MDX_FLAG_NL_STALE;
-  }
+  if (dist2(dx, dy, dz) > half_skin2) f |= MDX_FLAG_NL_STALE;
   if (!inside) f |= MDX_FLAG_OUT_OF_BOX;
   if (f) atomicOr(flags, f);
 }
@@ -494,27 +569,30 @@ hipError_t launch_build_list(Ctx& c, const float* pos, const int* gate) {
   const int n = c.n;
   const int nb = (n + 255) / 256;
   const int ncol = c.cg.ncell;
-  k_prepare<<<(ncol + 255) / 256, 256, 0, s>>>(gate, c.cell_count, ncol, c.nl_needed);
   k_bin<<<nb, 256, 0, s>>>(gate, pos, n, c.cg, c.cell_of, c.cell_count, c.x_build, c.flags);
   k_scan<<<1, 1024, 0, s>>>(gate, c.cell_count, ncol, c.cell_start, c.cell_cursor, c.slot_start,
-                            c.meta);
+                            c.meta, c.nl_needed);
   k_scatter<<<nb, 256, 0, s>>>(gate, c.cell_of, n, c.cell_cursor, c.perm_unsorted);
-  k_col_sort<<<(ncol + 3) / 4, 256, 0, s>>>(gate, c.cell_start, c.slot_start, ncol,
+  k_col_sort<<<ncol, kColThreads, 0, s>>>(gate, c.cell_start, c.slot_start, ncol,
                                             c.perm_unsorted, pos, n, c.q, c.atype, c.perm,
                                             c.inv_perm, c.xs, c.ts, c.zb);
-  k_cluster_box<<<(c.max_clusters + 255) / 256, 256, 0, s>>>(gate, c.meta, c.xs, c.perm,
-                                                             c.box_lo, c.box_hi);
+  const int cblocks = (c.max_clusters + 255) / 256;
+  ZRangeArgs zr{c.zb, c.slot_start, c.cell_start, c.brick_z, c.has_pme ? c.pg.nb[2] : 0, ncol,
+                c.cg.L[2], c.brick_zr};
+  const int zblocks = (zr.layers * ncol + 255) / 256;
+  k_cluster_box<<<cblocks + zblocks, 256, 0, s>>>(gate, c.meta, c.xs, c.perm, c.box_lo, c.box_hi,
+                                                  cblocks, zr);
   k_tile_search<<<(c.max_clusters + 3) / 4, 256, 0, s>>>(
-      gate, c.meta, c.xs, c.perm, c.box_lo, c.box_hi, c.slot_start, c.ex_start, c.ex_idx, c.cg,
-      c.nl_cap, c.tiles, c.tile_count, c.nl_needed, c.flags);
+      gate, c.meta, c.xs, c.perm, c.inv_perm, c.box_lo, c.box_hi, c.slot_start, c.ex_start,
+      c.ex_idx, c.cg, c.nl_cap, c.half_list ? 1 : 0, c.tiles, c.tile_count, c.nl_needed,
+      c.flags);
   return hipGetLastError();
 }
 
-hipError_t launch_refresh_sorted(Ctx& c, const float* pos, int* gate, bool force_rebuild) {
+hipError_t launch_refresh_sorted(Ctx& c, const float* pos) {
   float h = 0.5f * c.r_ghost;
   k_refresh<<<(c.max_slots + 255) / 256, 256, 0, c.stream>>>(pos, c.perm, c.q, c.x_build, c.meta,
-                                                             c.n, c.cg, h * h, c.xs, c.flags,
-                                                             gate, force_rebuild ? 1 : 0);
+                                                             c.n, c.cg, h * h, c.xs, c.flags);
   return hipGetLastError();
 }
 

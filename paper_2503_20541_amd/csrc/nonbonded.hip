@@ -6,14 +6,20 @@
 //   (Eqs. 4-5, type-pair table, optional Eq. 6 switch) + the minimum-image
 //   real-space Ewald term (Eq. 10) for pairs whose mask bit is set and with
 //   r2 < fl(r_c^2). A group of tiles with no such pair is skipped after the
-//   distance test. The list holds both directions of every pair, so each
-//   row only accumulates its own i force: a 16-lane row reduction at the end,
-//   no atomics, bitwise reproducible. Energies accumulate per lane in FP64.
+//   distance test. Full list (default): every pair is listed from both
+//   ends, the wave stores its i forces and nothing else, so the result is
+//   bitwise reproducible. Half list: every pair is listed once and its force
+//   acts on both atoms: the i force accumulates per lane over the whole
+//   list, the j forces of a group are summed over the four rows with lane
+//   swaps and added to the slot force array with one float atomic per lane
+//   (x, y, z of the 16 j atoms on rows 0-2). Energies accumulate per lane in
+//   FP64 in both modes.
 // k_bonded_excl: one thread per caller atom for the terms that involve it:
-//   the FP64 erf exclusion correction and FP32 harmonic bonds/angles (Eqs. 1-2).
+//   the FP64 erf exclusion correction and FP32 harmonic bonds/angles (Eqs. 1-2);
+//   it also moves the atom's pair force out of the slot array (clearing it).
 //   Each term's energy is booked once, by a designated member atom.
 // k_reduce_rows: fixed-order FP64 reduction of per-block partial sums.
-#include "mdx_internal.h"
+#include "atom_terms.h"
 
 namespace mdx {
 
@@ -54,7 +60,22 @@ struct PairParams {
 // of each pair's distance; k_e is applied in the final FP64 reduction. (The
 // real-space Coulomb sum cancels strongly, so a float32 erfc bias of 1e-7
 // would show up at the 1e-6 level in the total.)
-template <bool ENERGY, bool COUL, bool SWITCH>
+// Sum over the four 16-lane rows at this lane's position in its row
+// (lanes l, l^16, l^32, l^48), returned on every lane in one fixed order.
+__device__ __forceinline__ float sum_rows4(float x) {
+  const unsigned u = __float_as_uint(x);
+  const auto h = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+  const float s = __uint_as_float(h[0]) + __uint_as_float(h[1]);
+  const unsigned us = __float_as_uint(s);
+  const auto r = __builtin_amdgcn_permlane16_swap(us, us, false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Type pairs whose LJ coefficients the pair kernel stages in LDS (larger
+// tables are read from global memory).
+constexpr int kLdsTypePairs = 256;
+
+template <bool ENERGY, bool COUL, bool SWITCH, bool HALF>
 __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
                                               const int* __restrict__ ts,
                                               const uint2* __restrict__ tiles,
@@ -62,10 +83,16 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
                                               const int* __restrict__ meta, int cap,
                                               PairParams pp, const float4* __restrict__ lj_f,
                                               const double2* __restrict__ lj_d,
-                                              const int* __restrict__ perm, int n,
-                                              float* __restrict__ force,
+                                              float* __restrict__ fslot, int fstride,
                                               double* __restrict__ partials, int pstride) {
   __shared__ double red[16];
+  __shared__ float4 lj_s[kLdsTypePairs];
+  const bool lds_table = pp.ntypes * pp.ntypes <= kLdsTypePairs;
+  if (lds_table) {
+    for (int t = threadIdx.x; t < pp.ntypes * pp.ntypes; t += blockDim.x) lj_s[t] = lj_f[t];
+    __syncthreads();
+  }
+  const float4* __restrict__ ljt = lds_table ? lj_s : lj_f;
   const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   const int ic = blockIdx.x * 4 + w;
   const bool active = ic < meta[1];
@@ -80,24 +107,40 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
     const int trow = ts[si] * pp.ntypes;
     const int cnt = tile_count[ic];
     const uint2* tl = tiles + (size_t)ic * cap;
-    // lists are padded to groups of four; the prefetch of the next group is
-    // clamped into the list's allocation and only used while g < cnt
-    uint2 e_next = tl[tt];
+    // j-force component this lane stores: x, y, z on rows 0-2, none on row 3
+    float* const fcomp = fslot + (size_t)(ia < 3 ? ia : 0) * fstride;
+    // Software pipeline: the tiles of the next two groups and the j atoms of
+    // the next group are in flight while a group is computed. Lists are
+    // padded to groups of four (the padding tiles point at cluster 0); reads
+    // past the list are clamped into its allocation and their cluster index
+    // is replaced by 0 before it is used as an address.
+    uint2 e_nx = tl[tt];
+    uint2 e_nx2 = tl[min(4 + tt, cap - 1)];
+    int sj_nx = (cnt > 0 ? (int)e_nx.x : 0) * kClusterSize + jb;
+    float4 pj_nx = xs[sj_nx];
+    int tj_nx = ts[sj_nx];
     for (int g = 0; g < cnt; g += 4) {
-      const uint2 e = e_next;
-      e_next = tl[min(g + 4 + tt, cap - 1)];
+      const uint2 e = e_nx;
+      const int sj = sj_nx;
+      const float4 pj = pj_nx;
+      const int tj = tj_nx;
+      e_nx = e_nx2;
+      e_nx2 = tl[min(g + 8 + tt, cap - 1)];
+      sj_nx = (g + 4 < cnt ? (int)e_nx.x : 0) * kClusterSize + jb;
+      pj_nx = xs[sj_nx];
+      tj_nx = ts[sj_nx];
       const bool on = (e.y >> bitpos) & 1u;
-      const int sj = (int)e.x * kClusterSize + jb;
-      const float4 pj = xs[sj];
       float dx = min_image_h(pi.x, lmx, pj.x, pp.L[0], pp.hL[0]);
       float dy = min_image_h(pi.y, lmy, pj.y, pp.L[1], pp.hL[1]);
       float dz = min_image_h(pi.z, lmz, pj.z, pp.L[2], pp.hL[2]);
       float r2 = dist2(dx, dy, dz);
       const bool in = on && r2 < pp.rc2;
-      if (__ballot(in) == 0ull) continue;
+      const unsigned long long hit = __ballot(in);
+      if (hit == 0ull) continue;
+      float gx = 0.f, gy = 0.f, gz = 0.f;   // force on j (minus the force on i)
       if (in) {
-        const int tp = trow + ts[sj];
-        float4 lj = lj_f[tp];             // c12, c6, 12 c12, 6 c6
+        const int tp = trow + tj;
+        float4 lj = ljt[tp];              // c12, c6, 12 c12, 6 c6
         const float rinv = __builtin_amdgcn_rsqf(r2);   // r2 is never denormal here
         const float rinv2 = rinv * rinv;
         float r6 = rinv2 * rinv2 * rinv2;
@@ -124,9 +167,12 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
           ec = erfc_scaled(ar) * ex;
           f_over_r += pp.coulomb_k * (pi.w * pj.w) * (ec * rinv + pp.two_a_sqrtpi * ex) * rinv2;
         }
-        fx -= f_over_r * dx;
-        fy -= f_over_r * dy;
-        fz -= f_over_r * dz;
+        gx = f_over_r * dx;
+        gy = f_over_r * dy;
+        gz = f_over_r * dz;
+        fx -= gx;
+        fy -= gy;
+        fz -= gz;
         if (ENERGY) {
           double2 c = lj_d[tp];
           double r2d = (double)r2;
@@ -140,26 +186,39 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
           }
         }
       }
+      if (HALF) {
+        gx = sum_rows4(gx);
+        gy = sum_rows4(gy);
+        gz = sum_rows4(gz);
+        // j atoms (lane & 15) with at least one interacting pair in the group
+        const unsigned jhit = (unsigned)((hit | hit >> 16 | hit >> 32 | hit >> 48) & 0xffffull);
+        if (ia < 3 && ((jhit >> (lane & 15)) & 1u))
+          atomicAdd(fcomp + sj, ia == 0 ? gx : (ia == 1 ? gy : gz));
+      }
     }
   }
-  // sum the i force over the 16 lanes of the row
+  // sum the i force over the 16 lanes of the row; lanes 0-2 of the row add
+  // (half list) or store (full list: the wave owns the slot) its x, y, z
   for (int o = 8; o >= 1; o >>= 1) {
     fx += __shfl_xor(fx, o, kWave);
     fy += __shfl_xor(fy, o, kWave);
     fz += __shfl_xor(fz, o, kWave);
   }
-  if (active && (lane & 15) == 0) {
-    int a = perm[si];
-    if (a >= 0) {
-      force[a] = fx;
-      force[n + a] = fy;
-      force[2 * n + a] = fz;
-    }
+  const int c3 = lane & 15;
+  if (active && c3 < 3) {
+    const float v = c3 == 0 ? fx : (c3 == 1 ? fy : fz);
+    float* dst = fslot + (size_t)c3 * fstride + si;
+    if (!HALF) *dst = v;
+    else if (v != 0.f) atomicAdd(dst, v);
   }
   if (ENERGY) {
-    // every pair was visited from both ends
-    double s_lj = block_sum(0.5 * e_lj, red);
-    double s_c = block_sum(0.5 * e_c, red);
+    // a full list visits every pair from both ends
+    if (!HALF) {
+      e_lj *= 0.5;
+      e_c *= 0.5;
+    }
+    double s_lj = block_sum(e_lj, red);
+    double s_c = block_sum(e_c, red);
     if (threadIdx.x == 0) {
       partials[kRowLJ * pstride + blockIdx.x] = s_lj;
       partials[kRowDir * pstride + blockIdx.x] = s_c;
@@ -167,107 +226,27 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
   }
 }
 
-struct BondedParams {
-  float L[3], hL[3];
-  double Ld[3];
-  double alpha, two_a_sqrtpi, coulomb_k;
-};
-
 template <bool ENERGY, bool COUL>
-__global__ void __launch_bounds__(256) k_bonded_excl(
-    const float* __restrict__ pos, int n, BondedParams bp, const float* __restrict__ q,
-    const int* __restrict__ ex_start, const int* __restrict__ ex_idx,
-    const int* __restrict__ bonds, const float* __restrict__ bond_k,
-    const float* __restrict__ bond_r0, const int* __restrict__ bt_start,
-    const int* __restrict__ bt_idx, const int* __restrict__ angles,
-    const float* __restrict__ angle_k, const float* __restrict__ angle_t0,
-    const int* __restrict__ at_start, const int* __restrict__ at_idx, float* __restrict__ force,
-    double* __restrict__ partials, int pstride) {
+__global__ void __launch_bounds__(256) k_bonded_excl(const float* __restrict__ pos, int n,
+                                                     BondedParams bp, Topology tp,
+                                                     const int* __restrict__ inv_perm,
+                                                     float* __restrict__ fslot, int fstride,
+                                                     float* __restrict__ force,
+                                                     double* __restrict__ partials,
+                                                     int pstride) {
   __shared__ double red[16];
   int a = blockIdx.x * blockDim.x + threadIdx.x;
   double e_ex = 0.0, e_b = 0.0, e_a = 0.0;
   if (a < n) {
-    float xa = pos[a], ya = pos[n + a], za = pos[2 * n + a];
-    float fx = 0.f, fy = 0.f, fz = 0.f;
-    if (COUL) {
-      // -k_e q_a q_b erf(alpha r)/r over excluded partners, in FP64 with the
-      // exact minimum-image displacement of the float32 coordinates.
-      double gx = 0.0, gy = 0.0, gz = 0.0;
-      double qa = (double)q[a];
-      for (int k = ex_start[a]; k < ex_start[a + 1]; ++k) {
-        int b = ex_idx[k];
-        double d[3] = {(double)pos[b] - (double)xa, (double)pos[n + b] - (double)ya,
-                       (double)pos[2 * n + b] - (double)za};
-        for (int t = 0; t < 3; ++t) {
-          if (d[t] > 0.5 * bp.Ld[t]) d[t] -= bp.Ld[t];
-          else if (d[t] < -0.5 * bp.Ld[t]) d[t] += bp.Ld[t];
-        }
-        double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-        double r = sqrt(r2);
-        double qq = bp.coulomb_k * qa * (double)q[b];
-        double ar = bp.alpha * r;
-        double erfv = erf(ar);
-        double u = -qq * erfv / r;
-        // dU/dr = -qq (2a/sqrt(pi) exp(-a^2 r^2)/r - erf/r^2); force on a = dU/dr * d / r
-        double dudr = -qq * (bp.two_a_sqrtpi * exp(-ar * ar) / r - erfv / r2);
-        double s = dudr / r;
-        gx += s * d[0];
-        gy += s * d[1];
-        gz += s * d[2];
-        if (ENERGY && a < b) e_ex += u;
-      }
-      fx += (float)gx;
-      fy += (float)gy;
-      fz += (float)gz;
-    }
-    for (int k = bt_start[a]; k < bt_start[a + 1]; ++k) {
-      int t = bt_idx[k];
-      int i = bonds[2 * t], j = bonds[2 * t + 1];
-      float dx = min_image(pos[i], pos[j], bp.L[0], bp.hL[0]);
-      float dy = min_image(pos[n + i], pos[n + j], bp.L[1], bp.hL[1]);
-      float dz = min_image(pos[2 * n + i], pos[2 * n + j], bp.L[2], bp.hL[2]);
-      float r = sqrtf(dx * dx + dy * dy + dz * dz);
-      float dr = r - bond_r0[t];
-      float g = -2.0f * bond_k[t] * dr / r;   // force on j = g * d
-      float sgn = (a == j) ? 1.0f : -1.0f;
-      fx += sgn * g * dx;
-      fy += sgn * g * dy;
-      fz += sgn * g * dz;
-      if (ENERGY && a == i) e_b += (double)(bond_k[t] * dr * dr);
-    }
-    for (int k = at_start[a]; k < at_start[a + 1]; ++k) {
-      int t = at_idx[k];
-      int i = angles[3 * t], j = angles[3 * t + 1], l = angles[3 * t + 2];
-      float ax = min_image(pos[j], pos[i], bp.L[0], bp.hL[0]);
-      float ay = min_image(pos[n + j], pos[n + i], bp.L[1], bp.hL[1]);
-      float az = min_image(pos[2 * n + j], pos[2 * n + i], bp.L[2], bp.hL[2]);
-      float bx = min_image(pos[j], pos[l], bp.L[0], bp.hL[0]);
-      float by = min_image(pos[n + j], pos[n + l], bp.L[1], bp.hL[1]);
-      float bz = min_image(pos[2 * n + j], pos[2 * n + l], bp.L[2], bp.hL[2]);
-      float ra = sqrtf(ax * ax + ay * ay + az * az);
-      float rb = sqrtf(bx * bx + by * by + bz * bz);
-      float ira = 1.0f / ra, irb = 1.0f / rb;
-      float ahx = ax * ira, ahy = ay * ira, ahz = az * ira;
-      float bhx = bx * irb, bhy = by * irb, bhz = bz * irb;
-      float c = ahx * bhx + ahy * bhy + ahz * bhz;
-      c = fminf(1.0f, fmaxf(-1.0f, c));
-      float theta = acosf(c);
-      float dth = theta - angle_t0[t];
-      float dU = 2.0f * angle_k[t] * dth;
-      float s = sqrtf(fmaxf(1.0f - c * c, 1e-12f));
-      float pre = dU / s;
-      float fix = pre * (bhx - c * ahx) * ira, fiy = pre * (bhy - c * ahy) * ira,
-            fiz = pre * (bhz - c * ahz) * ira;
-      float flx = pre * (ahx - c * bhx) * irb, fly = pre * (ahy - c * bhy) * irb,
-            flz = pre * (ahz - c * bhz) * irb;
-      if (a == i) { fx += fix; fy += fiy; fz += fiz; }
-      if (a == l) { fx += flx; fy += fly; fz += flz; }
-      if (a == j) { fx -= fix + flx; fy -= fiy + fly; fz -= fiz + flz; }
-      if (ENERGY && a == j) e_a += (double)(angle_k[t] * dth * dth);
-    }
-    force[a] += fx;
-    force[n + a] += fy;
-    force[2 * n + a] += fz;
+    const int s = inv_perm[a];
+    float fx = fslot[s], fy = fslot[fstride + s], fz = fslot[2 * fstride + s];
+    fslot[s] = 0.f;
+    fslot[fstride + s] = 0.f;
+    fslot[2 * fstride + s] = 0.f;
+    bonded_excl_atom<ENERGY, COUL>(a, pos, n, bp, tp, fx, fy, fz, e_ex, e_b, e_a);
+    force[a] = fx;
+    force[n + a] = fy;
+    force[2 * n + a] = fz;
   }
   if (ENERGY) {
     double s1 = block_sum(e_ex, red);
@@ -314,7 +293,7 @@ __global__ void __launch_bounds__(256) k_reduce_rows(const double* __restrict__ 
   }
 }
 
-hipError_t launch_nonbonded(Ctx& c, float* force, bool energy) {
+hipError_t launch_nonbonded(Ctx& c, bool energy) {
   PairParams pp;
   for (int d = 0; d < 3; ++d) {
     pp.L[d] = c.cg.L[d];
@@ -332,27 +311,33 @@ hipError_t launch_nonbonded(Ctx& c, float* force, bool energy) {
   pp.inv_sw = c.has_switch ? 1.0f / (c.r_cut - c.switch_r) : 0.f;
   const int nb = (c.max_clusters + 3) / 4;
   c.nb_blocks = nb;
-#define MDX_PAIR(E, C, S)                                                                       \
-  k_pair<E, C, S><<<nb, 256, 0, c.stream>>>(c.xs, c.ts, c.tiles, c.tile_count, c.meta, c.nl_cap, \
-                                             pp, c.lj_f, c.lj_d, c.perm, c.n, force, c.partials, \
-                                             c.max_blocks)
+#define MDX_PAIR(E, C, S, H)                                                               \
+  k_pair<E, C, S, H><<<nb, 256, 0, c.stream>>>(c.xs, c.ts, c.tiles, c.tile_count, c.meta,   \
+                                                c.nl_cap, pp, c.lj_f, c.lj_d, c.fslot,      \
+                                                c.max_slots, c.partials, c.max_blocks)
+#define MDX_PAIR_H(E, C, S)      \
+  if (c.half_list)               \
+    MDX_PAIR(E, C, S, true);     \
+  else                           \
+    MDX_PAIR(E, C, S, false)
   bool C = c.has_coulomb, S = c.has_switch;
   if (energy) {
-    if (C && S) MDX_PAIR(true, true, true);
-    else if (C) MDX_PAIR(true, true, false);
-    else if (S) MDX_PAIR(true, false, true);
-    else MDX_PAIR(true, false, false);
+    if (C && S) { MDX_PAIR_H(true, true, true); }
+    else if (C) { MDX_PAIR_H(true, true, false); }
+    else if (S) { MDX_PAIR_H(true, false, true); }
+    else { MDX_PAIR_H(true, false, false); }
   } else {
-    if (C && S) MDX_PAIR(false, true, true);
-    else if (C) MDX_PAIR(false, true, false);
-    else if (S) MDX_PAIR(false, false, true);
-    else MDX_PAIR(false, false, false);
+    if (C && S) { MDX_PAIR_H(false, true, true); }
+    else if (C) { MDX_PAIR_H(false, true, false); }
+    else if (S) { MDX_PAIR_H(false, false, true); }
+    else { MDX_PAIR_H(false, false, false); }
   }
+#undef MDX_PAIR_H
 #undef MDX_PAIR
   return hipGetLastError();
 }
 
-hipError_t launch_bonded_excl(Ctx& c, const float* pos, float* force, bool energy) {
+BondedParams make_bonded_params(const Ctx& c) {
   BondedParams bp;
   for (int d = 0; d < 3; ++d) {
     bp.L[d] = c.cg.L[d];
@@ -362,13 +347,23 @@ hipError_t launch_bonded_excl(Ctx& c, const float* pos, float* force, bool energ
   bp.alpha = c.alpha;
   bp.two_a_sqrtpi = 2.0 * c.alpha / sqrt(M_PI);
   bp.coulomb_k = c.coulomb_k;
+  return bp;
+}
+
+Topology make_topology(const Ctx& c) {
+  return Topology{c.q,      c.ex_start, c.ex_idx,  c.bonds,  c.bond_k,   c.bond_r0, c.bt_start,
+                  c.bt_idx, c.angles,   c.angle_k, c.angle_t0, c.at_start, c.at_idx};
+}
+
+hipError_t launch_bonded_excl(Ctx& c, const float* pos, float* force, bool energy) {
+  const BondedParams bp = make_bonded_params(c);
+  const Topology tp = make_topology(c);
   const int nb = (c.n + 255) / 256;
-#define MDX_BX(E, C)                                                                        \
-  k_bonded_excl<E, C><<<nb, 256, 0, c.stream>>>(                                           \
-      pos, c.n, bp, c.q, c.ex_start, c.ex_idx, c.bonds, c.bond_k, c.bond_r0, c.bt_start,   \
-      c.bt_idx, c.angles, c.angle_k, c.angle_t0, c.at_start, c.at_idx, force, c.partials, \
-      c.max_blocks)
-  bool C = c.has_coulomb;
+  hipStream_t s = c.stream;
+  const bool C = c.has_coulomb;
+#define MDX_BX(E, C)                                                                    \
+  k_bonded_excl<E, C><<<nb, 256, 0, s>>>(pos, c.n, bp, tp, c.inv_perm, c.fslot, c.max_slots, \
+                                         force, c.partials, c.max_blocks)
   if (energy) {
     if (C) MDX_BX(true, true);
     else MDX_BX(true, false);

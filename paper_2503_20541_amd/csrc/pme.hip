@@ -3,7 +3,7 @@
 //  k_pme_spread   one workgroup per grid brick; candidate atoms come from the
 //                 column sort: columns within spline reach + r_g/2 of the
 //                 brick, and in each the slots whose build z is in reach
-//                 (binary search, the column is sorted by build z).
+//                 (ranges found by binary search once per list build).
 //                 Lanes first compute one atom's B-spline weights each, then
 //                 the wave walks the atoms one by one with lanes = the 4x4x4
 //                 stencil points, adding into its own LDS copy of the brick
@@ -16,7 +16,7 @@
 //
 // The 1D transforms are radix-2/3/4/5/7 Stockham FFTs in LDS with a twiddle
 // table exp(-2 pi i k/N) computed on the host in double precision.
-#include "mdx_internal.h"
+#include "atom_terms.h"
 
 namespace mdx {
 
@@ -26,68 +26,23 @@ struct FftPlan {
   int radix[16];
 };
 
-struct PmeParams {
-  int K[3];
-  int Kxh;
-  int B[3];
-  int nb[3];
-  float s_hi[3], s_lo[3];   // K_d / L_d = s_hi + s_lo
-  float coulomb_k;
-  double exp_fac;           // pi^2 / alpha^2
-  double inv_piV;           // 1 / (pi V)
-};
-
-// Cubic B-spline weights M_4(f + t), t = 0..3, for fractional part f, and
-// their derivatives with respect to u (uniform cubic basis written out).
-__device__ __forceinline__ void spline4(float f, float th[4], float dth[4]) {
-  float g = 1.0f - f;
-  float f2 = f * f, f3 = f2 * f;
-  const float s = 1.0f / 6.0f;
-  th[0] = f3 * s;
-  th[1] = (1.0f + 3.0f * f + 3.0f * f2 - 3.0f * f3) * s;
-  th[2] = (4.0f - 6.0f * f2 + 3.0f * f3) * s;
-  th[3] = g * g * g * s;
-  dth[0] = 0.5f * f2;
-  dth[1] = 0.5f * (1.0f + 2.0f * f - 3.0f * f2);
-  dth[2] = 0.5f * (-4.0f * f + 3.0f * f2);
-  dth[3] = -0.5f * g * g;
-}
-
-// u = x K/L split into integer base k0 in [0, K) and fraction f in [0, 1),
-// with the scale carried as a float pair so f is accurate to ~1 ulp.
-__device__ __forceinline__ void grid_coord(float x, float s_hi, float s_lo, int K, int& k0,
-                                           float& f) {
-  float u = x * s_hi;
-  float kf = floorf(u);
-  f = fmaf(x, s_hi, -kf) + x * s_lo;
-  int k = (int)kf;
-  if (f < 0.f) { f += 1.0f; --k; }
-  if (f >= 1.0f) { f -= 1.0f; ++k; }
-  if (f < 0.f) f = 0.f;
-  k %= K;
-  if (k < 0) k += K;
-  k0 = k;
-}
-
 constexpr int kSpreadThreads = 256;
 constexpr int kSpreadWaves = kSpreadThreads / kWave;
-constexpr int kMaxBrick = 512;       // B_x * B_y * B_z
+constexpr int kMaxBrick = 8 * 66;    // B_z planes of B_x * B_y + 2 points (padded, see below)
 constexpr int kMaxCandCells = 512;
 constexpr int kStage = 16;           // floats staged per atom
 
-__device__ __forceinline__ int lower_bound_f(const float* __restrict__ a, int lo, int hi, float v) {
-  while (lo < hi) {
-    int mid = (lo + hi) >> 1;
-    if (a[mid] < v) lo = mid + 1; else hi = mid;
-  }
-  return lo;
+// The LDS brick copies store point (lx, ly, lz) at lx + B_x ly + (B_x B_y + 2) lz:
+// with the 4x4x4 stencil on the 64 lanes every bank is hit at most twice
+// per instruction (32 or 64 banks).
+__device__ __forceinline__ int brick_index(int lx, int ly, int lz, const PmeParams& pp) {
+  return (lz * pp.B[1] + ly) * pp.B[0] + 2 * lz + lx;
 }
 
 __global__ void __launch_bounds__(kSpreadThreads) k_pme_spread(
-    const float4* __restrict__ xs, const int* __restrict__ slot_start,
-    const int* __restrict__ col_count, const float* __restrict__ zb,
-    const int* __restrict__ brick_cols, const float* __restrict__ brick_z, PmeParams pp,
-    CellGrid cg, float* __restrict__ grid_q) {
+    const float4* __restrict__ xs, const int4* __restrict__ brick_zr,
+    const int* __restrict__ brick_cols, PmeParams pp, CellGrid cg,
+    float* __restrict__ grid_q) {
   __shared__ float lgrid[kSpreadWaves][kMaxBrick];
   __shared__ float stage[kSpreadWaves][kWave * kStage];
   __shared__ int cand_start[kMaxCandCells];
@@ -99,50 +54,43 @@ __global__ void __launch_bounds__(kSpreadThreads) k_pme_spread(
   const int g0[3] = {bx * pp.B[0], by * pp.B[1], bz * pp.B[2]};
   int beff[3];
   for (int d = 0; d < 3; ++d) beff[d] = min(pp.B[d], pp.K[d] - g0[d]);
-  // candidate columns (first, count along x and y) and the z reach
+  // candidate columns (first, count along x and y); the slot ranges inside
+  // each column that reach this brick layer come from the list build
   const int* bcx = brick_cols + 2 * bx;
   const int* bcy = brick_cols + 2 * pp.nb[0] + 2 * by;
-  const float zlo = brick_z[2 * bz], zhi = brick_z[2 * bz + 1];
-  const float Lz = cg.L[2];
   const int ncx = bcx[1], ncy = bcy[1];
   const int ncol = ncx * ncy;
   const int ncand = 2 * ncol;    // up to two z segments per column (periodic wrap)
+  const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
 
   for (int t = threadIdx.x; t < kSpreadWaves * kMaxBrick; t += blockDim.x)
     (&lgrid[0][0])[t] = 0.f;
+  const int4* zr = brick_zr + (size_t)bz * cg.ncell;
   for (int t = threadIdx.x; t < ncol; t += blockDim.x) {
     int cx = (bcx[0] + t % ncx) % cg.n[0], cy = (bcy[0] + t / ncx) % cg.n[1];
-    int col = cy * cg.n[0] + cx;
-    int sb = slot_start[col], se = sb + col_count[col];
-    float a0 = zlo, b0 = zhi, a1 = 0.f, b1 = 0.f;
-    if (zlo < 0.f) {
-      a0 = 0.f; b0 = zhi; a1 = zlo + Lz; b1 = Lz;
-    } else if (zhi > Lz) {
-      a0 = zlo; b0 = Lz; a1 = 0.f; b1 = zhi - Lz;
-    }
-    int s0 = lower_bound_f(zb, sb, se, a0), e0 = lower_bound_f(zb, sb, se, b0);
-    int s1 = sb, e1 = sb;
-    if (b1 > a1) {
-      s1 = lower_bound_f(zb, sb, se, a1);
-      e1 = lower_bound_f(zb, sb, se, b1);
-    }
-    cand_start[2 * t] = s0;
-    cand_off[2 * t + 1] = max(0, e0 - s0);
-    cand_start[2 * t + 1] = s1;
-    cand_off[2 * t + 2] = max(0, e1 - s1);
+    const int4 r = zr[cy * cg.n[0] + cx];
+    cand_start[2 * t] = r.x;
+    cand_off[2 * t + 1] = r.y;
+    cand_start[2 * t + 1] = r.z;
+    cand_off[2 * t + 2] = r.w;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int acc = 0;
-    cand_off[0] = 0;
-    for (int t = 0; t < ncand; ++t) {
-      acc += cand_off[t + 1];
-      cand_off[t + 1] = acc;
+  if (w == 0) {   // inclusive scan of the segment sizes by the first wave
+    int carry = 0;
+    for (int base = 0; base < ncand; base += kWave) {
+      const int i = base + lane;
+      int v = i < ncand ? cand_off[i + 1] : 0;
+      for (int o = 1; o < kWave; o <<= 1) {
+        const int u = __shfl_up(v, o, kWave);
+        if (lane >= o) v += u;
+      }
+      if (i < ncand) cand_off[i + 1] = carry + v;
+      carry += __shfl(v, kWave - 1, kWave);
     }
+    if (lane == 0) cand_off[0] = 0;
   }
   __syncthreads();
   const int total = cand_off[ncand];
-  const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   const int t1 = lane >> 4, t2 = (lane >> 2) & 3, t3 = lane & 3;   // x, y, z stencil offsets
   float* my_grid = lgrid[w];
   float* my_stage = stage[w];
@@ -194,7 +142,7 @@ __global__ void __launch_bounds__(kSpreadThreads) k_pme_spread(
       if (lz < 0) lz += pp.K[2];
       if (lx < beff[0] && ly < beff[1] && lz < beff[2]) {
         float v = st[15] * st[t1] * st[4 + t2] * st[8 + t3];
-        atomicAdd(&my_grid[(lz * pp.B[1] + ly) * pp.B[0] + lx], v);
+        atomicAdd(&my_grid[brick_index(lx, ly, lz, pp)], v);
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -205,7 +153,7 @@ __global__ void __launch_bounds__(kSpreadThreads) k_pme_spread(
   const int nloc = beff[0] * beff[1] * beff[2];
   for (int t = threadIdx.x; t < nloc; t += blockDim.x) {
     int lx = t % beff[0], ly = (t / beff[0]) % beff[1], lz = t / (beff[0] * beff[1]);
-    int li = (lz * pp.B[1] + ly) * pp.B[0] + lx;
+    int li = brick_index(lx, ly, lz, pp);
     float s = lgrid[0][li];
     for (int c = 1; c < kSpreadWaves; ++c) s += lgrid[c][li];
     grid_q[((size_t)(g0[2] + lz) * pp.K[1] + (g0[1] + ly)) * pp.K[0] + g0[0] + lx] = s;
@@ -534,40 +482,11 @@ __global__ void __launch_bounds__(256) k_pme_gather(const float4* __restrict__ x
   if (s >= meta[0]) return;
   const int a = perm[s];
   if (a < 0) return;
-  float4 p = xs[s];
-  float xyz[3] = {p.x, p.y, p.z};
-  int k0[3];
-  float th[3][4], dth[3][4];
-  for (int d = 0; d < 3; ++d) {
-    float fr;
-    grid_coord(xyz[d], pp.s_hi[d], pp.s_lo[d], pp.K[d], k0[d], fr);
-    spline4(fr, th[d], dth[d]);
-  }
-  float gx = 0.f, gy = 0.f, gz = 0.f;
-  for (int t3 = 0; t3 < 4; ++t3) {
-    int z = k0[2] - t3;
-    z += z < 0 ? pp.K[2] : 0;
-    for (int t2 = 0; t2 < 4; ++t2) {
-      int y = k0[1] - t2;
-      y += y < 0 ? pp.K[1] : 0;
-      const float* rowp = phi + ((size_t)z * pp.K[1] + y) * pp.K[0];
-      float ayz = th[1][t2] * th[2][t3];
-      float dyz = dth[1][t2] * th[2][t3];
-      float ydz = th[1][t2] * dth[2][t3];
-      for (int t1 = 0; t1 < 4; ++t1) {
-        int x = k0[0] - t1;
-        x += x < 0 ? pp.K[0] : 0;
-        float v = rowp[x];
-        gx += dth[0][t1] * ayz * v;
-        gy += th[0][t1] * dyz * v;
-        gz += th[0][t1] * ydz * v;
-      }
-    }
-  }
-  float c = -pp.coulomb_k * p.w;
-  force[a] += c * gx * (pp.s_hi[0] + pp.s_lo[0]);
-  force[n + a] += c * gy * (pp.s_hi[1] + pp.s_lo[1]);
-  force[2 * n + a] += c * gz * (pp.s_hi[2] + pp.s_lo[2]);
+  float fx = 0.f, fy = 0.f, fz = 0.f;
+  pme_gather_atom(xs[s], phi, pp, fx, fy, fz);
+  force[a] += fx;
+  force[n + a] += fy;
+  force[2 * n + a] += fz;
 }
 
 // ---------------------------------------------------------------------------
@@ -639,8 +558,7 @@ static void cols(int N, int blocks, size_t sh, hipStream_t s, Ctx& c, const PmeP
   }
 }
 
-hipError_t launch_pme(Ctx& c, float* force, bool energy) {
-  (void)energy;   // the z pass always writes its energy partials
+PmeParams make_pme_params(const Ctx& c) {
   const PmeGrid& g = c.pg;
   PmeParams pp;
   for (int d = 0; d < 3; ++d) {
@@ -654,9 +572,16 @@ hipError_t launch_pme(Ctx& c, float* force, bool energy) {
   pp.coulomb_k = (float)c.coulomb_k;
   pp.exp_fac = M_PI * M_PI / (c.alpha * c.alpha);
   pp.inv_piV = c.pme_energy_scale;
-  hipStream_t s = c.stream;
-  k_pme_spread<<<g.nbrick, kSpreadThreads, 0, s>>>(c.xs, c.slot_start, c.cell_count, c.zb,
-                                                   c.brick_cols, c.brick_z, pp, c.cg, c.grid_q);
+  return pp;
+}
+
+// Spread and the five FFT passes (forward transform, influence multiply with
+// the energy partials, inverse) on stream s: leaves the potential in grid_phi.
+hipError_t launch_pme_potential(Ctx& c, hipStream_t s) {
+  const PmeGrid& g = c.pg;
+  const PmeParams pp = make_pme_params(c);
+  k_pme_spread<<<g.nbrick, kSpreadThreads, 0, s>>>(c.xs, c.brick_zr, c.brick_cols, pp, c.cg,
+                                                   c.grid_q);
   FftPlan px = make_plan(g.K[0]), py = make_plan(g.K[1]), pz = make_plan(g.K[2]);
   const int rows = g.K[1] * g.K[2];
   const int P = pencils_for(g.K[0]);
@@ -672,8 +597,16 @@ hipError_t launch_pme(Ctx& c, float* force, bool energy) {
   c.pme_blocks = g.K[1] * ntile;
   cols<1>(g.K[1], g.K[2] * ntile, shy, s, c, pp, Pc, py, c.tw[1]);
   rows_c2r(g.K[0], rblocks, sh, s, c.grid_c, c.grid_phi, rows, P, g.Kxh, px, c.tw[0]);
-  k_pme_gather<<<(c.max_slots + 255) / 256, 256, 0, s>>>(c.xs, c.perm, c.meta, c.grid_phi, c.n,
-                                                          pp, force);
+  return hipGetLastError();
+}
+
+hipError_t launch_pme(Ctx& c, float* force, bool energy) {
+  (void)energy;   // the z pass always writes its energy partials
+  hipError_t e = launch_pme_potential(c, c.stream);
+  if (e != hipSuccess) return e;
+  const PmeParams pp = make_pme_params(c);
+  k_pme_gather<<<(c.max_slots + 255) / 256, 256, 0, c.stream>>>(c.xs, c.perm, c.meta, c.grid_phi,
+                                                                c.n, pp, force);
   return hipGetLastError();
 }
 

@@ -21,6 +21,10 @@ struct mdx_ctx {
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];
   size_t used[3] = {0, 0, 0};
+  // second stream for the PME potential inside mdx_integrate_step, forked
+  // from and joined back into the context's stream every step
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace {
@@ -81,11 +85,14 @@ double m4_at(int k) { return k == 2 ? 2.0 / 3.0 : (k == 1 || k == 3 ? 1.0 / 6.0 
 
 // Tiles per i-cluster: clusters whose boxes lie within r_list of a box of
 // edge ~a, with headroom.
-int default_capacity(int n, const float box[3], float r_list, double a, int max_clusters) {
+int default_capacity(int n, const float box[3], float r_list, double a, int max_clusters,
+                     bool full_list) {
   double V = (double)box[0] * box[1] * box[2];
   double rho = n / V;
   double r = (double)r_list + a;
-  double expect = rho * 4.0 / 3.0 * M_PI * r * r * r / mdx::kClusterSize;
+  // clusters whose boxes reach within r_list; a half list holds each pair once
+  double expect = (full_list ? 1.0 : 0.5) * rho * 4.0 / 3.0 * M_PI * r * r * r /
+                  mdx::kClusterSize;
   int cap = (int)std::ceil(1.5 * expect + 16.0);
   cap = (cap + 15) / 16 * 16;
   return std::max(16, std::min(cap, (max_clusters + 15) / 16 * 16));
@@ -157,6 +164,7 @@ int setup_pme(mdx_ctx* x, const mdx_system_desc* d) {
   int rc = dev_upload(x, &c.brick_cols, bc);
   if (rc != MDX_OK) return rc;
   if ((rc = dev_upload(x, &c.brick_z, bz)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.brick_zr, (size_t)g.nb[2] * c.cg.ncell)) != MDX_OK) return rc;
 
   for (int k = 0; k < 3; ++k) {
     const int K = g.K[k];
@@ -204,6 +212,7 @@ int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
     if (d->atom_type[i] < 0 || d->atom_type[i] >= d->n_types) return MDX_E_INVALID;
     if (!(d->mass[i] > 0.f)) return MDX_E_INVALID;
   }
+  if (d->options & ~MDX_OPT_HALF_LIST) return MDX_E_INVALID;
   const int cdiv = d->cell_divisions == 0 ? 2 : d->cell_divisions;
   if (cdiv < 1 || cdiv > 4) return MDX_E_INVALID;
   if (d->switch_r > 0.f && !(d->switch_r < d->r_cut)) return MDX_E_INVALID;
@@ -219,6 +228,7 @@ int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
   c.accel = d->accel > 0 ? d->accel : 1.0;
   c.boltzmann = d->boltzmann;
   c.cell_div = cdiv;
+  c.half_list = (d->options & MDX_OPT_HALF_LIST) != 0;
   c.rebuild_every = d->rebuild_every > 0 ? d->rebuild_every : 10;
   for (int k = 0; k < 3; ++k)
     if ((double)c.r_list > 0.5 * (double)c.box[k]) return MDX_E_BOX_TOO_SMALL;
@@ -371,15 +381,18 @@ int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
   const int ncol = g.ncell;
   if ((rc = dev_alloc(x, &c.cell_of, n)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.cell_count, ncol)) != MDX_OK) return rc;
+  MDX_TRY(hipMemset(c.cell_count, 0, sizeof(int) * ncol));
   if ((rc = dev_alloc(x, &c.cell_start, ncol + 1)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.cell_cursor, ncol)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.slot_start, ncol + 1)) != MDX_OK) return rc;
-  if ((rc = dev_alloc(x, &c.meta, 2)) != MDX_OK) return rc;
-  MDX_TRY(hipMemset(c.meta, 0, 2 * sizeof(int)));
+  if ((rc = dev_alloc(x, &c.meta, 3)) != MDX_OK) return rc;
+  MDX_TRY(hipMemset(c.meta, 0, 3 * sizeof(int)));
   if ((rc = dev_alloc(x, &c.perm_unsorted, n)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.perm, c.max_slots)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.inv_perm, n)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.xs, c.max_slots)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.fslot, (size_t)3 * c.max_slots)) != MDX_OK) return rc;
+  MDX_TRY(hipMemset(c.fslot, 0, sizeof(float) * 3 * c.max_slots));
   if ((rc = dev_alloc(x, &c.ts, c.max_slots)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.zb, c.max_slots)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.box_lo, c.max_clusters)) != MDX_OK) return rc;
@@ -389,10 +402,11 @@ int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
   if ((rc = dev_alloc(x, &c.nl_needed, 1)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.flags, 1)) != MDX_OK) return rc;
   MDX_TRY(hipMemset(c.flags, 0, sizeof(unsigned)));
-  if ((rc = dev_alloc(x, &c.gate, 1)) != MDX_OK) return rc;
-  MDX_TRY(hipMemset(c.gate, 0, sizeof(int)));
+  if ((rc = dev_alloc(x, &c.gate, 2)) != MDX_OK) return rc;
+  MDX_TRY(hipMemset(c.gate, 0, 2 * sizeof(int)));
   int cap = d->nl_capacity > 0 ? d->nl_capacity
-                               : default_capacity(n, c.box, c.r_list, a_clu, c.max_clusters);
+                               : default_capacity(n, c.box, c.r_list, a_clu, c.max_clusters,
+                                                   !c.half_list);
   if ((rc = alloc_list(x, cap)) != MDX_OK) return rc;
 
   if (c.has_pme) {
@@ -418,7 +432,7 @@ constexpr size_t kMaxTimed = 8192;
 
 // Records an event pair around the launches made by `fn` when timing is on.
 template <typename F>
-hipError_t timed(mdx_ctx* x, int group, F&& fn) {
+hipError_t timed(mdx_ctx* x, int group, hipStream_t stream, F&& fn) {
   if (!x->timing || x->used[group] >= kMaxTimed) return fn();
   auto& v = x->ev[group];
   if (x->used[group] == v.size()) {
@@ -429,10 +443,10 @@ hipError_t timed(mdx_ctx* x, int group, F&& fn) {
     v.push_back({a, b});
   }
   auto& p = v[x->used[group]++];
-  hipError_t e = hipEventRecord(p.first, x->c.stream);
+  hipError_t e = hipEventRecord(p.first, stream);
   if (e != hipSuccess) return e;
   if ((e = fn()) != hipSuccess) return e;
-  return hipEventRecord(p.second, x->c.stream);
+  return hipEventRecord(p.second, stream);
 }
 
 }  // namespace
@@ -465,6 +479,12 @@ int mdx_create(mdx_ctx** out, const mdx_system_desc* d, void* hip_stream) {
     return MDX_E_HIP;
   }
   x->c.stream = static_cast<hipStream_t>(hip_stream);
+  if (hipStreamCreateWithFlags(&x->aux, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&x->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&x->ev_join, hipEventDisableTiming) != hipSuccess) {
+    mdx_destroy(x);
+    return MDX_E_HIP;
+  }
   int rc = create_impl(x, d);
   if (rc != MDX_OK) {
     mdx_destroy(x);
@@ -477,6 +497,12 @@ int mdx_create(mdx_ctx** out, const mdx_system_desc* d, void* hip_stream) {
 int mdx_destroy(mdx_ctx* x) {
   if (!x) return MDX_OK;
   (void)hipStreamSynchronize(x->c.stream);
+  if (x->aux) {
+    (void)hipStreamSynchronize(x->aux);
+    (void)hipStreamDestroy(x->aux);
+  }
+  if (x->ev_fork) (void)hipEventDestroy(x->ev_fork);
+  if (x->ev_join) (void)hipEventDestroy(x->ev_join);
   for (auto& v : x->ev)
     for (auto& p : v) {
       (void)hipEventDestroy(p.first);
@@ -497,7 +523,7 @@ int mdx_build_neighbors(mdx_ctx* x, const float* pos) {
   if (check_ctx(x) || !pos) return MDX_E_INVALID;
   Ctx& c = x->c;
   for (int attempt = 0; attempt < 3; ++attempt) {
-    MDX_TRY(timed(x, MDX_TIMING_BUILD, [&] { return mdx::launch_build_list(c, pos); }));
+    MDX_TRY(timed(x, MDX_TIMING_BUILD, c.stream, [&] { return mdx::launch_build_list(c, pos); }));
     int needed = 0;
     MDX_TRY(hipMemcpyAsync(&needed, c.nl_needed, sizeof(int), hipMemcpyDeviceToHost, c.stream));
     MDX_TRY(hipStreamSynchronize(c.stream));
@@ -517,21 +543,50 @@ int mdx_build_neighbors(mdx_ctx* x, const float* pos) {
   return MDX_E_HIP;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Host copy of the last built list: slot permutation, tiles per cluster and
+// the tiles themselves (synchronising).
+struct HostList {
+  int nslot = 0, nclu = 0, builds = 0;
+  std::vector<int> perm, cnt;
+  std::vector<uint2> tl;
+};
+
+int read_list(Ctx& c, HostList& h) {
+  MDX_TRY(hipStreamSynchronize(c.stream));
+  int meta[3];
+  MDX_TRY(hipMemcpy(meta, c.meta, sizeof(meta), hipMemcpyDeviceToHost));
+  h.nslot = meta[0];
+  h.nclu = meta[1];
+  h.builds = meta[2];
+  h.perm.assign(h.nslot, 0);
+  h.cnt.assign(h.nclu, 0);
+  h.tl.assign((size_t)h.nclu * c.nl_cap, uint2{0u, 0u});
+  if (h.nslot > 0) {
+    MDX_TRY(hipMemcpy(h.perm.data(), c.perm, sizeof(int) * h.nslot, hipMemcpyDeviceToHost));
+    MDX_TRY(hipMemcpy(h.cnt.data(), c.tile_count, sizeof(int) * h.nclu, hipMemcpyDeviceToHost));
+    MDX_TRY(hipMemcpy(h.tl.data(), c.tiles, sizeof(uint2) * h.tl.size(), hipMemcpyDeviceToHost));
+  }
+  return MDX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int mdx_get_neighbor_pairs(mdx_ctx* x, int32_t* pairs_host, int64_t cap, int64_t* n_out) {
   if (check_ctx(x) || !n_out || cap < 0 || (cap > 0 && !pairs_host)) return MDX_E_INVALID;
   Ctx& c = x->c;
   if (c.steps_since_build < 0) return MDX_E_NO_LIST;
-  MDX_TRY(hipStreamSynchronize(c.stream));
-  int meta[2];
-  MDX_TRY(hipMemcpy(meta, c.meta, sizeof(meta), hipMemcpyDeviceToHost));
-  const int nslot = meta[0], nclu = meta[1];
-  std::vector<int> perm(nslot), cnt(nclu);
-  std::vector<uint2> tl((size_t)nclu * c.nl_cap);
-  if (nslot > 0) {
-    MDX_TRY(hipMemcpy(perm.data(), c.perm, sizeof(int) * nslot, hipMemcpyDeviceToHost));
-    MDX_TRY(hipMemcpy(cnt.data(), c.tile_count, sizeof(int) * nclu, hipMemcpyDeviceToHost));
-    MDX_TRY(hipMemcpy(tl.data(), c.tiles, sizeof(uint2) * tl.size(), hipMemcpyDeviceToHost));
-  }
+  HostList h;
+  if (int rc = read_list(c, h)) return rc;
+  const int nclu = h.nclu;
+  const std::vector<int>& perm = h.perm;
+  const std::vector<int>& cnt = h.cnt;
+  const std::vector<uint2>& tl = h.tl;
   std::vector<std::pair<int, int>> pairs;
   for (int ic = 0; ic < nclu; ++ic)
     for (int k = 0; k < cnt[ic]; ++k) {
@@ -540,7 +595,8 @@ int mdx_get_neighbor_pairs(mdx_ctx* x, int32_t* pairs_host, int64_t cap, int64_t
         if (!((e.y >> bit) & 1u)) continue;
         int a = perm[ic * mdx::kClusterSize + bit / 4];
         int b = perm[(int)e.x * mdx::kClusterSize + bit % 4];
-        if (a < b) pairs.push_back({a, b});
+        // a full list holds both directions; a half list each pair once
+        if (c.half_list || a < b) pairs.push_back({std::min(a, b), std::max(a, b)});
       }
     }
   std::sort(pairs.begin(), pairs.end());
@@ -561,7 +617,7 @@ int mdx_compute_nonbonded(mdx_ctx* x, const float* pos, float* force, double* en
   if (c.steps_since_build < 0) return MDX_E_NO_LIST;
   const bool e = energy != nullptr;
   MDX_TRY(mdx::launch_refresh_sorted(c, pos));
-  MDX_TRY(timed(x, MDX_TIMING_PAIR, [&] { return mdx::launch_nonbonded(c, force, e); }));
+  MDX_TRY(timed(x, MDX_TIMING_PAIR, c.stream, [&] { return mdx::launch_nonbonded(c, e); }));
   MDX_TRY(mdx::launch_bonded_excl(c, pos, force, e));
   if (e) {
     const int nb = (c.n + 255) / 256;
@@ -580,7 +636,8 @@ int mdx_compute_pme(mdx_ctx* x, const float* pos, float* force, double* energy, 
   if (!c.has_pme) return MDX_E_NO_PME;
   if (c.steps_since_build < 0) return MDX_E_NO_LIST;
   MDX_TRY(mdx::launch_refresh_sorted(c, pos));
-  MDX_TRY(timed(x, MDX_TIMING_PME, [&] { return mdx::launch_pme(c, force, energy != nullptr); }));
+  MDX_TRY(timed(x, MDX_TIMING_PME, c.stream,
+                [&] { return mdx::launch_pme(c, force, energy != nullptr); }));
   if (energy) {
     int rows[1] = {mdx::kRowRec};
     int nblk[1] = {c.pme_blocks};
@@ -597,32 +654,38 @@ int mdx_integrate_step(mdx_ctx* x, float* pos, float* vel, float* force, int32_t
     MDX_TRY(mdx::launch_build_list(c, pos));
     c.steps_since_build = 0;
   }
-  const int nb = (c.n + 255) / 256;
   for (int s = 0; s < n_steps; ++s) {
     const bool e = energies != nullptr;
     // The list is rebuilt on the cadence, and in between whenever an atom
-    // has moved more than r_g/2 since the last build (decided on the device:
-    // the refresh kernel raises the gate, the build kernels run only if it
-    // is raised).
-    MDX_TRY(mdx::launch_kick_drift(c, pos, vel, force, dt, c.gate));
+    // has moved more than r_g/2 since the last build: the opening kernel
+    // raises this step's gate, the build kernels run only if it is raised.
+    // Two gates alternate with the step parity, so the kernel that clears
+    // the next step's gate never touches the one being raised.
+    int* gate_now = c.gate + (c.steps_taken & 1);
+    int* gate_next = c.gate + ((c.steps_taken + 1) & 1);
     const bool cadence = ++c.steps_since_build >= c.rebuild_every;
     if (cadence) c.steps_since_build = 0;
-    MDX_TRY(mdx::launch_refresh_sorted(c, pos, c.gate, cadence));
-    MDX_TRY(timed(x, MDX_TIMING_BUILD, [&] { return mdx::launch_build_list(c, pos, c.gate); }));
-    MDX_TRY(timed(x, MDX_TIMING_PAIR, [&] { return mdx::launch_nonbonded(c, force, e); }));
-    MDX_TRY(mdx::launch_bonded_excl(c, pos, force, e));
-    if (c.has_pme)
-      MDX_TRY(timed(x, MDX_TIMING_PME, [&] { return mdx::launch_pme(c, force, e); }));
-    MDX_TRY(mdx::launch_kick(c, vel, force, dt, e));
+    MDX_TRY(mdx::launch_begin_step(c, pos, vel, force, dt, gate_now, gate_next, cadence));
+    MDX_TRY(timed(x, MDX_TIMING_BUILD, c.stream, [&] { return mdx::launch_build_list(c, pos, gate_now); }));
+    // The reciprocal-space potential only needs this step's slot positions:
+    // it runs on the second stream, concurrently with the pair kernel, and
+    // the closing kernel (force interpolation) waits for it.
+    if (c.has_pme) {
+      MDX_TRY(hipEventRecord(x->ev_fork, c.stream));
+      MDX_TRY(hipStreamWaitEvent(x->aux, x->ev_fork, 0));
+      MDX_TRY(timed(x, MDX_TIMING_PME, x->aux,
+                    [&] { return mdx::launch_pme_potential(c, x->aux); }));
+      MDX_TRY(hipEventRecord(x->ev_join, x->aux));
+    }
+    MDX_TRY(timed(x, MDX_TIMING_PAIR, c.stream, [&] { return mdx::launch_nonbonded(c, e); }));
+    if (c.has_pme) MDX_TRY(hipStreamWaitEvent(c.stream, x->ev_join, 0));
+    MDX_TRY(mdx::launch_finish_step(c, pos, vel, force, dt, e));
     if (e) {
-      int rows[7] = {mdx::kRowLJ,   mdx::kRowDir,   mdx::kRowExcl, mdx::kRowBond,
-                     mdx::kRowAngle, mdx::kRowRec, mdx::kRowKin};
-      int nblk[7] = {c.nb_blocks, c.nb_blocks, nb, nb, nb, c.pme_blocks, nb};
-      int nrows = c.has_pme ? 7 : 6;
-      if (!c.has_pme) {
-        rows[5] = mdx::kRowKin;
-        nblk[5] = nb;
-      }
+      int rows[7] = {mdx::kRowLJ,    mdx::kRowDir, mdx::kRowExcl, mdx::kRowBond,
+                     mdx::kRowAngle, mdx::kRowKin, mdx::kRowRec};
+      int nblk[7] = {c.nb_blocks,      c.nb_blocks,      c.finish_blocks, c.finish_blocks,
+                     c.finish_blocks,  c.finish_blocks,  c.pme_blocks};
+      const int nrows = c.has_pme ? 7 : 6;
       double* out = energies + (size_t)s * MDX_N_ENERGY;
       MDX_TRY(mdx::launch_reduce_energy(c, rows, nblk, nrows, out, 0, c.e_self,
                                         MDX_ENERGY_COUL_SELF,
@@ -661,6 +724,21 @@ int mdx_get_info(mdx_ctx* x, mdx_info* info) {
   info->r_list = (double)c.r_list;
   info->n_list_entries = -1;
   info->steps_taken = c.steps_taken;
+  info->n_builds = 0;
+  info->n_list_tiles = -1;
+  if (c.steps_since_build >= 0) {
+    HostList h;
+    if (int rc = read_list(c, h)) return rc;
+    int64_t entries = 0, tiles = 0;
+    for (int ic = 0; ic < h.nclu; ++ic) {
+      tiles += h.cnt[ic];
+      for (int k = 0; k < h.cnt[ic]; ++k)
+        entries += __builtin_popcount(h.tl[(size_t)ic * c.nl_cap + k].y);
+    }
+    info->n_list_entries = entries;
+    info->n_list_tiles = tiles;
+    info->n_builds = h.builds;
+  }
   return MDX_OK;
 }
 

@@ -49,6 +49,8 @@ MDX_ENERGY_COUL_REC = 6
 MDX_ENERGY_KINETIC = 7
 MDX_N_ENERGY = 8
 
+MDX_OPT_HALF_LIST = 0x1
+
 MDX_TIMING_PAIR = 0
 MDX_TIMING_PME = 1
 MDX_TIMING_BUILD = 2
@@ -77,7 +79,7 @@ class SystemDesc(ctypes.Structure):
         ("coulomb_k", ctypes.c_double), ("accel", ctypes.c_double),
         ("boltzmann", ctypes.c_double),
         ("cell_divisions", ctypes.c_int32), ("nl_capacity", ctypes.c_int32),
-        ("rebuild_every", ctypes.c_int32), ("reserved", ctypes.c_uint32),
+        ("rebuild_every", ctypes.c_int32), ("options", ctypes.c_uint32),
     ]
 
 
@@ -88,6 +90,7 @@ class Info(ctypes.Structure):
         ("pme_grid", ctypes.c_int32 * 3), ("pme_brick", ctypes.c_int32 * 3),
         ("alpha", ctypes.c_double), ("r_list", ctypes.c_double),
         ("n_list_entries", ctypes.c_int64), ("steps_taken", ctypes.c_int64),
+        ("n_builds", ctypes.c_int64), ("n_list_tiles", ctypes.c_int64),
     ]
 
 
@@ -145,7 +148,7 @@ def make_desc(n_atoms, box, charge, mass, atom_type, type_sigma, type_epsilon,
               angle_k=None, angle_theta0=None, r_cut=1.0, r_ghost=0.0, switch_r=0.0,
               ewald_delta=0.0, ewald_alpha=0.0, pme_grid=(0, 0, 0), pme_order=4,
               coulomb_k=1.0, accel=1.0, boltzmann=1.0, cell_divisions=0, nl_capacity=0,
-              rebuild_every=10):
+              rebuild_every=10, options=0):
     """Fills an mdx_system_desc from host arrays. Returns (desc, keepalive)."""
     keep = []
 
@@ -198,6 +201,7 @@ def make_desc(n_atoms, box, charge, mass, atom_type, type_sigma, type_epsilon,
     d.cell_divisions = int(cell_divisions)
     d.nl_capacity = int(nl_capacity)
     d.rebuild_every = int(rebuild_every)
+    d.options = int(options)
     return d, keep
 
 

@@ -43,14 +43,27 @@ def test_struct_layout_matches_header(tmp_path):
         '#include <stdio.h>\n#include <stddef.h>\n#include "mdx.h"\n'
         "int main(void){printf(\"%zu %zu %zu %zu %zu\\n\", sizeof(mdx_system_desc),"
         " sizeof(mdx_info), offsetof(mdx_system_desc, ewald_delta),"
-        " offsetof(mdx_system_desc, pme_grid), offsetof(mdx_info, alpha)); return 0;}\n")
+        " offsetof(mdx_system_desc, pme_grid), offsetof(mdx_info, alpha));"
+        " printf(\"%zu %zu\\n\", offsetof(mdx_system_desc, options),"
+        " offsetof(mdx_info, n_list_tiles)); return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
                    check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
     got = [ctypes.sizeof(mdx.SystemDesc), ctypes.sizeof(mdx.Info), mdx.SystemDesc.ewald_delta.offset,
-           mdx.SystemDesc.pme_grid.offset, mdx.Info.alpha.offset]
+           mdx.SystemDesc.pme_grid.offset, mdx.Info.alpha.offset,
+           mdx.SystemDesc.options.offset, mdx.Info.n_list_tiles.offset]
     assert [int(v) for v in out] == got
+
+
+def test_binding_constants_match_header():
+    import paper_2503_20541_amd as mdx
+    text = open(HEADER).read()
+    defs = re.findall(r"^#define\s+(MDX_\w+)\s+\(?(-?(?:0x[0-9a-fA-F]+|\d+))u?\)?", text, re.M)
+    assert len(defs) >= 20
+    for name, val in defs:
+        assert hasattr(mdx, name), name
+        assert getattr(mdx, name) == int(val, 0), name
 
 
 def test_desc_marshalling_roundtrip():

@@ -26,11 +26,15 @@ def _nonbonded_gpu(s, **kw):
         return t["force"].cpu().numpy(), t["e_nb"].cpu().numpy(), flags
 
 
+HALF_LIST = 0x1   # MDX_OPT_HALF_LIST: each pair once, float atomics
+
+
+@pytest.mark.parametrize("options", [0, HALF_LIST], ids=["full", "half"])
 @pytest.mark.parametrize("name", ["lj1k", "water375", "water9k"])
-def test_nonbonded_parity(name):
+def test_nonbonded_parity(name, options):
     s = synth.config_system(name)
-    announce(f"nonbonded {name}")
-    F, E, flags = _nonbonded_gpu(s)
+    announce(f"nonbonded {name} options={options}")
+    F, E, flags = _nonbonded_gpu(s, options=options)
     assert flags == 0
     ref = forcefield.nonbonded_terms(s)
     assert rel_rms(F, ref["F"]) < F_TOL
@@ -52,6 +56,8 @@ def test_nonbonded_switched_random():
 
 
 def test_nonbonded_bitwise_deterministic():
+    # the default full list uses no float atomics: forces and energies
+    # repeat bit for bit
     import torch
     s = synth.config_system("water9k")
     announce("nonbonded determinism")
@@ -67,6 +73,21 @@ def test_nonbonded_bitwise_deterministic():
                          t["e_rec"].cpu().numpy().copy()))
     for a, b in zip(outs[0], outs[1]):
         assert np.array_equal(a, b)
+
+
+def test_half_list_matches_full_list_and_repeats_energies():
+    # the half list (float atomics) agrees with the full list to float32
+    # rounding, and its FP64 energies (no atomics) repeat bit for bit
+    s = synth.config_system("water9k")
+    announce("half vs full list")
+    F_full, E_full, _ = _nonbonded_gpu(s)
+    F1, E1, f1 = _nonbonded_gpu(s, options=HALF_LIST)
+    F2, E2, f2 = _nonbonded_gpu(s, options=HALF_LIST)
+    assert f1 == 0 and f2 == 0
+    assert rel_rms(F1, F_full) < 1e-6
+    assert rel_rms(F2, F1) < 1e-6
+    assert np.array_equal(E1, E2)
+    assert np.allclose(E1, E_full, rtol=1e-12, atol=1e-9)
 
 
 @pytest.mark.parametrize("name", ["water375", "water9k"])

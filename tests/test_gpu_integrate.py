@@ -74,8 +74,11 @@ def test_water9k_energy_conservation_and_no_stale():
         torch.cuda.synchronize()
         E = en.cpu().numpy()
         assert mdx.get_status(ctx) == 0
+        builds = mdx.get_info(ctx).n_builds
         x = t["pos"].cpu().numpy()
     assert np.all((x >= 0) & (x < s.box[:, None]))
+    # the explicit build, then one every rebuild_every steps at least
+    assert builds >= 1 + n_steps // s.rebuild_every
     etot = E.sum(axis=1)
     ke = E[:, 7]
     assert np.abs(etot - etot[0]).max() < 0.02 * ke.mean()

@@ -13,17 +13,25 @@ def _oracle_pairs(s):
     return neighbors.tree_pairs(s.pos, s.box, s.r_cut, s.r_ghost, s.exclusions)
 
 
+@pytest.mark.parametrize("options", [0, 1], ids=["full", "half"])
 @pytest.mark.parametrize("name", ["lj1k", "water375", "water9k"])
-def test_list_exact(name):
+def test_list_exact(name, options):
     s = synth.config_system(name)
-    announce(f"list {name} N={s.n_atoms}")
-    with gpu_context(s) as (mdx, ctx, t):
+    announce(f"list {name} N={s.n_atoms} options={options}")
+    with gpu_context(s, options=options) as (mdx, ctx, t):
+        assert mdx.get_info(ctx).n_list_entries == -1
         mdx.build_neighbors(ctx, t["pos"])
         got = mdx.get_neighbor_pairs(ctx)
         assert mdx.get_status(ctx) == 0
+        info = mdx.get_info(ctx)
     ref = _oracle_pairs(s)
     assert got.shape == ref.shape
     assert np.array_equal(got, ref)
+    # every pair is held from both ends (full list, the default) or once
+    # (MDX_OPT_HALF_LIST); tiles come in groups of four
+    assert info.n_list_entries == (1 if options else 2) * len(ref)
+    assert info.n_builds == 1
+    assert info.n_list_tiles % 4 == 0 and 16 * info.n_list_tiles >= info.n_list_entries
 
 
 @pytest.mark.parametrize("m", [1, 2, 3])
