@@ -161,7 +161,9 @@ def main():
         flags0 = mdx.get_status(ctx)
         t_start = temperature(s, vel)
         builds0 = mdx.get_info(ctx).n_builds
-        mdx.set_timing(ctx, True)
+        # only the pair kernel is bracketed by events inside the timed region
+        # (every event record adds a small gap between kernels)
+        mdx.set_timing(ctx, 1 << mdx.MDX_TIMING_PAIR)
         start = torch.cuda.Event(enable_timing=True)
         stop = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
@@ -171,12 +173,16 @@ def main():
         torch.cuda.synchronize()
         ms_total = start.elapsed_time(stop)
         pair_ms, pair_n = mdx.get_timing(ctx, mdx.MDX_TIMING_PAIR)
-        pme_ms, pme_n = mdx.get_timing(ctx, mdx.MDX_TIMING_PME)
-        build_ms, build_n = mdx.get_timing(ctx, mdx.MDX_TIMING_BUILD)
         mdx.set_timing(ctx, False)
         info = mdx.get_info(ctx)
         builds = info.n_builds - builds0
         t_end = temperature(s, vel)
+        # diagnostic only, after the timed region: PME chain and build times
+        mdx.set_timing(ctx, (1 << mdx.MDX_TIMING_PME) | (1 << mdx.MDX_TIMING_BUILD))
+        mdx.integrate_step(ctx, pos, vel, force, min(args.steps, 100), s.dt)
+        pme_ms, pme_n = mdx.get_timing(ctx, mdx.MDX_TIMING_PME)
+        build_ms, build_n = mdx.get_timing(ctx, mdx.MDX_TIMING_BUILD)
+        mdx.set_timing(ctx, False)
         flags = mdx.get_status(ctx) | flags0
         ok = bool(torch.isfinite(pos).all() and torch.isfinite(vel).all())
         mdx.destroy(ctx)
@@ -194,7 +200,7 @@ def main():
             "equilibration_steps": args.equilibrate,
             "list_builds": builds, "temperature_K": [round(t_start, 1), round(t_end, 1)],
             "list_tiles": info.n_list_tiles, "list_entries": info.n_list_entries,
-            "kernel_ms": {"pair": round(pair_ms, 5), "pme": round(pme_ms, 5),
+            "kernel_ms": {"pair": round(pair_ms, 5), "pme_chain_overlapped": round(pme_ms, 5),
                           "build_gated": round(build_ms, 5)},
             "roofline": {"bound": "alu", "achieved": round(achieved, 3),
                          "peak": round(VALU_PEAK_T, 2), "unit": "TFLOP/s",

@@ -104,9 +104,14 @@ typedef struct mdx_ctx mdx_ctx;
  * applies its force to both atoms (Newton's third law) with float atomics
  * into a per-atom accumulator: half the pair arithmetic and list memory,
  * forces that can differ in the last bits from run to run. Energies are
- * reproducible in both modes.
+ * reproducible in both modes. The list is built with one launch per build
+ * phase; MDX_OPT_COOPERATIVE_BUILD runs all phases in one cooperative launch
+ * with grid-wide barriers between them (one launch when no rebuild is due,
+ * but the launch goes through its own hardware queue, and on a real rebuild
+ * the resident grid is smaller). Both give the same list.
  */
-#define MDX_OPT_HALF_LIST 1u
+#define MDX_OPT_HALF_LIST         1u
+#define MDX_OPT_COOPERATIVE_BUILD 2u
 typedef struct mdx_system_desc {
   int32_t n_atoms;
   float box[3];
@@ -253,18 +258,22 @@ int mdx_get_status(mdx_ctx* ctx, uint32_t* flags);
 int mdx_get_info(mdx_ctx* ctx, mdx_info* info);
 
 /* ---- diagnostics ---------------------------------------------------------
- * Kernel timing with HIP events recorded on the context's stream around the
- * launches of one kernel group. Groups: MDX_TIMING_PAIR (the short-range
- * pair kernel), MDX_TIMING_PME (spread .. gather in mdx_compute_pme; spread
- * .. last FFT pass, on the second stream, in mdx_integrate_step, where it
- * overlaps the pair kernel), MDX_TIMING_BUILD (list build). mdx_set_timing(ctx, 1) clears earlier records and starts
- * recording (at most 8192 launches per group; later launches are not
- * recorded); 0 stops. mdx_get_timing is synchronising and returns the mean
- * duration in ms and the number of recorded launches. */
+ * Kernel timing with HIP events recorded around the launches of a kernel
+ * group, on the stream the group runs on. Groups: MDX_TIMING_PAIR (the
+ * short-range pair kernel), MDX_TIMING_PME (spread .. gather in
+ * mdx_compute_pme; spread .. last FFT pass, on the second stream, in
+ * mdx_integrate_step, where it overlaps the pair kernel), MDX_TIMING_BUILD
+ * (list build). mdx_set_timing(ctx, groups) takes a bit mask of groups
+ * (bit MDX_TIMING_x set = record group x; 0 stops all): it clears the
+ * earlier records of the groups it enables and records at most 8192
+ * launches per group. Event records add small gaps between kernels, so a
+ * run meant to time the whole step enables only the groups it needs.
+ * mdx_get_timing is synchronising and returns the mean duration in ms and
+ * the number of recorded launches. MDX_E_INVALID for a mask outside 0..7. */
 #define MDX_TIMING_PAIR  0
 #define MDX_TIMING_PME   1
 #define MDX_TIMING_BUILD 2
-int mdx_set_timing(mdx_ctx* ctx, int enable);
+int mdx_set_timing(mdx_ctx* ctx, int groups);
 int mdx_get_timing(mdx_ctx* ctx, int group, double* mean_ms, int64_t* launches);
 
 #ifdef __cplusplus

@@ -33,19 +33,22 @@ struct Topology {
 
 // Adds to (fx, fy, fz) the force on caller atom a from its bonds, angles and
 // (FP64) exclusion corrections; books each term's energy once: an exclusion
-// by its lower atom, a bond by its first atom, an angle by its vertex.
+// by its lower atom, a bond by its first atom, an angle by its vertex. With
+// nparts > 1 the call handles only the terms whose index in the atom's lists
+// is part modulo nparts (the callers sum the parts in a fixed order).
 template <bool ENERGY, bool COUL>
 __device__ __forceinline__ void bonded_excl_atom(int a, const float* __restrict__ pos, int n,
                                                  const BondedParams& bp, const Topology& tp,
                                                  float& fx, float& fy, float& fz, double& e_ex,
-                                                 double& e_b, double& e_a) {
+                                                 double& e_b, double& e_a, int part = 0,
+                                                 int nparts = 1) {
   float xa = pos[a], ya = pos[n + a], za = pos[2 * n + a];
   if (COUL) {
     // -k_e q_a q_b erf(alpha r)/r over excluded partners, in FP64 with the
     // exact minimum-image displacement of the float32 coordinates.
     double gx = 0.0, gy = 0.0, gz = 0.0;
     double qa = (double)tp.q[a];
-    for (int k = tp.ex_start[a]; k < tp.ex_start[a + 1]; ++k) {
+    for (int k = tp.ex_start[a] + part; k < tp.ex_start[a + 1]; k += nparts) {
       int b = tp.ex_idx[k];
       double d[3] = {(double)pos[b] - (double)xa, (double)pos[n + b] - (double)ya,
                      (double)pos[2 * n + b] - (double)za};
@@ -71,7 +74,7 @@ __device__ __forceinline__ void bonded_excl_atom(int a, const float* __restrict_
     fy += (float)gy;
     fz += (float)gz;
   }
-  for (int k = tp.bt_start[a]; k < tp.bt_start[a + 1]; ++k) {
+  for (int k = tp.bt_start[a] + part; k < tp.bt_start[a + 1]; k += nparts) {
     int t = tp.bt_idx[k];
     int i = tp.bonds[2 * t], j = tp.bonds[2 * t + 1];
     float dx = min_image(pos[i], pos[j], bp.L[0], bp.hL[0]);
@@ -86,7 +89,7 @@ __device__ __forceinline__ void bonded_excl_atom(int a, const float* __restrict_
     fz += sgn * g * dz;
     if (ENERGY && a == i) e_b += (double)(tp.bond_k[t] * dr * dr);
   }
-  for (int k = tp.at_start[a]; k < tp.at_start[a + 1]; ++k) {
+  for (int k = tp.at_start[a] + part; k < tp.at_start[a + 1]; k += nparts) {
     int t = tp.at_idx[k];
     int i = tp.angles[3 * t], j = tp.angles[3 * t + 1], l = tp.angles[3 * t + 2];
     float ax = min_image(pos[j], pos[i], bp.L[0], bp.hL[0]);
@@ -162,10 +165,11 @@ __device__ __forceinline__ void grid_coord(float x, float s_hi, float s_lo, int 
 }
 
 // Reciprocal-space force on an atom at p (charge p.w):
-// F = -k_e q sum_k grad(theta(u - k)) phi(k) over its 4x4x4 stencil.
+// F = -k_e q sum_k grad(theta(u - k)) phi(k) over its 4x4x4 stencil; the
+// z planes t3 = t3_first, t3_first + t3_step, ... < 4 of the stencil only.
 __device__ __forceinline__ void pme_gather_atom(float4 p, const float* __restrict__ phi,
                                                 const PmeParams& pp, float& fx, float& fy,
-                                                float& fz) {
+                                                float& fz, int t3_first = 0, int t3_step = 1) {
   float xyz[3] = {p.x, p.y, p.z};
   int k0[3];
   float th[3][4], dth[3][4];
@@ -175,7 +179,7 @@ __device__ __forceinline__ void pme_gather_atom(float4 p, const float* __restric
     spline4(fr, th[d], dth[d]);
   }
   float gx = 0.f, gy = 0.f, gz = 0.f;
-  for (int t3 = 0; t3 < 4; ++t3) {
+  for (int t3 = t3_first; t3 < 4; t3 += t3_step) {
     int z = k0[2] - t3;
     z += z < 0 ? pp.K[2] : 0;
     for (int t2 = 0; t2 < 4; ++t2) {

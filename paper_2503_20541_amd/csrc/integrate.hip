@@ -54,11 +54,14 @@ __global__ void __launch_bounds__(256) k_begin_step(
   if (dist2(dx, dy, dz) > half_skin2) atomicOr(gate_now, 1);
 }
 
-// Closing half of a step for every slot: the total force on the atom is the
-// pair force accumulated in the slot array (which is cleared for the next
-// evaluation), plus the PME interpolation and the bonded / exclusion terms;
-// it is stored and applied as v += (dt/2) a. FP64 energy partials
-// (exclusion, bond, angle, kinetic) per block.
+// Closing half of a step, four lanes per slot: lane q of the quad takes z
+// plane q of the PME stencil and every fourth bonded / exclusion term of the
+// atom; the quad sums its parts in a fixed order, and lane 0 adds the pair
+// force accumulated in the slot array (which it clears for the next
+// evaluation), stores the total and applies v += (dt/2) a. FP64 energy
+// partials (exclusion, bond, angle, kinetic) per block.
+constexpr int kFinishLanes = 4;
+
 template <bool ENERGY, bool COUL, bool PME>
 __global__ void __launch_bounds__(256) k_finish_step(
     const float4* __restrict__ xs, const int* __restrict__ perm, const int* __restrict__ meta,
@@ -68,16 +71,30 @@ __global__ void __launch_bounds__(256) k_finish_step(
     const float* __restrict__ acc_over_m, const float* __restrict__ mass, float half_dt,
     double inv_2acc, double* __restrict__ partials, int pstride) {
   __shared__ double red[16];
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = gt / kFinishLanes, q = gt & (kFinishLanes - 1);
   double e_ex = 0.0, e_b = 0.0, e_a = 0.0, ke = 0.0;
   const int a = s < meta[0] ? perm[s] : -1;
+  float fx = 0.f, fy = 0.f, fz = 0.f;
   if (a >= 0) {
-    float fx = fslot[s], fy = fslot[fstride + s], fz = fslot[2 * fstride + s];
+    if (PME) pme_gather_atom(xs[s], phi, pp, fx, fy, fz, q, kFinishLanes);
+    bonded_excl_atom<ENERGY, COUL>(a, pos, n, bp, tp, fx, fy, fz, e_ex, e_b, e_a, q,
+                                   kFinishLanes);
+  }
+  // quad sum (all four lanes of a quad share the slot, so a is quad-uniform)
+  fx += __shfl_xor(fx, 1, kWave);
+  fy += __shfl_xor(fy, 1, kWave);
+  fz += __shfl_xor(fz, 1, kWave);
+  fx += __shfl_xor(fx, 2, kWave);
+  fy += __shfl_xor(fy, 2, kWave);
+  fz += __shfl_xor(fz, 2, kWave);
+  if (a >= 0 && q == 0) {
+    fx += fslot[s];
+    fy += fslot[fstride + s];
+    fz += fslot[2 * fstride + s];
     fslot[s] = 0.f;
     fslot[fstride + s] = 0.f;
     fslot[2 * fstride + s] = 0.f;
-    if (PME) pme_gather_atom(xs[s], phi, pp, fx, fy, fz);
-    bonded_excl_atom<ENERGY, COUL>(a, pos, n, bp, tp, fx, fy, fz, e_ex, e_b, e_a);
     force[a] = fx;
     force[n + a] = fy;
     force[2 * n + a] = fz;
@@ -114,7 +131,7 @@ hipError_t launch_begin_step(Ctx& c, float* pos, float* vel, const float* force,
 
 hipError_t launch_finish_step(Ctx& c, const float* pos, float* vel, float* force, float dt,
                               bool energy) {
-  const int nb = (c.max_slots + 255) / 256;
+  const int nb = (c.max_slots * kFinishLanes + 255) / 256;
   const PmeParams pp = c.has_pme ? make_pme_params(c) : PmeParams{};
   const BondedParams bp = make_bonded_params(c);
   const Topology tp = make_topology(c);

@@ -51,6 +51,7 @@ struct Ctx {
   double e_self = 0.0;    // Eq. 12 + neutralising term (host FP64, fixed charges)
   bool has_coulomb = false, has_pme = false, has_switch = false;
   bool half_list = false;      // each pair once, float atomics (MDX_OPT_HALF_LIST)
+  int coop_blocks = 0;         // grid of the single-launch list build (0: one kernel per phase)
   int n_types = 0, n_excl = 0, n_bonds = 0, n_angles = 0;
   int cell_div = 2;
   int nl_cap = 0;               // tiles per i-cluster
@@ -133,6 +134,9 @@ hipError_t launch_build_list(Ctx& c, const float* pos, const int* gate = nullptr
 // Copies pos into the slot array and tests the r_g/2 validity rule; a
 // violation latches MDX_FLAG_NL_STALE.
 hipError_t launch_refresh_sorted(Ctx& c, const float* pos);
+// Blocks of the cooperative list build that are co-resident on the current
+// device (0 if cooperative launches are not available).
+int build_coop_blocks(int max_clusters, int n, int ncol);
 hipError_t launch_nonbonded(Ctx& c, bool energy);
 hipError_t launch_bonded_excl(Ctx& c, const float* pos, float* force, bool energy);
 // Sums the FP64 partial rows into out[slot - slot_base] (slots MDX_ENERGY_*);

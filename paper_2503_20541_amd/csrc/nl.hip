@@ -15,12 +15,20 @@
 // a < b. The set bits are exactly the pair list, so the exported list is the
 // definition's, while the force kernel streams whole 4x4 tiles.
 //
-// Build kernels (all gated: with a gate they return unless it is raised):
-//   k_bin (column of every atom, counts) -> k_scan (atom and
-//   padded-slot offsets per column) -> k_scatter -> k_col_sort (rank by z,
-//   write slot data) -> k_cluster_box (also the PME spreading's column
-//   ranges) -> k_tile_search (one wave per i-cluster).
+// Build phases (gated: with a gate they do nothing unless it is raised):
+//   bin (column of every atom, counts) -> scan (atom and padded-slot offsets
+//   per column) -> scatter -> column sort (rank by z, write slot data) ->
+//   cluster boxes (and the PME spreading's column ranges) -> tile search
+//   (one wave per i-cluster). By default each phase is one kernel;
+//   k_build_all runs them all in one cooperative launch with grid-wide
+//   barriers between phases (optional: cooperative launches use a separate
+//   hardware queue, and the resident grid is smaller than the per-phase
+//   grids).
 #include "mdx_internal.h"
+
+#include <hip/hip_cooperative_groups.h>
+
+#include <algorithm>
 
 namespace mdx {
 
@@ -63,170 +71,6 @@ __device__ __forceinline__ int wave_aggregated_inc(int* __restrict__ ctr, int ke
   return result;
 }
 
-// Column of every caller atom, atoms per column, build-position snapshot.
-__global__ void k_bin(const int* __restrict__ gate, const float* __restrict__ pos, int n,
-                      CellGrid cg, int* __restrict__ col_of, int* __restrict__ col_count,
-                      float* __restrict__ x_build, unsigned* __restrict__ flags) {
-  if (gated_off(gate)) return;
-  int a = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool active = a < n;
-  int c = 0;
-  if (active) {
-    float x = pos[a], y = pos[n + a], z = pos[2 * n + a];
-    bool inside = x >= 0.f && x < cg.L[0] && y >= 0.f && y < cg.L[1] && z >= 0.f && z < cg.L[2];
-    if (!inside) atomicOr(flags, MDX_FLAG_OUT_OF_BOX);
-    int cx = bin_coord(x, cg.inv_w[0], cg.n[0]);
-    int cy = bin_coord(y, cg.inv_w[1], cg.n[1]);
-    c = cy * cg.n[0] + cx;
-    col_of[a] = c;
-    x_build[a] = x;
-    x_build[n + a] = y;
-    x_build[2 * n + a] = z;
-  }
-  (void)wave_aggregated_inc(col_count, c, active);
-}
-
-// Exclusive scans of the column counts (atoms) and of the counts rounded up
-// to whole clusters (slots), in one 1024-thread block; a wave-level shuffle
-// scan combines per-thread chunk sums. meta[0] = slots, meta[1] = clusters,
-// meta[2] counts the builds. The counts are cleared once read (ready for the
-// next build's binning; they start at zero) and so is nl_needed.
-__global__ void __launch_bounds__(1024) k_scan(const int* __restrict__ gate,
-                                               int* __restrict__ count, int ncol,
-                                               int* __restrict__ start, int* __restrict__ cursor,
-                                               int* __restrict__ slot_start,
-                                               int* __restrict__ meta,
-                                               int* __restrict__ nl_needed) {
-  if (gated_off(gate)) return;
-  __shared__ int wave_tot[2][16];
-  int t = threadIdx.x;
-  int chunk = (ncol + blockDim.x - 1) / blockDim.x;
-  int b = t * chunk, e = min(b + chunk, ncol);
-  int s = 0, sp = 0;
-  for (int i = b; i < e; ++i) {
-    s += count[i];
-    sp += (count[i] + kClusterSize - 1) / kClusterSize * kClusterSize;
-  }
-  int lane = t & (kWave - 1), w = t / kWave;
-  int v = s, vp = sp;
-  for (int o = 1; o < kWave; o <<= 1) {
-    int u = __shfl_up(v, o, kWave);
-    int up = __shfl_up(vp, o, kWave);
-    if (lane >= o) {
-      v += u;
-      vp += up;
-    }
-  }
-  if (lane == kWave - 1) {
-    wave_tot[0][w] = v;
-    wave_tot[1][w] = vp;
-  }
-  __syncthreads();
-  if (t == 0) {
-    int acc = 0, accp = 0;
-    for (int i = 0; i < (int)(blockDim.x / kWave); ++i) {
-      int tmp = wave_tot[0][i], tmpp = wave_tot[1][i];
-      wave_tot[0][i] = acc;
-      wave_tot[1][i] = accp;
-      acc += tmp;
-      accp += tmpp;
-    }
-    start[ncol] = acc;
-    slot_start[ncol] = accp;
-    meta[0] = accp;
-    meta[1] = accp / kClusterSize;
-    meta[2] += 1;
-    *nl_needed = 0;
-  }
-  __syncthreads();
-  int run = wave_tot[0][w] + v - s;
-  int runp = wave_tot[1][w] + vp - sp;
-  for (int i = b; i < e; ++i) {
-    const int ci = count[i];
-    start[i] = run;
-    cursor[i] = run;
-    slot_start[i] = runp;
-    run += ci;
-    runp += (ci + kClusterSize - 1) / kClusterSize * kClusterSize;
-    count[i] = 0;
-  }
-}
-
-__global__ void k_scatter(const int* __restrict__ gate, const int* __restrict__ col_of, int n,
-                          int* __restrict__ cursor, int* __restrict__ perm_unsorted) {
-  if (gated_off(gate)) return;
-  int a = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool active = a < n;
-  const int c = active ? col_of[a] : 0;
-  const int slot = wave_aggregated_inc(cursor, c, active);
-  if (active) perm_unsorted[slot] = a;
-}
-
-// One workgroup per column: rank its atoms by (build z, atom index) - an
-// order that does not depend on the scatter's atomic order - and write the
-// slot data; padding slots of the column's last cluster are emptied.
-// Columns of up to kColStage atoms are ranked from LDS, larger ones from
-// global memory.
-constexpr int kColThreads = 128;
-constexpr int kColStage = 1024;
-
-__global__ void __launch_bounds__(kColThreads) k_col_sort(
-    const int* __restrict__ gate, const int* __restrict__ col_start,
-    const int* __restrict__ slot_start, int ncol, const int* __restrict__ perm_unsorted,
-    const float* __restrict__ pos, int n, const float* __restrict__ q,
-    const int* __restrict__ atype, int* __restrict__ perm, int* __restrict__ inv_perm,
-    float4* __restrict__ xs, int* __restrict__ ts, float* __restrict__ zb) {
-  if (gated_off(gate)) return;
-  __shared__ float2 st[kColStage];   // (build z, atom index bits)
-  const int c = blockIdx.x;
-  if (c >= ncol) return;
-  const int b = col_start[c], e = col_start[c + 1];
-  const int cnt = e - b;
-  const int sb = slot_start[c], se = slot_start[c + 1];
-  const bool staged = cnt <= kColStage;
-  if (staged) {
-    for (int p = threadIdx.x; p < cnt; p += kColThreads) {
-      const int v = perm_unsorted[b + p];
-      st[p] = make_float2(pos[2 * n + v], __int_as_float(v));
-    }
-    __syncthreads();
-  }
-  for (int p = threadIdx.x; p < cnt; p += kColThreads) {
-    int v, rank = 0;
-    float zv;
-    if (staged) {
-      const float2 me = st[p];
-      zv = me.x;
-      v = __float_as_int(me.y);
-      for (int k = 0; k < cnt; ++k) {
-        const float2 o = st[k];
-        const int u = __float_as_int(o.y);
-        rank += (o.x < zv || (o.x == zv && u < v)) ? 1 : 0;
-      }
-    } else {
-      v = perm_unsorted[b + p];
-      zv = pos[2 * n + v];
-      for (int k = 0; k < cnt; ++k) {
-        const int u = perm_unsorted[b + k];
-        const float zu = pos[2 * n + u];
-        rank += (zu < zv || (zu == zv && u < v)) ? 1 : 0;
-      }
-    }
-    const int s = sb + rank;
-    perm[s] = v;
-    inv_perm[v] = s;
-    xs[s] = make_float4(pos[v], pos[n + v], zv, q[v]);
-    ts[s] = atype[v];
-    zb[s] = zv;
-  }
-  for (int s = sb + cnt + threadIdx.x; s < se; s += kColThreads) {
-    perm[s] = -1;
-    xs[s] = make_float4(0.f, 0.f, 0.f, 0.f);
-    ts[s] = 0;
-    zb[s] = 3.0e38f;
-  }
-}
-
 // For the PME spreading: per (brick layer along z, column) the slots of the
 // column whose build z lies in the layer's reach [lo, hi) - one segment, or
 // two when the reach wraps around the periodic box.
@@ -260,32 +104,206 @@ __device__ void column_zrange(int e, const ZRangeArgs& z) {
   z.out[e] = make_int4(s0, max(0, e0 - s0), s1, max(0, e1 - s1));
 }
 
-// Bounding box of every cluster's real atoms at the build positions; blocks
-// past the cluster blocks fill the PME column ranges.
-__global__ void k_cluster_box(const int* __restrict__ gate, const int* __restrict__ meta,
-                              const float4* __restrict__ xs, const int* __restrict__ perm,
-                              float4* __restrict__ box_lo, float4* __restrict__ box_hi,
-                              int cluster_blocks, ZRangeArgs zr) {
-  if (gated_off(gate)) return;
-  if ((int)blockIdx.x >= cluster_blocks) {
-    const int e = ((int)blockIdx.x - cluster_blocks) * blockDim.x + threadIdx.x;
-    if (e < zr.layers * zr.ncol) column_zrange(e, zr);
-    return;
+// Everything the build phases read and write.
+struct BuildArgs {
+  const int* gate;
+  const float* pos;
+  int n;
+  CellGrid cg;
+  int* col_of;
+  int* col_count;
+  float* x_build;
+  unsigned* flags;
+  int* col_start;
+  int* cursor;
+  int* slot_start;
+  int* meta;
+  int* nl_needed;
+  int* perm_unsorted;
+  const float* q;
+  const int* atype;
+  int* perm;
+  int* inv_perm;
+  float4* xs;
+  int* ts;
+  float* zb;
+  float4* box_lo;
+  float4* box_hi;
+  ZRangeArgs zr;
+  const int* ex_start;
+  const int* ex_idx;
+  int cap;
+  int half;
+  uint2* tiles;
+  int* tile_count;
+  int max_clusters;
+};
+
+// Column of caller atom i, atoms per column, build-position snapshot. The
+// whole wave calls it (lanes with i >= n take part in the aggregation only).
+__device__ void bin_atom(const BuildArgs& a, int i) {
+  const bool active = i < a.n;
+  int c = 0;
+  if (active) {
+    const int n = a.n;
+    float x = a.pos[i], y = a.pos[n + i], z = a.pos[2 * n + i];
+    bool inside = x >= 0.f && x < a.cg.L[0] && y >= 0.f && y < a.cg.L[1] && z >= 0.f &&
+                  z < a.cg.L[2];
+    if (!inside) atomicOr(a.flags, MDX_FLAG_OUT_OF_BOX);
+    int cx = bin_coord(x, a.cg.inv_w[0], a.cg.n[0]);
+    int cy = bin_coord(y, a.cg.inv_w[1], a.cg.n[1]);
+    c = cy * a.cg.n[0] + cx;
+    a.col_of[i] = c;
+    a.x_build[i] = x;
+    a.x_build[n + i] = y;
+    a.x_build[2 * n + i] = z;
   }
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= meta[1]) return;
+  (void)wave_aggregated_inc(a.col_count, c, active);
+}
+
+// Exclusive scans of the column counts (atoms) and of the counts rounded up
+// to whole clusters (slots), by one block; a wave-level shuffle scan
+// combines per-thread chunk sums. meta[0] = slots, meta[1] = clusters,
+// meta[2] counts the builds. The counts are cleared once read (ready for the
+// next build's binning; they start at zero) and so is nl_needed.
+__device__ void scan_columns(const BuildArgs& a) {
+  __shared__ int wave_tot[2][16];
+  const int ncol = a.cg.ncell;
+  int* count = a.col_count;
+  int t = threadIdx.x;
+  int chunk = (ncol + blockDim.x - 1) / blockDim.x;
+  int b = t * chunk, e = min(b + chunk, ncol);
+  int s = 0, sp = 0;
+  for (int i = b; i < e; ++i) {
+    s += count[i];
+    sp += (count[i] + kClusterSize - 1) / kClusterSize * kClusterSize;
+  }
+  int lane = t & (kWave - 1), w = t / kWave;
+  int v = s, vp = sp;
+  for (int o = 1; o < kWave; o <<= 1) {
+    int u = __shfl_up(v, o, kWave);
+    int up = __shfl_up(vp, o, kWave);
+    if (lane >= o) {
+      v += u;
+      vp += up;
+    }
+  }
+  if (lane == kWave - 1) {
+    wave_tot[0][w] = v;
+    wave_tot[1][w] = vp;
+  }
+  __syncthreads();
+  if (t == 0) {
+    int acc = 0, accp = 0;
+    for (int i = 0; i < (int)(blockDim.x / kWave); ++i) {
+      int tmp = wave_tot[0][i], tmpp = wave_tot[1][i];
+      wave_tot[0][i] = acc;
+      wave_tot[1][i] = accp;
+      acc += tmp;
+      accp += tmpp;
+    }
+    a.col_start[ncol] = acc;
+    a.slot_start[ncol] = accp;
+    a.meta[0] = accp;
+    a.meta[1] = accp / kClusterSize;
+    a.meta[2] += 1;
+    *a.nl_needed = 0;
+  }
+  __syncthreads();
+  int run = wave_tot[0][w] + v - s;
+  int runp = wave_tot[1][w] + vp - sp;
+  for (int i = b; i < e; ++i) {
+    const int ci = count[i];
+    a.col_start[i] = run;
+    a.cursor[i] = run;
+    a.slot_start[i] = runp;
+    run += ci;
+    runp += (ci + kClusterSize - 1) / kClusterSize * kClusterSize;
+    count[i] = 0;
+  }
+}
+
+// Caller atom i into its column's next unsorted position (whole wave calls).
+__device__ void scatter_atom(const BuildArgs& a, int i) {
+  const bool active = i < a.n;
+  const int c = active ? a.col_of[i] : 0;
+  const int slot = wave_aggregated_inc(a.cursor, c, active);
+  if (active) a.perm_unsorted[slot] = i;
+}
+
+// One block per column: rank its atoms by (build z, atom index) - an order
+// that does not depend on the scatter's atomic order - and write the slot
+// data; padding slots of the column's last cluster are emptied. Columns of
+// up to kColStage atoms are ranked from LDS (st), larger ones from global
+// memory.
+constexpr int kColThreads = 128;
+constexpr int kColStage = 1024;
+
+__device__ void sort_column(const BuildArgs& a, int c, float2* st) {
+  const int n = a.n;
+  const int b = a.col_start[c], e = a.col_start[c + 1];
+  const int cnt = e - b;
+  const int sb = a.slot_start[c], se = a.slot_start[c + 1];
+  const bool staged = cnt <= kColStage;
+  __syncthreads();   // st may still be read for the previous column
+  if (staged) {
+    for (int p = threadIdx.x; p < cnt; p += blockDim.x) {
+      const int v = a.perm_unsorted[b + p];
+      st[p] = make_float2(a.pos[2 * n + v], __int_as_float(v));
+    }
+    __syncthreads();
+  }
+  for (int p = threadIdx.x; p < cnt; p += blockDim.x) {
+    int v, rank = 0;
+    float zv;
+    if (staged) {
+      const float2 me = st[p];
+      zv = me.x;
+      v = __float_as_int(me.y);
+      for (int k = 0; k < cnt; ++k) {
+        const float2 o = st[k];
+        const int u = __float_as_int(o.y);
+        rank += (o.x < zv || (o.x == zv && u < v)) ? 1 : 0;
+      }
+    } else {
+      v = a.perm_unsorted[b + p];
+      zv = a.pos[2 * n + v];
+      for (int k = 0; k < cnt; ++k) {
+        const int u = a.perm_unsorted[b + k];
+        const float zu = a.pos[2 * n + u];
+        rank += (zu < zv || (zu == zv && u < v)) ? 1 : 0;
+      }
+    }
+    const int s = sb + rank;
+    a.perm[s] = v;
+    a.inv_perm[v] = s;
+    a.xs[s] = make_float4(a.pos[v], a.pos[n + v], zv, a.q[v]);
+    a.ts[s] = a.atype[v];
+    a.zb[s] = zv;
+  }
+  for (int s = sb + cnt + threadIdx.x; s < se; s += blockDim.x) {
+    a.perm[s] = -1;
+    a.xs[s] = make_float4(0.f, 0.f, 0.f, 0.f);
+    a.ts[s] = 0;
+    a.zb[s] = 3.0e38f;
+  }
+}
+
+// Bounding box of cluster c's real atoms at the build positions.
+__device__ void cluster_box(const BuildArgs& a, int c) {
+  if (c >= a.meta[1]) return;
   float lx = 3e38f, ly = 3e38f, lz = 3e38f, hx = -3e38f, hy = -3e38f, hz = -3e38f;
   int nvalid = 0;
   for (int k = 0; k < kClusterSize; ++k) {
     int s = c * kClusterSize + k;
-    if (perm[s] < 0) continue;
-    float4 p = xs[s];
+    if (a.perm[s] < 0) continue;
+    float4 p = a.xs[s];
     lx = fminf(lx, p.x); ly = fminf(ly, p.y); lz = fminf(lz, p.z);
     hx = fmaxf(hx, p.x); hy = fmaxf(hy, p.y); hz = fmaxf(hz, p.z);
     ++nvalid;
   }
-  box_lo[c] = make_float4(lx, ly, lz, (float)nvalid);
-  box_hi[c] = make_float4(hx, hy, hz, 0.f);
+  a.box_lo[c] = make_float4(lx, ly, lz, (float)nvalid);
+  a.box_hi[c] = make_float4(hx, hy, hz, 0.f);
 }
 
 // Each unordered pair of distinct clusters is listed once, from the cluster
@@ -326,7 +344,7 @@ __device__ __forceinline__ int first_gt(const float4* __restrict__ b, int lo, in
   return lo;
 }
 
-// One wave per i-cluster: (1) enumerate the j-clusters of the columns within
+// One wave per i-cluster ic: (1) enumerate the j-clusters of the columns within
 // reach - inside a column only the z-sorted clusters that overlap the
 // i-box's z reach (one or two periodic segments, binary searches) - and keep
 // those the i-cluster owns (owns_pair) whose boxes come closer than r_nl
@@ -334,41 +352,29 @@ __device__ __forceinline__ int first_gt(const float4* __restrict__ b, int lo, in
 // pairs of four candidate tiles at once (one lane per pair) with the exact
 // predicate and the exclusions; tiles with a non-empty mask are appended to
 // the i-cluster's list in enumeration order.
-__global__ void __launch_bounds__(256) k_tile_search(
-    const int* __restrict__ gate, const int* __restrict__ meta, const float4* __restrict__ xs,
-    const int* __restrict__ perm, const int* __restrict__ inv_perm,
-    const float4* __restrict__ box_lo, const float4* __restrict__ box_hi,
-    const int* __restrict__ slot_start, const int* __restrict__ ex_start,
-    const int* __restrict__ ex_idx, CellGrid cg, int cap, int half,
-    uint2* __restrict__ tiles, int* __restrict__ tile_count, int* __restrict__ nl_needed,
-    unsigned* __restrict__ flags) {
-  if (gated_off(gate)) return;
-  __shared__ int cand[4][kSearchCand];
-  __shared__ int seg_first[4][kSearchSegs];
-  __shared__ int seg_pre[4][kSearchSegs + 1];
-  const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  const int ic = blockIdx.x * 4 + w;
-  const int nclu = meta[1];
+__device__ void search_cluster(const BuildArgs& a, int ic, int* mycand, int* seg_first,
+                               int* seg_pre) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int nclu = a.meta[1];
   if (ic >= nclu) return;
-  const float4 ilo = box_lo[ic], ihi = box_hi[ic];
-  int* mycand = cand[w];
+  const float4 ilo = a.box_lo[ic], ihi = a.box_hi[ic];
   int ncand = 0;
   bool overflow = false;
   if (ilo.w > 0.f) {
-    const float reach = cg.r_search;
+    const float reach = a.cg.r_search;
     // column ranges (periodic) that can hold a box within reach
-    int cx0 = (int)floorf((ilo.x - reach) * cg.inv_w[0]);
-    int cx1 = (int)floorf((ihi.x + reach) * cg.inv_w[0]);
-    int cy0 = (int)floorf((ilo.y - reach) * cg.inv_w[1]);
-    int cy1 = (int)floorf((ihi.y + reach) * cg.inv_w[1]);
-    int nx = min(cx1 - cx0 + 1, cg.n[0]);
-    int ny = min(cy1 - cy0 + 1, cg.n[1]);
-    if (nx == cg.n[0]) cx0 = 0;
-    if (ny == cg.n[1]) cy0 = 0;
+    int cx0 = (int)floorf((ilo.x - reach) * a.cg.inv_w[0]);
+    int cx1 = (int)floorf((ihi.x + reach) * a.cg.inv_w[0]);
+    int cy0 = (int)floorf((ilo.y - reach) * a.cg.inv_w[1]);
+    int cy1 = (int)floorf((ihi.y + reach) * a.cg.inv_w[1]);
+    int nx = min(cx1 - cx0 + 1, a.cg.n[0]);
+    int ny = min(cy1 - cy0 + 1, a.cg.n[1]);
+    if (nx == a.cg.n[0]) cx0 = 0;
+    if (ny == a.cg.n[1]) cy0 = 0;
     const int ncols = nx * ny;
     const float reach2 = reach * reach;
     // z reach as up to two segments inside [0, L)
-    const float Lz = cg.L[2];
+    const float Lz = a.cg.L[2];
     const float margin = 1e-3f * reach;
     float za = ilo.z - reach - margin, zb_ = ihi.z + reach + margin;
     float sa[2], sz[2];
@@ -390,18 +396,18 @@ __global__ void __launch_bounds__(256) k_tile_search(
         int u = u0 + lane;
         int t = u / nseg, sg = u - t * nseg;
         int x = cx0 + t % nx, y = cy0 + t / nx;
-        x %= cg.n[0]; x += x < 0 ? cg.n[0] : 0;
-        y %= cg.n[1]; y += y < 0 ? cg.n[1] : 0;
-        int col = y * cg.n[0] + x;
-        int c0 = slot_start[col] / kClusterSize, c1 = slot_start[col + 1] / kClusterSize;
+        x %= a.cg.n[0]; x += x < 0 ? a.cg.n[0] : 0;
+        y %= a.cg.n[1]; y += y < 0 ? a.cg.n[1] : 0;
+        int col = y * a.cg.n[0] + x;
+        int c0 = a.slot_start[col] / kClusterSize, c1 = a.slot_start[col + 1] / kClusterSize;
         // clusters overlapping [sa, sz]: max z >= sa and min z <= sz
-        int f = first_ge(box_hi, c0, c1, sa[sg]);
-        int l = first_gt(box_lo, f, c1, sz[sg]);
+        int f = first_ge(a.box_hi, c0, c1, sa[sg]);
+        int l = first_gt(a.box_lo, f, c1, sz[sg]);
         if (sg == 1) {
           // the two segments sit at opposite ends of the column; a cluster
           // reaching into both is taken once, by segment 0
-          int f0 = first_ge(box_hi, c0, c1, sa[0]);
-          int l0 = first_gt(box_lo, f0, c1, sz[0]);
+          int f0 = first_ge(a.box_hi, c0, c1, sa[0]);
+          int l0 = first_gt(a.box_lo, f0, c1, sz[0]);
           if (sa[1] > sa[0]) f = max(f, l0);
           else l = min(l, f0);
         }
@@ -414,10 +420,10 @@ __global__ void __launch_bounds__(256) k_tile_search(
         if (lane >= o) v += uu;
       }
       if (lane < nu) {
-        seg_first[w][lane] = first;
-        seg_pre[w][lane + 1] = v;
+        seg_first[lane] = first;
+        seg_pre[lane + 1] = v;
       }
-      if (lane == 0) seg_pre[w][0] = 0;
+      if (lane == 0) seg_pre[0] = 0;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -430,14 +436,14 @@ __global__ void __launch_bounds__(256) k_tile_search(
           int lo = 0, hi = nu - 1;
           while (lo < hi) {
             int mid = (lo + hi + 1) >> 1;
-            if (seg_pre[w][mid] <= f) lo = mid; else hi = mid - 1;
+            if (seg_pre[mid] <= f) lo = mid; else hi = mid - 1;
           }
-          jc = seg_first[w][lo] + (f - seg_pre[w][lo]);
-          float4 jlo = box_lo[jc], jhi = box_hi[jc];
-          if (jlo.w > 0.f && owns_pair(ic, jc, half)) {
-            float gx = axis_gap(ilo.x, ihi.x, jlo.x, jhi.x, cg.L[0]);
-            float gy = axis_gap(ilo.y, ihi.y, jlo.y, jhi.y, cg.L[1]);
-            float gz = axis_gap(ilo.z, ihi.z, jlo.z, jhi.z, cg.L[2]);
+          jc = seg_first[lo] + (f - seg_pre[lo]);
+          float4 jlo = a.box_lo[jc], jhi = a.box_hi[jc];
+          if (jlo.w > 0.f && owns_pair(ic, jc, a.half)) {
+            float gx = axis_gap(ilo.x, ihi.x, jlo.x, jhi.x, a.cg.L[0]);
+            float gy = axis_gap(ilo.y, ihi.y, jlo.y, jhi.y, a.cg.L[1]);
+            float gz = axis_gap(ilo.z, ihi.z, jlo.z, jhi.z, a.cg.L[2]);
             pass = gx * gx + gy * gy + gz * gz < reach2;
           }
         }
@@ -467,22 +473,22 @@ __global__ void __launch_bounds__(256) k_tile_search(
   // is below the cluster's real-atom count). The i atom's excluded partners
   // are held as slot indices in registers (the list walk is the fallback
   // for atoms with more than four exclusions).
-  const int t = lane >> 4, a = (lane >> 2) & 3, b = lane & 3;
-  const int si = ic * kClusterSize + a;
-  const bool ivalid = a < (int)ilo.w;
-  const float4 pi = xs[si];
-  const float lmx = cg.L[0] - pi.x, lmy = cg.L[1] - pi.y, lmz = cg.L[2] - pi.z;
+  const int t = lane >> 4, ia = (lane >> 2) & 3, b = lane & 3;
+  const int si = ic * kClusterSize + ia;
+  const bool ivalid = ia < (int)ilo.w;
+  const float4 pi = a.xs[si];
+  const float lmx = a.cg.L[0] - pi.x, lmy = a.cg.L[1] - pi.y, lmz = a.cg.L[2] - pi.z;
   int ex0 = -1, ex1 = -1, ex2 = -1, ex3 = -1;
   int eb = 0, ee = 0;
   if (ivalid) {
-    const int ai = perm[si];
-    eb = ex_start[ai];
-    ee = ex_start[ai + 1];
+    const int ai = a.perm[si];
+    eb = a.ex_start[ai];
+    ee = a.ex_start[ai + 1];
     const int ne = ee - eb;
-    if (ne > 0) ex0 = inv_perm[ex_idx[eb]];
-    if (ne > 1) ex1 = inv_perm[ex_idx[eb + 1]];
-    if (ne > 2) ex2 = inv_perm[ex_idx[eb + 2]];
-    if (ne > 3) ex3 = inv_perm[ex_idx[eb + 3]];
+    if (ne > 0) ex0 = a.inv_perm[a.ex_idx[eb]];
+    if (ne > 1) ex1 = a.inv_perm[a.ex_idx[eb + 1]];
+    if (ne > 2) ex2 = a.inv_perm[a.ex_idx[eb + 2]];
+    if (ne > 3) ex3 = a.inv_perm[a.ex_idx[eb + 3]];
   }
   const bool ex_more = ee - eb > 4;
   int count = 0;
@@ -490,8 +496,8 @@ __global__ void __launch_bounds__(256) k_tile_search(
   float nv_n = 0.f;
   float4 pj_n = make_float4(0.f, 0.f, 0.f, 0.f);
   if (jc_n >= 0) {
-    nv_n = box_lo[jc_n].w;
-    pj_n = xs[jc_n * kClusterSize + b];
+    nv_n = a.box_lo[jc_n].w;
+    pj_n = a.xs[jc_n * kClusterSize + b];
   }
   for (int g = 0; g < ncand; g += 4) {
     const int jc = jc_n;
@@ -499,21 +505,21 @@ __global__ void __launch_bounds__(256) k_tile_search(
     const float4 pj = pj_n;
     jc_n = (g + 4 + t < ncand) ? mycand[g + 4 + t] : -1;
     if (jc_n >= 0) {
-      nv_n = box_lo[jc_n].w;
-      pj_n = xs[jc_n * kClusterSize + b];
+      nv_n = a.box_lo[jc_n].w;
+      pj_n = a.xs[jc_n * kClusterSize + b];
     }
     unsigned bit = 0;
     const int sj = jc * kClusterSize + b;
     // the cluster's own tile: slot pairs a < b (half list) or a != b
-    if (jc >= 0 && ivalid && b < (int)nv && (jc != ic || b > a || (!half && b < a))) {
-      float dx = min_image_h(pi.x, lmx, pj.x, cg.L[0], cg.hL[0]);
-      float dy = min_image_h(pi.y, lmy, pj.y, cg.L[1], cg.hL[1]);
-      float dz = min_image_h(pi.z, lmz, pj.z, cg.L[2], cg.hL[2]);
-      if (dist2(dx, dy, dz) < cg.rnl2) {
+    if (jc >= 0 && ivalid && b < (int)nv && (jc != ic || b > ia || (!a.half && b < ia))) {
+      float dx = min_image_h(pi.x, lmx, pj.x, a.cg.L[0], a.cg.hL[0]);
+      float dy = min_image_h(pi.y, lmy, pj.y, a.cg.L[1], a.cg.hL[1]);
+      float dz = min_image_h(pi.z, lmz, pj.z, a.cg.L[2], a.cg.hL[2]);
+      if (dist2(dx, dy, dz) < a.cg.rnl2) {
         bool excluded = sj == ex0 || sj == ex1 || sj == ex2 || sj == ex3;
         if (ex_more && !excluded) {
-          const int aj = perm[sj];
-          for (int k = eb + 4; k < ee; ++k) excluded |= (ex_idx[k] == aj);
+          const int aj = a.perm[sj];
+          for (int k = eb + 4; k < ee; ++k) excluded |= (a.ex_idx[k] == aj);
         }
         bit = excluded ? 0u : 1u;
       }
@@ -521,24 +527,116 @@ __global__ void __launch_bounds__(256) k_tile_search(
     unsigned long long m = __ballot(bit != 0);
     // 16-bit mask of tile t: bits of lanes 16t .. 16t+15, bit index 4a + b
     unsigned mask = (unsigned)((m >> (16 * t)) & 0xffffull);
-    unsigned long long nonempty = __ballot(b == 0 && a == 0 && mask != 0);
+    unsigned long long nonempty = __ballot(b == 0 && ia == 0 && mask != 0);
     int before = __popcll(nonempty & ((1ull << lane) - 1ull));
-    if (a == 0 && b == 0 && mask != 0) {
+    if (ia == 0 && b == 0 && mask != 0) {
       int k = count + before;
-      if (k < cap) tiles[(size_t)ic * cap + k] = make_uint2((unsigned)jc, mask);
+      if (k < a.cap) a.tiles[(size_t)ic * a.cap + k] = make_uint2((unsigned)jc, mask);
     }
     count += __popcll(nonempty);
   }
   // pad the list to whole groups of four tiles with empty tiles (mask 0)
-  const int kept = count < cap ? count : cap;
-  const int padded = min((kept + 3) & ~3, cap);
-  if (lane < padded - kept) tiles[(size_t)ic * cap + kept + lane] = make_uint2(0u, 0u);
+  const int kept = count < a.cap ? count : a.cap;
+  const int padded = min((kept + 3) & ~3, a.cap);
+  if (lane < padded - kept) a.tiles[(size_t)ic * a.cap + kept + lane] = make_uint2(0u, 0u);
   if (lane == 0) {
-    tile_count[ic] = padded;
-    if (count > cap) atomicOr(flags, MDX_FLAG_NL_OVERFLOW);
-    if (overflow) atomicOr(flags, MDX_FLAG_CELL_OVERFLOW);
-    atomicMax(nl_needed, count);
+    a.tile_count[ic] = padded;
+    if (count > a.cap) atomicOr(a.flags, MDX_FLAG_NL_OVERFLOW);
+    if (overflow) atomicOr(a.flags, MDX_FLAG_CELL_OVERFLOW);
+    atomicMax(a.nl_needed, count);
   }
+}
+
+// ---- one kernel per phase ---------------------------------------------------
+__global__ void k_bin(BuildArgs a) {
+  if (gated_off(a.gate)) return;
+  bin_atom(a, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ void __launch_bounds__(1024) k_scan(BuildArgs a) {
+  if (gated_off(a.gate)) return;
+  scan_columns(a);
+}
+
+__global__ void k_scatter(BuildArgs a) {
+  if (gated_off(a.gate)) return;
+  scatter_atom(a, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ void __launch_bounds__(kColThreads) k_col_sort(BuildArgs a) {
+  if (gated_off(a.gate)) return;
+  __shared__ float2 st[kColStage];   // (build z, atom index bits)
+  sort_column(a, blockIdx.x, st);
+}
+
+// Cluster boxes; threads past the clusters fill the PME column ranges.
+__global__ void k_cluster_box(BuildArgs a) {
+  if (gated_off(a.gate)) return;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < a.max_clusters) cluster_box(a, e);
+  else if (e - a.max_clusters < a.zr.layers * a.zr.ncol) column_zrange(e - a.max_clusters, a.zr);
+}
+
+__global__ void __launch_bounds__(256) k_tile_search(BuildArgs a) {
+  if (gated_off(a.gate)) return;
+  __shared__ int cand[4][kSearchCand];
+  __shared__ int seg_first[4][kSearchSegs];
+  __shared__ int seg_pre[4][kSearchSegs + 1];
+  const int w = threadIdx.x / kWave;
+  search_cluster(a, blockIdx.x * 4 + w, cand[w], seg_first[w], seg_pre[w]);
+}
+
+// ---- all phases in one cooperative launch ------------------------------------
+// Every block runs every phase (grid-stride loops) with grid-wide barriers in
+// between; the gate test comes first and is the same for all blocks, so
+// either every block reaches every barrier or none does.
+constexpr int kBuildThreads = 256;
+
+__global__ void __launch_bounds__(kBuildThreads) k_build_all(BuildArgs a) {
+  if (gated_off(a.gate)) return;
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  __shared__ float2 st[kColStage];
+  __shared__ int cand[4][kSearchCand];
+  __shared__ int seg_first[4][kSearchSegs];
+  __shared__ int seg_pre[4][kSearchSegs + 1];
+  const int nthreads = gridDim.x * blockDim.x;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  // bounds rounded to whole blocks: the atom loops stay uniform per wave
+  const int nround = (a.n + blockDim.x - 1) / blockDim.x * blockDim.x;
+  for (int i = tid; i < nround; i += nthreads) bin_atom(a, i);
+  grid.sync();
+  if (blockIdx.x == 0) scan_columns(a);
+  grid.sync();
+  for (int i = tid; i < nround; i += nthreads) scatter_atom(a, i);
+  grid.sync();
+  for (int c = blockIdx.x; c < a.cg.ncell; c += gridDim.x) sort_column(a, c, st);
+  grid.sync();
+  const int nz = a.zr.layers * a.zr.ncol;
+  for (int e = tid; e < a.max_clusters + nz; e += nthreads) {
+    if (e < a.max_clusters) cluster_box(a, e);
+    else column_zrange(e - a.max_clusters, a.zr);
+  }
+  grid.sync();
+  const int w = threadIdx.x / kWave;
+  for (int ic = blockIdx.x * 4 + w; ic < a.max_clusters; ic += gridDim.x * 4)
+    search_cluster(a, ic, cand[w], seg_first[w], seg_pre[w]);
+}
+
+int build_coop_blocks(int max_clusters, int n, int ncol) {
+  int dev = 0, coop = 0, ncu = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess ||
+      !coop)
+    return 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_build_all, kBuildThreads, 0) !=
+          hipSuccess ||
+      per_cu <= 0)
+    return 0;
+  const int useful = std::max({(n + kBuildThreads - 1) / kBuildThreads, ncol,
+                               (max_clusters + 3) / 4, 1});
+  return std::min(per_cu * ncu, useful);
 }
 
 // Copy the current positions into the slot array and test the list's
@@ -567,25 +665,28 @@ __global__ void k_refresh(const float* __restrict__ pos, const int* __restrict__
 hipError_t launch_build_list(Ctx& c, const float* pos, const int* gate) {
   hipStream_t s = c.stream;
   const int n = c.n;
-  const int nb = (n + 255) / 256;
   const int ncol = c.cg.ncell;
-  k_bin<<<nb, 256, 0, s>>>(gate, pos, n, c.cg, c.cell_of, c.cell_count, c.x_build, c.flags);
-  k_scan<<<1, 1024, 0, s>>>(gate, c.cell_count, ncol, c.cell_start, c.cell_cursor, c.slot_start,
-                            c.meta, c.nl_needed);
-  k_scatter<<<nb, 256, 0, s>>>(gate, c.cell_of, n, c.cell_cursor, c.perm_unsorted);
-  k_col_sort<<<ncol, kColThreads, 0, s>>>(gate, c.cell_start, c.slot_start, ncol,
-                                            c.perm_unsorted, pos, n, c.q, c.atype, c.perm,
-                                            c.inv_perm, c.xs, c.ts, c.zb);
-  const int cblocks = (c.max_clusters + 255) / 256;
-  ZRangeArgs zr{c.zb, c.slot_start, c.cell_start, c.brick_z, c.has_pme ? c.pg.nb[2] : 0, ncol,
-                c.cg.L[2], c.brick_zr};
-  const int zblocks = (zr.layers * ncol + 255) / 256;
-  k_cluster_box<<<cblocks + zblocks, 256, 0, s>>>(gate, c.meta, c.xs, c.perm, c.box_lo, c.box_hi,
-                                                  cblocks, zr);
-  k_tile_search<<<(c.max_clusters + 3) / 4, 256, 0, s>>>(
-      gate, c.meta, c.xs, c.perm, c.inv_perm, c.box_lo, c.box_hi, c.slot_start, c.ex_start,
-      c.ex_idx, c.cg, c.nl_cap, c.half_list ? 1 : 0, c.tiles, c.tile_count, c.nl_needed,
-      c.flags);
+  BuildArgs a{gate, pos, n, c.cg, c.cell_of, c.cell_count, c.x_build, c.flags,
+              c.cell_start, c.cell_cursor, c.slot_start, c.meta, c.nl_needed,
+              c.perm_unsorted, c.q, c.atype, c.perm, c.inv_perm, c.xs, c.ts, c.zb,
+              c.box_lo, c.box_hi,
+              ZRangeArgs{c.zb, c.slot_start, c.cell_start, c.brick_z,
+                         c.has_pme ? c.pg.nb[2] : 0, ncol, c.cg.L[2], c.brick_zr},
+              c.ex_start, c.ex_idx, c.nl_cap, c.half_list ? 1 : 0, c.tiles, c.tile_count,
+              c.max_clusters};
+  if (c.coop_blocks > 0) {
+    void* args[] = {&a};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_build_all),
+                                      dim3(c.coop_blocks), dim3(kBuildThreads), args, 0, s);
+  }
+  const int nb = (n + 255) / 256;
+  k_bin<<<nb, 256, 0, s>>>(a);
+  k_scan<<<1, 1024, 0, s>>>(a);
+  k_scatter<<<nb, 256, 0, s>>>(a);
+  k_col_sort<<<ncol, kColThreads, 0, s>>>(a);
+  const int nz = a.zr.layers * ncol;
+  k_cluster_box<<<(c.max_clusters + nz + 255) / 256, 256, 0, s>>>(a);
+  k_tile_search<<<(c.max_clusters + 3) / 4, 256, 0, s>>>(a);
   return hipGetLastError();
 }
 

@@ -4,11 +4,9 @@
 //                 column sort: columns within spline reach + r_g/2 of the
 //                 brick, and in each the slots whose build z is in reach
 //                 (ranges found by binary search once per list build).
-//                 Lanes first compute one atom's B-spline weights each, then
-//                 the wave walks the atoms one by one with lanes = the 4x4x4
-//                 stencil points, adding into its own LDS copy of the brick
-//                 (distinct addresses per instruction). Copies are summed in
-//                 a fixed order: atomic-free and deterministic.
+//                 Each lane takes one atom and adds its stencil values
+//                 inside the brick into its wave's own LDS copy of the brick;
+//                 the copies are summed in a fixed order (no global atomics).
 //  k_fft_rows_*   x-direction real<->half-complex transforms, P rows per block
 //  k_fft_cols     y (forward / inverse) and z (forward, influence multiply
 //                 with the FP64 energy partial, inverse) pencils
@@ -30,30 +28,49 @@ constexpr int kSpreadThreads = 256;
 constexpr int kSpreadWaves = kSpreadThreads / kWave;
 constexpr int kMaxBrick = 8 * 66;    // B_z planes of B_x * B_y + 2 points (padded, see below)
 constexpr int kMaxCandCells = 512;
-constexpr int kStage = 16;           // floats staged per atom
+constexpr int kCandList = 2048;      // candidate slots a brick lists in LDS
 
-// The LDS brick copies store point (lx, ly, lz) at lx + B_x ly + (B_x B_y + 2) lz:
-// with the 4x4x4 stencil on the 64 lanes every bank is hit at most twice
-// per instruction (32 or 64 banks).
+// The LDS brick copies store point (lx, ly, lz) at lx + B_x ly + (B_x B_y + 2) lz
+// (the padding spreads the planes over the banks).
 __device__ __forceinline__ int brick_index(int lx, int ly, int lz, const PmeParams& pp) {
   return (lz * pp.B[1] + ly) * pp.B[0] + 2 * lz + lx;
 }
 
+// Candidate f of a brick: slot index from the LDS list, or (for bricks with
+// more candidates than the list holds) by binary search over the segment
+// offsets.
+__device__ __forceinline__ int spread_candidate(int f, int total, int ncand,
+                                                const int* cand_list, const int* cand_start,
+                                                const int* cand_off) {
+  if (total <= kCandList) return cand_list[f];
+  int lo = 0, hi = ncand - 1;             // last segment with cand_off <= f
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (cand_off[mid] <= f) lo = mid; else hi = mid - 1;
+  }
+  return cand_start[lo] + (f - cand_off[lo]);
+}
+
+// One workgroup per brick. Each lane takes one candidate atom, computes its
+// B-spline weights in registers and adds its (up to) 64 stencil values that
+// fall inside the brick into its wave's private LDS copy of the brick; the
+// copies are summed in a fixed order. No global atomics, and the result does
+// not depend on scheduling.
 __global__ void __launch_bounds__(kSpreadThreads) k_pme_spread(
     const float4* __restrict__ xs, const int4* __restrict__ brick_zr,
     const int* __restrict__ brick_cols, PmeParams pp, CellGrid cg,
     float* __restrict__ grid_q) {
   __shared__ float lgrid[kSpreadWaves][kMaxBrick];
-  __shared__ float stage[kSpreadWaves][kWave * kStage];
   __shared__ int cand_start[kMaxCandCells];
   __shared__ int cand_off[kMaxCandCells + 1];
+  __shared__ int cand_list[kCandList];
 
   const int brick = blockIdx.x;
   const int bx = brick % pp.nb[0], by = (brick / pp.nb[0]) % pp.nb[1],
             bz = brick / (pp.nb[0] * pp.nb[1]);
-  const int g0[3] = {bx * pp.B[0], by * pp.B[1], bz * pp.B[2]};
-  int beff[3];
-  for (int d = 0; d < 3; ++d) beff[d] = min(pp.B[d], pp.K[d] - g0[d]);
+  const int g0x = bx * pp.B[0], g0y = by * pp.B[1], g0z = bz * pp.B[2];
+  const int bex = min(pp.B[0], pp.K[0] - g0x), bey = min(pp.B[1], pp.K[1] - g0y),
+            bez = min(pp.B[2], pp.K[2] - g0z);
   // candidate columns (first, count along x and y); the slot ranges inside
   // each column that reach this brick layer come from the list build
   const int* bcx = brick_cols + 2 * bx;
@@ -91,72 +108,64 @@ __global__ void __launch_bounds__(kSpreadThreads) k_pme_spread(
   }
   __syncthreads();
   const int total = cand_off[ncand];
-  const int t1 = lane >> 4, t2 = (lane >> 2) & 3, t3 = lane & 3;   // x, y, z stencil offsets
+  if (total <= kCandList) {
+    for (int t = threadIdx.x; t < ncand; t += blockDim.x) {
+      const int b = cand_off[t], e = cand_off[t + 1], s0 = cand_start[t];
+      for (int k = b; k < e; ++k) cand_list[k] = s0 + (k - b);
+    }
+    __syncthreads();
+  }
   float* my_grid = lgrid[w];
-  float* my_stage = stage[w];
+  const int plane = pp.B[0] * pp.B[1] + 2;
 
   for (int ch = w; ch * kWave < total; ch += kSpreadWaves) {
-    int f = ch * kWave + lane;
-    bool touch = false;
-    if (f < total) {
-      int lo = 0, hi = ncand - 1;             // last cell with cand_off <= f
-      while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (cand_off[mid] <= f) lo = mid; else hi = mid - 1;
-      }
-      int j = cand_start[lo] + (f - cand_off[lo]);
-      float4 p = xs[j];
-      float xyz[3] = {p.x, p.y, p.z};
-      touch = true;
-      float* st = my_stage + lane * kStage;
-      for (int d = 0; d < 3; ++d) {
-        int k0;
-        float fr;
-        grid_coord(xyz[d], pp.s_hi[d], pp.s_lo[d], pp.K[d], k0, fr);
-        int delta = k0 - g0[d];
-        if (delta < 0) delta += pp.K[d];
-        touch = touch && (delta <= beff[d] + 2 || beff[d] + 3 > pp.K[d]);
-        float th[4], dth[4];
-        spline4(fr, th, dth);
-        st[4 * d + 0] = th[0];
-        st[4 * d + 1] = th[1];
-        st[4 * d + 2] = th[2];
-        st[4 * d + 3] = th[3];
-        st[12 + d] = __int_as_float(delta);
-      }
-      st[15] = p.w;
-    }
-    unsigned long long mask = __ballot(touch);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    while (mask) {
-      int m = __ffsll((long long)mask) - 1;
-      mask &= mask - 1;
-      const float* st = my_stage + m * kStage;
-      int lx = __float_as_int(st[12]) - t1;
-      int ly = __float_as_int(st[13]) - t2;
-      int lz = __float_as_int(st[14]) - t3;
+    const int f = ch * kWave + lane;
+    if (f >= total) continue;
+    const float4 p = xs[spread_candidate(f, total, ncand, cand_list, cand_start, cand_off)];
+    int kx, ky, kz;
+    float fx, fy, fz;
+    grid_coord(p.x, pp.s_hi[0], pp.s_lo[0], pp.K[0], kx, fx);
+    grid_coord(p.y, pp.s_hi[1], pp.s_lo[1], pp.K[1], ky, fy);
+    grid_coord(p.z, pp.s_hi[2], pp.s_lo[2], pp.K[2], kz, fz);
+    // stencil point t sits at k0 - t; its brick-local offset is k0 - g0 - t
+    int dx = kx - g0x, dy = ky - g0y, dz = kz - g0z;
+    if (dx < 0) dx += pp.K[0];
+    if (dy < 0) dy += pp.K[1];
+    if (dz < 0) dz += pp.K[2];
+    float tx[4], ty[4], tz[4], dummy[4];
+    spline4(fx, tx, dummy);
+    spline4(fy, ty, dummy);
+    spline4(fz, tz, dummy);
+#pragma unroll
+    for (int t1 = 0; t1 < 4; ++t1) {
+      int lx = dx - t1;
       if (lx < 0) lx += pp.K[0];
-      if (ly < 0) ly += pp.K[1];
-      if (lz < 0) lz += pp.K[2];
-      if (lx < beff[0] && ly < beff[1] && lz < beff[2]) {
-        float v = st[15] * st[t1] * st[4 + t2] * st[8 + t3];
-        atomicAdd(&my_grid[brick_index(lx, ly, lz, pp)], v);
+      if (lx >= bex) continue;
+      const float wx = p.w * tx[t1];
+#pragma unroll
+      for (int t2 = 0; t2 < 4; ++t2) {
+        int ly = dy - t2;
+        if (ly < 0) ly += pp.K[1];
+        if (ly >= bey) continue;
+        const float wxy = wx * ty[t2];
+        float* row = my_grid + ly * pp.B[0] + lx;
+#pragma unroll
+        for (int t3 = 0; t3 < 4; ++t3) {
+          int lz = dz - t3;
+          if (lz < 0) lz += pp.K[2];
+          if (lz < bez) atomicAdd(row + lz * plane, wxy * tz[t3]);
+        }
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   __syncthreads();
-  const int nloc = beff[0] * beff[1] * beff[2];
+  const int nloc = bex * bey * bez;
   for (int t = threadIdx.x; t < nloc; t += blockDim.x) {
-    int lx = t % beff[0], ly = (t / beff[0]) % beff[1], lz = t / (beff[0] * beff[1]);
+    int lx = t % bex, ly = (t / bex) % bey, lz = t / (bex * bey);
     int li = brick_index(lx, ly, lz, pp);
     float s = lgrid[0][li];
     for (int c = 1; c < kSpreadWaves; ++c) s += lgrid[c][li];
-    grid_q[((size_t)(g0[2] + lz) * pp.K[1] + (g0[1] + ly)) * pp.K[0] + g0[0] + lx] = s;
+    grid_q[((size_t)(g0z + lz) * pp.K[1] + (g0y + ly)) * pp.K[0] + g0x + lx] = s;
   }
 }
 

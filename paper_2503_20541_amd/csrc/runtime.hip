@@ -18,7 +18,7 @@ struct mdx_ctx {
   mdx::Ctx c;
   std::vector<void*> allocs;
   // event pairs per timing group, reused across recordings
-  bool timing = false;
+  unsigned timing = 0;   // bit g: record group g
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];
   size_t used[3] = {0, 0, 0};
   // second stream for the PME potential inside mdx_integrate_step, forked
@@ -212,7 +212,7 @@ int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
     if (d->atom_type[i] < 0 || d->atom_type[i] >= d->n_types) return MDX_E_INVALID;
     if (!(d->mass[i] > 0.f)) return MDX_E_INVALID;
   }
-  if (d->options & ~MDX_OPT_HALF_LIST) return MDX_E_INVALID;
+  if (d->options & ~(MDX_OPT_HALF_LIST | MDX_OPT_COOPERATIVE_BUILD)) return MDX_E_INVALID;
   const int cdiv = d->cell_divisions == 0 ? 2 : d->cell_divisions;
   if (cdiv < 1 || cdiv > 4) return MDX_E_INVALID;
   if (d->switch_r > 0.f && !(d->switch_r < d->r_cut)) return MDX_E_INVALID;
@@ -274,6 +274,9 @@ int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
   c.max_slots = n + (mdx::kClusterSize - 1) * g.ncell;
   c.max_slots = (c.max_slots + mdx::kClusterSize - 1) / mdx::kClusterSize * mdx::kClusterSize;
   c.max_clusters = c.max_slots / mdx::kClusterSize;
+  c.coop_blocks = (d->options & MDX_OPT_COOPERATIVE_BUILD)
+                      ? mdx::build_coop_blocks(c.max_clusters, n, g.ncell)
+                      : 0;
 
   // ---- per-atom parameters and the LJ type-pair table (Eqs. 4-5) ----
   std::vector<float> q(n), am(n), ms(n);
@@ -413,7 +416,8 @@ int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
     if ((rc = setup_pme(x, d)) != MDX_OK) return rc;
   }
   // ---- reductions ----
-  int mb = std::max((n + 255) / 256, (c.max_clusters + 3) / 4);
+  // partial rows hold one entry per block of the widest energy kernel
+  int mb = std::max({(n + 255) / 256, (c.max_clusters + 3) / 4, (c.max_slots * 4 + 255) / 256});
   if (c.has_pme) {
     int ntile = (c.pg.Kxh + 15) / 16;
     mb = std::max(mb, c.pg.K[1] * ntile);
@@ -433,7 +437,7 @@ constexpr size_t kMaxTimed = 8192;
 // Records an event pair around the launches made by `fn` when timing is on.
 template <typename F>
 hipError_t timed(mdx_ctx* x, int group, hipStream_t stream, F&& fn) {
-  if (!x->timing || x->used[group] >= kMaxTimed) return fn();
+  if (!((x->timing >> group) & 1u) || x->used[group] >= kMaxTimed) return fn();
   auto& v = x->ev[group];
   if (x->used[group] == v.size()) {
     hipEvent_t a, b;
@@ -742,11 +746,11 @@ int mdx_get_info(mdx_ctx* x, mdx_info* info) {
   return MDX_OK;
 }
 
-int mdx_set_timing(mdx_ctx* x, int enable) {
-  if (check_ctx(x)) return MDX_E_INVALID;
-  x->timing = enable != 0;
-  if (x->timing)
-    for (auto& u : x->used) u = 0;
+int mdx_set_timing(mdx_ctx* x, int groups) {
+  if (check_ctx(x) || groups < 0 || groups > 7) return MDX_E_INVALID;
+  x->timing = (unsigned)groups;
+  for (int g = 0; g < 3; ++g)
+    if ((x->timing >> g) & 1u) x->used[g] = 0;
   return MDX_OK;
 }
 

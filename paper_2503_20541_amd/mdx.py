@@ -50,6 +50,7 @@ MDX_ENERGY_KINETIC = 7
 MDX_N_ENERGY = 8
 
 MDX_OPT_HALF_LIST = 0x1
+MDX_OPT_COOPERATIVE_BUILD = 0x2
 
 MDX_TIMING_PAIR = 0
 MDX_TIMING_PME = 1
@@ -277,8 +278,10 @@ def get_info(ctx: int) -> Info:
     return info
 
 
-def set_timing(ctx: int, enable: bool) -> None:
-    _check(_lib.mdx_set_timing(ctx, 1 if enable else 0), "mdx_set_timing")
+def set_timing(ctx: int, groups) -> None:
+    """groups: True (all groups), False (none), or a bit mask of 1 << MDX_TIMING_*."""
+    mask = 7 if groups is True else (0 if groups is False else int(groups))
+    _check(_lib.mdx_set_timing(ctx, mask), "mdx_set_timing")
 
 
 def get_timing(ctx: int, group: int):

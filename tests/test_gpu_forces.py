@@ -140,3 +140,44 @@ def test_total_force_water9k():
     assert rel_rms(F, nb["F"] + rec["F"]) < F_TOL
     Et = nb["E"].sum() + rec["E"]
     assert abs(E.sum() - Et) <= E_TOL * abs(Et)
+
+
+def test_water96k_full_size_sampled_forces_and_energies():
+    # The benchmark's 96,000-atom box at full size, against FP64 oracle values
+    # stored by tests/golden/make_w96k_forces.py: all energy components, and
+    # the total force on 600 sampled atoms.
+    import json
+    import os
+    import torch
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "w96k_forces.json")))
+    s = synth.config_system("water96k")
+    announce("water96k full size")
+    with gpu_context(s) as (mdx, ctx, t):
+        mdx.build_neighbors(ctx, t["pos"])
+        mdx.compute_nonbonded(ctx, t["pos"], t["force"], t["e_nb"])
+        mdx.compute_pme(ctx, t["pos"], t["force"], t["e_rec"])
+        torch.cuda.synchronize()
+        assert mdx.get_status(ctx) == 0
+        F = t["force"].cpu().numpy().astype(np.float64)
+        E = np.concatenate([t["e_nb"].cpu().numpy(), t["e_rec"].cpu().numpy()])
+        # one step of the benchmark's path (list build in one cooperative
+        # launch, PME on the second stream, fused closing kernel): the force it
+        # leaves behind equals a fresh evaluation at the new positions
+        mdx.integrate_step(ctx, t["pos"], t["vel"], t["force"], 1, s.dt)
+        torch.cuda.synchronize()
+        F_step = t["force"].cpu().numpy().astype(np.float64)
+        f2 = torch.zeros_like(t["force"])
+        mdx.compute_nonbonded(ctx, t["pos"], f2)
+        mdx.compute_pme(ctx, t["pos"], f2)
+        torch.cuda.synchronize()
+        F_fresh = f2.cpu().numpy().astype(np.float64)
+        assert mdx.get_status(ctx) == 0
+    sample = np.array(gold["sample"])
+    Fref = np.array(gold["forces"]).T
+    assert rel_rms(F[:, sample], Fref) < F_TOL
+    Eref = np.array(gold["energies"])
+    scale = abs(Eref.sum())
+    for k in range(len(Eref)):
+        assert abs(E[k] - Eref[k]) <= E_TOL * max(abs(Eref[k]), scale), (k, E[k], Eref[k])
+    assert abs(E.sum() - Eref.sum()) <= E_TOL * scale, (E.sum(), Eref.sum())
+    assert rel_rms(F_step, F_fresh) < 1e-6

@@ -13,7 +13,7 @@ def _oracle_pairs(s):
     return neighbors.tree_pairs(s.pos, s.box, s.r_cut, s.r_ghost, s.exclusions)
 
 
-@pytest.mark.parametrize("options", [0, 1], ids=["full", "half"])
+@pytest.mark.parametrize("options", [0, 1, 2], ids=["full", "half", "cooperative-build"])
 @pytest.mark.parametrize("name", ["lj1k", "water375", "water9k"])
 def test_list_exact(name, options):
     s = synth.config_system(name)
@@ -29,7 +29,7 @@ def test_list_exact(name, options):
     assert np.array_equal(got, ref)
     # every pair is held from both ends (full list, the default) or once
     # (MDX_OPT_HALF_LIST); tiles come in groups of four
-    assert info.n_list_entries == (1 if options else 2) * len(ref)
+    assert info.n_list_entries == (1 if options & 1 else 2) * len(ref)
     assert info.n_builds == 1
     assert info.n_list_tiles % 4 == 0 and 16 * info.n_list_tiles >= info.n_list_entries
 
