@@ -240,11 +240,10 @@ int mdx_compute_pme(mdx_ctx* ctx, const float* pos, float* force, double* energy
  * holds F(pos) on exit. The list is rebuilt every rebuild_every steps, and
  * also on any step where an atom has moved more than r_g/2 since the last
  * build (tested every step on the device; no host synchronisation). The
- * number of builds is reported by mdx_get_info. Inside a step the PME
- * potential (spread, FFTs) runs on a library-owned second stream,
- * concurrently with the pair kernel; it is forked from and joined back into
- * the context's stream, so the call is ordered on that stream like any
- * other work. energies, if not
+ * number of builds is reported by mdx_get_info. Inside a step the PME FFT
+ * passes run on a library-owned second stream, concurrently with the pair
+ * kernel; they are forked from and joined back into the context's stream,
+ * so the call is ordered on that stream like any other work. energies, if not
  * NULL, is dev double[n_steps][MDX_N_ENERGY]: all slots after each step.
  */
 int mdx_integrate_step(mdx_ctx* ctx, float* pos, float* vel, float* force, int32_t n_steps,
@@ -261,8 +260,8 @@ int mdx_get_info(mdx_ctx* ctx, mdx_info* info);
  * Kernel timing with HIP events recorded around the launches of a kernel
  * group, on the stream the group runs on. Groups: MDX_TIMING_PAIR (the
  * short-range pair kernel), MDX_TIMING_PME (spread .. gather in
- * mdx_compute_pme; spread .. last FFT pass, on the second stream, in
- * mdx_integrate_step, where it overlaps the pair kernel), MDX_TIMING_BUILD
+ * mdx_compute_pme; in mdx_integrate_step from the spread to the last FFT
+ * pass on the second stream, which overlaps the pair kernel), MDX_TIMING_BUILD
  * (list build). mdx_set_timing(ctx, groups) takes a bit mask of groups
  * (bit MDX_TIMING_x set = record group x; 0 stops all): it clears the
  * earlier records of the groups it enables and records at most 8192

@@ -85,7 +85,8 @@ struct Ctx {
   int* cell_start = nullptr;   // [ncol + 1] first atom (unpadded) of each column
   int* cell_cursor = nullptr;  // [ncol]
   int* slot_start = nullptr;   // [ncol + 1] first slot of each column (padded to clusters)
-  int* meta = nullptr;         // [3] slots, clusters of the last build; builds so far
+  int* meta = nullptr;         // [4] slots, clusters of the last build; builds so far;
+                               // blocks done binning (the last one scans, then clears it)
   int* perm_unsorted = nullptr;// [n]
   int* perm = nullptr;         // [max_slots] slot -> caller atom, -1 for padding
   int* inv_perm = nullptr;     // [n] caller atom -> slot
@@ -152,7 +153,8 @@ hipError_t launch_begin_step(Ctx& c, float* pos, float* vel, const float* force,
 hipError_t launch_finish_step(Ctx& c, const float* pos, float* vel, float* force, float dt,
                               bool energy);
 // Spread + FFT passes only (the potential grid), for the fused closing kernel.
-hipError_t launch_pme_potential(Ctx& c, hipStream_t s);
+hipError_t launch_pme_spread(Ctx& c, hipStream_t s);
+hipError_t launch_pme_fft(Ctx& c, hipStream_t s);
 
 // Device helpers shared by kernels -------------------------------------------
 

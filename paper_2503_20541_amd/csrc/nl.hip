@@ -17,9 +17,10 @@
 //
 // Build phases (gated: with a gate they do nothing unless it is raised):
 //   bin (column of every atom, counts) -> scan (atom and padded-slot offsets
-//   per column) -> scatter -> column sort (rank by z, write slot data) ->
-//   cluster boxes (and the PME spreading's column ranges) -> tile search
-//   (one wave per i-cluster). By default each phase is one kernel;
+//   per column) -> scatter -> column sort (rank by z, write slot data), then
+//   the column's cluster boxes and PME spreading ranges -> tile search (one
+//   wave per i-cluster). By default these are four kernels (the last block
+//   to finish binning runs the scan);
 //   k_build_all runs them all in one cooperative launch with grid-wide
 //   barriers between phases (optional: cooperative launches use a separate
 //   hardware queue, and the resident grid is smaller than the per-phase
@@ -174,9 +175,11 @@ __device__ void scan_columns(const BuildArgs& a) {
   int chunk = (ncol + blockDim.x - 1) / blockDim.x;
   int b = t * chunk, e = min(b + chunk, ncol);
   int s = 0, sp = 0;
+  // the counts were formed by other blocks' atomics: read them at device scope
   for (int i = b; i < e; ++i) {
-    s += count[i];
-    sp += (count[i] + kClusterSize - 1) / kClusterSize * kClusterSize;
+    const int ci = __hip_atomic_load(&count[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s += ci;
+    sp += (ci + kClusterSize - 1) / kClusterSize * kClusterSize;
   }
   int lane = t & (kWave - 1), w = t / kWave;
   int v = s, vp = sp;
@@ -213,7 +216,7 @@ __device__ void scan_columns(const BuildArgs& a) {
   int run = wave_tot[0][w] + v - s;
   int runp = wave_tot[1][w] + vp - sp;
   for (int i = b; i < e; ++i) {
-    const int ci = count[i];
+    const int ci = __hip_atomic_load(&count[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     a.col_start[i] = run;
     a.cursor[i] = run;
     a.slot_start[i] = runp;
@@ -287,6 +290,19 @@ __device__ void sort_column(const BuildArgs& a, int c, float2* st) {
     a.ts[s] = 0;
     a.zb[s] = 3.0e38f;
   }
+}
+
+__device__ void cluster_box(const BuildArgs& a, int c);
+
+// Column c's sort, then (reading back what this block just wrote, ordered by
+// the block barrier) the bounding boxes of its clusters and its slot ranges
+// for every PME brick layer.
+__device__ void sort_column_boxes(const BuildArgs& a, int c, float2* st) {
+  sort_column(a, c, st);
+  __syncthreads();
+  const int c0 = a.slot_start[c] / kClusterSize, c1 = a.slot_start[c + 1] / kClusterSize;
+  for (int k = c0 + (int)threadIdx.x; k < c1; k += blockDim.x) cluster_box(a, k);
+  for (int l = threadIdx.x; l < a.zr.layers; l += blockDim.x) column_zrange(l * a.zr.ncol + c, a.zr);
 }
 
 // Bounding box of cluster c's real atoms at the build positions.
@@ -548,14 +564,19 @@ __device__ void search_cluster(const BuildArgs& a, int ic, int* mycand, int* seg
 }
 
 // ---- one kernel per phase ---------------------------------------------------
-__global__ void k_bin(BuildArgs a) {
+// Binning; the last block to finish (counted in meta[3]) runs the scan.
+__global__ void __launch_bounds__(256) k_bin_scan(BuildArgs a) {
   if (gated_off(a.gate)) return;
+  __shared__ int last;
   bin_atom(a, blockIdx.x * blockDim.x + threadIdx.x);
-}
-
-__global__ void __launch_bounds__(1024) k_scan(BuildArgs a) {
-  if (gated_off(a.gate)) return;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(&a.meta[3], 1) == (int)gridDim.x - 1;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
   scan_columns(a);
+  if (threadIdx.x == 0) a.meta[3] = 0;
 }
 
 __global__ void k_scatter(BuildArgs a) {
@@ -566,15 +587,7 @@ __global__ void k_scatter(BuildArgs a) {
 __global__ void __launch_bounds__(kColThreads) k_col_sort(BuildArgs a) {
   if (gated_off(a.gate)) return;
   __shared__ float2 st[kColStage];   // (build z, atom index bits)
-  sort_column(a, blockIdx.x, st);
-}
-
-// Cluster boxes; threads past the clusters fill the PME column ranges.
-__global__ void k_cluster_box(BuildArgs a) {
-  if (gated_off(a.gate)) return;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < a.max_clusters) cluster_box(a, e);
-  else if (e - a.max_clusters < a.zr.layers * a.zr.ncol) column_zrange(e - a.max_clusters, a.zr);
+  sort_column_boxes(a, blockIdx.x, st);
 }
 
 __global__ void __launch_bounds__(256) k_tile_search(BuildArgs a) {
@@ -609,13 +622,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_build_all(BuildArgs a) {
   grid.sync();
   for (int i = tid; i < nround; i += nthreads) scatter_atom(a, i);
   grid.sync();
-  for (int c = blockIdx.x; c < a.cg.ncell; c += gridDim.x) sort_column(a, c, st);
-  grid.sync();
-  const int nz = a.zr.layers * a.zr.ncol;
-  for (int e = tid; e < a.max_clusters + nz; e += nthreads) {
-    if (e < a.max_clusters) cluster_box(a, e);
-    else column_zrange(e - a.max_clusters, a.zr);
-  }
+  for (int c = blockIdx.x; c < a.cg.ncell; c += gridDim.x) sort_column_boxes(a, c, st);
   grid.sync();
   const int w = threadIdx.x / kWave;
   for (int ic = blockIdx.x * 4 + w; ic < a.max_clusters; ic += gridDim.x * 4)
@@ -680,12 +687,9 @@ hipError_t launch_build_list(Ctx& c, const float* pos, const int* gate) {
                                       dim3(c.coop_blocks), dim3(kBuildThreads), args, 0, s);
   }
   const int nb = (n + 255) / 256;
-  k_bin<<<nb, 256, 0, s>>>(a);
-  k_scan<<<1, 1024, 0, s>>>(a);
+  k_bin_scan<<<nb, 256, 0, s>>>(a);
   k_scatter<<<nb, 256, 0, s>>>(a);
   k_col_sort<<<ncol, kColThreads, 0, s>>>(a);
-  const int nz = a.zr.layers * ncol;
-  k_cluster_box<<<(c.max_clusters + nz + 255) / 256, 256, 0, s>>>(a);
   k_tile_search<<<(c.max_clusters + 3) / 4, 256, 0, s>>>(a);
   return hipGetLastError();
 }

@@ -584,13 +584,19 @@ PmeParams make_pme_params(const Ctx& c) {
   return pp;
 }
 
-// Spread and the five FFT passes (forward transform, influence multiply with
-// the energy partials, inverse) on stream s: leaves the potential in grid_phi.
-hipError_t launch_pme_potential(Ctx& c, hipStream_t s) {
+// Charge spreading onto grid_q on stream s.
+hipError_t launch_pme_spread(Ctx& c, hipStream_t s) {
+  const PmeParams pp = make_pme_params(c);
+  k_pme_spread<<<c.pg.nbrick, kSpreadThreads, 0, s>>>(c.xs, c.brick_zr, c.brick_cols, pp, c.cg,
+                                                      c.grid_q);
+  return hipGetLastError();
+}
+
+// The five FFT passes (forward transform, influence multiply with the energy
+// partials, inverse) on stream s: grid_q -> potential in grid_phi.
+hipError_t launch_pme_fft(Ctx& c, hipStream_t s) {
   const PmeGrid& g = c.pg;
   const PmeParams pp = make_pme_params(c);
-  k_pme_spread<<<g.nbrick, kSpreadThreads, 0, s>>>(c.xs, c.brick_zr, c.brick_cols, pp, c.cg,
-                                                   c.grid_q);
   FftPlan px = make_plan(g.K[0]), py = make_plan(g.K[1]), pz = make_plan(g.K[2]);
   const int rows = g.K[1] * g.K[2];
   const int P = pencils_for(g.K[0]);
@@ -611,7 +617,8 @@ hipError_t launch_pme_potential(Ctx& c, hipStream_t s) {
 
 hipError_t launch_pme(Ctx& c, float* force, bool energy) {
   (void)energy;   // the z pass always writes its energy partials
-  hipError_t e = launch_pme_potential(c, c.stream);
+  hipError_t e = launch_pme_spread(c, c.stream);
+  if (e == hipSuccess) e = launch_pme_fft(c, c.stream);
   if (e != hipSuccess) return e;
   const PmeParams pp = make_pme_params(c);
   k_pme_gather<<<(c.max_slots + 255) / 256, 256, 0, c.stream>>>(c.xs, c.perm, c.meta, c.grid_phi,

@@ -388,8 +388,8 @@ int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
   if ((rc = dev_alloc(x, &c.cell_start, ncol + 1)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.cell_cursor, ncol)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.slot_start, ncol + 1)) != MDX_OK) return rc;
-  if ((rc = dev_alloc(x, &c.meta, 3)) != MDX_OK) return rc;
-  MDX_TRY(hipMemset(c.meta, 0, 3 * sizeof(int)));
+  if ((rc = dev_alloc(x, &c.meta, 4)) != MDX_OK) return rc;
+  MDX_TRY(hipMemset(c.meta, 0, 4 * sizeof(int)));
   if ((rc = dev_alloc(x, &c.perm_unsorted, n)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.perm, c.max_slots)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.inv_perm, n)) != MDX_OK) return rc;
@@ -435,9 +435,13 @@ int check_ctx(mdx_ctx* x) { return x ? MDX_OK : MDX_E_INVALID; }
 constexpr size_t kMaxTimed = 8192;
 
 // Records an event pair around the launches made by `fn` when timing is on.
-template <typename F>
-hipError_t timed(mdx_ctx* x, int group, hipStream_t stream, F&& fn) {
-  if (!((x->timing >> group) & 1u) || x->used[group] >= kMaxTimed) return fn();
+// Starts a timed interval of `group` on `stream` (no-op unless the group is
+// recorded); *slot receives the event pair to close with timing_end, or
+// nullptr.
+hipError_t timing_begin(mdx_ctx* x, int group, hipStream_t stream,
+                        std::pair<hipEvent_t, hipEvent_t>** slot) {
+  *slot = nullptr;
+  if (!((x->timing >> group) & 1u) || x->used[group] >= kMaxTimed) return hipSuccess;
   auto& v = x->ev[group];
   if (x->used[group] == v.size()) {
     hipEvent_t a, b;
@@ -446,11 +450,21 @@ hipError_t timed(mdx_ctx* x, int group, hipStream_t stream, F&& fn) {
     if ((e = hipEventCreate(&b)) != hipSuccess) return e;
     v.push_back({a, b});
   }
-  auto& p = v[x->used[group]++];
-  hipError_t e = hipEventRecord(p.first, stream);
+  *slot = &v[x->used[group]++];
+  return hipEventRecord((*slot)->first, stream);
+}
+
+hipError_t timing_end(std::pair<hipEvent_t, hipEvent_t>* slot, hipStream_t stream) {
+  return slot ? hipEventRecord(slot->second, stream) : hipSuccess;
+}
+
+template <typename F>
+hipError_t timed(mdx_ctx* x, int group, hipStream_t stream, F&& fn) {
+  std::pair<hipEvent_t, hipEvent_t>* slot;
+  hipError_t e = timing_begin(x, group, stream, &slot);
   if (e != hipSuccess) return e;
   if ((e = fn()) != hipSuccess) return e;
-  return hipEventRecord(p.second, stream);
+  return timing_end(slot, stream);
 }
 
 }  // namespace
@@ -672,13 +686,17 @@ int mdx_integrate_step(mdx_ctx* x, float* pos, float* vel, float* force, int32_t
     MDX_TRY(mdx::launch_begin_step(c, pos, vel, force, dt, gate_now, gate_next, cadence));
     MDX_TRY(timed(x, MDX_TIMING_BUILD, c.stream, [&] { return mdx::launch_build_list(c, pos, gate_now); }));
     // The reciprocal-space potential only needs this step's slot positions:
-    // it runs on the second stream, concurrently with the pair kernel, and
-    // the closing kernel (force interpolation) waits for it.
+    // the charges are spread on the context's stream, the FFT passes run on
+    // the second stream concurrently with the pair kernel, and the closing
+    // kernel (force interpolation) waits for them.
     if (c.has_pme) {
+      std::pair<hipEvent_t, hipEvent_t>* tslot;
+      MDX_TRY(timing_begin(x, MDX_TIMING_PME, c.stream, &tslot));
+      MDX_TRY(mdx::launch_pme_spread(c, c.stream));
       MDX_TRY(hipEventRecord(x->ev_fork, c.stream));
       MDX_TRY(hipStreamWaitEvent(x->aux, x->ev_fork, 0));
-      MDX_TRY(timed(x, MDX_TIMING_PME, x->aux,
-                    [&] { return mdx::launch_pme_potential(c, x->aux); }));
+      MDX_TRY(mdx::launch_pme_fft(c, x->aux));
+      MDX_TRY(timing_end(tslot, x->aux));
       MDX_TRY(hipEventRecord(x->ev_join, x->aux));
     }
     MDX_TRY(timed(x, MDX_TIMING_PAIR, c.stream, [&] { return mdx::launch_nonbonded(c, e); }));
