@@ -75,7 +75,8 @@ typedef struct mdx_ctx mdx_ctx;
  * System description (all pointers host, read during mdx_create only).
  *
  * Atoms: charge, mass, atom_type [n_atoms]; per-type LJ sigma/epsilon
- * [n_types] (Lorentz-Berthelot mixing, Eq. 5). Topology index arrays use
+ * [n_types] (Lorentz-Berthelot mixing, Eq. 5; n_types <= 32, more is
+ * MDX_E_UNSUPPORTED). Topology index arrays use
  * the caller's atom order: exclusions [n_exclusions][2] (any order,
  * duplicates ignored), bonds [n_bonds][2] with bond_k, bond_r0, angles
  * [n_angles][3] as (end, vertex, end) with angle_k, angle_theta0 (radians).

@@ -11,7 +11,8 @@
 namespace mdx {
 
 constexpr int kWave = 64;
-constexpr int kClusterSize = 4;     // atoms per cluster (slots per tile side)
+constexpr int kClusterSize = 4;
+constexpr int kMaxLjTypes = 32;   // LJ atom types (the pair kernel keeps the type-pair table in LDS)     // atoms per cluster (slots per tile side)
 
 // Indices into the FP64 partial-sum rows written by force kernels.
 enum PartialRow { kRowLJ = 0, kRowDir, kRowExcl, kRowBond, kRowAngle, kRowRec, kRowKin, kRowCount };
@@ -26,6 +27,8 @@ struct CellGrid {
   float rnl2;        // fl(r_nl * r_nl)
   float rc2;         // fl(r_c * r_c)
   float r_search;    // cluster-box distance below which a tile is tested
+  int nzb;           // z bins of the per-column cluster lookup tables
+  float inv_zb;      // nzb / L_z
 };
 
 struct PmeGrid {
@@ -90,6 +93,8 @@ struct Ctx {
   int* perm_unsorted = nullptr;// [n]
   int* perm = nullptr;         // [max_slots] slot -> caller atom, -1 for padding
   int* inv_perm = nullptr;     // [n] caller atom -> slot
+  int2* zbin = nullptr;        // [columns][nzb + 1] first cluster with max z >= bin z, first
+                               // cluster with min z > bin z (per build)
   float4* xs = nullptr;        // [max_slots] (x, y, z, q) at the current positions
   float* fslot = nullptr;      // [3][max_slots] pair forces by slot; all zero between
                                // a force evaluation's consumer and the next pair kernel

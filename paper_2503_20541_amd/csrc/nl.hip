@@ -135,6 +135,7 @@ struct BuildArgs {
   const int* ex_idx;
   int cap;
   int half;
+  int2* zbin;
   uint2* tiles;
   int* tile_count;
   int max_clusters;
@@ -293,6 +294,8 @@ __device__ void sort_column(const BuildArgs& a, int c, float2* st) {
 }
 
 __device__ void cluster_box(const BuildArgs& a, int c);
+__device__ __forceinline__ int first_ge(const float4* __restrict__ b, int lo, int hi, float x);
+__device__ __forceinline__ int first_gt(const float4* __restrict__ b, int lo, int hi, float x);
 
 // Column c's sort, then (reading back what this block just wrote, ordered by
 // the block barrier) the bounding boxes of its clusters and its slot ranges
@@ -303,6 +306,16 @@ __device__ void sort_column_boxes(const BuildArgs& a, int c, float2* st) {
   const int c0 = a.slot_start[c] / kClusterSize, c1 = a.slot_start[c + 1] / kClusterSize;
   for (int k = c0 + (int)threadIdx.x; k < c1; k += blockDim.x) cluster_box(a, k);
   for (int l = threadIdx.x; l < a.zr.layers; l += blockDim.x) column_zrange(l * a.zr.ncol + c, a.zr);
+  __syncthreads();
+  // lookup table of the column's z-sorted clusters: for bin edge z_b = b L/nzb
+  // the first cluster whose max z >= z_b and the first whose min z > z_b
+  const int nzb = a.cg.nzb;
+  int2* zt = a.zbin + (size_t)c * (nzb + 1);
+  for (int b = threadIdx.x; b <= nzb; b += blockDim.x) {
+    const float zb = (float)b / a.cg.inv_zb;
+    const int f = first_ge(a.box_hi, c0, c1, zb);
+    zt[b] = make_int2(f, first_gt(a.box_lo, f, c1, zb));
+  }
 }
 
 // Bounding box of cluster c's real atoms at the build positions.
@@ -415,15 +428,22 @@ __device__ void search_cluster(const BuildArgs& a, int ic, int* mycand, int* seg
         x %= a.cg.n[0]; x += x < 0 ? a.cg.n[0] : 0;
         y %= a.cg.n[1]; y += y < 0 ? a.cg.n[1] : 0;
         int col = y * a.cg.n[0] + x;
-        int c0 = a.slot_start[col] / kClusterSize, c1 = a.slot_start[col + 1] / kClusterSize;
-        // clusters overlapping [sa, sz]: max z >= sa and min z <= sz
-        int f = first_ge(a.box_hi, c0, c1, sa[sg]);
-        int l = first_gt(a.box_lo, f, c1, sz[sg]);
+        // clusters overlapping [sa, sz] (max z >= sa and min z <= sz), from
+        // the column's lookup table one bin wider on each side: a superset,
+        // the box test below removes the extra clusters
+        const int2* zt = a.zbin + (size_t)col * (a.cg.nzb + 1);
+        auto lower = [&](float z) {
+          return min(max((int)floorf(z * a.cg.inv_zb) - 1, 0), a.cg.nzb);
+        };
+        auto upper = [&](float z) {
+          return min(max((int)ceilf(z * a.cg.inv_zb) + 1, 0), a.cg.nzb);
+        };
+        int f = zt[lower(sa[sg])].x;
+        int l = zt[upper(sz[sg])].y;
         if (sg == 1) {
           // the two segments sit at opposite ends of the column; a cluster
           // reaching into both is taken once, by segment 0
-          int f0 = first_ge(a.box_hi, c0, c1, sa[0]);
-          int l0 = first_gt(a.box_lo, f0, c1, sz[0]);
+          const int f0 = zt[lower(sa[0])].x, l0 = zt[upper(sz[0])].y;
           if (sa[1] > sa[0]) f = max(f, l0);
           else l = min(l, f0);
         }
@@ -679,8 +699,8 @@ hipError_t launch_build_list(Ctx& c, const float* pos, const int* gate) {
               c.box_lo, c.box_hi,
               ZRangeArgs{c.zb, c.slot_start, c.cell_start, c.brick_z,
                          c.has_pme ? c.pg.nb[2] : 0, ncol, c.cg.L[2], c.brick_zr},
-              c.ex_start, c.ex_idx, c.nl_cap, c.half_list ? 1 : 0, c.tiles, c.tile_count,
-              c.max_clusters};
+              c.ex_start, c.ex_idx, c.nl_cap, c.half_list ? 1 : 0, c.zbin, c.tiles,
+              c.tile_count, c.max_clusters};
   if (c.coop_blocks > 0) {
     void* args[] = {&a};
     return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_build_all),

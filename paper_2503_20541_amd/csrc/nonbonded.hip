@@ -71,9 +71,8 @@ __device__ __forceinline__ float sum_rows4(float x) {
   return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
-// Type pairs whose LJ coefficients the pair kernel stages in LDS (larger
-// tables are read from global memory).
-constexpr int kLdsTypePairs = 256;
+// The pair kernel stages the LJ type-pair table in LDS (at most
+// kMaxLjTypes^2 type pairs; mdx_create rejects more types).
 
 template <bool ENERGY, bool COUL, bool SWITCH, bool HALF>
 __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
@@ -86,13 +85,14 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
                                               float* __restrict__ fslot, int fstride,
                                               double* __restrict__ partials, int pstride) {
   __shared__ double red[16];
-  __shared__ float4 lj_s[kLdsTypePairs];
-  const bool lds_table = pp.ntypes * pp.ntypes <= kLdsTypePairs;
-  if (lds_table) {
-    for (int t = threadIdx.x; t < pp.ntypes * pp.ntypes; t += blockDim.x) lj_s[t] = lj_f[t];
-    __syncthreads();
-  }
-  const float4* __restrict__ ljt = lds_table ? lj_s : lj_f;
+  __shared__ float4 lj_s[kMaxLjTypes * kMaxLjTypes];
+  // Reserve 80 VGPRs (the clobber marks v79 as used): at most 6 of the 8
+  // wave slots per SIMD go to this kernel, and the PME FFT passes that run
+  // concurrently on the second stream always find room on every CU. The
+  // pair kernel is VALU-bound and loses little at 6 waves per SIMD.
+  asm volatile("" ::: "v79");
+  for (int t = threadIdx.x; t < pp.ntypes * pp.ntypes; t += blockDim.x) lj_s[t] = lj_f[t];
+  __syncthreads();
   const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   const int ic = blockIdx.x * 4 + w;
   const bool active = ic < meta[1];
@@ -114,19 +114,20 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
     // padded to groups of four (the padding tiles point at cluster 0); reads
     // past the list are clamped into its allocation and their cluster index
     // is replaced by 0 before it is used as an address.
-    uint2 e_nx = tl[tt];
-    uint2 e_nx2 = tl[min(4 + tt, cap - 1)];
-    int sj_nx = (cnt > 0 ? (int)e_nx.x : 0) * kClusterSize + jb;
+    // (unsigned 32-bit indices let the loads use a scalar base + 32-bit offset)
+    uint2 e_nx = tl[(unsigned)tt];
+    uint2 e_nx2 = tl[(unsigned)min(4 + tt, cap - 1)];
+    unsigned sj_nx = (cnt > 0 ? e_nx.x : 0u) * kClusterSize + (unsigned)jb;
     float4 pj_nx = xs[sj_nx];
     int tj_nx = ts[sj_nx];
     for (int g = 0; g < cnt; g += 4) {
       const uint2 e = e_nx;
-      const int sj = sj_nx;
+      const unsigned sj = sj_nx;
       const float4 pj = pj_nx;
       const int tj = tj_nx;
       e_nx = e_nx2;
-      e_nx2 = tl[min(g + 8 + tt, cap - 1)];
-      sj_nx = (g + 4 < cnt ? (int)e_nx.x : 0) * kClusterSize + jb;
+      e_nx2 = tl[(unsigned)min(g + 8 + tt, cap - 1)];
+      sj_nx = (g + 4 < cnt ? e_nx.x : 0u) * kClusterSize + (unsigned)jb;
       pj_nx = xs[sj_nx];
       tj_nx = ts[sj_nx];
       const bool on = (e.y >> bitpos) & 1u;
@@ -140,7 +141,7 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
       float gx = 0.f, gy = 0.f, gz = 0.f;   // force on j (minus the force on i)
       if (in) {
         const int tp = trow + tj;
-        float4 lj = ljt[tp];              // c12, c6, 12 c12, 6 c6
+        const float4 lj = lj_s[tp];       // c12, c6, 12 c12, 6 c6
         const float rinv = __builtin_amdgcn_rsqf(r2);   // r2 is never denormal here
         const float rinv2 = rinv * rinv;
         float r6 = rinv2 * rinv2 * rinv2;

@@ -197,6 +197,7 @@ int setup_pme(mdx_ctx* x, const mdx_system_desc* d) {
 int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
   Ctx& c = x->c;
   const int n = d->n_atoms;
+  if (d->n_types > mdx::kMaxLjTypes) return MDX_E_UNSUPPORTED;
   if (n <= 0 || !d->charge || !d->mass || !d->atom_type || d->n_types <= 0 || !d->type_sigma ||
       !d->type_epsilon)
     return MDX_E_INVALID;
@@ -271,6 +272,9 @@ int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
   g.rnl2 = c.r_list * c.r_list;
   g.rc2 = c.r_cut * c.r_cut;
   g.r_search = c.r_list * 1.001f + 1e-4f;
+  // z bins of about half a cluster's height for the tile search's lookups
+  g.nzb = std::max(1, std::min(1024, (int)std::ceil((double)c.box[2] / (0.5 * a_clu))));
+  g.inv_zb = (float)g.nzb / c.box[2];
   c.max_slots = n + (mdx::kClusterSize - 1) * g.ncell;
   c.max_slots = (c.max_slots + mdx::kClusterSize - 1) / mdx::kClusterSize * mdx::kClusterSize;
   c.max_clusters = c.max_slots / mdx::kClusterSize;
@@ -394,6 +398,7 @@ int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
   if ((rc = dev_alloc(x, &c.perm, c.max_slots)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.inv_perm, n)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.xs, c.max_slots)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.zbin, (size_t)ncol * (g.nzb + 1))) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.fslot, (size_t)3 * c.max_slots)) != MDX_OK) return rc;
   MDX_TRY(hipMemset(c.fslot, 0, sizeof(float) * 3 * c.max_slots));
   if ((rc = dev_alloc(x, &c.ts, c.max_slots)) != MDX_OK) return rc;
