@@ -158,8 +158,9 @@ hipError_t launch_begin_step(Ctx& c, float* pos, float* vel, const float* force,
 hipError_t launch_finish_step(Ctx& c, const float* pos, float* vel, float* force, float dt,
                               bool energy);
 // Spread + FFT passes only (the potential grid), for the fused closing kernel.
-hipError_t launch_pme_spread(Ctx& c, hipStream_t s);
-hipError_t launch_pme_fft(Ctx& c, hipStream_t s);
+// `done` (may be null) is recorded by the last kernel's own dispatch.
+hipError_t launch_pme_spread(Ctx& c, hipStream_t s, hipEvent_t done);
+hipError_t launch_pme_fft(Ctx& c, hipStream_t s, hipEvent_t done);
 
 // Device helpers shared by kernels -------------------------------------------
 

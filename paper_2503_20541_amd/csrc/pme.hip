@@ -16,6 +16,8 @@
 // table exp(-2 pi i k/N) computed on the host in double precision.
 #include "atom_terms.h"
 
+#include <hip/hip_ext.h>
+
 namespace mdx {
 
 struct FftPlan {
@@ -525,10 +527,20 @@ static void launch_rows_r2c(int blocks, size_t sh, hipStream_t s, const float* i
                             int rows, int P, int Kxh, const FftPlan& pl, const float2* tw) {
   k_fft_rows_r2c<N><<<blocks, 256, sh, s>>>(in, out, rows, P, Kxh, pl, tw);
 }
+// The last pass may record `done` as part of its own dispatch (no separate
+// marker on the stream).
 template <int N>
 static void launch_rows_c2r(int blocks, size_t sh, hipStream_t s, const float2* in, float* out,
-                            int rows, int P, int Kxh, const FftPlan& pl, const float2* tw) {
-  k_fft_rows_c2r<N><<<blocks, 256, sh, s>>>(in, out, rows, P, Kxh, pl, tw);
+                            int rows, int P, int Kxh, const FftPlan& pl, const float2* tw,
+                            hipEvent_t done) {
+  if (!done) {
+    k_fft_rows_c2r<N><<<blocks, 256, sh, s>>>(in, out, rows, P, Kxh, pl, tw);
+    return;
+  }
+  FftPlan plan = pl;
+  void* args[] = {&in, &out, &rows, &P, &Kxh, &plan, &tw};
+  (void)hipExtLaunchKernel(reinterpret_cast<const void*>(k_fft_rows_c2r<N>), dim3(blocks),
+                           dim3(256), args, sh, s, nullptr, done, 0);
 }
 template <int N, int MODE>
 static void launch_cols(int blocks, size_t sh, hipStream_t s, Ctx& c, const PmeParams& pp, int P,
@@ -548,12 +560,13 @@ static void rows_r2c(int N, int blocks, size_t sh, hipStream_t s, const float* i
   }
 }
 static void rows_c2r(int N, int blocks, size_t sh, hipStream_t s, const float2* in, float* out,
-                     int rows, int P, int Kxh, const FftPlan& pl, const float2* tw) {
+                     int rows, int P, int Kxh, const FftPlan& pl, const float2* tw,
+                     hipEvent_t done) {
   switch (N) {
-#define X(n) case n: launch_rows_c2r<n>(blocks, sh, s, in, out, rows, P, Kxh, pl, tw); return;
+#define X(n) case n: launch_rows_c2r<n>(blocks, sh, s, in, out, rows, P, Kxh, pl, tw, done); return;
     MDX_FFT_SIZES(X)
 #undef X
-    default: launch_rows_c2r<0>(blocks, sh, s, in, out, rows, P, Kxh, pl, tw);
+    default: launch_rows_c2r<0>(blocks, sh, s, in, out, rows, P, Kxh, pl, tw, done);
   }
 }
 template <int MODE>
@@ -584,17 +597,30 @@ PmeParams make_pme_params(const Ctx& c) {
   return pp;
 }
 
-// Charge spreading onto grid_q on stream s.
-hipError_t launch_pme_spread(Ctx& c, hipStream_t s) {
+// Charge spreading onto grid_q on stream s; `done` (if given) is recorded by
+// the kernel's own dispatch when it completes.
+hipError_t launch_pme_spread(Ctx& c, hipStream_t s, hipEvent_t done) {
   const PmeParams pp = make_pme_params(c);
-  k_pme_spread<<<c.pg.nbrick, kSpreadThreads, 0, s>>>(c.xs, c.brick_zr, c.brick_cols, pp, c.cg,
-                                                      c.grid_q);
-  return hipGetLastError();
+  if (!done) {
+    k_pme_spread<<<c.pg.nbrick, kSpreadThreads, 0, s>>>(c.xs, c.brick_zr, c.brick_cols, pp, c.cg,
+                                                        c.grid_q);
+    return hipGetLastError();
+  }
+  const float4* xs = c.xs;
+  const int4* zr = c.brick_zr;
+  const int* bc = c.brick_cols;
+  CellGrid cg = c.cg;
+  float* q = c.grid_q;
+  PmeParams p = pp;
+  void* args[] = {&xs, &zr, &bc, &p, &cg, &q};
+  return hipExtLaunchKernel(reinterpret_cast<const void*>(k_pme_spread), dim3(c.pg.nbrick),
+                            dim3(kSpreadThreads), args, 0, s, nullptr, done, 0);
 }
 
 // The five FFT passes (forward transform, influence multiply with the energy
-// partials, inverse) on stream s: grid_q -> potential in grid_phi.
-hipError_t launch_pme_fft(Ctx& c, hipStream_t s) {
+// partials, inverse) on stream s: grid_q -> potential in grid_phi; `done`
+// (if given) is recorded by the last pass's dispatch.
+hipError_t launch_pme_fft(Ctx& c, hipStream_t s, hipEvent_t done) {
   const PmeGrid& g = c.pg;
   const PmeParams pp = make_pme_params(c);
   FftPlan px = make_plan(g.K[0]), py = make_plan(g.K[1]), pz = make_plan(g.K[2]);
@@ -611,14 +637,14 @@ hipError_t launch_pme_fft(Ctx& c, hipStream_t s) {
   cols<2>(g.K[2], g.K[1] * ntile, shz, s, c, pp, Pc, pz, c.tw[2]);
   c.pme_blocks = g.K[1] * ntile;
   cols<1>(g.K[1], g.K[2] * ntile, shy, s, c, pp, Pc, py, c.tw[1]);
-  rows_c2r(g.K[0], rblocks, sh, s, c.grid_c, c.grid_phi, rows, P, g.Kxh, px, c.tw[0]);
+  rows_c2r(g.K[0], rblocks, sh, s, c.grid_c, c.grid_phi, rows, P, g.Kxh, px, c.tw[0], done);
   return hipGetLastError();
 }
 
 hipError_t launch_pme(Ctx& c, float* force, bool energy) {
   (void)energy;   // the z pass always writes its energy partials
-  hipError_t e = launch_pme_spread(c, c.stream);
-  if (e == hipSuccess) e = launch_pme_fft(c, c.stream);
+  hipError_t e = launch_pme_spread(c, c.stream, nullptr);
+  if (e == hipSuccess) e = launch_pme_fft(c, c.stream, nullptr);
   if (e != hipSuccess) return e;
   const PmeParams pp = make_pme_params(c);
   k_pme_gather<<<(c.max_slots + 255) / 256, 256, 0, c.stream>>>(c.xs, c.perm, c.meta, c.grid_phi,

@@ -503,8 +503,7 @@ int mdx_create(mdx_ctx** out, const mdx_system_desc* d, void* hip_stream) {
   }
   x->c.stream = static_cast<hipStream_t>(hip_stream);
   if (hipStreamCreateWithFlags(&x->aux, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&x->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&x->ev_join, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreate(&x->ev_fork) != hipSuccess || hipEventCreate(&x->ev_join) != hipSuccess) {
     mdx_destroy(x);
     return MDX_E_HIP;
   }
@@ -697,12 +696,13 @@ int mdx_integrate_step(mdx_ctx* x, float* pos, float* vel, float* force, int32_t
     if (c.has_pme) {
       std::pair<hipEvent_t, hipEvent_t>* tslot;
       MDX_TRY(timing_begin(x, MDX_TIMING_PME, c.stream, &tslot));
-      MDX_TRY(mdx::launch_pme_spread(c, c.stream));
-      MDX_TRY(hipEventRecord(x->ev_fork, c.stream));
+      // the fork and join events are recorded by the spread's and the last
+      // FFT pass's own dispatches (no marker packets between kernels)
+      MDX_TRY(mdx::launch_pme_spread(c, c.stream, x->ev_fork));
       MDX_TRY(hipStreamWaitEvent(x->aux, x->ev_fork, 0));
-      MDX_TRY(mdx::launch_pme_fft(c, x->aux));
+      MDX_TRY(mdx::launch_pme_fft(c, x->aux, tslot ? nullptr : x->ev_join));
       MDX_TRY(timing_end(tslot, x->aux));
-      MDX_TRY(hipEventRecord(x->ev_join, x->aux));
+      if (tslot) MDX_TRY(hipEventRecord(x->ev_join, x->aux));
     }
     MDX_TRY(timed(x, MDX_TIMING_PAIR, c.stream, [&] { return mdx::launch_nonbonded(c, e); }));
     if (c.has_pme) MDX_TRY(hipStreamWaitEvent(c.stream, x->ev_join, 0));
