@@ -109,27 +109,9 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
     const uint2* tl = tiles + (size_t)ic * cap;
     // j-force component this lane stores: x, y, z on rows 0-2, none on row 3
     float* const fcomp = fslot + (size_t)(ia < 3 ? ia : 0) * fstride;
-    // Software pipeline: the tiles of the next two groups and the j atoms of
-    // the next group are in flight while a group is computed. Lists are
-    // padded to groups of four (the padding tiles point at cluster 0); reads
-    // past the list are clamped into its allocation and their cluster index
-    // is replaced by 0 before it is used as an address.
-    // (unsigned 32-bit indices let the loads use a scalar base + 32-bit offset)
-    uint2 e_nx = tl[(unsigned)tt];
-    uint2 e_nx2 = tl[(unsigned)min(4 + tt, cap - 1)];
-    unsigned sj_nx = (cnt > 0 ? e_nx.x : 0u) * kClusterSize + (unsigned)jb;
-    float4 pj_nx = xs[sj_nx];
-    int tj_nx = ts[sj_nx];
-    for (int g = 0; g < cnt; g += 4) {
-      const uint2 e = e_nx;
-      const unsigned sj = sj_nx;
-      const float4 pj = pj_nx;
-      const int tj = tj_nx;
-      e_nx = e_nx2;
-      e_nx2 = tl[(unsigned)min(g + 8 + tt, cap - 1)];
-      sj_nx = (g + 4 < cnt ? e_nx.x : 0u) * kClusterSize + (unsigned)jb;
-      pj_nx = xs[sj_nx];
-      tj_nx = ts[sj_nx];
+    // One group of four tiles (e: this lane's tile, sj / pj / tj: its j slot,
+    // position and type).
+    auto group = [&](uint2 e, unsigned sj, float4 pj, int tj) {
       const bool on = (e.y >> bitpos) & 1u;
       float dx = min_image_h(pi.x, lmx, pj.x, pp.L[0], pp.hL[0]);
       float dy = min_image_h(pi.y, lmy, pj.y, pp.L[1], pp.hL[1]);
@@ -137,7 +119,7 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
       float r2 = dist2(dx, dy, dz);
       const bool in = on && r2 < pp.rc2;
       const unsigned long long hit = __ballot(in);
-      if (hit == 0ull) continue;
+      if (hit == 0ull) return;
       float gx = 0.f, gy = 0.f, gz = 0.f;   // force on j (minus the force on i)
       if (in) {
         const int tp = trow + tj;
@@ -196,6 +178,36 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
         if (ia < 3 && ((jhit >> (lane & 15)) & 1u))
           atomicAdd(fcomp + sj, ia == 0 ? gx : (ia == 1 ? gy : gz));
       }
+    };
+    // Software pipeline, two groups per iteration with fixed registers: while
+    // group g is computed the j atoms of group g + 4 are in flight, and the
+    // tiles of the groups after that. Lists are padded to groups of four
+    // (padding tiles point at cluster 0); reads past the list are clamped
+    // into its allocation and their cluster index is replaced by 0 before it
+    // is used as an address. (Unsigned 32-bit indices let the loads use a
+    // scalar base + 32-bit offset.)
+    auto tile_at = [&](int g) { return tl[(unsigned)min(g + tt, cap - 1)]; };
+    auto slot_of = [&](uint2 e, int g) {
+      return (g < cnt ? e.x : 0u) * kClusterSize + (unsigned)jb;
+    };
+    uint2 eA = tile_at(0), eB = tile_at(4);
+    uint2 eA2 = tile_at(8), eB2 = tile_at(12);
+    unsigned sA = slot_of(eA, 0), sB = slot_of(eB, 4);
+    float4 pA = xs[sA], pB = xs[sB];
+    int tA = ts[sA], tB = ts[sB];
+    for (int g = 0; g < cnt; g += 8) {
+      group(eA, sA, pA, tA);
+      eA = eA2;
+      eA2 = tile_at(g + 16);
+      sA = slot_of(eA, g + 8);
+      pA = xs[sA];
+      tA = ts[sA];
+      if (g + 4 < cnt) group(eB, sB, pB, tB);
+      eB = eB2;
+      eB2 = tile_at(g + 20);
+      sB = slot_of(eB, g + 12);
+      pB = xs[sB];
+      tB = ts[sB];
     }
   }
   // sum the i force over the 16 lanes of the row; lanes 0-2 of the row add
