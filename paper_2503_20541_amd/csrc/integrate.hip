@@ -20,19 +20,22 @@ __device__ __forceinline__ float wrap_box(float x, float L) {
 }
 
 // Opening half of a step for every slot: v += (dt/2) a, x += dt v (wrapped),
-// slot position refreshed, r_g/2 validity test (raises gate_now). Thread 0
-// clears the gate of the following step (nothing else touches it here) and
-// raises gate_now on a cadence rebuild.
+// slot position refreshed, r_g/2 validity test (raises gate_now) and the
+// pruned list's validity test (raises pgate_now). Thread 0 clears the flags
+// of the following step (nothing else touches them here) and raises
+// gate_now on a cadence rebuild.
 __global__ void __launch_bounds__(256) k_begin_step(
     float* __restrict__ pos, float* __restrict__ vel, const float* __restrict__ force,
     const float* __restrict__ acc_over_m, const int* __restrict__ perm,
     const float* __restrict__ q, const float* __restrict__ x_build, const int* __restrict__ meta,
     int n, CellGrid cg, float half_dt, float dt, float half_skin2, float4* __restrict__ xs,
     unsigned* __restrict__ flags, int* __restrict__ gate_now, int* __restrict__ gate_next,
-    int force_rebuild) {
+    const float4* __restrict__ xp, float prune_move2, int* __restrict__ pgate_now,
+    int* __restrict__ pgate_next, int force_rebuild) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s == 0) {
     *gate_next = 0;
+    *pgate_next = 0;
     if (force_rebuild) *gate_now = 1;
   }
   if (s >= meta[0]) return;
@@ -52,6 +55,12 @@ __global__ void __launch_bounds__(256) k_begin_step(
   const float dy = min_image(x_build[n + a], x[1], cg.L[1], cg.hL[1]);
   const float dz = min_image(x_build[2 * n + a], x[2], cg.L[2], cg.hL[2]);
   if (dist2(dx, dy, dz) > half_skin2) atomicOr(gate_now, 1);
+  // pruned list: displacement since it was made (same slot order)
+  const float4 q0 = xp[s];
+  const float px = min_image(q0.x, x[0], cg.L[0], cg.hL[0]);
+  const float py = min_image(q0.y, x[1], cg.L[1], cg.hL[1]);
+  const float pz = min_image(q0.z, x[2], cg.L[2], cg.hL[2]);
+  if (dist2(px, py, pz) > prune_move2) atomicOr(pgate_now, 1);
 }
 
 // Closing half of a step, four lanes per slot: lane q of the quad takes z
@@ -121,11 +130,13 @@ __global__ void __launch_bounds__(256) k_finish_step(
 }
 
 hipError_t launch_begin_step(Ctx& c, float* pos, float* vel, const float* force, float dt,
-                             int* gate_now, int* gate_next, bool force_rebuild) {
+                             int* gate_now, int* gate_next, int* pgate_now, int* pgate_next,
+                             bool force_rebuild) {
   const float h = 0.5f * c.r_ghost;
   k_begin_step<<<(c.max_slots + 255) / 256, 256, 0, c.stream>>>(
       pos, vel, force, c.hdt_scale, c.perm, c.q, c.x_build, c.meta, c.n, c.cg, 0.5f * dt, dt,
-      h * h, c.xs, c.flags, gate_now, gate_next, force_rebuild ? 1 : 0);
+      h * h, c.xs, c.flags, gate_now, gate_next, c.xp, c.prune_move2, pgate_now, pgate_next,
+      force_rebuild ? 1 : 0);
   return hipGetLastError();
 }
 

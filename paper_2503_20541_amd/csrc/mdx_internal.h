@@ -107,7 +107,13 @@ struct Ctx {
   int* tile_count = nullptr;   // [max_clusters]
   int* nl_needed = nullptr;    // [1] max tiles one cluster needed in the last build
   unsigned* flags = nullptr;   // [1] latched MDX_FLAG_*
-  int* gate = nullptr;         // [2] rebuild requests inside mdx_integrate_step (step parity)
+  int* gate = nullptr;         // [4] rebuild requests inside mdx_integrate_step (step parity),
+                               // then pruned-list invalid flags (step parity)
+  uint2* ptiles = nullptr;     // [max_clusters][nl_cap] pruned tile list
+  int* pcount = nullptr;       // [max_clusters]
+  float4* xp = nullptr;        // [max_slots] slot positions when the pruned list was made
+  float prune_r2 = 0.f;        // fl(r_p^2), r_p = r_c + 0.4 r_g
+  float prune_move2 = 0.f;     // (0.19 r_g)^2: displacement that invalidates the pruned list
 
   // ---- PME ----
   float* grid_q = nullptr;     // [Kz][Ky][Kx] real
@@ -143,7 +149,10 @@ hipError_t launch_refresh_sorted(Ctx& c, const float* pos);
 // Blocks of the cooperative list build that are co-resident on the current
 // device (0 if cooperative launches are not available).
 int build_coop_blocks(int max_clusters, int n, int ncol);
-hipError_t launch_nonbonded(Ctx& c, bool energy);
+// gate_now / pgate_now: the step's rebuild and prune flags inside
+// mdx_integrate_step (null for stand-alone calls: full list, no pruning).
+hipError_t launch_nonbonded(Ctx& c, bool energy, const int* gate_now = nullptr,
+                            const int* pgate_now = nullptr);
 hipError_t launch_bonded_excl(Ctx& c, const float* pos, float* force, bool energy);
 // Sums the FP64 partial rows into out[slot - slot_base] (slots MDX_ENERGY_*);
 // const_slot >= 0 also stores const_val there, zero_slot >= 0 stores 0.
@@ -154,7 +163,8 @@ bool pme_size_supported(int K);
 hipError_t launch_pme(Ctx& c, float* force, bool energy);
 // Fused per-slot step kernels used by mdx_integrate_step.
 hipError_t launch_begin_step(Ctx& c, float* pos, float* vel, const float* force, float dt,
-                             int* gate_now, int* gate_next, bool force_rebuild);
+                             int* gate_now, int* gate_next, int* pgate_now, int* pgate_next,
+                             bool force_rebuild);
 hipError_t launch_finish_step(Ctx& c, const float* pos, float* vel, float* force, float dt,
                               bool energy);
 // Spread + FFT passes only (the potential grid), for the fused closing kernel.

@@ -74,6 +74,20 @@ __device__ __forceinline__ float sum_rows4(float x) {
 // The pair kernel stages the LJ type-pair table in LDS (at most
 // kMaxLjTypes^2 type pairs; mdx_create rejects more types).
 
+// Dynamic pruning (an optimisation of the Verlet list's use, Sec. II.A.2):
+// the tiles with a pair within r_p = r_c + 0.4 r_g at the emitting step are
+// kept in a second list, used while every atom stays within 0.19 r_g of its
+// position at that step; a pair it drops was farther than r_p apart, so it
+// cannot come within r_c (0.8 r_g of closing) before the list is refreshed.
+struct PruneArgs {
+  const int* gate_now;    // rebuild flag of this step (null: stand-alone call)
+  const int* pgate_now;   // pruned list no longer valid (set by k_begin_step)
+  uint2* ptiles;          // [max_clusters][cap]
+  int* pcount;            // [max_clusters]
+  float4* xp;             // [max_slots] positions at the emitting step
+  float rp2;              // fl(r_p^2)
+};
+
 template <bool ENERGY, bool COUL, bool SWITCH, bool HALF>
 __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
                                               const int* __restrict__ ts,
@@ -83,7 +97,8 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
                                               PairParams pp, const float4* __restrict__ lj_f,
                                               const double2* __restrict__ lj_d,
                                               float* __restrict__ fslot, int fstride,
-                                              double* __restrict__ partials, int pstride) {
+                                              double* __restrict__ partials, int pstride,
+                                              PruneArgs pr) {
   __shared__ double red[16];
   __shared__ float4 lj_s[kMaxLjTypes * kMaxLjTypes];
   // Reserve 80 VGPRs (the clobber marks v79 as used): at most 6 of the 8
@@ -105,8 +120,18 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
     const float4 pi = xs[si];
     const float lmx = pp.L[0] - pi.x, lmy = pp.L[1] - pi.y, lmz = pp.L[2] - pi.z;
     const int trow = ts[si] * pp.ntypes;
-    const int cnt = tile_count[ic];
-    const uint2* tl = tiles + (size_t)ic * cap;
+    // List selection (the flags are the same for the whole grid): the full
+    // list, emitting the pruned list and the prune positions, on a rebuild
+    // step or when an atom has moved too far since the last emission; the
+    // pruned list otherwise. Without flags (stand-alone force calls) the full
+    // list, nothing emitted.
+    const bool emit = __builtin_amdgcn_readfirstlane(
+                          pr.gate_now && (*pr.gate_now != 0 || *pr.pgate_now != 0)) != 0;
+    const bool pruned = pr.gate_now && !emit;
+    const int cnt = pruned ? pr.pcount[ic] : tile_count[ic];
+    const uint2* tl = (pruned ? pr.ptiles : tiles) + (size_t)ic * cap;
+    uint2* const pl = pr.ptiles + (size_t)ic * cap;
+    int pn = 0;
     // j-force component this lane stores: x, y, z on rows 0-2, none on row 3
     float* const fcomp = fslot + (size_t)(ia < 3 ? ia : 0) * fstride;
     // One group of four tiles (e: this lane's tile, sj / pj / tj: its j slot,
@@ -118,6 +143,16 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
       float dz = min_image_h(pi.z, lmz, pj.z, pp.L[2], pp.hL[2]);
       float r2 = dist2(dx, dy, dz);
       const bool in = on && r2 < pp.rc2;
+      if (emit) {
+        // keep tile tt if any of its pairs is within r_p; lane (row 0, tile
+        // tt, slot 0) writes it, in list order
+        const unsigned long long nearm = __ballot(on && r2 < pr.rp2);
+        const bool keep = ((nearm >> (4 * tt)) & 0x000f000f000f000full) != 0ull;
+        const bool leader = ia == 0 && jb == 0;
+        const unsigned long long km = __ballot(leader && keep);
+        if (leader && keep) pl[pn + __popcll(km & ((1ull << lane) - 1ull))] = e;
+        pn += __popcll(km);
+      }
       const unsigned long long hit = __ballot(in);
       if (hit == 0ull) return;
       float gx = 0.f, gy = 0.f, gz = 0.f;   // force on j (minus the force on i)
@@ -208,6 +243,13 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
       sB = slot_of(eB, g + 12);
       pB = xs[sB];
       tB = ts[sB];
+    }
+    if (emit) {
+      // pad the pruned list to a whole group; record the prune positions
+      const int padded = (pn + 3) & ~3;
+      if (lane < padded - pn) pl[pn + lane] = make_uint2(0u, 0u);
+      if (lane == 0) pr.pcount[ic] = padded;
+      if ((lane & 15) == 0) pr.xp[si] = pi;
     }
   }
   // sum the i force over the 16 lanes of the row; lanes 0-2 of the row add
@@ -306,7 +348,7 @@ __global__ void __launch_bounds__(256) k_reduce_rows(const double* __restrict__ 
   }
 }
 
-hipError_t launch_nonbonded(Ctx& c, bool energy) {
+hipError_t launch_nonbonded(Ctx& c, bool energy, const int* gate_now, const int* pgate_now) {
   PairParams pp;
   for (int d = 0; d < 3; ++d) {
     pp.L[d] = c.cg.L[d];
@@ -324,10 +366,11 @@ hipError_t launch_nonbonded(Ctx& c, bool energy) {
   pp.inv_sw = c.has_switch ? 1.0f / (c.r_cut - c.switch_r) : 0.f;
   const int nb = (c.max_clusters + 3) / 4;
   c.nb_blocks = nb;
+  const PruneArgs pr{gate_now, pgate_now, c.ptiles, c.pcount, c.xp, c.prune_r2};
 #define MDX_PAIR(E, C, S, H)                                                               \
   k_pair<E, C, S, H><<<nb, 256, 0, c.stream>>>(c.xs, c.ts, c.tiles, c.tile_count, c.meta,   \
                                                 c.nl_cap, pp, c.lj_f, c.lj_d, c.fslot,      \
-                                                c.max_slots, c.partials, c.max_blocks)
+                                                c.max_slots, c.partials, c.max_blocks, pr)
 #define MDX_PAIR_H(E, C, S)      \
   if (c.half_list)               \
     MDX_PAIR(E, C, S, true);     \

@@ -102,9 +102,12 @@ int alloc_list(mdx_ctx* x, int cap) {
   Ctx& c = x->c;
   cap = std::max(4, (cap + 3) / 4 * 4);   // lists are padded to groups of four tiles
   dev_free(x, c.tiles);
+  dev_free(x, c.ptiles);
   c.tiles = nullptr;
+  c.ptiles = nullptr;
   int rc = dev_alloc(x, &c.tiles, (size_t)cap * c.max_clusters);
   if (rc != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.ptiles, (size_t)cap * c.max_clusters)) != MDX_OK) return rc;
   c.nl_cap = cap;
   return MDX_OK;
 }
@@ -410,8 +413,20 @@ int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
   if ((rc = dev_alloc(x, &c.nl_needed, 1)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.flags, 1)) != MDX_OK) return rc;
   MDX_TRY(hipMemset(c.flags, 0, sizeof(unsigned)));
-  if ((rc = dev_alloc(x, &c.gate, 2)) != MDX_OK) return rc;
-  MDX_TRY(hipMemset(c.gate, 0, 2 * sizeof(int)));
+  if ((rc = dev_alloc(x, &c.gate, 4)) != MDX_OK) return rc;
+  {
+    const int g0[4] = {0, 0, 1, 1};   // no pruned list yet
+    MDX_TRY(hipMemcpy(c.gate, g0, sizeof(g0), hipMemcpyHostToDevice));
+  }
+  if ((rc = dev_alloc(x, &c.pcount, c.max_clusters)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.xp, c.max_slots)) != MDX_OK) return rc;
+  MDX_TRY(hipMemset(c.xp, 0, sizeof(float4) * c.max_slots));
+  {
+    const float rp = c.r_cut + 0.4f * c.r_ghost;
+    const float mv = 0.19f * c.r_ghost;
+    c.prune_r2 = rp * rp;
+    c.prune_move2 = mv * mv;
+  }
   int cap = d->nl_capacity > 0 ? d->nl_capacity
                                : default_capacity(n, c.box, c.r_list, a_clu, c.max_clusters,
                                                    !c.half_list);
@@ -544,6 +559,8 @@ int mdx_set_stream(mdx_ctx* x, void* hip_stream) {
 int mdx_build_neighbors(mdx_ctx* x, const float* pos) {
   if (check_ctx(x) || !pos) return MDX_E_INVALID;
   Ctx& c = x->c;
+  // a new list (new slot order) invalidates the pruned list
+  MDX_TRY(mdx::launch_fill_i32(c.gate + 2, 1, 2, c.stream));
   for (int attempt = 0; attempt < 3; ++attempt) {
     MDX_TRY(timed(x, MDX_TIMING_BUILD, c.stream, [&] { return mdx::launch_build_list(c, pos); }));
     int needed = 0;
@@ -685,9 +702,12 @@ int mdx_integrate_step(mdx_ctx* x, float* pos, float* vel, float* force, int32_t
     // the next step's gate never touches the one being raised.
     int* gate_now = c.gate + (c.steps_taken & 1);
     int* gate_next = c.gate + ((c.steps_taken + 1) & 1);
+    int* pgate_now = gate_now + 2;
+    int* pgate_next = gate_next + 2;
     const bool cadence = ++c.steps_since_build >= c.rebuild_every;
     if (cadence) c.steps_since_build = 0;
-    MDX_TRY(mdx::launch_begin_step(c, pos, vel, force, dt, gate_now, gate_next, cadence));
+    MDX_TRY(mdx::launch_begin_step(c, pos, vel, force, dt, gate_now, gate_next, pgate_now,
+                                   pgate_next, cadence));
     MDX_TRY(timed(x, MDX_TIMING_BUILD, c.stream, [&] { return mdx::launch_build_list(c, pos, gate_now); }));
     // The reciprocal-space potential only needs this step's slot positions:
     // the charges are spread on the context's stream, the FFT passes run on
@@ -704,7 +724,8 @@ int mdx_integrate_step(mdx_ctx* x, float* pos, float* vel, float* force, int32_t
       MDX_TRY(timing_end(tslot, x->aux));
       if (tslot) MDX_TRY(hipEventRecord(x->ev_join, x->aux));
     }
-    MDX_TRY(timed(x, MDX_TIMING_PAIR, c.stream, [&] { return mdx::launch_nonbonded(c, e); }));
+    MDX_TRY(timed(x, MDX_TIMING_PAIR, c.stream,
+                  [&] { return mdx::launch_nonbonded(c, e, gate_now, pgate_now); }));
     if (c.has_pme) MDX_TRY(hipStreamWaitEvent(c.stream, x->ev_join, 0));
     MDX_TRY(mdx::launch_finish_step(c, pos, vel, force, dt, e));
     if (e) {

@@ -160,10 +160,11 @@ def test_water96k_full_size_sampled_forces_and_energies():
         assert mdx.get_status(ctx) == 0
         F = t["force"].cpu().numpy().astype(np.float64)
         E = np.concatenate([t["e_nb"].cpu().numpy(), t["e_rec"].cpu().numpy()])
-        # one step of the benchmark's path (list build in one cooperative
-        # launch, PME on the second stream, fused closing kernel): the force it
-        # leaves behind equals a fresh evaluation at the new positions
-        mdx.integrate_step(ctx, t["pos"], t["vel"], t["force"], 1, s.dt)
+        # 12 steps of the benchmark's path (in-step list rebuild, pruned
+        # list, PME FFTs on the second stream, fused closing kernel): the
+        # force it leaves behind equals a fresh full-list evaluation at the
+        # new positions
+        mdx.integrate_step(ctx, t["pos"], t["vel"], t["force"], 12, s.dt)
         torch.cuda.synchronize()
         F_step = t["force"].cpu().numpy().astype(np.float64)
         f2 = torch.zeros_like(t["force"])
