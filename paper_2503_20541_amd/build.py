@@ -23,7 +23,7 @@ HIPCC_FLAGS = [
     "-fPIC",
     "-shared",
     "-Wall",
-    # packed FP32 instructions stay disabled (hardware notes)
+    # packed FP32 instructions stay disabled
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 

@@ -11,8 +11,12 @@
 namespace mdx {
 
 constexpr int kWave = 64;
-constexpr int kClusterSize = 4;
-constexpr int kMaxLjTypes = 32;   // LJ atom types (the pair kernel keeps the type-pair table in LDS)     // atoms per cluster (slots per tile side)
+constexpr int kClusterSize = 4;   // atoms per cluster (slots per tile side)
+constexpr int kMaxLjTypes = 32;   // LJ atom types (the pair kernel keeps the type-pair table in LDS)
+// PME spreading bricks: kBrickXY x kBrickXY x kBrickZ grid points (smaller
+// along a dimension with fewer grid points)
+constexpr int kBrickXY = 8;
+constexpr int kBrickZ = 8;
 
 // Indices into the FP64 partial-sum rows written by force kernels.
 enum PartialRow { kRowLJ = 0, kRowDir, kRowExcl, kRowBond, kRowAngle, kRowRec, kRowKin, kRowCount };

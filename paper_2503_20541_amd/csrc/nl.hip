@@ -243,6 +243,11 @@ __device__ void scatter_atom(const BuildArgs& a, int i) {
 constexpr int kColThreads = 128;
 constexpr int kColStage = 1024;
 
+// Sort key of a build z: a NaN coordinate (a diverged trajectory, flagged
+// out of box by the binning) ranks as +inf, so that (key, atom index) stays
+// a strict total order and each slot of the column is written exactly once.
+__device__ __forceinline__ float z_key(float z) { return z == z ? z : __builtin_inff(); }
+
 __device__ void sort_column(const BuildArgs& a, int c, float2* st) {
   const int n = a.n;
   const int b = a.col_start[c], e = a.col_start[c + 1];
@@ -253,7 +258,7 @@ __device__ void sort_column(const BuildArgs& a, int c, float2* st) {
   if (staged) {
     for (int p = threadIdx.x; p < cnt; p += blockDim.x) {
       const int v = a.perm_unsorted[b + p];
-      st[p] = make_float2(a.pos[2 * n + v], __int_as_float(v));
+      st[p] = make_float2(z_key(a.pos[2 * n + v]), __int_as_float(v));
     }
     __syncthreads();
   }
@@ -271,17 +276,17 @@ __device__ void sort_column(const BuildArgs& a, int c, float2* st) {
       }
     } else {
       v = a.perm_unsorted[b + p];
-      zv = a.pos[2 * n + v];
+      zv = z_key(a.pos[2 * n + v]);
       for (int k = 0; k < cnt; ++k) {
         const int u = a.perm_unsorted[b + k];
-        const float zu = a.pos[2 * n + u];
+        const float zu = z_key(a.pos[2 * n + u]);
         rank += (zu < zv || (zu == zv && u < v)) ? 1 : 0;
       }
     }
     const int s = sb + rank;
     a.perm[s] = v;
     a.inv_perm[v] = s;
-    a.xs[s] = make_float4(a.pos[v], a.pos[n + v], zv, a.q[v]);
+    a.xs[s] = make_float4(a.pos[v], a.pos[n + v], a.pos[2 * n + v], a.q[v]);
     a.ts[s] = a.atype[v];
     a.zb[s] = zv;
   }
@@ -353,7 +358,9 @@ __device__ __forceinline__ float axis_gap(float alo, float ahi, float blo, float
   return fmaxf(0.f, d - 0.5f * (ahi - alo) - 0.5f * (bhi - blo));
 }
 
-constexpr int kSearchCand = 1024;   // bbox-passing j-clusters one i-cluster may have
+// bbox-passing j-clusters one i-cluster may have; an entry holds
+// 4 * j-cluster + (its real atoms - 1), never negative
+constexpr int kSearchCand = 1024;
 constexpr int kSearchSegs = 64;     // (column, z segment) units handled per chunk
 
 // First cluster in [lo, hi) whose value v(k) >= x (v nondecreasing).
@@ -467,7 +474,7 @@ __device__ void search_cluster(const BuildArgs& a, int ic, int* mycand, int* seg
       for (int f0 = 0; f0 < total; f0 += kWave) {
         int f = f0 + lane;
         bool pass = false;
-        int jc = 0;
+        int jc = 0, nvj = 0;
         if (f < total) {
           int lo = 0, hi = nu - 1;
           while (lo < hi) {
@@ -476,6 +483,7 @@ __device__ void search_cluster(const BuildArgs& a, int ic, int* mycand, int* seg
           }
           jc = seg_first[lo] + (f - seg_pre[lo]);
           float4 jlo = a.box_lo[jc], jhi = a.box_hi[jc];
+          nvj = (int)jlo.w;
           if (jlo.w > 0.f && owns_pair(ic, jc, a.half)) {
             float gx = axis_gap(ilo.x, ihi.x, jlo.x, jhi.x, a.cg.L[0]);
             float gy = axis_gap(ilo.y, ihi.y, jlo.y, jhi.y, a.cg.L[1]);
@@ -487,7 +495,7 @@ __device__ void search_cluster(const BuildArgs& a, int ic, int* mycand, int* seg
         int before = __popcll(m & ((1ull << lane) - 1ull));
         if (pass) {
           int slot = ncand + before;
-          if (slot < kSearchCand) mycand[slot] = jc;
+          if (slot < kSearchCand) mycand[slot] = jc * kClusterSize + (nvj - 1);
         }
         ncand += __popcll(m);
       }
@@ -528,26 +536,15 @@ __device__ void search_cluster(const BuildArgs& a, int ic, int* mycand, int* seg
   }
   const bool ex_more = ee - eb > 4;
   int count = 0;
-  int jc_n = (t < ncand) ? mycand[t] : -1;
-  float nv_n = 0.f;
-  float4 pj_n = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (jc_n >= 0) {
-    nv_n = a.box_lo[jc_n].w;
-    pj_n = a.xs[jc_n * kClusterSize + b];
-  }
-  for (int g = 0; g < ncand; g += 4) {
-    const int jc = jc_n;
-    const float nv = nv_n;
-    const float4 pj = pj_n;
-    jc_n = (g + 4 + t < ncand) ? mycand[g + 4 + t] : -1;
-    if (jc_n >= 0) {
-      nv_n = a.box_lo[jc_n].w;
-      pj_n = a.xs[jc_n * kClusterSize + b];
-    }
+  // One group of four candidate tiles: c = this lane's candidate entry (-1
+  // past the end), pj = its j slot's position.
+  auto group = [&](int c, float4 pj) {
+    const int jc = c >= 0 ? c / kClusterSize : -1;
+    const int nv = c >= 0 ? c % kClusterSize + 1 : 0;
     unsigned bit = 0;
     const int sj = jc * kClusterSize + b;
     // the cluster's own tile: slot pairs a < b (half list) or a != b
-    if (jc >= 0 && ivalid && b < (int)nv && (jc != ic || b > ia || (!a.half && b < ia))) {
+    if (jc >= 0 && ivalid && b < nv && (jc != ic || b > ia || (!a.half && b < ia))) {
       float dx = min_image_h(pi.x, lmx, pj.x, a.cg.L[0], a.cg.hL[0]);
       float dy = min_image_h(pi.y, lmy, pj.y, a.cg.L[1], a.cg.hL[1]);
       float dz = min_image_h(pi.z, lmz, pj.z, a.cg.L[2], a.cg.hL[2]);
@@ -570,6 +567,22 @@ __device__ void search_cluster(const BuildArgs& a, int ic, int* mycand, int* seg
       if (k < a.cap) a.tiles[(size_t)ic * a.cap + k] = make_uint2((unsigned)jc, mask);
     }
     count += __popcll(nonempty);
+  };
+  // two groups per iteration with fixed registers: the j positions of the
+  // next group of each half are in flight while a group is tested
+  auto cand_at = [&](int g) { return (g + t < ncand) ? mycand[g + t] : -1; };
+  auto pos_of = [&](int c) {
+    return c >= 0 ? a.xs[(c & ~(kClusterSize - 1)) + b] : make_float4(0.f, 0.f, 0.f, 0.f);
+  };
+  int cA = cand_at(0), cB = cand_at(4);
+  float4 pA = pos_of(cA), pB = pos_of(cB);
+  for (int g = 0; g < ncand; g += 8) {
+    group(cA, pA);
+    cA = cand_at(g + 8);
+    pA = pos_of(cA);
+    if (g + 4 < ncand) group(cB, pB);
+    cB = cand_at(g + 12);
+    pB = pos_of(cB);
   }
   // pad the list to whole groups of four tiles with empty tiles (mask 0)
   const int kept = count < a.cap ? count : a.cap;

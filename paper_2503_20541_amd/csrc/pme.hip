@@ -28,7 +28,8 @@ struct FftPlan {
 
 constexpr int kSpreadThreads = 256;
 constexpr int kSpreadWaves = kSpreadThreads / kWave;
-constexpr int kMaxBrick = 8 * 66;    // B_z planes of B_x * B_y + 2 points (padded, see below)
+// B_z planes of B_x * B_y + 2 points (padded, see below)
+constexpr int kMaxBrick = kBrickZ * (kBrickXY * kBrickXY + 2);
 constexpr int kMaxCandCells = 512;
 constexpr int kCandList = 2048;      // candidate slots a brick lists in LDS
 

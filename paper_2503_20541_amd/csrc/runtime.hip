@@ -117,7 +117,7 @@ int setup_pme(mdx_ctx* x, const mdx_system_desc* d) {
   mdx::PmeGrid& g = c.pg;
   for (int k = 0; k < 3; ++k) {
     g.K[k] = d->pme_grid[k];
-    g.B[k] = std::min(8, g.K[k]);
+    g.B[k] = std::min(k < 2 ? mdx::kBrickXY : mdx::kBrickZ, g.K[k]);
     g.nb[k] = (g.K[k] + g.B[k] - 1) / g.B[k];
     double s = (double)g.K[k] / (double)c.box[k];
     g.scale_hi[k] = (float)s;
@@ -399,6 +399,7 @@ int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
   MDX_TRY(hipMemset(c.meta, 0, 4 * sizeof(int)));
   if ((rc = dev_alloc(x, &c.perm_unsorted, n)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.perm, c.max_slots)) != MDX_OK) return rc;
+  MDX_TRY(hipMemset(c.perm, 0xff, sizeof(int) * c.max_slots));   // every slot empty (-1)
   if ((rc = dev_alloc(x, &c.inv_perm, n)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.xs, c.max_slots)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.zbin, (size_t)ncol * (g.nzb + 1))) != MDX_OK) return rc;
@@ -419,6 +420,7 @@ int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
     MDX_TRY(hipMemcpy(c.gate, g0, sizeof(g0), hipMemcpyHostToDevice));
   }
   if ((rc = dev_alloc(x, &c.pcount, c.max_clusters)) != MDX_OK) return rc;
+  MDX_TRY(hipMemset(c.pcount, 0, sizeof(int) * c.max_clusters));
   if ((rc = dev_alloc(x, &c.xp, c.max_slots)) != MDX_OK) return rc;
   MDX_TRY(hipMemset(c.xp, 0, sizeof(float4) * c.max_slots));
   {

@@ -103,3 +103,28 @@ def test_list_water96k_sampled_rows():
     rnl = float(np.float32(s.r_cut + s.r_ghost))
     expect = 0.5 * s.n_atoms * (s.n_atoms / np.prod(s.box.astype(float))) * 4 / 3 * np.pi * rnl ** 3
     assert abs(len(got) / expect - 1.0) < 0.02
+
+
+def test_list_with_nan_coordinates_flags_and_skips_them():
+    # a diverged trajectory: atoms with a NaN coordinate are flagged out of
+    # box, take part in no pair, and the rest of the list is unchanged
+    s = synth.random_box(1500, [10.0, 10.0, 10.0], 2.4, 0.4, 56, n_excl_per_atom=1)
+    bad = np.array([5, 17, 400, 1499])
+    s2 = s.copy()
+    s2.pos = s.pos.copy()
+    s2.pos[2, bad[0]] = np.nan      # z only: the column sort key
+    s2.pos[:, bad[1]] = np.nan      # every coordinate
+    s2.pos[0, bad[2]] = np.nan      # x only: the binning
+    s2.pos[2, bad[3]] = np.nan
+    announce("list with NaN coordinates")
+    with gpu_context(s2) as (mdx, ctx, t):
+        mdx.build_neighbors(ctx, t["pos"])
+        got = mdx.get_neighbor_pairs(ctx)
+        assert mdx.get_status(ctx) & mdx.MDX_FLAG_OUT_OF_BOX
+    keep = np.setdiff1d(np.arange(s.n_atoms), bad)
+    new = -np.ones(s.n_atoms, dtype=np.int64)
+    new[keep] = np.arange(len(keep))
+    ex = s.exclusions[np.all(new[s.exclusions] >= 0, axis=1)]
+    ref = neighbors.tree_pairs(np.ascontiguousarray(s.pos[:, keep]), s.box, s.r_cut,
+                               s.r_ghost, new[ex].astype(np.int32))
+    assert np.array_equal(got, keep[ref])
