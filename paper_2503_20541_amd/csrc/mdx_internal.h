@@ -145,8 +145,11 @@ struct Ctx {
 // ---- launchers (each returns hipError_t of the launch) ----
 hipError_t launch_fill_i32(int* p, int v, int count, hipStream_t s);
 // gate == nullptr: unconditional build; otherwise every build kernel returns
-// at once unless *gate != 0.
-hipError_t launch_build_list(Ctx& c, const float* pos, const int* gate = nullptr);
+// at once unless *gate != 0. `done` (if given) completes once the slot
+// positions and the PME brick slot ranges are in place (before the tile
+// search), for work on another stream that needs only those.
+hipError_t launch_build_list(Ctx& c, const float* pos, const int* gate = nullptr,
+                             hipEvent_t done = nullptr);
 // Copies pos into the slot array and tests the r_g/2 validity rule; a
 // violation latches MDX_FLAG_NL_STALE.
 hipError_t launch_refresh_sorted(Ctx& c, const float* pos);

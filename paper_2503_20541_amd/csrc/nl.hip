@@ -702,7 +702,7 @@ __global__ void k_refresh(const float* __restrict__ pos, const int* __restrict__
   if (f) atomicOr(flags, f);
 }
 
-hipError_t launch_build_list(Ctx& c, const float* pos, const int* gate) {
+hipError_t launch_build_list(Ctx& c, const float* pos, const int* gate, hipEvent_t done) {
   hipStream_t s = c.stream;
   const int n = c.n;
   const int ncol = c.cg.ncell;
@@ -716,13 +716,24 @@ hipError_t launch_build_list(Ctx& c, const float* pos, const int* gate) {
               c.tile_count, c.max_clusters};
   if (c.coop_blocks > 0) {
     void* args[] = {&a};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_build_all),
-                                      dim3(c.coop_blocks), dim3(kBuildThreads), args, 0, s);
+    hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_build_all),
+                                              dim3(c.coop_blocks), dim3(kBuildThreads), args, 0, s);
+    if (e == hipSuccess && done) e = hipEventRecord(done, s);
+    return e;
   }
   const int nb = (n + 255) / 256;
   k_bin_scan<<<nb, 256, 0, s>>>(a);
   k_scatter<<<nb, 256, 0, s>>>(a);
-  k_col_sort<<<ncol, kColThreads, 0, s>>>(a);
+  // the column sort completes the slot positions and the PME brick ranges:
+  // `done` is recorded by its own dispatch
+  if (done) {
+    void* args[] = {&a};
+    hipError_t e = hipExtLaunchKernel(reinterpret_cast<const void*>(k_col_sort), dim3(ncol),
+                                      dim3(kColThreads), args, 0, s, nullptr, done, 0);
+    if (e != hipSuccess) return e;
+  } else {
+    k_col_sort<<<ncol, kColThreads, 0, s>>>(a);
+  }
   k_tile_search<<<(c.max_clusters + 3) / 4, 256, 0, s>>>(a);
   return hipGetLastError();
 }

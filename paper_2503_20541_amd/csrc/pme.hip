@@ -172,6 +172,11 @@ __global__ void __launch_bounds__(kSpreadThreads) k_pme_spread(
   }
 }
 
+// The FFT passes share the chip with the pair kernel (they run on a second
+// stream): their waves take a raised issue priority so the short chain of
+// passes is not starved by the long-running pair waves on the same SIMDs.
+__device__ __forceinline__ void fft_priority() { __builtin_amdgcn_s_setprio(2); }
+
 // ---------------------------------------------------------------------------
 // LDS FFT: Stockham autosort, radix 4/2/3/5 (7 by table), twiddles from a
 // host-built table exp(-2 pi i m/N). Lengths with a compiled plan (kFftSizes)
@@ -348,6 +353,7 @@ __global__ void __launch_bounds__(256) k_fft_rows_r2c(const float* __restrict__ 
                                                       float2* __restrict__ out, int nrows,
                                                       int P, int Kxh, FftPlan pl,
                                                       const float2* __restrict__ twg) {
+  fft_priority();
   extern __shared__ float2 sm[];
   const int L = N > 0 ? N : pl.N;
   float2* tw = sm;
@@ -374,6 +380,7 @@ __global__ void __launch_bounds__(256) k_fft_rows_c2r(const float2* __restrict__
                                                       float* __restrict__ out, int nrows,
                                                       int P, int Kxh, FftPlan pl,
                                                       const float2* __restrict__ twg) {
+  fft_priority();
   extern __shared__ float2 sm[];
   const int L = N > 0 ? N : pl.N;
   float2* tw = sm;
@@ -417,6 +424,7 @@ __global__ void __launch_bounds__(256) k_fft_cols(float2* __restrict__ grid, Pme
                                                   const double* __restrict__ my,
                                                   const double* __restrict__ mz,
                                                   double* __restrict__ partials, int pstride) {
+  fft_priority();
   extern __shared__ float2 sm[];
   __shared__ double red[16];
   const int L = N > 0 ? N : pl.N;

@@ -710,18 +710,21 @@ int mdx_integrate_step(mdx_ctx* x, float* pos, float* vel, float* force, int32_t
     if (cadence) c.steps_since_build = 0;
     MDX_TRY(mdx::launch_begin_step(c, pos, vel, force, dt, gate_now, gate_next, pgate_now,
                                    pgate_next, cadence));
-    MDX_TRY(timed(x, MDX_TIMING_BUILD, c.stream, [&] { return mdx::launch_build_list(c, pos, gate_now); }));
-    // The reciprocal-space potential only needs this step's slot positions:
-    // the charges are spread on the context's stream, the FFT passes run on
-    // the second stream concurrently with the pair kernel, and the closing
-    // kernel (force interpolation) waits for them.
+    MDX_TRY(timed(x, MDX_TIMING_BUILD, c.stream, [&] {
+      return mdx::launch_build_list(c, pos, gate_now, c.has_pme ? x->ev_fork : nullptr);
+    }));
+    // The reciprocal-space potential only needs this step's slot positions
+    // and the PME brick slot ranges: the spread and the FFT passes run on the
+    // second stream, from the end of the column sort on, concurrently with
+    // the tile search and the pair kernel; the closing kernel (force
+    // interpolation) waits for them. The fork and join events are recorded
+    // by the column sort's and the last FFT pass's own dispatches (no marker
+    // packets between kernels).
     if (c.has_pme) {
-      std::pair<hipEvent_t, hipEvent_t>* tslot;
-      MDX_TRY(timing_begin(x, MDX_TIMING_PME, c.stream, &tslot));
-      // the fork and join events are recorded by the spread's and the last
-      // FFT pass's own dispatches (no marker packets between kernels)
-      MDX_TRY(mdx::launch_pme_spread(c, c.stream, x->ev_fork));
       MDX_TRY(hipStreamWaitEvent(x->aux, x->ev_fork, 0));
+      std::pair<hipEvent_t, hipEvent_t>* tslot;
+      MDX_TRY(timing_begin(x, MDX_TIMING_PME, x->aux, &tslot));
+      MDX_TRY(mdx::launch_pme_spread(c, x->aux, nullptr));
       MDX_TRY(mdx::launch_pme_fft(c, x->aux, tslot ? nullptr : x->ev_join));
       MDX_TRY(timing_end(tslot, x->aux));
       if (tslot) MDX_TRY(hipEventRecord(x->ev_join, x->aux));
