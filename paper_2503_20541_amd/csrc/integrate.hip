@@ -20,7 +20,8 @@ __device__ __forceinline__ float wrap_box(float x, float L) {
 }
 
 // Opening half of a step for every slot: v += (dt/2) a, x += dt v (wrapped),
-// slot position refreshed, r_g/2 validity test (raises gate_now) and the
+// slot position refreshed (as build position + minimum-image displacement),
+// r_g/2 validity test (raises gate_now) and the
 // pruned list's validity test (raises pgate_now). Thread 0 clears the flags
 // of the following step (nothing else touches them here) and raises
 // gate_now on a cadence rebuild.
@@ -50,10 +51,13 @@ __global__ void __launch_bounds__(256) k_begin_step(
     x[d] = wrap_box(pos[k] + dt * v, cg.L[d]);
     pos[k] = x[d];
   }
-  xs[s] = make_float4(x[0], x[1], x[2], q[a]);
-  const float dx = min_image(x_build[a], x[0], cg.L[0], cg.hL[0]);
-  const float dy = min_image(x_build[n + a], x[1], cg.L[1], cg.hL[1]);
-  const float dz = min_image(x_build[2 * n + a], x[2], cg.L[2], cg.hL[2]);
+  const float bx = x_build[a], by = x_build[n + a], bz = x_build[2 * n + a];
+  const float dx = min_image(bx, x[0], cg.L[0], cg.hL[0]);
+  const float dy = min_image(by, x[1], cg.L[1], cg.hL[1]);
+  const float dz = min_image(bz, x[2], cg.L[2], cg.hL[2]);
+  // slot position continued from the build position (not wrapped between
+  // builds), so the periodic image each list tile records stays valid
+  xs[s] = make_float4(bx + dx, by + dy, bz + dz, q[a]);
   if (dist2(dx, dy, dz) > half_skin2) atomicOr(gate_now, 1);
   // pruned list: displacement since it was made (same slot order)
   const float4 q0 = xp[s];

@@ -107,7 +107,10 @@ struct Ctx {
   float4* box_lo = nullptr;    // [max_clusters] cluster box (w = real atoms)
   float4* box_hi = nullptr;
   float* x_build = nullptr;    // [3][n] positions at the last build (caller order)
-  uint2* tiles = nullptr;      // [max_clusters][nl_cap] (j-cluster, 16-bit pair mask)
+  // [max_clusters][nl_cap] tiles: x = j-cluster, y = 16-bit pair mask (bit
+  // 4 a + b: i slot a, j slot b) | periodic image of the j-cluster << 16
+  // (2 bits per axis, image_code values; one image for all pairs of a tile)
+  uint2* tiles = nullptr;
   int* tile_count = nullptr;   // [max_clusters]
   int* nl_needed = nullptr;    // [1] max tiles one cluster needed in the last build
   unsigned* flags = nullptr;   // [1] latched MDX_FLAG_*
@@ -150,7 +153,8 @@ hipError_t launch_fill_i32(int* p, int v, int count, hipStream_t s);
 // search), for work on another stream that needs only those.
 hipError_t launch_build_list(Ctx& c, const float* pos, const int* gate = nullptr,
                              hipEvent_t done = nullptr);
-// Copies pos into the slot array and tests the r_g/2 validity rule; a
+// Copies pos into the slot array (as build position + minimum-image
+// displacement, like the integrator) and tests the r_g/2 validity rule; a
 // violation latches MDX_FLAG_NL_STALE.
 hipError_t launch_refresh_sorted(Ctx& c, const float* pos);
 // Blocks of the cooperative list build that are co-resident on the current
@@ -210,6 +214,21 @@ __device__ __forceinline__ float min_image_h(float xi, float Lmxi, float xj, flo
   float dn = xj + Lmxi;
   float d = s > hL ? up : s;
   return s < -hL ? dn : d;
+}
+
+// The image min_image_h takes for x_j: 0 (x_j itself), 1 (x_j - L) or
+// 2 (x_j + L).
+__device__ __forceinline__ unsigned image_code(float xi, float xj, float hL) {
+#pragma clang fp contract(off)
+  const float s = xj - xi;
+  return s > hL ? 1u : (s < -hL ? 2u : 0u);
+}
+
+// x_j - x_i at a given image, rounded exactly as min_image_h rounds it: am is
+// -L for image 1 and 0 otherwise, cp is L for image 2 and 0 otherwise.
+__device__ __forceinline__ float image_diff(float xi, float xj, float am, float cp) {
+#pragma clang fp contract(off)
+  return (xj + am) + (cp - xi);
 }
 
 __device__ __forceinline__ float dist2(float dx, float dy, float dz) {

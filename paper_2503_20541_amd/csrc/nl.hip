@@ -541,7 +541,7 @@ __device__ void search_cluster(const BuildArgs& a, int ic, int* mycand, int* seg
   auto group = [&](int c, float4 pj) {
     const int jc = c >= 0 ? c / kClusterSize : -1;
     const int nv = c >= 0 ? c % kClusterSize + 1 : 0;
-    unsigned bit = 0;
+    unsigned bit = 0, img = 0;
     const int sj = jc * kClusterSize + b;
     // the cluster's own tile: slot pairs a < b (half list) or a != b
     if (jc >= 0 && ivalid && b < nv && (jc != ic || b > ia || (!a.half && b < ia))) {
@@ -555,18 +555,31 @@ __device__ void search_cluster(const BuildArgs& a, int ic, int* mycand, int* seg
           for (int k = eb + 4; k < ee; ++k) excluded |= (a.ex_idx[k] == aj);
         }
         bit = excluded ? 0u : 1u;
+        img = image_code(pi.x, pj.x, a.cg.hL[0]) | image_code(pi.y, pj.y, a.cg.hL[1]) << 2 |
+              image_code(pi.z, pj.z, a.cg.hL[2]) << 4;
       }
     }
-    unsigned long long m = __ballot(bit != 0);
-    // 16-bit mask of tile t: bits of lanes 16t .. 16t+15, bit index 4a + b
-    unsigned mask = (unsigned)((m >> (16 * t)) & 0xffffull);
-    unsigned long long nonempty = __ballot(b == 0 && ia == 0 && mask != 0);
-    int before = __popcll(nonempty & ((1ull << lane) - 1ull));
-    if (ia == 0 && b == 0 && mask != 0) {
-      int k = count + before;
-      if (k < a.cap) a.tiles[(size_t)ic * a.cap + k] = make_uint2((unsigned)jc, mask);
+    // One tile entry per periodic image among a tile's pairs (a single one
+    // unless the box is small next to the clusters and the list radius): in
+    // each round, the pairs sharing the image of the tile's first remaining
+    // pair. Bit 4a + b of tile t's mask is lane 16t + 4a + b.
+    unsigned long long rem = __ballot(bit != 0);
+    while (rem) {
+      const unsigned tm = (unsigned)((rem >> (16 * t)) & 0xffffull);
+      const int lead = 16 * t + (tm ? __ffs(tm) - 1 : 0);
+      const unsigned limg = (unsigned)__shfl((int)img, lead, kWave);
+      const unsigned long long tk = __ballot(((rem >> lane) & 1ull) && img == limg);
+      const unsigned mask = (unsigned)((tk >> (16 * t)) & 0xffffull);
+      const unsigned long long nonempty = __ballot(b == 0 && ia == 0 && mask != 0);
+      const int before = __popcll(nonempty & ((1ull << lane) - 1ull));
+      if (ia == 0 && b == 0 && mask != 0) {
+        const int k = count + before;
+        if (k < a.cap)
+          a.tiles[(size_t)ic * a.cap + k] = make_uint2((unsigned)jc, mask | limg << 16);
+      }
+      count += __popcll(nonempty);
+      rem &= ~tk;
     }
-    count += __popcll(nonempty);
   };
   // two groups per iteration with fixed registers: the j positions of the
   // next group of each half are in flight while a group is tested
@@ -691,11 +704,13 @@ __global__ void k_refresh(const float* __restrict__ pos, const int* __restrict__
   int a = perm[s];
   if (a < 0) return;
   float x = pos[a], y = pos[n + a], z = pos[2 * n + a];
-  xs[s] = make_float4(x, y, z, q[a]);
   bool inside = x >= 0.f && x < cg.L[0] && y >= 0.f && y < cg.L[1] && z >= 0.f && z < cg.L[2];
-  float dx = min_image(x_build[a], x, cg.L[0], cg.hL[0]);
-  float dy = min_image(x_build[n + a], y, cg.L[1], cg.hL[1]);
-  float dz = min_image(x_build[2 * n + a], z, cg.L[2], cg.hL[2]);
+  const float bx = x_build[a], by = x_build[n + a], bz = x_build[2 * n + a];
+  float dx = min_image(bx, x, cg.L[0], cg.hL[0]);
+  float dy = min_image(by, y, cg.L[1], cg.hL[1]);
+  float dz = min_image(bz, z, cg.L[2], cg.hL[2]);
+  // continued from the build position, as the list's tile images require
+  xs[s] = make_float4(bx + dx, by + dy, bz + dz, q[a]);
   unsigned f = 0;
   if (dist2(dx, dy, dz) > half_skin2) f |= MDX_FLAG_NL_STALE;
   if (!inside) f |= MDX_FLAG_OUT_OF_BOX;

@@ -107,6 +107,19 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
   // pair kernel is VALU-bound and loses little at 6 waves per SIMD.
   asm volatile("" ::: "v79");
   for (int t = threadIdx.x; t < pp.ntypes * pp.ntypes; t += blockDim.x) lj_s[t] = lj_f[t];
+  // periodic image shifts by tile image code (2 bits per axis): x_j offset
+  // am (-L for image 1) and cp (L for image 2), see image_diff
+  __shared__ float4 img_am[64], img_cp[64];
+  if (threadIdx.x < 64) {
+    float am[3], cp[3];
+    for (int d = 0; d < 3; ++d) {
+      const unsigned code = (threadIdx.x >> (2 * d)) & 3u;
+      am[d] = code == 1u ? -pp.L[d] : 0.f;
+      cp[d] = code == 2u ? pp.L[d] : 0.f;
+    }
+    img_am[threadIdx.x] = make_float4(am[0], am[1], am[2], 0.f);
+    img_cp[threadIdx.x] = make_float4(cp[0], cp[1], cp[2], 0.f);
+  }
   __syncthreads();
   const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   const int ic = blockIdx.x * 4 + w;
@@ -118,7 +131,6 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
   double e_lj = 0.0, e_c = 0.0;
   if (active) {
     const float4 pi = xs[si];
-    const float lmx = pp.L[0] - pi.x, lmy = pp.L[1] - pi.y, lmz = pp.L[2] - pi.z;
     const int trow = ts[si] * pp.ntypes;
     // List selection (the flags are the same for the whole grid): the full
     // list, emitting the pruned list and the prune positions, on a rebuild
@@ -138,9 +150,12 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
     // position and type).
     auto group = [&](uint2 e, unsigned sj, float4 pj, int tj) {
       const bool on = (e.y >> bitpos) & 1u;
-      float dx = min_image_h(pi.x, lmx, pj.x, pp.L[0], pp.hL[0]);
-      float dy = min_image_h(pi.y, lmy, pj.y, pp.L[1], pp.hL[1]);
-      float dz = min_image_h(pi.z, lmz, pj.z, pp.L[2], pp.hL[2]);
+      // the tile's image: the same differences as the minimum-image rule
+      // gives for its listed pairs, without the per-pair selects
+      const float4 am = img_am[e.y >> 16], cp = img_cp[e.y >> 16];
+      float dx = image_diff(pi.x, pj.x, am.x, cp.x);
+      float dy = image_diff(pi.y, pj.y, am.y, cp.y);
+      float dz = image_diff(pi.z, pj.z, am.z, cp.z);
       float r2 = dist2(dx, dy, dz);
       const bool in = on && r2 < pp.rc2;
       if (emit) {

@@ -95,7 +95,9 @@ int default_capacity(int n, const float box[3], float r_list, double a, int max_
                   mdx::kClusterSize;
   int cap = (int)std::ceil(1.5 * expect + 16.0);
   cap = (cap + 15) / 16 * 16;
-  return std::max(16, std::min(cap, (max_clusters + 15) / 16 * 16));
+  // in a box small next to r_list a j-cluster can take one tile per periodic
+  // image its pairs use, so the bound is a few times the cluster count
+  return std::max(16, std::min(cap, (4 * max_clusters + 15) / 16 * 16));
 }
 
 int alloc_list(mdx_ctx* x, int cap) {
@@ -786,7 +788,7 @@ int mdx_get_info(mdx_ctx* x, mdx_info* info) {
     for (int ic = 0; ic < h.nclu; ++ic) {
       tiles += h.cnt[ic];
       for (int k = 0; k < h.cnt[ic]; ++k)
-        entries += __builtin_popcount(h.tl[(size_t)ic * c.nl_cap + k].y);
+        entries += __builtin_popcount(h.tl[(size_t)ic * c.nl_cap + k].y & 0xffffu);
     }
     info->n_list_entries = entries;
     info->n_list_tiles = tiles;
