@@ -106,13 +106,15 @@ struct Ctx {
   float* zb = nullptr;         // [max_slots] z at the last build (sorted within a column)
   float4* box_lo = nullptr;    // [max_clusters] cluster box (w = real atoms)
   float4* box_hi = nullptr;
+  float4* col_xy = nullptr;     // [ncell] x min, x max, y min, y max of a column's atoms
   float* x_build = nullptr;    // [3][n] positions at the last build (caller order)
   // [max_clusters][nl_cap] tiles: x = j-cluster, y = 16-bit pair mask (bit
   // 4 a + b: i slot a, j slot b) | periodic image of the j-cluster << 16
   // (2 bits per axis, image_code values; one image for all pairs of a tile)
   uint2* tiles = nullptr;
   int* tile_count = nullptr;   // [max_clusters]
-  int* nl_needed = nullptr;    // [1] max tiles one cluster needed in the last build
+  int* nl_needed = nullptr;    // [1] max tiles one cluster needed in the last build, if
+                               // above nl_cap (0 otherwise)
   unsigned* flags = nullptr;   // [1] latched MDX_FLAG_*
   int* gate = nullptr;         // [4] rebuild requests inside mdx_integrate_step (step parity),
                                // then pruned-list invalid flags (step parity)

@@ -130,6 +130,7 @@ struct BuildArgs {
   float* zb;
   float4* box_lo;
   float4* box_hi;
+  float4* col_xy;
   ZRangeArgs zr;
   const int* ex_start;
   const int* ex_idx;
@@ -312,6 +313,25 @@ __device__ void sort_column_boxes(const BuildArgs& a, int c, float2* st) {
   for (int k = c0 + (int)threadIdx.x; k < c1; k += blockDim.x) cluster_box(a, k);
   for (int l = threadIdx.x; l < a.zr.layers; l += blockDim.x) column_zrange(l * a.zr.ncol + c, a.zr);
   __syncthreads();
+  // x-y extent of the column's atoms (empty column: an inverted box), for
+  // the tile search's column reach test
+  if (threadIdx.x < kWave) {
+    float xl = 3e38f, xh = -3e38f, yl = 3e38f, yh = -3e38f;
+    for (int k = c0 + (int)threadIdx.x; k < c1; k += kWave) {
+      const float4 lo = a.box_lo[k], hi = a.box_hi[k];
+      if (lo.w > 0.f) {
+        xl = fminf(xl, lo.x); xh = fmaxf(xh, hi.x);
+        yl = fminf(yl, lo.y); yh = fmaxf(yh, hi.y);
+      }
+    }
+    for (int o = 1; o < kWave; o <<= 1) {
+      xl = fminf(xl, __shfl_xor(xl, o, kWave));
+      xh = fmaxf(xh, __shfl_xor(xh, o, kWave));
+      yl = fminf(yl, __shfl_xor(yl, o, kWave));
+      yh = fmaxf(yh, __shfl_xor(yh, o, kWave));
+    }
+    if (threadIdx.x == 0) a.col_xy[c] = make_float4(xl, xh, yl, yh);
+  }
   // lookup table of the column's z-sorted clusters: for bin edge z_b = b L/nzb
   // the first cluster whose max z >= z_b and the first whose min z > z_b
   const int nzb = a.cg.nzb;
@@ -358,10 +378,47 @@ __device__ __forceinline__ float axis_gap(float alo, float ahi, float blo, float
   return fmaxf(0.f, d - 0.5f * (ahi - alo) - 0.5f * (bhi - blo));
 }
 
+// The image (image_code values) every pair of points of two boxes takes
+// along one axis under min_image_h's rule, or 3 when pairs differ. Rounded
+// subtraction is monotonic in each operand, so the differences of the box
+// extremes bound every pair's.
+__device__ __forceinline__ unsigned box_image(float ilo, float ihi, float jlo, float jhi,
+                                              float hL) {
+#pragma clang fp contract(off)
+  const float smin = jlo - ihi, smax = jhi - ilo;
+  if (smin > hL) return 1u;
+  if (smax < -hL) return 2u;
+  return (smax <= hL && smin >= -hL) ? 0u : 3u;
+}
+
 // bbox-passing j-clusters one i-cluster may have; an entry holds
-// 4 * j-cluster + (its real atoms - 1), never negative
+// 4 * j-cluster + (its real atoms - 1), never negative, and its image byte
+// the 6-bit image code all its pairs share, or kMixedImage
 constexpr int kSearchCand = 1024;
 constexpr int kSearchSegs = 64;     // (column, z segment) units handled per chunk
+constexpr unsigned char kMixedImage = 0xff;
+
+// Per-wave scratch of the tile search.
+struct SearchLds {
+  int cand[kSearchCand];
+  unsigned char img[kSearchCand];
+  int seg_first[kSearchSegs];        // per unit: first cluster,
+  int seg_pre[kSearchSegs + 1];      // clusters before it
+};
+
+// Offsets of image_diff by image code (2 bits per axis), per block.
+__device__ void fill_image_tables(float4* am, float4* cp, const CellGrid& cg) {
+  for (int t = threadIdx.x; t < 64; t += blockDim.x) {
+    float m[3], p[3];
+    for (int d = 0; d < 3; ++d) {
+      const unsigned code = ((unsigned)t >> (2 * d)) & 3u;
+      m[d] = code == 1u ? -cg.L[d] : 0.f;
+      p[d] = code == 2u ? cg.L[d] : 0.f;
+    }
+    am[t] = make_float4(m[0], m[1], m[2], 0.f);
+    cp[t] = make_float4(p[0], p[1], p[2], 0.f);
+  }
+}
 
 // First cluster in [lo, hi) whose value v(k) >= x (v nondecreasing).
 __device__ __forceinline__ int first_ge(const float4* __restrict__ b, int lo, int hi, float x) {
@@ -380,16 +437,21 @@ __device__ __forceinline__ int first_gt(const float4* __restrict__ b, int lo, in
   return lo;
 }
 
-// One wave per i-cluster ic: (1) enumerate the j-clusters of the columns within
-// reach - inside a column only the z-sorted clusters that overlap the
-// i-box's z reach (one or two periodic segments, binary searches) - and keep
-// those the i-cluster owns (owns_pair) whose boxes come closer than r_nl
-// (+ margin); (2) test the 16 slot
+// One wave per i-cluster ic: (1) enumerate the j-clusters of the columns whose
+// atoms come within reach of its box in x-y - inside a column only the
+// z-sorted clusters that overlap the z reach left by that x-y distance (one
+// or two periodic segments, table lookups) - and keep those the i-cluster
+// owns (owns_pair) whose boxes come closer than r_nl (+ margin), with the
+// periodic image all their pairs take if there is one; (2) test the 16 slot
 // pairs of four candidate tiles at once (one lane per pair) with the exact
 // predicate and the exclusions; tiles with a non-empty mask are appended to
 // the i-cluster's list in enumeration order.
-__device__ void search_cluster(const BuildArgs& a, int ic, int* mycand, int* seg_first,
-                               int* seg_pre) {
+__device__ void search_cluster(const BuildArgs& a, int ic, SearchLds& sl, const float4* img_am,
+                               const float4* img_cp) {
+  int* const mycand = sl.cand;
+  unsigned char* const myimg = sl.img;
+  int* const seg_first = sl.seg_first;
+  int* const seg_pre = sl.seg_pre;
   const int lane = threadIdx.x & (kWave - 1);
   const int nclu = a.meta[1];
   if (ic >= nclu) return;
@@ -409,21 +471,14 @@ __device__ void search_cluster(const BuildArgs& a, int ic, int* mycand, int* seg
     if (ny == a.cg.n[1]) cy0 = 0;
     const int ncols = nx * ny;
     const float reach2 = reach * reach;
-    // z reach as up to two segments inside [0, L)
+    // z reach as up to two segments inside [0, L): one unit per column if
+    // the full reach neither wraps nor spans the column, else two (per
+    // column the reach shrinks with its x-y distance, and a unit may be empty)
     const float Lz = a.cg.L[2];
     const float margin = 1e-3f * reach;
-    float za = ilo.z - reach - margin, zb_ = ihi.z + reach + margin;
-    float sa[2], sz[2];
-    int nseg;
-    if (zb_ - za >= Lz) {
-      nseg = 1; sa[0] = -1.f; sz[0] = 2.f * Lz;
-    } else if (za < 0.f) {
-      nseg = 2; sa[0] = 0.f; sz[0] = zb_; sa[1] = za + Lz; sz[1] = 2.f * Lz;
-    } else if (zb_ >= Lz) {
-      nseg = 2; sa[0] = za; sz[0] = 2.f * Lz; sa[1] = -1.f; sz[1] = zb_ - Lz;
-    } else {
-      nseg = 1; sa[0] = za; sz[0] = zb_;
-    }
+    const int nseg =
+        (ilo.z - reach - margin >= 0.f && ihi.z + reach + margin < Lz &&
+         (ihi.z + reach + margin) - (ilo.z - reach - margin) < Lz) ? 1 : 2;
     const int nunits = ncols * nseg;
     for (int u0 = 0; u0 < nunits; u0 += kSearchSegs) {
       const int nu = min(kSearchSegs, nunits - u0);
@@ -435,27 +490,52 @@ __device__ void search_cluster(const BuildArgs& a, int ic, int* mycand, int* seg
         x %= a.cg.n[0]; x += x < 0 ? a.cg.n[0] : 0;
         y %= a.cg.n[1]; y += y < 0 ? a.cg.n[1] : 0;
         int col = y * a.cg.n[0] + x;
-        // clusters overlapping [sa, sz] (max z >= sa and min z <= sz), from
-        // the column's lookup table one bin wider on each side: a superset,
-        // the box test below removes the extra clusters
-        const int2* zt = a.zbin + (size_t)col * (a.cg.nzb + 1);
-        auto lower = [&](float z) {
-          return min(max((int)floorf(z * a.cg.inv_zb) - 1, 0), a.cg.nzb);
-        };
-        auto upper = [&](float z) {
-          return min(max((int)ceilf(z * a.cg.inv_zb) + 1, 0), a.cg.nzb);
-        };
-        int f = zt[lower(sa[sg])].x;
-        int l = zt[upper(sz[sg])].y;
-        if (sg == 1) {
-          // the two segments sit at opposite ends of the column; a cluster
-          // reaching into both is taken once, by segment 0
-          const int f0 = zt[lower(sa[0])].x, l0 = zt[upper(sz[0])].y;
-          if (sa[1] > sa[0]) f = max(f, l0);
-          else l = min(l, f0);
+        // the column's x-y gap to the i-box bounds the z reach it needs
+        const float4 cxy = a.col_xy[col];
+        float gap2 = 3e38f;
+        if (cxy.x <= cxy.y) {
+          const float gx = axis_gap(ilo.x, ihi.x, cxy.x, cxy.y, a.cg.L[0]);
+          const float gy = axis_gap(ilo.y, ihi.y, cxy.z, cxy.w, a.cg.L[1]);
+          gap2 = gx * gx + gy * gy;
         }
-        first = f;
-        cnt = max(0, l - f);
+        if (gap2 < reach2) {
+          const float zr = sqrtf(reach2 - gap2) + margin;
+          const float za = ilo.z - zr, zb_ = ihi.z + zr;
+          float sa[2], sz[2];
+          bool two = true;
+          if (zb_ - za >= Lz) {
+            sa[0] = -1.f; sz[0] = 2.f * Lz; two = false;
+          } else if (za < 0.f) {
+            sa[0] = 0.f; sz[0] = zb_; sa[1] = za + Lz; sz[1] = 2.f * Lz;
+          } else if (zb_ >= Lz) {
+            sa[0] = za; sz[0] = 2.f * Lz; sa[1] = -1.f; sz[1] = zb_ - Lz;
+          } else {
+            sa[0] = za; sz[0] = zb_; two = false;
+          }
+          // clusters overlapping [sa, sz] (max z >= sa and min z <= sz),
+          // from the column's lookup table one bin wider on each side: a
+          // superset, the box test below removes the extra clusters
+          const int2* zt = a.zbin + (size_t)col * (a.cg.nzb + 1);
+          auto lower = [&](float z) {
+            return min(max((int)floorf(z * a.cg.inv_zb) - 1, 0), a.cg.nzb);
+          };
+          auto upper = [&](float z) {
+            return min(max((int)ceilf(z * a.cg.inv_zb) + 1, 0), a.cg.nzb);
+          };
+          if (sg == 0 || two) {
+            int f = zt[lower(sa[sg])].x;
+            int l = zt[upper(sz[sg])].y;
+            if (sg == 1) {
+              // the two segments sit at opposite ends of the column; a
+              // cluster reaching into both is taken once, by segment 0
+              const int f0 = zt[lower(sa[0])].x, l0 = zt[upper(sz[0])].y;
+              if (sa[1] > sa[0]) f = max(f, l0);
+              else l = min(l, f0);
+            }
+            first = f;
+            cnt = max(0, l - f);
+          }
+        }
       }
       int v = cnt;
       for (int o = 1; o < kWave; o <<= 1) {
@@ -471,31 +551,53 @@ __device__ void search_cluster(const BuildArgs& a, int ic, int* mycand, int* seg
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       const int total = __shfl(v, nu - 1, kWave);
+      // cluster f of the units, from a binary search over them
+      auto cluster_of = [&](int f) {
+        int lo = 0, hi = nu - 1;
+        while (lo < hi) {
+          int mid = (lo + hi + 1) >> 1;
+          if (seg_pre[mid] <= f) lo = mid; else hi = mid - 1;
+        }
+        return seg_first[lo] + (f - seg_pre[lo]);
+      };
+      // the boxes of the next 64 clusters are loaded while the current ones
+      // are tested
+      int jcn = lane < total ? cluster_of(lane) : 0;
+      float4 lon = lane < total ? a.box_lo[jcn] : make_float4(0.f, 0.f, 0.f, 0.f);
+      float4 hin = lane < total ? a.box_hi[jcn] : make_float4(0.f, 0.f, 0.f, 0.f);
       for (int f0 = 0; f0 < total; f0 += kWave) {
-        int f = f0 + lane;
+        const int jc = jcn;
+        const float4 jlo = lon, jhi = hin;
+        const int fn = f0 + kWave + lane;
+        if (fn < total) {
+          jcn = cluster_of(fn);
+          lon = a.box_lo[jcn];
+          hin = a.box_hi[jcn];
+        }
         bool pass = false;
-        int jc = 0, nvj = 0;
-        if (f < total) {
-          int lo = 0, hi = nu - 1;
-          while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (seg_pre[mid] <= f) lo = mid; else hi = mid - 1;
-          }
-          jc = seg_first[lo] + (f - seg_pre[lo]);
-          float4 jlo = a.box_lo[jc], jhi = a.box_hi[jc];
+        int nvj = 0;
+        unsigned cimg = 0;
+        if (f0 + lane < total) {
           nvj = (int)jlo.w;
           if (jlo.w > 0.f && owns_pair(ic, jc, a.half)) {
             float gx = axis_gap(ilo.x, ihi.x, jlo.x, jhi.x, a.cg.L[0]);
             float gy = axis_gap(ilo.y, ihi.y, jlo.y, jhi.y, a.cg.L[1]);
             float gz = axis_gap(ilo.z, ihi.z, jlo.z, jhi.z, a.cg.L[2]);
             pass = gx * gx + gy * gy + gz * gz < reach2;
+            const unsigned bx = box_image(ilo.x, ihi.x, jlo.x, jhi.x, a.cg.hL[0]);
+            const unsigned by = box_image(ilo.y, ihi.y, jlo.y, jhi.y, a.cg.hL[1]);
+            const unsigned bz = box_image(ilo.z, ihi.z, jlo.z, jhi.z, a.cg.hL[2]);
+            cimg = (bx == 3u || by == 3u || bz == 3u) ? kMixedImage : (bx | by << 2 | bz << 4);
           }
         }
         unsigned long long m = __ballot(pass);
         int before = __popcll(m & ((1ull << lane) - 1ull));
         if (pass) {
           int slot = ncand + before;
-          if (slot < kSearchCand) mycand[slot] = jc * kClusterSize + (nvj - 1);
+          if (slot < kSearchCand) {
+            mycand[slot] = jc * kClusterSize + (nvj - 1);
+            myimg[slot] = (unsigned char)cimg;
+          }
         }
         ncand += __popcll(m);
       }
@@ -536,18 +638,41 @@ __device__ void search_cluster(const BuildArgs& a, int ic, int* mycand, int* seg
   }
   const bool ex_more = ee - eb > 4;
   int count = 0;
+  // Appends the tiles of the pairs in tk (bit 4a + b of tile t's mask is
+  // lane 16t + 4a + b) with image code limg, in tile order.
+  auto emit = [&](int jc, unsigned long long tk, unsigned limg) {
+    const unsigned mask = (unsigned)((tk >> (16 * t)) & 0xffffull);
+    const unsigned long long nonempty = __ballot(b == 0 && ia == 0 && mask != 0);
+    const int before = __popcll(nonempty & ((1ull << lane) - 1ull));
+    if (ia == 0 && b == 0 && mask != 0) {
+      const int k = count + before;
+      if (k < a.cap) a.tiles[(size_t)ic * a.cap + k] = make_uint2((unsigned)jc, mask | limg << 16);
+    }
+    count += __popcll(nonempty);
+  };
   // One group of four candidate tiles: c = this lane's candidate entry (-1
-  // past the end), pj = its j slot's position.
-  auto group = [&](int c, float4 pj) {
+  // past the end), cimg its image byte, pj its j slot's position.
+  auto group = [&](int c, unsigned cimg, float4 pj) {
     const int jc = c >= 0 ? c / kClusterSize : -1;
     const int nv = c >= 0 ? c % kClusterSize + 1 : 0;
+    // every candidate of the group with one image for all its pairs: the
+    // differences from the image table (rounded as min_image_h rounds them)
+    const bool shared = __ballot(c >= 0 && cimg == kMixedImage) == 0ull;
     unsigned bit = 0, img = 0;
     const int sj = jc * kClusterSize + b;
     // the cluster's own tile: slot pairs a < b (half list) or a != b
     if (jc >= 0 && ivalid && b < nv && (jc != ic || b > ia || (!a.half && b < ia))) {
-      float dx = min_image_h(pi.x, lmx, pj.x, a.cg.L[0], a.cg.hL[0]);
-      float dy = min_image_h(pi.y, lmy, pj.y, a.cg.L[1], a.cg.hL[1]);
-      float dz = min_image_h(pi.z, lmz, pj.z, a.cg.L[2], a.cg.hL[2]);
+      float dx, dy, dz;
+      if (shared) {
+        const float4 am = img_am[cimg], cp = img_cp[cimg];
+        dx = image_diff(pi.x, pj.x, am.x, cp.x);
+        dy = image_diff(pi.y, pj.y, am.y, cp.y);
+        dz = image_diff(pi.z, pj.z, am.z, cp.z);
+      } else {
+        dx = min_image_h(pi.x, lmx, pj.x, a.cg.L[0], a.cg.hL[0]);
+        dy = min_image_h(pi.y, lmy, pj.y, a.cg.L[1], a.cg.hL[1]);
+        dz = min_image_h(pi.z, lmz, pj.z, a.cg.L[2], a.cg.hL[2]);
+      }
       if (dist2(dx, dy, dz) < a.cg.rnl2) {
         bool excluded = sj == ex0 || sj == ex1 || sj == ex2 || sj == ex3;
         if (ex_more && !excluded) {
@@ -555,46 +680,46 @@ __device__ void search_cluster(const BuildArgs& a, int ic, int* mycand, int* seg
           for (int k = eb + 4; k < ee; ++k) excluded |= (a.ex_idx[k] == aj);
         }
         bit = excluded ? 0u : 1u;
-        img = image_code(pi.x, pj.x, a.cg.hL[0]) | image_code(pi.y, pj.y, a.cg.hL[1]) << 2 |
-              image_code(pi.z, pj.z, a.cg.hL[2]) << 4;
+        if (!shared)
+          img = image_code(pi.x, pj.x, a.cg.hL[0]) | image_code(pi.y, pj.y, a.cg.hL[1]) << 2 |
+                image_code(pi.z, pj.z, a.cg.hL[2]) << 4;
       }
     }
-    // One tile entry per periodic image among a tile's pairs (a single one
-    // unless the box is small next to the clusters and the list radius): in
-    // each round, the pairs sharing the image of the tile's first remaining
-    // pair. Bit 4a + b of tile t's mask is lane 16t + 4a + b.
     unsigned long long rem = __ballot(bit != 0);
+    if (shared) {
+      emit(jc, rem, cimg);
+      return;
+    }
+    // One tile entry per periodic image among a tile's pairs (several only
+    // in a box small next to the clusters and the list radius): in each
+    // round, the pairs sharing the image of the tile's first remaining pair.
     while (rem) {
       const unsigned tm = (unsigned)((rem >> (16 * t)) & 0xffffull);
       const int lead = 16 * t + (tm ? __ffs(tm) - 1 : 0);
       const unsigned limg = (unsigned)__shfl((int)img, lead, kWave);
       const unsigned long long tk = __ballot(((rem >> lane) & 1ull) && img == limg);
-      const unsigned mask = (unsigned)((tk >> (16 * t)) & 0xffffull);
-      const unsigned long long nonempty = __ballot(b == 0 && ia == 0 && mask != 0);
-      const int before = __popcll(nonempty & ((1ull << lane) - 1ull));
-      if (ia == 0 && b == 0 && mask != 0) {
-        const int k = count + before;
-        if (k < a.cap)
-          a.tiles[(size_t)ic * a.cap + k] = make_uint2((unsigned)jc, mask | limg << 16);
-      }
-      count += __popcll(nonempty);
+      emit(jc, tk, limg);
       rem &= ~tk;
     }
   };
   // two groups per iteration with fixed registers: the j positions of the
   // next group of each half are in flight while a group is tested
   auto cand_at = [&](int g) { return (g + t < ncand) ? mycand[g + t] : -1; };
+  auto img_at = [&](int g) { return (g + t < ncand) ? (unsigned)myimg[g + t] : 0u; };
   auto pos_of = [&](int c) {
     return c >= 0 ? a.xs[(c & ~(kClusterSize - 1)) + b] : make_float4(0.f, 0.f, 0.f, 0.f);
   };
   int cA = cand_at(0), cB = cand_at(4);
+  unsigned iA = img_at(0), iB = img_at(4);
   float4 pA = pos_of(cA), pB = pos_of(cB);
   for (int g = 0; g < ncand; g += 8) {
-    group(cA, pA);
+    group(cA, iA, pA);
     cA = cand_at(g + 8);
+    iA = img_at(g + 8);
     pA = pos_of(cA);
-    if (g + 4 < ncand) group(cB, pB);
+    if (g + 4 < ncand) group(cB, iB, pB);
     cB = cand_at(g + 12);
+    iB = img_at(g + 12);
     pB = pos_of(cB);
   }
   // pad the list to whole groups of four tiles with empty tiles (mask 0)
@@ -603,9 +728,13 @@ __device__ void search_cluster(const BuildArgs& a, int ic, int* mycand, int* seg
   if (lane < padded - kept) a.tiles[(size_t)ic * a.cap + kept + lane] = make_uint2(0u, 0u);
   if (lane == 0) {
     a.tile_count[ic] = padded;
-    if (count > a.cap) atomicOr(a.flags, MDX_FLAG_NL_OVERFLOW);
+    // only a cluster whose tiles overflow the capacity reports its count
+    // (one device-scope atomic per wave on one address would serialize)
+    if (count > a.cap) {
+      atomicOr(a.flags, MDX_FLAG_NL_OVERFLOW);
+      atomicMax(a.nl_needed, count);
+    }
     if (overflow) atomicOr(a.flags, MDX_FLAG_CELL_OVERFLOW);
-    atomicMax(a.nl_needed, count);
   }
 }
 
@@ -638,11 +767,12 @@ __global__ void __launch_bounds__(kColThreads) k_col_sort(BuildArgs a) {
 
 __global__ void __launch_bounds__(256) k_tile_search(BuildArgs a) {
   if (gated_off(a.gate)) return;
-  __shared__ int cand[4][kSearchCand];
-  __shared__ int seg_first[4][kSearchSegs];
-  __shared__ int seg_pre[4][kSearchSegs + 1];
+  __shared__ SearchLds sl[4];
+  __shared__ float4 img_am[64], img_cp[64];
+  fill_image_tables(img_am, img_cp, a.cg);
+  __syncthreads();
   const int w = threadIdx.x / kWave;
-  search_cluster(a, blockIdx.x * 4 + w, cand[w], seg_first[w], seg_pre[w]);
+  search_cluster(a, blockIdx.x * 4 + w, sl[w], img_am, img_cp);
 }
 
 // ---- all phases in one cooperative launch ------------------------------------
@@ -655,9 +785,10 @@ __global__ void __launch_bounds__(kBuildThreads) k_build_all(BuildArgs a) {
   if (gated_off(a.gate)) return;
   cooperative_groups::grid_group grid = cooperative_groups::this_grid();
   __shared__ float2 st[kColStage];
-  __shared__ int cand[4][kSearchCand];
-  __shared__ int seg_first[4][kSearchSegs];
-  __shared__ int seg_pre[4][kSearchSegs + 1];
+  __shared__ SearchLds sl[4];
+  __shared__ float4 img_am[64], img_cp[64];
+  fill_image_tables(img_am, img_cp, a.cg);
+  __syncthreads();
   const int nthreads = gridDim.x * blockDim.x;
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   // bounds rounded to whole blocks: the atom loops stay uniform per wave
@@ -672,7 +803,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_build_all(BuildArgs a) {
   grid.sync();
   const int w = threadIdx.x / kWave;
   for (int ic = blockIdx.x * 4 + w; ic < a.max_clusters; ic += gridDim.x * 4)
-    search_cluster(a, ic, cand[w], seg_first[w], seg_pre[w]);
+    search_cluster(a, ic, sl[w], img_am, img_cp);
 }
 
 int build_coop_blocks(int max_clusters, int n, int ncol) {
@@ -724,7 +855,7 @@ hipError_t launch_build_list(Ctx& c, const float* pos, const int* gate, hipEvent
   BuildArgs a{gate, pos, n, c.cg, c.cell_of, c.cell_count, c.x_build, c.flags,
               c.cell_start, c.cell_cursor, c.slot_start, c.meta, c.nl_needed,
               c.perm_unsorted, c.q, c.atype, c.perm, c.inv_perm, c.xs, c.ts, c.zb,
-              c.box_lo, c.box_hi,
+              c.box_lo, c.box_hi, c.col_xy,
               ZRangeArgs{c.zb, c.slot_start, c.cell_start, c.brick_z,
                          c.has_pme ? c.pg.nb[2] : 0, ncol, c.cg.L[2], c.brick_zr},
               c.ex_start, c.ex_idx, c.nl_cap, c.half_list ? 1 : 0, c.zbin, c.tiles,

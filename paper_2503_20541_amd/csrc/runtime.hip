@@ -411,6 +411,7 @@ int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
   if ((rc = dev_alloc(x, &c.zb, c.max_slots)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.box_lo, c.max_clusters)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.box_hi, c.max_clusters)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.col_xy, ncol)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.x_build, (size_t)3 * n)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.tile_count, c.max_clusters)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.nl_needed, 1)) != MDX_OK) return rc;
