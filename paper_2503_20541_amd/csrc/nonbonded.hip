@@ -23,30 +23,31 @@
 
 namespace mdx {
 
-// erfc(x) = exp(-x^2) R(x): R = t P(t), t = 1/(1 + 0.4 x), with P of degree 9
-// fitted (weighted least squares iterated towards equal ripple) to the
-// scaled complementary error function exp(x^2) erfc(x) on [0, 6]; relative
-// error below 1e-9 in exact arithmetic, a few float32 ulps as evaluated.
-// The caller multiplies by exp(-x^2), which it needs for the force anyway.
+// erfc(x) = exp(-x^2) R(x): R = t P(t), t = 1/(1 + 0.42 x), with P of degree 7
+// fitted (weighted least squares on the relative error, iterated towards
+// equal ripple; fit_erfc.py beside this file) to the scaled complementary
+// error function exp(x^2) erfc(x) on [0, 6]: relative error below 4e-8 in
+// exact arithmetic, about 3.5e-7 as evaluated in float32 (the rounding of t
+// dominates). The caller multiplies by exp(-x^2), which it needs for the
+// force anyway.
 __device__ __forceinline__ float erfc_scaled(float x) {
-  const float t = __builtin_amdgcn_rcpf(fmaf(0.4f, x, 1.0f));
-  float p = -3.839134390e-02f;
-  p = fmaf(p, t, 2.474407330e-01f);
-  p = fmaf(p, t, -6.196206523e-01f);
-  p = fmaf(p, t, 7.158111156e-01f);
-  p = fmaf(p, t, -4.316577684e-01f);
-  p = fmaf(p, t, 3.558386304e-01f);
-  p = fmaf(p, t, 9.873089759e-02f);
-  p = fmaf(p, t, 2.220756708e-01f);
-  p = fmaf(p, t, 2.240124465e-01f);
-  p = fmaf(p, t, 2.257602716e-01f);
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.42f, x, 1.0f));
+  float p = 7.619556785e-02f;
+  p = fmaf(p, t, -3.458804786e-01f);
+  p = fmaf(p, t, 4.864609241e-01f);
+  p = fmaf(p, t, -1.745370179e-01f);
+  p = fmaf(p, t, 2.932607532e-01f);
+  p = fmaf(p, t, 1.868254989e-01f);
+  p = fmaf(p, t, 2.409472317e-01f);
+  p = fmaf(p, t, 2.367275357e-01f);
   return p * t;
 }
 
 struct PairParams {
   float L[3], hL[3];
   float rc2;
-  float alpha_hi, alpha_lo;   // Ewald alpha as a float pair
+  float alpha;                // Ewald alpha
+  float exp_c;                // -alpha^2 log2(e): exp(-alpha^2 r^2) = 2^(exp_c r^2)
   float two_a_sqrtpi;         // 2 alpha / sqrt(pi)
   float coulomb_k;
   float r_s, r_c, inv_sw;     // switch r_s, r_c and 1/(r_c - r_s)
@@ -131,6 +132,7 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
   double e_lj = 0.0, e_c = 0.0;
   if (active) {
     const float4 pi = xs[si];
+    const float qik = pp.coulomb_k * pi.w;   // k_e q_i, per lane
     const int trow = ts[si] * pp.ntypes;
     // List selection (the flags are the same for the whole grid): the full
     // list, emitting the pruned list and the prune positions, on a rebuild
@@ -161,14 +163,14 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
       if (emit) {
         // keep tile tt if any of its pairs is within r_p; lane (row 0, tile
         // tt, slot 0) writes it, in list order
-        const unsigned long long nearm = __ballot(on && r2 < pr.rp2);
+        const unsigned long long nearm = __builtin_amdgcn_ballot_w64(on && r2 < pr.rp2);
         const bool keep = ((nearm >> (4 * tt)) & 0x000f000f000f000full) != 0ull;
         const bool leader = ia == 0 && jb == 0;
-        const unsigned long long km = __ballot(leader && keep);
+        const unsigned long long km = __builtin_amdgcn_ballot_w64(leader && keep);
         if (leader && keep) pl[pn + __popcll(km & ((1ull << lane) - 1ull))] = e;
         pn += __popcll(km);
       }
-      const unsigned long long hit = __ballot(in);
+      const unsigned long long hit = __builtin_amdgcn_ballot_w64(in);
       if (hit == 0ull) return;
       float gx = 0.f, gy = 0.f, gz = 0.f;   // force on j (minus the force on i)
       if (in) {
@@ -193,12 +195,11 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
         float ec = 0.f;
         if (COUL) {
           float r = r2 * rinv;
-          float ar = fmaf(pp.alpha_hi, r, pp.alpha_lo * r);
-          // exp(-x^2) as 2^(-x^2 log2 e) on the transcendental unit; the
-          // energies on measurement steps are evaluated separately in FP64
-          float ex = __builtin_amdgcn_exp2f(-ar * ar * 1.44269504088896341f);
-          ec = erfc_scaled(ar) * ex;
-          f_over_r += pp.coulomb_k * (pi.w * pj.w) * (ec * rinv + pp.two_a_sqrtpi * ex) * rinv2;
+          // exp(-alpha^2 r^2) as 2^(exp_c r^2) on the transcendental unit;
+          // the energies on measurement steps are evaluated separately in FP64
+          float ex = __builtin_amdgcn_exp2f(pp.exp_c * r2);
+          ec = erfc_scaled(pp.alpha * r) * ex;
+          f_over_r += qik * pj.w * (ec * rinv + pp.two_a_sqrtpi * ex) * rinv2;
         }
         gx = f_over_r * dx;
         gy = f_over_r * dy;
@@ -370,8 +371,8 @@ hipError_t launch_nonbonded(Ctx& c, bool energy, const int* gate_now, const int*
     pp.hL[d] = c.cg.hL[d];
   }
   pp.rc2 = c.cg.rc2;
-  pp.alpha_hi = (float)c.alpha;
-  pp.alpha_lo = (float)(c.alpha - (double)pp.alpha_hi);
+  pp.alpha = (float)c.alpha;
+  pp.exp_c = (float)(-c.alpha * c.alpha / M_LN2);
   pp.alpha_d = c.alpha;
   pp.ntypes = c.n_types;
   pp.two_a_sqrtpi = (float)(2.0 * c.alpha / sqrt(M_PI));
