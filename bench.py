@@ -44,7 +44,7 @@ VALU_PEAK_T = 256 * 64 * 2.4e9 / 1e12
 # passes, scaled by the same counters on a plain copy of known size
 # (profiles/pair_kernel_counters_water96k.md); set to None when the kernel
 # changes until the counters are taken again.
-PAIR_TRAFFIC_BYTES = None
+PAIR_TRAFFIC_BYTES = 67.8e6
 
 
 def parse():
