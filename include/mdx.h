@@ -253,6 +253,17 @@ int mdx_integrate_step(mdx_ctx* ctx, float* pos, float* vel, float* force, int32
 /* Synchronising. Returns the latched MDX_FLAG_* bits in *flags and clears them. */
 int mdx_get_status(mdx_ctx* ctx, uint32_t* flags);
 
+/*
+ * Periodic image counters (the wrap of Sec. II.D.1's position update):
+ * img (dev int32[3][N], caller atom order, caller-owned) receives, per
+ * coordinate, the net number of box lengths mdx_integrate_step has wrapped
+ * the atom by since the context was created (+1 each time x >= L_d moved it
+ * down by L_d, -1 each time x < 0 moved it up), so pos + img * L is the
+ * unwrapped trajectory. The copy is queued on the context's stream (not
+ * synchronising). MDX_E_INVALID for a NULL img.
+ */
+int mdx_get_images(mdx_ctx* ctx, int32_t* img);
+
 /* Fills *info (host). Synchronising once a list exists: the list is copied
  * to the host to count its entries. */
 int mdx_get_info(mdx_ctx* ctx, mdx_info* info);

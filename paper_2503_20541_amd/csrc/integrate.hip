@@ -9,12 +9,19 @@
 
 namespace mdx {
 
-__device__ __forceinline__ float wrap_box(float x, float L) {
+// x wrapped into [0, L); wraps gets the box lengths subtracted (+1 / -1).
+__device__ __forceinline__ float wrap_box(float x, float L, int& wraps) {
+  wraps = 0;
   if (x >= L) {
     x -= L;
+    wraps = 1;
   } else if (x < 0.f) {
     x += L;
-    if (x >= L) x = 0.f;   // a tiny negative x rounds onto L
+    wraps = -1;
+    if (x >= L) {   // a tiny negative x rounds onto L: it stays at 0
+      x = 0.f;
+      wraps = 0;
+    }
   }
   return x;
 }
@@ -32,7 +39,7 @@ __global__ void __launch_bounds__(256) k_begin_step(
     int n, CellGrid cg, float half_dt, float dt, float half_skin2, float4* __restrict__ xs,
     unsigned* __restrict__ flags, int* __restrict__ gate_now, int* __restrict__ gate_next,
     const float4* __restrict__ xp, float prune_move2, int* __restrict__ pgate_now,
-    int* __restrict__ pgate_next, int force_rebuild) {
+    int* __restrict__ pgate_next, int force_rebuild, int* __restrict__ img) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s == 0) {
     *gate_next = 0;
@@ -48,8 +55,10 @@ __global__ void __launch_bounds__(256) k_begin_step(
     const size_t k = (size_t)d * n + a;
     const float v = vel[k] + h * force[k];
     vel[k] = v;
-    x[d] = wrap_box(pos[k] + dt * v, cg.L[d]);
+    int wraps;
+    x[d] = wrap_box(pos[k] + dt * v, cg.L[d], wraps);
     pos[k] = x[d];
+    if (wraps) img[k] += wraps;
   }
   const float bx = x_build[a], by = x_build[n + a], bz = x_build[2 * n + a];
   const float dx = min_image(bx, x[0], cg.L[0], cg.hL[0]);
@@ -140,7 +149,7 @@ hipError_t launch_begin_step(Ctx& c, float* pos, float* vel, const float* force,
   k_begin_step<<<(c.max_slots + 255) / 256, 256, 0, c.stream>>>(
       pos, vel, force, c.hdt_scale, c.perm, c.q, c.x_build, c.meta, c.n, c.cg, 0.5f * dt, dt,
       h * h, c.xs, c.flags, gate_now, gate_next, c.xp, c.prune_move2, pgate_now, pgate_next,
-      force_rebuild ? 1 : 0);
+      force_rebuild ? 1 : 0, c.img);
   return hipGetLastError();
 }
 

@@ -107,6 +107,7 @@ struct Ctx {
   float4* box_lo = nullptr;    // [max_clusters] cluster box (w = real atoms)
   float4* box_hi = nullptr;
   float4* col_xy = nullptr;     // [ncell] x min, x max, y min, y max of a column's atoms
+  int* img = nullptr;           // [3][n] periodic image counters (atom order)
   float* x_build = nullptr;    // [3][n] positions at the last build (caller order)
   // [max_clusters][nl_cap] tiles: x = j-cluster, y = 16-bit pair mask (bit
   // 4 a + b: i slot a, j slot b) | periodic image of the j-cluster << 16

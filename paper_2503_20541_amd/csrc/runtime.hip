@@ -412,6 +412,8 @@ int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
   if ((rc = dev_alloc(x, &c.box_lo, c.max_clusters)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.box_hi, c.max_clusters)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.col_xy, ncol)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.img, (size_t)3 * n)) != MDX_OK) return rc;
+  MDX_TRY(hipMemset(c.img, 0, sizeof(int) * 3 * (size_t)n));
   if ((rc = dev_alloc(x, &c.x_build, (size_t)3 * n)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.tile_count, c.max_clusters)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.nl_needed, 1)) != MDX_OK) return rc;
@@ -761,6 +763,14 @@ int mdx_get_status(mdx_ctx* x, uint32_t* flags) {
   MDX_TRY(hipMemsetAsync(c.flags, 0, sizeof(unsigned), c.stream));
   MDX_TRY(hipStreamSynchronize(c.stream));
   *flags = f;
+  return MDX_OK;
+}
+
+int mdx_get_images(mdx_ctx* x, int32_t* img) {
+  if (check_ctx(x) || !img) return MDX_E_INVALID;
+  Ctx& c = x->c;
+  MDX_TRY(hipMemcpyAsync(img, c.img, sizeof(int32_t) * 3 * (size_t)c.n,
+                         hipMemcpyDeviceToDevice, c.stream));
   return MDX_OK;
 }
 

@@ -59,7 +59,7 @@ MDX_TIMING_BUILD = 2
 EXPORTED = ("mdx_error_string", "mdx_create", "mdx_destroy", "mdx_set_stream",
             "mdx_build_neighbors", "mdx_get_neighbor_pairs", "mdx_compute_nonbonded",
             "mdx_compute_pme", "mdx_integrate_step", "mdx_get_status", "mdx_get_info",
-            "mdx_set_timing", "mdx_get_timing")
+            "mdx_set_timing", "mdx_get_timing", "mdx_get_images")
 
 _fp = ctypes.POINTER(ctypes.c_float)
 _ip = ctypes.POINTER(ctypes.c_int32)
@@ -107,6 +107,7 @@ _lib.mdx_compute_nonbonded.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _lib.mdx_compute_pme.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _lib.mdx_integrate_step.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_float, _vp]
 _lib.mdx_get_status.argtypes = [_vp, ctypes.POINTER(ctypes.c_uint32)]
+_lib.mdx_get_images.argtypes = [_vp, _vp]
 _lib.mdx_get_info.argtypes = [_vp, ctypes.POINTER(Info)]
 _lib.mdx_set_timing.argtypes = [_vp, ctypes.c_int]
 _lib.mdx_get_timing.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
@@ -270,6 +271,11 @@ def get_status(ctx: int) -> int:
     f = ctypes.c_uint32(0)
     _check(_lib.mdx_get_status(ctx, ctypes.byref(f)), "mdx_get_status")
     return int(f.value)
+
+
+def get_images(ctx: int, img) -> None:
+    """Copies the image counters (int32 [3][N] device tensor) into img."""
+    _check(_lib.mdx_get_images(ctx, _ptr(img)), "mdx_get_images")
 
 
 def get_info(ctx: int) -> Info:

@@ -20,8 +20,11 @@ def test_lj1k_trajectory_tracks_oracle():
         mdx.compute_nonbonded(ctx, t["pos"], t["force"])
         en = torch.zeros((n_steps, mdx.MDX_N_ENERGY), dtype=torch.float64, device="cuda:0")
         mdx.integrate_step(ctx, t["pos"], t["vel"], t["force"], n_steps, s.dt, en)
+        img = torch.zeros((3, s.n_atoms), dtype=torch.int32, device="cuda:0")
+        mdx.get_images(ctx, img)
         torch.cuda.synchronize()
         x_gpu = t["pos"].cpu().numpy().astype(np.float64)
+        img = img.cpu().numpy()
         E = en.cpu().numpy()
         assert mdx.get_status(ctx) == 0
     F = lambda p: forcefield.total_forces_fp64(s, p)[1]
@@ -36,6 +39,13 @@ def test_lj1k_trajectory_tracks_oracle():
     d_f32 = dev(ref32["pos"].astype(np.float64), ref64["pos"])
     assert d_gpu <= 10 * max(d_f32, 1e-7), (d_gpu, d_f32)
     assert np.all(np.isfinite(E))
+    # image counters: the unwrapped trajectories agree (a wrong count would be
+    # off by a box length), and some atoms did cross a face
+    L = s.box.astype(np.float64)[:, None]
+    unwrapped_gpu = x_gpu + img * L
+    unwrapped_ref = ref64["pos"] + ref64["image"] * L
+    assert np.abs(unwrapped_gpu - unwrapped_ref).max() < 1e-2
+    assert np.count_nonzero(img) > 0
 
 
 def test_lj_switched_energy_conservation_dt2():
