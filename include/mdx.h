@@ -215,7 +215,13 @@ int mdx_get_neighbor_pairs(mdx_ctx* ctx, int32_t* pairs_host, int64_t cap, int64
  * the list), the erf exclusion correction (FP64), bonds and angles.
  * force (dev [3][N]) is OVERWRITTEN. energy (dev double[6], slots
  * MDX_ENERGY_LJ..MDX_ENERGY_ANGLE) may be NULL; with energy the variant with
- * FP64 reductions runs. virial must be NULL (MDX_E_UNSUPPORTED otherwise).
+ * FP64 reductions runs. virial (dev double[9], row-major, symmetric, may be
+ * NULL) is OVERWRITTEN with the virial of these terms, W_ab = sum over
+ * interactions of sum_k s_k,a F_k,b (s_k: member atom positions relative to
+ * one member of the interaction, minimum image; for a pair, r_j - r_i times
+ * the force on j), in FP64 (energy units); the pressure follows as
+ * P = (2 E_kin + tr W) / (3 V) with the reciprocal-space part from
+ * mdx_compute_pme added to W.
  * Latches MDX_FLAG_NL_STALE if an atom moved > r_g/2 since the build.
  */
 int mdx_compute_nonbonded(mdx_ctx* ctx, const float* pos, float* force, double* energy,
@@ -227,7 +233,10 @@ int mdx_compute_nonbonded(mdx_ctx* ctx, const float* pos, float* force, double* 
  * the influence function B(m) C(m), inverse FFT and force gather. force (dev
  * [3][N]) is ACCUMULATED into. energy (dev double[1], MDX_ENERGY_COUL_REC)
  * may be NULL. Needs a built list (atoms are processed in cell order).
- * virial must be NULL.
+ * virial (dev double[9], may be NULL) is OVERWRITTEN with the SPME virial
+ * sum_m E(m) (delta_ab - 2 (1 + pi^2 m^2 / alpha^2) m_a m_b / m^2), FP64,
+ * the strain derivative of E_rec (W_aa = -L_a dE_rec/dL_a with the atoms
+ * scaled along).
  */
 int mdx_compute_pme(mdx_ctx* ctx, const float* pos, float* force, double* energy,
                     double* virial);

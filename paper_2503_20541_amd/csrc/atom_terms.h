@@ -36,12 +36,15 @@ struct Topology {
 // by its lower atom, a bond by its first atom, an angle by its vertex. With
 // nparts > 1 the call handles only the terms whose index in the atom's lists
 // is part modulo nparts (the callers sum the parts in a fixed order).
-template <bool ENERGY, bool COUL>
+// With VIR, each term also adds its virial sum_k s_k (x) F_k (s_k: member
+// positions relative to one member, minimum image) to w[6], booked like its
+// energy.
+template <bool ENERGY, bool COUL, bool VIR = false>
 __device__ __forceinline__ void bonded_excl_atom(int a, const float* __restrict__ pos, int n,
                                                  const BondedParams& bp, const Topology& tp,
                                                  float& fx, float& fy, float& fz, double& e_ex,
                                                  double& e_b, double& e_a, int part = 0,
-                                                 int nparts = 1) {
+                                                 int nparts = 1, double* w = nullptr) {
   float xa = pos[a], ya = pos[n + a], za = pos[2 * n + a];
   if (COUL) {
     // -k_e q_a q_b erf(alpha r)/r over excluded partners, in FP64 with the
@@ -69,6 +72,7 @@ __device__ __forceinline__ void bonded_excl_atom(int a, const float* __restrict_
       gy += s * d[1];
       gz += s * d[2];
       if (ENERGY && a < b) e_ex += u;
+      if (VIR && a < b) vir_add_dd(w, -s, d[0], d[1], d[2]);   // d (x) F_b, F_b = -s d
     }
     fx += (float)gx;
     fy += (float)gy;
@@ -88,6 +92,7 @@ __device__ __forceinline__ void bonded_excl_atom(int a, const float* __restrict_
     fy += sgn * g * dy;
     fz += sgn * g * dz;
     if (ENERGY && a == i) e_b += (double)(tp.bond_k[t] * dr * dr);
+    if (VIR && a == i) vir_add_dd(w, (double)g, dx, dy, dz);   // d (x) F_j, F_j = g d
   }
   for (int k = tp.at_start[a] + part; k < tp.at_start[a + 1]; k += nparts) {
     int t = tp.at_idx[k];
@@ -118,6 +123,15 @@ __device__ __forceinline__ void bonded_excl_atom(int a, const float* __restrict_
     if (a == l) { fx += flx; fy += fly; fz += flz; }
     if (a == j) { fx -= fix + flx; fy -= fiy + fly; fz -= fiz + flz; }
     if (ENERGY && a == j) e_a += (double)(tp.angle_k[t] * dth * dth);
+    if (VIR && a == j) {
+      // (r_i - r_j) (x) F_i + (r_l - r_j) (x) F_l, symmetrised
+      w[0] += (double)ax * fix + (double)bx * flx;
+      w[1] += (double)ay * fiy + (double)by * fly;
+      w[2] += (double)az * fiz + (double)bz * flz;
+      w[3] += 0.5 * ((double)ax * fiy + (double)bx * fly + (double)ay * fix + (double)by * flx);
+      w[4] += 0.5 * ((double)ax * fiz + (double)bx * flz + (double)az * fix + (double)bz * flx);
+      w[5] += 0.5 * ((double)ay * fiz + (double)by * flz + (double)az * fiy + (double)bz * fly);
+    }
   }
 }
 

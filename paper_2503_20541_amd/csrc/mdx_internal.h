@@ -19,7 +19,22 @@ constexpr int kBrickXY = 8;
 constexpr int kBrickZ = 8;
 
 // Indices into the FP64 partial-sum rows written by force kernels.
-enum PartialRow { kRowLJ = 0, kRowDir, kRowExcl, kRowBond, kRowAngle, kRowRec, kRowKin, kRowCount };
+// kRowVir + k and kRowVirB + k: virial component k (xx, yy, zz, xy, xz, yz) of
+// the pair kernel (or of the PME z pass) and of the bonded/exclusion kernel.
+enum PartialRow {
+  kRowLJ = 0, kRowDir, kRowExcl, kRowBond, kRowAngle, kRowRec, kRowKin,
+  kRowVir, kRowVirB = kRowVir + 6, kRowCount = kRowVirB + 6
+};
+
+// Adds s * d (x) d (symmetric: xx, yy, zz, xy, xz, yz) to w.
+__device__ __forceinline__ void vir_add_dd(double* w, double s, double dx, double dy, double dz) {
+  w[0] += s * dx * dx;
+  w[1] += s * dy * dy;
+  w[2] += s * dz * dz;
+  w[3] += s * dx * dy;
+  w[4] += s * dx * dz;
+  w[5] += s * dy * dz;
+}
 
 // Geometry of the x-y column grid and the float32 predicate constants.
 struct CellGrid {
@@ -165,16 +180,24 @@ hipError_t launch_refresh_sorted(Ctx& c, const float* pos);
 int build_coop_blocks(int max_clusters, int n, int ncol);
 // gate_now / pgate_now: the step's rebuild and prune flags inside
 // mdx_integrate_step (null for stand-alone calls: full list, no pruning).
+// virial: also the FP64 virial partial rows (kRowVir), implies energy.
 hipError_t launch_nonbonded(Ctx& c, bool energy, const int* gate_now = nullptr,
-                            const int* pgate_now = nullptr);
-hipError_t launch_bonded_excl(Ctx& c, const float* pos, float* force, bool energy);
+                            const int* pgate_now = nullptr, bool virial = false);
+// virial: also the partial rows kRowVirB, implies energy.
+hipError_t launch_bonded_excl(Ctx& c, const float* pos, float* force, bool energy,
+                              bool virial = false);
+// out[9] (row-major, symmetric) = sum over the sources s of scale[s] times the
+// partial rows row0[s] + k (k = xx, yy, zz, xy, xz, yz) over nblk[s] blocks.
+hipError_t launch_reduce_virial(Ctx& c, const int* row0, const int* nblk, const double* scale,
+                                int nsrc, double* out);
 // Sums the FP64 partial rows into out[slot - slot_base] (slots MDX_ENERGY_*);
 // const_slot >= 0 also stores const_val there, zero_slot >= 0 stores 0.
 hipError_t launch_reduce_energy(Ctx& c, const int* rows, const int* nblk, int nrows, double* out,
                                 int slot_base, double const_val, int const_slot,
                                 int zero_slot = -1);
 bool pme_size_supported(int K);
-hipError_t launch_pme(Ctx& c, float* force, bool energy);
+// virial: also the reciprocal-space virial partial rows (kRowVir).
+hipError_t launch_pme(Ctx& c, float* force, bool energy, bool virial = false);
 // Fused per-slot step kernels used by mdx_integrate_step.
 hipError_t launch_begin_step(Ctx& c, float* pos, float* vel, const float* force, float dt,
                              int* gate_now, int* gate_next, int* pgate_now, int* pgate_next,
@@ -184,7 +207,8 @@ hipError_t launch_finish_step(Ctx& c, const float* pos, float* vel, float* force
 // Spread + FFT passes only (the potential grid), for the fused closing kernel.
 // `done` (may be null) is recorded by the last kernel's own dispatch.
 hipError_t launch_pme_spread(Ctx& c, hipStream_t s, hipEvent_t done);
-hipError_t launch_pme_fft(Ctx& c, hipStream_t s, hipEvent_t done);
+// virial: the z pass also writes the reciprocal-space virial rows (kRowVir).
+hipError_t launch_pme_fft(Ctx& c, hipStream_t s, hipEvent_t done, bool virial = false);
 
 // Device helpers shared by kernels -------------------------------------------
 

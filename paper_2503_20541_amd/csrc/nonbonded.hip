@@ -53,6 +53,8 @@ struct PairParams {
   float r_s, r_c, inv_sw;     // switch r_s, r_c and 1/(r_c - r_s)
   int ntypes;
   double alpha_d;             // alpha for the FP64 energy terms
+  double coulomb_kd;          // k_e and 2 alpha / sqrt(pi) for the FP64 virial
+  double two_a_sqrtpi_d;
 };
 
 // Energies of a pair on measurement steps: the float32 squared distance (and
@@ -89,7 +91,7 @@ struct PruneArgs {
   float rp2;              // fl(r_p^2)
 };
 
-template <bool ENERGY, bool COUL, bool SWITCH, bool HALF>
+template <bool ENERGY, bool COUL, bool SWITCH, bool HALF, bool VIR = false>
 __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
                                               const int* __restrict__ ts,
                                               const uint2* __restrict__ tiles,
@@ -130,6 +132,7 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
   const unsigned bitpos = (unsigned)(ia * kClusterSize + jb);
   float fx = 0.f, fy = 0.f, fz = 0.f;
   double e_lj = 0.0, e_c = 0.0;
+  double wv[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // virial (VIR)
   if (active) {
     const float4 pi = xs[si];
     const float qik = pp.coulomb_k * pi.w;   // k_e q_i, per lane
@@ -180,14 +183,14 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
         const float rinv2 = rinv * rinv;
         float r6 = rinv2 * rinv2 * rinv2;
         float f_over_r = r6 * (lj.z * r6 - lj.w) * rinv2;
-        float S = 1.f;
+        float S = 1.f, dS = 0.f;
         if (SWITCH) {
           float r = r2 * rinv;
           if (r > pp.r_s) {
             float x = (r - pp.r_s) * pp.inv_sw;
             float x2 = x * x, x3 = x2 * x;
             S = 1.0f + x3 * (-10.0f + x * (15.0f - 6.0f * x));
-            float dS = x2 * (-30.0f + x * (60.0f - 30.0f * x)) * pp.inv_sw;
+            dS = x2 * (-30.0f + x * (60.0f - 30.0f * x)) * pp.inv_sw;
             float u_lj = r6 * (lj.x * r6 - lj.y);
             f_over_r = f_over_r * S - u_lj * dS * rinv;
           }
@@ -217,6 +220,19 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
           if (COUL) {
             double rd = sqrt(r2d);
             e_c += (double)pi.w * (double)pj.w * erfc(pp.alpha_d * rd) / rd;
+          }
+          if (VIR) {
+            // d (x) F_j with F_j = fr d, fr = -(dU/dr)/r in FP64 from the
+            // widened float32 distance
+            const double rd = sqrt(r2d);
+            double fr = (12.0 * c.x * r6d - 6.0 * c.y) * r6d / r2d;
+            if (SWITCH) fr = fr * (double)S - r6d * (c.x * r6d - c.y) * (double)dS / rd;
+            if (COUL) {
+              const double ar = pp.alpha_d * rd;
+              fr += pp.coulomb_kd * (double)pi.w * (double)pj.w *
+                    (erfc(ar) / rd + pp.two_a_sqrtpi_d * exp(-ar * ar)) / r2d;
+            }
+            vir_add_dd(wv, fr, (double)dx, (double)dy, (double)dz);
           }
         }
       }
@@ -287,6 +303,7 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
     if (!HALF) {
       e_lj *= 0.5;
       e_c *= 0.5;
+      for (int k = 0; k < 6; ++k) wv[k] *= 0.5;
     }
     double s_lj = block_sum(e_lj, red);
     double s_c = block_sum(e_c, red);
@@ -294,10 +311,16 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
       partials[kRowLJ * pstride + blockIdx.x] = s_lj;
       partials[kRowDir * pstride + blockIdx.x] = s_c;
     }
+    if (VIR) {
+      for (int k = 0; k < 6; ++k) {
+        const double sk = block_sum(wv[k], red);
+        if (threadIdx.x == 0) partials[(kRowVir + k) * pstride + blockIdx.x] = sk;
+      }
+    }
   }
 }
 
-template <bool ENERGY, bool COUL>
+template <bool ENERGY, bool COUL, bool VIR>
 __global__ void __launch_bounds__(256) k_bonded_excl(const float* __restrict__ pos, int n,
                                                      BondedParams bp, Topology tp,
                                                      const int* __restrict__ inv_perm,
@@ -308,13 +331,14 @@ __global__ void __launch_bounds__(256) k_bonded_excl(const float* __restrict__ p
   __shared__ double red[16];
   int a = blockIdx.x * blockDim.x + threadIdx.x;
   double e_ex = 0.0, e_b = 0.0, e_a = 0.0;
+  double w[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (a < n) {
     const int s = inv_perm[a];
     float fx = fslot[s], fy = fslot[fstride + s], fz = fslot[2 * fstride + s];
     fslot[s] = 0.f;
     fslot[fstride + s] = 0.f;
     fslot[2 * fstride + s] = 0.f;
-    bonded_excl_atom<ENERGY, COUL>(a, pos, n, bp, tp, fx, fy, fz, e_ex, e_b, e_a);
+    bonded_excl_atom<ENERGY, COUL, VIR>(a, pos, n, bp, tp, fx, fy, fz, e_ex, e_b, e_a, 0, 1, w);
     force[a] = fx;
     force[n + a] = fy;
     force[2 * n + a] = fz;
@@ -327,6 +351,12 @@ __global__ void __launch_bounds__(256) k_bonded_excl(const float* __restrict__ p
       partials[kRowExcl * pstride + blockIdx.x] = s1;
       partials[kRowBond * pstride + blockIdx.x] = s2;
       partials[kRowAngle * pstride + blockIdx.x] = s3;
+    }
+  }
+  if (VIR) {
+    for (int k = 0; k < 6; ++k) {
+      const double sk = block_sum(w[k], red);
+      if (threadIdx.x == 0) partials[(kRowVirB + k) * pstride + blockIdx.x] = sk;
     }
   }
 }
@@ -364,7 +394,8 @@ __global__ void __launch_bounds__(256) k_reduce_rows(const double* __restrict__ 
   }
 }
 
-hipError_t launch_nonbonded(Ctx& c, bool energy, const int* gate_now, const int* pgate_now) {
+hipError_t launch_nonbonded(Ctx& c, bool energy, const int* gate_now, const int* pgate_now,
+                            bool virial) {
   PairParams pp;
   for (int d = 0; d < 3; ++d) {
     pp.L[d] = c.cg.L[d];
@@ -374,6 +405,8 @@ hipError_t launch_nonbonded(Ctx& c, bool energy, const int* gate_now, const int*
   pp.alpha = (float)c.alpha;
   pp.exp_c = (float)(-c.alpha * c.alpha / M_LN2);
   pp.alpha_d = c.alpha;
+  pp.coulomb_kd = c.coulomb_k;
+  pp.two_a_sqrtpi_d = 2.0 * c.alpha / sqrt(M_PI);
   pp.ntypes = c.n_types;
   pp.two_a_sqrtpi = (float)(2.0 * c.alpha / sqrt(M_PI));
   pp.coulomb_k = (float)c.coulomb_k;
@@ -383,17 +416,27 @@ hipError_t launch_nonbonded(Ctx& c, bool energy, const int* gate_now, const int*
   const int nb = (c.max_clusters + 3) / 4;
   c.nb_blocks = nb;
   const PruneArgs pr{gate_now, pgate_now, c.ptiles, c.pcount, c.xp, c.prune_r2};
-#define MDX_PAIR(E, C, S, H)                                                               \
-  k_pair<E, C, S, H><<<nb, 256, 0, c.stream>>>(c.xs, c.ts, c.tiles, c.tile_count, c.meta,   \
-                                                c.nl_cap, pp, c.lj_f, c.lj_d, c.fslot,      \
-                                                c.max_slots, c.partials, c.max_blocks, pr)
-#define MDX_PAIR_H(E, C, S)      \
-  if (c.half_list)               \
-    MDX_PAIR(E, C, S, true);     \
-  else                           \
-    MDX_PAIR(E, C, S, false)
+#define MDX_PAIR(E, C, S, H, V)                                                            \
+  k_pair<E, C, S, H, V><<<nb, 256, 0, c.stream>>>(c.xs, c.ts, c.tiles, c.tile_count, c.meta, \
+                                                   c.nl_cap, pp, c.lj_f, c.lj_d, c.fslot,    \
+                                                   c.max_slots, c.partials, c.max_blocks, pr)
+#define MDX_PAIR_H(E, C, S)             \
+  if (c.half_list)                      \
+    MDX_PAIR(E, C, S, true, false);     \
+  else                                  \
+    MDX_PAIR(E, C, S, false, false)
+#define MDX_PAIR_V(C, S)                \
+  if (c.half_list)                      \
+    MDX_PAIR(true, C, S, true, true);   \
+  else                                  \
+    MDX_PAIR(true, C, S, false, true)
   bool C = c.has_coulomb, S = c.has_switch;
-  if (energy) {
+  if (virial) {
+    if (C && S) { MDX_PAIR_V(true, true); }
+    else if (C) { MDX_PAIR_V(true, false); }
+    else if (S) { MDX_PAIR_V(false, true); }
+    else { MDX_PAIR_V(false, false); }
+  } else if (energy) {
     if (C && S) { MDX_PAIR_H(true, true, true); }
     else if (C) { MDX_PAIR_H(true, true, false); }
     else if (S) { MDX_PAIR_H(true, false, true); }
@@ -404,6 +447,7 @@ hipError_t launch_nonbonded(Ctx& c, bool energy, const int* gate_now, const int*
     else if (S) { MDX_PAIR_H(false, false, true); }
     else { MDX_PAIR_H(false, false, false); }
   }
+#undef MDX_PAIR_V
 #undef MDX_PAIR_H
 #undef MDX_PAIR
   return hipGetLastError();
@@ -427,23 +471,69 @@ Topology make_topology(const Ctx& c) {
                   c.bt_idx, c.angles,   c.angle_k, c.angle_t0, c.at_start, c.at_idx};
 }
 
-hipError_t launch_bonded_excl(Ctx& c, const float* pos, float* force, bool energy) {
+hipError_t launch_bonded_excl(Ctx& c, const float* pos, float* force, bool energy, bool virial) {
   const BondedParams bp = make_bonded_params(c);
   const Topology tp = make_topology(c);
   const int nb = (c.n + 255) / 256;
   hipStream_t s = c.stream;
   const bool C = c.has_coulomb;
-#define MDX_BX(E, C)                                                                    \
-  k_bonded_excl<E, C><<<nb, 256, 0, s>>>(pos, c.n, bp, tp, c.inv_perm, c.fslot, c.max_slots, \
-                                         force, c.partials, c.max_blocks)
-  if (energy) {
-    if (C) MDX_BX(true, true);
-    else MDX_BX(true, false);
+#define MDX_BX(E, C, V)                                                                       \
+  k_bonded_excl<E, C, V><<<nb, 256, 0, s>>>(pos, c.n, bp, tp, c.inv_perm, c.fslot, c.max_slots, \
+                                            force, c.partials, c.max_blocks)
+  if (virial) {
+    if (C) MDX_BX(true, true, true);
+    else MDX_BX(true, false, true);
+  } else if (energy) {
+    if (C) MDX_BX(true, true, false);
+    else MDX_BX(true, false, false);
   } else {
-    if (C) MDX_BX(false, true);
-    else MDX_BX(false, false);
+    if (C) MDX_BX(false, true, false);
+    else MDX_BX(false, false, false);
   }
 #undef MDX_BX
+  return hipGetLastError();
+}
+
+// One block per virial component: fixed-order sums over the sources' rows.
+struct VirialSpec {
+  int nsrc;
+  int row0[2];
+  int nblk[2];
+  double scale[2];
+};
+
+__global__ void __launch_bounds__(256) k_reduce_virial(const double* __restrict__ partials,
+                                                       int pstride, VirialSpec spec,
+                                                       double* __restrict__ out,
+                                                       unsigned* __restrict__ flags) {
+  __shared__ double red[16];
+  const int k = blockIdx.x;   // xx, yy, zz, xy, xz, yz
+  double total = 0.0;
+  for (int src = 0; src < spec.nsrc; ++src) {
+    const double* p = partials + (size_t)(spec.row0[src] + k) * pstride;
+    double v = 0.0;
+    for (int b = threadIdx.x; b < spec.nblk[src]; b += blockDim.x) v += p[b];
+    total += block_sum(v, red) * spec.scale[src];
+  }
+  if (threadIdx.x == 0) {
+    const int ij[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
+    out[3 * ij[k][0] + ij[k][1]] = total;
+    out[3 * ij[k][1] + ij[k][0]] = total;
+    if (!isfinite(total)) atomicOr(flags, MDX_FLAG_NONFINITE);
+  }
+}
+
+hipError_t launch_reduce_virial(Ctx& c, const int* row0, const int* nblk, const double* scale,
+                                int nsrc, double* out) {
+  if (nsrc < 1 || nsrc > 2) return hipErrorInvalidValue;
+  VirialSpec spec{};
+  spec.nsrc = nsrc;
+  for (int s = 0; s < nsrc; ++s) {
+    spec.row0[s] = row0[s];
+    spec.nblk[s] = nblk[s];
+    spec.scale[s] = scale[s];
+  }
+  k_reduce_virial<<<6, 256, 0, c.stream>>>(c.partials, c.max_blocks, spec, out, c.flags);
   return hipGetLastError();
 }
 

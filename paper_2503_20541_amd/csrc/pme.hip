@@ -438,7 +438,7 @@ __global__ void __launch_bounds__(256) k_fft_cols(float2* __restrict__ grid, Pme
   const int outer = blockIdx.x / ntile;       // z for the y pass, ky for the z pass
   const int kx0 = (blockIdx.x - outer * ntile) * P;
   size_t base, stride;
-  if (MODE == 2) {
+  if (MODE >= 2) {
     base = (size_t)outer * Kxh;
     stride = (size_t)pp.K[1] * Kxh;
   } else {
@@ -457,11 +457,14 @@ __global__ void __launch_bounds__(256) k_fft_cols(float2* __restrict__ grid, Pme
   } else {
     res = fft_any<N, -1>(a, b, SP, P, pl, tw);
   }
-  if (MODE == 2) {
+  if (MODE >= 2) {
     // influence function G = B(m) C(m) on the half spectrum. G is formed in
     // FP64 (its float32 value scales Q^; the FP64 value, without the
     // constant 1/(pi V) applied in the reduction, weights |Q^|^2 for E_rec).
+    // MODE 3 also sums the virial: each E(m) times
+    // delta_ab - 2 (1 + pi^2 m^2 / alpha^2) m_a m_b / m^2.
     double e = 0.0;
+    double w[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const int ky = outer;
     for (int idx = threadIdx.x; idx < P * L; idx += blockDim.x) {
       int p = idx / L, kz = idx - p * L;
@@ -473,7 +476,18 @@ __global__ void __launch_bounds__(256) k_fft_cols(float2* __restrict__ grid, Pme
         if (msq > 0.0) {
           double gd = bmx[kx] * bmy[ky] * bmz[kz] * exp(-pp.exp_fac * msq) / msq;
           int wgt = (kx == 0 || (2 * kx == pp.K[0])) ? 1 : 2;
-          e += (double)wgt * gd * ((double)v.x * v.x + (double)v.y * v.y);
+          const double ew = (double)wgt * gd * ((double)v.x * v.x + (double)v.y * v.y);
+          e += ew;
+          if (MODE == 3) {
+            const double fac = 2.0 * (1.0 + pp.exp_fac * msq) / msq;
+            const double m0 = mx[kx], m1 = my[ky], m2 = mz[kz];
+            w[0] += ew * (1.0 - fac * m0 * m0);
+            w[1] += ew * (1.0 - fac * m1 * m1);
+            w[2] += ew * (1.0 - fac * m2 * m2);
+            w[3] -= ew * fac * m0 * m1;
+            w[4] -= ew * fac * m0 * m2;
+            w[5] -= ew * fac * m1 * m2;
+          }
           g = (float)(gd * pp.inv_piV);
         }
       }
@@ -481,6 +495,12 @@ __global__ void __launch_bounds__(256) k_fft_cols(float2* __restrict__ grid, Pme
     }
     double s = block_sum(e, red);
     if (threadIdx.x == 0) partials[kRowRec * pstride + blockIdx.x] = s;
+    if (MODE == 3) {
+      for (int k = 0; k < 6; ++k) {
+        const double sk = block_sum(w[k], red);
+        if (threadIdx.x == 0) partials[(kRowVir + k) * pstride + blockIdx.x] = sk;
+      }
+    }
     __syncthreads();
     float2* other = (res == a) ? b : a;
     res = fft_any<N, +1>(res, other, SP, P, pl, tw);
@@ -629,7 +649,7 @@ hipError_t launch_pme_spread(Ctx& c, hipStream_t s, hipEvent_t done) {
 // The five FFT passes (forward transform, influence multiply with the energy
 // partials, inverse) on stream s: grid_q -> potential in grid_phi; `done`
 // (if given) is recorded by the last pass's dispatch.
-hipError_t launch_pme_fft(Ctx& c, hipStream_t s, hipEvent_t done) {
+hipError_t launch_pme_fft(Ctx& c, hipStream_t s, hipEvent_t done, bool virial) {
   const PmeGrid& g = c.pg;
   const PmeParams pp = make_pme_params(c);
   FftPlan px = make_plan(g.K[0]), py = make_plan(g.K[1]), pz = make_plan(g.K[2]);
@@ -643,17 +663,18 @@ hipError_t launch_pme_fft(Ctx& c, hipStream_t s, hipEvent_t done) {
   const size_t shy = (size_t)(g.K[1] + 2 * Pc * (g.K[1] + 1)) * sizeof(float2);
   const size_t shz = (size_t)(g.K[2] + 2 * Pc * (g.K[2] + 1)) * sizeof(float2);
   cols<0>(g.K[1], g.K[2] * ntile, shy, s, c, pp, Pc, py, c.tw[1]);
-  cols<2>(g.K[2], g.K[1] * ntile, shz, s, c, pp, Pc, pz, c.tw[2]);
+  if (virial) cols<3>(g.K[2], g.K[1] * ntile, shz, s, c, pp, Pc, pz, c.tw[2]);
+  else cols<2>(g.K[2], g.K[1] * ntile, shz, s, c, pp, Pc, pz, c.tw[2]);
   c.pme_blocks = g.K[1] * ntile;
   cols<1>(g.K[1], g.K[2] * ntile, shy, s, c, pp, Pc, py, c.tw[1]);
   rows_c2r(g.K[0], rblocks, sh, s, c.grid_c, c.grid_phi, rows, P, g.Kxh, px, c.tw[0], done);
   return hipGetLastError();
 }
 
-hipError_t launch_pme(Ctx& c, float* force, bool energy) {
+hipError_t launch_pme(Ctx& c, float* force, bool energy, bool virial) {
   (void)energy;   // the z pass always writes its energy partials
   hipError_t e = launch_pme_spread(c, c.stream, nullptr);
-  if (e == hipSuccess) e = launch_pme_fft(c, c.stream, nullptr);
+  if (e == hipSuccess) e = launch_pme_fft(c, c.stream, nullptr, virial);
   if (e != hipSuccess) return e;
   const PmeParams pp = make_pme_params(c);
   k_pme_gather<<<(c.max_slots + 255) / 256, 256, 0, c.stream>>>(c.xs, c.perm, c.meta, c.grid_phi,

@@ -658,14 +658,21 @@ int mdx_get_neighbor_pairs(mdx_ctx* x, int32_t* pairs_host, int64_t cap, int64_t
 int mdx_compute_nonbonded(mdx_ctx* x, const float* pos, float* force, double* energy,
                           double* virial) {
   if (check_ctx(x) || !pos || !force) return MDX_E_INVALID;
-  if (virial) return MDX_E_UNSUPPORTED;
   Ctx& c = x->c;
   if (c.steps_since_build < 0) return MDX_E_NO_LIST;
-  const bool e = energy != nullptr;
+  const bool v = virial != nullptr;
+  const bool e = energy != nullptr || v;
   MDX_TRY(mdx::launch_refresh_sorted(c, pos));
-  MDX_TRY(timed(x, MDX_TIMING_PAIR, c.stream, [&] { return mdx::launch_nonbonded(c, e); }));
-  MDX_TRY(mdx::launch_bonded_excl(c, pos, force, e));
-  if (e) {
+  MDX_TRY(timed(x, MDX_TIMING_PAIR, c.stream,
+                [&] { return mdx::launch_nonbonded(c, e, nullptr, nullptr, v); }));
+  MDX_TRY(mdx::launch_bonded_excl(c, pos, force, e, v));
+  if (v) {
+    const int row0[2] = {mdx::kRowVir, mdx::kRowVirB};
+    const int nblk[2] = {c.nb_blocks, (c.n + 255) / 256};
+    const double scale[2] = {1.0, 1.0};
+    MDX_TRY(mdx::launch_reduce_virial(c, row0, nblk, scale, 2, virial));
+  }
+  if (energy) {
     const int nb = (c.n + 255) / 256;
     int rows[5] = {mdx::kRowLJ, mdx::kRowDir, mdx::kRowExcl, mdx::kRowBond, mdx::kRowAngle};
     int nblk[5] = {c.nb_blocks, c.nb_blocks, nb, nb, nb};
@@ -677,13 +684,19 @@ int mdx_compute_nonbonded(mdx_ctx* x, const float* pos, float* force, double* en
 
 int mdx_compute_pme(mdx_ctx* x, const float* pos, float* force, double* energy, double* virial) {
   if (check_ctx(x) || !pos || !force) return MDX_E_INVALID;
-  if (virial) return MDX_E_UNSUPPORTED;
   Ctx& c = x->c;
   if (!c.has_pme) return MDX_E_NO_PME;
   if (c.steps_since_build < 0) return MDX_E_NO_LIST;
   MDX_TRY(mdx::launch_refresh_sorted(c, pos));
-  MDX_TRY(timed(x, MDX_TIMING_PME, c.stream,
-                [&] { return mdx::launch_pme(c, force, energy != nullptr); }));
+  MDX_TRY(timed(x, MDX_TIMING_PME, c.stream, [&] {
+    return mdx::launch_pme(c, force, energy != nullptr, virial != nullptr);
+  }));
+  if (virial) {
+    const int row0[1] = {mdx::kRowVir};
+    const int nblk[1] = {c.pme_blocks};
+    const double scale[1] = {0.5 * c.coulomb_k * c.pme_energy_scale};
+    MDX_TRY(mdx::launch_reduce_virial(c, row0, nblk, scale, 1, virial));
+  }
   if (energy) {
     int rows[1] = {mdx::kRowRec};
     int nblk[1] = {c.pme_blocks};

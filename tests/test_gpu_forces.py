@@ -1,7 +1,8 @@
-"""GPU parity: short-range forces/energies and PME vs the FP64 oracle.
+"""GPU parity: short-range forces/energies/virials and PME vs the FP64 oracle.
 
 Bars: forces within 1e-5 relative RMS (||F_gpu - F_orc|| / ||F_orc|| over all 3N
-components), energies within 1e-6 relative.
+components), energies within 1e-6 relative, virial entries within 1e-5 of the
+largest diagonal entry.
 """
 import numpy as np
 import pytest
@@ -14,6 +15,7 @@ pytestmark = pytest.mark.gpu
 
 F_TOL = 1e-5
 E_TOL = 1e-6
+W_TOL = 1e-5     # virial entries, relative to the largest diagonal entry
 
 
 def _nonbonded_gpu(s, **kw):
@@ -182,3 +184,62 @@ def test_water96k_full_size_sampled_forces_and_energies():
         assert abs(E[k] - Eref[k]) <= E_TOL * max(abs(Eref[k]), scale), (k, E[k], Eref[k])
     assert abs(E.sum() - Eref.sum()) <= E_TOL * scale, (E.sum(), Eref.sum())
     assert rel_rms(F_step, F_fresh) < 1e-6
+
+
+def _off_equilibrium(s, seed=4):
+    # water away from its rigid geometry, so bonds and angles carry force
+    s = s.copy()
+    p = s.pos.astype(np.float64) + np.random.default_rng(seed).normal(0.0, 0.02, s.pos.shape)
+    s.pos = np.mod(p, s.box.astype(np.float64)[:, None]).astype(np.float32)
+    return s
+
+
+@pytest.mark.parametrize("options", [0, HALF_LIST], ids=["full", "half"])
+@pytest.mark.parametrize("name", ["lj1k", "water375", "water9k"])
+def test_nonbonded_virial_parity(name, options):
+    import torch
+    s = synth.config_system(name)
+    if s.bonds.size:
+        s = _off_equilibrium(s)
+    announce(f"nonbonded virial {name} options={options}")
+    with gpu_context(s, options=options) as (mdx, ctx, t):
+        mdx.build_neighbors(ctx, t["pos"])
+        W = torch.zeros(9, dtype=torch.float64, device="cuda:0")
+        # virial without energies, then with: the same numbers
+        mdx.compute_nonbonded(ctx, t["pos"], t["force"], None, W)
+        torch.cuda.synchronize()
+        W1 = W.cpu().numpy().reshape(3, 3).copy()
+        mdx.compute_nonbonded(ctx, t["pos"], t["force"], t["e_nb"], W)
+        torch.cuda.synchronize()
+        W2 = W.cpu().numpy().reshape(3, 3)
+        F = t["force"].cpu().numpy()
+        assert mdx.get_status(ctx) == 0
+    ref = forcefield.nonbonded_terms(s)
+    assert rel_rms(F, ref["F"]) < F_TOL
+    Wref = ref["W"]
+    assert np.array_equal(W1, W2) and np.array_equal(W1, W1.T)
+    scale = np.abs(np.diag(Wref)).max()
+    assert np.abs(W1 - Wref).max() <= W_TOL * scale, (W1, Wref)
+    if s.bonds.size:   # the bonded part is exercised
+        assert np.abs(np.diag(ref["parts"]["bond"]["W"])).max() > 1e-3 * scale
+
+
+@pytest.mark.parametrize("name", ["water375", "water9k"])
+def test_pme_virial_parity(name):
+    import torch
+    s = synth.config_system(name)
+    announce(f"pme virial {name}")
+    with gpu_context(s) as (mdx, ctx, t):
+        mdx.build_neighbors(ctx, t["pos"])
+        t["force"].zero_()
+        W = torch.zeros(9, dtype=torch.float64, device="cuda:0")
+        mdx.compute_pme(ctx, t["pos"], t["force"], t["e_rec"], W)
+        torch.cuda.synchronize()
+        Wg = W.cpu().numpy().reshape(3, 3)
+        E = float(t["e_rec"].cpu().numpy()[0])
+        assert mdx.get_status(ctx) == 0
+    ref = forcefield.pme_terms(s)
+    assert abs(E - ref["E"]) <= E_TOL * abs(ref["E"])
+    scale = np.abs(np.diag(ref["W"])).max()
+    assert np.abs(Wg - ref["W"]).max() <= W_TOL * scale, (Wg, ref["W"])
+    assert np.array_equal(Wg, Wg.T)

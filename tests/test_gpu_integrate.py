@@ -136,9 +136,8 @@ def test_error_codes():
             mdx.compute_nonbonded(ctx, pos, f)
         assert e.value.code == mdx.MDX_E_NO_LIST
         mdx.build_neighbors(ctx, pos)
-        v = torch.zeros(9, dtype=torch.float64, device="cuda:0")
         with pytest.raises(mdx.MdxError) as e:
-            mdx.compute_nonbonded(ctx, pos, f, None, v)
-        assert e.value.code == mdx.MDX_E_UNSUPPORTED
+            mdx.get_images(ctx, None)
+        assert e.value.code == mdx.MDX_E_INVALID
     finally:
         mdx.destroy(ctx)

@@ -172,3 +172,22 @@ def test_kc_root_satisfies_eq14():
     val = kc * math.sqrt(d * a) / 20 * math.exp(-(math.pi * kc / (d * a)) ** 2)
     assert val == pytest.approx(5e-4, rel=1e-9)
     assert kc > d * a / (math.pi * math.sqrt(2))
+
+
+def test_spme_virial_diagonal_per_axis():
+    # W_aa = -dE_rec/d(eps_a): box length and coordinates along a scaled by
+    # 1 + eps_a (the grid counts stay, as for a box deformation)
+    s = synth.config_system("water375")
+    a = forcefield.alpha(s)
+    pos = s.pos.astype(np.float64)
+    box = s.box.astype(np.float64)
+    W = pme.spme(pos, s.charge, box, s.pme_grid, a, s.coulomb_k)["W"]
+    h = 1e-5
+    for ax in range(3):
+        sc = np.ones(3)
+        sc[ax] = 1 + h
+        Ep = pme.spme(pos * sc[:, None], s.charge, box * sc, s.pme_grid, a, s.coulomb_k)["E"]
+        sc[ax] = 1 - h
+        Em = pme.spme(pos * sc[:, None], s.charge, box * sc, s.pme_grid, a, s.coulomb_k)["E"]
+        assert W[ax, ax] == pytest.approx(-(Ep - Em) / (2 * h), rel=1e-7, abs=1e-8 * abs(W).max())
+    assert np.allclose(W, W.T, rtol=0, atol=1e-12 * np.abs(W).max())

@@ -172,3 +172,76 @@ def test_energy_components_water_signs():
     # rigid equilibrium geometry: bonded energy is rounding noise
     assert abs(E["bond"]) < 1e-6 and abs(E["angle"]) < 1e-6
     assert np.abs(nb["F"].sum(axis=1)).max() < 1e-8 * np.abs(nb["F"]).max()
+
+
+def _axis_scaled(pos, box, axis, lam):
+    s = np.ones(3)
+    s[axis] = lam
+    return pos * s[:, None], box * s
+
+
+def _term_energy(d):
+    return d["E_lj"] + d["E_dir"] if "E_lj" in d else d["E"]
+
+
+def _virial_terms(s, inter, alpha, k):
+    return {
+        "pair": lambda p, b: nonbonded.pair_terms(p, b, inter, s.atom_type, s.type_sigma,
+                                                  s.type_epsilon, s.charge, alpha, k),
+        "excl": lambda p, b: nonbonded.exclusion_correction(p, b, s.exclusions, s.charge,
+                                                            alpha, k),
+        "bond": lambda p, b: bonded.bonds(p, b, s.bonds, s.bond_k, s.bond_r0),
+        "angle": lambda p, b: bonded.angles(p, b, s.angles, s.angle_k, s.angle_theta0),
+    }
+
+
+def test_virial_diagonal_is_minus_axis_strain_derivative():
+    # W_aa = -dU/d(eps_a) when the box and every coordinate along a are
+    # scaled by 1 + eps_a (fixed interaction set, water off its equilibrium)
+    s = synth.config_system("water375")
+    pos = s.pos.astype(np.float64) + np.random.default_rng(5).normal(0.0, 0.03, s.pos.shape)
+    box = s.box.astype(np.float64)
+    p32 = pos.astype(np.float32)
+    pairs = neighbors.brute_force_pairs(p32, s.box, s.r_cut, s.r_ghost, s.exclusions)
+    inter = pairs[neighbors.interacting(p32, s.box, s.r_cut, s.r_ghost, pairs)]
+    h = 1e-6
+    for name, fn in _virial_terms(s, inter, forcefield.alpha(s), float(s.coulomb_k)).items():
+        W = fn(pos, box)["W"]
+        assert np.abs(W).max() > 0, name
+        for ax in range(3):
+            ep = _term_energy(fn(*_axis_scaled(pos, box, ax, 1 + h)))
+            em = _term_energy(fn(*_axis_scaled(pos, box, ax, 1 - h)))
+            fd = -(ep - em) / (2 * h)
+            assert W[ax, ax] == pytest.approx(fd, rel=1e-6, abs=1e-7 * np.abs(W).max()), (name, ax)
+
+
+def test_virial_off_diagonal_is_minus_shear_derivative():
+    # an isolated cluster (no periodic image within reach): shearing every
+    # coordinate r_a += eps r_b gives -dU/d(eps) = W_ba
+    rng = np.random.default_rng(8)
+    n = 36
+    pos = 46.0 + 8.0 * rng.random((3, n))
+    box = np.full(3, 100.0)
+    s = synth.random_box(n, [100.0, 100.0, 100.0], 20.0, 0.0, 9)
+    s.charge = rng.choice([-0.5, 0.5], n).astype(np.float32)
+    s.bonds = np.stack([np.arange(0, n - 1, 3), np.arange(1, n, 3)], 1).astype(np.int32)
+    s.bond_k = np.full(len(s.bonds), 300.0, np.float32)
+    s.bond_r0 = np.full(len(s.bonds), 1.2, np.float32)
+    s.angles = np.stack([np.arange(0, n - 2, 3), np.arange(1, n - 1, 3),
+                         np.arange(2, n, 3)], 1).astype(np.int32)
+    s.angle_k = np.full(len(s.angles), 40.0, np.float32)
+    s.angle_theta0 = np.full(len(s.angles), 1.8, np.float32)
+    s.exclusions = s.bonds.copy()
+    i, j = np.triu_indices(n, 1)
+    keep = ~np.isin(i * n + j, s.exclusions[:, 0] * n + s.exclusions[:, 1])
+    inter = np.stack([i[keep], j[keep]], 1)
+    h = 1e-6
+    for name, fn in _virial_terms(s, inter, 0.3, 1.0).items():
+        W = fn(pos, box)["W"]
+        assert np.abs(W).max() > 0, name
+        for a, b in ((0, 1), (0, 2), (1, 2), (1, 0), (2, 0), (2, 1)):
+            pp, pm = pos.copy(), pos.copy()
+            pp[a] += h * pos[b]
+            pm[a] -= h * pos[b]
+            fd = -(_term_energy(fn(pp, box)) - _term_energy(fn(pm, box))) / (2 * h)
+            assert W[b, a] == pytest.approx(fd, rel=1e-6, abs=1e-7 * np.abs(W).max()), (name, a, b)
