@@ -110,9 +110,15 @@ typedef struct mdx_ctx mdx_ctx;
  * with grid-wide barriers between them (one launch when no rebuild is due,
  * but the launch goes through its own hardware queue, and on a real rebuild
  * the resident grid is smaller). Both give the same list.
+ * MDX_OPT_KAHAN_VV compensates the velocity-Verlet sums (Kahan summation):
+ * each atom keeps the rounding error of its last position and velocity
+ * updates (two more float [3][N] arrays) and feeds it into the next one, so
+ * float32 round-off does not build up over long runs. The compensation is
+ * cleared by mdx_build_neighbors (a new state).
  */
 #define MDX_OPT_HALF_LIST         1u
 #define MDX_OPT_COOPERATIVE_BUILD 2u
+#define MDX_OPT_KAHAN_VV          4u
 typedef struct mdx_system_desc {
   int32_t n_atoms;
   float box[3];

@@ -39,7 +39,8 @@ __global__ void __launch_bounds__(256) k_begin_step(
     int n, CellGrid cg, float half_dt, float dt, float half_skin2, float4* __restrict__ xs,
     unsigned* __restrict__ flags, int* __restrict__ gate_now, int* __restrict__ gate_next,
     const float4* __restrict__ xp, float prune_move2, int* __restrict__ pgate_now,
-    int* __restrict__ pgate_next, int force_rebuild, int* __restrict__ img) {
+    int* __restrict__ pgate_next, int force_rebuild, int* __restrict__ img,
+    float* __restrict__ xc, float* __restrict__ vc) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s == 0) {
     *gate_next = 0;
@@ -53,10 +54,19 @@ __global__ void __launch_bounds__(256) k_begin_step(
   float x[3];
   for (int d = 0; d < 3; ++d) {
     const size_t k = (size_t)d * n + a;
-    const float v = vel[k] + h * force[k];
-    vel[k] = v;
     int wraps;
-    x[d] = wrap_box(pos[k] + dt * v, cg.L[d], wraps);
+    if (xc) {   // compensated sums (MDX_OPT_KAHAN_VV)
+      float cv = vc[k], cx = xc[k];
+      const float v = kahan_add(vel[k], h * force[k], cv);
+      vel[k] = v;
+      x[d] = wrap_box(kahan_add(pos[k], dt * v, cx), cg.L[d], wraps);
+      vc[k] = cv;
+      xc[k] = cx;
+    } else {
+      const float v = vel[k] + h * force[k];
+      vel[k] = v;
+      x[d] = wrap_box(pos[k] + dt * v, cg.L[d], wraps);
+    }
     pos[k] = x[d];
     if (wraps) img[k] += wraps;
   }
@@ -91,7 +101,7 @@ __global__ void __launch_bounds__(256) k_finish_step(
     BondedParams bp, Topology tp, float* __restrict__ fslot, int fstride,
     float* __restrict__ force, float* __restrict__ vel,
     const float* __restrict__ acc_over_m, const float* __restrict__ mass, float half_dt,
-    double inv_2acc, double* __restrict__ partials, int pstride) {
+    double inv_2acc, double* __restrict__ partials, int pstride, float* __restrict__ vc) {
   __shared__ double red[16];
   const int gt = blockIdx.x * blockDim.x + threadIdx.x;
   const int s = gt / kFinishLanes, q = gt & (kFinishLanes - 1);
@@ -121,7 +131,20 @@ __global__ void __launch_bounds__(256) k_finish_step(
     force[n + a] = fy;
     force[2 * n + a] = fz;
     const float h = half_dt * acc_over_m[a];
-    const float v0 = vel[a] + h * fx, v1 = vel[n + a] + h * fy, v2 = vel[2 * n + a] + h * fz;
+    float v0, v1, v2;
+    if (vc) {   // compensated sums (MDX_OPT_KAHAN_VV)
+      float c0 = vc[a], c1 = vc[n + a], c2 = vc[2 * n + a];
+      v0 = kahan_add(vel[a], h * fx, c0);
+      v1 = kahan_add(vel[n + a], h * fy, c1);
+      v2 = kahan_add(vel[2 * n + a], h * fz, c2);
+      vc[a] = c0;
+      vc[n + a] = c1;
+      vc[2 * n + a] = c2;
+    } else {
+      v0 = vel[a] + h * fx;
+      v1 = vel[n + a] + h * fy;
+      v2 = vel[2 * n + a] + h * fz;
+    }
     vel[a] = v0;
     vel[n + a] = v1;
     vel[2 * n + a] = v2;
@@ -149,7 +172,7 @@ hipError_t launch_begin_step(Ctx& c, float* pos, float* vel, const float* force,
   k_begin_step<<<(c.max_slots + 255) / 256, 256, 0, c.stream>>>(
       pos, vel, force, c.hdt_scale, c.perm, c.q, c.x_build, c.meta, c.n, c.cg, 0.5f * dt, dt,
       h * h, c.xs, c.flags, gate_now, gate_next, c.xp, c.prune_move2, pgate_now, pgate_next,
-      force_rebuild ? 1 : 0, c.img);
+      force_rebuild ? 1 : 0, c.img, c.xc, c.vc);
   return hipGetLastError();
 }
 
@@ -165,7 +188,7 @@ hipError_t launch_finish_step(Ctx& c, const float* pos, float* vel, float* force
   k_finish_step<E, C, P><<<nb, 256, 0, c.stream>>>(c.xs, c.perm, c.meta, c.grid_phi, pp, pos, \
                                                     c.n, bp, tp, c.fslot, c.max_slots, force, \
                                                     vel, c.hdt_scale, c.mass, 0.5f * dt,      \
-                                                    inv_2acc, c.partials, c.max_blocks)
+                                                    inv_2acc, c.partials, c.max_blocks, c.vc)
   const bool C = c.has_coulomb, P = c.has_pme;
   if (energy) {
     if (C && P) MDX_FIN(true, true, true);

@@ -123,6 +123,8 @@ struct Ctx {
   float4* box_hi = nullptr;
   float4* col_xy = nullptr;     // [ncell] x min, x max, y min, y max of a column's atoms
   int* img = nullptr;           // [3][n] periodic image counters (atom order)
+  float* xc = nullptr;          // [3][n] Kahan compensation of x and v (MDX_OPT_KAHAN_VV)
+  float* vc = nullptr;
   float* x_build = nullptr;    // [3][n] positions at the last build (caller order)
   // [max_clusters][nl_cap] tiles: x = j-cluster, y = 16-bit pair mask (bit
   // 4 a + b: i slot a, j slot b) | periodic image of the j-cluster << 16
@@ -256,6 +258,16 @@ __device__ __forceinline__ unsigned image_code(float xi, float xj, float hL) {
 __device__ __forceinline__ float image_diff(float xi, float xj, float am, float cp) {
 #pragma clang fp contract(off)
   return (xj + am) + (cp - xi);
+}
+
+// Kahan-compensated s + y: c carries the rounding error of the previous sum
+// into this one and receives this one's.
+__device__ __forceinline__ float kahan_add(float s, float y, float& c) {
+#pragma clang fp contract(off)
+  const float yc = y - c;
+  const float t = s + yc;
+  c = (t - s) - yc;
+  return t;
 }
 
 __device__ __forceinline__ float dist2(float dx, float dy, float dz) {

@@ -218,7 +218,8 @@ int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
     if (d->atom_type[i] < 0 || d->atom_type[i] >= d->n_types) return MDX_E_INVALID;
     if (!(d->mass[i] > 0.f)) return MDX_E_INVALID;
   }
-  if (d->options & ~(MDX_OPT_HALF_LIST | MDX_OPT_COOPERATIVE_BUILD)) return MDX_E_INVALID;
+  if (d->options & ~(MDX_OPT_HALF_LIST | MDX_OPT_COOPERATIVE_BUILD | MDX_OPT_KAHAN_VV))
+    return MDX_E_INVALID;
   const int cdiv = d->cell_divisions == 0 ? 2 : d->cell_divisions;
   if (cdiv < 1 || cdiv > 4) return MDX_E_INVALID;
   if (d->switch_r > 0.f && !(d->switch_r < d->r_cut)) return MDX_E_INVALID;
@@ -414,6 +415,12 @@ int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
   if ((rc = dev_alloc(x, &c.col_xy, ncol)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.img, (size_t)3 * n)) != MDX_OK) return rc;
   MDX_TRY(hipMemset(c.img, 0, sizeof(int) * 3 * (size_t)n));
+  if (d->options & MDX_OPT_KAHAN_VV) {
+    if ((rc = dev_alloc(x, &c.xc, (size_t)3 * n)) != MDX_OK) return rc;
+    if ((rc = dev_alloc(x, &c.vc, (size_t)3 * n)) != MDX_OK) return rc;
+    MDX_TRY(hipMemset(c.xc, 0, sizeof(float) * 3 * (size_t)n));
+    MDX_TRY(hipMemset(c.vc, 0, sizeof(float) * 3 * (size_t)n));
+  }
   if ((rc = dev_alloc(x, &c.x_build, (size_t)3 * n)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.tile_count, c.max_clusters)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.nl_needed, 1)) != MDX_OK) return rc;
@@ -568,6 +575,12 @@ int mdx_build_neighbors(mdx_ctx* x, const float* pos) {
   Ctx& c = x->c;
   // a new list (new slot order) invalidates the pruned list
   MDX_TRY(mdx::launch_fill_i32(c.gate + 2, 1, 2, c.stream));
+  // a new state: the Kahan compensation starts again from zero (all-zero
+  // bits are 0.0f)
+  if (c.xc) {
+    MDX_TRY(mdx::launch_fill_i32(reinterpret_cast<int*>(c.xc), 0, 3 * c.n, c.stream));
+    MDX_TRY(mdx::launch_fill_i32(reinterpret_cast<int*>(c.vc), 0, 3 * c.n, c.stream));
+  }
   for (int attempt = 0; attempt < 3; ++attempt) {
     MDX_TRY(timed(x, MDX_TIMING_BUILD, c.stream, [&] { return mdx::launch_build_list(c, pos); }));
     int needed = 0;

@@ -51,6 +51,7 @@ MDX_N_ENERGY = 8
 
 MDX_OPT_HALF_LIST = 0x1
 MDX_OPT_COOPERATIVE_BUILD = 0x2
+MDX_OPT_KAHAN_VV = 0x4
 
 MDX_TIMING_PAIR = 0
 MDX_TIMING_PME = 1

@@ -141,3 +141,38 @@ def test_error_codes():
         assert e.value.code == mdx.MDX_E_INVALID
     finally:
         mdx.destroy(ctx)
+
+
+def test_kahan_vv_keeps_free_flight_exact():
+    # particles with no interaction fly at constant velocity: after n steps
+    # the unwrapped positions are x0 + n fl32(dt v). Plain float32 sums drift
+    # by many ulps over thousands of steps; the compensated sums
+    # (MDX_OPT_KAHAN_VV) stay within a few
+    import torch
+    import paper_2503_20541_amd as mdx
+    s = synth.random_box(2000, [20.0, 20.0, 20.0], 2.0, 0.5, 77)
+    s.type_epsilon[:] = 0.0
+    s.charge[:] = 0.0
+    rng = np.random.default_rng(12)
+    s.vel = rng.uniform(-2e-3, 2e-3, s.pos.shape).astype(np.float32)
+    n_steps, dt = 3000, np.float32(0.005)
+    step = (dt * s.vel).astype(np.float32).astype(np.float64)      # fl32(dt v)
+    exact = s.pos.astype(np.float64) + n_steps * step
+    err = {}
+    for opt in (0, mdx.MDX_OPT_KAHAN_VV):
+        announce(f"free flight options={opt}")
+        with gpu_context(s, options=opt, rebuild_every=1000) as (m, ctx, t):
+            m.build_neighbors(ctx, t["pos"])
+            m.compute_nonbonded(ctx, t["pos"], t["force"])
+            m.integrate_step(ctx, t["pos"], t["vel"], t["force"], n_steps, float(dt))
+            img = torch.zeros((3, s.n_atoms), dtype=torch.int32, device="cuda:0")
+            m.get_images(ctx, img)
+            torch.cuda.synchronize()
+            assert float(t["force"].abs().max()) == 0.0
+            unwrapped = (t["pos"].cpu().numpy().astype(np.float64)
+                         + img.cpu().numpy() * s.box.astype(np.float64)[:, None])
+            assert np.array_equal(t["vel"].cpu().numpy(), s.vel)
+        err[opt] = float(np.abs(unwrapped - exact).max())
+    ulp_L = float(np.spacing(np.float32(20.0)))
+    assert err[mdx.MDX_OPT_KAHAN_VV] <= 4 * ulp_L, err
+    assert err[0] > 5 * err[mdx.MDX_OPT_KAHAN_VV], err
