@@ -57,6 +57,9 @@ extern "C" {
 #define MDX_FLAG_OUT_OF_BOX   0x8u  /* a coordinate outside [0, L)                */
 #define MDX_FLAG_CELL_OVERFLOW 0x10u /* a cluster had more candidate clusters than
                                         the search holds (list incomplete)   */
+#define MDX_FLAG_COLUMN_OVERFLOW 0x20u /* an x-y column held more atoms than its
+                                          capacity (list incomplete; grown and
+                                          rebuilt by mdx_build_neighbors)     */
 
 /* ---- energy slots (FP64) ----------------------------------------------- */
 #define MDX_ENERGY_LJ         0  /* Eq. 4 (switched by Eq. 6 if enabled)        */
@@ -256,11 +259,12 @@ int mdx_compute_pme(mdx_ctx* ctx, const float* pos, float* force, double* energy
  * holds F(pos) on exit. The list is rebuilt every rebuild_every steps, and
  * also on any step where an atom has moved more than r_g/2 since the last
  * build (tested every step on the device; no host synchronisation). The
- * number of builds is reported by mdx_get_info. Inside a step the PME FFT
- * passes run on a library-owned second stream, concurrently with the pair
- * kernel; they are forked from and joined back into the context's stream,
- * so the call is ordered on that stream like any other work. energies, if not
- * NULL, is dev double[n_steps][MDX_N_ENERGY]: all slots after each step.
+ * number of builds is reported by mdx_get_info. Inside a step the PME spread
+ * and FFT passes run on a library-owned second stream, concurrently with the
+ * pair kernel; they are forked from and joined back into the context's
+ * stream, so the call is ordered on that stream like any other work.
+ * energies, if not NULL, is dev double[n_steps][MDX_N_ENERGY]: all slots
+ * after each step.
  */
 int mdx_integrate_step(mdx_ctx* ctx, float* pos, float* vel, float* force, int32_t n_steps,
                        float dt, double* energies);

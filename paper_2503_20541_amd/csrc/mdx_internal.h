@@ -105,11 +105,11 @@ struct Ctx {
   int* cell_of = nullptr;      // [n] column of each caller atom at build
   int* cell_count = nullptr;   // [ncol] atoms per column
   int* cell_start = nullptr;   // [ncol + 1] first atom (unpadded) of each column
-  int* cell_cursor = nullptr;  // [ncol]
   int* slot_start = nullptr;   // [ncol + 1] first slot of each column (padded to clusters)
   int* meta = nullptr;         // [4] slots, clusters of the last build; builds so far;
                                // blocks done binning (the last one scans, then clears it)
-  int* perm_unsorted = nullptr;// [n]
+  int* col_atoms = nullptr;    // [ncol][col_cap] atoms binned into each column (unordered)
+  int col_cap = 0;
   int* perm = nullptr;         // [max_slots] slot -> caller atom, -1 for padding
   int* inv_perm = nullptr;     // [n] caller atom -> slot
   int2* zbin = nullptr;        // [columns][nzb + 1] first cluster with max z >= bin z, first
@@ -168,9 +168,10 @@ struct Ctx {
 // ---- launchers (each returns hipError_t of the launch) ----
 hipError_t launch_fill_i32(int* p, int v, int count, hipStream_t s);
 // gate == nullptr: unconditional build; otherwise every build kernel returns
-// at once unless *gate != 0. `done` (if given) completes once the slot
-// positions and the PME brick slot ranges are in place (before the tile
-// search), for work on another stream that needs only those.
+// at once unless *gate != 0. `done` (if given) is recorded by the column
+// sort's dispatch: the slot positions and the PME brick slot ranges are then
+// in place (before the tile search), for work on another stream that needs
+// only those.
 hipError_t launch_build_list(Ctx& c, const float* pos, const int* gate = nullptr,
                              hipEvent_t done = nullptr);
 // Copies pos into the slot array (as build position + minimum-image
@@ -183,8 +184,10 @@ int build_coop_blocks(int max_clusters, int n, int ncol);
 // gate_now / pgate_now: the step's rebuild and prune flags inside
 // mdx_integrate_step (null for stand-alone calls: full list, no pruning).
 // virial: also the FP64 virial partial rows (kRowVir), implies energy.
+// t_start / t_stop (optional): events recorded by the kernel's dispatch.
 hipError_t launch_nonbonded(Ctx& c, bool energy, const int* gate_now = nullptr,
-                            const int* pgate_now = nullptr, bool virial = false);
+                            const int* pgate_now = nullptr, bool virial = false,
+                            hipEvent_t t_start = nullptr, hipEvent_t t_stop = nullptr);
 // virial: also the partial rows kRowVirB, implies energy.
 hipError_t launch_bonded_excl(Ctx& c, const float* pos, float* force, bool energy,
                               bool virial = false);

@@ -16,11 +16,12 @@
 // definition's, while the force kernel streams whole 4x4 tiles.
 //
 // Build phases (gated: with a gate they do nothing unless it is raised):
-//   bin (column of every atom, counts) -> scan (atom and padded-slot offsets
-//   per column) -> scatter -> column sort (rank by z, write slot data), then
-//   the column's cluster boxes and PME spreading ranges -> tile search (one
-//   wave per i-cluster). By default these are four kernels (the last block
-//   to finish binning runs the scan);
+//   bin (column of every atom, appended to that column's fixed-capacity
+//   list) -> scan (atom and padded-slot offsets per column) -> column sort
+//   (rank by z, write slot data), then the column's cluster boxes and PME
+//   spreading ranges -> tile search (one wave per i-cluster). By default
+//   these are three kernels (the last block to finish binning runs the
+//   scan);
 //   k_build_all runs them all in one cooperative launch with grid-wide
 //   barriers between phases (optional: cooperative launches use a separate
 //   hardware queue, and the resident grid is smaller than the per-phase
@@ -116,11 +117,11 @@ struct BuildArgs {
   float* x_build;
   unsigned* flags;
   int* col_start;
-  int* cursor;
   int* slot_start;
   int* meta;
   int* nl_needed;
-  int* perm_unsorted;
+  int* col_atoms;   // [ncol][col_cap]
+  int col_cap;
   const float* q;
   const int* atype;
   int* perm;
@@ -142,7 +143,8 @@ struct BuildArgs {
   int max_clusters;
 };
 
-// Column of caller atom i, atoms per column, build-position snapshot. The
+// Column of caller atom i, atoms per column (the atom goes to the next free
+// place of its column's fixed-capacity list), build-position snapshot. The
 // whole wave calls it (lanes with i >= n take part in the aggregation only).
 __device__ void bin_atom(const BuildArgs& a, int i) {
   const bool active = i < a.n;
@@ -161,7 +163,11 @@ __device__ void bin_atom(const BuildArgs& a, int i) {
     a.x_build[n + i] = y;
     a.x_build[2 * n + i] = z;
   }
-  (void)wave_aggregated_inc(a.col_count, c, active);
+  const int k = wave_aggregated_inc(a.col_count, c, active);
+  if (active) {
+    if (k < a.col_cap) a.col_atoms[(size_t)c * a.col_cap + k] = i;
+    else atomicOr(a.flags, MDX_FLAG_COLUMN_OVERFLOW);
+  }
 }
 
 // Exclusive scans of the column counts (atoms) and of the counts rounded up
@@ -179,7 +185,8 @@ __device__ void scan_columns(const BuildArgs& a) {
   int s = 0, sp = 0;
   // the counts were formed by other blocks' atomics: read them at device scope
   for (int i = b; i < e; ++i) {
-    const int ci = __hip_atomic_load(&count[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int ci = min(__hip_atomic_load(&count[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                       a.col_cap);
     s += ci;
     sp += (ci + kClusterSize - 1) / kClusterSize * kClusterSize;
   }
@@ -218,9 +225,9 @@ __device__ void scan_columns(const BuildArgs& a) {
   int run = wave_tot[0][w] + v - s;
   int runp = wave_tot[1][w] + vp - sp;
   for (int i = b; i < e; ++i) {
-    const int ci = __hip_atomic_load(&count[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int ci = min(__hip_atomic_load(&count[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                       a.col_cap);
     a.col_start[i] = run;
-    a.cursor[i] = run;
     a.slot_start[i] = runp;
     run += ci;
     runp += (ci + kClusterSize - 1) / kClusterSize * kClusterSize;
@@ -228,16 +235,8 @@ __device__ void scan_columns(const BuildArgs& a) {
   }
 }
 
-// Caller atom i into its column's next unsorted position (whole wave calls).
-__device__ void scatter_atom(const BuildArgs& a, int i) {
-  const bool active = i < a.n;
-  const int c = active ? a.col_of[i] : 0;
-  const int slot = wave_aggregated_inc(a.cursor, c, active);
-  if (active) a.perm_unsorted[slot] = i;
-}
-
 // One block per column: rank its atoms by (build z, atom index) - an order
-// that does not depend on the scatter's atomic order - and write the slot
+// that does not depend on the binning's atomic order - and write the slot
 // data; padding slots of the column's last cluster are emptied. Columns of
 // up to kColStage atoms are ranked from LDS (st), larger ones from global
 // memory.
@@ -258,7 +257,7 @@ __device__ void sort_column(const BuildArgs& a, int c, float2* st) {
   __syncthreads();   // st may still be read for the previous column
   if (staged) {
     for (int p = threadIdx.x; p < cnt; p += blockDim.x) {
-      const int v = a.perm_unsorted[b + p];
+      const int v = a.col_atoms[(size_t)c * a.col_cap + p];
       st[p] = make_float2(z_key(a.pos[2 * n + v]), __int_as_float(v));
     }
     __syncthreads();
@@ -276,10 +275,10 @@ __device__ void sort_column(const BuildArgs& a, int c, float2* st) {
         rank += (o.x < zv || (o.x == zv && u < v)) ? 1 : 0;
       }
     } else {
-      v = a.perm_unsorted[b + p];
+      v = a.col_atoms[(size_t)c * a.col_cap + p];
       zv = z_key(a.pos[2 * n + v]);
       for (int k = 0; k < cnt; ++k) {
-        const int u = a.perm_unsorted[b + k];
+        const int u = a.col_atoms[(size_t)c * a.col_cap + k];
         const float zu = z_key(a.pos[2 * n + u]);
         rank += (zu < zv || (zu == zv && u < v)) ? 1 : 0;
       }
@@ -754,11 +753,6 @@ __global__ void __launch_bounds__(256) k_bin_scan(BuildArgs a) {
   if (threadIdx.x == 0) a.meta[3] = 0;
 }
 
-__global__ void k_scatter(BuildArgs a) {
-  if (gated_off(a.gate)) return;
-  scatter_atom(a, blockIdx.x * blockDim.x + threadIdx.x);
-}
-
 __global__ void __launch_bounds__(kColThreads) k_col_sort(BuildArgs a) {
   if (gated_off(a.gate)) return;
   __shared__ float2 st[kColStage];   // (build z, atom index bits)
@@ -796,8 +790,6 @@ __global__ void __launch_bounds__(kBuildThreads) k_build_all(BuildArgs a) {
   for (int i = tid; i < nround; i += nthreads) bin_atom(a, i);
   grid.sync();
   if (blockIdx.x == 0) scan_columns(a);
-  grid.sync();
-  for (int i = tid; i < nround; i += nthreads) scatter_atom(a, i);
   grid.sync();
   for (int c = blockIdx.x; c < a.cg.ncell; c += gridDim.x) sort_column_boxes(a, c, st);
   grid.sync();
@@ -853,8 +845,8 @@ hipError_t launch_build_list(Ctx& c, const float* pos, const int* gate, hipEvent
   const int n = c.n;
   const int ncol = c.cg.ncell;
   BuildArgs a{gate, pos, n, c.cg, c.cell_of, c.cell_count, c.x_build, c.flags,
-              c.cell_start, c.cell_cursor, c.slot_start, c.meta, c.nl_needed,
-              c.perm_unsorted, c.q, c.atype, c.perm, c.inv_perm, c.xs, c.ts, c.zb,
+              c.cell_start, c.slot_start, c.meta, c.nl_needed,
+              c.col_atoms, c.col_cap, c.q, c.atype, c.perm, c.inv_perm, c.xs, c.ts, c.zb,
               c.box_lo, c.box_hi, c.col_xy,
               ZRangeArgs{c.zb, c.slot_start, c.cell_start, c.brick_z,
                          c.has_pme ? c.pg.nb[2] : 0, ncol, c.cg.L[2], c.brick_zr},
@@ -869,7 +861,6 @@ hipError_t launch_build_list(Ctx& c, const float* pos, const int* gate, hipEvent
   }
   const int nb = (n + 255) / 256;
   k_bin_scan<<<nb, 256, 0, s>>>(a);
-  k_scatter<<<nb, 256, 0, s>>>(a);
   // the column sort completes the slot positions and the PME brick ranges:
   // `done` is recorded by its own dispatch
   if (done) {

@@ -21,6 +21,8 @@
 // k_reduce_rows: fixed-order FP64 reduction of per-block partial sums.
 #include "atom_terms.h"
 
+#include <hip/hip_ext.h>
+
 namespace mdx {
 
 // erfc(x) = exp(-x^2) R(x): R = t P(t), t = 1/(1 + 0.42 x), with P of degree 7
@@ -395,7 +397,7 @@ __global__ void __launch_bounds__(256) k_reduce_rows(const double* __restrict__ 
 }
 
 hipError_t launch_nonbonded(Ctx& c, bool energy, const int* gate_now, const int* pgate_now,
-                            bool virial) {
+                            bool virial, hipEvent_t t_start, hipEvent_t t_stop) {
   PairParams pp;
   for (int d = 0; d < 3; ++d) {
     pp.L[d] = c.cg.L[d];
@@ -416,10 +418,16 @@ hipError_t launch_nonbonded(Ctx& c, bool energy, const int* gate_now, const int*
   const int nb = (c.max_clusters + 3) / 4;
   c.nb_blocks = nb;
   const PruneArgs pr{gate_now, pgate_now, c.ptiles, c.pcount, c.xp, c.prune_r2};
-#define MDX_PAIR(E, C, S, H, V)                                                            \
-  k_pair<E, C, S, H, V><<<nb, 256, 0, c.stream>>>(c.xs, c.ts, c.tiles, c.tile_count, c.meta, \
-                                                   c.nl_cap, pp, c.lj_f, c.lj_d, c.fslot,    \
-                                                   c.max_slots, c.partials, c.max_blocks, pr)
+  // the timing events (optional) are recorded by the dispatch itself: no
+  // marker packets around the kernel
+#define MDX_PAIR(E, C, S, H, V)                                                              \
+  hipExtLaunchKernelGGL(k_pair<E, C, S, H, V>, dim3(nb), dim3(256), 0, c.stream, t_start,     \
+                        t_stop, 0u, static_cast<const float4*>(c.xs),                         \
+                        static_cast<const int*>(c.ts), static_cast<const uint2*>(c.tiles),    \
+                        static_cast<const int*>(c.tile_count), static_cast<const int*>(c.meta), \
+                        c.nl_cap, pp, static_cast<const float4*>(c.lj_f),                     \
+                        static_cast<const double2*>(c.lj_d), c.fslot, c.max_slots, c.partials, \
+                        c.max_blocks, pr)
 #define MDX_PAIR_H(E, C, S)             \
   if (c.half_list)                      \
     MDX_PAIR(E, C, S, true, false);     \

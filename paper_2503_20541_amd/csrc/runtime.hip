@@ -396,14 +396,18 @@ int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
   if ((rc = dev_alloc(x, &c.cell_count, ncol)) != MDX_OK) return rc;
   MDX_TRY(hipMemset(c.cell_count, 0, sizeof(int) * ncol));
   if ((rc = dev_alloc(x, &c.cell_start, ncol + 1)) != MDX_OK) return rc;
-  if ((rc = dev_alloc(x, &c.cell_cursor, ncol)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.slot_start, ncol + 1)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.meta, 4)) != MDX_OK) return rc;
   MDX_TRY(hipMemset(c.meta, 0, 4 * sizeof(int)));
-  if ((rc = dev_alloc(x, &c.perm_unsorted, n)) != MDX_OK) return rc;
+  // atoms binned per column: twice the mean with headroom (a column that
+  // overflows latches MDX_FLAG_COLUMN_OVERFLOW; mdx_build_neighbors grows it)
+  c.col_cap = std::min(n, std::max(64, 2 * ((n + ncol - 1) / ncol) + 32));
+  if ((rc = dev_alloc(x, &c.col_atoms, (size_t)ncol * c.col_cap)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.perm, c.max_slots)) != MDX_OK) return rc;
   MDX_TRY(hipMemset(c.perm, 0xff, sizeof(int) * c.max_slots));   // every slot empty (-1)
   if ((rc = dev_alloc(x, &c.inv_perm, n)) != MDX_OK) return rc;
+  // an atom a column could not hold keeps its previous slot: a valid index
+  MDX_TRY(hipMemset(c.inv_perm, 0, sizeof(int) * n));
   if ((rc = dev_alloc(x, &c.xs, c.max_slots)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.zbin, (size_t)ncol * (g.nzb + 1))) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.fslot, (size_t)3 * c.max_slots)) != MDX_OK) return rc;
@@ -468,12 +472,12 @@ int check_ctx(mdx_ctx* x) { return x ? MDX_OK : MDX_E_INVALID; }
 
 constexpr size_t kMaxTimed = 8192;
 
-// Records an event pair around the launches made by `fn` when timing is on.
-// Starts a timed interval of `group` on `stream` (no-op unless the group is
-// recorded); *slot receives the event pair to close with timing_end, or
-// nullptr.
-hipError_t timing_begin(mdx_ctx* x, int group, hipStream_t stream,
-                        std::pair<hipEvent_t, hipEvent_t>** slot) {
+// Event pairs of the timed groups. timing_slot hands out the next pair of
+// `group` (*slot = nullptr unless the group is recorded) for a caller that
+// has a dispatch record them; timing_begin also records the first event on
+// `stream` (close the interval with timing_end); timed() brackets the
+// launches made by `fn`.
+hipError_t timing_slot(mdx_ctx* x, int group, std::pair<hipEvent_t, hipEvent_t>** slot) {
   *slot = nullptr;
   if (!((x->timing >> group) & 1u) || x->used[group] >= kMaxTimed) return hipSuccess;
   auto& v = x->ev[group];
@@ -485,6 +489,13 @@ hipError_t timing_begin(mdx_ctx* x, int group, hipStream_t stream,
     v.push_back({a, b});
   }
   *slot = &v[x->used[group]++];
+  return hipSuccess;
+}
+
+hipError_t timing_begin(mdx_ctx* x, int group, hipStream_t stream,
+                        std::pair<hipEvent_t, hipEvent_t>** slot) {
+  hipError_t e = timing_slot(x, group, slot);
+  if (e != hipSuccess || !*slot) return e;
   return hipEventRecord((*slot)->first, stream);
 }
 
@@ -531,8 +542,13 @@ int mdx_create(mdx_ctx** out, const mdx_system_desc* d, void* hip_stream) {
     return MDX_E_HIP;
   }
   x->c.stream = static_cast<hipStream_t>(hip_stream);
+  // these events only order the two streams on this device: no timestamps,
+  // and a device-scope release (not a system-scope one, which writes the
+  // caches back for the host) when they are recorded
+  const unsigned ev_flags = hipEventDisableTiming | hipEventReleaseToDevice;
   if (hipStreamCreateWithFlags(&x->aux, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreate(&x->ev_fork) != hipSuccess || hipEventCreate(&x->ev_join) != hipSuccess) {
+      hipEventCreateWithFlags(&x->ev_fork, ev_flags) != hipSuccess ||
+      hipEventCreateWithFlags(&x->ev_join, ev_flags) != hipSuccess) {
     mdx_destroy(x);
     return MDX_E_HIP;
   }
@@ -581,22 +597,33 @@ int mdx_build_neighbors(mdx_ctx* x, const float* pos) {
     MDX_TRY(mdx::launch_fill_i32(reinterpret_cast<int*>(c.xc), 0, 3 * c.n, c.stream));
     MDX_TRY(mdx::launch_fill_i32(reinterpret_cast<int*>(c.vc), 0, 3 * c.n, c.stream));
   }
-  for (int attempt = 0; attempt < 3; ++attempt) {
+  // A column list grows by doubling up to n atoms (where it cannot
+  // overflow), the tile list to the count the build reported, so this ends
+  // after a few attempts.
+  for (int attempt = 0; attempt < 40; ++attempt) {
     MDX_TRY(timed(x, MDX_TIMING_BUILD, c.stream, [&] { return mdx::launch_build_list(c, pos); }));
     int needed = 0;
     MDX_TRY(hipMemcpyAsync(&needed, c.nl_needed, sizeof(int), hipMemcpyDeviceToHost, c.stream));
     MDX_TRY(hipStreamSynchronize(c.stream));
     c.steps_since_build = 0;
-    unsigned fl0 = 0;
-    MDX_TRY(hipMemcpy(&fl0, c.flags, sizeof(unsigned), hipMemcpyDeviceToHost));
-    if (fl0 & MDX_FLAG_CELL_OVERFLOW) return MDX_E_UNSUPPORTED;
-    if (needed <= c.nl_cap) return MDX_OK;
-    // grow, clear the overflow bit this build latched, and build again
-    int rc = alloc_list(x, (needed + needed / 8 + 16 + 15) / 16 * 16);
-    if (rc != MDX_OK) return rc;
     unsigned fl = 0;
     MDX_TRY(hipMemcpy(&fl, c.flags, sizeof(unsigned), hipMemcpyDeviceToHost));
-    fl &= ~MDX_FLAG_NL_OVERFLOW;
+    if (fl & MDX_FLAG_CELL_OVERFLOW) return MDX_E_UNSUPPORTED;
+    if (fl & MDX_FLAG_COLUMN_OVERFLOW) {
+      dev_free(x, c.col_atoms);
+      c.col_atoms = nullptr;
+      c.col_cap = std::min(c.n, 2 * c.col_cap);
+      int rc = dev_alloc(x, &c.col_atoms, (size_t)c.cg.ncell * c.col_cap);
+      if (rc != MDX_OK) return rc;
+      // the tile count of an incomplete list says nothing: build again first
+    } else if (needed <= c.nl_cap) {
+      return MDX_OK;
+    } else {
+      int rc = alloc_list(x, (needed + needed / 8 + 16 + 15) / 16 * 16);
+      if (rc != MDX_OK) return rc;
+    }
+    // clear the overflow bits this build latched, and build again
+    fl &= ~(MDX_FLAG_NL_OVERFLOW | MDX_FLAG_COLUMN_OVERFLOW);
     MDX_TRY(hipMemcpy(c.flags, &fl, sizeof(unsigned), hipMemcpyHostToDevice));
   }
   return MDX_E_HIP;
@@ -760,8 +787,14 @@ int mdx_integrate_step(mdx_ctx* x, float* pos, float* vel, float* force, int32_t
       MDX_TRY(timing_end(tslot, x->aux));
       if (tslot) MDX_TRY(hipEventRecord(x->ev_join, x->aux));
     }
-    MDX_TRY(timed(x, MDX_TIMING_PAIR, c.stream,
-                  [&] { return mdx::launch_nonbonded(c, e, gate_now, pgate_now); }));
+    {
+      // timed by events that the pair kernel's dispatch records (marker
+      // packets between kernels would lengthen the step)
+      std::pair<hipEvent_t, hipEvent_t>* ps;
+      MDX_TRY(timing_slot(x, MDX_TIMING_PAIR, &ps));
+      MDX_TRY(mdx::launch_nonbonded(c, e, gate_now, pgate_now, false,
+                                    ps ? ps->first : nullptr, ps ? ps->second : nullptr));
+    }
     if (c.has_pme) MDX_TRY(hipStreamWaitEvent(c.stream, x->ev_join, 0));
     MDX_TRY(mdx::launch_finish_step(c, pos, vel, force, dt, e));
     if (e) {

@@ -38,6 +38,7 @@ MDX_FLAG_NL_STALE = 0x2
 MDX_FLAG_NONFINITE = 0x4
 MDX_FLAG_OUT_OF_BOX = 0x8
 MDX_FLAG_CELL_OVERFLOW = 0x10
+MDX_FLAG_COLUMN_OVERFLOW = 0x20
 
 MDX_ENERGY_LJ = 0
 MDX_ENERGY_COUL_DIR = 1

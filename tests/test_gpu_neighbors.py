@@ -81,6 +81,22 @@ def test_list_relabelling_and_capacity_growth():
     assert np.array_equal(mapped, _oracle_pairs(s))
 
 
+def test_list_crowded_column_grows_column_capacity():
+    # 600 of 2000 atoms squeezed into one x-y column: far more than a column
+    # holds by default, so the build latches the column overflow, grows the
+    # column lists and builds again; the list is still the exact one
+    s = synth.random_box(2000, [20.0, 20.0, 20.0], 2.0, 0.5, 31, n_excl_per_atom=1)
+    rng = np.random.default_rng(5)
+    s.pos[0, :600] = rng.uniform(0.0, 1.0, 600).astype(np.float32)
+    s.pos[1, :600] = rng.uniform(0.0, 1.0, 600).astype(np.float32)
+    announce("list with one crowded column")
+    with gpu_context(s) as (mdx, ctx, t):
+        mdx.build_neighbors(ctx, t["pos"])
+        got = mdx.get_neighbor_pairs(ctx)
+        assert mdx.get_status(ctx) == 0
+    assert np.array_equal(got, _oracle_pairs(s))
+
+
 def test_list_water96k_sampled_rows():
     s = synth.config_system("water96k")
     announce("list water96k")
