@@ -53,26 +53,6 @@ __device__ __forceinline__ int bin_coord(float x, float inv_w, int n) {
 
 __device__ __forceinline__ bool gated_off(const int* gate) { return gate && *gate == 0; }
 
-// atomicAdd(&ctr[key], 1) for every active lane, aggregated over the lanes of
-// the wave that share a key (one atomic per distinct key); returns the value
-// this lane would have seen (leader's old value + rank among equal keys).
-__device__ __forceinline__ int wave_aggregated_inc(int* __restrict__ ctr, int key, bool active) {
-  const int lane = threadIdx.x & (kWave - 1);
-  unsigned long long todo = __ballot(active);
-  int result = 0;
-  while (todo) {
-    const int leader = __ffsll((long long)todo) - 1;
-    const int lkey = __shfl(key, leader, kWave);
-    const unsigned long long same = __ballot(active && key == lkey);
-    int base = 0;
-    if (lane == leader) base = atomicAdd(&ctr[lkey], __popcll(same));
-    base = __shfl(base, leader, kWave);
-    if (active && key == lkey) result = base + __popcll(same & ((1ull << lane) - 1ull));
-    todo &= ~same;
-  }
-  return result;
-}
-
 // For the PME spreading: per (brick layer along z, column) the slots of the
 // column whose build z lies in the layer's reach [lo, hi) - one segment, or
 // two when the reach wraps around the periodic box.
@@ -144,8 +124,11 @@ struct BuildArgs {
 };
 
 // Column of caller atom i, atoms per column (the atom goes to the next free
-// place of its column's fixed-capacity list), build-position snapshot. The
-// whole wave calls it (lanes with i >= n take part in the aggregation only).
+// place of its column's fixed-capacity list), build-position snapshot. One
+// returning atomic per atom: the lanes of a wave hit many columns once the
+// atoms have mixed, and one instruction keeps all of them in flight (a
+// wave-aggregated increment would wait for one round trip per distinct
+// column).
 __device__ void bin_atom(const BuildArgs& a, int i) {
   const bool active = i < a.n;
   int c = 0;
@@ -163,8 +146,8 @@ __device__ void bin_atom(const BuildArgs& a, int i) {
     a.x_build[n + i] = y;
     a.x_build[2 * n + i] = z;
   }
-  const int k = wave_aggregated_inc(a.col_count, c, active);
   if (active) {
+    const int k = atomicAdd(&a.col_count[c], 1);
     if (k < a.col_cap) a.col_atoms[(size_t)c * a.col_cap + k] = i;
     else atomicOr(a.flags, MDX_FLAG_COLUMN_OVERFLOW);
   }
@@ -743,12 +726,16 @@ __global__ void __launch_bounds__(256) k_bin_scan(BuildArgs a) {
   if (gated_off(a.gate)) return;
   __shared__ int last;
   bin_atom(a, blockIdx.x * blockDim.x + threadIdx.x);
-  __threadfence();
+  // The counts are atomics whose results every lane has received before the
+  // barrier; one device-scope release per block (not a cache write-back per
+  // wave) orders them before the block is counted, and the last block's
+  // acquire before the scan reads them.
   __syncthreads();
-  if (threadIdx.x == 0) last = atomicAdd(&a.meta[3], 1) == (int)gridDim.x - 1;
+  if (threadIdx.x == 0)
+    last = __hip_atomic_fetch_add(&a.meta[3], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) ==
+           (int)gridDim.x - 1;
   __syncthreads();
   if (!last) return;
-  __threadfence();
   scan_columns(a);
   if (threadIdx.x == 0) a.meta[3] = 0;
 }
