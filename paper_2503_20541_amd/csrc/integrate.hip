@@ -26,64 +26,91 @@ __device__ __forceinline__ float wrap_box(float x, float L, int& wraps) {
   return x;
 }
 
-// Opening half of a step for every slot: v += (dt/2) a, x += dt v (wrapped),
-// slot position refreshed (as build position + minimum-image displacement),
-// r_g/2 validity test (raises gate_now) and the
-// pruned list's validity test (raises pgate_now). Thread 0 clears the flags
-// of the following step (nothing else touches them here) and raises
-// gate_now on a cadence rebuild.
-__global__ void __launch_bounds__(256) k_begin_step(
-    float* __restrict__ pos, float* __restrict__ vel, const float* __restrict__ force,
-    const float* __restrict__ acc_over_m, const int* __restrict__ perm,
-    const float* __restrict__ q, const float* __restrict__ x_build, const int* __restrict__ meta,
-    int n, CellGrid cg, float half_dt, float dt, float half_skin2, float4* __restrict__ xs,
-    unsigned* __restrict__ flags, int* __restrict__ gate_now, int* __restrict__ gate_next,
-    const float4* __restrict__ xp, float prune_move2, int* __restrict__ pgate_now,
-    int* __restrict__ pgate_next, int force_rebuild, int* __restrict__ img,
-    float* __restrict__ xc, float* __restrict__ vc) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s == 0) {
-    *gate_next = 0;
-    *pgate_next = 0;
-    if (force_rebuild) *gate_now = 1;
-  }
-  if (s >= meta[0]) return;
-  const int a = perm[s];
-  if (a < 0) return;
-  const float h = half_dt * acc_over_m[a];
+// Opening half of a step (v += (dt/2) a, x += dt v wrapped) for atom a in
+// slot s, with the slot position refreshed (as build position + minimum-image
+// displacement), the r_g/2 validity test (raises gate_now) and the pruned
+// list's validity test (raises pgate_now). Positions are read from pos_in
+// and written to pos_out (the same array for the stand-alone kernel).
+struct OpenStep {
+  const float* pos_in;
+  float* pos_out;
+  const float* x_build;
+  const float4* xp;
+  const float* q;
+  const float* acc_over_m;
+  float4* xs;
+  int* img;
+  float* xc;
+  float* vc;
+  int* gate_now;
+  int* gate_next;
+  int* pgate_now;
+  int* pgate_next;
+  int force_rebuild;
+  int n;
+  CellGrid cg;
+  float half_dt, dt, half_skin2, prune_move2;
+};
+
+// Thread 0 of the grid clears the flags of the step after (nothing else
+// touches them in this kernel) and raises gate_now on a cadence rebuild.
+__device__ __forceinline__ void open_step_flags(const OpenStep& o) {
+  *o.gate_next = 0;
+  *o.pgate_next = 0;
+  if (o.force_rebuild) *o.gate_now = 1;
+}
+
+__device__ __forceinline__ void open_step_atom(const OpenStep& o, const float* __restrict__ force,
+                                               float* __restrict__ vel, int a, int s) {
+  const int n = o.n;
+  const CellGrid& cg = o.cg;
+  const float h = o.half_dt * o.acc_over_m[a];
   float x[3];
   for (int d = 0; d < 3; ++d) {
     const size_t k = (size_t)d * n + a;
     int wraps;
-    if (xc) {   // compensated sums (MDX_OPT_KAHAN_VV)
-      float cv = vc[k], cx = xc[k];
+    if (o.xc) {   // compensated sums (MDX_OPT_KAHAN_VV)
+      float cv = o.vc[k], cx = o.xc[k];
       const float v = kahan_add(vel[k], h * force[k], cv);
       vel[k] = v;
-      x[d] = wrap_box(kahan_add(pos[k], dt * v, cx), cg.L[d], wraps);
-      vc[k] = cv;
-      xc[k] = cx;
+      x[d] = wrap_box(kahan_add(o.pos_in[k], o.dt * v, cx), cg.L[d], wraps);
+      o.vc[k] = cv;
+      o.xc[k] = cx;
     } else {
       const float v = vel[k] + h * force[k];
       vel[k] = v;
-      x[d] = wrap_box(pos[k] + dt * v, cg.L[d], wraps);
+      x[d] = wrap_box(o.pos_in[k] + o.dt * v, cg.L[d], wraps);
     }
-    pos[k] = x[d];
-    if (wraps) img[k] += wraps;
+    o.pos_out[k] = x[d];
+    if (wraps) o.img[k] += wraps;
   }
-  const float bx = x_build[a], by = x_build[n + a], bz = x_build[2 * n + a];
+  const float bx = o.x_build[a], by = o.x_build[n + a], bz = o.x_build[2 * n + a];
   const float dx = min_image(bx, x[0], cg.L[0], cg.hL[0]);
   const float dy = min_image(by, x[1], cg.L[1], cg.hL[1]);
   const float dz = min_image(bz, x[2], cg.L[2], cg.hL[2]);
   // slot position continued from the build position (not wrapped between
   // builds), so the periodic image each list tile records stays valid
-  xs[s] = make_float4(bx + dx, by + dy, bz + dz, q[a]);
-  if (dist2(dx, dy, dz) > half_skin2) atomicOr(gate_now, 1);
+  o.xs[s] = make_float4(bx + dx, by + dy, bz + dz, o.q[a]);
+  if (dist2(dx, dy, dz) > o.half_skin2) atomicOr(o.gate_now, 1);
   // pruned list: displacement since it was made (same slot order)
-  const float4 q0 = xp[s];
+  const float4 q0 = o.xp[s];
   const float px = min_image(q0.x, x[0], cg.L[0], cg.hL[0]);
   const float py = min_image(q0.y, x[1], cg.L[1], cg.hL[1]);
   const float pz = min_image(q0.z, x[2], cg.L[2], cg.hL[2]);
-  if (dist2(px, py, pz) > prune_move2) atomicOr(pgate_now, 1);
+  if (dist2(px, py, pz) > o.prune_move2) atomicOr(o.pgate_now, 1);
+}
+
+// Stand-alone opening half for every slot (the first step of a call).
+__global__ void __launch_bounds__(256) k_begin_step(OpenStep o, const float* __restrict__ force,
+                                                    float* __restrict__ vel,
+                                                    const int* __restrict__ perm,
+                                                    const int* __restrict__ meta) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s == 0) open_step_flags(o);
+  if (s >= meta[0]) return;
+  const int a = perm[s];
+  if (a < 0) return;
+  open_step_atom(o, force, vel, a, s);
 }
 
 // Closing half of a step, four lanes per slot: lane q of the quad takes z
@@ -91,7 +118,12 @@ __global__ void __launch_bounds__(256) k_begin_step(
 // atom; the quad sums its parts in a fixed order, and lane 0 adds the pair
 // force accumulated in the slot array (which it clears for the next
 // evaluation), stores the total and applies v += (dt/2) a. FP64 energy
-// partials (exclusion, bond, angle, kinetic) per block.
+// partials (exclusion, bond, angle, kinetic) per block. With `open`, lane 0
+// then opens the next step for its atom (open_step_atom, from the velocity
+// and force it has just stored): the same values as a separate opening
+// kernel, one launch fewer per step. The bonded terms read the positions of
+// other atoms from `pos`, so the new positions go to o.pos_out (another
+// buffer).
 constexpr int kFinishLanes = 4;
 
 template <bool ENERGY, bool COUL, bool PME>
@@ -101,9 +133,11 @@ __global__ void __launch_bounds__(256) k_finish_step(
     BondedParams bp, Topology tp, float* __restrict__ fslot, int fstride,
     float* __restrict__ force, float* __restrict__ vel,
     const float* __restrict__ acc_over_m, const float* __restrict__ mass, float half_dt,
-    double inv_2acc, double* __restrict__ partials, int pstride, float* __restrict__ vc) {
+    double inv_2acc, double* __restrict__ partials, int pstride, float* __restrict__ vc,
+    OpenStep o, int open) {
   __shared__ double red[16];
   const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+  if (open && gt == 0) open_step_flags(o);
   const int s = gt / kFinishLanes, q = gt & (kFinishLanes - 1);
   double e_ex = 0.0, e_b = 0.0, e_a = 0.0, ke = 0.0;
   const int a = s < meta[0] ? perm[s] : -1;
@@ -150,6 +184,7 @@ __global__ void __launch_bounds__(256) k_finish_step(
     vel[2 * n + a] = v2;
     if (ENERGY)
       ke = (double)mass[a] * ((double)v0 * v0 + (double)v1 * v1 + (double)v2 * v2) * inv_2acc;
+    if (open) open_step_atom(o, force, vel, a, s);
   }
   if (ENERGY) {
     double s1 = block_sum(e_ex, red);
@@ -165,19 +200,49 @@ __global__ void __launch_bounds__(256) k_finish_step(
   }
 }
 
-hipError_t launch_begin_step(Ctx& c, float* pos, float* vel, const float* force, float dt,
-                             int* gate_now, int* gate_next, int* pgate_now, int* pgate_next,
-                             bool force_rebuild) {
+namespace {
+OpenStep make_open(const Ctx& c, const float* pos_in, float* pos_out, float dt,
+                   const StepGates& g) {
   const float h = 0.5f * c.r_ghost;
-  k_begin_step<<<(c.max_slots + 255) / 256, 256, 0, c.stream>>>(
-      pos, vel, force, c.hdt_scale, c.perm, c.q, c.x_build, c.meta, c.n, c.cg, 0.5f * dt, dt,
-      h * h, c.xs, c.flags, gate_now, gate_next, c.xp, c.prune_move2, pgate_now, pgate_next,
-      force_rebuild ? 1 : 0, c.img, c.xc, c.vc);
+  OpenStep o;
+  o.pos_in = pos_in;
+  o.pos_out = pos_out;
+  o.x_build = c.x_build;
+  o.xp = c.xp;
+  o.q = c.q;
+  o.acc_over_m = c.hdt_scale;
+  o.xs = c.xs;
+  o.img = c.img;
+  o.xc = c.xc;
+  o.vc = c.vc;
+  o.gate_now = g.gate_now;
+  o.gate_next = g.gate_next;
+  o.pgate_now = g.pgate_now;
+  o.pgate_next = g.pgate_next;
+  o.force_rebuild = g.cadence ? 1 : 0;
+  o.n = c.n;
+  o.cg = c.cg;
+  o.half_dt = 0.5f * dt;
+  o.dt = dt;
+  o.half_skin2 = h * h;
+  o.prune_move2 = c.prune_move2;
+  return o;
+}
+}  // namespace
+
+hipError_t launch_begin_step(Ctx& c, float* pos, float* vel, const float* force, float dt,
+                             const StepGates& g) {
+  k_begin_step<<<(c.max_slots + 255) / 256, 256, 0, c.stream>>>(make_open(c, pos, pos, dt, g),
+                                                                 force, vel, c.perm, c.meta);
   return hipGetLastError();
 }
 
 hipError_t launch_finish_step(Ctx& c, const float* pos, float* vel, float* force, float dt,
-                              bool energy) {
+                              bool energy, const StepGates* next, float* pos_next) {
+  if (next && (!pos_next || pos_next == pos)) return hipErrorInvalidValue;
+  const StepGates none{c.gate, c.gate, c.gate, c.gate, false};   // not used when !next
+  const OpenStep o = make_open(c, pos, pos_next, dt, next ? *next : none);
+  const int open = next ? 1 : 0;
   const int nb = (c.max_slots * kFinishLanes + 255) / 256;
   const PmeParams pp = c.has_pme ? make_pme_params(c) : PmeParams{};
   const BondedParams bp = make_bonded_params(c);
@@ -188,7 +253,8 @@ hipError_t launch_finish_step(Ctx& c, const float* pos, float* vel, float* force
   k_finish_step<E, C, P><<<nb, 256, 0, c.stream>>>(c.xs, c.perm, c.meta, c.grid_phi, pp, pos, \
                                                     c.n, bp, tp, c.fslot, c.max_slots, force, \
                                                     vel, c.hdt_scale, c.mass, 0.5f * dt,      \
-                                                    inv_2acc, c.partials, c.max_blocks, c.vc)
+                                                    inv_2acc, c.partials, c.max_blocks, c.vc, \
+                                                    o, open)
   const bool C = c.has_coulomb, P = c.has_pme;
   if (energy) {
     if (C && P) MDX_FIN(true, true, true);

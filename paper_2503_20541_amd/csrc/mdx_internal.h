@@ -89,6 +89,7 @@ struct Ctx {
   float4* lj_f = nullptr;      // [T*T] (c12, c6, 12 c12, 6 c6), c_n = 4 eps sigma^n, FP32
   double2* lj_d = nullptr;     // [T*T] (c12, c6) in FP64 for energies
   float* hdt_scale = nullptr;  // accel / m_i  (times dt/2 at use)
+  float* pos_alt = nullptr;    // [3][n] second position buffer of mdx_integrate_step
   float* mass = nullptr;
   // exclusions per atom (CSR, caller order, both directions)
   int* ex_start = nullptr;
@@ -204,11 +205,25 @@ bool pme_size_supported(int K);
 // virial: also the reciprocal-space virial partial rows (kRowVir).
 hipError_t launch_pme(Ctx& c, float* force, bool energy, bool virial = false);
 // Fused per-slot step kernels used by mdx_integrate_step.
+// The flags of one step: its rebuild and prune gates, the next step's (which
+// the opening kernel clears), and whether the rebuild cadence falls on it.
+struct StepGates {
+  int* gate_now;
+  int* gate_next;
+  int* pgate_now;
+  int* pgate_next;
+  bool cadence;
+};
+// Opening half of a step: positions read from and written to pos (in place).
 hipError_t launch_begin_step(Ctx& c, float* pos, float* vel, const float* force, float dt,
-                             int* gate_now, int* gate_next, int* pgate_now, int* pgate_next,
-                             bool force_rebuild);
+                             const StepGates& g);
+// Closing half of a step at positions pos. With `next`, the same kernel then
+// opens the following step (gates *next) from the closing kick's velocities
+// and forces, reading pos and writing the new positions to pos_next (another
+// buffer: the bonded terms of other atoms still read pos).
 hipError_t launch_finish_step(Ctx& c, const float* pos, float* vel, float* force, float dt,
-                              bool energy);
+                              bool energy, const StepGates* next = nullptr,
+                              float* pos_next = nullptr);
 // Spread + FFT passes only (the potential grid), for the fused closing kernel.
 // `done` (may be null) is recorded by the last kernel's own dispatch.
 hipError_t launch_pme_spread(Ctx& c, hipStream_t s, hipEvent_t done);

@@ -77,7 +77,7 @@ __device__ __forceinline__ float sum_rows4(float x) {
 }
 
 // The pair kernel stages the LJ type-pair table in LDS (at most
-// kMaxLjTypes^2 type pairs; mdx_create rejects more types).
+// kMaxLjTypes^2 type pairs, 16 KB; mdx_create rejects more types).
 
 // Dynamic pruning (an optimisation of the Verlet list's use, Sec. II.A.2):
 // the tiles with a pair within r_p = r_c + 0.4 r_g at the emitting step are
@@ -105,7 +105,9 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
                                               double* __restrict__ partials, int pstride,
                                               PruneArgs pr) {
   __shared__ double red[16];
-  __shared__ float4 lj_s[kMaxLjTypes * kMaxLjTypes];
+  // LJ type-pair table, ntypes^2 entries (dynamic: the concurrent PME
+  // kernels keep the rest of the CU's LDS)
+  extern __shared__ float4 lj_s[];
   // Reserve 80 VGPRs (the clobber marks v79 as used): at most 6 of the 8
   // wave slots per SIMD go to this kernel, and the PME FFT passes that run
   // concurrently on the second stream always find room on every CU. The
@@ -417,11 +419,12 @@ hipError_t launch_nonbonded(Ctx& c, bool energy, const int* gate_now, const int*
   pp.inv_sw = c.has_switch ? 1.0f / (c.r_cut - c.switch_r) : 0.f;
   const int nb = (c.max_clusters + 3) / 4;
   c.nb_blocks = nb;
+  const size_t lds = sizeof(float4) * (size_t)c.n_types * c.n_types;
   const PruneArgs pr{gate_now, pgate_now, c.ptiles, c.pcount, c.xp, c.prune_r2};
   // the timing events (optional) are recorded by the dispatch itself: no
   // marker packets around the kernel
 #define MDX_PAIR(E, C, S, H, V)                                                              \
-  hipExtLaunchKernelGGL(k_pair<E, C, S, H, V>, dim3(nb), dim3(256), 0, c.stream, t_start,     \
+  hipExtLaunchKernelGGL(k_pair<E, C, S, H, V>, dim3(nb), dim3(256), lds, c.stream, t_start,   \
                         t_stop, 0u, static_cast<const float4*>(c.xs),                         \
                         static_cast<const int*>(c.ts), static_cast<const uint2*>(c.tiles),    \
                         static_cast<const int*>(c.tile_count), static_cast<const int*>(c.meta), \

@@ -418,6 +418,7 @@ int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
   if ((rc = dev_alloc(x, &c.box_hi, c.max_clusters)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.col_xy, ncol)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.img, (size_t)3 * n)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.pos_alt, (size_t)3 * n)) != MDX_OK) return rc;
   MDX_TRY(hipMemset(c.img, 0, sizeof(int) * 3 * (size_t)n));
   if (d->options & MDX_OPT_KAHAN_VV) {
     if ((rc = dev_alloc(x, &c.xc, (size_t)3 * n)) != MDX_OK) return rc;
@@ -753,23 +754,35 @@ int mdx_integrate_step(mdx_ctx* x, float* pos, float* vel, float* force, int32_t
     MDX_TRY(mdx::launch_build_list(c, pos));
     c.steps_since_build = 0;
   }
+  const bool e = energies != nullptr;
+  // The list is rebuilt on the cadence, and in between whenever an atom has
+  // moved more than r_g/2 since the last build: the opening half of a step
+  // raises the step's gate, the build kernels run only if it is raised. Two
+  // gates alternate with the step parity, so the kernel that clears the next
+  // step's gate never touches the one being raised.
+  auto gates_of = [&](int64_t step) {
+    mdx::StepGates g;
+    g.gate_now = c.gate + (step & 1);
+    g.gate_next = c.gate + ((step + 1) & 1);
+    g.pgate_now = g.gate_now + 2;
+    g.pgate_next = g.gate_next + 2;
+    g.cadence = ++c.steps_since_build >= c.rebuild_every;
+    if (g.cadence) c.steps_since_build = 0;
+    return g;
+  };
+  // The first step opens with its own kernel; every later one is opened by
+  // the closing kernel of the step before, which reads the positions from
+  // one buffer and writes the new ones to the other (the caller's array and
+  // pos_alt, alternating); the last positions are copied back if needed.
+  float* pos_cur = pos;
+  float* pos_other = c.pos_alt;
+  mdx::StepGates g = gates_of(c.steps_taken);
+  MDX_TRY(mdx::launch_begin_step(c, pos_cur, vel, force, dt, g));
   for (int s = 0; s < n_steps; ++s) {
-    const bool e = energies != nullptr;
-    // The list is rebuilt on the cadence, and in between whenever an atom
-    // has moved more than r_g/2 since the last build: the opening kernel
-    // raises this step's gate, the build kernels run only if it is raised.
-    // Two gates alternate with the step parity, so the kernel that clears
-    // the next step's gate never touches the one being raised.
-    int* gate_now = c.gate + (c.steps_taken & 1);
-    int* gate_next = c.gate + ((c.steps_taken + 1) & 1);
-    int* pgate_now = gate_now + 2;
-    int* pgate_next = gate_next + 2;
-    const bool cadence = ++c.steps_since_build >= c.rebuild_every;
-    if (cadence) c.steps_since_build = 0;
-    MDX_TRY(mdx::launch_begin_step(c, pos, vel, force, dt, gate_now, gate_next, pgate_now,
-                                   pgate_next, cadence));
+    int* gate_now = g.gate_now;
+    int* pgate_now = g.pgate_now;
     MDX_TRY(timed(x, MDX_TIMING_BUILD, c.stream, [&] {
-      return mdx::launch_build_list(c, pos, gate_now, c.has_pme ? x->ev_fork : nullptr);
+      return mdx::launch_build_list(c, pos_cur, gate_now, c.has_pme ? x->ev_fork : nullptr);
     }));
     // The reciprocal-space potential only needs this step's slot positions
     // and the PME brick slot ranges: the spread and the FFT passes run on the
@@ -796,7 +809,14 @@ int mdx_integrate_step(mdx_ctx* x, float* pos, float* vel, float* force, int32_t
                                     ps ? ps->first : nullptr, ps ? ps->second : nullptr));
     }
     if (c.has_pme) MDX_TRY(hipStreamWaitEvent(c.stream, x->ev_join, 0));
-    MDX_TRY(mdx::launch_finish_step(c, pos, vel, force, dt, e));
+    if (s + 1 < n_steps) {
+      const mdx::StepGates next = gates_of(c.steps_taken + 1);
+      MDX_TRY(mdx::launch_finish_step(c, pos_cur, vel, force, dt, e, &next, pos_other));
+      std::swap(pos_cur, pos_other);
+      g = next;
+    } else {
+      MDX_TRY(mdx::launch_finish_step(c, pos_cur, vel, force, dt, e));
+    }
     if (e) {
       int rows[7] = {mdx::kRowLJ,    mdx::kRowDir, mdx::kRowExcl, mdx::kRowBond,
                      mdx::kRowAngle, mdx::kRowKin, mdx::kRowRec};
@@ -810,6 +830,9 @@ int mdx_integrate_step(mdx_ctx* x, float* pos, float* vel, float* force, int32_t
     }
     c.steps_taken++;
   }
+  if (pos_cur != pos)
+    MDX_TRY(hipMemcpyAsync(pos, pos_cur, sizeof(float) * 3 * (size_t)c.n,
+                           hipMemcpyDeviceToDevice, c.stream));
   return MDX_OK;
 }
 

@@ -176,3 +176,37 @@ def test_kahan_vv_keeps_free_flight_exact():
     ulp_L = float(np.spacing(np.float32(20.0)))
     assert err[mdx.MDX_OPT_KAHAN_VV] <= 4 * ulp_L, err
     assert err[0] > 5 * err[mdx.MDX_OPT_KAHAN_VV], err
+
+
+@pytest.mark.parametrize("name,n_steps", [("water9k", 24), ("lj1k", 30)])
+def test_split_calls_match_one_call_bitwise(name, n_steps):
+    # Inside one call the closing kernel of a step also opens the next one
+    # (positions alternating between the caller's array and a second
+    # buffer); a call of one step opens and closes with separate kernels.
+    # Both must give the same numbers bit for bit, also across list rebuilds.
+    import torch
+    s = synth.config_system(name)
+    dt = 0.5 if name == "water9k" else float(s.dt)
+    out = []
+    for chunks in ([n_steps], [5, 7, 1, n_steps - 13], [1] * n_steps):
+        announce(f"{name} {n_steps} steps in calls of {chunks[:4]}")
+        with gpu_context(s) as (m, ctx, t):
+            m.build_neighbors(ctx, t["pos"])
+            m.compute_nonbonded(ctx, t["pos"], t["force"])
+            if any(s.pme_grid):
+                m.compute_pme(ctx, t["pos"], t["force"])
+            en = torch.zeros((n_steps, m.MDX_N_ENERGY), dtype=torch.float64, device="cuda:0")
+            done = 0
+            for k in chunks:
+                m.integrate_step(ctx, t["pos"], t["vel"], t["force"], k, dt, en[done:done + k])
+                done += k
+            img = torch.zeros((3, s.n_atoms), dtype=torch.int32, device="cuda:0")
+            m.get_images(ctx, img)
+            torch.cuda.synchronize()
+            assert m.get_status(ctx) == 0
+            assert m.get_info(ctx).n_builds >= 2
+            out.append([t["pos"].cpu().numpy(), t["vel"].cpu().numpy(), t["force"].cpu().numpy(),
+                        en.cpu().numpy(), img.cpu().numpy()])
+    for other in out[1:]:
+        for a, b in zip(out[0], other):
+            assert np.array_equal(a, b)
