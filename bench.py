@@ -17,8 +17,8 @@ timed, and the temperature at the start and end of the timed run is
 reported. --equilibrate 0 times the run from the lattice start instead.
 
 Prints one JSON line: ns/day (value), pair-interactions/s, the pair kernel's
-roofline fraction (its launch durations from HIP events on the context's
-stream) and the CPU oracle timed on a bounded sample (rank 0, N = 1).
+roofline fraction (its launch durations from HIP events that its own dispatch
+records on the context's stream) and the CPU oracle timed on a bounded sample (rank 0, N = 1).
 """
 from __future__ import annotations
 
