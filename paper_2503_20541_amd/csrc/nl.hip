@@ -688,9 +688,10 @@ __device__ void search_cluster(const BuildArgs& a, int ic, SearchLds& sl, const 
   // next group of each half are in flight while a group is tested
   auto cand_at = [&](int g) { return (g + t < ncand) ? mycand[g + t] : -1; };
   auto img_at = [&](int g) { return (g + t < ncand) ? (unsigned)myimg[g + t] : 0u; };
-  auto pos_of = [&](int c) {
-    return c >= 0 ? a.xs[(c & ~(kClusterSize - 1)) + b] : make_float4(0.f, 0.f, 0.f, 0.f);
-  };
+  // unconditional loads (slot b of cluster 0 past the end, ignored there):
+  // a load under a branch makes the compiler wait for every load in flight
+  // before the group, including the prefetched one (2 % of the search)
+  auto pos_of = [&](int c) { return a.xs[(c >= 0 ? (c & ~(kClusterSize - 1)) : 0) + b]; };
   int cA = cand_at(0), cB = cand_at(4);
   unsigned iA = img_at(0), iB = img_at(4);
   float4 pA = pos_of(cA), pB = pos_of(cB);
