@@ -17,6 +17,8 @@ ENERGY_NAMES = ("lj", "coul_dir", "coul_excl", "coul_self", "bond", "angle")
 
 
 def alpha(sys) -> float:
+    if getattr(sys, "rf_epsilon", 0.0) > 0:
+        return 0.0   # reaction field: no Ewald split
     if not sys.ewald_delta or sys.ewald_delta <= 0:
         return 0.0
     return ewald.alpha_from_tolerance(float(sys.ewald_delta), float(sys.r_cut))
@@ -43,7 +45,8 @@ def nonbonded_terms(sys, pos=None, pairs=None):
     p64 = pos.astype(np.float64)
     pt = nonbonded.pair_terms(p64, sys.box, inter, sys.atom_type, sys.type_sigma,
                               sys.type_epsilon, sys.charge, a, sys.coulomb_k,
-                              r_cut=float(sys.r_cut), switch_r=float(sys.switch_r))
+                              r_cut=float(sys.r_cut), switch_r=float(sys.switch_r),
+                              rf_epsilon=float(getattr(sys, "rf_epsilon", 0.0)))
     ex = nonbonded.exclusion_correction(p64, sys.box, sys.exclusions, sys.charge, a,
                                         sys.coulomb_k)
     e_self = nonbonded.self_energy(sys.charge, sys.box, a, sys.coulomb_k) if a > 0 else 0.0
@@ -80,7 +83,8 @@ def total_forces_fp64(sys, pos64):
     a = alpha(sys)
     pt = nonbonded.pair_terms(pos64, sys.box, pairs, sys.atom_type, sys.type_sigma,
                               sys.type_epsilon, sys.charge, a, sys.coulomb_k,
-                              r_cut=float(sys.r_cut), switch_r=float(sys.switch_r))
+                              r_cut=float(sys.r_cut), switch_r=float(sys.switch_r),
+                              rf_epsilon=float(getattr(sys, "rf_epsilon", 0.0)))
     ex = nonbonded.exclusion_correction(pos64, sys.box, sys.exclusions, sys.charge, a,
                                         sys.coulomb_k)
     bo = bonded.bonds(pos64, sys.box, sys.bonds, sys.bond_k, sys.bond_r0)

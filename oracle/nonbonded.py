@@ -11,6 +11,12 @@
   image, no cutoff.
 * Self energy, Eq. (12), scaled by k_e, and the neutralising-background term
   -k_e pi Q^2 / (2 V alpha^2) for a net charge Q (zero for neutral systems).
+* Reaction field, Eq. (8), instead of Ewald when eps_s > 0: k_e q_i q_j
+  (1/r + k_RF r^2 - c_RF) for every interacting, non-excluded pair, with the
+  solvent dielectric eps_s in both constants (reading: the printed constants
+  mix eps and eps_s; with eps_s in both, the pair energy vanishes at r_c);
+  eps_s = inf is the conducting limit k_RF = 1/(2 r_c^3), c_RF = 3/(2 r_c).
+  Excluded pairs get no term, and there is no self or reciprocal part.
 
 Forces are the analytic negative gradients. The virial tensor is
 W_ab = sum_pairs d_a F_b, with d = x_j - x_i (minimum image) and F the force
@@ -50,9 +56,18 @@ def _accumulate(n, i, j, fj):
     return F
 
 
+def reaction_field_constants(r_cut, eps_s):
+    """(k_RF, c_RF) of Eq. (8) for cutoff r_cut and solvent dielectric eps_s."""
+    rc = float(r_cut)
+    if math.isinf(eps_s):
+        return 1.0 / (2.0 * rc ** 3), 3.0 / (2.0 * rc)
+    return (eps_s - 1.0) / ((2.0 * eps_s + 1.0) * rc ** 3), 3.0 * eps_s / ((2.0 * eps_s + 1.0) * rc)
+
+
 def pair_terms(pos, box, pairs, atom_type, type_sigma, type_epsilon, charge,
-               alpha, coulomb_k, r_cut=None, switch_r=0.0):
-    """LJ and real-space Ewald over the given interacting pairs.
+               alpha, coulomb_k, r_cut=None, switch_r=0.0, rf_epsilon=0.0):
+    """LJ and real-space Ewald (or, with rf_epsilon > 0, the reaction field)
+    over the given interacting pairs.
 
     Returns dict(E_lj, E_dir, F [3,N], W [3,3]).
     """
@@ -76,7 +91,12 @@ def pair_terms(pos, box, pairs, atom_type, type_sigma, type_epsilon, charge,
         du_lj = du_lj * S + u_lj * dS
         u_lj = u_lj * S
     q = np.asarray(charge, np.float64)
-    if alpha > 0 and coulomb_k != 0:
+    if rf_epsilon and rf_epsilon > 0 and coulomb_k != 0:
+        k_rf, c_rf = reaction_field_constants(r_cut, rf_epsilon)
+        qq = coulomb_k * q[i] * q[j]
+        u_c = qq * (1.0 / r + k_rf * r * r - c_rf)            # Eq. (8)
+        du_c = qq * (-1.0 / r ** 2 + 2.0 * k_rf * r)
+    elif alpha > 0 and coulomb_k != 0:
         qq = coulomb_k * q[i] * q[j]
         u_c = qq * erfc(alpha * r) / r            # Eq. (10), n = 0 term
         du_c = -qq * (erfc(alpha * r) / r ** 2

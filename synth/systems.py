@@ -71,6 +71,7 @@ class System:
     n_steps: int
     rebuild_every: int
     switch_r: np.float32 = np.float32(0.0)   # <= 0: plain truncation
+    rf_epsilon: float = 0.0      # > 0: reaction-field Coulomb with this eps_s (inf allowed)
 
     @property
     def n_atoms(self) -> int:
