@@ -92,6 +92,15 @@ typedef struct mdx_ctx mdx_ctx;
  * each in [4, 1024]); pme_order must be 4. switch_r in (0, r_c) enables
  * the Eq. 6 switch on LJ; <= 0 is plain truncation.
  *
+ * rf_epsilon > 0 selects the reaction field (Sec. II.A.2, Eq. 8) instead:
+ * every interacting, non-excluded pair gets k_e q_i q_j (1/r + k_RF r^2 -
+ * c_RF) with k_RF = (eps_s - 1) / ((2 eps_s + 1) r_c^3) and c_RF = 3 eps_s /
+ * ((2 eps_s + 1) r_c), eps_s = rf_epsilon (the pair energy vanishes at r_c;
+ * INFINITY gives k_RF = 1/(2 r_c^3), c_RF = 3/(2 r_c)); excluded pairs get
+ * nothing and there is no self or reciprocal term. It reports its energy in
+ * MDX_ENERGY_COUL_DIR. ewald_alpha, ewald_delta and pme_grid must then be 0
+ * (MDX_E_INVALID otherwise, as for a negative or NaN rf_epsilon).
+ *
  * Units: coulomb_k = 1/(4 pi eps0); accel converts force/mass to
  * acceleration (a = accel F / m); boltzmann is k_B (kinetic temperature).
  *
@@ -155,6 +164,9 @@ typedef struct mdx_system_desc {
   int32_t nl_capacity;
   int32_t rebuild_every;
   uint32_t options;
+  double rf_epsilon;   /* > 0: Coulomb by the reaction field of Eq. 8 instead of
+                          Ewald, with solvent dielectric eps_s = rf_epsilon
+                          (INFINITY: the conducting limit); see below */
 } mdx_system_desc;
 
 /* Read-only facts about a context (mdx_get_info). */
@@ -220,8 +232,9 @@ int mdx_get_neighbor_pairs(mdx_ctx* ctx, int32_t* pairs_host, int64_t cap, int64
 
 /*
  * Short-range forces at dev pos[3][N] from the current list: LJ + real-space
- * Ewald over listed pairs with r2 < fl(r_c^2) (same float32 expression as
- * the list), the erf exclusion correction (FP64), bonds and angles.
+ * Ewald (or the reaction field, rf_epsilon > 0) over listed pairs with
+ * r2 < fl(r_c^2) (same float32 expression as the list), the erf exclusion
+ * correction (FP64; Ewald only), bonds and angles.
  * force (dev [3][N]) is OVERWRITTEN. energy (dev double[6], slots
  * MDX_ENERGY_LJ..MDX_ENERGY_ANGLE) may be NULL; with energy the variant with
  * FP64 reductions runs. virial (dev double[9], row-major, symmetric, may be

@@ -71,7 +71,9 @@ struct Ctx {
   double alpha = 0.0;
   double coulomb_k = 0.0, accel = 1.0, boltzmann = 1.0;
   double e_self = 0.0;    // Eq. 12 + neutralising term (host FP64, fixed charges)
-  bool has_coulomb = false, has_pme = false, has_switch = false;
+  bool has_coulomb = false, has_pme = false, has_switch = false;   // has_coulomb: Ewald
+  bool rf = false;             // reaction-field Coulomb (Eq. 8) instead of Ewald
+  double k_rf = 0.0, c_rf = 0.0;
   bool half_list = false;      // each pair once, float atomics (MDX_OPT_HALF_LIST)
   int coop_blocks = 0;         // grid of the single-launch list build (0: one kernel per phase)
   int n_types = 0, n_excl = 0, n_bonds = 0, n_angles = 0;

@@ -57,7 +57,13 @@ struct PairParams {
   double alpha_d;             // alpha for the FP64 energy terms
   double coulomb_kd;          // k_e and 2 alpha / sqrt(pi) for the FP64 virial
   double two_a_sqrtpi_d;
+  float two_k_rf;             // reaction field (Eq. 8): 2 k_RF
+  double k_rf_d, c_rf_d;      // k_RF, c_RF for the FP64 energy and virial
 };
+
+// Coulomb term of the pair kernel: none, real-space Ewald (Eq. 10) or the
+// reaction field (Eq. 8).
+constexpr int kCoulNone = 0, kCoulEwald = 1, kCoulRF = 2;
 
 // Energies of a pair on measurement steps: the float32 squared distance (and
 // the switch value) is widened and the pair energy is evaluated in FP64 with
@@ -93,7 +99,7 @@ struct PruneArgs {
   float rp2;              // fl(r_p^2)
 };
 
-template <bool ENERGY, bool COUL, bool SWITCH, bool HALF, bool VIR = false>
+template <bool ENERGY, int COUL, bool SWITCH, bool HALF, bool VIR = false>
 __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
                                               const int* __restrict__ ts,
                                               const uint2* __restrict__ tiles,
@@ -200,7 +206,7 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
           }
         }
         float ec = 0.f;
-        if (COUL) {
+        if (COUL == kCoulEwald) {
           float r = r2 * rinv;
           // exp(-alpha^2 r^2) as 2^(exp_c r^2) on the transcendental unit;
           // the energies on measurement steps are evaluated separately in FP64
@@ -208,6 +214,7 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
           ec = erfc_scaled(pp.alpha * r) * ex;
           f_over_r += qik * pj.w * (ec * rinv + pp.two_a_sqrtpi * ex) * rinv2;
         }
+        if (COUL == kCoulRF) f_over_r += qik * pj.w * (rinv * rinv2 - pp.two_k_rf);
         gx = f_over_r * dx;
         gy = f_over_r * dy;
         gz = f_over_r * dz;
@@ -221,9 +228,13 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
           double u = r6d * (c.x * r6d - c.y);
           if (SWITCH) u *= (double)S;
           e_lj += u;
-          if (COUL) {
+          if (COUL == kCoulEwald) {
             double rd = sqrt(r2d);
             e_c += (double)pi.w * (double)pj.w * erfc(pp.alpha_d * rd) / rd;
+          }
+          if (COUL == kCoulRF) {
+            double rd = sqrt(r2d);
+            e_c += (double)pi.w * (double)pj.w * (1.0 / rd + pp.k_rf_d * r2d - pp.c_rf_d);
           }
           if (VIR) {
             // d (x) F_j with F_j = fr d, fr = -(dU/dr)/r in FP64 from the
@@ -231,11 +242,14 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
             const double rd = sqrt(r2d);
             double fr = (12.0 * c.x * r6d - 6.0 * c.y) * r6d / r2d;
             if (SWITCH) fr = fr * (double)S - r6d * (c.x * r6d - c.y) * (double)dS / rd;
-            if (COUL) {
+            if (COUL == kCoulEwald) {
               const double ar = pp.alpha_d * rd;
               fr += pp.coulomb_kd * (double)pi.w * (double)pj.w *
                     (erfc(ar) / rd + pp.two_a_sqrtpi_d * exp(-ar * ar)) / r2d;
             }
+            if (COUL == kCoulRF)
+              fr += pp.coulomb_kd * (double)pi.w * (double)pj.w *
+                    (1.0 / (r2d * rd) - 2.0 * pp.k_rf_d);
             vir_add_dd(wv, fr, (double)dx, (double)dy, (double)dz);
           }
         }
@@ -417,6 +431,9 @@ hipError_t launch_nonbonded(Ctx& c, bool energy, const int* gate_now, const int*
   pp.r_s = c.switch_r;
   pp.r_c = c.r_cut;
   pp.inv_sw = c.has_switch ? 1.0f / (c.r_cut - c.switch_r) : 0.f;
+  pp.two_k_rf = (float)(2.0 * c.k_rf);
+  pp.k_rf_d = c.k_rf;
+  pp.c_rf_d = c.c_rf;
   const int nb = (c.max_clusters + 3) / 4;
   c.nb_blocks = nb;
   const size_t lds = sizeof(float4) * (size_t)c.n_types * c.n_types;
@@ -441,23 +458,33 @@ hipError_t launch_nonbonded(Ctx& c, bool energy, const int* gate_now, const int*
     MDX_PAIR(true, C, S, true, true);   \
   else                                  \
     MDX_PAIR(true, C, S, false, true)
-  bool C = c.has_coulomb, S = c.has_switch;
-  if (virial) {
-    if (C && S) { MDX_PAIR_V(true, true); }
-    else if (C) { MDX_PAIR_V(true, false); }
-    else if (S) { MDX_PAIR_V(false, true); }
-    else { MDX_PAIR_V(false, false); }
-  } else if (energy) {
-    if (C && S) { MDX_PAIR_H(true, true, true); }
-    else if (C) { MDX_PAIR_H(true, true, false); }
-    else if (S) { MDX_PAIR_H(true, false, true); }
-    else { MDX_PAIR_H(true, false, false); }
-  } else {
-    if (C && S) { MDX_PAIR_H(false, true, true); }
-    else if (C) { MDX_PAIR_H(false, true, false); }
-    else if (S) { MDX_PAIR_H(false, false, true); }
-    else { MDX_PAIR_H(false, false, false); }
+#define MDX_PAIR_VE(E, C, S) MDX_PAIR_V(C, S)
+#define MDX_PAIR_S(M, E, C) \
+  if (S) {                  \
+    M(E, C, true);          \
+  } else {                  \
+    M(E, C, false);         \
   }
+#define MDX_PAIR_C(M, E)                \
+  if (C == kCoulEwald) {                \
+    MDX_PAIR_S(M, E, kCoulEwald)        \
+  } else if (C == kCoulRF) {            \
+    MDX_PAIR_S(M, E, kCoulRF)           \
+  } else {                              \
+    MDX_PAIR_S(M, E, kCoulNone)         \
+  }
+  const int C = c.has_coulomb ? kCoulEwald : (c.rf ? kCoulRF : kCoulNone);
+  const bool S = c.has_switch;
+  if (virial) {
+    MDX_PAIR_C(MDX_PAIR_VE, true)
+  } else if (energy) {
+    MDX_PAIR_C(MDX_PAIR_H, true)
+  } else {
+    MDX_PAIR_C(MDX_PAIR_H, false)
+  }
+#undef MDX_PAIR_C
+#undef MDX_PAIR_S
+#undef MDX_PAIR_VE
 #undef MDX_PAIR_V
 #undef MDX_PAIR_H
 #undef MDX_PAIR

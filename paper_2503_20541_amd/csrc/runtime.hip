@@ -250,6 +250,20 @@ int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
   for (int i = 0; i < n; ++i) any_q |= d->charge[i] != 0.f;
   c.has_coulomb = c.alpha > 0.0 && d->coulomb_k != 0.0 && any_q;
   const bool want_pme = d->pme_grid[0] > 0 || d->pme_grid[1] > 0 || d->pme_grid[2] > 0;
+  // reaction field (Eq. 8, with eps_s in both constants): no Ewald parts
+  if (!(d->rf_epsilon >= 0.0)) return MDX_E_INVALID;
+  if (d->rf_epsilon > 0.0) {
+    if (d->ewald_alpha > 0.0 || d->ewald_delta > 0.0 || want_pme) return MDX_E_INVALID;
+    const double rc = (double)d->r_cut, es = d->rf_epsilon;
+    if (std::isinf(es)) {
+      c.k_rf = 1.0 / (2.0 * rc * rc * rc);
+      c.c_rf = 3.0 / (2.0 * rc);
+    } else {
+      c.k_rf = (es - 1.0) / ((2.0 * es + 1.0) * rc * rc * rc);
+      c.c_rf = 3.0 * es / ((2.0 * es + 1.0) * rc);
+    }
+    c.rf = d->coulomb_k != 0.0 && any_q;
+  }
   if (want_pme) {
     if (d->pme_order != 4 && d->pme_order != 0) return MDX_E_UNSUPPORTED;
     for (int k = 0; k < 3; ++k)
@@ -293,7 +307,7 @@ int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
   std::vector<int> ty(n);
   double q2 = 0.0, qsum = 0.0;
   for (int i = 0; i < n; ++i) {
-    q[i] = c.has_coulomb ? d->charge[i] : 0.f;
+    q[i] = c.has_coulomb || c.rf ? d->charge[i] : 0.f;
     ty[i] = d->atom_type[i];
     am[i] = (float)(c.accel / (double)d->mass[i]);
     ms[i] = d->mass[i];

@@ -83,6 +83,7 @@ class SystemDesc(ctypes.Structure):
         ("boltzmann", ctypes.c_double),
         ("cell_divisions", ctypes.c_int32), ("nl_capacity", ctypes.c_int32),
         ("rebuild_every", ctypes.c_int32), ("options", ctypes.c_uint32),
+        ("rf_epsilon", ctypes.c_double),
     ]
 
 
@@ -152,7 +153,7 @@ def make_desc(n_atoms, box, charge, mass, atom_type, type_sigma, type_epsilon,
               angle_k=None, angle_theta0=None, r_cut=1.0, r_ghost=0.0, switch_r=0.0,
               ewald_delta=0.0, ewald_alpha=0.0, pme_grid=(0, 0, 0), pme_order=4,
               coulomb_k=1.0, accel=1.0, boltzmann=1.0, cell_divisions=0, nl_capacity=0,
-              rebuild_every=10, options=0):
+              rebuild_every=10, options=0, rf_epsilon=0.0):
     """Fills an mdx_system_desc from host arrays. Returns (desc, keepalive)."""
     keep = []
 
@@ -206,6 +207,7 @@ def make_desc(n_atoms, box, charge, mass, atom_type, type_sigma, type_epsilon,
     d.nl_capacity = int(nl_capacity)
     d.rebuild_every = int(rebuild_every)
     d.options = int(options)
+    d.rf_epsilon = float(rf_epsilon)
     return d, keep
 
 
@@ -219,7 +221,8 @@ def desc_from_system(sys, **overrides):
               r_ghost=float(sys.r_ghost), switch_r=float(sys.switch_r),
               ewald_delta=float(sys.ewald_delta), pme_grid=tuple(sys.pme_grid),
               coulomb_k=float(sys.coulomb_k), accel=float(sys.accel),
-              boltzmann=float(sys.boltzmann), rebuild_every=int(sys.rebuild_every))
+              boltzmann=float(sys.boltzmann), rebuild_every=int(sys.rebuild_every),
+              rf_epsilon=float(getattr(sys, "rf_epsilon", 0.0)))
     kw.update(overrides)
     return make_desc(**kw)
 
