@@ -57,6 +57,10 @@ def parse():
                    help="steps of velocity-rescaled equilibration to 300 K before the warm-up "
                         "(0: start the timed run from the lattice start, which heats up)")
     p.add_argument("--cpu-only", action="store_true", help=argparse.SUPPRESS)
+    p.add_argument("--sweep", action="store_true",
+                   help="instead of the benchmark: time per step against system size for "
+                        "water boxes with reaction-field and with PME electrostatics (one "
+                        "JSON line per box and method)")
     p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                    help="only copy a MIB-sized float32 buffer 10 times (calibrates the "
                         "FETCH_SIZE / WRITE_SIZE counters against known traffic) and exit")
@@ -123,10 +127,70 @@ def copy_probe(mib):
     print(json.dumps({"copy_probe_MiB": mib, "launches": 10}), flush=True)
 
 
+# (molecules, PME grid) of the size sweep: water at 0.997 g/cm^3, box edge
+# (29.91 A^3 per molecule)^(1/3), grid spacing about 1 A
+SWEEP_BOXES = ((1000, 32), (4000, 48), (8000, 64), (27000, 96), (32000, 100), (64000, 128))
+
+
+def sweep(args):
+    """Time per step against N for the same water model with the reaction
+    field (Eq. 8, eps_s = 78.5) and with SPME (the shape of the paper's
+    RFA / PME scaling figure), r_c = 9 A, r_g = 2.25 A, dt = 1 fs, list
+    rebuilt every 10 steps; each box is equilibrated to 300 K for 1000
+    untimed steps first."""
+    import torch
+    import synth
+    import paper_2503_20541_amd as mdx
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    for n_mol, K in SWEEP_BOXES:
+        L = (n_mol * 29.91) ** (1.0 / 3.0)
+        base = synth.water_box(n_mol, L, (K, K, K), 9.0, None, 5e-4, 11, n_steps=1000,
+                               name=f"water{3 * n_mol}")
+        for method in ("rf", "pme"):
+            s = base.copy()
+            if method == "rf":
+                s.rf_epsilon, s.ewald_delta, s.pme_grid = 78.5, 0.0, (0, 0, 0)
+            desc, keep = mdx.desc_from_system(s)
+            ctx = mdx.create(desc, stream.cuda_stream)
+            pos = torch.from_numpy(s.pos.copy()).to(dev)
+            vel = torch.from_numpy(s.vel.copy()).to(dev)
+            force = torch.zeros_like(pos)
+            mdx.build_neighbors(ctx, pos)
+            mdx.compute_nonbonded(ctx, pos, force)
+            if method == "pme":
+                mdx.compute_pme(ctx, pos, force)
+            for _ in range(10):
+                mdx.integrate_step(ctx, pos, vel, force, 100, s.dt)
+                vel.mul_((300.0 / temperature(s, vel)) ** 0.5)
+            mdx.integrate_step(ctx, pos, vel, force, args.warmup, s.dt)
+            b0 = mdx.get_info(ctx).n_builds
+            start = torch.cuda.Event(enable_timing=True)
+            stop = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            start.record(stream)
+            mdx.integrate_step(ctx, pos, vel, force, args.steps, s.dt)
+            stop.record(stream)
+            torch.cuda.synchronize()
+            ms = start.elapsed_time(stop) / args.steps
+            builds = mdx.get_info(ctx).n_builds - b0
+            flags = mdx.get_status(ctx)
+            mdx.destroy(ctx)
+            print(json.dumps({"sweep": "time_per_step_vs_n", "coulomb": method,
+                              "n_atoms": s.n_atoms, "box_A": round(L, 2),
+                              "pme_grid": K if method == "pme" else None,
+                              "steps": args.steps, "ms_per_step": round(ms, 5),
+                              "ns_per_day": round(0.0864 * s.dt * 1e3 / ms, 3),
+                              "list_builds": builds, "status_flags": flags}), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_probe > 0:
         copy_probe(args.copy_probe)
+        return
+    if args.sweep:
+        sweep(args)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
