@@ -296,6 +296,24 @@ int mdx_get_status(mdx_ctx* ctx, uint32_t* flags);
  */
 int mdx_get_images(mdx_ctx* ctx, int32_t* img);
 
+/*
+ * Langevin dynamics for the following mdx_integrate_step calls (the paper's
+ * stochastic integrator, Sec. II.D; the splitting read as BAOAB): each step
+ * opens with v += (dt/2) a, x += (dt/2) v, v = c1 v + c2 sqrt(kT accel / m) xi,
+ * x += (dt/2) v (c1 = exp(-gamma dt), c2 = sqrt(1 - c1^2)) and closes with
+ * v += (dt/2) a as before. xi: three standard normals per atom and step,
+ * Box-Muller of Philox4x64-10 (Salmon et al., SC'11) with counter (atom,
+ * step, 0, 0) and key (seed low 64 bits, 0); step counts every step the
+ * context has taken, so a run is reproducible from (seed, state, step) and
+ * independent of how it is split into calls. Uniforms are the top 24 bits
+ * + 1 over 2^24, normals sqrt(-2 ln u1) (cos, sin)(2 pi u2) and
+ * sqrt(-2 ln u3) cos(2 pi u4), in float32. kT in energy units (k_B T),
+ * gamma in 1/time; gamma = 0 returns to velocity Verlet. MDX_E_INVALID for
+ * kT < 0, gamma < 0 or non-finite values; MDX_E_UNSUPPORTED with
+ * MDX_OPT_KAHAN_VV.
+ */
+int mdx_set_langevin(mdx_ctx* ctx, double kT, double gamma, uint64_t seed);
+
 /* Fills *info (host). Synchronising once a list exists: the list is copied
  * to the host to count its entries. */
 int mdx_get_info(mdx_ctx* ctx, mdx_info* info);

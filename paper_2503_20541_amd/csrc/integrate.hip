@@ -33,6 +33,9 @@ __device__ __forceinline__ float wrap_box(float x, float L, int& wraps) {
 // and written to pos_out (the same array for the stand-alone kernel).
 struct OpenStep {
   const float* pos_in;
+  const float* lv_sig;   // Langevin: sqrt(kT accel / m) per atom (null: velocity Verlet)
+  float lv_c1, lv_c2;
+  unsigned long long lv_seed, lv_step;
   float* pos_out;
   const float* x_build;
   const float4* xp;
@@ -60,12 +63,66 @@ __device__ __forceinline__ void open_step_flags(const OpenStep& o) {
   if (o.force_rebuild) *o.gate_now = 1;
 }
 
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 64 x 64 -> 128-bit products with the Weyl-sequence key schedule.
+__device__ __forceinline__ void philox4x64_10(unsigned long long c[4], unsigned long long k0,
+                                              unsigned long long k1) {
+  const unsigned long long M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const unsigned long long W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const unsigned long long hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
+    const unsigned long long hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
+    const unsigned long long n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+
+// Three standard normals for atom a at a step: Box-Muller of the block's
+// four uniforms (top 24 bits + 1) / 2^24 in (0, 1].
+__device__ __forceinline__ void langevin_normals(unsigned long long seed, unsigned long long step,
+                                                 int a, float z[3]) {
+  unsigned long long c[4] = {(unsigned long long)a, step, 0ull, 0ull};
+  philox4x64_10(c, seed, 0ull);
+  float u[4];
+  for (int k = 0; k < 4; ++k) u[k] = (float)((c[k] >> 40) + 1ull) * 5.9604644775390625e-8f;
+  const float r1 = sqrtf(-2.0f * logf(u[0])), r2 = sqrtf(-2.0f * logf(u[2]));
+  const float t1 = 6.28318530717958648f * u[1], t2 = 6.28318530717958648f * u[3];
+  z[0] = r1 * cosf(t1);
+  z[1] = r1 * sinf(t1);
+  z[2] = r2 * cosf(t2);
+}
+
 __device__ __forceinline__ void open_step_atom(const OpenStep& o, const float* __restrict__ force,
                                                float* __restrict__ vel, int a, int s) {
   const int n = o.n;
   const CellGrid& cg = o.cg;
   const float h = o.half_dt * o.acc_over_m[a];
   float x[3];
+  if (o.lv_sig) {
+    // Langevin, BAOAB: kick, half drift, Ornstein-Uhlenbeck step, half drift
+    float z[3];
+    langevin_normals(o.lv_seed, o.lv_step, a, z);
+    const float sg = o.lv_sig[a];
+    const float hdt = 0.5f * o.dt;
+    for (int d = 0; d < 3; ++d) {
+      const size_t k = (size_t)d * n + a;
+      int wraps;
+      const float v1 = vel[k] + h * force[k];
+      const float xh = o.pos_in[k] + hdt * v1;
+      const float v2 = o.lv_c1 * v1 + o.lv_c2 * sg * z[d];
+      vel[k] = v2;
+      x[d] = wrap_box(xh + hdt * v2, cg.L[d], wraps);
+      o.pos_out[k] = x[d];
+      if (wraps) o.img[k] += wraps;
+    }
+  } else
   for (int d = 0; d < 3; ++d) {
     const size_t k = (size_t)d * n + a;
     int wraps;
@@ -226,6 +283,11 @@ OpenStep make_open(const Ctx& c, const float* pos_in, float* pos_out, float dt,
   o.dt = dt;
   o.half_skin2 = h * h;
   o.prune_move2 = c.prune_move2;
+  o.lv_sig = c.langevin ? c.lv_sig : nullptr;
+  o.lv_c1 = (float)std::exp(-c.lv_gamma * (double)dt);
+  o.lv_c2 = (float)std::sqrt(std::max(0.0, 1.0 - std::exp(-2.0 * c.lv_gamma * (double)dt)));
+  o.lv_seed = c.lv_seed;
+  o.lv_step = (unsigned long long)g.step;
   return o;
 }
 }  // namespace
@@ -240,7 +302,7 @@ hipError_t launch_begin_step(Ctx& c, float* pos, float* vel, const float* force,
 hipError_t launch_finish_step(Ctx& c, const float* pos, float* vel, float* force, float dt,
                               bool energy, const StepGates* next, float* pos_next) {
   if (next && (!pos_next || pos_next == pos)) return hipErrorInvalidValue;
-  const StepGates none{c.gate, c.gate, c.gate, c.gate, false};   // not used when !next
+  const StepGates none{c.gate, c.gate, c.gate, c.gate, false, 0};   // not used when !next
   const OpenStep o = make_open(c, pos, pos_next, dt, next ? *next : none);
   const int open = next ? 1 : 0;
   const int nb = (c.max_slots * kFinishLanes + 255) / 256;

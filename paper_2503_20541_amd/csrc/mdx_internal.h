@@ -92,6 +92,12 @@ struct Ctx {
   double2* lj_d = nullptr;     // [T*T] (c12, c6) in FP64 for energies
   float* hdt_scale = nullptr;  // accel / m_i  (times dt/2 at use)
   float* pos_alt = nullptr;    // [3][n] second position buffer of mdx_integrate_step
+  // Langevin (BAOAB) opening half, mdx_set_langevin
+  bool langevin = false;
+  double lv_kT = 0.0, lv_gamma = 0.0;
+  unsigned long long lv_seed = 0;
+  float* lv_sig = nullptr;     // [n] sqrt(kT accel / m_i)
+  std::vector<float> mass_h;   // [n] masses (host copy)
   float* mass = nullptr;
   // exclusions per atom (CSR, caller order, both directions)
   int* ex_start = nullptr;
@@ -215,6 +221,7 @@ struct StepGates {
   int* pgate_now;
   int* pgate_next;
   bool cadence;
+  long long step;   // the step's index among all the context's steps (Langevin noise)
 };
 // Opening half of a step: positions read from and written to pos (in place).
 hipError_t launch_begin_step(Ctx& c, float* pos, float* vel, const float* force, float dt,

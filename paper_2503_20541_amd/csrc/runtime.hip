@@ -340,6 +340,7 @@ int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
   if ((rc = dev_upload(x, &c.lj_d, ljd)) != MDX_OK) return rc;
   if ((rc = dev_upload(x, &c.hdt_scale, am)) != MDX_OK) return rc;
   if ((rc = dev_upload(x, &c.mass, ms)) != MDX_OK) return rc;
+  c.mass_h = ms;
 
   // ---- topology ----
   std::set<std::pair<int, int>> ex;
@@ -782,6 +783,7 @@ int mdx_integrate_step(mdx_ctx* x, float* pos, float* vel, float* force, int32_t
     g.pgate_next = g.gate_next + 2;
     g.cadence = ++c.steps_since_build >= c.rebuild_every;
     if (g.cadence) c.steps_since_build = 0;
+    g.step = (long long)step;
     return g;
   };
   // The first step opens with its own kernel; every later one is opened by
@@ -859,6 +861,27 @@ int mdx_get_status(mdx_ctx* x, uint32_t* flags) {
   MDX_TRY(hipMemsetAsync(c.flags, 0, sizeof(unsigned), c.stream));
   MDX_TRY(hipStreamSynchronize(c.stream));
   *flags = f;
+  return MDX_OK;
+}
+
+int mdx_set_langevin(mdx_ctx* x, double kT, double gamma, uint64_t seed) {
+  if (check_ctx(x) || !(kT >= 0.0) || !(gamma >= 0.0) || !std::isfinite(kT) ||
+      !std::isfinite(gamma))
+    return MDX_E_INVALID;
+  Ctx& c = x->c;
+  if (c.xc && gamma > 0.0) return MDX_E_UNSUPPORTED;
+  c.langevin = gamma > 0.0;
+  c.lv_kT = kT;
+  c.lv_gamma = gamma;
+  c.lv_seed = seed;
+  if (!c.langevin) return MDX_OK;
+  std::vector<float> sig(c.n);
+  for (int i = 0; i < c.n; ++i) sig[i] = (float)std::sqrt(kT * c.accel / (double)c.mass_h[i]);
+  if (!c.lv_sig) {
+    int rc = dev_alloc(x, &c.lv_sig, (size_t)c.n);
+    if (rc != MDX_OK) return rc;
+  }
+  MDX_TRY(hipMemcpy(c.lv_sig, sig.data(), sizeof(float) * c.n, hipMemcpyHostToDevice));
   return MDX_OK;
 }
 
