@@ -61,6 +61,10 @@ def parse():
                    help="instead of the benchmark: time per step against system size for "
                         "water boxes with reaction-field and with PME electrostatics (one "
                         "JSON line per box and method)")
+    p.add_argument("--ewald-direct", action="store_true",
+                   help="instead of the benchmark: time the direct reciprocal Ewald sum "
+                        "(converged to 1e-8 in the Gaussian factor) against SPME for the "
+                        "9,000- and 96,000-atom water boxes (one JSON line each)")
     p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                    help="only copy a MIB-sized float32 buffer 10 times (calibrates the "
                         "FETCH_SIZE / WRITE_SIZE counters against known traffic) and exit")
@@ -184,10 +188,65 @@ def sweep(args):
                               "list_builds": builds, "status_flags": flags}), flush=True)
 
 
+def ewald_direct_vs_pme():
+    """Reciprocal energy and time of one evaluation by the direct sum and by
+    SPME at the configured grid, same alpha: the direct sum's n_max makes the
+    Gaussian factor exp(-pi^2 m^2/alpha^2) fall below 1e-8 at the cube face."""
+    import math
+    import torch
+    import synth
+    import paper_2503_20541_amd as mdx
+    from oracle import forcefield
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    for name in ("water9k", "water96k"):
+        s = synth.config_system(name)
+        a = forcefield.alpha(s)
+        L = float(max(s.box))
+        n_max = int(math.ceil(L * a * math.sqrt(math.log(1e8)) / math.pi))
+        desc, keep = mdx.desc_from_system(s)
+        ctx = mdx.create(desc, stream.cuda_stream)
+        pos = torch.from_numpy(s.pos.copy()).to(dev)
+        mdx.build_neighbors(ctx, pos)
+        out = {}
+        for method in ("pme", "direct"):
+            e = torch.zeros(1, dtype=torch.float64, device=dev)
+            f = torch.zeros_like(pos)
+            call = (lambda: mdx.compute_pme(ctx, pos, f, e)) if method == "pme" else \
+                (lambda: mdx.compute_ewald_direct(ctx, pos, f, e, n_max))
+            call()
+            f.zero_()                 # the forces accumulate: count the timed calls only
+            torch.cuda.synchronize()
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            reps = 20 if method == "pme" else 3
+            t0.record(stream)
+            for _ in range(reps):
+                call()
+            t1.record(stream)
+            torch.cuda.synchronize()
+            out[method] = (t0.elapsed_time(t1) / reps, float(e.cpu()[0]), f.cpu().numpy() / reps)
+        mdx.destroy(ctx)
+        import numpy as np
+        fd, fp = out["direct"][2], out["pme"][2]
+        print(json.dumps({"ewald_direct_vs_pme": name, "n_atoms": s.n_atoms,
+                          "pme_grid": list(s.pme_grid), "direct_n_max": n_max,
+                          "direct_vectors": ((2 * n_max + 1) ** 3 - 1) // 2,
+                          "ms_pme": round(out["pme"][0], 4), "ms_direct": round(out["direct"][0], 3),
+                          "E_rec_pme": out["pme"][1], "E_rec_direct": out["direct"][1],
+                          "pme_energy_rel_error": abs(out["pme"][1] / out["direct"][1] - 1.0),
+                          "pme_force_rel_rms_error": float(np.sqrt(((fp - fd) ** 2).sum()
+                                                                   / (fd ** 2).sum()))}),
+              flush=True)
+
+
 def main():
     args = parse()
     if args.copy_probe > 0:
         copy_probe(args.copy_probe)
+        return
+    if args.ewald_direct:
+        ewald_direct_vs_pme()
         return
     if args.sweep:
         sweep(args)

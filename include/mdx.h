@@ -264,6 +264,21 @@ int mdx_compute_pme(mdx_ctx* ctx, const float* pos, float* force, double* energy
                     double* virial);
 
 /*
+ * The reciprocal Ewald sum evaluated directly (Sec. II.A.2, Eqs. 9-12 with
+ * Eq. 11 in its standard form, tin-foil boundary): over m = (n_x/L_x,
+ * n_y/L_y, n_z/L_z), |n_d| <= n_max, m != 0, E_rec = k_e/(2 pi V) sum_m
+ * exp(-pi^2 m^2/alpha^2)/m^2 |S(m)|^2 with S(m) = sum_j q_j exp(2 pi i m.r_j),
+ * and its forces; O(N n_max^3), all sums in FP64: a high-accuracy reference
+ * for mdx_compute_pme. pos dev [3][N]; force (dev [3][N]) is ACCUMULATED
+ * into; energy (dev double[1], may be NULL) is OVERWRITTEN with E_rec.
+ * Scratch (16 (3 (2 n_max + 1) N + (2 n_max + 1)^3) bytes) is allocated on
+ * the first call with a larger n_max and kept. MDX_E_INVALID without Ewald
+ * electrostatics (ewald_delta or ewald_alpha), or for n_max outside [1, 64].
+ */
+int mdx_compute_ewald_direct(mdx_ctx* ctx, const float* pos, float* force, double* energy,
+                             int32_t n_max);
+
+/*
  * Velocity Verlet (Sec. II.D.1) for n_steps >= 1 with step dt:
  *   v += (dt/2) accel F/m;  x += dt v (wrapped into [0, L));  F = F(x);
  *   v += (dt/2) accel F/m.

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmdx.so")
-SOURCES = ["runtime.hip", "nl.hip", "nonbonded.hip", "pme.hip", "integrate.hip"]
+SOURCES = ["runtime.hip", "nl.hip", "nonbonded.hip", "pme.hip", "integrate.hip", "ewald_direct.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

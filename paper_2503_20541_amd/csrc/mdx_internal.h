@@ -98,6 +98,12 @@ struct Ctx {
   unsigned long long lv_seed = 0;
   float* lv_sig = nullptr;     // [n] sqrt(kT accel / m_i)
   std::vector<float> mass_h;   // [n] masses (host copy)
+  // direct reciprocal Ewald sum (mdx_compute_ewald_direct): scratch for the
+  // largest n_max asked for so far
+  int ew_nmax = 0;
+  double2* ew_tab = nullptr;   // [3][2 n_max + 1][n] phase factors
+  double2* ew_S = nullptr;     // [K] structure factors of the half-space vectors
+  double* ew_eterm = nullptr;  // [K] their energy terms
   float* mass = nullptr;
   // exclusions per atom (CSR, caller order, both directions)
   int* ex_start = nullptr;
@@ -238,6 +244,10 @@ hipError_t launch_finish_step(Ctx& c, const float* pos, float* vel, float* force
 hipError_t launch_pme_spread(Ctx& c, hipStream_t s, hipEvent_t done);
 // virial: the z pass also writes the reciprocal-space virial rows (kRowVir).
 hipError_t launch_pme_fft(Ctx& c, hipStream_t s, hipEvent_t done, bool virial = false);
+// Direct reciprocal Ewald sum over |n_d| <= nmax into force (accumulated);
+// energy (dev double[1], may be null) overwritten. Scratch sized for nmax.
+hipError_t launch_ewald_direct(Ctx& c, const float* pos, float* force, double* energy, int nmax,
+                               double2* tab, double2* S, double* eterm);
 
 // Device helpers shared by kernels -------------------------------------------
 

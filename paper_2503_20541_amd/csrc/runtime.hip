@@ -864,6 +864,30 @@ int mdx_get_status(mdx_ctx* x, uint32_t* flags) {
   return MDX_OK;
 }
 
+int mdx_compute_ewald_direct(mdx_ctx* x, const float* pos, float* force, double* energy,
+                             int32_t n_max) {
+  if (check_ctx(x) || !pos || !force || n_max < 1 || n_max > 64) return MDX_E_INVALID;
+  Ctx& c = x->c;
+  if (!c.has_coulomb) return MDX_E_INVALID;
+  if (n_max > c.ew_nmax) {
+    const size_t w = 2 * (size_t)n_max + 1, K = (w * w * w - 1) / 2;
+    dev_free(x, c.ew_tab);
+    dev_free(x, c.ew_S);
+    dev_free(x, c.ew_eterm);
+    c.ew_tab = nullptr;
+    c.ew_S = nullptr;
+    c.ew_eterm = nullptr;
+    c.ew_nmax = 0;
+    int rc;
+    if ((rc = dev_alloc(x, &c.ew_tab, 3 * w * (size_t)c.n)) != MDX_OK) return rc;
+    if ((rc = dev_alloc(x, &c.ew_S, K)) != MDX_OK) return rc;
+    if ((rc = dev_alloc(x, &c.ew_eterm, K)) != MDX_OK) return rc;
+    c.ew_nmax = n_max;
+  }
+  MDX_TRY(mdx::launch_ewald_direct(c, pos, force, energy, n_max, c.ew_tab, c.ew_S, c.ew_eterm));
+  return MDX_OK;
+}
+
 int mdx_set_langevin(mdx_ctx* x, double kT, double gamma, uint64_t seed) {
   if (check_ctx(x) || !(kT >= 0.0) || !(gamma >= 0.0) || !std::isfinite(kT) ||
       !std::isfinite(gamma))
