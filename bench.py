@@ -132,16 +132,21 @@ def copy_probe(mib):
 
 
 # (molecules, PME grid) of the size sweep: water at 0.997 g/cm^3, box edge
-# (29.91 A^3 per molecule)^(1/3), grid spacing about 1 A
-SWEEP_BOXES = ((1000, 32), (4000, 48), (8000, 64), (27000, 96), (32000, 100), (64000, 128))
+# (29.91 A^3 per molecule)^(1/3), grid spacing about 1 A (no PME grid for the
+# largest box, which runs the reaction-field protocols only)
+SWEEP_BOXES = ((1000, 32), (4000, 48), (8000, 64), (27000, 96), (32000, 100), (64000, 128),
+               (100000, 0))
 
 
 def sweep(args):
-    """Time per step against N for the same water model with the reaction
-    field (Eq. 8, eps_s = 78.5) and with SPME (the shape of the paper's
-    RFA / PME scaling figure), r_c = 9 A, r_g = 2.25 A, dt = 1 fs, list
-    rebuilt every 10 steps; each box is equilibrated to 300 K for 1000
-    untimed steps first."""
+    """Time per step against N for the same water model under three
+    protocols: velocity Verlet with the reaction field (Eq. 8, eps_s = 78.5)
+    and with SPME (the shape of the paper's RFA / PME scaling figure), both at
+    r_c = 9 A, r_g = 2.25 A, dt = 1 fs; and the paper's own benchmark protocol
+    (reaction field, Langevin dynamics at 300 K with gamma = 0.1 / fs,
+    dt = 0.5 fs, r_c = 10 A, r_g = 2.5 A). Lists are rebuilt every 10 steps
+    (and whenever an atom has moved more than r_g / 2); each run is brought to
+    300 K for 1000 untimed steps first."""
     import torch
     import synth
     import paper_2503_20541_amd as mdx
@@ -149,12 +154,18 @@ def sweep(args):
     stream = torch.cuda.current_stream(dev)
     for n_mol, K in SWEEP_BOXES:
         L = (n_mol * 29.91) ** (1.0 / 3.0)
-        base = synth.water_box(n_mol, L, (K, K, K), 9.0, None, 5e-4, 11, n_steps=1000,
-                               name=f"water{3 * n_mol}")
-        for method in ("rf", "pme"):
+        base = synth.water_box(n_mol, L, (max(K, 32),) * 3, 9.0, None, 5e-4, 11,
+                               n_steps=1000, name=f"water{3 * n_mol}")
+        for method in ("rf", "pme", "rf_langevin_paper"):
+            if method == "pme" and K == 0:
+                continue
             s = base.copy()
-            if method == "rf":
+            dt, gamma = float(s.dt), 0.0
+            if method != "pme":
                 s.rf_epsilon, s.ewald_delta, s.pme_grid = 78.5, 0.0, (0, 0, 0)
+            if method == "rf_langevin_paper":
+                s.r_cut, s.r_ghost = s.r_cut.__class__(10.0), s.r_ghost.__class__(2.5)
+                dt, gamma = 0.5, 0.1
             desc, keep = mdx.desc_from_system(s)
             ctx = mdx.create(desc, stream.cuda_stream)
             pos = torch.from_numpy(s.pos.copy()).to(dev)
@@ -165,27 +176,32 @@ def sweep(args):
             if method == "pme":
                 mdx.compute_pme(ctx, pos, force)
             for _ in range(10):
-                mdx.integrate_step(ctx, pos, vel, force, 100, s.dt)
+                mdx.integrate_step(ctx, pos, vel, force, 100, dt)
                 vel.mul_((300.0 / temperature(s, vel)) ** 0.5)
-            mdx.integrate_step(ctx, pos, vel, force, args.warmup, s.dt)
+            if gamma > 0:
+                mdx.set_langevin(ctx, float(s.boltzmann) * 300.0, gamma, 2025)
+            mdx.integrate_step(ctx, pos, vel, force, args.warmup, dt)
             b0 = mdx.get_info(ctx).n_builds
             start = torch.cuda.Event(enable_timing=True)
             stop = torch.cuda.Event(enable_timing=True)
             torch.cuda.synchronize()
             start.record(stream)
-            mdx.integrate_step(ctx, pos, vel, force, args.steps, s.dt)
+            mdx.integrate_step(ctx, pos, vel, force, args.steps, dt)
             stop.record(stream)
             torch.cuda.synchronize()
             ms = start.elapsed_time(stop) / args.steps
             builds = mdx.get_info(ctx).n_builds - b0
             flags = mdx.get_status(ctx)
+            t_end = temperature(s, vel)
             mdx.destroy(ctx)
-            print(json.dumps({"sweep": "time_per_step_vs_n", "coulomb": method,
+            print(json.dumps({"sweep": "time_per_step_vs_n", "protocol": method,
                               "n_atoms": s.n_atoms, "box_A": round(L, 2),
                               "pme_grid": K if method == "pme" else None,
+                              "r_cut_A": float(s.r_cut), "dt_fs": dt, "langevin_gamma": gamma,
                               "steps": args.steps, "ms_per_step": round(ms, 5),
-                              "ns_per_day": round(0.0864 * s.dt * 1e3 / ms, 3),
-                              "list_builds": builds, "status_flags": flags}), flush=True)
+                              "ns_per_day": round(0.0864 * dt * 1e3 / ms, 3),
+                              "list_builds": builds, "temperature_K_end": round(t_end, 1),
+                              "status_flags": flags}), flush=True)
 
 
 def ewald_direct_vs_pme():
