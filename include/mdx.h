@@ -292,7 +292,9 @@ int mdx_compute_ewald_direct(mdx_ctx* ctx, const float* pos, float* force, doubl
  * pair kernel; they are forked from and joined back into the context's
  * stream, so the call is ordered on that stream like any other work.
  * energies, if not NULL, is dev double[n_steps][MDX_N_ENERGY]: all slots
- * after each step.
+ * after each step. After mdx_set_langevin with gamma > 0 each step opens with
+ * the Langevin (BAOAB) half instead (kinetic energy from the closing kick's
+ * velocities as before).
  */
 int mdx_integrate_step(mdx_ctx* ctx, float* pos, float* vel, float* force, int32_t n_steps,
                        float dt, double* energies);
