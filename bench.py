@@ -57,6 +57,9 @@ def parse():
                    help="steps of velocity-rescaled equilibration to 300 K before the warm-up "
                         "(0: start the timed run from the lattice start, which heats up)")
     p.add_argument("--cpu-only", action="store_true", help=argparse.SUPPRESS)
+    p.add_argument("--half-list", action="store_true",
+                   help="run the benchmark with MDX_OPT_HALF_LIST (each pair once, float "
+                        "atomics: forces not bitwise reproducible) instead of the default list")
     p.add_argument("--sweep", action="store_true",
                    help="instead of the benchmark: time per step against system size for "
                         "water boxes with reaction-field and with PME electrostatics (one "
@@ -284,6 +287,8 @@ def main():
                                       "L=98.6 A, r_c=9 A, r_g=2.25 A, Ewald delta 5e-4, "
                                       "PME 100^3 order 4, dt=1 fs, list rebuilt every 10 steps"),
                          "n_atoms": s.n_atoms, "dt_fs": s.dt, "pme_grid": list(s.pme_grid),
+                         "list": "half (each pair once)" if args.half_list else
+                                 "full (each pair from both ends, deterministic)",
                          "parallelism": "single GPU"}}
 
     if not args.cpu_only:
@@ -292,7 +297,8 @@ def main():
 
         dev = torch.device("cuda:0")
         stream = torch.cuda.current_stream(dev)
-        desc, keep = mdx.desc_from_system(s)
+        desc, keep = mdx.desc_from_system(
+            s, options=mdx.MDX_OPT_HALF_LIST if args.half_list else 0)
         ctx = mdx.create(desc, stream.cuda_stream)
         pos = torch.from_numpy(s.pos.copy()).to(dev)
         vel = torch.from_numpy(s.vel.copy()).to(dev)
