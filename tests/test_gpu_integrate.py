@@ -210,3 +210,35 @@ def test_split_calls_match_one_call_bitwise(name, n_steps):
     for other in out[1:]:
         for a, b in zip(out[0], other):
             assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 37])
+def test_tiny_systems_follow_the_oracle(n):
+    # degenerate sizes: one atom (no pairs), a single pair, a partly filled
+    # cluster, a ragged last cluster; LJ only, 25 velocity-Verlet steps
+    import torch
+    s = synth.random_box(n, [6.0, 6.5, 7.0], 2.0, 0.5, 300 + n)
+    s.charge[:] = 0.0
+    # well-separated start (random points can overlap and blow up): the
+    # first n sites of a jittered 4 x 4 x 4 lattice
+    g = np.stack(np.meshgrid(np.arange(4), np.arange(4), np.arange(4), indexing="ij"), 0)
+    g = g.reshape(3, -1)[:, :n].astype(np.float64)
+    jit = np.random.default_rng(n).uniform(-0.1, 0.1, g.shape)
+    s.pos = np.mod((g + 0.5 + jit) * (s.box.astype(np.float64)[:, None] / 4.0),
+                   s.box.astype(np.float64)[:, None]).astype(np.float32)
+    n_steps, dt = 25, 0.002
+    announce(f"tiny system n={n}")
+    with gpu_context(s) as (mdx, ctx, t):
+        mdx.build_neighbors(ctx, t["pos"])
+        mdx.compute_nonbonded(ctx, t["pos"], t["force"])
+        en = torch.zeros((n_steps, mdx.MDX_N_ENERGY), dtype=torch.float64, device="cuda:0")
+        mdx.integrate_step(ctx, t["pos"], t["vel"], t["force"], n_steps, dt, en)
+        torch.cuda.synchronize()
+        assert mdx.get_status(ctx) == 0
+        x_gpu = t["pos"].cpu().numpy().astype(np.float64)
+        assert np.all(np.isfinite(en.cpu().numpy()))
+    F = lambda p: forcefield.total_forces_fp64(s, p)[1]
+    ref = integrate.velocity_verlet(s.pos, s.vel, s.mass, s.box, F, dt, n_steps, float(s.accel))
+    d = x_gpu - ref["pos"]
+    d -= s.box[:, None] * np.round(d / s.box[:, None])
+    assert np.abs(d).max() < 1e-4
