@@ -70,12 +70,13 @@ def test_lj_switched_energy_conservation_dt2():
     assert 2.5 < amp[0] / amp[1] < 6.0, amp
 
 
-def test_water9k_energy_conservation_and_no_stale():
+@pytest.mark.parametrize("options", [0, 1, 2], ids=["full", "half", "cooperative-build"])
+def test_water9k_energy_conservation_and_no_stale(options):
     import torch
     s = synth.config_system("water9k")
     n_steps = 50
-    announce("integrate water9k 50 steps")
-    with gpu_context(s) as (mdx, ctx, t):
+    announce(f"integrate water9k 50 steps options={options}")
+    with gpu_context(s, options=options) as (mdx, ctx, t):
         mdx.build_neighbors(ctx, t["pos"])
         mdx.compute_nonbonded(ctx, t["pos"], t["force"])
         mdx.compute_pme(ctx, t["pos"], t["force"])
