@@ -102,3 +102,27 @@ def test_langevin_argument_checks():
         with pytest.raises(m.MdxError) as e:
             m.set_langevin(ctx, 0.6, 0.1, 1)
         assert e.value.code == m.MDX_E_UNSUPPORTED
+
+
+def test_paper_protocol_reaction_field_langevin_water():
+    # the paper's scaling protocol on a small box: reaction field, Langevin at
+    # 300 K with gamma = 0.1 / fs, dt = 0.5 fs; the thermostat holds the
+    # temperature while the lattice start relaxes
+    import math
+    import torch
+    s = synth.config_system("water9k")
+    s.rf_epsilon, s.ewald_delta, s.pme_grid = 78.5, 0.0, (0, 0, 0)
+    n_steps = 300
+    announce("reaction field + Langevin water9k")
+    with gpu_context(s) as (mdx, ctx, t):
+        mdx.build_neighbors(ctx, t["pos"])
+        mdx.compute_nonbonded(ctx, t["pos"], t["force"])
+        mdx.set_langevin(ctx, float(s.boltzmann) * 300.0, 0.1, 99)
+        en = torch.zeros((n_steps, mdx.MDX_N_ENERGY), dtype=torch.float64, device="cuda:0")
+        mdx.integrate_step(ctx, t["pos"], t["vel"], t["force"], n_steps, 0.5, en)
+        torch.cuda.synchronize()
+        assert mdx.get_status(ctx) == 0
+        E = en.cpu().numpy()
+    assert np.all(np.isfinite(E)) and np.all(E[:, 6] == 0.0) and np.all(E[:, 3] == 0.0)
+    temp = 2.0 * E[:, 7] / (3 * s.n_atoms * float(s.boltzmann))
+    assert abs(temp[150:].mean() / 300.0 - 1.0) < 0.06, temp[150:].mean()
