@@ -59,7 +59,10 @@ extern "C" {
                                         the search holds (list incomplete)   */
 #define MDX_FLAG_COLUMN_OVERFLOW 0x20u /* an x-y column held more atoms than its
                                           capacity (list incomplete; grown and
-                                          rebuilt by mdx_build_neighbors)     */
+                                          rebuilt by mdx_build_neighbors; inside
+                                          mdx_integrate_step the atoms left out
+                                          are not integrated: results invalid,
+                                          call mdx_build_neighbors)           */
 
 /* ---- energy slots (FP64) ----------------------------------------------- */
 #define MDX_ENERGY_LJ         0  /* Eq. 4 (switched by Eq. 6 if enabled)        */

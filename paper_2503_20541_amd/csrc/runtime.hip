@@ -434,6 +434,7 @@ int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
   if ((rc = dev_alloc(x, &c.col_xy, ncol)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.img, (size_t)3 * n)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.pos_alt, (size_t)3 * n)) != MDX_OK) return rc;
+  MDX_TRY(hipMemset(c.pos_alt, 0, sizeof(float) * 3 * (size_t)n));
   MDX_TRY(hipMemset(c.img, 0, sizeof(int) * 3 * (size_t)n));
   if (d->options & MDX_OPT_KAHAN_VV) {
     if ((rc = dev_alloc(x, &c.xc, (size_t)3 * n)) != MDX_OK) return rc;
