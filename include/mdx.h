@@ -334,6 +334,24 @@ int mdx_get_images(mdx_ctx* ctx, int32_t* img);
  */
 int mdx_set_langevin(mdx_ctx* ctx, double kT, double gamma, uint64_t seed);
 
+/*
+ * Rigid water for the following mdx_integrate_step calls (the rigid-water
+ * option the paper uses for its longer time step, Sec. III; RATTLE with
+ * velocity Verlet): mols (host int32[n_mol][3], caller atoms O, H1, H2, each
+ * atom at most once) are held at |O-H| = d_oh and |H1-H2| = d_hh. After each
+ * drift the three distances are restored by SHAKE iterations along the
+ * previous bond vectors (float32, to a relative 2e-6 in r^2) with the same
+ * correction over dt applied to the velocities, and after the closing kick
+ * the velocities are projected onto the constraints (r . v_rel = 0). The
+ * bond and angle terms of these molecules should be zero (their energy is
+ * constant). Every step then runs its own opening kernel (no fused
+ * closing/opening), and the kinetic energy slot is taken before the velocity
+ * projection. n_mol = 0 switches it off. MDX_E_INVALID for bad indices or
+ * distances; MDX_E_UNSUPPORTED together with Langevin or MDX_OPT_KAHAN_VV.
+ */
+int mdx_set_rigid_water(mdx_ctx* ctx, const int32_t* mols, int32_t n_mol, double d_oh,
+                        double d_hh);
+
 /* Fills *info (host). Synchronising once a list exists: the list is copied
  * to the host to count its entries. */
 int mdx_get_info(mdx_ctx* ctx, mdx_info* info);

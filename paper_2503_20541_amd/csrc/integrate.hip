@@ -99,6 +99,27 @@ __device__ __forceinline__ void langevin_normals(unsigned long long seed, unsign
   z[2] = r2 * cosf(t2);
 }
 
+// The rest of the opening half once the three new coordinates of atom a
+// (slot s) are known: slot refresh and the two validity tests.
+__device__ __forceinline__ void open_tail(const OpenStep& o, int a, int s, const float x[3]) {
+  const int n = o.n;
+  const CellGrid& cg = o.cg;
+  const float bx = o.x_build[a], by = o.x_build[n + a], bz = o.x_build[2 * n + a];
+  const float dx = min_image(bx, x[0], cg.L[0], cg.hL[0]);
+  const float dy = min_image(by, x[1], cg.L[1], cg.hL[1]);
+  const float dz = min_image(bz, x[2], cg.L[2], cg.hL[2]);
+  // slot position continued from the build position (not wrapped between
+  // builds), so the periodic image each list tile records stays valid
+  o.xs[s] = make_float4(bx + dx, by + dy, bz + dz, o.q[a]);
+  if (dist2(dx, dy, dz) > o.half_skin2) atomicOr(o.gate_now, 1);
+  // pruned list: displacement since it was made (same slot order)
+  const float4 q0 = o.xp[s];
+  const float px = min_image(q0.x, x[0], cg.L[0], cg.hL[0]);
+  const float py = min_image(q0.y, x[1], cg.L[1], cg.hL[1]);
+  const float pz = min_image(q0.z, x[2], cg.L[2], cg.hL[2]);
+  if (dist2(px, py, pz) > o.prune_move2) atomicOr(o.pgate_now, 1);
+}
+
 __device__ __forceinline__ void open_step_atom(const OpenStep& o, const float* __restrict__ force,
                                                float* __restrict__ vel, int a, int s) {
   const int n = o.n;
@@ -141,20 +162,7 @@ __device__ __forceinline__ void open_step_atom(const OpenStep& o, const float* _
     o.pos_out[k] = x[d];
     if (wraps) o.img[k] += wraps;
   }
-  const float bx = o.x_build[a], by = o.x_build[n + a], bz = o.x_build[2 * n + a];
-  const float dx = min_image(bx, x[0], cg.L[0], cg.hL[0]);
-  const float dy = min_image(by, x[1], cg.L[1], cg.hL[1]);
-  const float dz = min_image(bz, x[2], cg.L[2], cg.hL[2]);
-  // slot position continued from the build position (not wrapped between
-  // builds), so the periodic image each list tile records stays valid
-  o.xs[s] = make_float4(bx + dx, by + dy, bz + dz, o.q[a]);
-  if (dist2(dx, dy, dz) > o.half_skin2) atomicOr(o.gate_now, 1);
-  // pruned list: displacement since it was made (same slot order)
-  const float4 q0 = o.xp[s];
-  const float px = min_image(q0.x, x[0], cg.L[0], cg.hL[0]);
-  const float py = min_image(q0.y, x[1], cg.L[1], cg.hL[1]);
-  const float pz = min_image(q0.z, x[2], cg.L[2], cg.hL[2]);
-  if (dist2(px, py, pz) > o.prune_move2) atomicOr(o.pgate_now, 1);
+  open_tail(o, a, s, x);
 }
 
 // Stand-alone opening half for every slot (the first step of a call).
@@ -291,6 +299,169 @@ OpenStep make_open(const Ctx& c, const float* pos_in, float* pos_out, float dt,
   return o;
 }
 }  // namespace
+
+// Rigid water (RATTLE): after the drift, each molecule's three distances
+// (O-H1, O-H2, H1-H2) are restored by SHAKE iterations along the bond
+// vectors of the previous positions x_old (minimum image), the velocities
+// take the same correction over dt, and the atoms are wrapped, their slots
+// refreshed and the validity tests redone; after the closing kick the
+// velocities are projected onto the constraints (an exact 3x3 solve). One
+// thread per molecule.
+struct RigidArgs {
+  const int* mols;     // [n_mol][3] caller atoms O, H1, H2
+  int n_mol;
+  float d[3];          // O-H1, O-H2, H1-H2
+  const float* acc_over_m;
+};
+
+__device__ __forceinline__ float3 mi3(float3 d, const CellGrid& cg) {
+  return make_float3(min_image(0.f, d.x, cg.L[0], cg.hL[0]), min_image(0.f, d.y, cg.L[1], cg.hL[1]),
+                     min_image(0.f, d.z, cg.L[2], cg.hL[2]));
+}
+
+__global__ void __launch_bounds__(256) k_rigid_positions(RigidArgs r, OpenStep o,
+                                                         const float* __restrict__ x_old,
+                                                         float* __restrict__ pos,
+                                                         float* __restrict__ vel,
+                                                         const int* __restrict__ inv_perm) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= r.n_mol) return;
+  const int n = o.n;
+  const CellGrid& cg = o.cg;
+  int at[3];
+  float3 y0[3], dl[3], ref[3], d0[3];
+  float w[3];
+  for (int k = 0; k < 3; ++k) {
+    at[k] = r.mols[3 * m + k];
+    y0[k] = make_float3(pos[at[k]], pos[n + at[k]], pos[2 * n + at[k]]);
+    dl[k] = make_float3(0.f, 0.f, 0.f);
+    w[k] = 1.0f / r.acc_over_m[at[k]];   // mass / accel: the ratio is what matters
+  }
+  // constraint c joins atoms (ca, cb): (0,1), (0,2), (1,2); directions from x_old
+  const int ca[3] = {0, 0, 1}, cb[3] = {1, 2, 2};
+  for (int c = 0; c < 3; ++c) {
+    const int a = at[ca[c]], b = at[cb[c]];
+    ref[c] = mi3(make_float3(x_old[a] - x_old[b], x_old[n + a] - x_old[n + b],
+                             x_old[2 * n + a] - x_old[2 * n + b]), cg);
+    d0[c] = mi3(make_float3(y0[ca[c]].x - y0[cb[c]].x, y0[ca[c]].y - y0[cb[c]].y,
+                            y0[ca[c]].z - y0[cb[c]].z), cg);
+  }
+  // The iteration moves the displacements dl (small numbers) rather than the
+  // coordinates: the velocity correction dl/dt then carries no cancellation
+  // between two coordinates of the size of the box.
+  for (int it = 0; it < 200; ++it) {
+    float worst = 0.f;
+    for (int c = 0; c < 3; ++c) {
+      const int a = ca[c], b = cb[c];
+      const float3 d = make_float3(d0[c].x + (dl[a].x - dl[b].x), d0[c].y + (dl[a].y - dl[b].y),
+                                   d0[c].z + (dl[a].z - dl[b].z));
+      const float diff = d.x * d.x + d.y * d.y + d.z * d.z - r.d[c] * r.d[c];
+      worst = fmaxf(worst, fabsf(diff) / (r.d[c] * r.d[c]));
+      const float g = diff / (2.0f * (1.0f / w[a] + 1.0f / w[b]) *
+                              (d.x * ref[c].x + d.y * ref[c].y + d.z * ref[c].z));
+      dl[a].x -= g * ref[c].x / w[a];
+      dl[a].y -= g * ref[c].y / w[a];
+      dl[a].z -= g * ref[c].z / w[a];
+      dl[b].x += g * ref[c].x / w[b];
+      dl[b].y += g * ref[c].y / w[b];
+      dl[b].z += g * ref[c].z / w[b];
+    }
+    if (worst < 5e-7f) break;
+  }
+  for (int k = 0; k < 3; ++k) {
+    const int a = at[k];
+    const float inv_dt = 1.0f / o.dt;
+    const float dx0[3] = {dl[k].x, dl[k].y, dl[k].z};
+    float x[3] = {y0[k].x + dl[k].x, y0[k].y + dl[k].y, y0[k].z + dl[k].z};
+    for (int d = 0; d < 3; ++d) {
+      const size_t kk = (size_t)d * n + a;
+      vel[kk] += dx0[d] * inv_dt;
+      int wraps;
+      x[d] = wrap_box(x[d], cg.L[d], wraps);
+      pos[kk] = x[d];
+      if (wraps) o.img[kk] += wraps;
+    }
+    const int s = inv_perm[a];
+    open_tail(o, a, s, x);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_rigid_velocities(RigidArgs r, CellGrid cg, int n,
+                                                          const float* __restrict__ pos,
+                                                          float* __restrict__ vel) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= r.n_mol) return;
+  int at[3];
+  float3 v[3];
+  float iw[3];
+  for (int k = 0; k < 3; ++k) {
+    at[k] = r.mols[3 * m + k];
+    v[k] = make_float3(vel[at[k]], vel[n + at[k]], vel[2 * n + at[k]]);
+    iw[k] = r.acc_over_m[at[k]];   // 1 / (mass / accel)
+  }
+  const int ca[3] = {0, 0, 1}, cb[3] = {1, 2, 2};
+  float3 rc[3];
+  for (int c = 0; c < 3; ++c) {
+    const int a = at[ca[c]], b = at[cb[c]];
+    rc[c] = mi3(make_float3(pos[a] - pos[b], pos[n + a] - pos[n + b], pos[2 * n + a] - pos[2 * n + b]),
+                cg);
+  }
+  // A mu = rhs: r_c . (v_a - v_b) after v_i += sum_c' mu_c' s_c',i r_c' w_i^-1 vanishes
+  double A[3][3], rhs[3];
+  for (int c = 0; c < 3; ++c) {
+    const int a = ca[c], b = cb[c];
+    const float3 dv = make_float3(v[a].x - v[b].x, v[a].y - v[b].y, v[a].z - v[b].z);
+    rhs[c] = -((double)rc[c].x * dv.x + (double)rc[c].y * dv.y + (double)rc[c].z * dv.z);
+    for (int c2 = 0; c2 < 3; ++c2) {
+      const int a2 = ca[c2], b2 = cb[c2];
+      const double coef = (a2 == a ? iw[a] : 0.0) - (b2 == a ? iw[a] : 0.0) -
+                          (a2 == b ? iw[b] : 0.0) + (b2 == b ? iw[b] : 0.0);
+      A[c][c2] = ((double)rc[c].x * rc[c2].x + (double)rc[c].y * rc[c2].y +
+                  (double)rc[c].z * rc[c2].z) * coef;
+    }
+  }
+  // Cramer's rule (3x3)
+  const double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+                     A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                     A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+  double mu[3];
+  for (int c = 0; c < 3; ++c) {
+    double B[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) B[i][j] = j == c ? rhs[i] : A[i][j];
+    mu[c] = (B[0][0] * (B[1][1] * B[2][2] - B[1][2] * B[2][1]) -
+             B[0][1] * (B[1][0] * B[2][2] - B[1][2] * B[2][0]) +
+             B[0][2] * (B[1][0] * B[2][1] - B[1][1] * B[2][0])) / det;
+  }
+  for (int c = 0; c < 3; ++c) {
+    const int a = ca[c], b = cb[c];
+    v[a].x += (float)(mu[c] * rc[c].x * iw[a]);
+    v[a].y += (float)(mu[c] * rc[c].y * iw[a]);
+    v[a].z += (float)(mu[c] * rc[c].z * iw[a]);
+    v[b].x -= (float)(mu[c] * rc[c].x * iw[b]);
+    v[b].y -= (float)(mu[c] * rc[c].y * iw[b]);
+    v[b].z -= (float)(mu[c] * rc[c].z * iw[b]);
+  }
+  for (int k = 0; k < 3; ++k) {
+    vel[at[k]] = v[k].x;
+    vel[n + at[k]] = v[k].y;
+    vel[2 * n + at[k]] = v[k].z;
+  }
+}
+
+hipError_t launch_rigid_positions(Ctx& c, const float* x_old, float* pos, float* vel, float dt,
+                                  const StepGates& g) {
+  RigidArgs r{c.rigid_mols, c.n_rigid, {c.rigid_d[0], c.rigid_d[1], c.rigid_d[2]}, c.hdt_scale};
+  k_rigid_positions<<<(c.n_rigid + 255) / 256, 256, 0, c.stream>>>(r, make_open(c, pos, pos, dt, g),
+                                                                   x_old, pos, vel, c.inv_perm);
+  return hipGetLastError();
+}
+
+hipError_t launch_rigid_velocities(Ctx& c, const float* pos, float* vel) {
+  RigidArgs r{c.rigid_mols, c.n_rigid, {c.rigid_d[0], c.rigid_d[1], c.rigid_d[2]}, c.hdt_scale};
+  k_rigid_velocities<<<(c.n_rigid + 255) / 256, 256, 0, c.stream>>>(r, c.cg, c.n, pos, vel);
+  return hipGetLastError();
+}
 
 hipError_t launch_begin_step(Ctx& c, float* pos, float* vel, const float* force, float dt,
                              const StepGates& g) {

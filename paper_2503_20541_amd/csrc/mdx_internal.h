@@ -98,6 +98,10 @@ struct Ctx {
   unsigned long long lv_seed = 0;
   float* lv_sig = nullptr;     // [n] sqrt(kT accel / m_i)
   std::vector<float> mass_h;   // [n] masses (host copy)
+  // rigid water (mdx_set_rigid_water)
+  int n_rigid = 0;
+  int* rigid_mols = nullptr;   // [n_rigid][3] caller atoms O, H1, H2
+  float rigid_d[3] = {0.f, 0.f, 0.f};
   // direct reciprocal Ewald sum (mdx_compute_ewald_direct): scratch for the
   // largest n_max asked for so far
   int ew_nmax = 0;
@@ -239,6 +243,12 @@ hipError_t launch_begin_step(Ctx& c, float* pos, float* vel, const float* force,
 hipError_t launch_finish_step(Ctx& c, const float* pos, float* vel, float* force, float dt,
                               bool energy, const StepGates* next = nullptr,
                               float* pos_next = nullptr);
+// Rigid water: SHAKE after the drift (x_old: positions before it) with the
+// velocity correction, wrap, slot refresh and validity tests; RATTLE velocity
+// projection after the closing kick.
+hipError_t launch_rigid_positions(Ctx& c, const float* x_old, float* pos, float* vel, float dt,
+                                  const StepGates& g);
+hipError_t launch_rigid_velocities(Ctx& c, const float* pos, float* vel);
 // Spread + FFT passes only (the potential grid), for the fused closing kernel.
 // `done` (may be null) is recorded by the last kernel's own dispatch.
 hipError_t launch_pme_spread(Ctx& c, hipStream_t s, hipEvent_t done);

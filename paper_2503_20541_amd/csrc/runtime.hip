@@ -793,8 +793,20 @@ int mdx_integrate_step(mdx_ctx* x, float* pos, float* vel, float* force, int32_t
   // pos_alt, alternating); the last positions are copied back if needed.
   float* pos_cur = pos;
   float* pos_other = c.pos_alt;
+  // Rigid water: every step opens with its own kernel, in place, followed by
+  // the position constraints (pos_alt holds the positions before the drift),
+  // and closes with the velocity projection.
+  const bool rigid = c.n_rigid > 0;
+  auto open_rigid = [&](const mdx::StepGates& gs) -> hipError_t {
+    hipError_t err = hipMemcpyAsync(c.pos_alt, pos, sizeof(float) * 3 * (size_t)c.n,
+                                    hipMemcpyDeviceToDevice, c.stream);
+    if (err == hipSuccess) err = mdx::launch_begin_step(c, pos, vel, force, dt, gs);
+    if (err == hipSuccess) err = mdx::launch_rigid_positions(c, c.pos_alt, pos, vel, dt, gs);
+    return err;
+  };
   mdx::StepGates g = gates_of(c.steps_taken);
-  MDX_TRY(mdx::launch_begin_step(c, pos_cur, vel, force, dt, g));
+  if (rigid) MDX_TRY(open_rigid(g));
+  else MDX_TRY(mdx::launch_begin_step(c, pos_cur, vel, force, dt, g));
   for (int s = 0; s < n_steps; ++s) {
     int* gate_now = g.gate_now;
     int* pgate_now = g.pgate_now;
@@ -826,7 +838,14 @@ int mdx_integrate_step(mdx_ctx* x, float* pos, float* vel, float* force, int32_t
                                     ps ? ps->first : nullptr, ps ? ps->second : nullptr));
     }
     if (c.has_pme) MDX_TRY(hipStreamWaitEvent(c.stream, x->ev_join, 0));
-    if (s + 1 < n_steps) {
+    if (rigid) {
+      MDX_TRY(mdx::launch_finish_step(c, pos_cur, vel, force, dt, e));
+      MDX_TRY(mdx::launch_rigid_velocities(c, pos_cur, vel));
+      if (s + 1 < n_steps) {
+        g = gates_of(c.steps_taken + 1);
+        MDX_TRY(open_rigid(g));
+      }
+    } else if (s + 1 < n_steps) {
       const mdx::StepGates next = gates_of(c.steps_taken + 1);
       MDX_TRY(mdx::launch_finish_step(c, pos_cur, vel, force, dt, e, &next, pos_other));
       std::swap(pos_cur, pos_other);
@@ -889,12 +908,39 @@ int mdx_compute_ewald_direct(mdx_ctx* x, const float* pos, float* force, double*
   return MDX_OK;
 }
 
+int mdx_set_rigid_water(mdx_ctx* x, const int32_t* mols, int32_t n_mol, double d_oh,
+                        double d_hh) {
+  if (check_ctx(x) || n_mol < 0 || (n_mol > 0 && (!mols || !(d_oh > 0.0) || !(d_hh > 0.0))))
+    return MDX_E_INVALID;
+  Ctx& c = x->c;
+  if (n_mol > 0 && (c.xc || c.langevin)) return MDX_E_UNSUPPORTED;
+  std::vector<int> seen(c.n, 0);
+  for (int64_t i = 0; i < 3 * (int64_t)n_mol; ++i) {
+    const int a = mols[i];
+    if (a < 0 || a >= c.n || seen[a]++) return MDX_E_INVALID;   // in range, each atom once
+  }
+  if (n_mol > c.n_rigid) {
+    dev_free(x, c.rigid_mols);
+    c.rigid_mols = nullptr;
+    int rc = dev_alloc(x, &c.rigid_mols, (size_t)3 * n_mol);
+    if (rc != MDX_OK) return rc;
+  }
+  if (n_mol > 0)
+    MDX_TRY(hipMemcpy(c.rigid_mols, mols, sizeof(int) * 3 * (size_t)n_mol,
+                      hipMemcpyHostToDevice));
+  c.n_rigid = n_mol;
+  c.rigid_d[0] = c.rigid_d[1] = (float)d_oh;
+  c.rigid_d[2] = (float)d_hh;
+  return MDX_OK;
+}
+
 int mdx_set_langevin(mdx_ctx* x, double kT, double gamma, uint64_t seed) {
   if (check_ctx(x) || !(kT >= 0.0) || !(gamma >= 0.0) || !std::isfinite(kT) ||
       !std::isfinite(gamma))
     return MDX_E_INVALID;
   Ctx& c = x->c;
   if (c.xc && gamma > 0.0) return MDX_E_UNSUPPORTED;
+  if (c.n_rigid > 0 && gamma > 0.0) return MDX_E_UNSUPPORTED;
   c.langevin = gamma > 0.0;
   c.lv_kT = kT;
   c.lv_gamma = gamma;

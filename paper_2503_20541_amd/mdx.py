@@ -62,7 +62,7 @@ EXPORTED = ("mdx_error_string", "mdx_create", "mdx_destroy", "mdx_set_stream",
             "mdx_build_neighbors", "mdx_get_neighbor_pairs", "mdx_compute_nonbonded",
             "mdx_compute_pme", "mdx_integrate_step", "mdx_get_status", "mdx_get_info",
             "mdx_set_timing", "mdx_get_timing", "mdx_get_images", "mdx_set_langevin",
-            "mdx_compute_ewald_direct")
+            "mdx_compute_ewald_direct", "mdx_set_rigid_water")
 
 _fp = ctypes.POINTER(ctypes.c_float)
 _ip = ctypes.POINTER(ctypes.c_int32)
@@ -114,6 +114,7 @@ _lib.mdx_get_status.argtypes = [_vp, ctypes.POINTER(ctypes.c_uint32)]
 _lib.mdx_get_images.argtypes = [_vp, _vp]
 _lib.mdx_set_langevin.argtypes = [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_uint64]
 _lib.mdx_compute_ewald_direct.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int32]
+_lib.mdx_set_rigid_water.argtypes = [_vp, _vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double]
 _lib.mdx_get_info.argtypes = [_vp, ctypes.POINTER(Info)]
 _lib.mdx_set_timing.argtypes = [_vp, ctypes.c_int]
 _lib.mdx_get_timing.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
@@ -284,6 +285,13 @@ def get_status(ctx: int) -> int:
 def compute_ewald_direct(ctx: int, pos, force, energy=None, n_max: int = 8) -> None:
     _check(_lib.mdx_compute_ewald_direct(ctx, _ptr(pos), _ptr(force), _ptr(energy), int(n_max)),
            "mdx_compute_ewald_direct")
+
+
+def set_rigid_water(ctx: int, mols, d_oh: float, d_hh: float) -> None:
+    """Rigid water (RATTLE) for later integrate_step calls; mols: host int [M, 3]."""
+    m = np.ascontiguousarray(np.asarray(mols, np.int32).reshape(-1, 3))
+    _check(_lib.mdx_set_rigid_water(ctx, m.ctypes.data if m.size else None, int(len(m)),
+                                    float(d_oh), float(d_hh)), "mdx_set_rigid_water")
 
 
 def set_langevin(ctx: int, kT: float, gamma: float, seed: int) -> None:
