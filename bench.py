@@ -64,6 +64,8 @@ def parse():
                    help="instead of the benchmark: time per step against system size for "
                         "water boxes with reaction-field and with PME electrostatics (one "
                         "JSON line per box and method)")
+    p.add_argument("--sweep-protocols", default="rf,pme,rf_langevin_paper,rf_rigid_2fs",
+                   help="comma-separated protocols of --sweep")
     p.add_argument("--ewald-direct", action="store_true",
                    help="instead of the benchmark: time the direct reciprocal Ewald sum "
                         "(converged to 1e-8 in the Gaussian factor) against SPME for the "
@@ -142,14 +144,18 @@ SWEEP_BOXES = ((1000, 32), (4000, 48), (8000, 64), (27000, 96), (32000, 100), (6
 
 
 def sweep(args):
-    """Time per step against N for the same water model under three
+    """Time per step against N for the same water model under up to four
     protocols: velocity Verlet with the reaction field (Eq. 8, eps_s = 78.5)
     and with SPME (the shape of the paper's RFA / PME scaling figure), both at
     r_c = 9 A, r_g = 2.25 A, dt = 1 fs; and the paper's own benchmark protocol
     (reaction field, Langevin dynamics at 300 K with gamma = 0.1 / fs,
-    dt = 0.5 fs, r_c = 10 A, r_g = 2.5 A). Lists are rebuilt every 10 steps
+    dt = 0.5 fs, r_c = 10 A, r_g = 2.5 A); and, as a fourth protocol, the
+    reaction field with rigid water (SHAKE / RATTLE) at dt = 2 fs. Lists are
+    rebuilt every 10 steps
     (and whenever an atom has moved more than r_g / 2); each run is brought to
     300 K for 1000 untimed steps first."""
+    import math
+    import numpy as np
     import torch
     import synth
     import paper_2503_20541_amd as mdx
@@ -159,7 +165,7 @@ def sweep(args):
         L = (n_mol * 29.91) ** (1.0 / 3.0)
         base = synth.water_box(n_mol, L, (max(K, 32),) * 3, 9.0, None, 5e-4, 11,
                                n_steps=1000, name=f"water{3 * n_mol}")
-        for method in ("rf", "pme", "rf_langevin_paper"):
+        for method in args.sweep_protocols.split(","):
             if method == "pme" and K == 0:
                 continue
             s = base.copy()
@@ -169,6 +175,8 @@ def sweep(args):
             if method == "rf_langevin_paper":
                 s.r_cut, s.r_ghost = s.r_cut.__class__(10.0), s.r_ghost.__class__(2.5)
                 dt, gamma = 0.5, 0.1
+            if method == "rf_rigid_2fs":
+                dt = 2.0
             desc, keep = mdx.desc_from_system(s)
             ctx = mdx.create(desc, stream.cuda_stream)
             pos = torch.from_numpy(s.pos.copy()).to(dev)
@@ -178,6 +186,12 @@ def sweep(args):
             mdx.compute_nonbonded(ctx, pos, force)
             if method == "pme":
                 mdx.compute_pme(ctx, pos, force)
+            if method == "rf_rigid_2fs":
+                w = synth.systems.WATER
+                d_oh = float(w["bond_r0"])
+                d_hh = 2.0 * d_oh * math.sin(math.radians(w["angle_theta0_deg"]) / 2.0)
+                mdx.set_rigid_water(ctx, np.arange(s.n_atoms, dtype=np.int32).reshape(-1, 3),
+                                    d_oh, d_hh)
             for _ in range(10):
                 mdx.integrate_step(ctx, pos, vel, force, 100, dt)
                 vel.mul_((300.0 / temperature(s, vel)) ** 0.5)
