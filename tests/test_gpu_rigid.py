@@ -16,11 +16,12 @@ D_OH = W["bond_r0"]
 D_HH = 2.0 * D_OH * math.sin(math.radians(W["angle_theta0_deg"]) / 2.0)
 
 
-def rigid_rf_water(name):
+def rigid_rf_water(name, coulomb="rf"):
     s = synth.config_system(name)
     s.bond_k[:] = 0.0
     s.angle_k[:] = 0.0
-    s.rf_epsilon, s.ewald_delta, s.pme_grid = math.inf, 0.0, (0, 0, 0)
+    if coulomb == "rf":
+        s.rf_epsilon, s.ewald_delta, s.pme_grid = math.inf, 0.0, (0, 0, 0)
     mols = np.arange(s.n_atoms, dtype=np.int32).reshape(-1, 3)
     return s, mols
 
@@ -41,17 +42,21 @@ def _dev(a, b, box):
     return float(np.sqrt((d * d).mean()))
 
 
-def test_rigid_water_tracks_the_rattle_oracle():
+@pytest.mark.parametrize("coulomb", ["rf", "pme"])
+def test_rigid_water_tracks_the_rattle_oracle(coulomb):
+    # with PME the intramolecular pairs carry the Ewald exclusion correction
     import torch
-    s, mols = rigid_rf_water("water375")
+    s, mols = rigid_rf_water("water375", coulomb)
     # start from velocities that already satisfy the constraints (the library
     # projects after each closing kick, the oracle also before the first step)
     s.vel = constraints.rattle_velocities(s.pos, s.vel, s.mass, s.box, mols).astype(np.float32)
     n_steps, dt = 30, 2.0
-    announce("rigid water375 30 steps at 2 fs")
+    announce(f"rigid water375 ({coulomb}) 30 steps at 2 fs")
     with gpu_context(s) as (mdx, ctx, t):
         mdx.build_neighbors(ctx, t["pos"])
         mdx.compute_nonbonded(ctx, t["pos"], t["force"])
+        if coulomb == "pme":
+            mdx.compute_pme(ctx, t["pos"], t["force"])
         mdx.set_rigid_water(ctx, mols, D_OH, D_HH)
         mdx.integrate_step(ctx, t["pos"], t["vel"], t["force"], n_steps, dt)
         torch.cuda.synchronize()
@@ -105,6 +110,27 @@ def test_rigid_water_conserves_energy_at_two_femtoseconds():
         assert np.abs(d / ref - 1.0).max() < 1e-5
     etot = E.sum(axis=1)
     assert np.abs(etot - etot[0]).max() < 0.02 * E[:, 7].mean()
+
+
+def test_rigid_water_split_calls_match_one_call_bitwise():
+    import torch
+    s, mols = rigid_rf_water("water9k", "pme")
+    n_steps = 24
+    out = []
+    for chunks in ([n_steps], [5, 7, 1, n_steps - 13]):
+        announce(f"rigid water9k {n_steps} steps in calls of {chunks}")
+        with gpu_context(s) as (mdx, ctx, t):
+            mdx.build_neighbors(ctx, t["pos"])
+            mdx.compute_nonbonded(ctx, t["pos"], t["force"])
+            mdx.compute_pme(ctx, t["pos"], t["force"])
+            mdx.set_rigid_water(ctx, mols, D_OH, D_HH)
+            for k in chunks:
+                mdx.integrate_step(ctx, t["pos"], t["vel"], t["force"], k, 2.0)
+            torch.cuda.synchronize()
+            assert mdx.get_status(ctx) == 0
+            out.append((t["pos"].cpu().numpy(), t["vel"].cpu().numpy()))
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
 
 
 def test_rigid_water_argument_checks():
