@@ -66,6 +66,8 @@ def parse():
                         "JSON line per box and method)")
     p.add_argument("--sweep-protocols", default="rf,pme,rf_langevin_paper,rf_rigid_2fs",
                    help="comma-separated protocols of --sweep")
+    p.add_argument("--sweep-molecules", type=int, nargs="*", default=None,
+                   help="only these box sizes (water molecules) in --sweep")
     p.add_argument("--ewald-direct", action="store_true",
                    help="instead of the benchmark: time the direct reciprocal Ewald sum "
                         "(converged to 1e-8 in the Gaussian factor) against SPME for the "
@@ -162,6 +164,8 @@ def sweep(args):
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     for n_mol, K in SWEEP_BOXES:
+        if args.sweep_molecules and n_mol not in args.sweep_molecules:
+            continue
         L = (n_mol * 29.91) ** (1.0 / 3.0)
         base = synth.water_box(n_mol, L, (max(K, 32),) * 3, 9.0, None, 5e-4, 11,
                                n_steps=1000, name=f"water{3 * n_mol}")

@@ -319,9 +319,13 @@ __device__ __forceinline__ float3 mi3(float3 d, const CellGrid& cg) {
                      min_image(0.f, d.z, cg.L[2], cg.hL[2]));
 }
 
-__global__ void __launch_bounds__(256) k_rigid_positions(RigidArgs r, OpenStep o,
-                                                         const float* __restrict__ x_old,
-                                                         float* __restrict__ pos,
+// x_old: positions before the drift; y_in: after it; pos: where the
+// constrained positions go (x_old and pos may be the same array: a thread
+// reads and writes the coordinates of its own molecule only).
+__global__ void __launch_bounds__(64) k_rigid_positions(RigidArgs r, OpenStep o,
+                                                        const float* x_old,
+                                                        const float* __restrict__ y_in,
+                                                        float* pos,
                                                          float* __restrict__ vel,
                                                          const int* __restrict__ inv_perm) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
@@ -330,12 +334,12 @@ __global__ void __launch_bounds__(256) k_rigid_positions(RigidArgs r, OpenStep o
   const CellGrid& cg = o.cg;
   int at[3];
   float3 y0[3], dl[3], ref[3], d0[3];
-  float w[3];
+  float iw[3];
   for (int k = 0; k < 3; ++k) {
     at[k] = r.mols[3 * m + k];
-    y0[k] = make_float3(pos[at[k]], pos[n + at[k]], pos[2 * n + at[k]]);
+    y0[k] = make_float3(y_in[at[k]], y_in[n + at[k]], y_in[2 * n + at[k]]);
     dl[k] = make_float3(0.f, 0.f, 0.f);
-    w[k] = 1.0f / r.acc_over_m[at[k]];   // mass / accel: the ratio is what matters
+    iw[k] = r.acc_over_m[at[k]];   // accel / mass: only the ratios matter
   }
   // constraint c joins atoms (ca, cb): (0,1), (0,2), (1,2); directions from x_old
   const int ca[3] = {0, 0, 1}, cb[3] = {1, 2, 2};
@@ -357,16 +361,19 @@ __global__ void __launch_bounds__(256) k_rigid_positions(RigidArgs r, OpenStep o
                                    d0[c].z + (dl[a].z - dl[b].z));
       const float diff = d.x * d.x + d.y * d.y + d.z * d.z - r.d[c] * r.d[c];
       worst = fmaxf(worst, fabsf(diff) / (r.d[c] * r.d[c]));
-      const float g = diff / (2.0f * (1.0f / w[a] + 1.0f / w[b]) *
+      const float g = diff / (2.0f * (iw[a] + iw[b]) *
                               (d.x * ref[c].x + d.y * ref[c].y + d.z * ref[c].z));
-      dl[a].x -= g * ref[c].x / w[a];
-      dl[a].y -= g * ref[c].y / w[a];
-      dl[a].z -= g * ref[c].z / w[a];
-      dl[b].x += g * ref[c].x / w[b];
-      dl[b].y += g * ref[c].y / w[b];
-      dl[b].z += g * ref[c].z / w[b];
+      const float ga = g * iw[a], gb = g * iw[b];
+      dl[a].x -= ga * ref[c].x;
+      dl[a].y -= ga * ref[c].y;
+      dl[a].z -= ga * ref[c].z;
+      dl[b].x += gb * ref[c].x;
+      dl[b].y += gb * ref[c].y;
+      dl[b].z += gb * ref[c].z;
     }
-    if (worst < 5e-7f) break;
+    // 2e-6 in r^2 (1e-6 in length) stays well above the float32 rounding of
+    // |d|^2 (a few 1e-7), so every molecule stops after a few sweeps
+    if (worst < 2e-6f) break;
   }
   for (int k = 0; k < 3; ++k) {
     const int a = at[k];
@@ -386,7 +393,7 @@ __global__ void __launch_bounds__(256) k_rigid_positions(RigidArgs r, OpenStep o
   }
 }
 
-__global__ void __launch_bounds__(256) k_rigid_velocities(RigidArgs r, CellGrid cg, int n,
+__global__ void __launch_bounds__(64) k_rigid_velocities(RigidArgs r, CellGrid cg, int n,
                                                           const float* __restrict__ pos,
                                                           float* __restrict__ vel) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
@@ -449,23 +456,24 @@ __global__ void __launch_bounds__(256) k_rigid_velocities(RigidArgs r, CellGrid 
   }
 }
 
-hipError_t launch_rigid_positions(Ctx& c, const float* x_old, float* pos, float* vel, float dt,
-                                  const StepGates& g) {
+hipError_t launch_rigid_positions(Ctx& c, const float* x_old, const float* y_in, float* pos,
+                                  float* vel, float dt, const StepGates& g) {
   RigidArgs r{c.rigid_mols, c.n_rigid, {c.rigid_d[0], c.rigid_d[1], c.rigid_d[2]}, c.hdt_scale};
-  k_rigid_positions<<<(c.n_rigid + 255) / 256, 256, 0, c.stream>>>(r, make_open(c, pos, pos, dt, g),
-                                                                   x_old, pos, vel, c.inv_perm);
+  // 64-lane groups: one molecule per lane, and enough groups to reach every CU
+  k_rigid_positions<<<(c.n_rigid + 63) / 64, 64, 0, c.stream>>>(r, make_open(c, pos, pos, dt, g),
+                                                                x_old, y_in, pos, vel, c.inv_perm);
   return hipGetLastError();
 }
 
 hipError_t launch_rigid_velocities(Ctx& c, const float* pos, float* vel) {
   RigidArgs r{c.rigid_mols, c.n_rigid, {c.rigid_d[0], c.rigid_d[1], c.rigid_d[2]}, c.hdt_scale};
-  k_rigid_velocities<<<(c.n_rigid + 255) / 256, 256, 0, c.stream>>>(r, c.cg, c.n, pos, vel);
+  k_rigid_velocities<<<(c.n_rigid + 63) / 64, 64, 0, c.stream>>>(r, c.cg, c.n, pos, vel);
   return hipGetLastError();
 }
 
 hipError_t launch_begin_step(Ctx& c, float* pos, float* vel, const float* force, float dt,
-                             const StepGates& g) {
-  k_begin_step<<<(c.max_slots + 255) / 256, 256, 0, c.stream>>>(make_open(c, pos, pos, dt, g),
+                             const StepGates& g, float* pos_out) {
+  k_begin_step<<<(c.max_slots + 255) / 256, 256, 0, c.stream>>>(make_open(c, pos, pos_out ? pos_out : pos, dt, g),
                                                                  force, vel, c.perm, c.meta);
   return hipGetLastError();
 }

@@ -233,9 +233,10 @@ struct StepGates {
   bool cadence;
   long long step;   // the step's index among all the context's steps (Langevin noise)
 };
-// Opening half of a step: positions read from and written to pos (in place).
+// Opening half of a step: positions read from pos and written to pos_out
+// (in place when pos_out is null).
 hipError_t launch_begin_step(Ctx& c, float* pos, float* vel, const float* force, float dt,
-                             const StepGates& g);
+                             const StepGates& g, float* pos_out = nullptr);
 // Closing half of a step at positions pos. With `next`, the same kernel then
 // opens the following step (gates *next) from the closing kick's velocities
 // and forces, reading pos and writing the new positions to pos_next (another
@@ -244,10 +245,11 @@ hipError_t launch_finish_step(Ctx& c, const float* pos, float* vel, float* force
                               bool energy, const StepGates* next = nullptr,
                               float* pos_next = nullptr);
 // Rigid water: SHAKE after the drift (x_old: positions before it) with the
-// velocity correction, wrap, slot refresh and validity tests; RATTLE velocity
-// projection after the closing kick.
-hipError_t launch_rigid_positions(Ctx& c, const float* x_old, float* pos, float* vel, float dt,
-                                  const StepGates& g);
+// velocity correction, wrap, slot refresh and validity tests (x_old: positions
+// before the drift, y_in: after it, pos: output, which may be x_old or y_in);
+// RATTLE velocity projection after the closing kick.
+hipError_t launch_rigid_positions(Ctx& c, const float* x_old, const float* y_in, float* pos,
+                                  float* vel, float dt, const StepGates& g);
 hipError_t launch_rigid_velocities(Ctx& c, const float* pos, float* vel);
 // Spread + FFT passes only (the potential grid), for the fused closing kernel.
 // `done` (may be null) is recorded by the last kernel's own dispatch.

@@ -793,15 +793,23 @@ int mdx_integrate_step(mdx_ctx* x, float* pos, float* vel, float* force, int32_t
   // pos_alt, alternating); the last positions are copied back if needed.
   float* pos_cur = pos;
   float* pos_other = c.pos_alt;
-  // Rigid water: every step opens with its own kernel, in place, followed by
-  // the position constraints (pos_alt holds the positions before the drift),
-  // and closes with the velocity projection.
+  // Rigid water: every step opens with its own kernel, followed by the
+  // position constraints, and closes with the velocity projection. When every
+  // atom belongs to a rigid molecule the drift writes pos_alt and the
+  // constraint kernel writes every position back to pos; otherwise pos_alt
+  // keeps a copy of the positions before the drift, which happens in place.
   const bool rigid = c.n_rigid > 0;
+  const bool rigid_all = 3 * (size_t)c.n_rigid == (size_t)c.n;   // molecules are disjoint
   auto open_rigid = [&](const mdx::StepGates& gs) -> hipError_t {
+    if (rigid_all) {
+      hipError_t err = mdx::launch_begin_step(c, pos, vel, force, dt, gs, c.pos_alt);
+      if (err == hipSuccess) err = mdx::launch_rigid_positions(c, pos, c.pos_alt, pos, vel, dt, gs);
+      return err;
+    }
     hipError_t err = hipMemcpyAsync(c.pos_alt, pos, sizeof(float) * 3 * (size_t)c.n,
                                     hipMemcpyDeviceToDevice, c.stream);
     if (err == hipSuccess) err = mdx::launch_begin_step(c, pos, vel, force, dt, gs);
-    if (err == hipSuccess) err = mdx::launch_rigid_positions(c, c.pos_alt, pos, vel, dt, gs);
+    if (err == hipSuccess) err = mdx::launch_rigid_positions(c, c.pos_alt, pos, pos, vel, dt, gs);
     return err;
   };
   mdx::StepGates g = gates_of(c.steps_taken);

@@ -16,10 +16,11 @@ D_OH = W["bond_r0"]
 D_HH = 2.0 * D_OH * math.sin(math.radians(W["angle_theta0_deg"]) / 2.0)
 
 
-def rigid_rf_water(name, coulomb="rf"):
+def rigid_rf_water(name, coulomb="rf", flexible_terms=False):
     s = synth.config_system(name)
-    s.bond_k[:] = 0.0
-    s.angle_k[:] = 0.0
+    if not flexible_terms:
+        s.bond_k[:] = 0.0
+        s.angle_k[:] = 0.0
     if coulomb == "rf":
         s.rf_epsilon, s.ewald_delta, s.pme_grid = math.inf, 0.0, (0, 0, 0)
     mols = np.arange(s.n_atoms, dtype=np.int32).reshape(-1, 3)
@@ -42,16 +43,21 @@ def _dev(a, b, box):
     return float(np.sqrt((d * d).mean()))
 
 
-@pytest.mark.parametrize("coulomb", ["rf", "pme"])
-def test_rigid_water_tracks_the_rattle_oracle(coulomb):
-    # with PME the intramolecular pairs carry the Ewald exclusion correction
+@pytest.mark.parametrize("coulomb,part", [("rf", False), ("pme", False), ("rf", True)])
+def test_rigid_water_tracks_the_rattle_oracle(coulomb, part):
+    # with PME the intramolecular pairs carry the Ewald exclusion correction;
+    # part: only every other molecule rigid, the others flexible (bond and
+    # angle terms on, dt = 0.5 fs), which takes the library's other opening
+    # path (positions before the drift copied aside)
     import torch
-    s, mols = rigid_rf_water("water375", coulomb)
+    s, mols = rigid_rf_water("water375", coulomb, flexible_terms=part)
+    if part:
+        mols = mols[::2].copy()
     # start from velocities that already satisfy the constraints (the library
     # projects after each closing kick, the oracle also before the first step)
     s.vel = constraints.rattle_velocities(s.pos, s.vel, s.mass, s.box, mols).astype(np.float32)
-    n_steps, dt = 30, 2.0
-    announce(f"rigid water375 ({coulomb}) 30 steps at 2 fs")
+    n_steps, dt = (40, 0.5) if part else (30, 2.0)
+    announce(f"rigid water375 ({coulomb}, part={part}) {n_steps} steps at {dt} fs")
     with gpu_context(s) as (mdx, ctx, t):
         mdx.build_neighbors(ctx, t["pos"])
         mdx.compute_nonbonded(ctx, t["pos"], t["force"])
