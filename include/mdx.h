@@ -343,8 +343,10 @@ int mdx_set_langevin(mdx_ctx* ctx, double kT, double gamma, uint64_t seed);
  * previous bond vectors (float32, to a relative 2e-6 in r^2) with the same
  * correction over dt applied to the velocities, and after the closing kick
  * the velocities are projected onto the constraints (r . v_rel = 0). The
- * bond and angle terms of these molecules should be zero (their energy is
- * constant). Every step then runs its own opening kernel (no fused
+ * bond and angle terms of these molecules may stay on (their energy is then
+ * constant) or be zero; atoms in no listed molecule move freely (the step
+ * then keeps a copy of the positions before the drift in a buffer of the
+ * context). Every step then runs its own opening kernel (no fused
  * closing/opening), and the kinetic energy slot is taken before the velocity
  * projection. n_mol = 0 switches it off. MDX_E_INVALID for bad indices or
  * distances; MDX_E_UNSUPPORTED together with Langevin or MDX_OPT_KAHAN_VV.
