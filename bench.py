@@ -84,12 +84,15 @@ def pair_counts():
         return json.load(f)[WORKLOAD]
 
 
-def temperature(sys_, vel):
-    """Instantaneous temperature from the device velocities (3N degrees of freedom)."""
+def temperature(sys_, vel, n_rigid=0):
+    """Instantaneous temperature from the device velocities: 3N degrees of
+    freedom, less three per rigid molecule and three for the conserved
+    momentum when molecules are rigid."""
     import torch
     m = torch.from_numpy(sys_.mass.astype("float64")).to(vel.device)
     ke = 0.5 * float((m[None, :] * vel.double() ** 2).sum()) / float(sys_.accel)
-    return 2.0 * ke / (3 * sys_.n_atoms * float(sys_.boltzmann))
+    dof = 3 * sys_.n_atoms - (3 * n_rigid + 3 if n_rigid else 0)
+    return 2.0 * ke / (dof * float(sys_.boltzmann))
 
 
 def cpu_baseline(sys_):
@@ -173,7 +176,7 @@ def sweep(args):
             if method == "pme" and K == 0:
                 continue
             s = base.copy()
-            dt, gamma = float(s.dt), 0.0
+            dt, gamma, n_rigid = float(s.dt), 0.0, 0
             if method != "pme":
                 s.rf_epsilon, s.ewald_delta, s.pme_grid = 78.5, 0.0, (0, 0, 0)
             if method == "rf_langevin_paper":
@@ -194,11 +197,12 @@ def sweep(args):
                 w = synth.systems.WATER
                 d_oh = float(w["bond_r0"])
                 d_hh = 2.0 * d_oh * math.sin(math.radians(w["angle_theta0_deg"]) / 2.0)
+                n_rigid = s.n_atoms // 3
                 mdx.set_rigid_water(ctx, np.arange(s.n_atoms, dtype=np.int32).reshape(-1, 3),
                                     d_oh, d_hh)
             for _ in range(10):
                 mdx.integrate_step(ctx, pos, vel, force, 100, dt)
-                vel.mul_((300.0 / temperature(s, vel)) ** 0.5)
+                vel.mul_((300.0 / temperature(s, vel, n_rigid)) ** 0.5)
             if gamma > 0:
                 mdx.set_langevin(ctx, float(s.boltzmann) * 300.0, gamma, 2025)
             mdx.integrate_step(ctx, pos, vel, force, args.warmup, dt)
@@ -213,7 +217,7 @@ def sweep(args):
             ms = start.elapsed_time(stop) / args.steps
             builds = mdx.get_info(ctx).n_builds - b0
             flags = mdx.get_status(ctx)
-            t_end = temperature(s, vel)
+            t_end = temperature(s, vel, n_rigid)
             mdx.destroy(ctx)
             print(json.dumps({"sweep": "time_per_step_vs_n", "protocol": method,
                               "n_atoms": s.n_atoms, "box_A": round(L, 2),
