@@ -5,8 +5,10 @@ kernels of libmdx.so. Device buffers are passed as raw addresses (for torch
 tensors, ``t.data_ptr()``), streams as ``hipStream_t`` handles
 (``torch.cuda.current_stream().cuda_stream``).
 
-Importing this package loads libmdx.so from the package directory and raises
-ImportError if it is missing (build it with ``python -m paper_2503_20541_amd.build``).
+Importing this module loads libmdx.so from the package directory. When the
+library is missing or older than any of its sources it is built first with
+hipcc (``build.ensure_built``); if that fails the import raises ImportError.
+There is no fallback path.
 """
 from __future__ import annotations
 
@@ -18,8 +20,12 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmdx.so")
 
-if not os.path.exists(LIB_PATH):
-    raise ImportError(f"libmdx.so not found at {LIB_PATH}; run `python -m paper_2503_20541_amd.build`")
+from . import build as _build
+
+try:
+    _build.ensure_built()
+except Exception as exc:          # no hipcc, or the sources do not compile
+    raise ImportError(f"libmdx.so could not be built at {LIB_PATH}: {exc}") from exc
 _lib = ctypes.CDLL(LIB_PATH)
 
 # ---- constants mirrored from mdx.h ------------------------------------------
@@ -39,6 +45,7 @@ MDX_FLAG_NONFINITE = 0x4
 MDX_FLAG_OUT_OF_BOX = 0x8
 MDX_FLAG_CELL_OVERFLOW = 0x10
 MDX_FLAG_COLUMN_OVERFLOW = 0x20
+MDX_FLAG_CONSTRAINT = 0x40
 
 MDX_ENERGY_LJ = 0
 MDX_ENERGY_COUL_DIR = 1
@@ -62,7 +69,8 @@ EXPORTED = ("mdx_error_string", "mdx_create", "mdx_destroy", "mdx_set_stream",
             "mdx_build_neighbors", "mdx_get_neighbor_pairs", "mdx_compute_nonbonded",
             "mdx_compute_pme", "mdx_integrate_step", "mdx_get_status", "mdx_get_info",
             "mdx_set_timing", "mdx_get_timing", "mdx_get_images", "mdx_set_langevin",
-            "mdx_compute_ewald_direct", "mdx_set_rigid_water")
+            "mdx_compute_ewald_direct", "mdx_set_rigid_water", "mdx_state_size",
+            "mdx_save_state", "mdx_load_state")
 
 _fp = ctypes.POINTER(ctypes.c_float)
 _ip = ctypes.POINTER(ctypes.c_int32)
@@ -116,6 +124,9 @@ _lib.mdx_set_langevin.argtypes = [_vp, ctypes.c_double, ctypes.c_double, ctypes.
 _lib.mdx_compute_ewald_direct.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int32]
 _lib.mdx_set_rigid_water.argtypes = [_vp, _vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double]
 _lib.mdx_get_info.argtypes = [_vp, ctypes.POINTER(Info)]
+_lib.mdx_state_size.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64)]
+_lib.mdx_save_state.argtypes = [_vp, _vp, ctypes.c_int64]
+_lib.mdx_load_state.argtypes = [_vp, _vp, ctypes.c_int64]
 _lib.mdx_set_timing.argtypes = [_vp, ctypes.c_int]
 _lib.mdx_get_timing.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                 ctypes.POINTER(ctypes.c_int64)]
@@ -303,6 +314,23 @@ def set_langevin(ctx: int, kT: float, gamma: float, seed: int) -> None:
 def get_images(ctx: int, img) -> None:
     """Copies the image counters (int32 [3][N] device tensor) into img."""
     _check(_lib.mdx_get_images(ctx, _ptr(img)), "mdx_get_images")
+
+
+def state_size(ctx: int) -> int:
+    n = ctypes.c_int64(0)
+    _check(_lib.mdx_state_size(ctx, ctypes.byref(n)), "mdx_state_size")
+    return int(n.value)
+
+
+def save_state(ctx: int, state, capacity: int | None = None) -> None:
+    """Writes the context's state into a device buffer (e.g. a uint8 tensor)."""
+    cap = capacity if capacity is not None else state.numel() * state.element_size()
+    _check(_lib.mdx_save_state(ctx, _ptr(state), int(cap)), "mdx_save_state")
+
+
+def load_state(ctx: int, state, size: int | None = None) -> None:
+    size = size if size is not None else state.numel() * state.element_size()
+    _check(_lib.mdx_load_state(ctx, _ptr(state), int(size)), "mdx_load_state")
 
 
 def get_info(ctx: int) -> Info:

@@ -78,3 +78,39 @@ def test_desc_marshalling_roundtrip():
     assert d.charge[5] == pytest.approx(float(s.charge[5]))
     assert d.exclusions[1] == s.exclusions[0, 1]
     assert np.isclose(d.r_cut, float(s.r_cut))
+
+
+@pytest.mark.skipif(shutil.which("hipcc") is None and not os.path.exists("/opt/rocm/bin/hipcc"),
+                    reason="needs hipcc")
+def test_fresh_checkout_builds_library_on_import(tmp_path):
+    """A tree without libmdx.so (a fresh clone) builds it on first import."""
+    pkg = "paper_2503_20541_amd"
+    shutil.copytree(os.path.join(ROOT, pkg), tmp_path / pkg,
+                    ignore=shutil.ignore_patterns("*.so", "_build", "__pycache__", ".libmdx.lock"))
+    shutil.copytree(os.path.join(ROOT, "include"), tmp_path / "include")
+    assert not (tmp_path / pkg / "libmdx.so").exists()
+    code = ("import paper_2503_20541_amd as m; lib = m.library(); "
+            "print(lib._name); [getattr(lib, n) for n in m.EXPORTED]")
+    res = subprocess.run(["python", "-c", code], cwd=tmp_path, capture_output=True,
+                         text=True, timeout=600)
+    assert res.returncode == 0, res.stdout + res.stderr
+    assert res.stdout.strip().endswith(os.path.join(str(tmp_path), pkg, "libmdx.so"))
+    assert (tmp_path / pkg / "libmdx.so").exists()
+
+
+def test_stale_library_is_detected(tmp_path, monkeypatch):
+    """A source newer than the built library marks it stale."""
+    from paper_2503_20541_amd import build
+    lib = tmp_path / "libmdx.so"
+    src = tmp_path / "k.hip"
+    src.write_text("//")
+    lib.write_text("")
+    os.utime(lib, (1000, 1000))
+    os.utime(src, (2000, 2000))
+    monkeypatch.setattr(build, "LIB", str(lib))
+    monkeypatch.setattr(build, "_inputs", lambda: [str(src)])
+    assert build.is_stale()
+    os.utime(lib, (3000, 3000))
+    assert not build.is_stale()
+    lib.unlink()
+    assert build.is_stale()

@@ -191,3 +191,35 @@ def test_spme_virial_diagonal_per_axis():
         Em = pme.spme(pos * sc[:, None], s.charge, box * sc, s.pme_grid, a, s.coulomb_k)["E"]
         assert W[ax, ax] == pytest.approx(-(Ep - Em) / (2 * h), rel=1e-7, abs=1e-8 * abs(W).max())
     assert np.allclose(W, W.T, rtol=0, atol=1e-12 * np.abs(W).max())
+
+
+def test_self_energy_madelung_and_net_charge_alpha_invariance():
+    """nonbonded.self_energy (Eq. 12 plus the neutralising background for a
+    net charge Q): the NaCl Madelung energy through it, and the Ewald total of a
+    net-charged box independent of alpha (the remark after Eq. 12) only with the
+    background term -pi Q^2 / (2 V alpha^2)."""
+    g = json.load(open(os.path.join(GOLD, "madelung_nacl.json")))
+    pos, q, box = _nacl()
+    a = box[0]
+    alpha = 0.8
+    Er, _ = ewald.real_images(pos, q, box, alpha, 1.0, r_max=8.0 / alpha)
+    Ek, _ = ewald.reciprocal_direct(pos, q, box, alpha, 1.0, n_max=int(3 * alpha * a) + 3)
+    Es = nonbonded.self_energy(q, box, alpha, 1.0)
+    assert Er + Ek + Es == pytest.approx(-4.0 * g["madelung"] / (a / 2), rel=1e-10)
+
+    rng = np.random.default_rng(7)
+    box = np.array([6.0, 6.5, 7.0])
+    pos = rng.uniform(0.0, 1.0, (3, 5)) * box[:, None]
+    q = np.array([1.0, -0.4, 0.9, 0.5, -0.7])          # Q = +1.3
+    k_e = 332.0637
+    tot, tot_without_net = [], []
+    for alpha in (0.5, 0.7, 0.9):
+        Er, _ = ewald.real_images(pos, q, box, alpha, k_e, r_max=8.0 / alpha)
+        Ek, _ = ewald.reciprocal_direct(pos, q, box, alpha, k_e,
+                                        n_max=int(3 * alpha * box.max()) + 3)
+        Es = nonbonded.self_energy(q, box, alpha, k_e)
+        tot.append(Er + Ek + Es)
+        tot_without_net.append(Er + Ek + ewald.self_term(q, alpha, k_e))
+    assert max(tot) - min(tot) < 1e-10 * abs(tot[0])
+    # the background term is what removes the alpha dependence here
+    assert max(tot_without_net) - min(tot_without_net) > 1e-2 * abs(tot[0])
