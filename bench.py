@@ -45,6 +45,15 @@ VALU_PEAK_T = 256 * 64 * 2.4e9 / 1e12
 # (profiles/pair_kernel_counters_water96k.md); set to None when the kernel
 # changes until the counters are taken again.
 PAIR_TRAFFIC_BYTES = 67.8e6
+PAIR_TRAFFIC_COMMIT = "c4f7bd9"     # the commit whose k_pair the counters measured
+# Whole-step floors of the 96,000-atom water step (the method's compulsory
+# work per step: 199 MB of HBM traffic -- fused integrate 6.1 MB, pair kernel
+# per-atom I/O plus a 4-byte-per-pair Verlet list 118 MB, PME 56 MB, list
+# build amortised over 10 steps 12 MB -- and 1.2e9 FP32 VALU lane operations):
+# 24.9 us at 8 TB/s, 30.5 us at the non-packed VALU issue rate.
+STEP_HBM_BYTES = 199e6
+STEP_VALU_OPS = 1.2e9
+HBM_PEAK_BPS = 8.0e12
 
 
 def parse():
@@ -95,37 +104,107 @@ def temperature(sys_, vel, n_rigid=0):
     return 2.0 * ke / (dof * float(sys_.boltzmann))
 
 
-def cpu_baseline(sys_):
-    """The oracle, untuned, on a bounded sample of the same workload: one list
-    build and two full force evaluations (nonbonded + SPME) with their
-    velocity-Verlet updates of the 96,000-atom box, single thread. Per-step
-    time counts the list build once per 10 steps (the workload's rebuild
-    cadence)."""
-    import numpy as np
-    from oracle import forcefield
+_POOL_SYS = None      # the system the pool's workers sum pair terms of (fork start)
 
-    reps = 2
+
+def _pair_chunk(bounds):
+    """Interaction test and pair terms of one slice of the listed pairs (pool
+    worker)."""
+    import numpy as np
+    from oracle import forcefield, neighbors, nonbonded
+    s, pairs = _POOL_SYS
+    lo, hi = bounds
+    chunk = pairs[lo:hi]
+    inter = chunk[neighbors.interacting(s.pos, s.box, s.r_cut, s.r_ghost, chunk)]
+    pt = nonbonded.pair_terms(s.pos.astype(np.float64), s.box, inter, s.atom_type,
+                              s.type_sigma, s.type_epsilon, s.charge, forcefield.alpha(s),
+                              s.coulomb_k, r_cut=float(s.r_cut), switch_r=float(s.switch_r))
+    return pt["F"], len(inter)
+
+
+def _oracle_step_seconds(sys_, reps, cores):
+    """The untuned oracle: one list build (amortised over the rebuild cadence)
+    and `reps` force evaluations (nonbonded + SPME when the system has a grid)
+    with their velocity-Verlet updates. cores > 1: the pair sum, which
+    dominates, is split into `cores` slices of the interacting pairs summed by
+    a process pool; the rest stays in one process."""
+    import multiprocessing as mp
+    import numpy as np
+    from oracle import forcefield, neighbors
+
+    global _POOL_SYS
     t0 = time.perf_counter()
     pairs = forcefield.neighbor_list(sys_)
+    t_list = time.perf_counter() - t0
+    n_int = 0
+    pool = None
+    if cores > 1:     # pool start-up is not timed
+        _POOL_SYS = (sys_, pairs)
+        pool = mp.get_context("fork").Pool(cores)
+        edges = np.linspace(0, len(pairs), cores + 1).astype(int)
+        chunks = list(zip(edges[:-1], edges[1:]))
     t1 = time.perf_counter()
-    for _ in range(reps):
-        nb = forcefield.nonbonded_terms(sys_, pairs=pairs)
-        rec = forcefield.pme_terms(sys_)
-        F = nb["F"] + rec["F"]
-        x = sys_.pos.astype(np.float64)
-        v = sys_.vel.astype(np.float64)
-        m = sys_.mass.astype(np.float64)
-        v = v + 0.5 * sys_.dt * sys_.accel * F / m[None, :]
-        x = x + sys_.dt * v
+    try:
+        for _ in range(reps):
+            if pool is None:
+                nb = forcefield.nonbonded_terms(sys_, pairs=pairs)
+                F = nb["F"]
+                n_int = nb["n_interacting"]
+            else:
+                # the pair terms in the pool, the exclusion, bonded and self
+                # terms through the oracle with an empty pair list
+                parts = pool.map(_pair_chunk, chunks)
+                nb = forcefield.nonbonded_terms(sys_, pairs=pairs[:0])
+                F = nb["F"] + sum(p[0] for p in parts)
+                n_int = sum(p[1] for p in parts)
+            if sum(sys_.pme_grid) > 0:
+                F = F + forcefield.pme_terms(sys_)["F"]
+            x = sys_.pos.astype(np.float64)
+            v = sys_.vel.astype(np.float64)
+            m = sys_.mass.astype(np.float64)
+            v = v + 0.5 * sys_.dt * sys_.accel * F / m[None, :]
+            x = x + sys_.dt * v
+    finally:
+        if pool is not None:
+            pool.close()
+            pool.join()
+        _POOL_SYS = None
     t2 = time.perf_counter()
-    t_step = (t1 - t0) / sys_.rebuild_every + (t2 - t1) / reps
-    ns_day = 0.0864 * sys_.dt / t_step
-    return dict(value=ns_day, unit="ns/day", cores=1, kind="oracle",
-                sample=("one list build + two nonbonded+SPME force evaluations with VV updates "
-                        "of the 96,000-atom water box's initial state (list build amortised "
-                        f"over 10 steps); {t2 - t0:.1f} s of CPU work"),
-                seconds_per_step=t_step,
-                pair_interactions_per_s=nb["n_interacting"] / t_step)
+    t_step = t_list / sys_.rebuild_every + (t2 - t1) / reps
+    return t_step, n_int, t_list + (t2 - t1)
+
+
+def cpu_baseline(sys_, names=("lj1k", "water9k")):
+    """The oracle on a bounded sample of the workload, on 1 core (the headline
+    value: NumPy element-wise work is single-threaded) and on all the host's
+    cores (pair sum in a process pool), for the 96,000-atom box and the two
+    smaller configurations."""
+    import synth
+    cores_all = max(1, min(len(os.sched_getaffinity(0)), 16))
+    t1c, n_int, cpu_s = _oracle_step_seconds(sys_, 2, 1)
+    tall, _, cpu_all = _oracle_step_seconds(sys_, 2, cores_all)
+    out = dict(value=0.0864 * sys_.dt / t1c, unit="ns/day", cores=1, kind="oracle",
+               sample=("one list build + two nonbonded+SPME force evaluations with VV updates "
+                       "of the 96,000-atom water box's initial state (list build amortised "
+                       f"over 10 steps); {cpu_s:.1f} s of CPU work"),
+               seconds_per_step=t1c, pair_interactions_per_s=n_int / t1c,
+               host_cores=len(os.sched_getaffinity(0)),
+               all_cores={"cores": cores_all, "value": 0.0864 * sys_.dt / tall,
+                          "seconds_per_step": tall, "pair_interactions_per_s": n_int / tall,
+                          "wall_s": round(cpu_all, 1)},
+               by_workload={})
+    for name in names:
+        s = synth.config_system(name)
+        reps = 5 if s.n_atoms < 5000 else 2
+        row = {}
+        for cores in (1, cores_all):
+            t, n, _ = _oracle_step_seconds(s, reps, cores)
+            unit = "steps/s" if name == "lj1k" else "ns/day"
+            val = 1.0 / t if name == "lj1k" else 0.0864 * s.dt / t
+            row[f"cores_{cores}"] = {"value": val, "unit": unit, "seconds_per_step": t,
+                                     "pair_interactions_per_s": n / t}
+        out["by_workload"][name] = row
+    return out
 
 
 def copy_probe(mib):
@@ -376,8 +455,15 @@ def main():
         ops = (OPS_PER_INTERACTING * counts["interacting_pairs"]
                + OPS_PER_LISTED_ONLY * (counts["listed_pairs"] - counts["interacting_pairs"]))
         achieved = ops / (pair_ms * 1e-3) / 1e12
+        t_hbm = STEP_HBM_BYTES / HBM_PEAK_BPS
+        t_valu = STEP_VALU_OPS / (VALU_PEAK_T * 1e12)
         result.update({
             "value": round(ns_day, 3), "ms_per_step": round(ms_step, 5),
+            # step time against the step's floors (compulsory HBM bytes; the
+            # larger of the HBM and VALU floors)
+            "hbm_frac_step": round(t_hbm / (ms_step * 1e-3), 4),
+            "binding_roof_frac_step": round(max(t_hbm, t_valu) / (ms_step * 1e-3), 4),
+            "step_floor_us": {"hbm": round(t_hbm * 1e6, 2), "valu": round(t_valu * 1e6, 2)},
             "pair_interactions_per_s": counts["interacting_pairs"] * steps_per_s,
             "status_flags": flags, "finite": ok,
             "equilibration_steps": args.equilibrate,
@@ -388,6 +474,7 @@ def main():
             "roofline": {"bound": "alu", "achieved": round(achieved, 3),
                          "peak": round(VALU_PEAK_T, 2), "unit": "TFLOP/s",
                          "frac": round(achieved / VALU_PEAK_T, 4), "traffic": PAIR_TRAFFIC_BYTES,
+                         "traffic_measured_on": PAIR_TRAFFIC_COMMIT,
                          "kernel": "k_pair", "launches": pair_n,
                          "per_unit": f"{OPS_PER_INTERACTING:g} FP32 VALU ops per interacting "
                                      f"pair + {OPS_PER_LISTED_ONLY:g} per listed pair beyond r_c; "

@@ -63,6 +63,10 @@ extern "C" {
                                           mdx_integrate_step the atoms left out
                                           are not integrated: results invalid,
                                           call mdx_build_neighbors)           */
+#define MDX_FLAG_CONSTRAINT   0x40u /* rigid water: SHAKE did not reach its
+                                       tolerance in 200 sweeps, or a molecule's
+                                       RATTLE system was singular (positions
+                                       or velocities of that molecule invalid) */
 
 /* ---- energy slots (FP64) ----------------------------------------------- */
 #define MDX_ENERGY_LJ         0  /* Eq. 4 (switched by Eq. 6 if enabled)        */
@@ -347,9 +351,12 @@ int mdx_set_langevin(mdx_ctx* ctx, double kT, double gamma, uint64_t seed);
  * constant) or be zero; atoms in no listed molecule move freely (the step
  * then keeps a copy of the positions before the drift in a buffer of the
  * context). Every step then runs its own opening kernel (no fused
- * closing/opening), and the kinetic energy slot is taken before the velocity
- * projection. n_mol = 0 switches it off. MDX_E_INVALID for bad indices or
- * distances; MDX_E_UNSUPPORTED together with Langevin or MDX_OPT_KAHAN_VV.
+ * closing/opening), and the kinetic energy slot holds the kinetic energy
+ * of the projected velocities. A molecule whose SHAKE iteration does not
+ * reach its tolerance in 200 sweeps, or whose velocity system is singular,
+ * latches MDX_FLAG_CONSTRAINT. n_mol = 0 switches it off. MDX_E_INVALID for
+ * bad indices or distances; MDX_E_UNSUPPORTED together with Langevin or
+ * MDX_OPT_KAHAN_VV.
  */
 int mdx_set_rigid_water(mdx_ctx* ctx, const int32_t* mols, int32_t n_mol, double d_oh,
                         double d_hh);
@@ -357,6 +364,37 @@ int mdx_set_rigid_water(mdx_ctx* ctx, const int32_t* mols, int32_t n_mol, double
 /* Fills *info (host). Synchronising once a list exists: the list is copied
  * to the host to count its entries. */
 int mdx_get_info(mdx_ctx* ctx, mdx_info* info);
+
+/*
+ * Checkpoint and resume of a trajectory (the paper's simulation object keeps
+ * its state between step calls, Sec. II.D; these calls make that state
+ * portable). Everything mdx_integrate_step carries from one step to the next
+ * besides the caller's position, velocity and force arrays:
+ *   - the step counter (it keys the Langevin noise) and the number of steps
+ *     since the last list build (the rebuild cadence),
+ *   - the periodic image counters,
+ *   - the neighbour list as built (slot order, cluster boxes, tiles, the
+ *     build positions) and the pruned list with the positions it was made at,
+ *   - the rebuild and prune gates, the Kahan compensation terms
+ *     (MDX_OPT_KAHAN_VV).
+ * The latched status flags, timing records and configuration calls
+ * (mdx_set_langevin, mdx_set_rigid_water) are not part of it.
+ *
+ * mdx_state_size: *bytes (host) receives the size of the state as it stands
+ * (it grows when the list capacity grows).
+ * mdx_save_state: writes it into state (dev, caller-owned, `capacity` bytes,
+ * 8-byte aligned). MDX_E_CAPACITY if capacity < mdx_state_size.
+ * mdx_load_state: reads a state written by mdx_save_state of a context made
+ * from the same descriptor (atom count, box, cutoffs, PME grid, options);
+ * the list capacities are grown or shrunk to the saved ones. MDX_E_INVALID if
+ * the buffer is not such a state or `size` is short of it. After loading,
+ * mdx_integrate_step from the saved positions, velocities and forces repeats
+ * bit for bit the steps the saving context took next.
+ * All three are synchronising.
+ */
+int mdx_state_size(mdx_ctx* ctx, int64_t* bytes);
+int mdx_save_state(mdx_ctx* ctx, void* state, int64_t capacity);
+int mdx_load_state(mdx_ctx* ctx, const void* state, int64_t size);
 
 /* ---- diagnostics ---------------------------------------------------------
  * Kernel timing with HIP events recorded around the launches of a kernel

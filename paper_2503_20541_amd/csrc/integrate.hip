@@ -327,9 +327,15 @@ __global__ void __launch_bounds__(64) k_rigid_positions(RigidArgs r, OpenStep o,
                                                         const float* __restrict__ y_in,
                                                         float* pos,
                                                          float* __restrict__ vel,
-                                                         const int* __restrict__ inv_perm) {
+                                                         const int* __restrict__ inv_perm,
+                                                         unsigned* __restrict__ flags) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= r.n_mol) return;
+  // a molecule with an atom that a full column left out of the list was not
+  // drifted: it is left as it is (the build latched MDX_FLAG_COLUMN_OVERFLOW)
+  if (inv_perm[r.mols[3 * m]] < 0 || inv_perm[r.mols[3 * m + 1]] < 0 ||
+      inv_perm[r.mols[3 * m + 2]] < 0)
+    return;
   const int n = o.n;
   const CellGrid& cg = o.cg;
   int at[3];
@@ -353,8 +359,9 @@ __global__ void __launch_bounds__(64) k_rigid_positions(RigidArgs r, OpenStep o,
   // The iteration moves the displacements dl (small numbers) rather than the
   // coordinates: the velocity correction dl/dt then carries no cancellation
   // between two coordinates of the size of the box.
+  float worst = 0.f;
   for (int it = 0; it < 200; ++it) {
-    float worst = 0.f;
+    worst = 0.f;
     for (int c = 0; c < 3; ++c) {
       const int a = ca[c], b = cb[c];
       const float3 d = make_float3(d0[c].x + (dl[a].x - dl[b].x), d0[c].y + (dl[a].y - dl[b].y),
@@ -375,6 +382,7 @@ __global__ void __launch_bounds__(64) k_rigid_positions(RigidArgs r, OpenStep o,
     // |d|^2 (a few 1e-7), so every molecule stops after a few sweeps
     if (worst < 2e-6f) break;
   }
+  if (!(worst < 2e-6f)) atomicOr(flags, MDX_FLAG_CONSTRAINT);   // also for a NaN
   for (int k = 0; k < 3; ++k) {
     const int a = at[k];
     const float inv_dt = 1.0f / o.dt;
@@ -393,11 +401,21 @@ __global__ void __launch_bounds__(64) k_rigid_positions(RigidArgs r, OpenStep o,
   }
 }
 
+// ENERGY: the kinetic energy change of the projection, FP64, one partial per
+// block (the closing kernel took the kinetic energy before it).
+template <bool ENERGY>
 __global__ void __launch_bounds__(64) k_rigid_velocities(RigidArgs r, CellGrid cg, int n,
                                                           const float* __restrict__ pos,
-                                                          float* __restrict__ vel) {
+                                                          float* __restrict__ vel,
+                                                          const float* __restrict__ mass,
+                                                          double inv_2acc,
+                                                          double* __restrict__ partials,
+                                                          int pstride,
+                                                          unsigned* __restrict__ flags) {
+  __shared__ double red[16];
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= r.n_mol) return;
+  double dke = 0.0;
+  if (m < r.n_mol) {
   int at[3];
   float3 v[3];
   float iw[3];
@@ -431,6 +449,7 @@ __global__ void __launch_bounds__(64) k_rigid_velocities(RigidArgs r, CellGrid c
   const double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
                      A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
                      A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+  if (!(det != 0.0) || !isfinite(det)) atomicOr(flags, MDX_FLAG_CONSTRAINT);
   double mu[3];
   for (int c = 0; c < 3; ++c) {
     double B[3][3];
@@ -450,9 +469,21 @@ __global__ void __launch_bounds__(64) k_rigid_velocities(RigidArgs r, CellGrid c
     v[b].z -= (float)(mu[c] * rc[c].z * iw[b]);
   }
   for (int k = 0; k < 3; ++k) {
-    vel[at[k]] = v[k].x;
-    vel[n + at[k]] = v[k].y;
-    vel[2 * n + at[k]] = v[k].z;
+    const int a = at[k];
+    if (ENERGY) {
+      const double v0x = vel[a], v0y = vel[n + a], v0z = vel[2 * n + a];
+      dke += (double)mass[a] *
+             (((double)v[k].x * v[k].x + (double)v[k].y * v[k].y + (double)v[k].z * v[k].z) -
+              (v0x * v0x + v0y * v0y + v0z * v0z)) * inv_2acc;
+    }
+    vel[a] = v[k].x;
+    vel[n + a] = v[k].y;
+    vel[2 * n + a] = v[k].z;
+  }
+  }
+  if (ENERGY) {
+    const double sb = block_sum(dke, red);
+    if (threadIdx.x == 0) partials[kRowKinRigid * pstride + blockIdx.x] = sb;
   }
 }
 
@@ -461,13 +492,24 @@ hipError_t launch_rigid_positions(Ctx& c, const float* x_old, const float* y_in,
   RigidArgs r{c.rigid_mols, c.n_rigid, {c.rigid_d[0], c.rigid_d[1], c.rigid_d[2]}, c.hdt_scale};
   // 64-lane groups: one molecule per lane, and enough groups to reach every CU
   k_rigid_positions<<<(c.n_rigid + 63) / 64, 64, 0, c.stream>>>(r, make_open(c, pos, pos, dt, g),
-                                                                x_old, y_in, pos, vel, c.inv_perm);
+                                                                x_old, y_in, pos, vel, c.inv_perm,
+                                                                c.flags);
   return hipGetLastError();
 }
 
-hipError_t launch_rigid_velocities(Ctx& c, const float* pos, float* vel) {
+hipError_t launch_rigid_velocities(Ctx& c, const float* pos, float* vel, bool energy,
+                                   int* blocks) {
   RigidArgs r{c.rigid_mols, c.n_rigid, {c.rigid_d[0], c.rigid_d[1], c.rigid_d[2]}, c.hdt_scale};
-  k_rigid_velocities<<<(c.n_rigid + 63) / 64, 64, 0, c.stream>>>(r, c.cg, c.n, pos, vel);
+  const int nb = (c.n_rigid + 63) / 64;
+  if (blocks) *blocks = nb;
+  if (energy && nb > c.max_blocks) return hipErrorInvalidValue;   // partial rows too short
+  const double inv_2acc = 0.5 / c.accel;
+  if (energy)
+    k_rigid_velocities<true><<<nb, 64, 0, c.stream>>>(r, c.cg, c.n, pos, vel, c.mass, inv_2acc,
+                                                       c.partials, c.max_blocks, c.flags);
+  else
+    k_rigid_velocities<false><<<nb, 64, 0, c.stream>>>(r, c.cg, c.n, pos, vel, c.mass, inv_2acc,
+                                                        c.partials, c.max_blocks, c.flags);
   return hipGetLastError();
 }
 

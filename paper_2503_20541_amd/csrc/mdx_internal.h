@@ -23,6 +23,7 @@ constexpr int kBrickZ = 8;
 // the pair kernel (or of the PME z pass) and of the bonded/exclusion kernel.
 enum PartialRow {
   kRowLJ = 0, kRowDir, kRowExcl, kRowBond, kRowAngle, kRowRec, kRowKin,
+  kRowKinRigid,   // rigid water: kinetic energy change of the velocity projection
   kRowVir, kRowVirB = kRowVir + 6, kRowCount = kRowVirB + 6
 };
 
@@ -216,9 +217,11 @@ hipError_t launch_reduce_virial(Ctx& c, const int* row0, const int* nblk, const 
                                 int nsrc, double* out);
 // Sums the FP64 partial rows into out[slot - slot_base] (slots MDX_ENERGY_*);
 // const_slot >= 0 also stores const_val there, zero_slot >= 0 stores 0.
+// rigid_blocks > 0: the kinetic row also takes the kRowKinRigid partials of
+// that many blocks.
 hipError_t launch_reduce_energy(Ctx& c, const int* rows, const int* nblk, int nrows, double* out,
                                 int slot_base, double const_val, int const_slot,
-                                int zero_slot = -1);
+                                int zero_slot = -1, int rigid_blocks = 0);
 bool pme_size_supported(int K);
 // virial: also the reciprocal-space virial partial rows (kRowVir).
 hipError_t launch_pme(Ctx& c, float* force, bool energy, bool virial = false);
@@ -250,7 +253,10 @@ hipError_t launch_finish_step(Ctx& c, const float* pos, float* vel, float* force
 // RATTLE velocity projection after the closing kick.
 hipError_t launch_rigid_positions(Ctx& c, const float* x_old, const float* y_in, float* pos,
                                   float* vel, float dt, const StepGates& g);
-hipError_t launch_rigid_velocities(Ctx& c, const float* pos, float* vel);
+// energy: also the kinetic energy change of the projection (kRowKinRigid
+// partials, one per 64 molecules; returns the block count in *blocks).
+hipError_t launch_rigid_velocities(Ctx& c, const float* pos, float* vel, bool energy = false,
+                                   int* blocks = nullptr);
 // Spread + FFT passes only (the potential grid), for the fused closing kernel.
 // `done` (may be null) is recorded by the last kernel's own dispatch.
 hipError_t launch_pme_spread(Ctx& c, hipStream_t s, hipEvent_t done);

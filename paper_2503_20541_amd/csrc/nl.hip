@@ -148,8 +148,14 @@ __device__ void bin_atom(const BuildArgs& a, int i) {
   }
   if (active) {
     const int k = atomicAdd(&a.col_count[c], 1);
-    if (k < a.col_cap) a.col_atoms[(size_t)c * a.col_cap + k] = i;
-    else atomicOr(a.flags, MDX_FLAG_COLUMN_OVERFLOW);
+    if (k < a.col_cap) {
+      a.col_atoms[(size_t)c * a.col_cap + k] = i;
+    } else {
+      // left out of this list: no slot (the column sort writes the slots of
+      // the atoms it places only)
+      a.inv_perm[i] = -1;
+      atomicOr(a.flags, MDX_FLAG_COLUMN_OVERFLOW);
+    }
   }
 }
 

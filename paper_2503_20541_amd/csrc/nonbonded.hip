@@ -351,11 +351,16 @@ __global__ void __launch_bounds__(256) k_bonded_excl(const float* __restrict__ p
   double e_ex = 0.0, e_b = 0.0, e_a = 0.0;
   double w[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (a < n) {
-    const int s = inv_perm[a];
-    float fx = fslot[s], fy = fslot[fstride + s], fz = fslot[2 * fstride + s];
-    fslot[s] = 0.f;
-    fslot[fstride + s] = 0.f;
-    fslot[2 * fstride + s] = 0.f;
+    const int s = inv_perm[a];   // -1: an atom a full column left out of the list
+    float fx = 0.f, fy = 0.f, fz = 0.f;
+    if (s >= 0) {
+      fx = fslot[s];
+      fy = fslot[fstride + s];
+      fz = fslot[2 * fstride + s];
+      fslot[s] = 0.f;
+      fslot[fstride + s] = 0.f;
+      fslot[2 * fstride + s] = 0.f;
+    }
     bonded_excl_atom<ENERGY, COUL, VIR>(a, pos, n, bp, tp, fx, fy, fz, e_ex, e_b, e_a, 0, 1, w);
     force[a] = fx;
     force[n + a] = fy;
@@ -388,6 +393,7 @@ struct ReduceSpec {
   int const_slot;      // -1: none
   double const_val;
   int zero_slot;       // -1: none
+  int kin_extra_blocks;   // > 0: the kinetic row also sums kRowKinRigid over these blocks
 };
 
 // One block per requested row: fixed-order sum of its partials.
@@ -401,6 +407,10 @@ __global__ void __launch_bounds__(256) k_reduce_rows(const double* __restrict__ 
     const double* p = partials + (size_t)spec.row[r] * pstride;
     double v = 0.0;
     for (int k = threadIdx.x; k < spec.nblk[r]; k += blockDim.x) v += p[k];
+    if (spec.row[r] == kRowKin && spec.kin_extra_blocks > 0) {
+      const double* pr = partials + (size_t)kRowKinRigid * pstride;
+      for (int k = threadIdx.x; k < spec.kin_extra_blocks; k += blockDim.x) v += pr[k];
+    }
     double s = block_sum(v, red) * spec.scale[r];
     if (threadIdx.x == 0) {
       out[spec.slot[r]] = s;
@@ -576,8 +586,10 @@ hipError_t launch_reduce_virial(Ctx& c, const int* row0, const int* nblk, const 
 }
 
 hipError_t launch_reduce_energy(Ctx& c, const int* rows, const int* nblk, int nrows, double* out,
-                                int slot_base, double const_val, int const_slot, int zero_slot) {
+                                int slot_base, double const_val, int const_slot, int zero_slot,
+                                int rigid_blocks) {
   ReduceSpec spec{};
+  spec.kin_extra_blocks = rigid_blocks;
   spec.nrows = nrows;
   for (int r = 0; r < nrows; ++r) {
     spec.row[r] = rows[r];

@@ -812,6 +812,7 @@ int mdx_integrate_step(mdx_ctx* x, float* pos, float* vel, float* force, int32_t
     if (err == hipSuccess) err = mdx::launch_rigid_positions(c, c.pos_alt, pos, pos, vel, dt, gs);
     return err;
   };
+  int rigid_blocks = 0;   // blocks of the velocity projection's kinetic partials
   mdx::StepGates g = gates_of(c.steps_taken);
   if (rigid) MDX_TRY(open_rigid(g));
   else MDX_TRY(mdx::launch_begin_step(c, pos_cur, vel, force, dt, g));
@@ -848,7 +849,7 @@ int mdx_integrate_step(mdx_ctx* x, float* pos, float* vel, float* force, int32_t
     if (c.has_pme) MDX_TRY(hipStreamWaitEvent(c.stream, x->ev_join, 0));
     if (rigid) {
       MDX_TRY(mdx::launch_finish_step(c, pos_cur, vel, force, dt, e));
-      MDX_TRY(mdx::launch_rigid_velocities(c, pos_cur, vel));
+      MDX_TRY(mdx::launch_rigid_velocities(c, pos_cur, vel, e, &rigid_blocks));
       if (s + 1 < n_steps) {
         g = gates_of(c.steps_taken + 1);
         MDX_TRY(open_rigid(g));
@@ -870,7 +871,8 @@ int mdx_integrate_step(mdx_ctx* x, float* pos, float* vel, float* force, int32_t
       double* out = energies + (size_t)s * MDX_N_ENERGY;
       MDX_TRY(mdx::launch_reduce_energy(c, rows, nblk, nrows, out, 0, c.e_self,
                                         MDX_ENERGY_COUL_SELF,
-                                        c.has_pme ? -1 : MDX_ENERGY_COUL_REC));
+                                        c.has_pme ? -1 : MDX_ENERGY_COUL_REC,
+                                        rigid ? rigid_blocks : 0));
     }
     c.steps_taken++;
   }
@@ -969,6 +971,153 @@ int mdx_get_images(mdx_ctx* x, int32_t* img) {
   Ctx& c = x->c;
   MDX_TRY(hipMemcpyAsync(img, c.img, sizeof(int32_t) * 3 * (size_t)c.n,
                          hipMemcpyDeviceToDevice, c.stream));
+  return MDX_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Layout of a saved state: a header, then the device arrays that a later step
+// reads, each starting at a multiple of 256 bytes.
+constexpr uint64_t kStateMagic = 0x3154535844584d44ull;   // "DMXDXST1"
+constexpr int64_t kStateVersion = 1;
+
+struct StateHeader {
+  uint64_t magic;
+  int64_t version;
+  int64_t total;                  // bytes, header included
+  // geometry that must match the loading context
+  int64_t n, max_slots, max_clusters, ncol, nzb, brick_layers;
+  int64_t kahan, half_list, has_pme;
+  // capacities (the loading context adopts them)
+  int64_t nl_cap, col_cap;
+  // host counters
+  int64_t steps_since_build, steps_taken;
+};
+
+struct Segment {
+  void* p;
+  size_t bytes;
+};
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// The arrays, in state order, of a context with the given capacities.
+std::vector<Segment> state_segments(const Ctx& c) {
+  const size_t n = (size_t)c.n, ns = (size_t)c.max_slots, nc = (size_t)c.max_clusters;
+  const size_t ncol = (size_t)c.cg.ncell;
+  std::vector<Segment> s = {
+      {c.img, sizeof(int) * 3 * n},          {c.x_build, sizeof(float) * 3 * n},
+      {c.gate, sizeof(int) * 4},             {c.meta, sizeof(int) * 4},
+      {c.perm, sizeof(int) * ns},            {c.inv_perm, sizeof(int) * n},
+      {c.cell_of, sizeof(int) * n},          {c.cell_count, sizeof(int) * ncol},
+      {c.cell_start, sizeof(int) * (ncol + 1)}, {c.slot_start, sizeof(int) * (ncol + 1)},
+      {c.zbin, sizeof(int2) * ncol * (c.cg.nzb + 1)},
+      {c.xs, sizeof(float4) * ns},           {c.ts, sizeof(int) * ns},
+      {c.zb, sizeof(float) * ns},            {c.box_lo, sizeof(float4) * nc},
+      {c.box_hi, sizeof(float4) * nc},       {c.col_xy, sizeof(float4) * ncol},
+      {c.tiles, sizeof(uint2) * nc * c.nl_cap}, {c.tile_count, sizeof(int) * nc},
+      {c.nl_needed, sizeof(int)},            {c.ptiles, sizeof(uint2) * nc * c.nl_cap},
+      {c.pcount, sizeof(int) * nc},          {c.xp, sizeof(float4) * ns},
+  };
+  if (c.xc) {
+    s.push_back({c.xc, sizeof(float) * 3 * n});
+    s.push_back({c.vc, sizeof(float) * 3 * n});
+  }
+  if (c.has_pme) s.push_back({c.brick_zr, sizeof(int4) * (size_t)c.pg.nb[2] * ncol});
+  return s;
+}
+
+StateHeader state_header(const Ctx& c) {
+  StateHeader h{};
+  h.magic = kStateMagic;
+  h.version = kStateVersion;
+  h.n = c.n;
+  h.max_slots = c.max_slots;
+  h.max_clusters = c.max_clusters;
+  h.ncol = c.cg.ncell;
+  h.nzb = c.cg.nzb;
+  h.brick_layers = c.has_pme ? c.pg.nb[2] : 0;
+  h.kahan = c.xc != nullptr;
+  h.half_list = c.half_list;
+  h.has_pme = c.has_pme;
+  h.nl_cap = c.nl_cap;
+  h.col_cap = c.col_cap;
+  h.steps_since_build = c.steps_since_build;
+  h.steps_taken = c.steps_taken;
+  size_t total = align256(sizeof(StateHeader));
+  for (const Segment& sg : state_segments(c)) total += align256(sg.bytes);
+  h.total = (int64_t)total;
+  return h;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mdx_state_size(mdx_ctx* x, int64_t* bytes) {
+  if (check_ctx(x) || !bytes) return MDX_E_INVALID;
+  *bytes = state_header(x->c).total;
+  return MDX_OK;
+}
+
+int mdx_save_state(mdx_ctx* x, void* state, int64_t capacity) {
+  if (check_ctx(x) || !state || capacity < 0 || (reinterpret_cast<uintptr_t>(state) & 7u))
+    return MDX_E_INVALID;
+  Ctx& c = x->c;
+  const StateHeader h = state_header(c);
+  if (capacity < h.total) return MDX_E_CAPACITY;
+  char* dst = static_cast<char*>(state);
+  MDX_TRY(hipMemcpyAsync(dst, &h, sizeof(h), hipMemcpyHostToDevice, c.stream));
+  size_t off = align256(sizeof(StateHeader));
+  for (const Segment& sg : state_segments(c)) {
+    MDX_TRY(hipMemcpyAsync(dst + off, sg.p, sg.bytes, hipMemcpyDeviceToDevice, c.stream));
+    off += align256(sg.bytes);
+  }
+  MDX_TRY(hipStreamSynchronize(c.stream));   // the header is read from the host stack
+  return MDX_OK;
+}
+
+int mdx_load_state(mdx_ctx* x, const void* state, int64_t size) {
+  if (check_ctx(x) || !state || size < (int64_t)sizeof(StateHeader) ||
+      (reinterpret_cast<uintptr_t>(state) & 7u))
+    return MDX_E_INVALID;
+  Ctx& c = x->c;
+  StateHeader h;
+  MDX_TRY(hipStreamSynchronize(c.stream));
+  MDX_TRY(hipMemcpy(&h, state, sizeof(h), hipMemcpyDeviceToHost));
+  const StateHeader mine = state_header(c);
+  if (h.magic != kStateMagic || h.version != kStateVersion || h.n != mine.n ||
+      h.max_slots != mine.max_slots || h.max_clusters != mine.max_clusters ||
+      h.ncol != mine.ncol || h.nzb != mine.nzb || h.brick_layers != mine.brick_layers ||
+      h.kahan != mine.kahan || h.half_list != mine.half_list || h.has_pme != mine.has_pme ||
+      h.nl_cap < 4 || h.col_cap < 1 || h.col_cap > c.n || h.total > size ||
+      h.steps_since_build < -1 || h.steps_taken < 0)
+    return MDX_E_INVALID;
+  // adopt the saved capacities, so the arrays have the saved sizes
+  if (h.nl_cap != c.nl_cap) {
+    int rc = alloc_list(x, (int)h.nl_cap);
+    if (rc != MDX_OK) return rc;
+    if (c.nl_cap != h.nl_cap) return MDX_E_INVALID;   // not a capacity alloc_list makes
+  }
+  if (h.col_cap != c.col_cap) {
+    dev_free(x, c.col_atoms);
+    c.col_atoms = nullptr;
+    c.col_cap = (int)h.col_cap;
+    int rc = dev_alloc(x, &c.col_atoms, (size_t)c.cg.ncell * c.col_cap);
+    if (rc != MDX_OK) return rc;
+  }
+  if (state_header(c).total != h.total) return MDX_E_INVALID;
+  const char* src = static_cast<const char*>(state);
+  size_t off = align256(sizeof(StateHeader));
+  for (const Segment& sg : state_segments(c)) {
+    MDX_TRY(hipMemcpyAsync(sg.p, src + off, sg.bytes, hipMemcpyDeviceToDevice, c.stream));
+    off += align256(sg.bytes);
+  }
+  MDX_TRY(hipStreamSynchronize(c.stream));
+  c.steps_since_build = (int)h.steps_since_build;
+  c.steps_taken = h.steps_taken;
   return MDX_OK;
 }
 

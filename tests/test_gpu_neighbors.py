@@ -97,13 +97,24 @@ def test_list_crowded_column_grows_column_capacity():
     assert np.array_equal(got, _oracle_pairs(s))
 
 
-def test_list_water96k_sampled_rows():
+def test_list_water96k_whole_list_and_sampled_rows():
+    # the whole sorted pair list against the oracle's (its count and sha256,
+    # written by tests/golden/make_counts.py from the oracle), then 300 rows
+    # against the brute-force rows of the oracle
+    import hashlib
+    import json
+    import os
     s = synth.config_system("water96k")
     announce("list water96k")
     with gpu_context(s) as (mdx, ctx, t):
         mdx.build_neighbors(ctx, t["pos"])
         got = mdx.get_neighbor_pairs(ctx)
         assert mdx.get_status(ctx) == 0
+    with open(os.path.join(os.path.dirname(__file__), "golden", "pair_counts.json")) as f:
+        golden = json.load(f)["water96k"]
+    assert len(got) == golden["listed_pairs"]
+    rows = np.ascontiguousarray(got, dtype="<i4")
+    assert hashlib.sha256(rows.tobytes()).hexdigest() == golden["list_sha256"]
     rng = np.random.default_rng(3)
     sample = rng.choice(s.n_atoms, 300, replace=False)
     first, second = got[:, 0], got[:, 1]
