@@ -286,6 +286,27 @@ int mdx_compute_ewald_direct(mdx_ctx* ctx, const float* pos, float* force, doubl
                              int32_t n_max);
 
 /*
+ * mdx_compute_ewald_direct for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels, arithmetic and results, bit for bit, but the
+ * scratch (per-atom phase tables, structure factors, energy terms) lives in
+ * one fixed array of the library per device, 32 MiB, which each GPU the
+ * library runs on holds until the process ends; the call makes no
+ * allocation, free or memset. mdx_create takes the array's device address.
+ * The scratch needs 48 (2 n_max + 1) N + 24 K bytes, K = ((2 n_max + 1)^3 -
+ * 1) / 2, each part rounded up to 256 bytes; mdx_ewald_direct_noalloc_bytes
+ * reports it and the limit. MDX_E_CAPACITY when it exceeds the array; the
+ * other errors as mdx_compute_ewald_direct. Every call on a device uses the
+ * same array and overwrites all of the scratch it reads, so nothing carries
+ * over from an earlier call; calls that overlap on one device (another
+ * stream, another context, another thread) race and give wrong results.
+ */
+int mdx_compute_ewald_direct_noalloc(mdx_ctx* ctx, const float* pos, float* force,
+                                     double* energy, int32_t n_max);
+int mdx_ewald_direct_noalloc_bytes(int32_t n_atoms, int32_t n_max, int64_t* bytes,
+                                   int64_t* limit);
+
+/*
  * Velocity Verlet (Sec. II.D.1) for n_steps >= 1 with step dt:
  *   v += (dt/2) accel F/m;  x += dt v (wrapped into [0, L));  F = F(x);
  *   v += (dt/2) accel F/m.

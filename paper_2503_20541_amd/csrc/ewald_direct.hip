@@ -135,6 +135,54 @@ __global__ void __launch_bounds__(kEwThreads) k_ew_energy(const double* __restri
   if (threadIdx.x == 0) *out = escale * 2.0 * s[0];   // both m and -m
 }
 
+// ---- fixed scratch for callers that cannot allocate --------------------
+// One array per device (each GPU the library runs on holds its own copy until
+// the process ends). Host code never passes `scratch` itself to a kernel: the
+// name stands for a host-side shadow; the device address comes from
+// hipGetSymbolAddress, taken once per device by ewald_scratch_setup.
+static __device__ __align__(256) unsigned char scratch[kEwScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t ewald_scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  // called with `device` current; a second call on a device keeps the first address
+  if (__atomic_load_n(&g_scratch_ptr[device], __ATOMIC_ACQUIRE)) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!ptr) return hipErrorInvalidSymbol;
+  __atomic_store_n(&g_scratch_ptr[device], ptr, __ATOMIC_RELEASE);
+  return hipSuccess;
+}
+
+size_t ewald_scratch_bytes(int n, int nmax, size_t* off_S, size_t* off_e) {
+  const size_t w = 2 * (size_t)nmax + 1, K = (w * w * w - 1) / 2;
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t tab = up(3 * w * (size_t)n * sizeof(double2));
+  const size_t S = up(K * sizeof(double2));
+  if (off_S) *off_S = tab;
+  if (off_e) *off_e = tab + S;
+  return tab + S + up(K * sizeof(double));
+}
+
+hipError_t launch_ewald_direct_static(Ctx& c, const float* pos, float* force, double* energy,
+                                      int nmax) {
+  if (c.device < 0 || c.device >= kMaxDevices) return hipErrorInvalidDevice;
+  unsigned char* base =
+      static_cast<unsigned char*>(__atomic_load_n(&g_scratch_ptr[c.device], __ATOMIC_ACQUIRE));
+  if (!base) return hipErrorNotInitialized;
+  size_t off_S = 0, off_e = 0;
+  if (ewald_scratch_bytes(c.n, nmax, &off_S, &off_e) > kEwScratchBytes)
+    return hipErrorInvalidValue;
+  return launch_ewald_direct(c, pos, force, energy, nmax, reinterpret_cast<double2*>(base),
+                             reinterpret_cast<double2*>(base + off_S),
+                             reinterpret_cast<double*>(base + off_e));
+}
+
 hipError_t launch_ewald_direct(Ctx& c, const float* pos, float* force, double* energy, int nmax,
                                double2* tab, double2* S, double* eterm) {
   const int n = c.n;

@@ -266,6 +266,16 @@ hipError_t launch_pme_fft(Ctx& c, hipStream_t s, hipEvent_t done, bool virial = 
 // energy (dev double[1], may be null) overwritten. Scratch sized for nmax.
 hipError_t launch_ewald_direct(Ctx& c, const float* pos, float* force, double* energy, int nmax,
                                double2* tab, double2* S, double* eterm);
+// The same sum with its scratch (phase tables, structure factors, energy
+// terms) in the library's fixed per-device array of kEwScratchBytes, so the
+// call allocates nothing. ewald_scratch_setup(device), with that device
+// current, takes the array's device address once (mdx_create calls it).
+// hipErrorInvalidValue when the scratch of (n, nmax) exceeds the array.
+constexpr size_t kEwScratchBytes = 32u << 20;
+hipError_t ewald_scratch_setup(int device);
+size_t ewald_scratch_bytes(int n, int nmax, size_t* off_S = nullptr, size_t* off_e = nullptr);
+hipError_t launch_ewald_direct_static(Ctx& c, const float* pos, float* force, double* energy,
+                                      int nmax);
 
 // Device helpers shared by kernels -------------------------------------------
 

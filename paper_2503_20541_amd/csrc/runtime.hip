@@ -574,6 +574,12 @@ int mdx_create(mdx_ctx** out, const mdx_system_desc* d, void* hip_stream) {
     mdx_destroy(x);
     return rc;
   }
+  // the device address of the fixed scratch array of
+  // mdx_compute_ewald_direct_noalloc (once per device)
+  if (mdx::ewald_scratch_setup(x->c.device) != hipSuccess) {
+    mdx_destroy(x);
+    return MDX_E_HIP;
+  }
   *out = x;
   return MDX_OK;
 }
@@ -915,6 +921,24 @@ int mdx_compute_ewald_direct(mdx_ctx* x, const float* pos, float* force, double*
     c.ew_nmax = n_max;
   }
   MDX_TRY(mdx::launch_ewald_direct(c, pos, force, energy, n_max, c.ew_tab, c.ew_S, c.ew_eterm));
+  return MDX_OK;
+}
+
+int mdx_compute_ewald_direct_noalloc(mdx_ctx* x, const float* pos, float* force,
+                                     double* energy, int32_t n_max) {
+  if (check_ctx(x) || !pos || !force || n_max < 1 || n_max > 64) return MDX_E_INVALID;
+  Ctx& c = x->c;
+  if (!c.has_coulomb) return MDX_E_INVALID;
+  if (mdx::ewald_scratch_bytes(c.n, n_max) > mdx::kEwScratchBytes) return MDX_E_CAPACITY;
+  MDX_TRY(mdx::launch_ewald_direct_static(c, pos, force, energy, n_max));
+  return MDX_OK;
+}
+
+int mdx_ewald_direct_noalloc_bytes(int32_t n_atoms, int32_t n_max, int64_t* bytes,
+                                   int64_t* limit) {
+  if (n_atoms < 1 || n_max < 1 || n_max > 64 || !bytes) return MDX_E_INVALID;
+  *bytes = (int64_t)mdx::ewald_scratch_bytes(n_atoms, n_max);
+  if (limit) *limit = (int64_t)mdx::kEwScratchBytes;
   return MDX_OK;
 }
 

@@ -70,7 +70,8 @@ EXPORTED = ("mdx_error_string", "mdx_create", "mdx_destroy", "mdx_set_stream",
             "mdx_compute_pme", "mdx_integrate_step", "mdx_get_status", "mdx_get_info",
             "mdx_set_timing", "mdx_get_timing", "mdx_get_images", "mdx_set_langevin",
             "mdx_compute_ewald_direct", "mdx_set_rigid_water", "mdx_state_size",
-            "mdx_save_state", "mdx_load_state")
+            "mdx_save_state", "mdx_load_state", "mdx_compute_ewald_direct_noalloc",
+            "mdx_ewald_direct_noalloc_bytes")
 
 _fp = ctypes.POINTER(ctypes.c_float)
 _ip = ctypes.POINTER(ctypes.c_int32)
@@ -122,6 +123,10 @@ _lib.mdx_get_status.argtypes = [_vp, ctypes.POINTER(ctypes.c_uint32)]
 _lib.mdx_get_images.argtypes = [_vp, _vp]
 _lib.mdx_set_langevin.argtypes = [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_uint64]
 _lib.mdx_compute_ewald_direct.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int32]
+_lib.mdx_compute_ewald_direct_noalloc.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int32]
+_lib.mdx_ewald_direct_noalloc_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32,
+                                                ctypes.POINTER(ctypes.c_int64),
+                                                ctypes.POINTER(ctypes.c_int64)]
 _lib.mdx_set_rigid_water.argtypes = [_vp, _vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double]
 _lib.mdx_get_info.argtypes = [_vp, ctypes.POINTER(Info)]
 _lib.mdx_state_size.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64)]
@@ -296,6 +301,23 @@ def get_status(ctx: int) -> int:
 def compute_ewald_direct(ctx: int, pos, force, energy=None, n_max: int = 8) -> None:
     _check(_lib.mdx_compute_ewald_direct(ctx, _ptr(pos), _ptr(force), _ptr(energy), int(n_max)),
            "mdx_compute_ewald_direct")
+
+
+def compute_ewald_direct_noalloc(ctx: int, pos, force, energy=None, n_max: int = 8) -> None:
+    """compute_ewald_direct with the library's fixed scratch array (no allocation)."""
+    _check(_lib.mdx_compute_ewald_direct_noalloc(ctx, _ptr(pos), _ptr(force), _ptr(energy),
+                                                 int(n_max)),
+           "mdx_compute_ewald_direct_noalloc")
+
+
+def ewald_direct_noalloc_bytes(n_atoms: int, n_max: int):
+    """(scratch bytes the no-allocation direct sum needs, the array's size)."""
+    b = ctypes.c_int64(0)
+    lim = ctypes.c_int64(0)
+    _check(_lib.mdx_ewald_direct_noalloc_bytes(int(n_atoms), int(n_max), ctypes.byref(b),
+                                               ctypes.byref(lim)),
+           "mdx_ewald_direct_noalloc_bytes")
+    return int(b.value), int(lim.value)
 
 
 def set_rigid_water(ctx: int, mols, d_oh: float, d_hh: float) -> None:
