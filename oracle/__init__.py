@@ -22,4 +22,7 @@ Modules
   ewald      - alpha heuristic (Eq. 13), k_c root (Eq. 14), direct Ewald sum
   integrate  - velocity Verlet (Sec. II.D.1) in float64 and float32-emulated
   forcefield - sums the components for a synth.System-like object
+  adjoint    - gradients of a velocity-Verlet trajectory loss (parameters,
+               initial state, time step) by the reverse recursion, with a
+               complex-safe force field for exact directional derivatives
 """
