@@ -382,6 +382,72 @@ int mdx_set_langevin(mdx_ctx* ctx, double kT, double gamma, uint64_t seed);
 int mdx_set_rigid_water(mdx_ctx* ctx, const int32_t* mols, int32_t n_mol, double d_oh,
                         double d_hh);
 
+/*
+ * Parameters of the model for the following calls (the quantities the
+ * paper's differentiable simulation is differentiated with respect to,
+ * Sec. IV): type_sigma, type_epsilon (host float[n_types], Eqs. 4-5) and
+ * charge (host float[N]); a NULL array leaves that parameter unchanged. The
+ * LJ tables, the charges and the self term (Eq. 12) are replaced; the list
+ * is not affected. A context created without electrostatics accepts only
+ * zero charges (MDX_E_UNSUPPORTED otherwise). MDX_E_INVALID for sigma <= 0,
+ * epsilon < 0 or non-finite values. Synchronising.
+ */
+int mdx_set_parameters(mdx_ctx* ctx, const float* type_sigma, const float* type_epsilon,
+                       const float* charge);
+
+/*
+ * Reverse mode of a velocity-Verlet trajectory (the paper differentiates
+ * whole simulations, Sec. I and IV). For a run x_0 -> x_T of
+ * mdx_integrate_step and a loss L(x_T, U(x_T)), the reverse pass gives
+ * dL/dx_0, dL/dv_0, dL/d(dt) and dL/dtheta with theta = (epsilon_t for each
+ * type, sigma_t for each type, t), where t moves the charges along the
+ * direction of mdx_set_charge_direction, q(t) = q + t dq (for water,
+ * dq = 1 on O and -1/2 on H gives d/dq_O with q_H = -q_O / 2).
+ *
+ * The derivatives are those of the run with its interaction sets held fixed
+ * (pairs closer than r_c at each step, as the forward evaluated them): the
+ * truncated potentials make the loss discontinuous where a pair crosses
+ * r_c, and these are the derivatives of its smooth pieces. Per step the pass
+ * applies the transpose of the velocity-Verlet step with one Hessian-vector
+ * product of the force field (pairs, exclusion corrections, bonds, angles,
+ * smooth PME with its dipole grid) and the parameter derivatives of the
+ * force, FP32 arithmetic with FP64 sums. An epsilon_t of 0 has no
+ * derivative (Lorentz-Berthelot mixing): its entry stays 0. Supported for
+ * velocity Verlet with the default (full) list and unswitched potentials
+ * (MDX_E_UNSUPPORTED with MDX_OPT_HALF_LIST, a switch, Langevin dynamics or
+ * rigid water).
+ *
+ * Use: run the trajectory in segments, saving the state (mdx_save_state)
+ * and the positions, velocities and forces at each segment's start
+ * (checkpoints); then
+ *   mdx_adjoint_begin(ctx, pos_T, force_T, gx, gU, q, p, grad)
+ * with pos_T, force_T (dev [3][N]) the final state, gx = dL/dx_T (dev
+ * [3][N], unwrapped coordinates) and gU = dL/dU_T (dev double[1]): it sets
+ * q = gx - gU F(x_T), p = 0 and grad = gU dU/dtheta (dev double[2 T + 2]:
+ * epsilon_t, sigma_t, t, dt); then, for each segment from the last to the
+ * first, mdx_load_state of its checkpoint and
+ *   mdx_adjoint_segment(ctx, x_s, v_s, f_s, n_steps, dt, first, q, p, grad)
+ * which repeats the segment's n_steps forward from (x_s, v_s, f_s)
+ * (dev [3][N]; bit for bit the forward's steps, recorded in library-owned
+ * buffers) and runs the reverse steps over it, updating q, p and grad in
+ * place; first != 0 for the segment that starts the trajectory. At the end
+ * q = dL/dx_0, p = dL/dv_0 (through the trajectory; a loss term in x_0
+ * itself is the caller's) and grad holds dL/dtheta and dL/d(dt). The
+ * context's list state afterwards is that of the segment. Asynchronous.
+ */
+int mdx_set_charge_direction(mdx_ctx* ctx, const float* dq);   /* host float[N]; synchronising */
+int mdx_adjoint_begin(mdx_ctx* ctx, const float* pos, const float* force, const float* gx,
+                      const double* gU, float* q, float* p, double* grad);
+int mdx_adjoint_segment(mdx_ctx* ctx, const float* x0, const float* v0, const float* f0,
+                        int32_t n_steps, float dt, int32_t first, float* q, float* p,
+                        double* grad);
+
+/* Sets the periodic image counters (mdx_get_images) to zero. */
+int mdx_reset_images(mdx_ctx* ctx);
+/* out (dev [3][N]) = pos + img L: the positions unwrapped by the image
+ * counters. */
+int mdx_get_unwrapped(mdx_ctx* ctx, const float* pos, float* out);
+
 /* Fills *info (host). Synchronising once a list exists: the list is copied
  * to the host to count its entries. */
 int mdx_get_info(mdx_ctx* ctx, mdx_info* info);

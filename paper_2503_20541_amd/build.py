@@ -25,7 +25,7 @@ LIB = os.path.join(HERE, "libmdx.so")
 OBJDIR = os.path.join(HERE, "_build")
 LOCK = os.path.join(HERE, ".libmdx.lock")
 SOURCES = ["runtime.hip", "nl.hip", "nonbonded.hip", "pme.hip", "integrate.hip",
-           "ewald_direct.hip"]
+           "ewald_direct.hip", "adjoint.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -62,6 +62,32 @@ struct PmeGrid {
   float disp_max;    // r_g / 2 plus margin: how far an atom may sit outside its cell
 };
 
+// Scratch of the reverse (adjoint) pass, allocated by its first call.
+struct AdjScratch {
+  bool ready = false;
+  float* u = nullptr;          // [3][n] tangent c p / m of the node
+  float4* us = nullptr;        // [max_slots] (u, charge direction) by slot
+  float* dfs = nullptr;        // [3][max_slots] pair Hessian-vector product by slot
+  double* gslot = nullptr;     // [3][max_slots] pair parameter terms by slot
+  double* gatom = nullptr;     // [3][n] parameter terms by atom
+  float* dq = nullptr;         // [n] charge direction (mdx_set_charge_direction)
+  float* phi2 = nullptr;       // [K^3] potential of the dipole grid
+  double* dt_part = nullptr;   // [blocks] dt-gradient partials of a node
+  int* gate = nullptr;         // [1] rebuild request of a node
+  float4* lj_f = nullptr;      // [T*T] parameter-derivative factors (e1, e2, g1, g2)
+  double4* lj_d = nullptr;     // [T*T] energy parameter-derivative factors
+  // one segment's forward states: positions, velocities, forces, potential
+  int rec_steps = 0;
+  float* rec_x = nullptr;      // [rec_steps + 1][3][n]
+  float* rec_v = nullptr;
+  float* rec_f = nullptr;
+  float* rec_phi = nullptr;    // [rec_steps + 1][K^3]
+  float* pos = nullptr;        // [3][n] the segment's running state
+  float* vel = nullptr;
+  float* force = nullptr;
+  std::vector<float> dq_h;     // host copy of the charge direction
+};
+
 struct Ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -99,6 +125,10 @@ struct Ctx {
   unsigned long long lv_seed = 0;
   float* lv_sig = nullptr;     // [n] sqrt(kT accel / m_i)
   std::vector<float> mass_h;   // [n] masses (host copy)
+  // current parameters (host copies; mdx_set_parameters replaces them)
+  std::vector<float> sig_h, eps_h;   // [n_types]
+  std::vector<float> q_h;            // [n] charges as used (0 without electrostatics)
+  AdjScratch adj;
   // rigid water (mdx_set_rigid_water)
   int n_rigid = 0;
   int* rigid_mols = nullptr;   // [n_rigid][3] caller atoms O, H1, H2
@@ -260,6 +290,9 @@ hipError_t launch_rigid_velocities(Ctx& c, const float* pos, float* vel, bool en
 // Spread + FFT passes only (the potential grid), for the fused closing kernel.
 // `done` (may be null) is recorded by the last kernel's own dispatch.
 hipError_t launch_pme_spread(Ctx& c, hipStream_t s, hipEvent_t done);
+// The tangent of the charge grid along per-slot displacements us[slot].xyz
+// (sum of q u . grad theta) into grid_q, on the context's stream.
+hipError_t launch_pme_spread_dipole(Ctx& c, const float4* us);
 // virial: the z pass also writes the reciprocal-space virial rows (kRowVir).
 hipError_t launch_pme_fft(Ctx& c, hipStream_t s, hipEvent_t done, bool virial = false);
 // Direct reciprocal Ewald sum over |n_d| <= nmax into force (accumulated);
@@ -276,6 +309,23 @@ hipError_t ewald_scratch_setup(int device);
 size_t ewald_scratch_bytes(int n, int nmax, size_t* off_S = nullptr, size_t* off_e = nullptr);
 hipError_t launch_ewald_direct_static(Ctx& c, const float* pos, float* force, double* energy,
                                       int nmax);
+
+// Reverse pass (adjoint.hip). A node: launch_adj_pre (p <- p + dt q, dt
+// partials, tangent u), launch_adj_slots (slot refresh and gated rebuild at
+// pos when `refresh`, tangent by slot), launch_pair_jvp, the dipole spread
+// and FFT passes, launch_jvp_finish (q += wdt dF, parameter terms by atom),
+// launch_adj_reduce. eparam: the energy's parameter derivatives instead.
+hipError_t launch_adj_pre(Ctx& c, float dt, float w, const float* q, float* p, const float* v_n,
+                          const float* f_n);
+hipError_t launch_adj_slots(Ctx& c, const float* pos, bool refresh);
+hipError_t launch_pair_jvp(Ctx& c, bool eparam);
+hipError_t launch_jvp_finish(Ctx& c, bool eparam, const float* pos, const float* phi,
+                             const float* dphi, float* q, float wdt);
+hipError_t launch_adj_begin(Ctx& c, const float* gx, const double* gU, const float* force,
+                            float* q, float* p);
+hipError_t launch_adj_reduce(Ctx& c, double scale, const double* scale_dev, double q_const,
+                             int dt_blocks, double* grad);
+hipError_t launch_unwrap(Ctx& c, const float* pos, float* out);
 
 // Device helpers shared by kernels -------------------------------------------
 

@@ -59,10 +59,15 @@ __device__ __forceinline__ int spread_candidate(int f, int total, int ncand,
 // fall inside the brick into its wave's private LDS copy of the brick; the
 // copies are summed in a fixed order. No global atomics, and the result does
 // not depend on scheduling.
+//
+// DIPOLE: the tangent of the charge grid along per-slot displacements u
+// (us[slot].xyz): each atom adds q u . grad(theta) instead of q theta, the
+// grid the Hessian-vector product of the reciprocal force convolves.
+template <bool DIPOLE>
 __global__ void __launch_bounds__(kSpreadThreads) k_pme_spread(
     const float4* __restrict__ xs, const int4* __restrict__ brick_zr,
     const int* __restrict__ brick_cols, PmeParams pp, CellGrid cg,
-    float* __restrict__ grid_q) {
+    float* __restrict__ grid_q, const float4* __restrict__ us) {
   __shared__ float lgrid[kSpreadWaves][kMaxBrick];
   __shared__ int cand_start[kMaxCandCells];
   __shared__ int cand_off[kMaxCandCells + 1];
@@ -124,7 +129,8 @@ __global__ void __launch_bounds__(kSpreadThreads) k_pme_spread(
   for (int ch = w; ch * kWave < total; ch += kSpreadWaves) {
     const int f = ch * kWave + lane;
     if (f >= total) continue;
-    const float4 p = xs[spread_candidate(f, total, ncand, cand_list, cand_start, cand_off)];
+    const int sl = spread_candidate(f, total, ncand, cand_list, cand_start, cand_off);
+    const float4 p = xs[sl];
     int kx, ky, kz;
     float fx, fy, fz;
     grid_coord(p.x, pp.s_hi[0], pp.s_lo[0], pp.K[0], kx, fx);
@@ -135,10 +141,18 @@ __global__ void __launch_bounds__(kSpreadThreads) k_pme_spread(
     if (dx < 0) dx += pp.K[0];
     if (dy < 0) dy += pp.K[1];
     if (dz < 0) dz += pp.K[2];
-    float tx[4], ty[4], tz[4], dummy[4];
-    spline4(fx, tx, dummy);
-    spline4(fy, ty, dummy);
-    spline4(fz, tz, dummy);
+    float tx[4], ty[4], tz[4], dtx[4], dty[4], dtz[4];
+    spline4(fx, tx, dtx);
+    spline4(fy, ty, dty);
+    spline4(fz, tz, dtz);
+    // dipole mode: q u_d (K_d / L_d) scales the derivative factor along d
+    float ux = 0.f, uy = 0.f, uz = 0.f;
+    if (DIPOLE) {
+      const float4 u = us[sl];
+      ux = p.w * u.x * (pp.s_hi[0] + pp.s_lo[0]);
+      uy = p.w * u.y * (pp.s_hi[1] + pp.s_lo[1]);
+      uz = p.w * u.z * (pp.s_hi[2] + pp.s_lo[2]);
+    }
 #pragma unroll
     for (int t1 = 0; t1 < 4; ++t1) {
       int lx = dx - t1;
@@ -151,12 +165,16 @@ __global__ void __launch_bounds__(kSpreadThreads) k_pme_spread(
         if (ly < 0) ly += pp.K[1];
         if (ly >= bey) continue;
         const float wxy = wx * ty[t2];
+        // dipole: (ux dtx ty + uy tx dty) tz + uz tx ty dtz
+        const float a = DIPOLE ? ux * dtx[t1] * ty[t2] + uy * tx[t1] * dty[t2] : 0.f;
+        const float b = DIPOLE ? uz * tx[t1] * ty[t2] : 0.f;
         float* row = my_grid + ly * pp.B[0] + lx;
 #pragma unroll
         for (int t3 = 0; t3 < 4; ++t3) {
           int lz = dz - t3;
           if (lz < 0) lz += pp.K[2];
-          if (lz < bez) atomicAdd(row + lz * plane, wxy * tz[t3]);
+          if (lz < bez)
+            atomicAdd(row + lz * plane, DIPOLE ? a * tz[t3] + b * dtz[t3] : wxy * tz[t3]);
         }
       }
     }
@@ -631,8 +649,8 @@ PmeParams make_pme_params(const Ctx& c) {
 hipError_t launch_pme_spread(Ctx& c, hipStream_t s, hipEvent_t done) {
   const PmeParams pp = make_pme_params(c);
   if (!done) {
-    k_pme_spread<<<c.pg.nbrick, kSpreadThreads, 0, s>>>(c.xs, c.brick_zr, c.brick_cols, pp, c.cg,
-                                                        c.grid_q);
+    k_pme_spread<false><<<c.pg.nbrick, kSpreadThreads, 0, s>>>(c.xs, c.brick_zr, c.brick_cols,
+                                                               pp, c.cg, c.grid_q, nullptr);
     return hipGetLastError();
   }
   const float4* xs = c.xs;
@@ -641,9 +659,17 @@ hipError_t launch_pme_spread(Ctx& c, hipStream_t s, hipEvent_t done) {
   CellGrid cg = c.cg;
   float* q = c.grid_q;
   PmeParams p = pp;
-  void* args[] = {&xs, &zr, &bc, &p, &cg, &q};
-  return hipExtLaunchKernel(reinterpret_cast<const void*>(k_pme_spread), dim3(c.pg.nbrick),
-                            dim3(kSpreadThreads), args, 0, s, nullptr, done, 0);
+  const float4* us = nullptr;
+  void* args[] = {&xs, &zr, &bc, &p, &cg, &q, &us};
+  return hipExtLaunchKernel(reinterpret_cast<const void*>(k_pme_spread<false>),
+                            dim3(c.pg.nbrick), dim3(kSpreadThreads), args, 0, s, nullptr, done, 0);
+}
+
+hipError_t launch_pme_spread_dipole(Ctx& c, const float4* us) {
+  const PmeParams pp = make_pme_params(c);
+  k_pme_spread<true><<<c.pg.nbrick, kSpreadThreads, 0, c.stream>>>(c.xs, c.brick_zr, c.brick_cols,
+                                                                   pp, c.cg, c.grid_q, us);
+  return hipGetLastError();
 }
 
 // The five FFT passes (forward transform, influence multiply with the energy

@@ -100,6 +100,63 @@ int default_capacity(int n, const float box[3], float r_list, double a, int max_
   return std::max(16, std::min(cap, (4 * max_clusters + 15) / 16 * 16));
 }
 
+// LJ type-pair tables from the current per-type sigma and epsilon (Eqs. 4-5,
+// FP64 mixing): the force kernel's (c12, c6, 12 c12, 6 c6) in float32 and
+// (c12, c6) in FP64, and the reverse pass's parameter-derivative factors
+// (per ordered type pair, for the i end: a = sqrt(eps_tj / eps_ti) / 2,
+// 0 when eps_ti = 0):
+//   force: (48 a s^12, 24 a s^6, 288 eps s^11, 72 eps s^5)
+//   energy: (4 a s^12, 4 a s^6, 24 eps s^11, 12 eps s^5)
+// uploaded into the context's tables (allocated on the first call).
+int upload_lj_tables(mdx_ctx* x) {
+  Ctx& c = x->c;
+  const int T = c.n_types;
+  std::vector<float4> ljf((size_t)T * T), adf((size_t)T * T);
+  std::vector<double2> ljd((size_t)T * T);
+  std::vector<double4> add((size_t)T * T);
+  for (int a = 0; a < T; ++a)
+    for (int b = 0; b < T; ++b) {
+      const double ea = c.eps_h[a], eb = c.eps_h[b];
+      double sig = 0.5 * ((double)c.sig_h[a] + (double)c.sig_h[b]);
+      double eps = std::sqrt(std::max(0.0, ea * eb));
+      double s6 = sig * sig * sig * sig * sig * sig;
+      double c6 = 4.0 * eps * s6, c12 = 4.0 * eps * s6 * s6;
+      const size_t k = (size_t)a * T + b;
+      ljf[k] = make_float4((float)c12, (float)c6, (float)(12.0 * c12), (float)(6.0 * c6));
+      ljd[k] = make_double2(c12, c6);
+      const double at = ea > 0.0 ? 0.5 * std::sqrt(std::max(0.0, eb) / ea) : 0.0;
+      const double s5 = s6 / sig, s11 = s6 * s5, s12 = s6 * s6;
+      adf[k] = make_float4((float)(48.0 * at * s12), (float)(24.0 * at * s6),
+                           (float)(288.0 * eps * s11), (float)(72.0 * eps * s5));
+      add[k] = make_double4(4.0 * at * s12, 4.0 * at * s6, 24.0 * eps * s11, 12.0 * eps * s5);
+    }
+  int rc;
+  if (!c.lj_f) {
+    if ((rc = dev_alloc(x, &c.lj_f, ljf.size())) != MDX_OK) return rc;
+    if ((rc = dev_alloc(x, &c.lj_d, ljd.size())) != MDX_OK) return rc;
+    if ((rc = dev_alloc(x, &c.adj.lj_f, adf.size())) != MDX_OK) return rc;
+    if ((rc = dev_alloc(x, &c.adj.lj_d, add.size())) != MDX_OK) return rc;
+  }
+  MDX_TRY(hipMemcpy(c.lj_f, ljf.data(), sizeof(float4) * ljf.size(), hipMemcpyHostToDevice));
+  MDX_TRY(hipMemcpy(c.lj_d, ljd.data(), sizeof(double2) * ljd.size(), hipMemcpyHostToDevice));
+  MDX_TRY(hipMemcpy(c.adj.lj_f, adf.data(), sizeof(float4) * adf.size(), hipMemcpyHostToDevice));
+  MDX_TRY(hipMemcpy(c.adj.lj_d, add.data(), sizeof(double4) * add.size(), hipMemcpyHostToDevice));
+  return MDX_OK;
+}
+
+// Eq. 12 times k_e plus the neutralising term, from the current charges.
+double self_energy(const Ctx& c) {
+  if (!c.has_coulomb) return 0.0;
+  double q2 = 0.0, qsum = 0.0;
+  for (float q : c.q_h) {
+    q2 += (double)q * q;
+    qsum += q;
+  }
+  const double V = (double)c.box[0] * c.box[1] * c.box[2];
+  return -c.coulomb_k * c.alpha / std::sqrt(M_PI) * q2 -
+         c.coulomb_k * M_PI * qsum * qsum / (2.0 * V * c.alpha * c.alpha);
+}
+
 int alloc_list(mdx_ctx* x, int cap) {
   Ctx& c = x->c;
   cap = std::max(4, (cap + 3) / 4 * 4);   // lists are padded to groups of four tiles
@@ -305,39 +362,22 @@ int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
   // ---- per-atom parameters and the LJ type-pair table (Eqs. 4-5) ----
   std::vector<float> q(n), am(n), ms(n);
   std::vector<int> ty(n);
-  double q2 = 0.0, qsum = 0.0;
   for (int i = 0; i < n; ++i) {
     q[i] = c.has_coulomb || c.rf ? d->charge[i] : 0.f;
     ty[i] = d->atom_type[i];
     am[i] = (float)(c.accel / (double)d->mass[i]);
     ms[i] = d->mass[i];
-    q2 += (double)d->charge[i] * d->charge[i];
-    qsum += d->charge[i];
   }
   const int T = d->n_types;
   c.n_types = T;
-  std::vector<float4> ljf((size_t)T * T);
-  std::vector<double2> ljd((size_t)T * T);
-  for (int a = 0; a < T; ++a)
-    for (int b = 0; b < T; ++b) {
-      double sig = 0.5 * ((double)d->type_sigma[a] + (double)d->type_sigma[b]);
-      double eps = std::sqrt(std::max(0.0, (double)d->type_epsilon[a] * d->type_epsilon[b]));
-      double s6 = sig * sig * sig * sig * sig * sig;
-      double c6 = 4.0 * eps * s6, c12 = 4.0 * eps * s6 * s6;
-      ljf[(size_t)a * T + b] = make_float4((float)c12, (float)c6, (float)(12.0 * c12),
-                                           (float)(6.0 * c6));
-      ljd[(size_t)a * T + b] = make_double2(c12, c6);
-    }
-  if (c.has_coulomb) {
-    double V = (double)c.box[0] * c.box[1] * c.box[2];
-    c.e_self = -c.coulomb_k * c.alpha / std::sqrt(M_PI) * q2 -
-               c.coulomb_k * M_PI * qsum * qsum / (2.0 * V * c.alpha * c.alpha);
-  }
+  c.sig_h.assign(d->type_sigma, d->type_sigma + T);
+  c.eps_h.assign(d->type_epsilon, d->type_epsilon + T);
+  c.q_h = q;
+  c.e_self = self_energy(c);
   int rc;
+  if ((rc = upload_lj_tables(x)) != MDX_OK) return rc;
   if ((rc = dev_upload(x, &c.q, q)) != MDX_OK) return rc;
   if ((rc = dev_upload(x, &c.atype, ty)) != MDX_OK) return rc;
-  if ((rc = dev_upload(x, &c.lj_f, ljf)) != MDX_OK) return rc;
-  if ((rc = dev_upload(x, &c.lj_d, ljd)) != MDX_OK) return rc;
   if ((rc = dev_upload(x, &c.hdt_scale, am)) != MDX_OK) return rc;
   if ((rc = dev_upload(x, &c.mass, ms)) != MDX_OK) return rc;
   c.mass_h = ms;
@@ -1142,6 +1182,225 @@ int mdx_load_state(mdx_ctx* x, const void* state, int64_t size) {
   MDX_TRY(hipStreamSynchronize(c.stream));
   c.steps_since_build = (int)h.steps_since_build;
   c.steps_taken = h.steps_taken;
+  return MDX_OK;
+}
+
+int mdx_set_parameters(mdx_ctx* x, const float* type_sigma, const float* type_epsilon,
+                       const float* charge) {
+  if (check_ctx(x)) return MDX_E_INVALID;
+  Ctx& c = x->c;
+  const int T = c.n_types;
+  for (int t = 0; type_sigma && t < T; ++t)
+    if (!(type_sigma[t] > 0.f) || !std::isfinite(type_sigma[t])) return MDX_E_INVALID;
+  for (int t = 0; type_epsilon && t < T; ++t)
+    if (!(type_epsilon[t] >= 0.f) || !std::isfinite(type_epsilon[t])) return MDX_E_INVALID;
+  for (int i = 0; charge && i < c.n; ++i) {
+    if (!std::isfinite(charge[i])) return MDX_E_INVALID;
+    // electrostatics were configured (or not) at mdx_create
+    if (!c.has_coulomb && !c.rf && charge[i] != 0.f) return MDX_E_UNSUPPORTED;
+  }
+  MDX_TRY(hipStreamSynchronize(c.stream));   // kernels in flight read the tables
+  if (type_sigma) c.sig_h.assign(type_sigma, type_sigma + T);
+  if (type_epsilon) c.eps_h.assign(type_epsilon, type_epsilon + T);
+  if (type_sigma || type_epsilon) {
+    int rc = upload_lj_tables(x);
+    if (rc != MDX_OK) return rc;
+  }
+  if (charge) {
+    c.q_h.assign(charge, charge + c.n);
+    MDX_TRY(hipMemcpy(c.q, c.q_h.data(), sizeof(float) * c.n, hipMemcpyHostToDevice));
+    c.e_self = self_energy(c);
+  }
+  return MDX_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+int ensure_adjoint(mdx_ctx* x) {
+  Ctx& c = x->c;
+  mdx::AdjScratch& a = c.adj;
+  if (a.ready) return MDX_OK;
+  const size_t n3 = 3 * (size_t)c.n, ns = (size_t)c.max_slots;
+  int rc;
+  if ((rc = dev_alloc(x, &a.u, n3)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &a.us, ns)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &a.dfs, 3 * ns)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &a.gslot, 3 * ns)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &a.gatom, n3)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &a.dq, (size_t)c.n)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &a.dt_part, (size_t)(c.n + 255) / 256)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &a.gate, 1)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &a.pos, n3)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &a.vel, n3)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &a.force, n3)) != MDX_OK) return rc;
+  if (c.has_pme) {
+    const size_t K3 = (size_t)c.pg.K[0] * c.pg.K[1] * c.pg.K[2];
+    if ((rc = dev_alloc(x, &a.phi2, K3)) != MDX_OK) return rc;
+  }
+  MDX_TRY(hipMemset(a.dq, 0, sizeof(float) * c.n));
+  a.dq_h.assign(c.n, 0.f);
+  a.ready = true;
+  return MDX_OK;
+}
+
+int ensure_records(mdx_ctx* x, int steps) {
+  Ctx& c = x->c;
+  mdx::AdjScratch& a = c.adj;
+  if (steps <= a.rec_steps) return MDX_OK;
+  dev_free(x, a.rec_x);
+  dev_free(x, a.rec_v);
+  dev_free(x, a.rec_f);
+  dev_free(x, a.rec_phi);
+  a.rec_x = a.rec_v = a.rec_f = a.rec_phi = nullptr;
+  a.rec_steps = 0;
+  const size_t m = (size_t)(steps + 1) * 3 * c.n;
+  int rc;
+  if ((rc = dev_alloc(x, &a.rec_x, m)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &a.rec_v, m)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &a.rec_f, m)) != MDX_OK) return rc;
+  if (c.has_pme) {
+    const size_t K3 = (size_t)c.pg.K[0] * c.pg.K[1] * c.pg.K[2];
+    if ((rc = dev_alloc(x, &a.rec_phi, (size_t)(steps + 1) * K3)) != MDX_OK) return rc;
+  }
+  a.rec_steps = steps;
+  return MDX_OK;
+}
+
+// The reverse pass covers plain velocity Verlet with the full list and the
+// unswitched pair potentials.
+int adjoint_supported(const Ctx& c) {
+  if (c.half_list || c.langevin || c.n_rigid > 0 || c.has_switch) return MDX_E_UNSUPPORTED;
+  return MDX_OK;
+}
+
+// d E_self / dt for charges q + t dq (Eq. 12 and the neutralising term).
+double self_energy_charge_derivative(const Ctx& c) {
+  if (!c.has_coulomb) return 0.0;
+  double qdq = 0.0, qs = 0.0, dqs = 0.0;
+  for (int i = 0; i < c.n; ++i) {
+    qdq += (double)c.q_h[i] * c.adj.dq_h[i];
+    qs += c.q_h[i];
+    dqs += c.adj.dq_h[i];
+  }
+  const double V = (double)c.box[0] * c.box[1] * c.box[2];
+  return -2.0 * c.coulomb_k * c.alpha / std::sqrt(M_PI) * qdq -
+         c.coulomb_k * M_PI * qs * dqs / (V * c.alpha * c.alpha);
+}
+
+// The potential of the dipole grid of the tangent by slot into adj.phi2.
+hipError_t dipole_potential(Ctx& c) {
+  hipError_t e = mdx::launch_pme_spread_dipole(c, c.adj.us);
+  if (e != hipSuccess) return e;
+  std::swap(c.grid_phi, c.adj.phi2);
+  e = mdx::launch_pme_fft(c, c.stream, nullptr);
+  std::swap(c.grid_phi, c.adj.phi2);
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mdx_set_charge_direction(mdx_ctx* x, const float* dq) {
+  if (check_ctx(x) || !dq) return MDX_E_INVALID;
+  Ctx& c = x->c;
+  for (int i = 0; i < c.n; ++i)
+    if (!std::isfinite(dq[i])) return MDX_E_INVALID;
+  if (int rc = ensure_adjoint(x)) return rc;
+  MDX_TRY(hipStreamSynchronize(c.stream));
+  c.adj.dq_h.assign(dq, dq + c.n);
+  MDX_TRY(hipMemcpy(c.adj.dq, dq, sizeof(float) * c.n, hipMemcpyHostToDevice));
+  return MDX_OK;
+}
+
+int mdx_reset_images(mdx_ctx* x) {
+  if (check_ctx(x)) return MDX_E_INVALID;
+  MDX_TRY(mdx::launch_fill_i32(x->c.img, 0, 3 * x->c.n, x->c.stream));
+  return MDX_OK;
+}
+
+int mdx_get_unwrapped(mdx_ctx* x, const float* pos, float* out) {
+  if (check_ctx(x) || !pos || !out) return MDX_E_INVALID;
+  MDX_TRY(mdx::launch_unwrap(x->c, pos, out));
+  return MDX_OK;
+}
+
+int mdx_adjoint_begin(mdx_ctx* x, const float* pos, const float* force, const float* gx,
+                      const double* gU, float* q, float* p, double* grad) {
+  if (check_ctx(x) || !pos || !force || !gx || !gU || !q || !p || !grad) return MDX_E_INVALID;
+  Ctx& c = x->c;
+  if (int rc = adjoint_supported(c)) return rc;
+  if (int rc = ensure_adjoint(x)) return rc;
+  const int T = c.n_types;
+  MDX_TRY(mdx::launch_fill_i32(reinterpret_cast<int*>(grad), 0, 2 * (2 * T + 2), c.stream));
+  // the energy's parameter derivatives at pos, scaled by dL/dU
+  MDX_TRY(mdx::launch_build_list(c, pos));
+  c.steps_since_build = 0;
+  MDX_TRY(mdx::launch_fill_i32(reinterpret_cast<int*>(c.adj.u), 0, 3 * c.n, c.stream));
+  MDX_TRY(mdx::launch_adj_slots(c, pos, false));
+  if (c.has_pme) {
+    MDX_TRY(mdx::launch_pme_spread(c, c.stream, nullptr));
+    MDX_TRY(mdx::launch_pme_fft(c, c.stream, nullptr));
+  }
+  MDX_TRY(mdx::launch_pair_jvp(c, true));
+  MDX_TRY(mdx::launch_jvp_finish(c, true, pos, c.grid_phi, nullptr, nullptr, 0.f));
+  MDX_TRY(mdx::launch_adj_reduce(c, 1.0, gU, self_energy_charge_derivative(c), 0, grad));
+  MDX_TRY(mdx::launch_adj_begin(c, gx, gU, force, q, p));
+  return MDX_OK;
+}
+
+int mdx_adjoint_segment(mdx_ctx* x, const float* x0, const float* v0, const float* f0,
+                        int32_t n_steps, float dt, int32_t first, float* q, float* p,
+                        double* grad) {
+  if (check_ctx(x) || !x0 || !v0 || !f0 || !q || !p || !grad || n_steps < 1 || !(dt > 0.f))
+    return MDX_E_INVALID;
+  Ctx& c = x->c;
+  if (c.steps_since_build < 0) return MDX_E_NO_LIST;
+  if (int rc = adjoint_supported(c)) return rc;
+  if (int rc = ensure_adjoint(x)) return rc;
+  if (int rc = ensure_records(x, n_steps)) return rc;
+  mdx::AdjScratch& a = c.adj;
+  const size_t n3 = 3 * (size_t)c.n;
+  const size_t K3 = c.has_pme ? (size_t)c.pg.K[0] * c.pg.K[1] * c.pg.K[2] : 0;
+  const size_t b3 = sizeof(float) * n3;
+  auto copy = [&](void* dst, const void* src, size_t bytes) {
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c.stream);
+  };
+  // the segment again, from its saved start, recording every state
+  MDX_TRY(copy(a.pos, x0, b3));
+  MDX_TRY(copy(a.vel, v0, b3));
+  MDX_TRY(copy(a.force, f0, b3));
+  MDX_TRY(copy(a.rec_x, x0, b3));
+  MDX_TRY(copy(a.rec_v, v0, b3));
+  MDX_TRY(copy(a.rec_f, f0, b3));
+  if (c.has_pme) {
+    MDX_TRY(mdx::launch_refresh_sorted(c, x0));
+    MDX_TRY(mdx::launch_pme_spread(c, c.stream, nullptr));
+    MDX_TRY(mdx::launch_pme_fft(c, c.stream, nullptr));
+    MDX_TRY(copy(a.rec_phi, c.grid_phi, sizeof(float) * K3));
+  }
+  for (int k = 0; k < n_steps; ++k) {
+    if (int rc = mdx_integrate_step(x, a.pos, a.vel, a.force, 1, dt, nullptr)) return rc;
+    MDX_TRY(copy(a.rec_x + (k + 1) * n3, a.pos, b3));
+    MDX_TRY(copy(a.rec_v + (k + 1) * n3, a.vel, b3));
+    MDX_TRY(copy(a.rec_f + (k + 1) * n3, a.force, b3));
+    if (c.has_pme) MDX_TRY(copy(a.rec_phi + (k + 1) * K3, c.grid_phi, sizeof(float) * K3));
+  }
+  // reverse over the segment's nodes
+  const int nblk = (c.n + 255) / 256;
+  for (int k = n_steps - 1; k >= 0; --k) {
+    const float w = (first && k == 0) ? 0.5f : 1.0f;
+    const float* xk = a.rec_x + k * n3;
+    MDX_TRY(mdx::launch_adj_pre(c, dt, w, q, p, a.rec_v + k * n3, a.rec_f + k * n3));
+    MDX_TRY(mdx::launch_adj_slots(c, xk, true));
+    MDX_TRY(mdx::launch_pair_jvp(c, false));
+    if (c.has_pme) MDX_TRY(dipole_potential(c));
+    MDX_TRY(mdx::launch_jvp_finish(c, false, xk, c.has_pme ? a.rec_phi + k * K3 : nullptr,
+                                   a.phi2, q, w * dt));
+    MDX_TRY(mdx::launch_adj_reduce(c, (double)w * dt, nullptr, 0.0, nblk, grad));
+  }
   return MDX_OK;
 }
 

@@ -71,7 +71,8 @@ EXPORTED = ("mdx_error_string", "mdx_create", "mdx_destroy", "mdx_set_stream",
             "mdx_set_timing", "mdx_get_timing", "mdx_get_images", "mdx_set_langevin",
             "mdx_compute_ewald_direct", "mdx_set_rigid_water", "mdx_state_size",
             "mdx_save_state", "mdx_load_state", "mdx_compute_ewald_direct_noalloc",
-            "mdx_ewald_direct_noalloc_bytes")
+            "mdx_ewald_direct_noalloc_bytes", "mdx_set_parameters", "mdx_set_charge_direction",
+            "mdx_adjoint_begin", "mdx_adjoint_segment", "mdx_reset_images", "mdx_get_unwrapped")
 
 _fp = ctypes.POINTER(ctypes.c_float)
 _ip = ctypes.POINTER(ctypes.c_int32)
@@ -132,6 +133,13 @@ _lib.mdx_get_info.argtypes = [_vp, ctypes.POINTER(Info)]
 _lib.mdx_state_size.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64)]
 _lib.mdx_save_state.argtypes = [_vp, _vp, ctypes.c_int64]
 _lib.mdx_load_state.argtypes = [_vp, _vp, ctypes.c_int64]
+_lib.mdx_set_parameters.argtypes = [_vp, _vp, _vp, _vp]
+_lib.mdx_set_charge_direction.argtypes = [_vp, _vp]
+_lib.mdx_adjoint_begin.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.mdx_adjoint_segment.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_float,
+                                     ctypes.c_int32, _vp, _vp, _vp]
+_lib.mdx_reset_images.argtypes = [_vp]
+_lib.mdx_get_unwrapped.argtypes = [_vp, _vp, _vp]
 _lib.mdx_set_timing.argtypes = [_vp, ctypes.c_int]
 _lib.mdx_get_timing.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                 ctypes.POINTER(ctypes.c_int64)]
@@ -353,6 +361,46 @@ def save_state(ctx: int, state, capacity: int | None = None) -> None:
 def load_state(ctx: int, state, size: int | None = None) -> None:
     size = size if size is not None else state.numel() * state.element_size()
     _check(_lib.mdx_load_state(ctx, _ptr(state), int(size)), "mdx_load_state")
+
+
+def _host_f32(a):
+    if a is None:
+        return None, None
+    h = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    return h, h.ctypes.data
+
+
+def set_parameters(ctx: int, type_sigma=None, type_epsilon=None, charge=None) -> None:
+    """Host arrays (per type, per type, per atom); None leaves one unchanged."""
+    s, sp = _host_f32(type_sigma)
+    e, ep = _host_f32(type_epsilon)
+    q, qp = _host_f32(charge)
+    _check(_lib.mdx_set_parameters(ctx, sp, ep, qp), "mdx_set_parameters")
+
+
+def set_charge_direction(ctx: int, dq) -> None:
+    h, hp = _host_f32(dq)
+    _check(_lib.mdx_set_charge_direction(ctx, hp), "mdx_set_charge_direction")
+
+
+def adjoint_begin(ctx: int, pos, force, gx, gU, q, p, grad) -> None:
+    _check(_lib.mdx_adjoint_begin(ctx, _ptr(pos), _ptr(force), _ptr(gx), _ptr(gU), _ptr(q),
+                                  _ptr(p), _ptr(grad)), "mdx_adjoint_begin")
+
+
+def adjoint_segment(ctx: int, x0, v0, f0, n_steps: int, dt: float, first: bool, q, p,
+                    grad) -> None:
+    _check(_lib.mdx_adjoint_segment(ctx, _ptr(x0), _ptr(v0), _ptr(f0), int(n_steps), float(dt),
+                                    1 if first else 0, _ptr(q), _ptr(p), _ptr(grad)),
+           "mdx_adjoint_segment")
+
+
+def reset_images(ctx: int) -> None:
+    _check(_lib.mdx_reset_images(ctx), "mdx_reset_images")
+
+
+def get_unwrapped(ctx: int, pos, out) -> None:
+    _check(_lib.mdx_get_unwrapped(ctx, _ptr(pos), _ptr(out)), "mdx_get_unwrapped")
 
 
 def get_info(ctx: int) -> Info:

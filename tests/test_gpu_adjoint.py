@@ -1,0 +1,135 @@
+"""GPU: gradients of the trajectory loss U(x_T)/N + MSD through the library's
+reverse pass (paper_2503_20541_amd.trajectory over mdx_adjoint_begin /
+mdx_adjoint_segment) against the FP64 adjoint oracle and closed forms."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import adjoint
+from helpers import announce
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(s, n_steps, dt, every, dq=None, **over):
+    """GPU loss and gradients (x0, v0, eps, sig, t_q, dt) of s's initial state."""
+    import torch
+    from paper_2503_20541_amd import trajectory as tj
+    dev = torch.device("cuda:0")
+    sim = tj.Simulation(s, n_steps, every, charge_direction=dq, **over)
+    try:
+        x0 = torch.from_numpy(s.pos.copy()).to(dev).requires_grad_(True)
+        v0 = torch.from_numpy(s.vel.copy()).to(dev).requires_grad_(True)
+        eps = torch.from_numpy(s.type_epsilon.copy()).to(dev).requires_grad_(True)
+        sig = torch.from_numpy(s.type_sigma.copy()).to(dev).requires_grad_(True)
+        tq = torch.zeros((), device=dev, requires_grad=True)
+        dtt = torch.tensor(float(dt), device=dev, requires_grad=True)
+        xT, UT = tj.trajectory(sim, x0, v0, eps, sig, tq, dtt)
+        n = s.n_atoms
+        L = UT / n + ((xT.double() - x0.double()) ** 2).sum() / n
+        L.backward()
+        torch.cuda.synchronize()
+        out = dict(loss=float(L.detach()), x0=x0.grad.double().cpu().numpy(),
+                   v0=v0.grad.double().cpu().numpy(), eps=eps.grad.double().cpu().numpy(),
+                   sig=sig.grad.double().cpu().numpy(), tq=float(tq.grad), dt=float(dtt.grad))
+        import paper_2503_20541_amd as mdx
+        out["flags"] = mdx.get_status(sim.ctx)
+        return out
+    finally:
+        sim.close()
+
+
+def _rel(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_water_gradients_match_the_fp64_oracle():
+    s = synth.config_system("water375")
+    dq = np.where(s.atom_type == 0, 1.0, -0.5).astype(np.float32)
+    n_steps, dt = 20, 1.0
+    announce("adjoint water375 20 steps vs oracle")
+    g = _run(s, n_steps, dt, 10, dq)
+    assert g["flags"] == 0
+    ff = adjoint.ForceField(s)
+    ref = adjoint.gradients(ff, ff.params0(), s.pos.astype(np.float64),
+                            s.vel.astype(np.float64), dt, n_steps, dq.astype(np.float64))
+    th = ref["theta"]          # eps_O, eps_H, sig_O, sig_H, t
+    rows = {"loss": (g["loss"], ref["loss"]), "eps_O": (g["eps"][0], th[0]),
+            "sig_O": (g["sig"][0], th[2]), "q_O": (g["tq"], th[4]), "dt": (g["dt"], ref["dt"])}
+    for k, (a, b) in rows.items():
+        print(f"{k}: gpu {a:.9g} oracle {b:.9g} rel {abs(a - b) / abs(b):.2e}", flush=True)
+    print(f"x0 rel {_rel(g['x0'], ref['x0']):.2e} v0 rel {_rel(g['v0'], ref['v0']):.2e}",
+          flush=True)
+    for k, (a, b) in rows.items():
+        assert abs(a - b) <= 1e-3 * abs(b), (k, a, b)
+    assert g["eps"][1] == 0.0            # eps_H = 0: no derivative, reported 0
+    assert _rel(g["x0"], ref["x0"]) < 1e-3
+    assert _rel(g["v0"], ref["v0"]) < 1e-3
+
+
+def test_checkpoint_spacing_does_not_change_the_gradients():
+    s = synth.config_system("water375")
+    dq = np.where(s.atom_type == 0, 1.0, -0.5).astype(np.float32)
+    announce("adjoint water375 checkpoint spacings 20 / 7")
+    a = _run(s, 20, 1.0, 20, dq)
+    b = _run(s, 20, 1.0, 7, dq)
+    assert a["loss"] == b["loss"]        # the same forward, bit for bit
+    for k in ("eps", "sig"):
+        assert np.allclose(a[k], b[k], rtol=1e-5, atol=0), k
+    for k in ("tq", "dt"):
+        assert abs(a[k] - b[k]) <= 1e-5 * abs(a[k]), k
+    for k in ("x0", "v0"):
+        assert _rel(a[k], b[k]) < 1e-5, k
+
+
+def test_free_particles_closed_form():
+    s = synth.random_box(300, [12.0, 12.0, 12.0], 2.0, 0.5, 8, charged=False)
+    s.type_epsilon[:] = 0.0
+    n_steps, dt = 30, 0.01
+    announce("adjoint free particles")
+    g = _run(s, n_steps, dt, 10)
+    v = s.vel.astype(np.float64)
+    n = s.n_atoms
+    T = n_steps
+    assert np.abs(g["x0"]).max() <= 1e-6 * np.abs(2.0 * T * dt * v / n).max()
+    # x_T - x_0 (about 0.3 here) carries the float32 rounding of 30 drifts
+    # of coordinates near 6 (a few 1e-7 each): about 1e-5 of the gradient
+    ref_v = 2.0 * T * T * dt * dt * v / n
+    assert np.abs(g["v0"] - ref_v).max() <= 1e-4 * np.abs(ref_v).max()
+    ref_dt = 2.0 * T * T * dt * (v * v).sum() / n
+    assert abs(g["dt"] - ref_dt) <= 1e-4 * abs(ref_dt)
+
+
+def test_harmonic_dimer_closed_form():
+    from test_oracle_adjoint import _dimer, _dimer_loss_closed_form
+    s = _dimer()
+    dt, T = 0.05, 60
+    announce("adjoint harmonic dimer")
+    g = _run(s, T, dt, 10)
+    L = _dimer_loss_closed_form(s, dt, 0.0, T)
+    h = 1e-30
+    dL_ddt = np.imag(_dimer_loss_closed_form(s, dt + 1j * h, 0.0, T)) / h
+    dL_dx = np.imag(_dimer_loss_closed_form(s, dt, 1j * h, T)) / h
+    assert abs(g["loss"] - L) <= 1e-5 * abs(L)
+    assert abs(g["dt"] - dL_ddt) <= 1e-4 * abs(dL_ddt), (g["dt"], dL_ddt)
+    assert abs(g["x0"][0, 0] - dL_dx) <= 1e-4 * abs(dL_dx), (g["x0"][0, 0], dL_dx)
+
+
+def test_unsupported_modes_are_refused():
+    import torch
+    import paper_2503_20541_amd as mdx
+    from paper_2503_20541_amd import trajectory as tj
+    s = synth.config_system("water375")
+    sim = tj.Simulation(s, 10, 10, options=mdx.MDX_OPT_HALF_LIST)
+    try:
+        x = torch.from_numpy(s.pos.copy()).cuda()
+        z = torch.zeros_like(x)
+        grad = torch.zeros(6, dtype=torch.float64, device="cuda:0")
+        gU = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+        with pytest.raises(mdx.MdxError) as e:
+            mdx.adjoint_begin(sim.ctx, x, z, z, gU, z.clone(), z.clone(), grad)
+        assert e.value.code == mdx.MDX_E_UNSUPPORTED
+    finally:
+        sim.close()
