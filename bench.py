@@ -62,6 +62,8 @@ def parse():
     p.add_argument("--steps", type=int, default=1000)
     p.add_argument("--warmup", type=int, default=100)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-adjoint", action="store_true",
+                   help="skip the forward+adjoint against plain forward timing (9k water)")
     p.add_argument("--equilibrate", type=int, default=3000,
                    help="steps of velocity-rescaled equilibration to 300 K before the warm-up "
                         "(0: start the timed run from the lattice start, which heats up)")
@@ -360,6 +362,73 @@ def ewald_direct_vs_pme():
               flush=True)
 
 
+def adjoint_ratio(reps=5):
+    """The metric's second half on the 9,000-atom water box: 100 velocity-
+    Verlet steps of 1 fs as a plain forward (mdx_integrate_step) against the
+    differentiable forward with checkpoints every 10 steps plus its reverse
+    pass (loss U(x_T)/N + MSD; gradients with respect to x0, v0, eps, sigma,
+    the O charge and dt), both timed with events on the context's stream,
+    median of `reps`."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2503_20541_amd as mdx
+    from paper_2503_20541_amd import trajectory as tj
+    s = synth.config_system("water9k")
+    n_steps, every, dt = 100, 10, 1.0
+    dev = torch.device("cuda:0")
+    dq = np.where(s.atom_type == 0, 1.0, -0.5).astype(np.float32)
+    sim = tj.Simulation(s, n_steps, every, charge_direction=dq)
+    stream = sim.stream
+    try:
+        def timed(fn):
+            out = []
+            for _ in range(reps + 1):
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                torch.cuda.synchronize()
+                a.record(stream)
+                fn()
+                b.record(stream)
+                torch.cuda.synchronize()
+                out.append(a.elapsed_time(b))
+            return float(np.median(out[1:]))      # the first is a warm-up
+
+        pos = torch.from_numpy(s.pos.copy()).to(dev)
+        vel = torch.from_numpy(s.vel.copy()).to(dev)
+        force = torch.zeros_like(pos)
+
+        def plain():
+            pos.copy_(torch.from_numpy(s.pos))
+            vel.copy_(torch.from_numpy(s.vel))
+            mdx.build_neighbors(sim.ctx, pos)
+            mdx.compute_nonbonded(sim.ctx, pos, force)
+            mdx.compute_pme(sim.ctx, pos, force)
+            mdx.integrate_step(sim.ctx, pos, vel, force, n_steps, dt)
+
+        def fwd_adj():
+            x0 = torch.from_numpy(s.pos.copy()).to(dev).requires_grad_(True)
+            v0 = torch.from_numpy(s.vel.copy()).to(dev).requires_grad_(True)
+            eps = torch.from_numpy(s.type_epsilon.copy()).to(dev).requires_grad_(True)
+            sig = torch.from_numpy(s.type_sigma.copy()).to(dev).requires_grad_(True)
+            tq = torch.zeros((), device=dev, requires_grad=True)
+            dtt = torch.tensor(dt, device=dev, requires_grad=True)
+            xT, UT = tj.trajectory(sim, x0, v0, eps, sig, tq, dtt)
+            L = UT / s.n_atoms + ((xT.double() - x0.double()) ** 2).sum() / s.n_atoms
+            L.backward()
+
+        t_fwd = timed(plain)
+        t_adj = timed(fwd_adj)
+        flags = mdx.get_status(sim.ctx)
+    finally:
+        sim.close()
+    return {"workload": "water9k: 3,000 flexible waters, PME 48^3, 100 steps of 1 fs, "
+                        "checkpoints every 10 steps, loss U(x_T)/N + MSD",
+            "ms_per_step_fwd": round(t_fwd / n_steps, 5),
+            "ms_per_step_fwd_adjoint": round(t_adj / n_steps, 5),
+            "ratio": round(t_adj / t_fwd, 3), "repetitions": reps, "status_flags": flags}
+
+
 def main():
     args = parse()
     if args.copy_probe > 0:
@@ -482,6 +551,8 @@ def main():
                                      f"{counts['listed_pairs'] - counts['interacting_pairs']} "
                                      "unique pairs per launch"},
         })
+    if not args.cpu_only and not args.no_adjoint:
+        result["adjoint"] = adjoint_ratio()
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(s)
     print(json.dumps(result), flush=True)

@@ -63,10 +63,11 @@ extern "C" {
                                           mdx_integrate_step the atoms left out
                                           are not integrated: results invalid,
                                           call mdx_build_neighbors)           */
-#define MDX_FLAG_CONSTRAINT   0x40u /* rigid water: SHAKE did not reach its
-                                       tolerance in 200 sweeps, or a molecule's
-                                       RATTLE system was singular (positions
-                                       or velocities of that molecule invalid) */
+#define MDX_FLAG_CONSTRAINT   0x40u /* rigid water: no SETTLE solution, SHAKE
+                                       did not reach its tolerance in 200
+                                       sweeps, or a molecule's RATTLE system
+                                       was singular (positions or velocities
+                                       of that molecule invalid) */
 
 /* ---- energy slots (FP64) ----------------------------------------------- */
 #define MDX_ENERGY_LJ         0  /* Eq. 4 (switched by Eq. 6 if enabled)        */
@@ -364,18 +365,20 @@ int mdx_set_langevin(mdx_ctx* ctx, double kT, double gamma, uint64_t seed);
  * option the paper uses for its longer time step, Sec. III; RATTLE with
  * velocity Verlet): mols (host int32[n_mol][3], caller atoms O, H1, H2, each
  * atom at most once) are held at |O-H| = d_oh and |H1-H2| = d_hh. After each
- * drift the three distances are restored by SHAKE iterations along the
- * previous bond vectors (float32, to a relative 2e-6 in r^2) with the same
- * correction over dt applied to the velocities, and after the closing kick
+ * drift the three distances are restored along the previous bond vectors
+ * with the same correction over dt applied to the velocities: in closed form
+ * (SETTLE, FP64 per molecule) when the two hydrogens of every molecule have
+ * the same mass, else by SHAKE iterations (float32, to a relative 2e-6 in
+ * r^2); both reach the same constrained positions. After the closing kick
  * the velocities are projected onto the constraints (r . v_rel = 0). The
  * bond and angle terms of these molecules may stay on (their energy is then
  * constant) or be zero; atoms in no listed molecule move freely (the step
  * then keeps a copy of the positions before the drift in a buffer of the
  * context). Every step then runs its own opening kernel (no fused
  * closing/opening), and the kinetic energy slot holds the kinetic energy
- * of the projected velocities. A molecule whose SHAKE iteration does not
- * reach its tolerance in 200 sweeps, or whose velocity system is singular,
- * latches MDX_FLAG_CONSTRAINT. n_mol = 0 switches it off. MDX_E_INVALID for
+ * of the projected velocities. A molecule with no SETTLE solution, whose
+ * SHAKE iteration does not reach its tolerance in 200 sweeps, or whose
+ * velocity system is singular, latches MDX_FLAG_CONSTRAINT. n_mol = 0 switches it off. MDX_E_INVALID for
  * bad indices or distances; MDX_E_UNSUPPORTED together with Langevin or
  * MDX_OPT_KAHAN_VV.
  */

@@ -14,6 +14,27 @@ plain definitions, in float64:
   r_c . (v'_a - v'_b) = 0 for every constraint, an exact 3 x 3 solve per
   molecule.
 * velocity_verlet_rattle: the velocity-Verlet step with both (RATTLE).
+* settle: the same position constraints in closed form (the method of
+  Miyamoto and Kollman, 1992, as derived below), for molecules with two
+  equal hydrogen masses.
+
+SETTLE, derivation. The SHAKE solution moves each atom by a combination of
+the old bond vectors, so (1) every displacement lies in the old molecular
+plane, (2) the centre of mass stays where the unconstrained step put it, and
+(3) sum_i x0_i x m_i (y'_i - y_i) = 0 (each constraint moves its two atoms
+by equal and opposite amounts along their old separation). In a frame with
+Z normal to the old plane and the origin at the centre of mass, (1) fixes
+every atom's Z coordinate at its unconstrained value. The rigid triangle
+(O at (0, ra), H at (-+rc, -rb), ra + rb its height h, ra = 2 m_H h / M)
+rotated by psi about Y and phi about X has Z coordinates ra sin(phi) (O) and
+-rb sin(phi) -+ rc sin(psi) cos(phi) (H1, H2), which give phi and psi; a
+rotation by theta about Z changes no Z, and (3)'s Z component,
+alpha sin(theta) + beta cos(theta) = gamma with
+  alpha = sum m (x0 x2 + y0 y2), beta = sum m (x0 y2 - y0 x2),
+  gamma = sum m (x0 y1 - y0 x1)
+(x0, y0: old in-plane coordinates, x2, y2: the triangle after phi and psi,
+x1, y1: unconstrained, all about the centres of mass), gives theta (the root
+next to theta = 0).
 """
 from __future__ import annotations
 
@@ -50,6 +71,58 @@ def shake(x_ref, y, mass, box, mols, d_oh, d_hh, tol=1e-12, max_iter=1000):
         if worst < tol:
             return y, it
     raise RuntimeError("SHAKE did not converge")
+
+
+def settle(x_ref, y, mass, box, mols, d_oh, d_hh):
+    """Closed-form solution of the position constraints (see the module
+    docstring): the same fixed point as shake(), without iterations."""
+    x_ref = np.asarray(x_ref, np.float64)
+    y = np.asarray(y, np.float64).copy()
+    L = np.asarray(box, np.float64)[:, None]
+    m = np.asarray(mass, np.float64)
+    mol = np.asarray(mols, np.int64)
+    ia, ib, ic = mol[:, 0], mol[:, 1], mol[:, 2]
+    mo, mh = m[ia], m[ib]
+    M = mo + 2.0 * mh
+    rc = 0.5 * d_hh
+    h = np.sqrt(d_oh * d_oh - rc * rc)
+    ra = 2.0 * mh * h / M
+    rb = h - ra
+    # old and new geometry relative to O (minimum image), then to the COM
+    ob0, oc0 = _mi(x_ref[:, ib] - x_ref[:, ia], L), _mi(x_ref[:, ic] - x_ref[:, ia], L)
+    ob1, oc1 = _mi(y[:, ib] - y[:, ia], L), _mi(y[:, ic] - y[:, ia], L)
+    com0 = (mh * ob0 + mh * oc0) / M
+    com1 = (mh * ob1 + mh * oc1) / M
+    old = [-com0, ob0 - com0, oc0 - com0]
+    new = [-com1, ob1 - com1, oc1 - com1]
+    Z = np.cross(ob0.T, oc0.T).T
+    Z /= np.sqrt((Z * Z).sum(axis=0))
+    X = np.cross(new[0].T, Z.T).T
+    X /= np.sqrt((X * X).sum(axis=0))
+    Y = np.cross(Z.T, X.T).T
+    to = lambda v: ((v * X).sum(axis=0), (v * Y).sum(axis=0), (v * Z).sum(axis=0))
+    o0, n1 = [to(v) for v in old], [to(v) for v in new]
+    sphi = n1[0][2] / ra
+    cphi = np.sqrt(1.0 - sphi * sphi)
+    spsi = (n1[1][2] - n1[2][2]) / (2.0 * rc * cphi)
+    cpsi = np.sqrt(1.0 - spsi * spsi)
+    t2 = [(0.0 * sphi, ra * cphi),
+          (-rc * cpsi, -rb * cphi - rc * spsi * sphi),
+          (rc * cpsi, -rb * cphi + rc * spsi * sphi)]
+    z2 = [ra * sphi, -rb * sphi + rc * spsi * cphi, -rb * sphi - rc * spsi * cphi]
+    w = [mo, mh, mh]
+    alpha = sum(wk * (o[0] * t[0] + o[1] * t[1]) for wk, o, t in zip(w, o0, t2))
+    beta = sum(wk * (o[0] * t[1] - o[1] * t[0]) for wk, o, t in zip(w, o0, t2))
+    gamma = sum(wk * (o[0] * n[1] - o[1] * n[0]) for wk, o, n in zip(w, o0, n1))
+    ab = alpha * alpha + beta * beta
+    sth = (alpha * gamma - beta * np.sqrt(ab - gamma * gamma)) / ab
+    cth = np.sqrt(1.0 - sth * sth)
+    cm = y[:, ia] + com1
+    for k, atom in enumerate((ia, ib, ic)):
+        x3 = t2[k][0] * cth - t2[k][1] * sth
+        y3 = t2[k][0] * sth + t2[k][1] * cth
+        y[:, atom] = cm + x3 * X + y3 * Y + z2[k] * Z
+    return y
 
 
 def rattle_velocities(x, v, mass, box, mols):

@@ -312,7 +312,81 @@ struct RigidArgs {
   int n_mol;
   float d[3];          // O-H1, O-H2, H1-H2
   const float* acc_over_m;
+  int settle;          // closed form (every molecule's hydrogens weigh the same)
 };
+
+__device__ __forceinline__ double3 d3(float3 v) { return make_double3(v.x, v.y, v.z); }
+__device__ __forceinline__ double3 operator+(double3 a, double3 b) {
+  return make_double3(a.x + b.x, a.y + b.y, a.z + b.z);
+}
+__device__ __forceinline__ double3 operator-(double3 a, double3 b) {
+  return make_double3(a.x - b.x, a.y - b.y, a.z - b.z);
+}
+__device__ __forceinline__ double3 operator*(double s, double3 a) {
+  return make_double3(s * a.x, s * a.y, s * a.z);
+}
+__device__ __forceinline__ double dot3(double3 a, double3 b) {
+  return a.x * b.x + a.y * b.y + a.z * b.z;
+}
+__device__ __forceinline__ double3 cross3(double3 a, double3 b) {
+  return make_double3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ double3 unit3(double3 a) { return rsqrt(dot3(a, a)) * a; }
+
+// SETTLE: the closed-form solution of the three distance constraints (the
+// fixed point SHAKE iterates to). Every displacement lies in the old plane,
+// the centre of mass is kept, and the constraint moves carry no torque about
+// the old plane's normal; in a frame with Z along that normal, the new Z
+// coordinates fix the triangle's tilts (phi about X, psi about Y) and the
+// torque condition alpha sin(theta) + beta cos(theta) = gamma its turn about
+// Z. ob0, oc0: old H1 - O, H2 - O; ob1, oc1: the same after the drift;
+// returns the displacements of O, H1, H2 from the drifted positions, false
+// for a geometry with no solution. FP64 throughout (vectors of ~1 A).
+__device__ bool settle_water(double3 ob0, double3 oc0, double3 ob1, double3 oc1, double mo,
+                             double mh, double d_oh, double d_hh, double3 dl[3]) {
+  const double M = mo + 2.0 * mh, rc = 0.5 * d_hh;
+  const double h = sqrt(d_oh * d_oh - rc * rc), ra = 2.0 * mh * h / M, rb = h - ra;
+  const double3 com0 = (mh / M) * (ob0 + oc0), com1 = (mh / M) * (ob1 + oc1);
+  const double3 o0[3] = {-1.0 * com0, ob0 - com0, oc0 - com0};
+  const double3 n1[3] = {-1.0 * com1, ob1 - com1, oc1 - com1};
+  const double3 Z = unit3(cross3(ob0, oc0));
+  const double3 X = unit3(cross3(n1[0], Z));
+  const double3 Y = cross3(Z, X);
+  double ox[3], oy[3], nx[3], ny[3], nz[3];
+  for (int k = 0; k < 3; ++k) {
+    ox[k] = dot3(o0[k], X);
+    oy[k] = dot3(o0[k], Y);
+    nx[k] = dot3(n1[k], X);
+    ny[k] = dot3(n1[k], Y);
+    nz[k] = dot3(n1[k], Z);
+  }
+  const double sphi = nz[0] / ra;
+  if (!(fabs(sphi) < 1.0)) return false;
+  const double cphi = sqrt(1.0 - sphi * sphi);
+  const double spsi = (nz[1] - nz[2]) / (2.0 * rc * cphi);
+  if (!(fabs(spsi) < 1.0)) return false;
+  const double cpsi = sqrt(1.0 - spsi * spsi);
+  const double tx[3] = {0.0, -rc * cpsi, rc * cpsi};
+  const double ty[3] = {ra * cphi, -rb * cphi - rc * spsi * sphi, -rb * cphi + rc * spsi * sphi};
+  const double tz[3] = {ra * sphi, -rb * sphi + rc * spsi * cphi, -rb * sphi - rc * spsi * cphi};
+  const double w[3] = {mo, mh, mh};
+  double al = 0.0, be = 0.0, ga = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    al += w[k] * (ox[k] * tx[k] + oy[k] * ty[k]);
+    be += w[k] * (ox[k] * ty[k] - oy[k] * tx[k]);
+    ga += w[k] * (ox[k] * ny[k] - oy[k] * nx[k]);
+  }
+  const double ab = al * al + be * be, disc = ab - ga * ga;
+  if (!(ab > 0.0) || !(disc >= 0.0)) return false;
+  const double sth = (al * ga - be * sqrt(disc)) / ab;
+  const double cth = sqrt(1.0 - sth * sth);
+  const double3 rel[3] = {make_double3(0.0, 0.0, 0.0), ob1, oc1};   // drifted, from O
+  for (int k = 0; k < 3; ++k) {
+    const double x3 = tx[k] * cth - ty[k] * sth, y3 = tx[k] * sth + ty[k] * cth;
+    dl[k] = com1 + (x3 * X + y3 * Y + tz[k] * Z) - rel[k];
+  }
+  return true;
+}
 
 __device__ __forceinline__ float3 mi3(float3 d, const CellGrid& cg) {
   return make_float3(min_image(0.f, d.x, cg.L[0], cg.hL[0]), min_image(0.f, d.y, cg.L[1], cg.hL[1]),
@@ -356,6 +430,17 @@ __global__ void __launch_bounds__(64) k_rigid_positions(RigidArgs r, OpenStep o,
     d0[c] = mi3(make_float3(y0[ca[c]].x - y0[cb[c]].x, y0[ca[c]].y - y0[cb[c]].y,
                             y0[ca[c]].z - y0[cb[c]].z), cg);
   }
+  if (r.settle) {
+    // closed form, FP64 (ratios of the masses only: 1 / (accel / m))
+    double3 dd[3];
+    const bool ok = settle_water(-1.0 * d3(ref[0]), -1.0 * d3(ref[1]), -1.0 * d3(d0[0]),
+                                 -1.0 * d3(d0[1]), 1.0 / (double)iw[0], 1.0 / (double)iw[1],
+                                 (double)r.d[0], (double)r.d[2], dd);
+    if (!ok) atomicOr(flags, MDX_FLAG_CONSTRAINT);
+    for (int k = 0; k < 3; ++k)
+      dl[k] = ok ? make_float3((float)dd[k].x, (float)dd[k].y, (float)dd[k].z)
+                 : make_float3(0.f, 0.f, 0.f);
+  } else {
   // The iteration moves the displacements dl (small numbers) rather than the
   // coordinates: the velocity correction dl/dt then carries no cancellation
   // between two coordinates of the size of the box.
@@ -383,6 +468,7 @@ __global__ void __launch_bounds__(64) k_rigid_positions(RigidArgs r, OpenStep o,
     if (worst < 2e-6f) break;
   }
   if (!(worst < 2e-6f)) atomicOr(flags, MDX_FLAG_CONSTRAINT);   // also for a NaN
+  }
   for (int k = 0; k < 3; ++k) {
     const int a = at[k];
     const float inv_dt = 1.0f / o.dt;
@@ -489,7 +575,8 @@ __global__ void __launch_bounds__(64) k_rigid_velocities(RigidArgs r, CellGrid c
 
 hipError_t launch_rigid_positions(Ctx& c, const float* x_old, const float* y_in, float* pos,
                                   float* vel, float dt, const StepGates& g) {
-  RigidArgs r{c.rigid_mols, c.n_rigid, {c.rigid_d[0], c.rigid_d[1], c.rigid_d[2]}, c.hdt_scale};
+  RigidArgs r{c.rigid_mols, c.n_rigid, {c.rigid_d[0], c.rigid_d[1], c.rigid_d[2]}, c.hdt_scale,
+              c.rigid_settle ? 1 : 0};
   // 64-lane groups: one molecule per lane, and enough groups to reach every CU
   k_rigid_positions<<<(c.n_rigid + 63) / 64, 64, 0, c.stream>>>(r, make_open(c, pos, pos, dt, g),
                                                                 x_old, y_in, pos, vel, c.inv_perm,
@@ -499,7 +586,8 @@ hipError_t launch_rigid_positions(Ctx& c, const float* x_old, const float* y_in,
 
 hipError_t launch_rigid_velocities(Ctx& c, const float* pos, float* vel, bool energy,
                                    int* blocks) {
-  RigidArgs r{c.rigid_mols, c.n_rigid, {c.rigid_d[0], c.rigid_d[1], c.rigid_d[2]}, c.hdt_scale};
+  RigidArgs r{c.rigid_mols, c.n_rigid, {c.rigid_d[0], c.rigid_d[1], c.rigid_d[2]}, c.hdt_scale,
+              c.rigid_settle ? 1 : 0};
   const int nb = (c.n_rigid + 63) / 64;
   if (blocks) *blocks = nb;
   if (energy && nb > c.max_blocks) return hipErrorInvalidValue;   // partial rows too short

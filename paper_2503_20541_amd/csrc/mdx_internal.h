@@ -133,6 +133,7 @@ struct Ctx {
   int n_rigid = 0;
   int* rigid_mols = nullptr;   // [n_rigid][3] caller atoms O, H1, H2
   float rigid_d[3] = {0.f, 0.f, 0.f};
+  bool rigid_settle = false;   // closed form: both hydrogens of every molecule weigh the same
   // direct reciprocal Ewald sum (mdx_compute_ewald_direct): scratch for the
   // largest n_max asked for so far
   int ew_nmax = 0;

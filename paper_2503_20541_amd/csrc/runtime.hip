@@ -1005,6 +1005,11 @@ int mdx_set_rigid_water(mdx_ctx* x, const int32_t* mols, int32_t n_mol, double d
   c.n_rigid = n_mol;
   c.rigid_d[0] = c.rigid_d[1] = (float)d_oh;
   c.rigid_d[2] = (float)d_hh;
+  // the closed form (SETTLE) when every molecule's hydrogens weigh the same
+  // and the triangle exists, SHAKE iterations otherwise
+  c.rigid_settle = d_hh < 2.0 * d_oh;
+  for (int64_t k = 0; k < n_mol && c.rigid_settle; ++k)
+    c.rigid_settle = c.mass_h[mols[3 * k + 1]] == c.mass_h[mols[3 * k + 2]];
   return MDX_OK;
 }
 

@@ -114,3 +114,30 @@ def test_rigid_water_conserves_energy_at_two_femtoseconds():
     ke1 = 0.5 * float((m * r["vel"] ** 2).sum()) / acc
     e1 = E(r["pos"])[0] + ke1
     assert abs(e1 - e0) < 0.02 * ke1, (e0, e1, ke1)
+
+
+@pytest.mark.parametrize("scale", [0.01, 0.1])
+def test_settle_closed_form_equals_converged_shake(scale):
+    # SETTLE and SHAKE solve the same equations (displacements along the old
+    # bond vectors); the closed form must land on SHAKE's fixed point, keep
+    # the centre of mass, move atoms only within the old plane, and satisfy
+    # the constraints to rounding
+    s, mols = _water()
+    x = s.pos.astype(np.float64)
+    x, _ = constraints.shake(x, x, s.mass, s.box, mols, D_OH, D_HH)
+    y = x + np.random.default_rng(7).normal(0.0, scale, x.shape)
+    ys, _ = constraints.shake(x, y, s.mass, s.box, mols, D_OH, D_HH)
+    yt = constraints.settle(x, y, s.mass, s.box, mols, D_OH, D_HH)
+    assert np.abs(yt - ys).max() < 1e-10
+    doh1, doh2, dhh = _dists(yt, s.box, mols)
+    for d, ref in ((doh1, D_OH), (doh2, D_OH), (dhh, D_HH)):
+        assert np.abs(d / ref - 1).max() < 1e-13
+    m = s.mass.astype(np.float64)
+    a, b, c = mols[:, 0], mols[:, 1], mols[:, 2]
+    com = lambda z: m[a] * z[:, a] + m[b] * z[:, b] + m[c] * z[:, c]
+    assert np.abs(com(yt) - com(y)).max() < 1e-12 * np.abs(com(y)).max()
+    L = s.box.astype(np.float64)[:, None]
+    mi = lambda d: d - L * np.round(d / L)
+    nrm = np.cross(mi(x[:, b] - x[:, a]).T, mi(x[:, c] - x[:, a]).T).T
+    for k in (a, b, c):
+        assert np.abs((nrm * (yt[:, k] - y[:, k])).sum(axis=0)).max() < 1e-12
