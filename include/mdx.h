@@ -81,6 +81,7 @@ extern "C" {
 #define MDX_N_ENERGY          8
 
 typedef struct mdx_ctx mdx_ctx;
+typedef struct mdx_batch mdx_batch;
 
 /*
  * System description (all pointers host, read during mdx_create only).
@@ -327,6 +328,66 @@ int mdx_ewald_direct_noalloc_bytes(int32_t n_atoms, int32_t n_max, int64_t* byte
  */
 int mdx_integrate_step(mdx_ctx* ctx, float* pos, float* vel, float* force, int32_t n_steps,
                        float dt, double* energies);
+
+/*
+ * Graph replay of mdx_integrate_step (the chunked step loop recorded once as
+ * a HIP graph and launched as one unit, instead of a dozen launches per
+ * step). With chunk > 0 (a multiple of rebuild_every), a call whose n_steps
+ * is a multiple of chunk runs as chunk-step graph launches: the first one
+ * records the chunk's launches on a library-owned stream and instantiates
+ * them; later ones replay it as long as the call has the same pos, vel,
+ * force and dt, the context has reallocated or reconfigured nothing (list
+ * growth, mdx_load_state, mdx_set_rigid_water, mdx_set_langevin) and the
+ * rebuild phase is the same; otherwise the chunk is recorded again. A call
+ * with energies, timing enabled or Langevin dynamics runs its launches one
+ * by one as before. Results are bit for bit those of the launch-by-launch
+ * path. chunk = 0 switches it off. MDX_E_INVALID for chunk < 0 or not a
+ * multiple of rebuild_every.
+ */
+int mdx_set_graph(mdx_ctx* ctx, int32_t chunk);
+
+/*
+ * Batched replicas (independent systems stepped together, e.g. the chains of
+ * the paper's Hamiltonian Monte Carlo tuning, Sec. IV, which uses many
+ * replicas): mdx_batch_create takes n_rep contexts (host array; each made by
+ * mdx_create from its own descriptor, box and PME grid; each context at most
+ * once; chunk a multiple of every replica's rebuild_every) on one device.
+ * mdx_batch_integrate(b, pos, vel, force, n_steps, dt, stream) advances every
+ * replica r by n_steps (a multiple of chunk) steps of mdx_integrate_step with
+ * its own pos[r], vel[r], force[r] (host arrays of dev [3][N_r] pointers) and
+ * dt[r] (host array). mdx_batch_create switches every member to graph
+ * replay with the batch's chunk (mdx_set_graph); each replica's chunks are
+ * then single graph launches on a stream of the batch's own (one per
+ * replica, forked from `stream` and joined back into it by events), so the
+ * small systems run side by side on the chip and the host issues one launch
+ * per replica and chunk instead of a dozen per step. Results are bit for bit
+ * those of mdx_integrate_step on each replica. Work on a replica's own
+ * stream must be complete or ordered before `stream`. MDX_E_INVALID for bad
+ * arguments, MDX_E_NO_LIST if a replica has no list yet, MDX_E_UNSUPPORTED
+ * with Langevin dynamics or timing on a replica. mdx_batch_destroy frees the
+ * batch (not the contexts).
+ */
+int mdx_batch_create(mdx_batch** out, mdx_ctx* const* ctxs, int32_t n_rep, int32_t chunk);
+int mdx_batch_integrate(mdx_batch* b, float* const* pos, float* const* vel, float* const* force,
+                        int32_t n_steps, const float* dt, void* hip_stream);
+int mdx_batch_destroy(mdx_batch* b);
+
+/*
+ * Autotuner of the tuning fields of a descriptor: times `steps` steps (after
+ * `steps` untimed ones) of fresh contexts for each column width
+ * cell_divisions = 1..4, each with the list built phase by phase and with
+ * MDX_OPT_COOPERATIVE_BUILD, from pos, vel (dev [3][N], copied) with step dt
+ * on `stream`, and returns the fastest in *cell_divisions and *options (d's
+ * options with the build-mode bit of the winner). ms_per_step (host
+ * double[8] or NULL): the times, build phase by phase then cooperative,
+ * cell_divisions 1..4 each. None of these choices changes the list or the
+ * forces' pairs (the list is independent of the column grid); the 4 x 4
+ * cluster tile is fixed by the kernels' lane layout. Synchronising;
+ * allocates while it runs.
+ */
+int mdx_autotune(const mdx_system_desc* d, const float* pos, const float* vel, float dt,
+                 int32_t steps, void* hip_stream, int32_t* cell_divisions, uint32_t* options,
+                 double* ms_per_step);
 
 /* Synchronising. Returns the latched MDX_FLAG_* bits in *flags and clears them. */
 int mdx_get_status(mdx_ctx* ctx, uint32_t* flags);

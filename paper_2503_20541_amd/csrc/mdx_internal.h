@@ -91,6 +91,12 @@ struct AdjScratch {
 struct Ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  // the launches are being captured into a graph: no events recorded by a
+  // kernel's own dispatch (explicit records instead)
+  bool capturing = false;
+  // bumped by every change that a captured graph would not see (buffers
+  // reallocated, rigid water, Langevin, a new list build phase)
+  uint64_t version = 0;
   int n = 0;              // atoms
   int npad = 0;           // n rounded up to a wave multiple (ELL stride)
   float box[3];

@@ -857,10 +857,15 @@ hipError_t launch_build_list(Ctx& c, const float* pos, const int* gate, hipEvent
   k_bin_scan<<<nb, 256, 0, s>>>(a);
   // the column sort completes the slot positions and the PME brick ranges:
   // `done` is recorded by its own dispatch
-  if (done) {
+  if (done && !c.capturing) {
     void* args[] = {&a};
     hipError_t e = hipExtLaunchKernel(reinterpret_cast<const void*>(k_col_sort), dim3(ncol),
                                       dim3(kColThreads), args, 0, s, nullptr, done, 0);
+    if (e != hipSuccess) return e;
+  } else if (done) {
+    // under graph capture the event becomes a dependency edge after the sort
+    k_col_sort<<<ncol, kColThreads, 0, s>>>(a);
+    hipError_t e = hipEventRecord(done, s);
     if (e != hipSuccess) return e;
   } else {
     k_col_sort<<<ncol, kColThreads, 0, s>>>(a);

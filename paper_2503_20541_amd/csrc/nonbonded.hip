@@ -451,13 +451,21 @@ hipError_t launch_nonbonded(Ctx& c, bool energy, const int* gate_now, const int*
   // the timing events (optional) are recorded by the dispatch itself: no
   // marker packets around the kernel
 #define MDX_PAIR(E, C, S, H, V)                                                              \
-  hipExtLaunchKernelGGL(k_pair<E, C, S, H, V>, dim3(nb), dim3(256), lds, c.stream, t_start,   \
-                        t_stop, 0u, static_cast<const float4*>(c.xs),                         \
-                        static_cast<const int*>(c.ts), static_cast<const uint2*>(c.tiles),    \
-                        static_cast<const int*>(c.tile_count), static_cast<const int*>(c.meta), \
-                        c.nl_cap, pp, static_cast<const float4*>(c.lj_f),                     \
-                        static_cast<const double2*>(c.lj_d), c.fslot, c.max_slots, c.partials, \
-                        c.max_blocks, pr)
+  do {                                                                                        \
+  if (t_start || t_stop)                                                                      \
+    hipExtLaunchKernelGGL(k_pair<E, C, S, H, V>, dim3(nb), dim3(256), lds, c.stream, t_start, \
+                          t_stop, 0u, static_cast<const float4*>(c.xs),                       \
+                          static_cast<const int*>(c.ts), static_cast<const uint2*>(c.tiles),  \
+                          static_cast<const int*>(c.tile_count),                              \
+                          static_cast<const int*>(c.meta), c.nl_cap, pp,                      \
+                          static_cast<const float4*>(c.lj_f),                                 \
+                          static_cast<const double2*>(c.lj_d), c.fslot, c.max_slots,          \
+                          c.partials, c.max_blocks, pr);                                      \
+  else                                                                                        \
+    k_pair<E, C, S, H, V><<<nb, 256, lds, c.stream>>>(c.xs, c.ts, c.tiles, c.tile_count, c.meta, \
+                                                      c.nl_cap, pp, c.lj_f, c.lj_d, c.fslot,  \
+                                                      c.max_slots, c.partials, c.max_blocks, pr); \
+  } while (0)
 #define MDX_PAIR_H(E, C, S)             \
   if (c.half_list)                      \
     MDX_PAIR(E, C, S, true, false);     \

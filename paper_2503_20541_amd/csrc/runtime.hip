@@ -25,6 +25,22 @@ struct mdx_ctx {
   // from and joined back into the context's stream every step
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // graph replay of integrate_step chunks (mdx_set_graph): the chunk length,
+  // the stream captures are recorded on, the instantiated graph and what it
+  // was captured for
+  int graph_chunk = 0;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  struct GraphKey {
+    const float* pos = nullptr;
+    const float* vel = nullptr;
+    const float* force = nullptr;
+    float dt = 0.f;
+    uint64_t version = 0;
+    int steps_since_build = -2;
+  } gkey;
+  int64_t graph_launches = 0;
 };
 
 namespace {
@@ -164,6 +180,7 @@ int alloc_list(mdx_ctx* x, int cap) {
   dev_free(x, c.ptiles);
   c.tiles = nullptr;
   c.ptiles = nullptr;
+  c.version++;   // a graph captured before holds the old addresses
   int rc = dev_alloc(x, &c.tiles, (size_t)cap * c.max_clusters);
   if (rc != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.ptiles, (size_t)cap * c.max_clusters)) != MDX_OK) return rc;
@@ -633,6 +650,9 @@ int mdx_destroy(mdx_ctx* x) {
   }
   if (x->ev_fork) (void)hipEventDestroy(x->ev_fork);
   if (x->ev_join) (void)hipEventDestroy(x->ev_join);
+  if (x->gexec) (void)hipGraphExecDestroy(x->gexec);
+  if (x->graph) (void)hipGraphDestroy(x->graph);
+  if (x->cap) (void)hipStreamDestroy(x->cap);
   for (auto& v : x->ev)
     for (auto& p : v) {
       (void)hipEventDestroy(p.first);
@@ -673,6 +693,7 @@ int mdx_build_neighbors(mdx_ctx* x, const float* pos) {
     MDX_TRY(hipMemcpy(&fl, c.flags, sizeof(unsigned), hipMemcpyDeviceToHost));
     if (fl & MDX_FLAG_CELL_OVERFLOW) return MDX_E_UNSUPPORTED;
     if (fl & MDX_FLAG_COLUMN_OVERFLOW) {
+      c.version++;
       dev_free(x, c.col_atoms);
       c.col_atoms = nullptr;
       c.col_cap = std::min(c.n, 2 * c.col_cap);
@@ -808,9 +829,14 @@ int mdx_compute_pme(mdx_ctx* x, const float* pos, float* force, double* energy, 
   return MDX_OK;
 }
 
-int mdx_integrate_step(mdx_ctx* x, float* pos, float* vel, float* force, int32_t n_steps,
-                       float dt, double* energies) {
-  if (check_ctx(x) || !pos || !vel || !force || n_steps < 1 || !(dt > 0.f)) return MDX_E_INVALID;
+}  // extern "C"
+
+namespace {
+
+// The steps of mdx_integrate_step as launches on the context's stream (and
+// its second stream); under graph capture the same sequence is recorded.
+int integrate_eager(mdx_ctx* x, float* pos, float* vel, float* force, int32_t n_steps,
+                    float dt, double* energies) {
   Ctx& c = x->c;
   if (c.steps_since_build < 0) {
     MDX_TRY(mdx::launch_build_list(c, pos));
@@ -880,9 +906,12 @@ int mdx_integrate_step(mdx_ctx* x, float* pos, float* vel, float* force, int32_t
       std::pair<hipEvent_t, hipEvent_t>* tslot;
       MDX_TRY(timing_begin(x, MDX_TIMING_PME, x->aux, &tslot));
       MDX_TRY(mdx::launch_pme_spread(c, x->aux, nullptr));
-      MDX_TRY(mdx::launch_pme_fft(c, x->aux, tslot ? nullptr : x->ev_join));
+      // the join event is recorded by the last pass's dispatch, or (timing,
+      // graph capture) explicitly after it
+      const bool by_dispatch = !tslot && !c.capturing;
+      MDX_TRY(mdx::launch_pme_fft(c, x->aux, by_dispatch ? x->ev_join : nullptr));
       MDX_TRY(timing_end(tslot, x->aux));
-      if (tslot) MDX_TRY(hipEventRecord(x->ev_join, x->aux));
+      if (!by_dispatch) MDX_TRY(hipEventRecord(x->ev_join, x->aux));
     }
     {
       // timed by events that the pair kernel's dispatch records (marker
@@ -925,6 +954,262 @@ int mdx_integrate_step(mdx_ctx* x, float* pos, float* vel, float* force, int32_t
   if (pos_cur != pos)
     MDX_TRY(hipMemcpyAsync(pos, pos_cur, sizeof(float) * 3 * (size_t)c.n,
                            hipMemcpyDeviceToDevice, c.stream));
+  return MDX_OK;
+}
+
+// A chunk of `chunk` steps replays as one graph when nothing it recorded has
+// changed: the same buffers and dt, no reallocation or configuration change,
+// the same rebuild phase, no energies, timing or Langevin (whose noise is
+// keyed by the step index the launches carry).
+bool graph_eligible(const mdx_ctx* x, int32_t n_steps, double* energies) {
+  const Ctx& c = x->c;
+  return x->graph_chunk > 0 && n_steps % x->graph_chunk == 0 && !energies && x->timing == 0 &&
+         !c.langevin && c.steps_since_build >= 0;
+}
+
+bool graph_matches(const mdx_ctx* x, const float* pos, const float* vel, const float* force,
+                   float dt) {
+  const mdx_ctx::GraphKey& k = x->gkey;
+  return x->gexec && k.pos == pos && k.vel == vel && k.force == force && k.dt == dt &&
+         k.version == x->c.version && k.steps_since_build == x->c.steps_since_build;
+}
+
+// Records one chunk on the capture stream (launches are recorded, nothing
+// runs; the host counters advance as for an eager chunk) and instantiates it.
+int capture_chunk(mdx_ctx* x, float* pos, float* vel, float* force, float dt) {
+  Ctx& c = x->c;
+  if (!x->cap) MDX_TRY(hipStreamCreateWithFlags(&x->cap, hipStreamNonBlocking));
+  if (x->gexec) (void)hipGraphExecDestroy(x->gexec);
+  if (x->graph) (void)hipGraphDestroy(x->graph);
+  x->gexec = nullptr;
+  x->graph = nullptr;
+  mdx_ctx::GraphKey key{pos, vel, force, dt, c.version, c.steps_since_build};
+  hipStream_t user = c.stream;
+  c.stream = x->cap;
+  c.capturing = true;
+  hipError_t e = hipStreamBeginCapture(x->cap, hipStreamCaptureModeRelaxed);
+  int rc = e == hipSuccess ? integrate_eager(x, pos, vel, force, x->graph_chunk, dt, nullptr)
+                           : MDX_E_HIP;
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(x->cap, &g);
+  c.stream = user;
+  c.capturing = false;
+  if (rc != MDX_OK || e2 != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return rc != MDX_OK ? rc : MDX_E_HIP;
+  }
+  x->graph = g;
+  MDX_TRY(hipGraphInstantiate(&x->gexec, g, nullptr, nullptr, 0));
+  // the rebuild phase repeats every chunk (chunk is a multiple of the cadence)
+  x->gkey = key;
+  return MDX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mdx_integrate_step(mdx_ctx* x, float* pos, float* vel, float* force, int32_t n_steps,
+                       float dt, double* energies) {
+  if (check_ctx(x) || !pos || !vel || !force || n_steps < 1 || !(dt > 0.f)) return MDX_E_INVALID;
+  Ctx& c = x->c;
+  if (c.steps_since_build < 0) {
+    MDX_TRY(mdx::launch_build_list(c, pos));
+    c.steps_since_build = 0;
+  }
+  if (!graph_eligible(x, n_steps, energies)) return integrate_eager(x, pos, vel, force, n_steps,
+                                                                     dt, energies);
+  for (int done = 0; done < n_steps; done += x->graph_chunk) {
+    if (!graph_matches(x, pos, vel, force, dt)) {
+      // the capture advances the host counters by one chunk without running
+      // it; the launch below runs it
+      if (int rc = capture_chunk(x, pos, vel, force, dt)) return rc;
+    } else {
+      c.steps_taken += x->graph_chunk;
+    }
+    MDX_TRY(hipGraphLaunch(x->gexec, c.stream));
+    x->graph_launches++;
+  }
+  return MDX_OK;
+}
+
+}  // extern "C"
+
+struct mdx_batch {
+  std::vector<mdx_ctx*> ctx;
+  int chunk = 0;
+  std::vector<hipStream_t> streams;   // per replica: the stream its graph launches go to
+  hipEvent_t ev_start = nullptr;      // the caller's stream reached the batch call
+  std::vector<hipEvent_t> ev_end;     // per replica: its launches are done
+};
+
+namespace {
+
+// Mean time per step of `steps` steps of a fresh context for desc (after
+// `steps` untimed ones), from events on `stream`.
+int time_config(const mdx_system_desc* d, const float* pos, const float* vel, float dt,
+                int steps, hipStream_t stream, double* ms) {
+  mdx_ctx* x = nullptr;
+  int rc = mdx_create(&x, d, stream);
+  if (rc != MDX_OK) return rc;
+  const size_t b3 = sizeof(float) * 3 * (size_t)d->n_atoms;
+  float *p = nullptr, *v = nullptr, *f = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto done = [&](int code) {
+    if (p) (void)hipFree(p);
+    if (v) (void)hipFree(v);
+    if (f) (void)hipFree(f);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    mdx_destroy(x);
+    return code;
+  };
+  if (hipMalloc(&p, b3) != hipSuccess || hipMalloc(&v, b3) != hipSuccess ||
+      hipMalloc(&f, b3) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+      hipEventCreate(&e1) != hipSuccess)
+    return done(MDX_E_OUT_OF_MEMORY);
+  if (hipMemcpyAsync(p, pos, b3, hipMemcpyDeviceToDevice, stream) != hipSuccess ||
+      hipMemcpyAsync(v, vel, b3, hipMemcpyDeviceToDevice, stream) != hipSuccess ||
+      hipMemsetAsync(f, 0, b3, stream) != hipSuccess)
+    return done(MDX_E_HIP);
+  if ((rc = mdx_build_neighbors(x, p)) != MDX_OK) return done(rc);
+  if ((rc = mdx_compute_nonbonded(x, p, f, nullptr, nullptr)) != MDX_OK) return done(rc);
+  if (x->c.has_pme && (rc = mdx_compute_pme(x, p, f, nullptr, nullptr)) != MDX_OK)
+    return done(rc);
+  if ((rc = mdx_integrate_step(x, p, v, f, steps, dt, nullptr)) != MDX_OK) return done(rc);
+  if (hipEventRecord(e0, stream) != hipSuccess) return done(MDX_E_HIP);
+  if ((rc = mdx_integrate_step(x, p, v, f, steps, dt, nullptr)) != MDX_OK) return done(rc);
+  if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+    return done(MDX_E_HIP);
+  float t = 0.f;
+  if (hipEventElapsedTime(&t, e0, e1) != hipSuccess) return done(MDX_E_HIP);
+  *ms = (double)t / steps;
+  return done(MDX_OK);
+}
+
+}  // namespace
+
+extern "C" {
+
+int mdx_batch_create(mdx_batch** out, mdx_ctx* const* ctxs, int32_t n_rep, int32_t chunk) {
+  if (!out) return MDX_E_INVALID;
+  *out = nullptr;
+  if (!ctxs || n_rep < 1 || chunk < 1) return MDX_E_INVALID;
+  for (int r = 0; r < n_rep; ++r) {
+    if (!ctxs[r]) return MDX_E_INVALID;
+    if (chunk % ctxs[r]->c.rebuild_every != 0) return MDX_E_INVALID;
+    for (int q = 0; q < r; ++q)
+      if (ctxs[q] == ctxs[r]) return MDX_E_INVALID;   // each context once
+  }
+  mdx_batch* b = new (std::nothrow) mdx_batch();
+  if (!b) return MDX_E_OUT_OF_MEMORY;
+  b->ctx.assign(ctxs, ctxs + n_rep);
+  b->chunk = chunk;
+  b->ev_end.assign(n_rep, nullptr);
+  b->streams.assign(n_rep, nullptr);
+  const unsigned fl = hipEventDisableTiming;
+  bool ok = hipEventCreateWithFlags(&b->ev_start, fl) == hipSuccess;
+  for (int r = 0; r < n_rep && ok; ++r)
+    ok = hipEventCreateWithFlags(&b->ev_end[r], fl) == hipSuccess &&
+         hipStreamCreateWithFlags(&b->streams[r], hipStreamNonBlocking) == hipSuccess;
+  if (!ok) {
+    mdx_batch_destroy(b);
+    return MDX_E_HIP;
+  }
+  // every member replays its steps in graphs of the batch's chunk
+  for (int r = 0; r < n_rep; ++r)
+    if (mdx_set_graph(ctxs[r], chunk) != MDX_OK) {
+      mdx_batch_destroy(b);
+      return MDX_E_INVALID;
+    }
+  *out = b;
+  return MDX_OK;
+}
+
+int mdx_batch_destroy(mdx_batch* b) {
+  if (!b) return MDX_OK;
+  for (hipStream_t st : b->streams)
+    if (st) {
+      (void)hipStreamSynchronize(st);
+      (void)hipStreamDestroy(st);
+    }
+  for (hipEvent_t e : b->ev_end)
+    if (e) (void)hipEventDestroy(e);
+  if (b->ev_start) (void)hipEventDestroy(b->ev_start);
+  delete b;
+  return MDX_OK;
+}
+
+int mdx_batch_integrate(mdx_batch* b, float* const* pos, float* const* vel, float* const* force,
+                        int32_t n_steps, const float* dt, void* hip_stream) {
+  if (!b || !pos || !vel || !force || !dt || n_steps < 1 || n_steps % b->chunk != 0)
+    return MDX_E_INVALID;
+  hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  const size_t n = b->ctx.size();
+  for (size_t r = 0; r < n; ++r) {
+    mdx_ctx* x = b->ctx[r];
+    if (!pos[r] || !vel[r] || !force[r] || !(dt[r] > 0.f)) return MDX_E_INVALID;
+    if (x->c.langevin || x->timing) return MDX_E_UNSUPPORTED;
+    if (x->c.steps_since_build < 0) return MDX_E_NO_LIST;
+  }
+  // every replica on its own stream, ordered after the caller's stream and
+  // joined back into it; each replica's chunks are its own graph launches
+  MDX_TRY(hipEventRecord(b->ev_start, stream));
+  for (size_t r = 0; r < n; ++r) {
+    mdx_ctx* x = b->ctx[r];
+    hipStream_t user = x->c.stream;
+    x->c.stream = b->streams[r];
+    int rc = hipStreamWaitEvent(b->streams[r], b->ev_start, 0) == hipSuccess ? MDX_OK : MDX_E_HIP;
+    if (rc == MDX_OK) rc = mdx_integrate_step(x, pos[r], vel[r], force[r], n_steps, dt[r], nullptr);
+    if (rc == MDX_OK && (hipEventRecord(b->ev_end[r], b->streams[r]) != hipSuccess ||
+                         hipStreamWaitEvent(stream, b->ev_end[r], 0) != hipSuccess))
+      rc = MDX_E_HIP;
+    x->c.stream = user;
+    if (rc != MDX_OK) return rc;
+  }
+  return MDX_OK;
+}
+
+int mdx_autotune(const mdx_system_desc* d, const float* pos, const float* vel, float dt,
+                 int32_t steps, void* hip_stream, int32_t* cell_divisions, uint32_t* options,
+                 double* ms_per_step) {
+  if (!d || !pos || !vel || !(dt > 0.f) || steps < 1 || !cell_divisions || !options)
+    return MDX_E_INVALID;
+  hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  double best = 0.0;
+  int best_m = 0;
+  uint32_t best_o = 0;
+  for (int coop = 0; coop < 2; ++coop)
+    for (int m = 1; m <= 4; ++m) {
+      mdx_system_desc t = *d;
+      t.cell_divisions = m;
+      t.options = (d->options & ~(uint32_t)MDX_OPT_COOPERATIVE_BUILD) |
+                  (coop ? (uint32_t)MDX_OPT_COOPERATIVE_BUILD : 0u);
+      double ms = 0.0;
+      int rc = time_config(&t, pos, vel, dt, steps, stream, &ms);
+      if (rc != MDX_OK) return rc;
+      if (ms_per_step) ms_per_step[coop * 4 + m - 1] = ms;
+      if (best_m == 0 || ms < best) {
+        best = ms;
+        best_m = m;
+        best_o = t.options;
+      }
+    }
+  *cell_divisions = best_m;
+  *options = best_o;
+  return MDX_OK;
+}
+
+int mdx_set_graph(mdx_ctx* x, int32_t chunk) {
+  if (check_ctx(x) || chunk < 0) return MDX_E_INVALID;
+  Ctx& c = x->c;
+  if (chunk > 0 && chunk % c.rebuild_every != 0) return MDX_E_INVALID;
+  x->graph_chunk = chunk;
+  if (x->gexec) (void)hipGraphExecDestroy(x->gexec);
+  if (x->graph) (void)hipGraphDestroy(x->graph);
+  x->gexec = nullptr;
+  x->graph = nullptr;
   return MDX_OK;
 }
 
@@ -1002,6 +1287,7 @@ int mdx_set_rigid_water(mdx_ctx* x, const int32_t* mols, int32_t n_mol, double d
   if (n_mol > 0)
     MDX_TRY(hipMemcpy(c.rigid_mols, mols, sizeof(int) * 3 * (size_t)n_mol,
                       hipMemcpyHostToDevice));
+  c.version++;
   c.n_rigid = n_mol;
   c.rigid_d[0] = c.rigid_d[1] = (float)d_oh;
   c.rigid_d[2] = (float)d_hh;
@@ -1020,6 +1306,7 @@ int mdx_set_langevin(mdx_ctx* x, double kT, double gamma, uint64_t seed) {
   Ctx& c = x->c;
   if (c.xc && gamma > 0.0) return MDX_E_UNSUPPORTED;
   if (c.n_rigid > 0 && gamma > 0.0) return MDX_E_UNSUPPORTED;
+  c.version++;
   c.langevin = gamma > 0.0;
   c.lv_kT = kT;
   c.lv_gamma = gamma;
@@ -1170,6 +1457,7 @@ int mdx_load_state(mdx_ctx* x, const void* state, int64_t size) {
     if (rc != MDX_OK) return rc;
     if (c.nl_cap != h.nl_cap) return MDX_E_INVALID;   // not a capacity alloc_list makes
   }
+  c.version++;
   if (h.col_cap != c.col_cap) {
     dev_free(x, c.col_atoms);
     c.col_atoms = nullptr;

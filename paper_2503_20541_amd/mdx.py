@@ -72,7 +72,9 @@ EXPORTED = ("mdx_error_string", "mdx_create", "mdx_destroy", "mdx_set_stream",
             "mdx_compute_ewald_direct", "mdx_set_rigid_water", "mdx_state_size",
             "mdx_save_state", "mdx_load_state", "mdx_compute_ewald_direct_noalloc",
             "mdx_ewald_direct_noalloc_bytes", "mdx_set_parameters", "mdx_set_charge_direction",
-            "mdx_adjoint_begin", "mdx_adjoint_segment", "mdx_reset_images", "mdx_get_unwrapped")
+            "mdx_adjoint_begin", "mdx_adjoint_segment", "mdx_reset_images", "mdx_get_unwrapped",
+            "mdx_set_graph", "mdx_batch_create", "mdx_batch_integrate", "mdx_batch_destroy",
+            "mdx_autotune")
 
 _fp = ctypes.POINTER(ctypes.c_float)
 _ip = ctypes.POINTER(ctypes.c_int32)
@@ -139,6 +141,16 @@ _lib.mdx_adjoint_begin.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.mdx_adjoint_segment.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_float,
                                      ctypes.c_int32, _vp, _vp, _vp]
 _lib.mdx_reset_images.argtypes = [_vp]
+_lib.mdx_set_graph.argtypes = [_vp, ctypes.c_int32]
+_lib.mdx_batch_create.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int32,
+                                  ctypes.c_int32]
+_lib.mdx_batch_integrate.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                     ctypes.POINTER(_vp), ctypes.c_int32,
+                                     ctypes.POINTER(ctypes.c_float), _vp]
+_lib.mdx_batch_destroy.argtypes = [_vp]
+_lib.mdx_autotune.argtypes = [ctypes.POINTER(SystemDesc), _vp, _vp, ctypes.c_float,
+                              ctypes.c_int32, _vp, ctypes.POINTER(ctypes.c_int32),
+                              ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_double)]
 _lib.mdx_get_unwrapped.argtypes = [_vp, _vp, _vp]
 _lib.mdx_set_timing.argtypes = [_vp, ctypes.c_int]
 _lib.mdx_get_timing.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
@@ -393,6 +405,45 @@ def adjoint_segment(ctx: int, x0, v0, f0, n_steps: int, dt: float, first: bool, 
     _check(_lib.mdx_adjoint_segment(ctx, _ptr(x0), _ptr(v0), _ptr(f0), int(n_steps), float(dt),
                                     1 if first else 0, _ptr(q), _ptr(p), _ptr(grad)),
            "mdx_adjoint_segment")
+
+
+def set_graph(ctx: int, chunk: int) -> None:
+    """Replay integrate_step in chunk-step HIP graphs (0: launch by launch)."""
+    _check(_lib.mdx_set_graph(ctx, int(chunk)), "mdx_set_graph")
+
+
+def batch_create(ctxs, chunk: int) -> int:
+    arr = (_vp * len(ctxs))(*ctxs)
+    out = _vp()
+    _check(_lib.mdx_batch_create(ctypes.byref(out), arr, len(ctxs), int(chunk)),
+           "mdx_batch_create")
+    return out.value
+
+
+def batch_integrate(batch: int, pos, vel, force, n_steps: int, dt, stream) -> None:
+    """pos, vel, force: sequences of device tensors (one per replica); dt:
+    sequence of floats; stream: a hipStream_t handle."""
+    n = len(pos)
+    P = (_vp * n)(*[_ptr(t) for t in pos])
+    V = (_vp * n)(*[_ptr(t) for t in vel])
+    F = (_vp * n)(*[_ptr(t) for t in force])
+    D = (ctypes.c_float * n)(*[float(d) for d in dt])
+    _check(_lib.mdx_batch_integrate(batch, P, V, F, int(n_steps), D, stream),
+           "mdx_batch_integrate")
+
+
+def batch_destroy(batch: int) -> None:
+    _check(_lib.mdx_batch_destroy(batch), "mdx_batch_destroy")
+
+
+def autotune(desc, pos, vel, dt: float, steps: int, stream):
+    """(cell_divisions, options, ms per step of the eight candidates)."""
+    m = ctypes.c_int32(0)
+    o = ctypes.c_uint32(0)
+    ms = (ctypes.c_double * 8)()
+    _check(_lib.mdx_autotune(ctypes.byref(desc), _ptr(pos), _ptr(vel), float(dt), int(steps),
+                             stream, ctypes.byref(m), ctypes.byref(o), ms), "mdx_autotune")
+    return int(m.value), int(o.value), list(ms)
 
 
 def reset_images(ctx: int) -> None:

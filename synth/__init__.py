@@ -9,6 +9,9 @@ from .systems import (  # noqa: F401
     lj_fluid,
     water_box,
     random_box,
+    lj_fluid_n,
+    batch_replicas,
+    smooth_grid_size,
     config_system,
     CONFIGS,
 )

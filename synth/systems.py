@@ -301,6 +301,70 @@ def random_box(n_atoms: int, box, r_cut: float, r_ghost: float, seed: int,
 
 
 # ---------------------------------------------------------------------------
+# Batched replicas
+# ---------------------------------------------------------------------------
+def lj_fluid_n(n_atoms: int, density: float = 0.8, seed_stream: int = 0, jitter: float = 0.1,
+               r_cut: float = 2.5, r_ghost: float = 0.3, temperature: float = 1.0,
+               dt: float = 0.005, name: str = "lj") -> System:
+    """LJ fluid of any size: n_atoms of the n_side^3 >= n_atoms sites of a
+    simple-cubic lattice at reduced density, chosen by a seeded permutation
+    and kept in lattice order."""
+    n_side = int(math.ceil(n_atoms ** (1.0 / 3.0) - 1e-9))
+    L64 = (n_atoms / density) ** (1.0 / 3.0)
+    a = L64 / n_side
+    rng = np.random.Generator(np.random.PCG64(20541 + 30 + seed_stream))
+    keep = np.sort(rng.permutation(n_side ** 3)[:n_atoms])
+    ix, iy, iz = keep // (n_side * n_side), (keep // n_side) % n_side, keep % n_side
+    sites = np.stack([(ix + 0.5) * a, (iy + 0.5) * a, (iz + 0.5) * a])
+    sites = sites + rng.uniform(-jitter, jitter, size=sites.shape)
+    box = np.full(3, L64, dtype=np.float32)
+    s = lj_fluid(2, density, 0.0, r_cut, r_ghost, temperature, 0, dt, 10, 10, name)
+    mass = np.ones(n_atoms, dtype=np.float32)
+    return dataclasses.replace(
+        s, box=box, pos=_to_box_f32(sites, box),
+        vel=_maxwell_boltzmann(rng, mass.astype(np.float64), temperature, 1.0, 1.0),
+        charge=np.zeros(n_atoms, np.float32), mass=mass,
+        atom_type=np.zeros(n_atoms, np.int32))
+
+
+def smooth_grid_size(n: int) -> int:
+    """Smallest 2^a 3^b 5^c >= n (an FFT-friendly grid dimension)."""
+    k = max(4, int(n))
+    while True:
+        m = k
+        for p in (2, 3, 5):
+            while m % p == 0:
+                m //= p
+        if m == 1:
+            return k
+        k += 1
+
+
+def batch_replicas(n_rep: int = 256, n_min: int = 500, n_max: int = 20000,
+                   water_min_atoms: int = 1143) -> list:
+    """The batched-replica workload: even index an LJ fluid at reduced density
+    0.8, odd index flexible water at 0.033383 molecules/A^3, sizes
+    round(exp(U(ln n_min, ln n_max))); water sizes rounded to whole molecules
+    and clamped to >= water_min_atoms (a smaller box is under twice the list
+    radius, 2 (9 + 2.25) A); per-replica box and a PME grid of about 1 A
+    spacing (the next 2^a 3^b 5^c)."""
+    rng = np.random.Generator(np.random.PCG64(20541 + 30))
+    sizes = np.rint(np.exp(rng.uniform(math.log(n_min), math.log(n_max), n_rep))).astype(int)
+    out = []
+    for r, n in enumerate(sizes):
+        if r % 2 == 0:
+            out.append(lj_fluid_n(int(n), 0.8, seed_stream=r, name=f"lj{n}_{r}"))
+        else:
+            n_mol = max(int(round(n / 3)), -(-water_min_atoms // 3))
+            L = (n_mol / WATER_MOLECULE_DENSITY) ** (1.0 / 3.0)
+            K = smooth_grid_size(int(math.ceil(L)))
+            # little oxygen jitter: a size just above a lattice cube leaves ~2.7 A sites
+            out.append(water_box(n_mol, L, (K, K, K), 9.0, None, 5e-4, 3, o_jitter=0.05,
+                                 name=f"water{3 * n_mol}_{r}"))
+    return out
+
+
+# ---------------------------------------------------------------------------
 # Named workload configurations
 # ---------------------------------------------------------------------------
 CONFIGS = {
