@@ -62,6 +62,8 @@ def parse():
     p.add_argument("--steps", type=int, default=1000)
     p.add_argument("--warmup", type=int, default=100)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-batch", action="store_true",
+                   help="skip the 256-replica batch against sequential replicas timing")
     p.add_argument("--no-adjoint", action="store_true",
                    help="skip the forward+adjoint against plain forward timing (9k water)")
     p.add_argument("--equilibrate", type=int, default=3000,
@@ -429,6 +431,114 @@ def adjoint_ratio(reps=5):
             "ratio": round(t_adj / t_fwd, 3), "repetitions": reps, "status_flags": flags}
 
 
+def batch_throughput(steps=50):
+    """Batched replicas: the 256-replica workload (even index LJ at reduced
+    density 0.8, odd index flexible water, 500-20,000 atoms log-uniform, each
+    with its own box and ~1 A PME grid) stepped together by mdx_batch_integrate
+    (graph launches of 10-step chunks on one stream per replica), against the
+    same replicas stepped one after another launch by launch. The column
+    width and list-build mode of every replica come from mdx_autotune, run
+    on one replica per kind and size quartile."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2503_20541_amd as mdx
+    t0 = time.perf_counter()
+    systems = synth.batch_replicas()
+    t_gen = time.perf_counter() - t0
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    sizes = np.array([s.n_atoms for s in systems])
+    kind = np.array([0 if s.pme_grid[0] == 0 else 1 for s in systems])
+    # autotune one representative per (kind, size quartile)
+    tuned = {}
+    for k in (0, 1):
+        idx = np.where(kind == k)[0]
+        q = np.quantile(sizes[idx], [0.25, 0.5, 0.75])
+        for b in range(4):
+            members = [i for i in idx if np.searchsorted(q, sizes[i]) == b]
+            if not members:
+                continue
+            rep = members[len(members) // 2]
+            desc, keep = mdx.desc_from_system(systems[rep])
+            pos = torch.from_numpy(systems[rep].pos.copy()).to(dev)
+            vel = torch.from_numpy(systems[rep].vel.copy()).to(dev)
+            m, opt, _ = mdx.autotune(desc, pos, vel, float(systems[rep].dt), 10, stream.cuda_stream)
+            for i in members:
+                tuned[i] = (m, opt)
+    ctxs, keep, T = [], [], []
+    try:
+        for i, s in enumerate(systems):
+            m, opt = tuned[i]
+            desc, kp = mdx.desc_from_system(s, cell_divisions=m, options=opt)
+            keep.append(kp)
+            ctx = mdx.create(desc, stream.cuda_stream)
+            ctxs.append(ctx)
+            t = dict(pos=torch.from_numpy(s.pos.copy()).to(dev),
+                     vel=torch.from_numpy(s.vel.copy()).to(dev))
+            t["force"] = torch.zeros_like(t["pos"])
+            mdx.build_neighbors(ctx, t["pos"])
+            mdx.compute_nonbonded(ctx, t["pos"], t["force"])
+            if s.pme_grid[0]:
+                mdx.compute_pme(ctx, t["pos"], t["force"])
+            T.append(t)
+        dts = [float(s.dt) for s in systems]
+        P, V, F = ([t[k] for t in T] for k in ("pos", "vel", "force"))
+        b = None
+
+        def run_batch():
+            mdx.batch_integrate(b, P, V, F, steps, dts, stream.cuda_stream)
+
+        def run_sequential():
+            for ctx, t, d in zip(ctxs, T, dts):
+                mdx.integrate_step(ctx, t["pos"], t["vel"], t["force"], steps, d)
+
+        def timed(fn):
+            a = torch.cuda.Event(enable_timing=True)
+            z = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            a.record(stream)
+            fn()
+            z.record(stream)
+            torch.cuda.synchronize()
+            return a.elapsed_time(z)
+
+        # replicas side by side, each on its own stream: launch by launch,
+        # then as graph launches of 10-step chunks; then one after another
+        ms = {}
+        for chunk in (0, 10):
+            b = mdx.batch_create(ctxs, chunk)
+            try:
+                run_batch()               # warm-up (with a chunk: records each replica's)
+                ms[chunk] = min(timed(run_batch) for _ in range(3))
+            finally:
+                mdx.batch_destroy(b)
+        for ctx in ctxs:
+            mdx.set_graph(ctx, 0)         # launch by launch again
+        run_sequential()
+        ms_seq = min(timed(run_sequential) for _ in range(3))
+        ms_batch = min(ms.values())
+        flags = 0
+        for ctx in ctxs:
+            flags |= mdx.get_status(ctx)
+    finally:
+        torch.cuda.synchronize()
+        for ctx in ctxs:
+            mdx.destroy(ctx)
+    atom_steps = float(sizes.sum()) * steps
+    return {"workload": "256 replicas, even LJ (rho* 0.8), odd water (0.0334 molecules/A^3), "
+                        "500-20,000 atoms log-uniform, own box and ~1 A PME grid",
+            "n_atoms_total": int(sizes.sum()), "steps": steps,
+            "ms_batched": round(ms_batch, 3), "ms_sequential": round(ms_seq, 3),
+            "ms_batched_streams": round(ms[0], 3), "ms_batched_graphs": round(ms[10], 3),
+            "atom_steps_per_s_batched": atom_steps / (ms_batch * 1e-3),
+            "atom_steps_per_s_sequential": atom_steps / (ms_seq * 1e-3),
+            "speedup": round(ms_seq / ms_batch, 3),
+            "autotuned": {"cell_divisions": sorted({int(v[0]) for v in tuned.values()}),
+                          "cooperative_build": sum(1 for v in tuned.values() if v[1] & 2)},
+            "input_generation_s": round(t_gen, 1), "status_flags": flags}
+
+
 def main():
     args = parse()
     if args.copy_probe > 0:
@@ -514,6 +624,19 @@ def main():
         pme_ms, pme_n = mdx.get_timing(ctx, mdx.MDX_TIMING_PME)
         build_ms, build_n = mdx.get_timing(ctx, mdx.MDX_TIMING_BUILD)
         mdx.set_timing(ctx, False)
+        # diagnostic only: the same steps as graph launches of 10-step chunks
+        mdx.set_graph(ctx, 10)
+        n_g = max(10, min(args.steps, 200) // 10 * 10)
+        mdx.integrate_step(ctx, pos, vel, force, 10, s.dt)        # records the chunk
+        g0 = torch.cuda.Event(enable_timing=True)
+        g1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        g0.record(stream)
+        mdx.integrate_step(ctx, pos, vel, force, n_g, s.dt)
+        g1.record(stream)
+        torch.cuda.synchronize()
+        ms_graph = g0.elapsed_time(g1) / n_g
+        mdx.set_graph(ctx, 0)
         flags = mdx.get_status(ctx) | flags0
         ok = bool(torch.isfinite(pos).all() and torch.isfinite(vel).all())
         mdx.destroy(ctx)
@@ -540,6 +663,7 @@ def main():
             "list_tiles": info.n_list_tiles, "list_entries": info.n_list_entries,
             "kernel_ms": {"pair": round(pair_ms, 5), "pme_chain_overlapped": round(pme_ms, 5),
                           "build_gated": round(build_ms, 5)},
+            "graph_replay_ms_per_step": round(ms_graph, 5),
             "roofline": {"bound": "alu", "achieved": round(achieved, 3),
                          "peak": round(VALU_PEAK_T, 2), "unit": "TFLOP/s",
                          "frac": round(achieved / VALU_PEAK_T, 4), "traffic": PAIR_TRAFFIC_BYTES,
@@ -553,6 +677,8 @@ def main():
         })
     if not args.cpu_only and not args.no_adjoint:
         result["adjoint"] = adjoint_ratio()
+    if not args.cpu_only and not args.no_batch:
+        result["batch"] = batch_throughput()
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(s)
     print(json.dumps(result), flush=True)

@@ -351,21 +351,21 @@ int mdx_set_graph(mdx_ctx* ctx, int32_t chunk);
  * the paper's Hamiltonian Monte Carlo tuning, Sec. IV, which uses many
  * replicas): mdx_batch_create takes n_rep contexts (host array; each made by
  * mdx_create from its own descriptor, box and PME grid; each context at most
- * once; chunk a multiple of every replica's rebuild_every) on one device.
- * mdx_batch_integrate(b, pos, vel, force, n_steps, dt, stream) advances every
- * replica r by n_steps (a multiple of chunk) steps of mdx_integrate_step with
- * its own pos[r], vel[r], force[r] (host arrays of dev [3][N_r] pointers) and
- * dt[r] (host array). mdx_batch_create switches every member to graph
- * replay with the batch's chunk (mdx_set_graph); each replica's chunks are
- * then single graph launches on a stream of the batch's own (one per
- * replica, forked from `stream` and joined back into it by events), so the
- * small systems run side by side on the chip and the host issues one launch
- * per replica and chunk instead of a dozen per step. Results are bit for bit
- * those of mdx_integrate_step on each replica. Work on a replica's own
- * stream must be complete or ordered before `stream`. MDX_E_INVALID for bad
- * arguments, MDX_E_NO_LIST if a replica has no list yet, MDX_E_UNSUPPORTED
- * with Langevin dynamics or timing on a replica. mdx_batch_destroy frees the
- * batch (not the contexts).
+ * once) on one device, and chunk: 0, or a multiple of every replica's
+ * rebuild_every. mdx_batch_integrate(b, pos, vel, force, n_steps, dt, stream)
+ * advances every replica r by n_steps (a multiple of chunk if chunk > 0)
+ * steps of mdx_integrate_step with its own pos[r], vel[r], force[r] (host
+ * arrays of dev [3][N_r] pointers) and dt[r] (host array), each replica on a
+ * stream of the batch's own (one per replica, forked from `stream` and
+ * joined back into it by events), so the small systems run side by side on
+ * the chip. With chunk > 0, mdx_batch_create switches every member to graph
+ * replay of that chunk (mdx_set_graph) and each replica's chunks are single
+ * graph launches; with chunk = 0 the replicas' launches go one by one.
+ * Results are bit for bit those of mdx_integrate_step on each replica. Work
+ * on a replica's own stream must be complete or ordered before `stream`.
+ * MDX_E_INVALID for bad arguments, MDX_E_NO_LIST if a replica has no list
+ * yet, MDX_E_UNSUPPORTED for graph replay with Langevin dynamics or timing on
+ * a replica. mdx_batch_destroy frees the batch (not the contexts).
  */
 int mdx_batch_create(mdx_batch** out, mdx_ctx* const* ctxs, int32_t n_rep, int32_t chunk);
 int mdx_batch_integrate(mdx_batch* b, float* const* pos, float* const* vel, float* const* force,

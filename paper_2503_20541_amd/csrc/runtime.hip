@@ -1095,10 +1095,10 @@ extern "C" {
 int mdx_batch_create(mdx_batch** out, mdx_ctx* const* ctxs, int32_t n_rep, int32_t chunk) {
   if (!out) return MDX_E_INVALID;
   *out = nullptr;
-  if (!ctxs || n_rep < 1 || chunk < 1) return MDX_E_INVALID;
+  if (!ctxs || n_rep < 1 || chunk < 0) return MDX_E_INVALID;
   for (int r = 0; r < n_rep; ++r) {
     if (!ctxs[r]) return MDX_E_INVALID;
-    if (chunk % ctxs[r]->c.rebuild_every != 0) return MDX_E_INVALID;
+    if (chunk > 0 && chunk % ctxs[r]->c.rebuild_every != 0) return MDX_E_INVALID;
     for (int q = 0; q < r; ++q)
       if (ctxs[q] == ctxs[r]) return MDX_E_INVALID;   // each context once
   }
@@ -1117,8 +1117,8 @@ int mdx_batch_create(mdx_batch** out, mdx_ctx* const* ctxs, int32_t n_rep, int32
     mdx_batch_destroy(b);
     return MDX_E_HIP;
   }
-  // every member replays its steps in graphs of the batch's chunk
-  for (int r = 0; r < n_rep; ++r)
+  // with a chunk, every member replays its steps in graphs of that length
+  for (int r = 0; r < n_rep && chunk > 0; ++r)
     if (mdx_set_graph(ctxs[r], chunk) != MDX_OK) {
       mdx_batch_destroy(b);
       return MDX_E_INVALID;
@@ -1143,14 +1143,15 @@ int mdx_batch_destroy(mdx_batch* b) {
 
 int mdx_batch_integrate(mdx_batch* b, float* const* pos, float* const* vel, float* const* force,
                         int32_t n_steps, const float* dt, void* hip_stream) {
-  if (!b || !pos || !vel || !force || !dt || n_steps < 1 || n_steps % b->chunk != 0)
+  if (!b || !pos || !vel || !force || !dt || n_steps < 1 ||
+      (b->chunk > 0 && n_steps % b->chunk != 0))
     return MDX_E_INVALID;
   hipStream_t stream = static_cast<hipStream_t>(hip_stream);
   const size_t n = b->ctx.size();
   for (size_t r = 0; r < n; ++r) {
     mdx_ctx* x = b->ctx[r];
     if (!pos[r] || !vel[r] || !force[r] || !(dt[r] > 0.f)) return MDX_E_INVALID;
-    if (x->c.langevin || x->timing) return MDX_E_UNSUPPORTED;
+    if (b->chunk > 0 && (x->c.langevin || x->timing)) return MDX_E_UNSUPPORTED;
     if (x->c.steps_since_build < 0) return MDX_E_NO_LIST;
   }
   // every replica on its own stream, ordered after the caller's stream and

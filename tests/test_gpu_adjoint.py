@@ -133,3 +133,42 @@ def test_unsupported_modes_are_refused():
         assert e.value.code == mdx.MDX_E_UNSUPPORTED
     finally:
         sim.close()
+
+
+def test_water9k_100_steps_against_the_oracle_golden():
+    # the adjoint configuration: 9,000-atom water, 100 steps of 1 fs,
+    # checkpoints every 10; the FP64 oracle's gradients were written by
+    # tests/golden/make_adjoint9k.py
+    import importlib.util
+    import json
+    import os
+    here = os.path.join(os.path.dirname(__file__), "golden")
+    with open(os.path.join(here, "adjoint_water9k.json")) as f:
+        gold = json.load(f)
+    spec = importlib.util.spec_from_file_location("make_adjoint9k",
+                                                  os.path.join(here, "make_adjoint9k.py"))
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    s = synth.config_system("water9k")
+    dq = np.where(s.atom_type == 0, 1.0, -0.5).astype(np.float32)
+    announce("adjoint water9k 100 steps vs oracle golden")
+    g = _run(s, gold["n_steps"], gold["dt_fs"], 10, dq)
+    assert g["flags"] == 0
+    dirs, coords = mk.probes(s.n_atoms)
+    rows = {"loss": (g["loss"], gold["loss"]), "eps_O": (g["eps"][0], gold["eps_O"]),
+            "sig_O": (g["sig"][0], gold["sig_O"]), "q_O": (g["tq"], gold["q_O"]),
+            "dt": (g["dt"], gold["dt"])}
+    for k in range(3):
+        rows[f"x0.d{k}"] = (float((g["x0"] * dirs[k]).sum()), gold["x0_dirs"][k])
+        rows[f"v0.d{k}"] = (float((g["v0"] * dirs[k]).sum()), gold["v0_dirs"][k])
+    for k, (a, b) in rows.items():
+        print(f"{k}: gpu {a:.9g} oracle {b:.9g} rel {abs(a - b) / abs(b):.2e}", flush=True)
+    for k, (a, b) in rows.items():
+        assert abs(a - b) <= 1e-3 * abs(b), (k, a, b)
+    # sampled coordinates, against the gradient's RMS entry
+    for name in ("x0", "v0"):
+        rms = gold[f"{name}_norm"] / np.sqrt(3 * s.n_atoms)
+        got = np.array([g[name][a, i] for a, i in coords])
+        err = np.abs(got - np.array(gold[f"{name}_coords"])).max() / rms
+        print(f"{name} sampled coordinates: max error / rms entry {err:.2e}", flush=True)
+        assert err < 1e-2
