@@ -484,27 +484,57 @@ int mdx_set_parameters(mdx_ctx* ctx, const float* type_sigma, const float* type_
  * Use: run the trajectory in segments, saving the state (mdx_save_state)
  * and the positions, velocities and forces at each segment's start
  * (checkpoints); then
- *   mdx_adjoint_begin(ctx, pos_T, force_T, gx, gU, q, p, grad)
+ *   mdx_adjoint_begin(ctx, pos_T, force_T, gx, gv, gU, q, p, grad)
  * with pos_T, force_T (dev [3][N]) the final state, gx = dL/dx_T (dev
  * [3][N], unwrapped coordinates) and gU = dL/dU_T (dev double[1]): it sets
- * q = gx - gU F(x_T), p = 0 and grad = gU dU/dtheta (dev double[2 T + 2]:
+ * q = gx - gU F(x_T), p = gv (or 0) and grad = gU dU/dtheta (dev double[2 T + 2]:
  * epsilon_t, sigma_t, t, dt); then, for each segment from the last to the
  * first, mdx_load_state of its checkpoint and
- *   mdx_adjoint_segment(ctx, x_s, v_s, f_s, n_steps, dt, first, q, p, grad)
+ *   mdx_adjoint_segment(ctx, x_s, v_s, f_s, n_steps, dt, flags, q, p, grad, gm)
  * which repeats the segment's n_steps forward from (x_s, v_s, f_s)
  * (dev [3][N]; bit for bit the forward's steps, recorded in library-owned
  * buffers) and runs the reverse steps over it, updating q, p and grad in
- * place; first != 0 for the segment that starts the trajectory. At the end
+ * place (flags below). At the end
  * q = dL/dx_0, p = dL/dv_0 (through the trajectory; a loss term in x_0
  * itself is the caller's) and grad holds dL/dtheta and dL/d(dt). The
  * context's list state afterwards is that of the segment. Asynchronous.
+ *
+ * A loss that also depends on the final velocities passes gv = dL/dv_T
+ * (dev [3][N], or NULL for none) to mdx_adjoint_begin and MDX_ADJ_LAST to
+ * the first mdx_adjoint_segment call (the trajectory's last segment), which
+ * then also takes the end state's half of the last step. flags:
+ * MDX_ADJ_FIRST for the segment that starts the trajectory, MDX_ADJ_LAST for
+ * the one that ends it (both for a single segment). grad_mass (dev
+ * double[N] or NULL) accumulates dL/dm_i through the dynamics (a = c F / m);
+ * a loss term in the masses themselves (the sampled initial velocities, the
+ * kinetic energy) is the caller's.
  */
+#define MDX_ADJ_FIRST 0x1
+#define MDX_ADJ_LAST  0x2
+/* A loss term on an intermediate state n joins the reverse pass between the
+ * segments that end and start there: q += gx - gU F(x_n), p += gv (gx, gv:
+ * dev [3][N]; gU dev double[1]; each may be NULL; force = F(x_n), needed
+ * with gU). With one-step segments (flags MDX_ADJ_FIRST | MDX_ADJ_LAST each)
+ * (q, p) are dL/dx_n and dL/dv_n between segments, so every state of the
+ * trajectory can carry loss terms. The energy's parameter derivatives at an
+ * intermediate state are not added. Asynchronous. */
+int mdx_adjoint_inject(mdx_ctx* ctx, const float* force, const float* gx, const float* gv,
+                       const double* gU, float* q, float* p);
 int mdx_set_charge_direction(mdx_ctx* ctx, const float* dq);   /* host float[N]; synchronising */
 int mdx_adjoint_begin(mdx_ctx* ctx, const float* pos, const float* force, const float* gx,
-                      const double* gU, float* q, float* p, double* grad);
+                      const float* gv, const double* gU, float* q, float* p, double* grad);
 int mdx_adjoint_segment(mdx_ctx* ctx, const float* x0, const float* v0, const float* f0,
-                        int32_t n_steps, float dt, int32_t first, float* q, float* p,
-                        double* grad);
+                        int32_t n_steps, float dt, int32_t flags, float* q, float* p,
+                        double* grad, double* grad_mass);
+
+/*
+ * Masses for the following calls (host float[N], each > 0): the integrator's
+ * accel / m, the Langevin noise amplitudes and the rigid-water closed form
+ * follow. Mass repartitioning, as the paper's Hamiltonian Monte Carlo tuning
+ * does it (Sec. IV), changes the dynamics but not the sampled positional
+ * distribution. MDX_E_INVALID for a mass <= 0 or not finite. Synchronising.
+ */
+int mdx_set_masses(mdx_ctx* ctx, const float* mass);
 
 /* Sets the periodic image counters (mdx_get_images) to zero. */
 int mdx_reset_images(mdx_ctx* ctx);

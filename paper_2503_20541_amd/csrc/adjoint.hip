@@ -64,30 +64,40 @@ __device__ __forceinline__ void spline4_d2(float f, float d2[4]) {
 // ---- kernels -----------------------------------------------------------------
 
 // Opening of a reverse node, one thread per atom: p <- p + dt q, the dt
-// gradient's dot products (FP64 block partials), the tangent u = c p / m.
-__global__ void __launch_bounds__(256) k_adj_pre(int n, float dt, float w,
+// gradient's dot products (FP64 block partials), the tangent u = c p / m,
+// and (gmass non-null) the node's mass term -w dt p . a / m per atom
+// (a = c F / m depends on m). open = 0: the trajectory's end node taken with
+// half weight when the loss also depends on the final velocities (no p
+// update and no drift term there).
+__global__ void __launch_bounds__(256) k_adj_pre(int n, float dt, float w, int open,
                                                  const float* __restrict__ q,
                                                  float* __restrict__ p,
                                                  const float* __restrict__ v_n,
                                                  const float* __restrict__ f_n,
                                                  const float* __restrict__ acc_over_m,
+                                                 const float* __restrict__ mass,
                                                  float* __restrict__ u,
-                                                 double* __restrict__ partials) {
+                                                 double* __restrict__ partials,
+                                                 double* __restrict__ gmass) {
   __shared__ double red[16];
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
   double acc = 0.0;
   if (a < n) {
     const float am = acc_over_m[a];
     const float h = 0.5f * dt * am;
+    double pa = 0.0;
     for (int d = 0; d < 3; ++d) {
       const size_t k = (size_t)d * n + a;
       const float qk = q[k];
-      const float pk = p[k] + dt * qk;
+      const float pk = open ? p[k] + dt * qk : p[k];
       const float vh = v_n[k] + h * f_n[k];   // the half-step velocity, as the step made it
-      acc += (double)qk * vh + (double)w * pk * (am * f_n[k]);
+      const double pak = (double)pk * (am * f_n[k]);
+      acc += (open ? (double)qk * vh : 0.0) + (double)w * pak;
+      pa += pak;
       p[k] = pk;
       u[k] = am * pk;
     }
+    if (gmass) gmass[a] -= (double)w * dt * pa / (double)mass[a];
   }
   const double s = block_sum(acc, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
@@ -488,8 +498,24 @@ __global__ void __launch_bounds__(256) k_jvp_finish(JvpAtomArgs g, BondedParams 
   g.gatom[2 * (size_t)n + a] = gq;
 }
 
-// q = gx - gU F, p = 0 (start of the reverse pass).
+// q += gx - gU F, p += gv (each term optional): a loss term on an
+// intermediate state joins the reverse pass there.
+__global__ void __launch_bounds__(256) k_adj_inject(int n3, const float* __restrict__ gx,
+                                                    const float* __restrict__ gv,
+                                                    const double* __restrict__ gU,
+                                                    const float* __restrict__ force,
+                                                    float* __restrict__ q, float* __restrict__ p) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n3) return;
+  float dq = gx ? gx[k] : 0.f;
+  if (gU) dq -= (float)*gU * force[k];
+  q[k] += dq;
+  if (gv) p[k] += gv[k];
+}
+
+// q = gx - gU F, p = gv (or 0): the start of the reverse pass.
 __global__ void __launch_bounds__(256) k_adj_begin(int n3, const float* __restrict__ gx,
+                                                   const float* __restrict__ gv,
                                                    const double* __restrict__ gU,
                                                    const float* __restrict__ force,
                                                    float* __restrict__ q, float* __restrict__ p) {
@@ -497,7 +523,7 @@ __global__ void __launch_bounds__(256) k_adj_begin(int n3, const float* __restri
   if (k >= n3) return;
   const float gu = (float)*gU;
   q[k] = gx[k] - gu * force[k];
-  p[k] = 0.f;
+  p[k] = gv ? gv[k] : 0.f;
 }
 
 // grad[b] += scale (* *scale_dev) * sum, one block per entry: b < T the eps
@@ -567,11 +593,11 @@ JvpPairParams make_jvp_params(const Ctx& c) {
 }
 }  // namespace
 
-hipError_t launch_adj_pre(Ctx& c, float dt, float w, const float* q, float* p, const float* v_n,
-                          const float* f_n) {
+hipError_t launch_adj_pre(Ctx& c, float dt, float w, bool open, const float* q, float* p,
+                          const float* v_n, const float* f_n, double* gmass) {
   const int nb = (c.n + 255) / 256;
-  k_adj_pre<<<nb, 256, 0, c.stream>>>(c.n, dt, w, q, p, v_n, f_n, c.hdt_scale, c.adj.u,
-                                      c.adj.dt_part);
+  k_adj_pre<<<nb, 256, 0, c.stream>>>(c.n, dt, w, open ? 1 : 0, q, p, v_n, f_n, c.hdt_scale,
+                                      c.mass, c.adj.u, c.adj.dt_part, gmass);
   return hipGetLastError();
 }
 
@@ -637,10 +663,17 @@ hipError_t launch_jvp_finish(Ctx& c, bool eparam, const float* pos, const float*
   return hipGetLastError();
 }
 
-hipError_t launch_adj_begin(Ctx& c, const float* gx, const double* gU, const float* force,
-                            float* q, float* p) {
+hipError_t launch_adj_begin(Ctx& c, const float* gx, const float* gv, const double* gU,
+                            const float* force, float* q, float* p) {
   const int n3 = 3 * c.n;
-  k_adj_begin<<<(n3 + 255) / 256, 256, 0, c.stream>>>(n3, gx, gU, force, q, p);
+  k_adj_begin<<<(n3 + 255) / 256, 256, 0, c.stream>>>(n3, gx, gv, gU, force, q, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_inject(Ctx& c, const float* gx, const float* gv, const double* gU,
+                             const float* force, float* q, float* p) {
+  const int n3 = 3 * c.n;
+  k_adj_inject<<<(n3 + 255) / 256, 256, 0, c.stream>>>(n3, gx, gv, gU, force, q, p);
   return hipGetLastError();
 }
 

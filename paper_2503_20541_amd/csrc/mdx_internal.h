@@ -322,14 +322,16 @@ hipError_t launch_ewald_direct_static(Ctx& c, const float* pos, float* force, do
 // pos when `refresh`, tangent by slot), launch_pair_jvp, the dipole spread
 // and FFT passes, launch_jvp_finish (q += wdt dF, parameter terms by atom),
 // launch_adj_reduce. eparam: the energy's parameter derivatives instead.
-hipError_t launch_adj_pre(Ctx& c, float dt, float w, const float* q, float* p, const float* v_n,
-                          const float* f_n);
+hipError_t launch_adj_pre(Ctx& c, float dt, float w, bool open, const float* q, float* p,
+                          const float* v_n, const float* f_n, double* gmass);
 hipError_t launch_adj_slots(Ctx& c, const float* pos, bool refresh);
 hipError_t launch_pair_jvp(Ctx& c, bool eparam);
 hipError_t launch_jvp_finish(Ctx& c, bool eparam, const float* pos, const float* phi,
                              const float* dphi, float* q, float wdt);
-hipError_t launch_adj_begin(Ctx& c, const float* gx, const double* gU, const float* force,
-                            float* q, float* p);
+hipError_t launch_adj_begin(Ctx& c, const float* gx, const float* gv, const double* gU,
+                            const float* force, float* q, float* p);
+hipError_t launch_adj_inject(Ctx& c, const float* gx, const float* gv, const double* gU,
+                             const float* force, float* q, float* p);
 hipError_t launch_adj_reduce(Ctx& c, double scale, const double* scale_dev, double q_const,
                              int dt_blocks, double* grad);
 hipError_t launch_unwrap(Ctx& c, const float* pos, float* out);

@@ -1621,8 +1621,38 @@ int mdx_get_unwrapped(mdx_ctx* x, const float* pos, float* out) {
   return MDX_OK;
 }
 
+int mdx_set_masses(mdx_ctx* x, const float* mass) {
+  if (check_ctx(x) || !mass) return MDX_E_INVALID;
+  Ctx& c = x->c;
+  for (int i = 0; i < c.n; ++i)
+    if (!(mass[i] > 0.f) || !std::isfinite(mass[i])) return MDX_E_INVALID;
+  MDX_TRY(hipStreamSynchronize(c.stream));   // kernels in flight read the arrays
+  c.mass_h.assign(mass, mass + c.n);
+  std::vector<float> am(c.n);
+  for (int i = 0; i < c.n; ++i) am[i] = (float)(c.accel / (double)mass[i]);
+  MDX_TRY(hipMemcpy(c.mass, mass, sizeof(float) * c.n, hipMemcpyHostToDevice));
+  MDX_TRY(hipMemcpy(c.hdt_scale, am.data(), sizeof(float) * c.n, hipMemcpyHostToDevice));
+  if (c.langevin) {
+    std::vector<float> sig(c.n);
+    for (int i = 0; i < c.n; ++i) sig[i] = (float)std::sqrt(c.lv_kT * c.accel / (double)mass[i]);
+    MDX_TRY(hipMemcpy(c.lv_sig, sig.data(), sizeof(float) * c.n, hipMemcpyHostToDevice));
+  }
+  if (c.n_rigid > 0) {
+    // the closed form needs equal hydrogen masses in every molecule
+    std::vector<int> mols(3 * (size_t)c.n_rigid);
+    MDX_TRY(hipMemcpy(mols.data(), c.rigid_mols, sizeof(int) * mols.size(),
+                      hipMemcpyDeviceToHost));
+    bool settle = c.rigid_d[2] < 2.0f * c.rigid_d[0];
+    for (int k = 0; k < c.n_rigid && settle; ++k)
+      settle = c.mass_h[mols[3 * k + 1]] == c.mass_h[mols[3 * k + 2]];
+    if (settle != c.rigid_settle) c.version++;
+    c.rigid_settle = settle;
+  }
+  return MDX_OK;
+}
+
 int mdx_adjoint_begin(mdx_ctx* x, const float* pos, const float* force, const float* gx,
-                      const double* gU, float* q, float* p, double* grad) {
+                      const float* gv, const double* gU, float* q, float* p, double* grad) {
   if (check_ctx(x) || !pos || !force || !gx || !gU || !q || !p || !grad) return MDX_E_INVALID;
   Ctx& c = x->c;
   if (int rc = adjoint_supported(c)) return rc;
@@ -1641,15 +1671,24 @@ int mdx_adjoint_begin(mdx_ctx* x, const float* pos, const float* force, const fl
   MDX_TRY(mdx::launch_pair_jvp(c, true));
   MDX_TRY(mdx::launch_jvp_finish(c, true, pos, c.grid_phi, nullptr, nullptr, 0.f));
   MDX_TRY(mdx::launch_adj_reduce(c, 1.0, gU, self_energy_charge_derivative(c), 0, grad));
-  MDX_TRY(mdx::launch_adj_begin(c, gx, gU, force, q, p));
+  MDX_TRY(mdx::launch_adj_begin(c, gx, gv, gU, force, q, p));
+  return MDX_OK;
+}
+
+int mdx_adjoint_inject(mdx_ctx* x, const float* force, const float* gx, const float* gv,
+                       const double* gU, float* q, float* p) {
+  if (check_ctx(x) || !q || !p || (gU && !force)) return MDX_E_INVALID;
+  MDX_TRY(mdx::launch_adj_inject(x->c, gx, gv, gU, force, q, p));
   return MDX_OK;
 }
 
 int mdx_adjoint_segment(mdx_ctx* x, const float* x0, const float* v0, const float* f0,
-                        int32_t n_steps, float dt, int32_t first, float* q, float* p,
-                        double* grad) {
-  if (check_ctx(x) || !x0 || !v0 || !f0 || !q || !p || !grad || n_steps < 1 || !(dt > 0.f))
+                        int32_t n_steps, float dt, int32_t flags, float* q, float* p,
+                        double* grad, double* grad_mass) {
+  if (check_ctx(x) || !x0 || !v0 || !f0 || !q || !p || !grad || n_steps < 1 || !(dt > 0.f) ||
+      (flags & ~(MDX_ADJ_FIRST | MDX_ADJ_LAST)))
     return MDX_E_INVALID;
+  const bool first = flags & MDX_ADJ_FIRST;
   Ctx& c = x->c;
   if (c.steps_since_build < 0) return MDX_E_NO_LIST;
   if (int rc = adjoint_supported(c)) return rc;
@@ -1682,12 +1721,15 @@ int mdx_adjoint_segment(mdx_ctx* x, const float* x0, const float* v0, const floa
     MDX_TRY(copy(a.rec_f + (k + 1) * n3, a.force, b3));
     if (c.has_pme) MDX_TRY(copy(a.rec_phi + (k + 1) * K3, c.grid_phi, sizeof(float) * K3));
   }
-  // reverse over the segment's nodes
+  // reverse over the segment's nodes; with MDX_ADJ_LAST first its end node
+  // with half weight (the loss's velocity adjoint in p reaches the positions)
   const int nblk = (c.n + 255) / 256;
-  for (int k = n_steps - 1; k >= 0; --k) {
-    const float w = (first && k == 0) ? 0.5f : 1.0f;
+  for (int k = (flags & MDX_ADJ_LAST) ? n_steps : n_steps - 1; k >= 0; --k) {
+    const bool end = k == n_steps;
+    const float w = ((first && k == 0) || end) ? 0.5f : 1.0f;
     const float* xk = a.rec_x + k * n3;
-    MDX_TRY(mdx::launch_adj_pre(c, dt, w, q, p, a.rec_v + k * n3, a.rec_f + k * n3));
+    MDX_TRY(mdx::launch_adj_pre(c, dt, w, !end, q, p, a.rec_v + k * n3, a.rec_f + k * n3,
+                                grad_mass));
     MDX_TRY(mdx::launch_adj_slots(c, xk, true));
     MDX_TRY(mdx::launch_pair_jvp(c, false));
     if (c.has_pme) MDX_TRY(dipole_potential(c));

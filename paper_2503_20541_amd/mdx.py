@@ -73,8 +73,8 @@ EXPORTED = ("mdx_error_string", "mdx_create", "mdx_destroy", "mdx_set_stream",
             "mdx_save_state", "mdx_load_state", "mdx_compute_ewald_direct_noalloc",
             "mdx_ewald_direct_noalloc_bytes", "mdx_set_parameters", "mdx_set_charge_direction",
             "mdx_adjoint_begin", "mdx_adjoint_segment", "mdx_reset_images", "mdx_get_unwrapped",
-            "mdx_set_graph", "mdx_batch_create", "mdx_batch_integrate", "mdx_batch_destroy",
-            "mdx_autotune")
+            "mdx_set_graph", "mdx_set_masses", "mdx_adjoint_inject", "mdx_batch_create",
+            "mdx_batch_integrate", "mdx_batch_destroy", "mdx_autotune")
 
 _fp = ctypes.POINTER(ctypes.c_float)
 _ip = ctypes.POINTER(ctypes.c_int32)
@@ -137,9 +137,11 @@ _lib.mdx_save_state.argtypes = [_vp, _vp, ctypes.c_int64]
 _lib.mdx_load_state.argtypes = [_vp, _vp, ctypes.c_int64]
 _lib.mdx_set_parameters.argtypes = [_vp, _vp, _vp, _vp]
 _lib.mdx_set_charge_direction.argtypes = [_vp, _vp]
-_lib.mdx_adjoint_begin.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.mdx_adjoint_begin.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.mdx_adjoint_segment.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_float,
-                                     ctypes.c_int32, _vp, _vp, _vp]
+                                     ctypes.c_int32, _vp, _vp, _vp, _vp]
+_lib.mdx_set_masses.argtypes = [_vp, _vp]
+_lib.mdx_adjoint_inject.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.mdx_reset_images.argtypes = [_vp]
 _lib.mdx_set_graph.argtypes = [_vp, ctypes.c_int32]
 _lib.mdx_batch_create.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int32,
@@ -395,16 +397,31 @@ def set_charge_direction(ctx: int, dq) -> None:
     _check(_lib.mdx_set_charge_direction(ctx, hp), "mdx_set_charge_direction")
 
 
-def adjoint_begin(ctx: int, pos, force, gx, gU, q, p, grad) -> None:
-    _check(_lib.mdx_adjoint_begin(ctx, _ptr(pos), _ptr(force), _ptr(gx), _ptr(gU), _ptr(q),
-                                  _ptr(p), _ptr(grad)), "mdx_adjoint_begin")
+MDX_ADJ_FIRST = 0x1
+MDX_ADJ_LAST = 0x2
+
+
+def adjoint_begin(ctx: int, pos, force, gx, gU, q, p, grad, gv=None) -> None:
+    _check(_lib.mdx_adjoint_begin(ctx, _ptr(pos), _ptr(force), _ptr(gx), _ptr(gv), _ptr(gU),
+                                  _ptr(q), _ptr(p), _ptr(grad)), "mdx_adjoint_begin")
 
 
 def adjoint_segment(ctx: int, x0, v0, f0, n_steps: int, dt: float, first: bool, q, p,
-                    grad) -> None:
+                    grad, last: bool = False, grad_mass=None) -> None:
+    flags = (MDX_ADJ_FIRST if first else 0) | (MDX_ADJ_LAST if last else 0)
     _check(_lib.mdx_adjoint_segment(ctx, _ptr(x0), _ptr(v0), _ptr(f0), int(n_steps), float(dt),
-                                    1 if first else 0, _ptr(q), _ptr(p), _ptr(grad)),
+                                    flags, _ptr(q), _ptr(p), _ptr(grad), _ptr(grad_mass)),
            "mdx_adjoint_segment")
+
+
+def adjoint_inject(ctx: int, force, gx, gv, gU, q, p) -> None:
+    _check(_lib.mdx_adjoint_inject(ctx, _ptr(force), _ptr(gx), _ptr(gv), _ptr(gU), _ptr(q),
+                                   _ptr(p)), "mdx_adjoint_inject")
+
+
+def set_masses(ctx: int, mass) -> None:
+    h, hp = _host_f32(mass)
+    _check(_lib.mdx_set_masses(ctx, hp), "mdx_set_masses")
 
 
 def set_graph(ctx: int, chunk: int) -> None:
