@@ -161,14 +161,44 @@ def test_water9k_100_steps_against_the_oracle_golden():
     for k in range(3):
         rows[f"x0.d{k}"] = (float((g["x0"] * dirs[k]).sum()), gold["x0_dirs"][k])
         rows[f"v0.d{k}"] = (float((g["v0"] * dirs[k]).sum()), gold["v0_dirs"][k])
+    # 100 fs of this liquid amplify rounding: a second oracle run, started
+    # from positions perturbed at float32 rounding (6e-8 relative), moves the
+    # state gradients by up to ~1e-2 relative. That one run samples the
+    # scale of the divergence; its RMS over the six state projections is the
+    # scale, and each projection's bar is 1e-3 relative or three times that
+    # scale, whichever is larger. The loss and the parameter derivatives
+    # (sums over all atoms) meet 1e-3 outright.
+    pert = gold["perturbed_start"]
+    spread = {"loss": pert["loss"], "eps_O": pert["eps_O"], "sig_O": pert["sig_O"],
+              "q_O": pert["q_O"], "dt": pert["dt"]}
+    for k in range(3):
+        spread[f"x0.d{k}"] = pert["x0_dirs"][k]
+        spread[f"v0.d{k}"] = pert["v0_dirs"][k]
+    rel_spread = {k: abs(spread[k] - b) / abs(b) for k, (_, b) in rows.items()}
+    state = [k for k in rows if k.startswith(("x0.", "v0."))]
+    scale = float(np.sqrt(np.mean([rel_spread[k] ** 2 for k in state])))
     for k, (a, b) in rows.items():
-        print(f"{k}: gpu {a:.9g} oracle {b:.9g} rel {abs(a - b) / abs(b):.2e}", flush=True)
-    for k, (a, b) in rows.items():
+        print(f"{k}: gpu {a:.9g} oracle {b:.9g} rel {abs(a - b) / abs(b):.2e} "
+              f"(oracle spread {rel_spread[k]:.2e})", flush=True)
+    print(f"state projections: rms relative spread {scale:.2e}", flush=True)
+    for k in ("loss", "eps_O", "sig_O", "q_O", "dt"):
+        a, b = rows[k]
         assert abs(a - b) <= 1e-3 * abs(b), (k, a, b)
-    # sampled coordinates, against the gradient's RMS entry
+    for k in state:
+        a, b = rows[k]
+        assert abs(a - b) <= max(1e-3, 3.0 * scale) * abs(b), (k, a, b)
+    # sampled coordinates, against the gradient's RMS entry: their RMS error
+    # within 1e-3 of it or twice the oracle's RMS spread over the 64 samples,
+    # every one within 1e-2 of it or ten times that spread (the perturbed
+    # oracle's own largest deviation is 5-7 times its RMS)
     for name in ("x0", "v0"):
         rms = gold[f"{name}_norm"] / np.sqrt(3 * s.n_atoms)
         got = np.array([g[name][a, i] for a, i in coords])
-        err = np.abs(got - np.array(gold[f"{name}_coords"])).max() / rms
-        print(f"{name} sampled coordinates: max error / rms entry {err:.2e}", flush=True)
-        assert err < 1e-2
+        ref = np.array(gold[f"{name}_coords"])
+        spr = float(np.sqrt(np.mean((np.array(pert[f"{name}_coords"]) - ref) ** 2)))
+        err = np.abs(got - ref)
+        print(f"{name} sampled coordinates: max error / rms entry {err.max() / rms:.2e}, "
+              f"rms error / rms entry {np.sqrt(np.mean(err ** 2)) / rms:.2e}, "
+              f"oracle rms spread / rms entry {spr / rms:.2e}", flush=True)
+        assert np.sqrt(np.mean(err ** 2)) <= max(1e-3 * rms, 2.0 * spr)
+        assert np.all(err <= max(1e-2 * rms, 10.0 * spr))
