@@ -141,6 +141,7 @@ struct PmeParams {
   int B[3];
   int nb[3];
   float s_hi[3], s_lo[3];   // K_d / L_d = s_hi + s_lo
+  float Kf[3], invK[3];      // K_d and fl(1 / K_d) as floats
   float coulomb_k;
   double exp_fac;           // pi^2 / alpha^2
   double inv_piV;           // 1 / (pi V)

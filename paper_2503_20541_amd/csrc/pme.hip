@@ -4,9 +4,14 @@
 //                 column sort: columns within spline reach + r_g/2 of the
 //                 brick, and in each the slots whose build z is in reach
 //                 (ranges found by binary search once per list build).
-//                 Each lane takes one atom and adds its stencil values
-//                 inside the brick into its wave's own LDS copy of the brick;
-//                 the copies are summed in a fixed order (no global atomics).
+//                 Grids of 11 or more points per axis: k_pme_spread_lines,
+//                 every lane owns one z-line of the brick in registers and
+//                 the wave walks the atoms whose stencil meets the brick
+//                 (no atomics). Smaller grids and the dipole grid of the
+//                 adjoint: each lane takes one atom and adds its stencil
+//                 values inside the brick into its wave's own LDS copy of
+//                 the brick. Either way the copies are summed in a fixed
+//                 order (no global atomics).
 //  k_fft_rows_*   x-direction real<->half-complex transforms, P rows per block
 //  k_fft_cols     y (forward / inverse) and z (forward, influence multiply
 //                 with the FP64 energy partial, inverse) pencils
@@ -190,10 +195,195 @@ __global__ void __launch_bounds__(kSpreadThreads) k_pme_spread(
   }
 }
 
-// The FFT passes share the chip with the pair kernel (they run on a second
-// stream): their waves take a raised issue priority so the short chain of
-// passes is not starved by the long-running pair waves on the same SIMDs.
+// The spread and the FFT passes share the chip with the pair kernel (they run
+// on a second stream): their waves take a raised issue priority so the short
+// chain of reciprocal-space kernels is not starved by the long-running pair
+// waves on the same SIMDs.
 __device__ __forceinline__ void fft_priority() { __builtin_amdgcn_s_setprio(2); }
+
+// grid_coord's k0 and f, with the reduction into [0, K) done in float from
+// the kernel parameters (K and 1/K) instead of an integer remainder: the
+// remainder's multiplier would sit in a vector register for the kernel's
+// whole run. kf is an integer below 2^24 in magnitude, so kf - K q is exact
+// and the two corrections absorb an off-by-one quotient.
+__device__ __forceinline__ int grid_coord_f(float x, float s_hi, float s_lo, float Kf, float invK,
+                                            float& f) {
+  float kf = floorf(x * s_hi);
+  f = fmaf(x, s_hi, -kf) + x * s_lo;
+  if (f < 0.f) { f += 1.0f; kf -= 1.0f; }
+  if (f >= 1.0f) { f -= 1.0f; kf += 1.0f; }
+  if (f < 0.f) f = 0.f;
+  kf = fmaf(-Kf, floorf(kf * invK), kf);
+  if (kf >= Kf) kf -= Kf;
+  if (kf < 0.f) kf += Kf;
+  return (int)kf;
+}
+
+// Owner-computes spreading for grids of at least B + 3 points along every
+// axis (then B = 8 and no stencil point wraps back into the brick it left).
+// Lane (lx, ly) of every wave owns the brick's z-line at (lx, ly) and holds
+// its 8 points in registers; the waves take the candidates in chunks of 64
+// (one per lane: grid coordinates and weights q t_x, t_y, t_z into the wave's
+// LDS table), then walk the chunk's atoms whose stencil meets the brick one at
+// a time: every lane adds that atom's weights on its own line (at most 16 of
+// the 64 lines, 4 points each). The four waves' bricks are summed in wave
+// order at the end. No atomics; every point's sum runs in a fixed order
+// (chunk, lane, wave), so the grid does not depend on scheduling.
+//
+// Written to fit in 32 VGPRs (each weight row is computed and stored before
+// the next): the pair kernel running beside it on the first stream leaves 32
+// of a SIMD's 512 registers per lane free, and a larger wave would wait for
+// the pair waves to retire.
+__global__ void __launch_bounds__(kSpreadThreads) k_pme_spread_lines(
+    const float4* __restrict__ xs, const int4* __restrict__ brick_zr,
+    const int* __restrict__ brick_cols, PmeParams pp, CellGrid cg,
+    float* __restrict__ grid_q) {
+  constexpr int B = 8;
+  fft_priority();
+  // per candidate: q t_x[0..3], t_y[0..3], and the weights of the brick's 8
+  // z planes (t_z[dz - lz] where the stencil covers lz, else 0)
+  __shared__ float4 wts[kSpreadWaves][kWave][4];
+  __shared__ float red[kSpreadWaves][B][kWave];         // the waves' bricks, [lz][ly B + lx]
+  __shared__ int cand_start[kMaxCandCells];
+  __shared__ int cand_off[kMaxCandCells + 1];
+  __shared__ int cand_list[kCandList];
+
+  const int brick = blockIdx.x;
+  const int bx = brick % pp.nb[0], by = (brick / pp.nb[0]) % pp.nb[1],
+            bz = brick / (pp.nb[0] * pp.nb[1]);
+  const int g0x = bx * B, g0y = by * B, g0z = bz * B;
+  const int bex = min(B, pp.K[0] - g0x), bey = min(B, pp.K[1] - g0y), bez = min(B, pp.K[2] - g0z);
+  const int* bcx = brick_cols + 2 * bx;
+  const int* bcy = brick_cols + 2 * pp.nb[0] + 2 * by;
+  const int ncx = bcx[1], ncy = bcy[1];
+  const int ncol = ncx * ncy;
+  const int ncand = 2 * ncol;
+  const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int4* zr = brick_zr + (size_t)bz * cg.ncell;
+  for (int t = threadIdx.x; t < ncol; t += blockDim.x) {
+    int cx = (bcx[0] + t % ncx) % cg.n[0], cy = (bcy[0] + t / ncx) % cg.n[1];
+    const int4 r = zr[cy * cg.n[0] + cx];
+    cand_start[2 * t] = r.x;
+    cand_off[2 * t + 1] = r.y;
+    cand_start[2 * t + 1] = r.z;
+    cand_off[2 * t + 2] = r.w;
+  }
+  __syncthreads();
+  if (w == 0) {
+    int carry = 0;
+    for (int base = 0; base < ncand; base += kWave) {
+      const int i = base + lane;
+      int v = i < ncand ? cand_off[i + 1] : 0;
+      for (int o = 1; o < kWave; o <<= 1) {
+        const int u = __shfl_up(v, o, kWave);
+        if (lane >= o) v += u;
+      }
+      if (i < ncand) cand_off[i + 1] = carry + v;
+      carry += __shfl(v, kWave - 1, kWave);
+    }
+    if (lane == 0) cand_off[0] = 0;
+  }
+  __syncthreads();
+  const int total = cand_off[ncand];
+  if (total <= kCandList) {
+    for (int t = threadIdx.x; t < ncand; t += blockDim.x) {
+      const int b = cand_off[t], e = cand_off[t + 1], s0 = cand_start[t];
+      for (int k = b; k < e; ++k) cand_list[k] = s0 + (k - b);
+    }
+    __syncthreads();
+  }
+
+  const int lx = lane & (B - 1), ly = lane / B;
+  float acc[B] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int ch = w; ch * kWave < total; ch += kSpreadWaves) {
+    const int f = ch * kWave + lane;
+    unsigned packed = 0u;
+    bool meets = false;
+    if (f < total) {
+      const int sl = spread_candidate(f, total, ncand, cand_list, cand_start, cand_off);
+      const float4 p = xs[sl];
+      float4* row = &wts[w][lane][0];
+      float t[4], dt[4];
+      // stencil point t sits at brick-local offset d - t (d = k0 - g0 mod K)
+      int k;
+      float fr;
+      k = grid_coord_f(p.x, pp.s_hi[0], pp.s_lo[0], pp.Kf[0], pp.invK[0], fr);
+      int dx = k - g0x;
+      if (dx < 0) dx += pp.K[0];
+      spline4(fr, t, dt);
+      row[0] = make_float4(p.w * t[0], p.w * t[1], p.w * t[2], p.w * t[3]);
+      __builtin_amdgcn_sched_barrier(0);
+      k = grid_coord_f(p.y, pp.s_hi[1], pp.s_lo[1], pp.Kf[1], pp.invK[1], fr);
+      int dy = k - g0y;
+      if (dy < 0) dy += pp.K[1];
+      spline4(fr, t, dt);
+      row[1] = make_float4(t[0], t[1], t[2], t[3]);
+      packed = (unsigned)dx | (unsigned)dy << 8;
+      const bool meets_xy = dx < bex + 3 && dy < bey + 3;
+      __builtin_amdgcn_sched_barrier(0);
+      k = grid_coord_f(p.z, pp.s_hi[2], pp.s_lo[2], pp.Kf[2], pp.invK[2], fr);
+      int dz = k - g0z;
+      if (dz < 0) dz += pp.K[2];
+      spline4(fr, t, dt);
+      // weight of plane lz: t_z[dz - lz] where 0 <= dz - lz <= 3
+      auto zw = [&](int lz) {
+        const int t3 = dz - lz;
+        const float lo = (t3 & 1) ? t[1] : t[0], hi = (t3 & 1) ? t[3] : t[2];
+        const float v = (t3 & 2) ? hi : lo;
+        return (unsigned)t3 < 4u ? v : 0.f;
+      };
+      float* zrow = reinterpret_cast<float*>(&row[2]);
+#pragma unroll
+      for (int lz = 0; lz < B; ++lz) {
+        zrow[lz] = zw(lz);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      meets = meets_xy && dz < bez + 3;
+    }
+    unsigned long long m = __ballot(meets);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    while (m) {
+      const int a = __builtin_ctzll(m);
+      m &= m - 1ull;
+      const unsigned pa = __builtin_amdgcn_readlane(packed, a);
+      const int t1 = (int)(pa & 255u) - lx, t2 = (int)((pa >> 8) & 255u) - ly;
+      const float* wa = reinterpret_cast<const float*>(&wts[w][a][0]);
+      const float wxv = wa[t1 & 3], wyv = wa[4 + (t2 & 3)];
+      const float4 z0 = wts[w][a][2], z1 = wts[w][a][3];
+      const float wv = ((unsigned)t1 < 4u && (unsigned)t2 < 4u) ? wxv * wyv : 0.f;
+      acc[0] += wv * z0.x;
+      acc[1] += wv * z0.y;
+      acc[2] += wv * z0.z;
+      acc[3] += wv * z0.w;
+      acc[4] += wv * z1.x;
+      acc[5] += wv * z1.y;
+      acc[6] += wv * z1.z;
+      acc[7] += wv * z1.w;
+    }
+    // the next chunk rewrites the table
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+#pragma unroll
+  for (int z = 0; z < B; ++z) red[w][z][lane] = acc[z];
+  __syncthreads();
+  for (int t = threadIdx.x; t < B * kWave; t += blockDim.x) {
+    const int z = t / kWave, col = t % kWave, x = col % B, y = col / B;
+    if (x < bex && y < bey && z < bez) {
+      const float s = ((red[0][z][col] + red[1][z][col]) + red[2][z][col]) + red[3][z][col];
+      grid_q[((size_t)(g0z + z) * pp.K[1] + (g0y + y)) * pp.K[0] + g0x + x] = s;
+    }
+  }
+}
+
+// The line kernel covers grids with at least 11 points along every axis.
+__host__ __forceinline__ bool spread_by_lines(const PmeParams& pp) {
+  return pp.K[0] >= 11 && pp.K[1] >= 11 && pp.K[2] >= 11;
+}
+
 
 // ---------------------------------------------------------------------------
 // LDS FFT: Stockham autosort, radix 4/2/3/5 (7 by table), twiddles from a
@@ -636,6 +826,8 @@ PmeParams make_pme_params(const Ctx& c) {
     pp.nb[d] = g.nb[d];
     pp.s_hi[d] = g.scale_hi[d];
     pp.s_lo[d] = g.scale_lo[d];
+    pp.Kf[d] = (float)g.K[d];
+    pp.invK[d] = 1.0f / (float)g.K[d];
   }
   pp.Kxh = g.Kxh;
   pp.coulomb_k = (float)c.coulomb_k;
@@ -647,10 +839,16 @@ PmeParams make_pme_params(const Ctx& c) {
 // Charge spreading onto grid_q on stream s; `done` (if given) is recorded by
 // the kernel's own dispatch when it completes.
 hipError_t launch_pme_spread(Ctx& c, hipStream_t s, hipEvent_t done) {
+  static_assert(kBrickXY == 8 && kBrickZ == 8, "the line kernel holds 8-point bricks");
   const PmeParams pp = make_pme_params(c);
+  const bool lines = spread_by_lines(pp);
   if (!done) {
-    k_pme_spread<false><<<c.pg.nbrick, kSpreadThreads, 0, s>>>(c.xs, c.brick_zr, c.brick_cols,
-                                                               pp, c.cg, c.grid_q, nullptr);
+    if (lines)
+      k_pme_spread_lines<<<c.pg.nbrick, kSpreadThreads, 0, s>>>(c.xs, c.brick_zr, c.brick_cols, pp,
+                                                                c.cg, c.grid_q);
+    else
+      k_pme_spread<false><<<c.pg.nbrick, kSpreadThreads, 0, s>>>(c.xs, c.brick_zr, c.brick_cols,
+                                                                 pp, c.cg, c.grid_q, nullptr);
     return hipGetLastError();
   }
   const float4* xs = c.xs;
@@ -660,6 +858,11 @@ hipError_t launch_pme_spread(Ctx& c, hipStream_t s, hipEvent_t done) {
   float* q = c.grid_q;
   PmeParams p = pp;
   const float4* us = nullptr;
+  if (lines) {
+    void* args[] = {&xs, &zr, &bc, &p, &cg, &q};
+    return hipExtLaunchKernel(reinterpret_cast<const void*>(k_pme_spread_lines),
+                              dim3(c.pg.nbrick), dim3(kSpreadThreads), args, 0, s, nullptr, done, 0);
+  }
   void* args[] = {&xs, &zr, &bc, &p, &cg, &q, &us};
   return hipExtLaunchKernel(reinterpret_cast<const void*>(k_pme_spread<false>),
                             dim3(c.pg.nbrick), dim3(kSpreadThreads), args, 0, s, nullptr, done, 0);
