@@ -123,10 +123,14 @@ typedef struct mdx_batch mdx_batch;
  * options: MDX_OPT_* bits (0 = defaults). By default every pair is listed
  * from both ends and each end accumulates its own force: no atomics,
  * bitwise-reproducible forces. MDX_OPT_HALF_LIST lists each pair once and
- * applies its force to both atoms (Newton's third law) with float atomics
- * into a per-atom accumulator: half the pair arithmetic and list memory,
- * forces that can differ in the last bits from run to run. Energies are
- * reproducible in both modes. The list is built with one launch per build
+ * applies its force to both atoms (Newton's third law): the cluster that
+ * lists a tile keeps its own atoms' forces, the forces on the tile's other
+ * cluster go to a per-tile buffer, and each atom sums the tiles naming its
+ * cluster in list order. Half the pair arithmetic, no atomics either, so
+ * forces and energies are bitwise reproducible in both modes; the half list
+ * needs 60 bytes of device memory per tile of capacity for that buffer and its
+ * index. A stand-alone force call between mdx_integrate_step calls makes
+ * the next step walk the whole list (not the pruned one). The list is built with one launch per build
  * phase; MDX_OPT_COOPERATIVE_BUILD runs all phases in one cooperative launch
  * with grid-wide barriers between them (one launch when no rebuild is due,
  * but the launch goes through its own hardware queue, and on a real rebuild

@@ -180,9 +180,10 @@ __global__ void __launch_bounds__(256) k_begin_step(OpenStep o, const float* __r
 
 // Closing half of a step, four lanes per slot: lane q of the quad takes z
 // plane q of the PME stencil and every fourth bonded / exclusion term of the
-// atom; the quad sums its parts in a fixed order, and lane 0 adds the pair
-// force accumulated in the slot array (which it clears for the next
-// evaluation), stores the total and applies v += (dt/2) a. FP64 energy
+// atom (and, with a half list, every fourth of the j partials naming its
+// cluster); the quad sums its parts in a fixed order, and lane 0 adds the
+// pair force the pair kernel stored in the slot array (clearing it), stores
+// the total and applies v += (dt/2) a. FP64 energy
 // partials (exclusion, bond, angle, kinetic) per block. With `open`, lane 0
 // then opens the next step for its atom (open_step_atom, from the velocity
 // and force it has just stored): the same values as a separate opening
@@ -199,7 +200,7 @@ __global__ void __launch_bounds__(256) k_finish_step(
     float* __restrict__ force, float* __restrict__ vel,
     const float* __restrict__ acc_over_m, const float* __restrict__ mass, float half_dt,
     double inv_2acc, double* __restrict__ partials, int pstride, float* __restrict__ vc,
-    OpenStep o, int open) {
+    OpenStep o, int open, JParts jp) {
   __shared__ double red[16];
   const int gt = blockIdx.x * blockDim.x + threadIdx.x;
   if (open && gt == 0) open_step_flags(o);
@@ -211,6 +212,7 @@ __global__ void __launch_bounds__(256) k_finish_step(
     if (PME) pme_gather_atom(xs[s], phi, pp, fx, fy, fz, q, kFinishLanes);
     bonded_excl_atom<ENERGY, COUL>(a, pos, n, bp, tp, fx, fy, fz, e_ex, e_b, e_a, q,
                                    kFinishLanes);
+    if (jp.jpart) add_jparts(jp, s, q, kFinishLanes, fx, fy, fz);
   }
   // quad sum (all four lanes of a quad share the slot, so a is quad-uniform)
   fx += __shfl_xor(fx, 1, kWave);
@@ -625,7 +627,7 @@ hipError_t launch_finish_step(Ctx& c, const float* pos, float* vel, float* force
                                                     c.n, bp, tp, c.fslot, c.max_slots, force, \
                                                     vel, c.hdt_scale, c.mass, 0.5f * dt,      \
                                                     inv_2acc, c.partials, c.max_blocks, c.vc, \
-                                                    o, open)
+                                                    o, open, c.jparts())
   const bool C = c.has_coulomb, P = c.has_pme;
   if (energy) {
     if (C && P) MDX_FIN(true, true, true);

@@ -37,6 +37,29 @@ __device__ __forceinline__ void vir_add_dd(double* w, double s, double dx, doubl
   w[5] += s * dy * dz;
 }
 
+// Half list: the forces that the tiles naming slot s's cluster as their
+// j-cluster put on s (the tiles' j partials), entries first, first + step, ...
+// of the cluster's incoming list, in list order. jpart null: full list.
+struct JParts {
+  const float* jpart;       // [tile][3][4]
+  const int* in_count;      // [max_clusters]
+  const int* in_sorted;     // [max_clusters][cap]
+  int cap;
+};
+
+__device__ __forceinline__ void add_jparts(const JParts& jp, int s, int first, int step, float& fx,
+                                           float& fy, float& fz) {
+  const int c = s / kClusterSize, jb = s - c * kClusterSize;
+  const int nin = min(jp.in_count[c], jp.cap);
+  const int* lst = jp.in_sorted + (size_t)c * jp.cap;
+  for (int k = first; k < nin; k += step) {
+    const float* t = jp.jpart + (size_t)lst[k] * 12 + jb;
+    fx += t[0];
+    fy += t[4];
+    fz += t[8];
+  }
+}
+
 // Geometry of the x-y column grid and the float32 predicate constants.
 struct CellGrid {
   int n[3];          // columns along x and y (n[2] = 1)
@@ -107,7 +130,7 @@ struct Ctx {
   bool has_coulomb = false, has_pme = false, has_switch = false;   // has_coulomb: Ewald
   bool rf = false;             // reaction-field Coulomb (Eq. 8) instead of Ewald
   double k_rf = 0.0, c_rf = 0.0;
-  bool half_list = false;      // each pair once, float atomics (MDX_OPT_HALF_LIST)
+  bool half_list = false;      // each pair once (MDX_OPT_HALF_LIST), j forces through jpart
   int coop_blocks = 0;         // grid of the single-launch list build (0: one kernel per phase)
   int n_types = 0, n_excl = 0, n_bonds = 0, n_angles = 0;
   int cell_div = 2;
@@ -196,6 +219,19 @@ struct Ctx {
   uint2* ptiles = nullptr;     // [max_clusters][nl_cap] pruned tile list
   int* pcount = nullptr;       // [max_clusters]
   float4* xp = nullptr;        // [max_slots] slot positions when the pruned list was made
+  // Half list: the j-atom forces of each tile (summed over its 4 i atoms) go
+  // to jpart at the tile's full-list position [max_clusters * nl_cap][3][4]
+  // (component, j slot); ppos gives a pruned tile's full-list position. The
+  // tiles whose j-cluster is c are listed, by full-list position, at
+  // in_sorted[c * nl_cap ...] (in_count[c] of them; the tile search appends
+  // them to in_fill in any order, the pair kernel sorts them), and the
+  // closing kernel sums them in that order.
+  float* jpart = nullptr;
+  int* ppos = nullptr;         // [max_clusters][nl_cap]
+  int* in_count = nullptr;     // [max_clusters]
+  int* in_fill = nullptr;      // [max_clusters][nl_cap]
+  int* in_sorted = nullptr;    // [max_clusters][nl_cap]
+  JParts jparts() const { return JParts{jpart, in_count, in_sorted, nl_cap}; }
   float prune_r2 = 0.f;        // fl(r_p^2), r_p = r_c + 0.4 r_g
   float prune_move2 = 0.f;     // (0.19 r_g)^2: displacement that invalidates the pruned list
 

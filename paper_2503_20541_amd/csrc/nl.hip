@@ -12,8 +12,10 @@
 // pair is held once (Newton's third law: the force kernel applies each pair
 // force to both atoms): a pair of distinct clusters is listed by one of the
 // two, chosen by index parity, and a cluster's own tile keeps the slot pairs
-// a < b. The set bits are exactly the pair list, so the exported list is the
-// definition's, while the force kernel streams whole 4x4 tiles.
+// a < b; the tile search also lists every tile under its j-cluster
+// (in_count / in_fill), from which the force kernel's j-side sums are
+// gathered. The set bits are exactly the pair list, so the exported list is
+// the definition's, while the force kernel streams whole 4x4 tiles.
 //
 // Build phases (gated: with a gate they do nothing unless it is raised):
 //   bin (column of every atom, appended to that column's fixed-capacity
@@ -121,6 +123,10 @@ struct BuildArgs {
   uint2* tiles;
   int* tile_count;
   int max_clusters;
+  // half list: tiles listed per j-cluster (cleared by the binning, appended
+  // by the tile search in any order)
+  int* in_count;   // [max_clusters]
+  int* in_fill;    // [max_clusters][cap]: i-cluster * cap + full-list position
 };
 
 // Column of caller atom i, atoms per column (the atom goes to the next free
@@ -634,7 +640,19 @@ __device__ void search_cluster(const BuildArgs& a, int ic, SearchLds& sl, const 
     const int before = __popcll(nonempty & ((1ull << lane) - 1ull));
     if (ia == 0 && b == 0 && mask != 0) {
       const int k = count + before;
-      if (k < a.cap) a.tiles[(size_t)ic * a.cap + k] = make_uint2((unsigned)jc, mask | limg << 16);
+      if (k < a.cap) {
+        a.tiles[(size_t)ic * a.cap + k] = make_uint2((unsigned)jc, mask | limg << 16);
+        if (a.in_count) {
+          // the tile's j partials (jpart at ic * cap + k) belong to jc
+          const int r = atomicAdd(&a.in_count[jc], 1);
+          if (r < a.cap) {
+            a.in_fill[(size_t)jc * a.cap + r] = ic * a.cap + k;
+          } else {
+            atomicOr(a.flags, MDX_FLAG_NL_OVERFLOW);
+            atomicMax(a.nl_needed, r + 1);
+          }
+        }
+      }
     }
     count += __popcll(nonempty);
   };
@@ -729,9 +747,16 @@ __device__ void search_cluster(const BuildArgs& a, int ic, SearchLds& sl, const 
 
 // ---- one kernel per phase ---------------------------------------------------
 // Binning; the last block to finish (counted in meta[3]) runs the scan.
+// Half list: no tile is listed under any j-cluster before the tile search.
+__device__ __forceinline__ void clear_in_counts(const BuildArgs& a, int tid, int nthreads) {
+  if (!a.in_count) return;
+  for (int c = tid; c < a.max_clusters; c += nthreads) a.in_count[c] = 0;
+}
+
 __global__ void __launch_bounds__(256) k_bin_scan(BuildArgs a) {
   if (gated_off(a.gate)) return;
   __shared__ int last;
+  clear_in_counts(a, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
   bin_atom(a, blockIdx.x * blockDim.x + threadIdx.x);
   // The counts are atomics whose results every lane has received before the
   // barrier; one device-scope release per block (not a cache write-back per
@@ -781,6 +806,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_build_all(BuildArgs a) {
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   // bounds rounded to whole blocks: the atom loops stay uniform per wave
   const int nround = (a.n + blockDim.x - 1) / blockDim.x * blockDim.x;
+  clear_in_counts(a, tid, nthreads);
   for (int i = tid; i < nround; i += nthreads) bin_atom(a, i);
   grid.sync();
   if (blockIdx.x == 0) scan_columns(a);
@@ -845,7 +871,7 @@ hipError_t launch_build_list(Ctx& c, const float* pos, const int* gate, hipEvent
               ZRangeArgs{c.zb, c.slot_start, c.cell_start, c.brick_z,
                          c.has_pme ? c.pg.nb[2] : 0, ncol, c.cg.L[2], c.brick_zr},
               c.ex_start, c.ex_idx, c.nl_cap, c.half_list ? 1 : 0, c.zbin, c.tiles,
-              c.tile_count, c.max_clusters};
+              c.tile_count, c.max_clusters, c.in_count, c.in_fill};
   if (c.coop_blocks > 0) {
     void* args[] = {&a};
     hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_build_all),
@@ -855,22 +881,19 @@ hipError_t launch_build_list(Ctx& c, const float* pos, const int* gate, hipEvent
   }
   const int nb = (n + 255) / 256;
   k_bin_scan<<<nb, 256, 0, s>>>(a);
-  // the column sort completes the slot positions and the PME brick ranges:
-  // `done` is recorded by its own dispatch
+  k_col_sort<<<ncol, kColThreads, 0, s>>>(a);
+  // `done` is recorded by the tile search's own dispatch (the slot positions
+  // and the PME brick ranges were complete after the column sort; work
+  // forked from here starts together with the force kernel)
+  const int sb = (c.max_clusters + 3) / 4;
   if (done && !c.capturing) {
     void* args[] = {&a};
-    hipError_t e = hipExtLaunchKernel(reinterpret_cast<const void*>(k_col_sort), dim3(ncol),
-                                      dim3(kColThreads), args, 0, s, nullptr, done, 0);
-    if (e != hipSuccess) return e;
-  } else if (done) {
-    // under graph capture the event becomes a dependency edge after the sort
-    k_col_sort<<<ncol, kColThreads, 0, s>>>(a);
-    hipError_t e = hipEventRecord(done, s);
-    if (e != hipSuccess) return e;
-  } else {
-    k_col_sort<<<ncol, kColThreads, 0, s>>>(a);
+    return hipExtLaunchKernel(reinterpret_cast<const void*>(k_tile_search), dim3(sb), dim3(256),
+                              args, 0, s, nullptr, done, 0);
   }
-  k_tile_search<<<(c.max_clusters + 3) / 4, 256, 0, s>>>(a);
+  k_tile_search<<<sb, 256, 0, s>>>(a);
+  // under graph capture the event becomes a dependency edge after the search
+  if (done) return hipEventRecord(done, s);
   return hipGetLastError();
 }
 

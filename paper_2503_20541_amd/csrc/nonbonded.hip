@@ -97,6 +97,31 @@ struct PruneArgs {
   int* pcount;            // [max_clusters]
   float4* xp;             // [max_slots] positions at the emitting step
   float rp2;              // fl(r_p^2)
+  // half list, stand-alone call: the in-step pruned-list flags of both step
+  // parities, raised so that the next step walks the full list (this call
+  // writes every tile's j partials for its own positions)
+  int* invalidate;
+};
+
+// Half list (each pair once, Newton's third law): the wave of cluster ic
+// stores its atoms' forces as with the full list, and the forces on each
+// tile's j atoms, summed over the tile's four i atoms, go to jpart at the
+// tile's position in the full list: [tile][component][j slot]. Every real
+// tile of the list a step walks writes its entry, zero if no pair
+// interacted; a tile the pruned list drops had no pair within r_p when it
+// was dropped (that step walked the full list and wrote zeros for it), and
+// has none within r_c while the pruned list is in use. The closing kernel
+// adds, to each atom, the entries of the tiles whose j-cluster holds it, in
+// the order of in_sorted: the tile search appends them to in_fill in any
+// order, and on a build step (or a stand-alone call) the wave of each
+// cluster sorts its own entries by full-list position. No float atomics:
+// the forces do not depend on scheduling.
+struct HalfArgs {
+  float* jpart;          // [max_clusters * cap][3][4]
+  int* ppos;             // [max_clusters][cap] pruned tile -> full-list position
+  const int* in_count;   // [max_clusters]
+  const int* in_fill;    // [max_clusters][cap]
+  int* in_sorted;        // [max_clusters][cap]
 };
 
 template <bool ENERGY, int COUL, bool SWITCH, bool HALF, bool VIR = false>
@@ -109,7 +134,7 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
                                               const double2* __restrict__ lj_d,
                                               float* __restrict__ fslot, int fstride,
                                               double* __restrict__ partials, int pstride,
-                                              PruneArgs pr) {
+                                              PruneArgs pr, HalfArgs ha) {
   __shared__ double red[16];
   // LJ type-pair table, ntypes^2 entries (dynamic: the concurrent PME
   // kernels keep the rest of the CU's LDS)
@@ -137,6 +162,7 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
   const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   const int ic = blockIdx.x * 4 + w;
   const bool active = ic < meta[1];
+  if (HALF && pr.invalidate && blockIdx.x == 0 && threadIdx.x < 2) pr.invalidate[threadIdx.x] = 1;
   const int ia = lane >> 4, tt = (lane >> 2) & 3, jb = lane & 3;
   const int si = ic * kClusterSize + ia;
   const unsigned bitpos = (unsigned)(ia * kClusterSize + jb);
@@ -159,11 +185,15 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
     const uint2* tl = (pruned ? pr.ptiles : tiles) + (size_t)ic * cap;
     uint2* const pl = pr.ptiles + (size_t)ic * cap;
     int pn = 0;
-    // j-force component this lane stores: x, y, z on rows 0-2, none on row 3
-    float* const fcomp = fslot + (size_t)(ia < 3 ? ia : 0) * fstride;
+    // half list: full-list positions of the pruned tiles; this lane's j
+    // partial (component ia of j slot jb) of the tile at full position f is
+    // jpart[((ic * cap + f) * 3 + ia) * 4 + jb]
+    int* const ppl = HALF ? ha.ppos + (size_t)ic * cap : nullptr;
+    float* const jrow = HALF ? ha.jpart + (size_t)ic * cap * 12 + (ia < 3 ? ia : 0) * 4 + jb
+                             : nullptr;
     // One group of four tiles (e: this lane's tile, sj / pj / tj: its j slot,
-    // position and type).
-    auto group = [&](uint2 e, unsigned sj, float4 pj, int tj) {
+    // position and type; f: the tile's full-list position).
+    auto group = [&](uint2 e, unsigned sj, float4 pj, int tj, int f) {
       const bool on = (e.y >> bitpos) & 1u;
       // the tile's image: the same differences as the minimum-image rule
       // gives for its listed pairs, without the per-pair selects
@@ -180,11 +210,20 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
         const bool keep = ((nearm >> (4 * tt)) & 0x000f000f000f000full) != 0ull;
         const bool leader = ia == 0 && jb == 0;
         const unsigned long long km = __builtin_amdgcn_ballot_w64(leader && keep);
-        if (leader && keep) pl[pn + __popcll(km & ((1ull << lane) - 1ull))] = e;
+        if (leader && keep) {
+          const int k = pn + __popcll(km & ((1ull << lane) - 1ull));
+          pl[k] = e;
+          if (HALF) ppl[k] = f;
+        }
         pn += __popcll(km);
       }
       const unsigned long long hit = __builtin_amdgcn_ballot_w64(in);
-      if (hit == 0ull) return;
+      // half list: every real tile (mask != 0) writes its j partials
+      const bool jw = HALF && ia < 3 && (e.y & 0xffffu) != 0u;
+      if (hit == 0ull) {
+        if (jw) jrow[(size_t)f * 12] = 0.f;
+        return;
+      }
       float gx = 0.f, gy = 0.f, gz = 0.f;   // force on j (minus the force on i)
       if (in) {
         const int tp = trow + tj;
@@ -258,10 +297,7 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
         gx = sum_rows4(gx);
         gy = sum_rows4(gy);
         gz = sum_rows4(gz);
-        // j atoms (lane & 15) with at least one interacting pair in the group
-        const unsigned jhit = (unsigned)((hit | hit >> 16 | hit >> 32 | hit >> 48) & 0xffffull);
-        if (ia < 3 && ((jhit >> (lane & 15)) & 1u))
-          atomicAdd(fcomp + sj, ia == 0 ? gx : (ia == 1 ? gy : gz));
+        if (jw) jrow[(size_t)f * 12] = ia == 0 ? gx : (ia == 1 ? gy : gz);
       }
     };
     // Software pipeline, two groups per iteration with fixed registers: while
@@ -275,21 +311,33 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
     auto slot_of = [&](uint2 e, int g) {
       return (g < cnt ? e.x : 0u) * kClusterSize + (unsigned)jb;
     };
+    // full-list position of this lane's tile of group g (half list)
+    auto full_at = [&](int g) {
+      if (!HALF) return 0;
+      const int k = min(g + tt, cap - 1);
+      return pruned ? ppl[k] : k;
+    };
     uint2 eA = tile_at(0), eB = tile_at(4);
     uint2 eA2 = tile_at(8), eB2 = tile_at(12);
+    int fA = full_at(0), fB = full_at(4);
+    int fA2 = full_at(8), fB2 = full_at(12);
     unsigned sA = slot_of(eA, 0), sB = slot_of(eB, 4);
     float4 pA = xs[sA], pB = xs[sB];
     int tA = ts[sA], tB = ts[sB];
     for (int g = 0; g < cnt; g += 8) {
-      group(eA, sA, pA, tA);
+      group(eA, sA, pA, tA, fA);
       eA = eA2;
+      fA = fA2;
       eA2 = tile_at(g + 16);
+      fA2 = full_at(g + 16);
       sA = slot_of(eA, g + 8);
       pA = xs[sA];
       tA = ts[sA];
-      if (g + 4 < cnt) group(eB, sB, pB, tB);
+      if (g + 4 < cnt) group(eB, sB, pB, tB, fB);
       eB = eB2;
+      fB = fB2;
       eB2 = tile_at(g + 20);
+      fB2 = full_at(g + 20);
       sB = slot_of(eB, g + 12);
       pB = xs[sB];
       tB = ts[sB];
@@ -301,9 +349,21 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
       if (lane == 0) pr.pcount[ic] = padded;
       if ((lane & 15) == 0) pr.xp[si] = pi;
     }
+    // half list, on a build step or a stand-alone call: this cluster's
+    // incoming tiles in full-list order (rank of each distinct position)
+    if (HALF && (!pr.gate_now || *pr.gate_now != 0)) {
+      const int nin = min(ha.in_count[ic], cap);
+      const int* src = ha.in_fill + (size_t)ic * cap;
+      for (int k = lane; k < nin; k += kWave) {
+        const int key = src[k];
+        int rank = 0;
+        for (int m = 0; m < nin; ++m) rank += src[m] < key ? 1 : 0;
+        ha.in_sorted[(size_t)ic * cap + rank] = key;
+      }
+    }
   }
-  // sum the i force over the 16 lanes of the row; lanes 0-2 of the row add
-  // (half list) or store (full list: the wave owns the slot) its x, y, z
+  // sum the i force over the 16 lanes of the row; lanes 0-2 of the row
+  // store its x, y, z (the wave owns the slot)
   for (int o = 8; o >= 1; o >>= 1) {
     fx += __shfl_xor(fx, o, kWave);
     fy += __shfl_xor(fy, o, kWave);
@@ -312,9 +372,7 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
   const int c3 = lane & 15;
   if (active && c3 < 3) {
     const float v = c3 == 0 ? fx : (c3 == 1 ? fy : fz);
-    float* dst = fslot + (size_t)c3 * fstride + si;
-    if (!HALF) *dst = v;
-    else if (v != 0.f) atomicAdd(dst, v);
+    fslot[(size_t)c3 * fstride + si] = v;
   }
   if (ENERGY) {
     // a full list visits every pair from both ends
@@ -345,7 +403,7 @@ __global__ void __launch_bounds__(256) k_bonded_excl(const float* __restrict__ p
                                                      float* __restrict__ fslot, int fstride,
                                                      float* __restrict__ force,
                                                      double* __restrict__ partials,
-                                                     int pstride) {
+                                                     int pstride, JParts jp) {
   __shared__ double red[16];
   int a = blockIdx.x * blockDim.x + threadIdx.x;
   double e_ex = 0.0, e_b = 0.0, e_a = 0.0;
@@ -360,6 +418,7 @@ __global__ void __launch_bounds__(256) k_bonded_excl(const float* __restrict__ p
       fslot[s] = 0.f;
       fslot[fstride + s] = 0.f;
       fslot[2 * fstride + s] = 0.f;
+      if (jp.jpart) add_jparts(jp, s, 0, 1, fx, fy, fz);
     }
     bonded_excl_atom<ENERGY, COUL, VIR>(a, pos, n, bp, tp, fx, fy, fz, e_ex, e_b, e_a, 0, 1, w);
     force[a] = fx;
@@ -447,7 +506,9 @@ hipError_t launch_nonbonded(Ctx& c, bool energy, const int* gate_now, const int*
   const int nb = (c.max_clusters + 3) / 4;
   c.nb_blocks = nb;
   const size_t lds = sizeof(float4) * (size_t)c.n_types * c.n_types;
-  const PruneArgs pr{gate_now, pgate_now, c.ptiles, c.pcount, c.xp, c.prune_r2};
+  const PruneArgs pr{gate_now, pgate_now, c.ptiles, c.pcount, c.xp, c.prune_r2,
+                     c.half_list && !gate_now ? c.gate + 2 : nullptr};
+  const HalfArgs ha{c.jpart, c.ppos, c.in_count, c.in_fill, c.in_sorted};
   // the timing events (optional) are recorded by the dispatch itself: no
   // marker packets around the kernel
 #define MDX_PAIR(E, C, S, H, V)                                                              \
@@ -460,11 +521,12 @@ hipError_t launch_nonbonded(Ctx& c, bool energy, const int* gate_now, const int*
                           static_cast<const int*>(c.meta), c.nl_cap, pp,                      \
                           static_cast<const float4*>(c.lj_f),                                 \
                           static_cast<const double2*>(c.lj_d), c.fslot, c.max_slots,          \
-                          c.partials, c.max_blocks, pr);                                      \
+                          c.partials, c.max_blocks, pr, ha);                                  \
   else                                                                                        \
     k_pair<E, C, S, H, V><<<nb, 256, lds, c.stream>>>(c.xs, c.ts, c.tiles, c.tile_count, c.meta, \
                                                       c.nl_cap, pp, c.lj_f, c.lj_d, c.fslot,  \
-                                                      c.max_slots, c.partials, c.max_blocks, pr); \
+                                                      c.max_slots, c.partials, c.max_blocks, pr, \
+                                                      ha);                                    \
   } while (0)
 #define MDX_PAIR_H(E, C, S)             \
   if (c.half_list)                      \
@@ -535,7 +597,7 @@ hipError_t launch_bonded_excl(Ctx& c, const float* pos, float* force, bool energ
   const bool C = c.has_coulomb;
 #define MDX_BX(E, C, V)                                                                       \
   k_bonded_excl<E, C, V><<<nb, 256, 0, s>>>(pos, c.n, bp, tp, c.inv_perm, c.fslot, c.max_slots, \
-                                            force, c.partials, c.max_blocks)
+                                            force, c.partials, c.max_blocks, c.jparts())
   if (virial) {
     if (C) MDX_BX(true, true, true);
     else MDX_BX(true, false, true);

@@ -240,13 +240,17 @@ __global__ void __launch_bounds__(kSpreadThreads) k_pme_spread_lines(
     float* __restrict__ grid_q) {
   constexpr int B = 8;
   fft_priority();
-  // per candidate: q t_x[0..3], t_y[0..3], and the weights of the brick's 8
-  // z planes (t_z[dz - lz] where the stencil covers lz, else 0)
+  // 20 KB of LDS in all, so that LDS leaves room for 8 waves per SIMD and
+  // the register allocation stays at what the code uses (the compiler sizes
+  // it to the occupancy the LDS allows). Per candidate: q t_x[0..3],
+  // t_y[0..3], and the weights of the brick's 8 z planes (t_z[dz - lz] where
+  // the stencil covers lz, else 0); after its chunks each wave keeps its
+  // brick lines ([lz][ly B + lx]) in its own part of the table.
   __shared__ float4 wts[kSpreadWaves][kWave][4];
-  __shared__ float red[kSpreadWaves][B][kWave];         // the waves' bricks, [lz][ly B + lx]
-  __shared__ int cand_start[kMaxCandCells];
-  __shared__ int cand_off[kMaxCandCells + 1];
-  __shared__ int cand_list[kCandList];
+  // the candidate slot ranges (two per column, periodic wrap) and the
+  // inclusive prefix sums of their sizes
+  __shared__ int seg_start[kMaxCandCells];
+  __shared__ int seg_end[kMaxCandCells];
 
   const int brick = blockIdx.x;
   const int bx = brick % pp.nb[0], by = (brick / pp.nb[0]) % pp.nb[1],
@@ -263,35 +267,36 @@ __global__ void __launch_bounds__(kSpreadThreads) k_pme_spread_lines(
   for (int t = threadIdx.x; t < ncol; t += blockDim.x) {
     int cx = (bcx[0] + t % ncx) % cg.n[0], cy = (bcy[0] + t / ncx) % cg.n[1];
     const int4 r = zr[cy * cg.n[0] + cx];
-    cand_start[2 * t] = r.x;
-    cand_off[2 * t + 1] = r.y;
-    cand_start[2 * t + 1] = r.z;
-    cand_off[2 * t + 2] = r.w;
+    seg_start[2 * t] = r.x;
+    seg_end[2 * t] = r.y;
+    seg_start[2 * t + 1] = r.z;
+    seg_end[2 * t + 1] = r.w;
   }
   __syncthreads();
   if (w == 0) {
     int carry = 0;
     for (int base = 0; base < ncand; base += kWave) {
       const int i = base + lane;
-      int v = i < ncand ? cand_off[i + 1] : 0;
+      int v = i < ncand ? seg_end[i] : 0;
       for (int o = 1; o < kWave; o <<= 1) {
         const int u = __shfl_up(v, o, kWave);
         if (lane >= o) v += u;
       }
-      if (i < ncand) cand_off[i + 1] = carry + v;
+      if (i < ncand) seg_end[i] = carry + v;
       carry += __shfl(v, kWave - 1, kWave);
     }
-    if (lane == 0) cand_off[0] = 0;
   }
   __syncthreads();
-  const int total = cand_off[ncand];
-  if (total <= kCandList) {
-    for (int t = threadIdx.x; t < ncand; t += blockDim.x) {
-      const int b = cand_off[t], e = cand_off[t + 1], s0 = cand_start[t];
-      for (int k = b; k < e; ++k) cand_list[k] = s0 + (k - b);
+  const int total = ncand > 0 ? seg_end[ncand - 1] : 0;
+  // candidate f: the first segment whose end passes f (never an empty one)
+  auto candidate = [&](int f) {
+    int lo = 0, hi = ncand - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (seg_end[mid] > f) hi = mid; else lo = mid + 1;
     }
-    __syncthreads();
-  }
+    return seg_start[lo] + f - (lo > 0 ? seg_end[lo - 1] : 0);
+  };
 
   const int lx = lane & (B - 1), ly = lane / B;
   float acc[B] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -300,7 +305,7 @@ __global__ void __launch_bounds__(kSpreadThreads) k_pme_spread_lines(
     unsigned packed = 0u;
     bool meets = false;
     if (f < total) {
-      const int sl = spread_candidate(f, total, ncand, cand_list, cand_start, cand_off);
+      const int sl = candidate(f);
       const float4 p = xs[sl];
       float4* row = &wts[w][lane][0];
       float t[4], dt[4];
@@ -367,13 +372,17 @@ __global__ void __launch_bounds__(kSpreadThreads) k_pme_spread_lines(
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
+  float* const mine = reinterpret_cast<float*>(&wts[w][0][0]);
 #pragma unroll
-  for (int z = 0; z < B; ++z) red[w][z][lane] = acc[z];
+  for (int z = 0; z < B; ++z) mine[z * kWave + lane] = acc[z];
   __syncthreads();
+  auto line = [&](int c, int z, int col) {
+    return reinterpret_cast<const float*>(&wts[c][0][0])[z * kWave + col];
+  };
   for (int t = threadIdx.x; t < B * kWave; t += blockDim.x) {
     const int z = t / kWave, col = t % kWave, x = col % B, y = col / B;
     if (x < bex && y < bey && z < bez) {
-      const float s = ((red[0][z][col] + red[1][z][col]) + red[2][z][col]) + red[3][z][col];
+      const float s = ((line(0, z, col) + line(1, z, col)) + line(2, z, col)) + line(3, z, col);
       grid_q[((size_t)(g0z + z) * pp.K[1] + (g0y + y)) * pp.K[0] + g0x + x] = s;
     }
   }

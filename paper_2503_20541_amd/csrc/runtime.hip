@@ -178,12 +178,33 @@ int alloc_list(mdx_ctx* x, int cap) {
   cap = std::max(4, (cap + 3) / 4 * 4);   // lists are padded to groups of four tiles
   dev_free(x, c.tiles);
   dev_free(x, c.ptiles);
+  dev_free(x, c.jpart);
+  dev_free(x, c.ppos);
+  dev_free(x, c.in_fill);
+  dev_free(x, c.in_sorted);
   c.tiles = nullptr;
   c.ptiles = nullptr;
+  c.jpart = nullptr;
+  c.ppos = nullptr;
+  c.in_fill = nullptr;
+  c.in_sorted = nullptr;
   c.version++;   // a graph captured before holds the old addresses
-  int rc = dev_alloc(x, &c.tiles, (size_t)cap * c.max_clusters);
+  const size_t nt = (size_t)cap * c.max_clusters;
+  int rc = dev_alloc(x, &c.tiles, nt);
   if (rc != MDX_OK) return rc;
-  if ((rc = dev_alloc(x, &c.ptiles, (size_t)cap * c.max_clusters)) != MDX_OK) return rc;
+  if ((rc = dev_alloc(x, &c.ptiles, nt)) != MDX_OK) return rc;
+  if (c.half_list) {
+    if ((rc = dev_alloc(x, &c.jpart, 12 * nt)) != MDX_OK) return rc;
+    if ((rc = dev_alloc(x, &c.ppos, nt)) != MDX_OK) return rc;
+    if ((rc = dev_alloc(x, &c.in_fill, nt)) != MDX_OK) return rc;
+    if ((rc = dev_alloc(x, &c.in_sorted, nt)) != MDX_OK) return rc;
+    if (!c.in_count) {
+      if ((rc = dev_alloc(x, &c.in_count, (size_t)c.max_clusters)) != MDX_OK) return rc;
+    }
+    // no list yet: nothing listed as anyone's j-cluster
+    MDX_TRY(hipMemset(c.in_count, 0, sizeof(int) * c.max_clusters));
+    MDX_TRY(hipMemset(c.jpart, 0, sizeof(float) * 12 * nt));
+  }
   c.nl_cap = cap;
   return MDX_OK;
 }
@@ -1338,7 +1359,7 @@ namespace {
 // Layout of a saved state: a header, then the device arrays that a later step
 // reads, each starting at a multiple of 256 bytes.
 constexpr uint64_t kStateMagic = 0x3154535844584d44ull;   // "DMXDXST1"
-constexpr int64_t kStateVersion = 1;
+constexpr int64_t kStateVersion = 2;
 
 struct StateHeader {
   uint64_t magic;
@@ -1383,6 +1404,16 @@ std::vector<Segment> state_segments(const Ctx& c) {
     s.push_back({c.vc, sizeof(float) * 3 * n});
   }
   if (c.has_pme) s.push_back({c.brick_zr, sizeof(int4) * (size_t)c.pg.nb[2] * ncol});
+  if (c.half_list) {
+    // the tiles' j partials (a pruned step keeps the dropped tiles' zeros)
+    // and the incoming lists
+    const size_t nt = nc * (size_t)c.nl_cap;
+    s.push_back({c.jpart, sizeof(float) * 12 * nt});
+    s.push_back({c.ppos, sizeof(int) * nt});
+    s.push_back({c.in_count, sizeof(int) * nc});
+    s.push_back({c.in_fill, sizeof(int) * nt});
+    s.push_back({c.in_sorted, sizeof(int) * nt});
+  }
   return s;
 }
 

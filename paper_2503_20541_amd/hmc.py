@@ -147,5 +147,5 @@ def esjd_loss(sims, x0s, m, mu_dt, mu_L, xi_v, xi_dt, kT, sigma_dt_rel=0.01, sig
         alpha = torch.clamp(torch.exp(-(Etot[1:] - Etot[0]) / kT), max=1.0)
         jump = ((X[1:].double() - X[0].double()) ** 2).sum(dim=(1, 2))
         total = total + (w * alpha / ell * jump).sum()
-        info.append(dict(alpha=alpha.detach(), jump=jump.detach(), dt=float(dt)))
+        info.append(dict(alpha=alpha.detach(), jump=jump.detach(), dt=float(dt.detach())))
     return total / len(sims), dict(L_q=L_q, replicas=info)

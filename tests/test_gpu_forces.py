@@ -28,7 +28,7 @@ def _nonbonded_gpu(s, **kw):
         return t["force"].cpu().numpy(), t["e_nb"].cpu().numpy(), flags
 
 
-HALF_LIST = 0x1   # MDX_OPT_HALF_LIST: each pair once, float atomics
+HALF_LIST = 0x1   # MDX_OPT_HALF_LIST: each pair once, j forces summed in list order
 
 
 @pytest.mark.parametrize("options", [0, HALF_LIST], ids=["full", "half"])
@@ -77,9 +77,12 @@ def test_nonbonded_bitwise_deterministic():
         assert np.array_equal(a, b)
 
 
-def test_half_list_matches_full_list_and_repeats_energies():
-    # the half list (float atomics) agrees with the full list to float32
-    # rounding, and its FP64 energies (no atomics) repeat bit for bit
+def test_half_list_matches_full_list_and_repeats_bitwise():
+    # the half list agrees with the full list to float32 rounding; it uses no
+    # float atomics (the j forces are summed in list order), so its forces
+    # and FP64 energies repeat bit for bit, in a fresh context and in the
+    # same one after a rebuild
+    import torch
     s = synth.config_system("water9k")
     announce("half vs full list")
     F_full, E_full, _ = _nonbonded_gpu(s)
@@ -87,9 +90,15 @@ def test_half_list_matches_full_list_and_repeats_energies():
     F2, E2, f2 = _nonbonded_gpu(s, options=HALF_LIST)
     assert f1 == 0 and f2 == 0
     assert rel_rms(F1, F_full) < 1e-6
-    assert rel_rms(F2, F1) < 1e-6
+    assert np.array_equal(F1, F2)
     assert np.array_equal(E1, E2)
     assert np.allclose(E1, E_full, rtol=1e-12, atol=1e-9)
+    with gpu_context(s, options=HALF_LIST) as (mdx, ctx, t):
+        for _ in range(2):
+            mdx.build_neighbors(ctx, t["pos"])
+            mdx.compute_nonbonded(ctx, t["pos"], t["force"], t["e_nb"])
+        torch.cuda.synchronize()
+        assert np.array_equal(t["force"].cpu().numpy(), F1)
 
 
 @pytest.mark.parametrize("name", ["water375", "water9k"])

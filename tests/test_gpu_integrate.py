@@ -179,19 +179,22 @@ def test_kahan_vv_keeps_free_flight_exact():
     assert err[0] > 5 * err[mdx.MDX_OPT_KAHAN_VV], err
 
 
-@pytest.mark.parametrize("name,n_steps", [("water9k", 24), ("lj1k", 30)])
-def test_split_calls_match_one_call_bitwise(name, n_steps):
+@pytest.mark.parametrize("name,n_steps,options", [("water9k", 24, 0), ("lj1k", 30, 0),
+                                                  ("water9k", 24, 1)],
+                         ids=["water9k", "lj1k", "water9k-half"])
+def test_split_calls_match_one_call_bitwise(name, n_steps, options):
     # Inside one call the closing kernel of a step also opens the next one
     # (positions alternating between the caller's array and a second
     # buffer); a call of one step opens and closes with separate kernels.
-    # Both must give the same numbers bit for bit, also across list rebuilds.
+    # Both must give the same numbers bit for bit, also across list rebuilds
+    # (and with the half list, whose j forces are summed in list order).
     import torch
     s = synth.config_system(name)
     dt = 0.5 if name == "water9k" else float(s.dt)
     out = []
     for chunks in ([n_steps], [5, 7, 1, n_steps - 13], [1] * n_steps):
-        announce(f"{name} {n_steps} steps in calls of {chunks[:4]}")
-        with gpu_context(s) as (m, ctx, t):
+        announce(f"{name} {n_steps} steps in calls of {chunks[:4]} options={options}")
+        with gpu_context(s, options=options) as (m, ctx, t):
             m.build_neighbors(ctx, t["pos"])
             m.compute_nonbonded(ctx, t["pos"], t["force"])
             if any(s.pme_grid):
@@ -243,3 +246,38 @@ def test_tiny_systems_follow_the_oracle(n):
     d = x_gpu - ref["pos"]
     d -= s.box[:, None] * np.round(d / s.box[:, None])
     assert np.abs(d).max() < 1e-4
+
+
+def test_half_list_stand_alone_call_between_steps():
+    # With the half list a pruned step reuses the j partials that the last
+    # full-list walk wrote for the tiles it drops (zero). A stand-alone force
+    # call at other positions writes every tile's partials for those: the
+    # next step must walk the full list again. After such a call in the
+    # middle of a run, the force the run leaves behind equals a fresh
+    # evaluation at its final positions.
+    import torch
+    s = synth.config_system("water9k")
+    announce("half list: stand-alone call between integrate calls")
+    with gpu_context(s, options=1) as (m, ctx, t):
+        m.build_neighbors(ctx, t["pos"])
+        m.compute_nonbonded(ctx, t["pos"], t["force"])
+        m.compute_pme(ctx, t["pos"], t["force"])
+        m.integrate_step(ctx, t["pos"], t["vel"], t["force"], 4, 0.5)
+        # up to 0.5 A per coordinate: below r_g / 2 (no stale list), enough
+        # to bring pairs of tiles the pruned list dropped within r_c
+        shifted = t["pos"] + (torch.rand(t["pos"].shape, generator=torch.Generator(
+            device="cuda:0").manual_seed(3), device="cuda:0") - 0.5)
+        box = torch.as_tensor(s.box, device="cuda:0")[:, None]
+        shifted = torch.remainder(shifted, box).contiguous()
+        scratch = torch.zeros_like(t["force"])
+        m.compute_nonbonded(ctx, shifted, scratch)
+        m.integrate_step(ctx, t["pos"], t["vel"], t["force"], 3, 0.5)
+        F_run = t["force"].cpu().numpy().astype(np.float64)
+        m.build_neighbors(ctx, t["pos"])
+        fresh = torch.zeros_like(t["force"])
+        m.compute_nonbonded(ctx, t["pos"], fresh)
+        m.compute_pme(ctx, t["pos"], fresh)
+        torch.cuda.synchronize()
+        assert m.get_status(ctx) == 0
+        F_fresh = fresh.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(F_run - F_fresh) < 1e-6 * np.linalg.norm(F_fresh)

@@ -62,6 +62,7 @@ def _run(s, chunks, langevin, options, save_after=None):
     ("water375", (0.596, 0.1, 20541), 0),          # PME water, Langevin 300 K
     ("water9k", None, 0),                           # PME water, velocity Verlet
     ("lj1k", None, 0x4),                            # MDX_OPT_KAHAN_VV
+    ("water9k", None, 0x1),                         # MDX_OPT_HALF_LIST
 ])
 def test_resume_from_saved_state_is_bitwise(name, langevin, options):
     s = synth.config_system(name)
