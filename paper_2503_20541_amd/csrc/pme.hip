@@ -245,8 +245,10 @@ __global__ void __launch_bounds__(kSpreadThreads) k_pme_spread_lines(
   // it to the occupancy the LDS allows). Per candidate: q t_x[0..3],
   // t_y[0..3], and the weights of the brick's 8 z planes (t_z[dz - lz] where
   // the stencil covers lz, else 0); after its chunks each wave keeps its
-  // brick lines ([lz][ly B + lx]) in its own part of the table.
-  __shared__ float4 wts[kSpreadWaves][kWave][4];
+  // brick lines ([lz][ly B + lx]) in its own part of the table. Stored
+  // component-major ([wave][k][lane]): a row write is then one 16-byte
+  // store per lane at consecutive addresses (no bank conflicts).
+  __shared__ float4 wts[kSpreadWaves][4][kWave];
   // the candidate slot ranges (two per column, periodic wrap) and the
   // inclusive prefix sums of their sizes
   __shared__ int seg_start[kMaxCandCells];
@@ -307,7 +309,7 @@ __global__ void __launch_bounds__(kSpreadThreads) k_pme_spread_lines(
     if (f < total) {
       const int sl = candidate(f);
       const float4 p = xs[sl];
-      float4* row = &wts[w][lane][0];
+      auto row = [&](int k) -> float4& { return wts[w][k][lane]; };
       float t[4], dt[4];
       // stencil point t sits at brick-local offset d - t (d = k0 - g0 mod K)
       int k;
@@ -316,13 +318,13 @@ __global__ void __launch_bounds__(kSpreadThreads) k_pme_spread_lines(
       int dx = k - g0x;
       if (dx < 0) dx += pp.K[0];
       spline4(fr, t, dt);
-      row[0] = make_float4(p.w * t[0], p.w * t[1], p.w * t[2], p.w * t[3]);
+      row(0) = make_float4(p.w * t[0], p.w * t[1], p.w * t[2], p.w * t[3]);
       __builtin_amdgcn_sched_barrier(0);
       k = grid_coord_f(p.y, pp.s_hi[1], pp.s_lo[1], pp.Kf[1], pp.invK[1], fr);
       int dy = k - g0y;
       if (dy < 0) dy += pp.K[1];
       spline4(fr, t, dt);
-      row[1] = make_float4(t[0], t[1], t[2], t[3]);
+      row(1) = make_float4(t[0], t[1], t[2], t[3]);
       packed = (unsigned)dx | (unsigned)dy << 8;
       const bool meets_xy = dx < bex + 3 && dy < bey + 3;
       __builtin_amdgcn_sched_barrier(0);
@@ -337,10 +339,9 @@ __global__ void __launch_bounds__(kSpreadThreads) k_pme_spread_lines(
         const float v = (t3 & 2) ? hi : lo;
         return (unsigned)t3 < 4u ? v : 0.f;
       };
-      float* zrow = reinterpret_cast<float*>(&row[2]);
 #pragma unroll
       for (int lz = 0; lz < B; ++lz) {
-        zrow[lz] = zw(lz);
+        reinterpret_cast<float*>(&row(2 + lz / 4))[lz % 4] = zw(lz);
         __builtin_amdgcn_sched_barrier(0);
       }
       meets = meets_xy && dz < bez + 3;
@@ -354,9 +355,9 @@ __global__ void __launch_bounds__(kSpreadThreads) k_pme_spread_lines(
       m &= m - 1ull;
       const unsigned pa = __builtin_amdgcn_readlane(packed, a);
       const int t1 = (int)(pa & 255u) - lx, t2 = (int)((pa >> 8) & 255u) - ly;
-      const float* wa = reinterpret_cast<const float*>(&wts[w][a][0]);
-      const float wxv = wa[t1 & 3], wyv = wa[4 + (t2 & 3)];
-      const float4 z0 = wts[w][a][2], z1 = wts[w][a][3];
+      const float wxv = reinterpret_cast<const float*>(&wts[w][0][a])[t1 & 3];
+      const float wyv = reinterpret_cast<const float*>(&wts[w][1][a])[t2 & 3];
+      const float4 z0 = wts[w][2][a], z1 = wts[w][3][a];
       const float wv = ((unsigned)t1 < 4u && (unsigned)t2 < 4u) ? wxv * wyv : 0.f;
       acc[0] += wv * z0.x;
       acc[1] += wv * z0.y;
