@@ -917,11 +917,10 @@ int integrate_eager(mdx_ctx* x, float* pos, float* vel, float* force, int32_t n_
     }));
     // The reciprocal-space potential only needs this step's slot positions
     // and the PME brick slot ranges: the spread and the FFT passes run on the
-    // second stream, from the end of the column sort on, concurrently with
-    // the tile search and the pair kernel; the closing kernel (force
-    // interpolation) waits for them. The fork and join events are recorded
-    // by the column sort's and the last FFT pass's own dispatches (no marker
-    // packets between kernels).
+    // second stream, from the end of the list build on, concurrently with
+    // the pair kernel; the closing kernel (force interpolation) waits for
+    // them. The fork and join events are recorded by the tile search's and
+    // the last FFT pass's own dispatches (no marker packets between kernels).
     if (c.has_pme) {
       MDX_TRY(hipStreamWaitEvent(x->aux, x->ev_fork, 0));
       std::pair<hipEvent_t, hipEvent_t>* tslot;
