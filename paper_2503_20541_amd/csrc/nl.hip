@@ -735,12 +735,12 @@ __device__ void search_cluster(const BuildArgs& a, int ic, SearchLds& sl, const 
   if (lane < padded - kept) a.tiles[(size_t)ic * a.cap + kept + lane] = make_uint2(0u, 0u);
   if (lane == 0) {
     a.tile_count[ic] = padded;
-    // only a cluster whose tiles overflow the capacity reports its count
-    // (one device-scope atomic per wave on one address would serialize)
-    if (count > a.cap) {
-      atomicOr(a.flags, MDX_FLAG_NL_OVERFLOW);
-      atomicMax(a.nl_needed, count);
-    }
+    // only a cluster whose tiles fill more than two thirds of the capacity
+    // reports its count (one device-scope atomic per wave on one address
+    // would serialize): an explicit build then grows the list ahead of the
+    // rebuilds inside mdx_integrate_step, which cannot grow it
+    if (count > a.cap - a.cap / 3) atomicMax(a.nl_needed, count);
+    if (count > a.cap) atomicOr(a.flags, MDX_FLAG_NL_OVERFLOW);
     if (overflow) atomicOr(a.flags, MDX_FLAG_CELL_OVERFLOW);
   }
 }

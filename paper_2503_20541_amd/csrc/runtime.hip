@@ -702,8 +702,10 @@ int mdx_build_neighbors(mdx_ctx* x, const float* pos) {
     MDX_TRY(mdx::launch_fill_i32(reinterpret_cast<int*>(c.vc), 0, 3 * c.n, c.stream));
   }
   // A column list grows by doubling up to n atoms (where it cannot
-  // overflow), the tile list to the count the build reported, so this ends
-  // after a few attempts.
+  // overflow), the tile list to 1.5 times the largest count the build
+  // reported when that count overflows or fills more than two thirds of the
+  // capacity (headroom for the rebuilds inside mdx_integrate_step, which
+  // cannot grow it), so this ends after a few attempts.
   for (int attempt = 0; attempt < 40; ++attempt) {
     MDX_TRY(timed(x, MDX_TIMING_BUILD, c.stream, [&] { return mdx::launch_build_list(c, pos); }));
     int needed = 0;
@@ -721,10 +723,10 @@ int mdx_build_neighbors(mdx_ctx* x, const float* pos) {
       int rc = dev_alloc(x, &c.col_atoms, (size_t)c.cg.ncell * c.col_cap);
       if (rc != MDX_OK) return rc;
       // the tile count of an incomplete list says nothing: build again first
-    } else if (needed <= c.nl_cap) {
+    } else if (needed <= c.nl_cap - c.nl_cap / 3) {
       return MDX_OK;
     } else {
-      int rc = alloc_list(x, (needed + needed / 8 + 16 + 15) / 16 * 16);
+      int rc = alloc_list(x, (needed + needed / 2 + 16 + 15) / 16 * 16);
       if (rc != MDX_OK) return rc;
     }
     // clear the overflow bits this build latched, and build again
