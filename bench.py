@@ -64,6 +64,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-batch", action="store_true",
                    help="skip the 256-replica batch against sequential replicas timing")
+    p.add_argument("--no-hmc", action="store_true",
+                   help="skip the HMC tuning measurement")
     p.add_argument("--no-adjoint", action="store_true",
                    help="skip the forward+adjoint against plain forward timing (9k water)")
     p.add_argument("--equilibrate", type=int, default=3000,
@@ -431,6 +433,73 @@ def adjoint_ratio(reps=5):
             "ratio": round(t_adj / t_fwd, 3), "repetitions": reps, "status_flags": flags}
 
 
+def hmc_tuning(iters=8, chains=10):
+    """Differentiable HMC tuning (the paper's Sec. IV) on the 9,000-atom water
+    box equilibrated at 300 K: `chains` chains (the paper's R = 10) from the paper's untuned
+    parameters (dt 0.5 fs, L = 10, no mass repartitioning), O and H masses as
+    two shared groups with the total mass fixed. Each iteration evaluates
+    L_HMC over every chain's proposal (forward steps with the state saved
+    after each), its reverse pass, an Adam step and the chains' Metropolis
+    moves. Timed on the host around whole iterations (the iteration
+    synchronises to read the acceptances)."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2503_20541_amd as mdx
+    from paper_2503_20541_amd import hmc
+    s = synth.config_system("water9k")
+    kT = 0.0019872041 * 300.0
+    # the chains start from a 300 K liquid: 2,000 Langevin steps of 1 fs
+    # (gamma 0.1 / fs) from the synthetic lattice start
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    desc, keep = mdx.desc_from_system(s)
+    ctx = mdx.create(desc, stream.cuda_stream)
+    try:
+        pos = torch.from_numpy(s.pos.copy()).to(dev)
+        vel = torch.from_numpy(s.vel.copy()).to(dev)
+        force = torch.zeros_like(pos)
+        mdx.build_neighbors(ctx, pos)
+        mdx.compute_nonbonded(ctx, pos, force)
+        mdx.compute_pme(ctx, pos, force)
+        mdx.set_langevin(ctx, kT, 0.1, 20541)
+        mdx.integrate_step(ctx, pos, vel, force, 2000, 1.0)
+        torch.cuda.synchronize()
+        eq_flags = mdx.get_status(ctx)
+        s = s.copy()
+        s.pos = pos.cpu().numpy()
+    finally:
+        mdx.destroy(ctx)
+    groups = np.where(s.atom_type == 0, 0, 1)
+    t = hmc.HMCTuner(s, chains, kT, 0.5, 10.0, groups, seed=20541)
+    try:
+        t.step()                      # warm-up (library set-up, first allocations)
+        torch.cuda.synchronize()
+        hist, steps = [], 0
+        t0 = time.perf_counter()
+        for _ in range(iters):
+            r = t.step()
+            hist.append(r)
+            steps += chains * r["L_q"]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        flags = eq_flags
+        for sim in t.sims:
+            flags |= mdx.get_status(sim.ctx)
+    finally:
+        t.close()
+    return {"workload": "water9k: 3,000 flexible waters, PME 48^3, 300 K; %d chains, L_HMC over "
+                        "L_q steps, gradients in mu_dt, mu_L and the O/H masses (total fixed)"
+                        % chains,
+            "iterations": iters, "ms_per_iteration": round(1e3 * dt / iters, 2),
+            "trajectory_steps_per_s": round(steps / dt, 1),
+            "loss": [round(h["loss"], 6) for h in hist],
+            "mu_dt_fs": round(hist[-1]["mu_dt"], 4), "mu_L": round(hist[-1]["mu_L"], 3),
+            "masses_O_H": [round(v, 4) for v in hist[-1]["group_masses"]],
+            "acceptance": round(float(np.mean([h["acceptance"] for h in hist])), 3),
+            "status_flags": flags}
+
+
 def batch_throughput(steps=50):
     """Batched replicas: the 256-replica workload (even index LJ at reduced
     density 0.8, odd index flexible water, 500-20,000 atoms log-uniform, each
@@ -679,6 +748,8 @@ def main():
         result["adjoint"] = adjoint_ratio()
     if not args.cpu_only and not args.no_batch:
         result["batch"] = batch_throughput()
+    if not args.cpu_only and not args.no_hmc:
+        result["hmc"] = hmc_tuning()
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(s)
     print(json.dumps(result), flush=True)

@@ -22,6 +22,8 @@ one-step segments with each state's loss terms injected between them
 dynamics; the sampled velocities and the kinetic energy depend on them in
 torch) and dt. Every step of the forward and reverse pass runs in the
 library's kernels; this module assembles the objective from their outputs.
+`HMCTuner` runs the tuning: gradient steps on mu_dt, mu_L and a mass
+repartitioning with the total mass fixed, and the chains' Metropolis moves.
 """
 from __future__ import annotations
 
@@ -147,5 +149,101 @@ def esjd_loss(sims, x0s, m, mu_dt, mu_L, xi_v, xi_dt, kT, sigma_dt_rel=0.01, sig
         alpha = torch.clamp(torch.exp(-(Etot[1:] - Etot[0]) / kT), max=1.0)
         jump = ((X[1:].double() - X[0].double()) ** 2).sum(dim=(1, 2))
         total = total + (w * alpha / ell * jump).sum()
-        info.append(dict(alpha=alpha.detach(), jump=jump.detach(), dt=float(dt.detach())))
+        info.append(dict(alpha=alpha.detach(), jump=jump.detach(), dt=float(dt.detach()),
+                         positions=X.detach()))
     return total / len(sims), dict(L_q=L_q, replicas=info)
+
+
+class HMCTuner:
+    """Tunes the HMC proposal by gradient ascent on L_HMC (Sec. IV).
+
+    R chains of `system` (one library context each) start from its
+    positions. Each iteration draws the chains' velocity and time-step
+    normals from a seeded generator and evaluates L_HMC and its gradient with
+    respect to mu_dt, mu_L and one log-scale per mass group: m_i = m0_i
+    exp(theta_g(i)), rescaled so that the total mass stays that of m0 (a
+    change of the total mass is a change of the time step). It then takes an
+    Adam step towards a larger L_HMC and moves every chain. The proposal is
+    the state after l steps, l drawn from the weights w_l of L_HMC (the folded
+    normal N_F(mu_L, sigma_L) at l = 1..L_q, normalised), accepted with its
+    probability alpha_{i,l}. The chains run one after another, each on its own
+    context; all force and reverse-pass work runs in the library's kernels.
+    """
+
+    def __init__(self, system, n_chains: int, kT: float, mu_dt: float, mu_L: float, mass_groups,
+                 lr=(0.01, 0.2, 0.01), seed: int = 0, device="cuda:0"):
+        import numpy as np
+        from .trajectory import Simulation
+        self.dev = torch.device(device)
+        self.sims = [Simulation(system, 1, 1, device=device) for _ in range(n_chains)]
+        self.n = int(system.n_atoms)
+        self.kT = float(kT)
+        self.box = torch.as_tensor(np.asarray(system.box, np.float32), device=self.dev)[:, None]
+        self.x = [torch.from_numpy(np.asarray(system.pos, np.float32).copy()).to(self.dev)
+                  for _ in range(n_chains)]
+        self.m0 = torch.from_numpy(np.asarray(system.mass, np.float64)).to(self.dev)
+        self.groups = torch.as_tensor(np.asarray(mass_groups), dtype=torch.long, device=self.dev)
+        n_groups = int(self.groups.max()) + 1
+        f64 = dict(dtype=torch.float64, device=self.dev)
+        self.mu_dt = torch.tensor(float(mu_dt), requires_grad=True, **f64)
+        self.mu_L = torch.tensor(float(mu_L), requires_grad=True, **f64)
+        self.theta = torch.zeros(n_groups, requires_grad=True, **f64)
+        self.opt = torch.optim.Adam([{"params": [self.mu_dt], "lr": lr[0]},
+                                     {"params": [self.mu_L], "lr": lr[1]},
+                                     {"params": [self.theta], "lr": lr[2]}])
+        self.rng = np.random.Generator(np.random.PCG64(seed))
+
+    def masses(self):
+        """Per-atom masses (float64, differentiable in theta), total fixed."""
+        m = self.m0 * torch.exp(self.theta[self.groups])
+        return m * (self.m0.sum() / m.sum())
+
+    def _wrap(self, x):
+        w = torch.remainder(x, self.box)
+        return torch.where(w >= self.box, w - self.box, w).contiguous()
+
+    def step(self):
+        """One iteration; returns the objective before the update, the
+        parameters after it and the chains' acceptances."""
+        R = len(self.sims)
+        xi_v = [torch.from_numpy(self.rng.standard_normal((3, self.n)).astype("float32"))
+                .to(self.dev) for _ in range(R)]
+        xi_dt = [float(z) for z in self.rng.standard_normal(R)]
+        m = self.masses()
+        mu_L0 = float(self.mu_L.detach())
+        loss, info = esjd_loss(self.sims, self.x, m.float(), self.mu_dt, self.mu_L, xi_v, xi_dt,
+                               self.kT)
+        self.opt.zero_grad()
+        (-loss).backward()
+        self.opt.step()
+        with torch.no_grad():
+            self.mu_dt.clamp_(min=1e-3)
+            self.mu_L.clamp_(min=1.0)
+        # chain moves: l from the weights of L_HMC, accepted with alpha_{i,l}
+        L_q = info["L_q"]
+        ell = torch.arange(1, L_q + 1, dtype=torch.float64)
+        w = folded_normal_pdf(ell, mu_L0, 1.0).numpy()
+        w = w / w.sum()
+        accepted = []
+        for i, r in enumerate(info["replicas"]):
+            l = int(self.rng.choice(L_q, p=w)) + 1
+            ok = bool(self.rng.random() < float(r["alpha"][l - 1]))
+            if ok:
+                self.x[i] = self._wrap(r["positions"][l])
+            accepted.append(ok)
+        return dict(loss=float(loss.detach()), mu_dt=float(self.mu_dt.detach()),
+                    mu_L=float(self.mu_L.detach()),
+                    group_masses=self.group_masses(), acceptance=sum(accepted) / R, L_q=L_q)
+
+    def group_masses(self):
+        """The current mass of one atom of each group (the first of the group)."""
+        m = self.masses().detach()
+        out = []
+        for g in range(int(self.groups.max()) + 1):
+            idx = torch.nonzero(self.groups == g)[0, 0]
+            out.append(float(m[idx]))
+        return out
+
+    def close(self):
+        for s in self.sims:
+            s.close()

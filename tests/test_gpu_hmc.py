@@ -109,3 +109,49 @@ def test_free_particles_closed_form():
     dW = (ohmc.folded_normal_pdf(ell, mu_L + 1e-6, 1.0) * ell).sum() - \
          (ohmc.folded_normal_pdf(ell, mu_L - 1e-6, 1.0) * ell).sum()
     assert abs(g["mu_L"] - L / W * dW / 2e-6) <= 1e-4 * abs(L / W * dW / 2e-6)
+
+
+def _tune(seed, iters=2):
+    import torch
+    from paper_2503_20541_amd import hmc
+    s = synth.config_system("water375")
+    groups = np.where(s.atom_type == 0, 0, 1)
+    t = hmc.HMCTuner(s, 2, KT, 1.0, 5.0, groups, lr=(0.01, 0.2, 0.01), seed=seed)
+    try:
+        x_start = [x.clone() for x in t.x]
+        out = [t.step() for _ in range(iters)]
+        m = t.masses().detach().cpu().numpy()
+        x = [xi.cpu().numpy() for xi in t.x]
+        flags = [hmc.mdx.get_status(sim.ctx) for sim in t.sims]
+        theta = t.theta.detach().cpu().numpy()
+        torch.cuda.synchronize()
+        return s, out, m, x, [xs.cpu().numpy() for xs in x_start], flags, theta
+    finally:
+        t.close()
+
+
+def test_tuner_steps_keep_the_total_mass_and_repeat():
+    # two iterations of gradient ascent on L_HMC with the chains' Metropolis
+    # moves: the total mass stays fixed, Adam's first steps have the size of
+    # the learning rate (the gradients were finite and non-zero), the chains
+    # stay in the box, and a second tuner with the same seed repeats the
+    # first bit for bit
+    announce("hmc tuner water375 two chains two iterations")
+    s, out, m, x, x0, flags, theta = _tune(7)
+    assert flags == [0, 0]
+    m0 = s.mass.astype(np.float64)
+    assert abs(m.sum() - m0.sum()) <= 1e-12 * m0.sum()
+    first = out[0]
+    # Adam's first step is lr g / (|g| + 1e-8)
+    assert abs(abs(first["mu_dt"] - 1.0) - 0.01) <= 1e-4 * 0.01
+    assert abs(abs(first["mu_L"] - 5.0) - 0.2) <= 1e-4 * 0.2
+    assert np.all(np.isfinite(theta)) and np.all(theta != 0.0)
+    for xi in x:
+        assert np.all((xi >= 0.0) & (xi < s.box[:, None]))
+    for r in out:
+        assert np.isfinite(r["loss"]) and r["loss"] > 0.0
+    s2, out2, m2, x2, _, _, _ = _tune(7)
+    assert out2 == out
+    assert np.array_equal(m2, m)
+    for a, b in zip(x, x2):
+        assert np.array_equal(a, b)
