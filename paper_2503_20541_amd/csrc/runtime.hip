@@ -106,10 +106,13 @@ int default_capacity(int n, const float box[3], float r_list, double a, int max_
   double V = (double)box[0] * box[1] * box[2];
   double rho = n / V;
   double r = (double)r_list + a;
-  // clusters whose boxes reach within r_list; a half list holds each pair once
+  // clusters whose boxes reach within r_list; a half list holds each pair
+  // once. The build regrows a list whose largest per-cluster count passes two
+  // thirds of the capacity, and the largest count runs above this mean, so
+  // the capacity starts at 2.25 times it.
   double expect = (full_list ? 1.0 : 0.5) * rho * 4.0 / 3.0 * M_PI * r * r * r /
                   mdx::kClusterSize;
-  int cap = (int)std::ceil(1.5 * expect + 16.0);
+  int cap = (int)std::ceil(2.25 * expect + 16.0);
   cap = (cap + 15) / 16 * 16;
   // in a box small next to r_list a j-cluster can take one tile per periodic
   // image its pairs use, so the bound is a few times the cluster count
