@@ -664,21 +664,33 @@ __device__ void search_cluster(const BuildArgs& a, int ic, SearchLds& sl, const 
     // every candidate of the group with one image for all its pairs: the
     // differences from the image table (rounded as min_image_h rounds them)
     const bool shared = __ballot(c >= 0 && cimg == kMixedImage) == 0ull;
-    unsigned bit = 0, img = 0;
     const int sj = jc * kClusterSize + b;
     // the cluster's own tile: slot pairs a < b (half list) or a != b
-    if (jc >= 0 && ivalid && b < nv && (jc != ic || b > ia || (!a.half && b < ia))) {
-      float dx, dy, dz;
-      if (shared) {
-        const float4 am = img_am[cimg], cp = img_cp[cimg];
-        dx = image_diff(pi.x, pj.x, am.x, cp.x);
-        dy = image_diff(pi.y, pj.y, am.y, cp.y);
-        dz = image_diff(pi.z, pj.z, am.z, cp.z);
-      } else {
-        dx = min_image_h(pi.x, lmx, pj.x, a.cg.L[0], a.cg.hL[0]);
-        dy = min_image_h(pi.y, lmy, pj.y, a.cg.L[1], a.cg.hL[1]);
-        dz = min_image_h(pi.z, lmz, pj.z, a.cg.L[2], a.cg.hL[2]);
+    const bool cand =
+        (jc >= 0) & ivalid & (b < nv) & ((jc != ic) | (b > ia) | (!a.half & (b < ia)));
+    if (shared) {
+      // Without branches: every lane forms its pair's difference and the
+      // predicate (candidate, within r_nl, not excluded) decides its bit;
+      // only atoms with more than four exclusions walk their list.
+      const float4 am = img_am[cimg], cp = img_cp[cimg];
+      const float dx = image_diff(pi.x, pj.x, am.x, cp.x);
+      const float dy = image_diff(pi.y, pj.y, am.y, cp.y);
+      const float dz = image_diff(pi.z, pj.z, am.z, cp.z);
+      const bool within = cand & (dist2(dx, dy, dz) < a.cg.rnl2);
+      bool excluded = (sj == ex0) | (sj == ex1) | (sj == ex2) | (sj == ex3);
+      const bool walk = within & ex_more & !excluded;
+      if (__ballot(walk) != 0ull && walk) {
+        const int aj = a.perm[sj];
+        for (int k = eb + 4; k < ee; ++k) excluded |= (a.ex_idx[k] == aj);
       }
+      emit(jc, __ballot(within & !excluded), cimg);
+      return;
+    }
+    unsigned bit = 0, img = 0;
+    if (cand) {
+      const float dx = min_image_h(pi.x, lmx, pj.x, a.cg.L[0], a.cg.hL[0]);
+      const float dy = min_image_h(pi.y, lmy, pj.y, a.cg.L[1], a.cg.hL[1]);
+      const float dz = min_image_h(pi.z, lmz, pj.z, a.cg.L[2], a.cg.hL[2]);
       if (dist2(dx, dy, dz) < a.cg.rnl2) {
         bool excluded = sj == ex0 || sj == ex1 || sj == ex2 || sj == ex3;
         if (ex_more && !excluded) {
@@ -686,16 +698,11 @@ __device__ void search_cluster(const BuildArgs& a, int ic, SearchLds& sl, const 
           for (int k = eb + 4; k < ee; ++k) excluded |= (a.ex_idx[k] == aj);
         }
         bit = excluded ? 0u : 1u;
-        if (!shared)
-          img = image_code(pi.x, pj.x, a.cg.hL[0]) | image_code(pi.y, pj.y, a.cg.hL[1]) << 2 |
-                image_code(pi.z, pj.z, a.cg.hL[2]) << 4;
+        img = image_code(pi.x, pj.x, a.cg.hL[0]) | image_code(pi.y, pj.y, a.cg.hL[1]) << 2 |
+              image_code(pi.z, pj.z, a.cg.hL[2]) << 4;
       }
     }
     unsigned long long rem = __ballot(bit != 0);
-    if (shared) {
-      emit(jc, rem, cimg);
-      return;
-    }
     // One tile entry per periodic image among a tile's pairs (several only
     // in a box small next to the clusters and the list radius): in each
     // round, the pairs sharing the image of the tile's first remaining pair.
