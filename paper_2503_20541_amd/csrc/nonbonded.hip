@@ -23,6 +23,8 @@
 
 #include <hip/hip_ext.h>
 
+#include <type_traits>
+
 namespace mdx {
 
 // erfc(x) = exp(-x^2) R(x): R = t P(t), t = 1/(1 + 0.42 x), with P of degree 7
@@ -30,10 +32,10 @@ namespace mdx {
 // equal ripple; fit_erfc.py beside this file) to the scaled complementary
 // error function exp(x^2) erfc(x) on [0, 6]: relative error below 4e-8 in
 // exact arithmetic, about 3.5e-7 as evaluated in float32 (the rounding of t
-// dominates). The caller multiplies by exp(-x^2), which it needs for the
-// force anyway.
-__device__ __forceinline__ float erfc_scaled(float x) {
-  const float t = __builtin_amdgcn_rcpf(fmaf(0.42f, x, 1.0f));
+// dominates). Here x = alpha r and the caller passes r and c = 0.42 alpha.
+// The caller multiplies by exp(-x^2), which it needs for the force anyway.
+__device__ __forceinline__ float erfc_scaled(float r, float c) {
+  const float t = __builtin_amdgcn_rcpf(fmaf(c, r, 1.0f));
   float p = 7.619556785e-02f;
   p = fmaf(p, t, -3.458804786e-01f);
   p = fmaf(p, t, 4.864609241e-01f);
@@ -49,6 +51,7 @@ struct PairParams {
   float L[3], hL[3];
   float rc2;
   float alpha;                // Ewald alpha
+  float alpha_t;              // 0.42 alpha: erfc's t = 1/(1 + alpha_t r)
   float exp_c;                // -alpha^2 log2(e): exp(-alpha^2 r^2) = 2^(exp_c r^2)
   float two_a_sqrtpi;         // 2 alpha / sqrt(pi)
   float coulomb_k;
@@ -159,7 +162,10 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
     img_cp[threadIdx.x] = make_float4(cp[0], cp[1], cp[2], 0.f);
   }
   __syncthreads();
-  const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  // the wave index is the same on every lane: read it as such, so that the
+  // cluster and its list rows are addressed from scalar registers
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int lane = threadIdx.x & (kWave - 1);
   const int ic = blockIdx.x * 4 + w;
   const bool active = ic < meta[1];
   if (HALF && pr.invalidate && blockIdx.x == 0 && threadIdx.x < 2) pr.invalidate[threadIdx.x] = 1;
@@ -192,8 +198,11 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
     float* const jrow = HALF ? ha.jpart + (size_t)ic * cap * 12 + (ia < 3 ? ia : 0) * 4 + jb
                              : nullptr;
     // One group of four tiles (e: this lane's tile, sj / pj / tj: its j slot,
-    // position and type; f: the tile's full-list position).
-    auto group = [&](uint2 e, unsigned sj, float4 pj, int tj, int f) {
+    // position and type; f: the tile's full-list position). EMIT (whether
+    // this walk writes the pruned list) is a compile-time constant of each
+    // of the two loops below.
+    auto group = [&](auto emit_c, uint2 e, unsigned sj, float4 pj, int tj, int f) {
+      constexpr bool EMIT = decltype(emit_c)::value;
       const bool on = (e.y >> bitpos) & 1u;
       // the tile's image: the same differences as the minimum-image rule
       // gives for its listed pairs, without the per-pair selects
@@ -203,7 +212,7 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
       float dz = image_diff(pi.z, pj.z, am.z, cp.z);
       float r2 = dist2(dx, dy, dz);
       const bool in = on && r2 < pp.rc2;
-      if (emit) {
+      if (EMIT) {
         // keep tile tt if any of its pairs is within r_p; lane (row 0, tile
         // tt, slot 0) writes it, in list order
         const unsigned long long nearm = __builtin_amdgcn_ballot_w64(on && r2 < pr.rp2);
@@ -224,43 +233,51 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
         if (jw) jrow[(size_t)f * 12] = 0.f;
         return;
       }
-      float gx = 0.f, gy = 0.f, gz = 0.f;   // force on j (minus the force on i)
-      if (in) {
+      // Every lane evaluates the pair terms (the branch above is the same for
+      // the whole wave, so no lane's registers need to be kept aside), and a
+      // lane without a pair within r_c takes a zero factor: its operands may
+      // be infinite or NaN (r2 = 0 on the diagonal), the select drops them.
+      float gx, gy, gz;   // force on j (minus the force on i)
+      {
         const int tp = trow + tj;
         const float4 lj = lj_s[tp];       // c12, c6, 12 c12, 6 c6
-        const float rinv = __builtin_amdgcn_rsqf(r2);   // r2 is never denormal here
+        // r2 of a pair within r_c is never denormal
+        const float rinv = __builtin_amdgcn_rsqf(r2);
         const float rinv2 = rinv * rinv;
+        const float r = r2 * rinv;
         float r6 = rinv2 * rinv2 * rinv2;
-        float f_over_r = r6 * (lj.z * r6 - lj.w) * rinv2;
+        // F/r is assembled as (F/r) r^2 and multiplied by 1/r^2 once
+        float fr2 = r6 * (lj.z * r6 - lj.w);   // LJ
         float S = 1.f, dS = 0.f;
         if (SWITCH) {
-          float r = r2 * rinv;
           if (r > pp.r_s) {
             float x = (r - pp.r_s) * pp.inv_sw;
             float x2 = x * x, x3 = x2 * x;
             S = 1.0f + x3 * (-10.0f + x * (15.0f - 6.0f * x));
             dS = x2 * (-30.0f + x * (60.0f - 30.0f * x)) * pp.inv_sw;
             float u_lj = r6 * (lj.x * r6 - lj.y);
-            f_over_r = f_over_r * S - u_lj * dS * rinv;
+            fr2 = fr2 * S - u_lj * dS * r;
           }
         }
-        float ec = 0.f;
+        const float qq = qik * pj.w;
         if (COUL == kCoulEwald) {
-          float r = r2 * rinv;
-          // exp(-alpha^2 r^2) as 2^(exp_c r^2) on the transcendental unit;
-          // the energies on measurement steps are evaluated separately in FP64
-          float ex = __builtin_amdgcn_exp2f(pp.exp_c * r2);
-          ec = erfc_scaled(pp.alpha * r) * ex;
-          f_over_r += qik * pj.w * (ec * rinv + pp.two_a_sqrtpi * ex) * rinv2;
+          // k q_i q_j exp(-alpha^2 r^2) (R(alpha r) / r + 2 alpha / sqrt(pi)),
+          // with exp(-alpha^2 r^2) as 2^(exp_c r^2) on the transcendental
+          // unit; the energies on measurement steps are evaluated separately
+          // in FP64
+          const float ex = __builtin_amdgcn_exp2f(pp.exp_c * r2);
+          const float w = fmaf(erfc_scaled(r, pp.alpha_t), rinv, pp.two_a_sqrtpi);
+          fr2 = fmaf(qq, ex * w, fr2);
         }
-        if (COUL == kCoulRF) f_over_r += qik * pj.w * (rinv * rinv2 - pp.two_k_rf);
+        if (COUL == kCoulRF) fr2 = fmaf(qq, fmaf(-pp.two_k_rf, r2, rinv), fr2);
+        const float f_over_r = in ? fr2 * rinv2 : 0.f;
         gx = f_over_r * dx;
         gy = f_over_r * dy;
         gz = f_over_r * dz;
         fx -= gx;
         fy -= gy;
         fz -= gz;
-        if (ENERGY) {
+        if (ENERGY && in) {
           double2 c = lj_d[tp];
           double r2d = (double)r2;
           double r6d = 1.0 / (r2d * r2d * r2d);
@@ -307,9 +324,20 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
     // into its allocation and their cluster index is replaced by 0 before it
     // is used as an address. (Unsigned 32-bit indices let the loads use a
     // scalar base + 32-bit offset.)
-    auto tile_at = [&](int g) { return tl[(unsigned)min(g + tt, cap - 1)]; };
+    auto tile_at = [&](int g) {
+      return *reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(tl) +
+                                             ((unsigned)min(g + tt, cap - 1) << 3));
+    };
     auto slot_of = [&](uint2 e, int g) {
       return (g < cnt ? e.x : 0u) * kClusterSize + (unsigned)jb;
+    };
+    // 32-bit byte offsets from the arrays' bases (the slot arrays are far
+    // below 4 GB)
+    auto pos_at = [&](unsigned s) {
+      return *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(xs) + (s << 4));
+    };
+    auto type_at = [&](unsigned s) {
+      return *reinterpret_cast<const int*>(reinterpret_cast<const char*>(ts) + (s << 2));
     };
     // full-list position of this lane's tile of group g (half list)
     auto full_at = [&](int g) {
@@ -317,31 +345,35 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
       const int k = min(g + tt, cap - 1);
       return pruned ? ppl[k] : k;
     };
-    uint2 eA = tile_at(0), eB = tile_at(4);
-    uint2 eA2 = tile_at(8), eB2 = tile_at(12);
-    int fA = full_at(0), fB = full_at(4);
-    int fA2 = full_at(8), fB2 = full_at(12);
-    unsigned sA = slot_of(eA, 0), sB = slot_of(eB, 4);
-    float4 pA = xs[sA], pB = xs[sB];
-    int tA = ts[sA], tB = ts[sB];
-    for (int g = 0; g < cnt; g += 8) {
-      group(eA, sA, pA, tA, fA);
-      eA = eA2;
-      fA = fA2;
-      eA2 = tile_at(g + 16);
-      fA2 = full_at(g + 16);
-      sA = slot_of(eA, g + 8);
-      pA = xs[sA];
-      tA = ts[sA];
-      if (g + 4 < cnt) group(eB, sB, pB, tB, fB);
-      eB = eB2;
-      fB = fB2;
-      eB2 = tile_at(g + 20);
-      fB2 = full_at(g + 20);
-      sB = slot_of(eB, g + 12);
-      pB = xs[sB];
-      tB = ts[sB];
-    }
+    auto walk = [&](auto emit_c) {
+      uint2 eA = tile_at(0), eB = tile_at(4);
+      uint2 eA2 = tile_at(8), eB2 = tile_at(12);
+      int fA = full_at(0), fB = full_at(4);
+      int fA2 = full_at(8), fB2 = full_at(12);
+      unsigned sA = slot_of(eA, 0), sB = slot_of(eB, 4);
+      float4 pA = pos_at(sA), pB = pos_at(sB);
+      int tA = type_at(sA), tB = type_at(sB);
+      for (int g = 0; g < cnt; g += 8) {
+        group(emit_c, eA, sA, pA, tA, fA);
+        eA = eA2;
+        fA = fA2;
+        eA2 = tile_at(g + 16);
+        fA2 = full_at(g + 16);
+        sA = slot_of(eA, g + 8);
+        pA = pos_at(sA);
+        tA = type_at(sA);
+        if (g + 4 < cnt) group(emit_c, eB, sB, pB, tB, fB);
+        eB = eB2;
+        fB = fB2;
+        eB2 = tile_at(g + 20);
+        fB2 = full_at(g + 20);
+        sB = slot_of(eB, g + 12);
+        pB = pos_at(sB);
+        tB = type_at(sB);
+      }
+    };
+    if (emit) walk(std::true_type{});
+    else walk(std::false_type{});
     if (emit) {
       // pad the pruned list to a whole group; record the prune positions
       const int padded = (pn + 3) & ~3;
@@ -490,6 +522,7 @@ hipError_t launch_nonbonded(Ctx& c, bool energy, const int* gate_now, const int*
   }
   pp.rc2 = c.cg.rc2;
   pp.alpha = (float)c.alpha;
+  pp.alpha_t = (float)(0.42 * c.alpha);
   pp.exp_c = (float)(-c.alpha * c.alpha / M_LN2);
   pp.alpha_d = c.alpha;
   pp.coulomb_kd = c.coulomb_k;
