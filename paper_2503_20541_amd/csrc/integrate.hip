@@ -202,11 +202,14 @@ __global__ void __launch_bounds__(256) k_finish_step(
     double inv_2acc, double* __restrict__ partials, int pstride, float* __restrict__ vc,
     OpenStep o, int open, JParts jp) {
   __shared__ double red[16];
-  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
-  if (open && gt == 0) open_step_flags(o);
+  if (open && blockIdx.x == 0 && threadIdx.x == 0) open_step_flags(o);
+  // neighbouring slots on one XCD: the PME potential they gather comes from
+  // one part of the grid
+  const int lb = xcd_block((meta[0] * kFinishLanes + 255) / 256);
+  const int gt = lb * blockDim.x + threadIdx.x;
   const int s = gt / kFinishLanes, q = gt & (kFinishLanes - 1);
   double e_ex = 0.0, e_b = 0.0, e_a = 0.0, ke = 0.0;
-  const int a = s < meta[0] ? perm[s] : -1;
+  const int a = lb >= 0 && s < meta[0] ? perm[s] : -1;
   float fx = 0.f, fy = 0.f, fz = 0.f;
   if (a >= 0) {
     if (PME) pme_gather_atom(xs[s], phi, pp, fx, fy, fz, q, kFinishLanes);
@@ -616,7 +619,7 @@ hipError_t launch_finish_step(Ctx& c, const float* pos, float* vel, float* force
   const StepGates none{c.gate, c.gate, c.gate, c.gate, false, 0};   // not used when !next
   const OpenStep o = make_open(c, pos, pos_next, dt, next ? *next : none);
   const int open = next ? 1 : 0;
-  const int nb = (c.max_slots * kFinishLanes + 255) / 256;
+  const int nb = xcd_grid((c.max_slots * kFinishLanes + 255) / 256);
   const PmeParams pp = c.has_pme ? make_pme_params(c) : PmeParams{};
   const BondedParams bp = make_bonded_params(c);
   const Topology tp = make_topology(c);

@@ -12,6 +12,23 @@ namespace mdx {
 
 constexpr int kWave = 64;
 constexpr int kClusterSize = 4;   // atoms per cluster (slots per tile side)
+
+// Workgroups go to the chip's eight XCDs in turn (block b to XCD b mod 8),
+// and each XCD has its own L2. A kernel whose consecutive blocks work on
+// neighbouring atoms numbers its blocks with xcd_block(nwork), nwork being
+// the blocks that hold work at this launch (the grid is sized for the
+// largest count): XCD x takes the contiguous logical blocks
+// [x p, (x+1) p), p = ceil(nwork / 8), so its L2 holds the data of one region
+// of the box instead of the whole box, and the work stays even over the
+// XCDs. Blocks left over return -1 (no work). The grid is a multiple of
+// eight blocks (xcd_grid) and at least nwork.
+constexpr int kXcds = 8;
+inline int xcd_grid(int nb) { return (nb + kXcds - 1) / kXcds * kXcds; }
+__device__ __forceinline__ int xcd_block(int nwork) {
+  const int per = (nwork + kXcds - 1) / kXcds;
+  const int i = (int)(blockIdx.x / kXcds);
+  return i < per ? (int)(blockIdx.x % kXcds) * per + i : -1;
+}
 constexpr int kMaxLjTypes = 32;   // LJ atom types (the pair kernel keeps the type-pair table in LDS)
 // PME spreading bricks: kBrickXY x kBrickXY x kBrickZ grid points (smaller
 // along a dimension with fewer grid points)

@@ -166,8 +166,10 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
   // cluster and its list rows are addressed from scalar registers
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int lane = threadIdx.x & (kWave - 1);
-  const int ic = blockIdx.x * 4 + w;
-  const bool active = ic < meta[1];
+  // neighbouring clusters on one XCD: their j clusters come from one region
+  const int lb = xcd_block((meta[1] + 3) / 4);
+  const int ic = lb * 4 + w;
+  const bool active = lb >= 0 && ic < meta[1];
   if (HALF && pr.invalidate && blockIdx.x == 0 && threadIdx.x < 2) pr.invalidate[threadIdx.x] = 1;
   const int ia = lane >> 4, tt = (lane >> 2) & 3, jb = lane & 3;
   const int si = ic * kClusterSize + ia;
@@ -536,7 +538,7 @@ hipError_t launch_nonbonded(Ctx& c, bool energy, const int* gate_now, const int*
   pp.two_k_rf = (float)(2.0 * c.k_rf);
   pp.k_rf_d = c.k_rf;
   pp.c_rf_d = c.c_rf;
-  const int nb = (c.max_clusters + 3) / 4;
+  const int nb = xcd_grid((c.max_clusters + 3) / 4);
   c.nb_blocks = nb;
   const size_t lds = sizeof(float4) * (size_t)c.n_types * c.n_types;
   const PruneArgs pr{gate_now, pgate_now, c.ptiles, c.pcount, c.xp, c.prune_r2,

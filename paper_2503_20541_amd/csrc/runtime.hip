@@ -553,7 +553,8 @@ int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
   }
   // ---- reductions ----
   // partial rows hold one entry per block of the widest energy kernel
-  int mb = std::max({(n + 255) / 256, (c.max_clusters + 3) / 4, (c.max_slots * 4 + 255) / 256});
+  int mb = std::max({(n + 255) / 256, mdx::xcd_grid((c.max_clusters + 3) / 4),
+                     mdx::xcd_grid((c.max_slots * 4 + 255) / 256)});
   if (c.has_pme) {
     int ntile = (c.pg.Kxh + 15) / 16;
     mb = std::max(mb, c.pg.K[1] * ntile);
