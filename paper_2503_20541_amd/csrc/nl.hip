@@ -792,7 +792,10 @@ __global__ void __launch_bounds__(256) k_tile_search(BuildArgs a) {
   fill_image_tables(img_am, img_cp, a.cg);
   __syncthreads();
   const int w = threadIdx.x / kWave;
-  search_cluster(a, blockIdx.x * 4 + w, sl[w], img_am, img_cp);
+  // neighbouring i-clusters on one XCD: their candidates come from one region
+  const int lb = xcd_block((a.meta[1] + 3) / 4);
+  if (lb < 0) return;
+  search_cluster(a, lb * 4 + w, sl[w], img_am, img_cp);
 }
 
 // ---- all phases in one cooperative launch ------------------------------------
@@ -892,7 +895,7 @@ hipError_t launch_build_list(Ctx& c, const float* pos, const int* gate, hipEvent
   // `done` is recorded by the tile search's own dispatch (the slot positions
   // and the PME brick ranges were complete after the column sort; work
   // forked from here starts together with the force kernel)
-  const int sb = (c.max_clusters + 3) / 4;
+  const int sb = xcd_grid((c.max_clusters + 3) / 4);
   if (done && !c.capturing) {
     void* args[] = {&a};
     return hipExtLaunchKernel(reinterpret_cast<const void*>(k_tile_search), dim3(sb), dim3(256),
