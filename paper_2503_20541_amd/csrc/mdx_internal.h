@@ -203,8 +203,10 @@ struct Ctx {
   int* cell_count = nullptr;   // [ncol] atoms per column
   int* cell_start = nullptr;   // [ncol + 1] first atom (unpadded) of each column
   int* slot_start = nullptr;   // [ncol + 1] first slot of each column (padded to clusters)
-  int* meta = nullptr;         // [4] slots, clusters of the last build; builds so far;
-                               // blocks done binning (the last one scans, then clears it)
+  int* meta = nullptr;         // [8] slots, clusters of the last build; builds so far;
+                               // blocks done binning (the last one scans, then clears it);
+                               // 1 if the last build placed every atom (the next one
+                               // may bin in its slot order)
   int* col_atoms = nullptr;    // [ncol][col_cap] atoms binned into each column (unordered)
   int col_cap = 0;
   int* perm = nullptr;         // [max_slots] slot -> caller atom, -1 for padding

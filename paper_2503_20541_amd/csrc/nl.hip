@@ -129,15 +129,30 @@ struct BuildArgs {
   int* in_fill;    // [max_clusters][cap]: i-cluster * cap + full-list position
 };
 
-// Column of caller atom i, atoms per column (the atom goes to the next free
-// place of its column's fixed-capacity list), build-position snapshot. One
-// returning atomic per atom: the lanes of a wave hit many columns once the
-// atoms have mixed, and one instruction keeps all of them in flight (a
-// wave-aggregated increment would wait for one round trip per distinct
-// column).
+// Binning order. Every atom is binned once per build, in the slot order of
+// the previous build when that build placed every atom (meta[4], set by the
+// scan: the clamped column counts add up to n), else in atom order. In slot
+// order the lanes of a wave fall into one or two columns, and each run of
+// lanes with the same column takes its places in that column's list with a
+// single atomic; in atom order the runs are short and this is one atomic
+// per atom, as before. Which order was used does not change the list: the
+// column sort ranks each column's atoms by (build z, atom index).
+__device__ __forceinline__ bool bin_by_slot(const BuildArgs& a) { return a.meta[4] != 0; }
+__device__ __forceinline__ int bin_count(const BuildArgs& a, bool by_slot) {
+  return by_slot ? a.meta[0] : a.n;
+}
+__device__ __forceinline__ int bin_atom_at(const BuildArgs& a, bool by_slot, int j) {
+  if (j >= bin_count(a, by_slot)) return -1;
+  return by_slot ? a.perm[j] : j;
+}
+
+// Column of atom i (-1: none for this lane), atoms per column (the atom goes
+// to the next free place of its column's fixed-capacity list), build-position
+// snapshot. Called by every lane of the wave (the runs are found with
+// cross-lane operations).
 __device__ void bin_atom(const BuildArgs& a, int i) {
-  const bool active = i < a.n;
-  int c = 0;
+  const bool active = i >= 0;
+  int c = -1;
   if (active) {
     const int n = a.n;
     float x = a.pos[i], y = a.pos[n + i], z = a.pos[2 * n + i];
@@ -152,8 +167,24 @@ __device__ void bin_atom(const BuildArgs& a, int i) {
     a.x_build[n + i] = y;
     a.x_build[2 * n + i] = z;
   }
+  // runs of consecutive active lanes with the same column: the first lane of
+  // a run adds the run's length, the others take the following places
+  const int lane = threadIdx.x & (kWave - 1);
+  const int prev = __shfl_up(c, 1, kWave);
+  const bool head = active && (lane == 0 || prev != c);
+  const unsigned long long heads = __ballot(head);
+  const unsigned long long stops = __ballot(head || !active);
+  const unsigned long long below = lane == kWave - 1 ? ~0ull : (2ull << lane) - 1ull;
+  const int leader = active ? kWave - 1 - __clzll(heads & below) : lane;
+  int base = 0;
+  if (head) {
+    const unsigned long long after = lane == kWave - 1 ? 0ull : stops >> (lane + 1);
+    const int len = after ? __ffsll((long long)after) : kWave - lane;
+    base = atomicAdd(&a.col_count[c], len);
+  }
+  base = __shfl(base, leader, kWave);
   if (active) {
-    const int k = atomicAdd(&a.col_count[c], 1);
+    const int k = base + (lane - leader);
     if (k < a.col_cap) {
       a.col_atoms[(size_t)c * a.col_cap + k] = i;
     } else {
@@ -214,6 +245,8 @@ __device__ void scan_columns(const BuildArgs& a) {
     a.meta[0] = accp;
     a.meta[1] = accp / kClusterSize;
     a.meta[2] += 1;
+    // every atom placed: the next build may bin in this build's slot order
+    a.meta[4] = acc == a.n ? 1 : 0;
     *a.nl_needed = 0;
   }
   __syncthreads();
@@ -764,7 +797,8 @@ __global__ void __launch_bounds__(256) k_bin_scan(BuildArgs a) {
   if (gated_off(a.gate)) return;
   __shared__ int last;
   clear_in_counts(a, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
-  bin_atom(a, blockIdx.x * blockDim.x + threadIdx.x);
+  const bool by_slot = bin_by_slot(a);
+  bin_atom(a, bin_atom_at(a, by_slot, blockIdx.x * blockDim.x + threadIdx.x));
   // The counts are atomics whose results every lane has received before the
   // barrier; one device-scope release per block (not a cache write-back per
   // wave) orders them before the block is counted, and the last block's
@@ -815,9 +849,12 @@ __global__ void __launch_bounds__(kBuildThreads) k_build_all(BuildArgs a) {
   const int nthreads = gridDim.x * blockDim.x;
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   // bounds rounded to whole blocks: the atom loops stay uniform per wave
-  const int nround = (a.n + blockDim.x - 1) / blockDim.x * blockDim.x;
+  const bool by_slot = bin_by_slot(a);
+  const int nround = (bin_count(a, by_slot) + blockDim.x - 1) / blockDim.x * blockDim.x;
   clear_in_counts(a, tid, nthreads);
-  for (int i = tid; i < nround; i += nthreads) bin_atom(a, i);
+  // every block has read meta before the barrier after the binning, and the
+  // scan (block 0) writes it after that barrier
+  for (int j = tid; j < nround; j += nthreads) bin_atom(a, bin_atom_at(a, by_slot, j));
   grid.sync();
   if (blockIdx.x == 0) scan_columns(a);
   grid.sync();
@@ -889,7 +926,8 @@ hipError_t launch_build_list(Ctx& c, const float* pos, const int* gate, hipEvent
     if (e == hipSuccess && done) e = hipEventRecord(done, s);
     return e;
   }
-  const int nb = (n + 255) / 256;
+  // binning in slot order visits up to max_slots entries
+  const int nb = (std::max(n, c.max_slots) + 255) / 256;
   k_bin_scan<<<nb, 256, 0, s>>>(a);
   k_col_sort<<<ncol, kColThreads, 0, s>>>(a);
   // `done` is recorded by the tile search's own dispatch (the slot positions

@@ -493,8 +493,10 @@ int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
   MDX_TRY(hipMemset(c.cell_count, 0, sizeof(int) * ncol));
   if ((rc = dev_alloc(x, &c.cell_start, ncol + 1)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.slot_start, ncol + 1)) != MDX_OK) return rc;
-  if ((rc = dev_alloc(x, &c.meta, 4)) != MDX_OK) return rc;
-  MDX_TRY(hipMemset(c.meta, 0, 4 * sizeof(int)));
+  // meta: slots, clusters, builds, binning blocks done, slot-order binning
+  // allowed (meta[4]); padded to 8
+  if ((rc = dev_alloc(x, &c.meta, 8)) != MDX_OK) return rc;
+  MDX_TRY(hipMemset(c.meta, 0, 8 * sizeof(int)));
   // atoms binned per column: twice the mean with headroom (a column that
   // overflows latches MDX_FLAG_COLUMN_OVERFLOW; mdx_build_neighbors grows it)
   c.col_cap = std::min(n, std::max(64, 2 * ((n + ncol - 1) / ncol) + 32));
@@ -1509,6 +1511,9 @@ int mdx_load_state(mdx_ctx* x, const void* state, int64_t size) {
     MDX_TRY(hipMemcpyAsync(sg.p, src + off, sg.bytes, hipMemcpyDeviceToDevice, c.stream));
     off += align256(sg.bytes);
   }
+  // the next build bins in atom order (the slot-order hint, meta[4], is not
+  // part of the state; the list does not depend on the binning order)
+  MDX_TRY(mdx::launch_fill_i32(c.meta + 4, 0, 1, c.stream));
   MDX_TRY(hipStreamSynchronize(c.stream));
   c.steps_since_build = (int)h.steps_since_build;
   c.steps_taken = h.steps_taken;

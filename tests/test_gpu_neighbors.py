@@ -97,6 +97,32 @@ def test_list_crowded_column_grows_column_capacity():
     assert np.array_equal(got, _oracle_pairs(s))
 
 
+def test_list_rebuilds_in_slot_order_stay_exact():
+    # Later builds bin the atoms in the slot order of the build before, when
+    # that build placed every atom, and in atom order otherwise (after a
+    # column overflow). The list must be the exact one either way: a normal
+    # build, a moved configuration (slot order), a crowded column (slot order,
+    # overflow, regrown and rebuilt in atom order), and a normal one again.
+    s = synth.random_box(2000, [20.0, 20.0, 20.0], 2.0, 0.5, 33, n_excl_per_atom=1)
+    rng = np.random.default_rng(9)
+    moved = s.copy()
+    moved.pos = np.mod(s.pos + rng.uniform(-1.5, 1.5, s.pos.shape), 20.0).astype(np.float32)
+    moved.pos[moved.pos >= 20.0] = 0.0   # float32 rounding onto the box edge
+    crowded = s.copy()
+    crowded.pos = s.pos.copy()
+    crowded.pos[0, :600] = rng.uniform(0.0, 1.0, 600).astype(np.float32)
+    crowded.pos[1, :600] = rng.uniform(0.0, 1.0, 600).astype(np.float32)
+    import torch
+    announce("list rebuilt in slot order (moved, crowded, normal)")
+    with gpu_context(s) as (mdx, ctx, t):
+        for k, cfg in enumerate([s, moved, crowded, s]):
+            p = torch.from_numpy(np.ascontiguousarray(cfg.pos)).to(t["pos"].device)
+            mdx.build_neighbors(ctx, p)
+            got = mdx.get_neighbor_pairs(ctx)
+            assert mdx.get_status(ctx) == 0, k
+            assert np.array_equal(got, _oracle_pairs(cfg)), k
+
+
 def test_list_water96k_whole_list_and_sampled_rows():
     # the whole sorted pair list against the oracle's (its count and sha256,
     # written by tests/golden/make_counts.py from the oracle), then 300 rows
