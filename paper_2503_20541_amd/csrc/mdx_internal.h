@@ -439,6 +439,10 @@ __device__ __forceinline__ float image_diff(float xi, float xj, float am, float 
   return (xj + am) + (cp - xi);
 }
 
+// image_diff at image 0 (am = cp = 0): (x_j + 0) + (0 - x_i) is x_j - x_i
+// rounded once, the same value in one operation.
+__device__ __forceinline__ float plain_diff(float xi, float xj) { return xj - xi; }
+
 // Kahan-compensated s + y: c carries the rounding error of the previous sum
 // into this one and receives this one's.
 __device__ __forceinline__ float kahan_add(float s, float y, float& c) {

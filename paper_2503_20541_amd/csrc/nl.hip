@@ -705,10 +705,17 @@ __device__ void search_cluster(const BuildArgs& a, int ic, SearchLds& sl, const 
       // Without branches: every lane forms its pair's difference and the
       // predicate (candidate, within r_nl, not excluded) decides its bit;
       // only atoms with more than four exclusions walk their list.
-      const float4 am = img_am[cimg], cp = img_cp[cimg];
-      const float dx = image_diff(pi.x, pj.x, am.x, cp.x);
-      const float dy = image_diff(pi.y, pj.y, am.y, cp.y);
-      const float dz = image_diff(pi.z, pj.z, am.z, cp.z);
+      float dx, dy, dz;
+      if (__ballot(cimg != 0u) == 0ull) {   // no candidate of the group wraps
+        dx = plain_diff(pi.x, pj.x);
+        dy = plain_diff(pi.y, pj.y);
+        dz = plain_diff(pi.z, pj.z);
+      } else {
+        const float4 am = img_am[cimg], cp = img_cp[cimg];
+        dx = image_diff(pi.x, pj.x, am.x, cp.x);
+        dy = image_diff(pi.y, pj.y, am.y, cp.y);
+        dz = image_diff(pi.z, pj.z, am.z, cp.z);
+      }
       const bool within = cand & (dist2(dx, dy, dz) < a.cg.rnl2);
       bool excluded = (sj == ex0) | (sj == ex1) | (sj == ex2) | (sj == ex3);
       const bool walk = within & ex_more & !excluded;

@@ -207,11 +207,21 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
       constexpr bool EMIT = decltype(emit_c)::value;
       const bool on = (e.y >> bitpos) & 1u;
       // the tile's image: the same differences as the minimum-image rule
-      // gives for its listed pairs, without the per-pair selects
-      const float4 am = img_am[e.y >> 16], cp = img_cp[e.y >> 16];
-      float dx = image_diff(pi.x, pj.x, am.x, cp.x);
-      float dy = image_diff(pi.y, pj.y, am.y, cp.y);
-      float dz = image_diff(pi.z, pj.z, am.z, cp.z);
+      // gives for its listed pairs, without the per-pair selects; when no
+      // tile of the group wraps (the common case; the test is the same for
+      // the whole wave) that is the plain difference
+      const unsigned code = e.y >> 16;
+      float dx, dy, dz;
+      if (__builtin_amdgcn_ballot_w64(code != 0u) == 0ull) {
+        dx = plain_diff(pi.x, pj.x);
+        dy = plain_diff(pi.y, pj.y);
+        dz = plain_diff(pi.z, pj.z);
+      } else {
+        const float4 am = img_am[code], cp = img_cp[code];
+        dx = image_diff(pi.x, pj.x, am.x, cp.x);
+        dy = image_diff(pi.y, pj.y, am.y, cp.y);
+        dz = image_diff(pi.z, pj.z, am.z, cp.z);
+      }
       float r2 = dist2(dx, dy, dz);
       const bool in = on && r2 < pp.rc2;
       if (EMIT) {
