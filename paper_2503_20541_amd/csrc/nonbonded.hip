@@ -127,6 +127,9 @@ struct HalfArgs {
   int* in_sorted;        // [max_clusters][cap]
 };
 
+// tiles whose keep flags a wave holds before writing them out (a power of two)
+constexpr int kKeepTiles = 2048;
+
 template <bool ENERGY, int COUL, bool SWITCH, bool HALF, bool VIR = false>
 __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
                                               const int* __restrict__ ts,
@@ -151,6 +154,9 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
   // periodic image shifts by tile image code (2 bits per axis): x_j offset
   // am (-L for image 1) and cp (L for image 2), see image_diff
   __shared__ float4 img_am[64], img_cp[64];
+  // per wave, on a walk that writes the pruned list: the keep flags of the
+  // last kKeepTiles tiles, one byte per group of four
+  __shared__ unsigned char keep_s[4][kKeepTiles / 4];
   if (threadIdx.x < 64) {
     float am[3], cp[3];
     for (int d = 0; d < 3; ++d) {
@@ -203,7 +209,7 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
     // position and type; f: the tile's full-list position). EMIT (whether
     // this walk writes the pruned list) is a compile-time constant of each
     // of the two loops below.
-    auto group = [&](auto emit_c, uint2 e, unsigned sj, float4 pj, int tj, int f) {
+    auto group = [&](auto emit_c, int g0, uint2 e, unsigned sj, float4 pj, int tj, int f) {
       constexpr bool EMIT = decltype(emit_c)::value;
       const bool on = (e.y >> bitpos) & 1u;
       // the tile's image: the same differences as the minimum-image rule
@@ -225,18 +231,21 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
       float r2 = dist2(dx, dy, dz);
       const bool in = on && r2 < pp.rc2;
       if (EMIT) {
-        // keep tile tt if any of its pairs is within r_p; lane (row 0, tile
-        // tt, slot 0) writes it, in list order
-        const unsigned long long nearm = __builtin_amdgcn_ballot_w64(on && r2 < pr.rp2);
-        const bool keep = ((nearm >> (4 * tt)) & 0x000f000f000f000full) != 0ull;
-        const bool leader = ia == 0 && jb == 0;
-        const unsigned long long km = __builtin_amdgcn_ballot_w64(leader && keep);
-        if (leader && keep) {
-          const int k = pn + __popcll(km & ((1ull << lane) - 1ull));
-          pl[k] = e;
-          if (HALF) ppl[k] = f;
-        }
-        pn += __popcll(km);
+        // tile t of the group is kept if any of its pairs (lanes 16 a + 4 t
+        // + b) is within r_p: four flags from one ballot (scalar work),
+        // stored as the group's byte; the kept tiles are written out in list
+        // order by compact()
+        // (ballots of single compares, combined as masks; the folding is
+        // integer work on the wave-uniform mask)
+        unsigned long long m =
+            __builtin_amdgcn_ballot_w64(on) & __builtin_amdgcn_ballot_w64(r2 < pr.rp2);
+        m |= m >> 32;
+        m |= m >> 16;                          // bit 4 t + b: any row
+        unsigned x = (unsigned)m & 0xffffu;
+        x |= x >> 2;
+        x |= x >> 1;                           // bit 4 t: any pair of tile t
+        const unsigned nib = (x & 1u) | ((x >> 3) & 2u) | ((x >> 6) & 4u) | ((x >> 9) & 8u);
+        if (lane == 0) keep_s[w][(g0 >> 2) & (kKeepTiles / 4 - 1)] = (unsigned char)nib;
       }
       const unsigned long long hit = __builtin_amdgcn_ballot_w64(in);
       // half list: every real tile (mask != 0) writes its j partials
@@ -340,9 +349,6 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
       return *reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(tl) +
                                              ((unsigned)min(g + tt, cap - 1) << 3));
     };
-    auto slot_of = [&](uint2 e, int g) {
-      return (g < cnt ? e.x : 0u) * kClusterSize + (unsigned)jb;
-    };
     // 32-bit byte offsets from the arrays' bases (the slot arrays are far
     // below 4 GB)
     auto pos_at = [&](unsigned s) {
@@ -357,31 +363,68 @@ __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,
       const int k = min(g + tt, cap - 1);
       return pruned ? ppl[k] : k;
     };
+    // Writing the pruned list: the tiles [c0, c1) of the full list (c0 a
+    // multiple of kKeepTiles) whose flags the walk has stored, appended in
+    // list order, one wave instruction per 64 tiles.
+    auto compact = [&](int c0, int c1) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int t0 = c0; t0 < c1; t0 += kWave) {
+        const int t = t0 + lane;
+        const bool k =
+            t < c1 && ((keep_s[w][(t >> 2) & (kKeepTiles / 4 - 1)] >> (t & 3)) & 1u) != 0u;
+        const unsigned long long km = __builtin_amdgcn_ballot_w64(k);
+        if (k) {
+          const int pos = pn + __popcll(km & ((1ull << lane) - 1ull));
+          pl[pos] = tl[t];
+          if (HALF) ppl[pos] = t;
+        }
+        pn += __popcll(km);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
     auto walk = [&](auto emit_c) {
-      uint2 eA = tile_at(0), eB = tile_at(4);
-      uint2 eA2 = tile_at(8), eB2 = tile_at(12);
-      int fA = full_at(0), fB = full_at(4);
-      int fA2 = full_at(8), fB2 = full_at(12);
-      unsigned sA = slot_of(eA, 0), sB = slot_of(eB, 4);
-      float4 pA = pos_at(sA), pB = pos_at(sB);
-      int tA = type_at(sA), tB = type_at(sB);
-      for (int g = 0; g < cnt; g += 8) {
-        group(emit_c, eA, sA, pA, tA, fA);
-        eA = eA2;
-        fA = fA2;
-        eA2 = tile_at(g + 16);
-        fA2 = full_at(g + 16);
-        sA = slot_of(eA, g + 8);
-        pA = pos_at(sA);
-        tA = type_at(sA);
-        if (g + 4 < cnt) group(emit_c, eB, sB, pB, tB, fB);
-        eB = eB2;
-        fB = fB2;
-        eB2 = tile_at(g + 20);
-        fB2 = full_at(g + 20);
-        sB = slot_of(eB, g + 12);
-        pB = pos_at(sB);
-        tB = type_at(sB);
+      constexpr bool EMIT = decltype(emit_c)::value;
+      // A walk that writes the pruned list takes the list in chunks of
+      // kKeepTiles tiles and writes out each chunk's kept tiles after it:
+      // the group loop itself then holds no other memory operations, and its
+      // loads stay in flight across groups (with the writes inside the loop
+      // every group waited for all of them).
+      const int chunk = EMIT ? kKeepTiles : (cnt > 0 ? cnt : 1);
+      for (int c0 = 0; c0 < cnt; c0 += chunk) {
+        const int c1 = min(c0 + chunk, cnt);
+        auto slot = [&](uint2 e, int g) {
+          return (g < c1 ? e.x : 0u) * kClusterSize + (unsigned)jb;
+        };
+        uint2 eA = tile_at(c0), eB = tile_at(c0 + 4);
+        uint2 eA2 = tile_at(c0 + 8), eB2 = tile_at(c0 + 12);
+        int fA = full_at(c0), fB = full_at(c0 + 4);
+        int fA2 = full_at(c0 + 8), fB2 = full_at(c0 + 12);
+        unsigned sA = slot(eA, c0), sB = slot(eB, c0 + 4);
+        float4 pA = pos_at(sA), pB = pos_at(sB);
+        int tA = type_at(sA), tB = type_at(sB);
+        for (int g = c0; g < c1; g += 8) {
+          group(emit_c, g, eA, sA, pA, tA, fA);
+          eA = eA2;
+          fA = fA2;
+          eA2 = tile_at(g + 16);
+          fA2 = full_at(g + 16);
+          sA = slot(eA, g + 8);
+          pA = pos_at(sA);
+          tA = type_at(sA);
+          if (g + 4 < c1) group(emit_c, g + 4, eB, sB, pB, tB, fB);
+          eB = eB2;
+          fB = fB2;
+          eB2 = tile_at(g + 20);
+          fB2 = full_at(g + 20);
+          sB = slot(eB, g + 12);
+          pB = pos_at(sB);
+          tB = type_at(sB);
+        }
+        if (EMIT) compact(c0, c1);
       }
     };
     if (emit) walk(std::true_type{});
