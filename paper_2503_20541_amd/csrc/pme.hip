@@ -409,6 +409,7 @@ struct Radices {
 __host__ __device__ constexpr Radices factor_radices(int N) {
   Radices f{};
   int m = N;
+  while (m % 10 == 0 && f.n < 16) { f.r[f.n++] = 10; m /= 10; }
   while (m % 4 == 0 && f.n < 16) { f.r[f.n++] = 4; m /= 4; }
   while (m % 2 == 0 && f.n < 16) { f.r[f.n++] = 2; m /= 2; }
   while (m % 3 == 0 && f.n < 16) { f.r[f.n++] = 3; m /= 3; }
@@ -480,6 +481,23 @@ __device__ __forceinline__ void dft_fixed(float2* v, const float2* tw, int N) {
     v[4] = make_float2(a1.x - b1.x, a1.y - b1.y);
     v[2] = make_float2(a2.x + b2.x, a2.y + b2.y);
     v[3] = make_float2(a2.x - b2.x, a2.y - b2.y);
+  } else if constexpr (R == 10) {
+    // prime-factor (Good-Thomas) split 10 = 2 x 5, no twiddles: with input
+    // x[(5 a + 2 b) mod 10] and output X[(5 c + 6 d) mod 10], X is the
+    // 2-point DFT over a of the 5-point DFTs over b
+    float2 e[5], o[5];
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+      e[b] = v[(2 * b) % 10];
+      o[b] = v[(5 + 2 * b) % 10];
+    }
+    dft_fixed<5, SIGN>(e, tw, N);
+    dft_fixed<5, SIGN>(o, tw, N);
+#pragma unroll
+    for (int d = 0; d < 5; ++d) {
+      v[(6 * d) % 10] = make_float2(e[d].x + o[d].x, e[d].y + o[d].y);
+      v[(5 + 6 * d) % 10] = make_float2(e[d].x - o[d].x, e[d].y - o[d].y);
+    }
   } else {
     float2 in[R];
     for (int r = 0; r < R; ++r) in[r] = v[r];
@@ -545,6 +563,7 @@ __device__ float2* fft_rt(float2* a, float2* b, int SP, int P, const FftPlan& pl
       case 2: fft_stage<2, SIGN>(a, b, pl.N, SP, NS, P, tw); break;
       case 3: fft_stage<3, SIGN>(a, b, pl.N, SP, NS, P, tw); break;
       case 5: fft_stage<5, SIGN>(a, b, pl.N, SP, NS, P, tw); break;
+      case 10: fft_stage<10, SIGN>(a, b, pl.N, SP, NS, P, tw); break;
       default: fft_stage<7, SIGN>(a, b, pl.N, SP, NS, P, tw); break;
     }
     float2* t = a;
