@@ -352,6 +352,9 @@ hipError_t launch_rigid_velocities(Ctx& c, const float* pos, float* vel, bool en
 // Spread + FFT passes only (the potential grid), for the fused closing kernel.
 // `done` (may be null) is recorded by the last kernel's own dispatch.
 hipError_t launch_pme_spread(Ctx& c, hipStream_t s, hipEvent_t done);
+// Pencils per block of the FFT column passes for a half spectrum of kxh
+// columns (the z pass writes one energy partial per block).
+int pme_col_pencils(int kxh);
 // The tangent of the charge grid along per-slot displacements us[slot].xyz
 // (sum of q u . grad theta) into grid_q, on the context's stream.
 hipError_t launch_pme_spread_dipole(Ctx& c, const float4* us);

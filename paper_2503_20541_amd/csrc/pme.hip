@@ -682,10 +682,19 @@ __global__ void __launch_bounds__(256) k_fft_cols(float2* __restrict__ grid, Pme
     base = (size_t)outer * pp.K[1] * Kxh;
     stride = Kxh;
   }
-  for (int idx = threadIdx.x; idx < P * L; idx += blockDim.x) {
-    int i = idx / P, p = idx - i * P;
-    int kx = kx0 + p;
-    a[p * SP + i] = kx < Kxh ? grid[base + i * stride + kx] : make_float2(0.f, 0.f);
+  // element i P + p of the tile (i along the pencil, p the pencil): each
+  // thread steps (i, p) by the block size, without a division per element
+  const int di = (int)blockDim.x / P, dp = (int)blockDim.x - di * P;
+  const int i0 = (int)threadIdx.x / P, p0 = (int)threadIdx.x - i0 * P;
+  for (int i = i0, p = p0; i < L;) {
+    const int kx = kx0 + p;
+    a[p * SP + i] = kx < Kxh ? grid[base + (size_t)i * stride + kx] : make_float2(0.f, 0.f);
+    i += di;
+    p += dp;
+    if (p >= P) {
+      p -= P;
+      ++i;
+    }
   }
   __syncthreads();
   float2* res;
@@ -742,10 +751,15 @@ __global__ void __launch_bounds__(256) k_fft_cols(float2* __restrict__ grid, Pme
     float2* other = (res == a) ? b : a;
     res = fft_any<N, +1>(res, other, SP, P, pl, tw);
   }
-  for (int idx = threadIdx.x; idx < P * L; idx += blockDim.x) {
-    int i = idx / P, p = idx - i * P;
-    int kx = kx0 + p;
-    if (kx < Kxh) grid[base + i * stride + kx] = res[p * SP + i];
+  for (int i = i0, p = p0; i < L;) {
+    const int kx = kx0 + p;
+    if (kx < Kxh) grid[base + (size_t)i * stride + kx] = res[p * SP + i];
+    i += di;
+    p += dp;
+    if (p >= P) {
+      p -= P;
+      ++i;
+    }
   }
 }
 
@@ -777,6 +791,21 @@ static FftPlan make_plan(int N) {
 }
 
 bool pme_size_supported(int K) { return K >= 4 && K <= 1024 && make_plan(K).nst > 0; }
+
+// Pencils (consecutive kx) per block of the column passes: the count in
+// [12, 24] that leaves the fewest padding columns in the last tile of the
+// Kxh columns (17 for Kxh = 51: three full tiles), the larger on a tie.
+int pme_col_pencils(int kxh) {
+  int best = 16, waste = 1 << 30;
+  for (int pc = 12; pc <= 24; ++pc) {
+    const int w = (kxh + pc - 1) / pc * pc - kxh;
+    if (w <= waste) {
+      best = pc;
+      waste = w;
+    }
+  }
+  return best;
+}
 
 static int pencils_for(int N) {
   int P = 2048 / N;
@@ -916,7 +945,7 @@ hipError_t launch_pme_fft(Ctx& c, hipStream_t s, hipEvent_t done, bool virial) {
   const size_t sh = (size_t)(g.K[0] + 2 * P * g.K[0]) * sizeof(float2);
   const int rblocks = (rows + P - 1) / P;
   rows_r2c(g.K[0], rblocks, sh, s, c.grid_q, c.grid_c, rows, P, g.Kxh, px, c.tw[0]);
-  const int Pc = 16;
+  const int Pc = pme_col_pencils(g.Kxh);
   const int ntile = (g.Kxh + Pc - 1) / Pc;
   const size_t shy = (size_t)(g.K[1] + 2 * Pc * (g.K[1] + 1)) * sizeof(float2);
   const size_t shz = (size_t)(g.K[2] + 2 * Pc * (g.K[2] + 1)) * sizeof(float2);

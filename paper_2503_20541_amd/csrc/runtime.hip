@@ -558,7 +558,8 @@ int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
   int mb = std::max({(n + 255) / 256, mdx::xcd_grid((c.max_clusters + 3) / 4),
                      mdx::xcd_grid((c.max_slots * 4 + 255) / 256)});
   if (c.has_pme) {
-    int ntile = (c.pg.Kxh + 15) / 16;
+    const int pc = mdx::pme_col_pencils(c.pg.Kxh);
+    int ntile = (c.pg.Kxh + pc - 1) / pc;
     mb = std::max(mb, c.pg.K[1] * ntile);
   }
   c.max_blocks = mb;
