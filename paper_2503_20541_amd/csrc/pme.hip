@@ -585,6 +585,10 @@ __device__ __forceinline__ float2* fft_any(float2* a, float2* b, int SP, int P, 
 }
 
 // x-direction forward: real rows [Kz*Ky][Kx] -> half spectrum [Kz*Ky][Kxh].
+// Two real rows per complex transform: pencil q holds rows a = r0 + 2q (real
+// part) and b = a + 1 (imaginary part) of the block's 2P rows; with Z the
+// transform, X_a(k) = (Z(k) + conj Z(L-k)) / 2 and X_b(k) = (Z(k) -
+// conj Z(L-k)) / (2i).
 template <int N>
 __global__ void __launch_bounds__(256) k_fft_rows_r2c(const float* __restrict__ in,
                                                       float2* __restrict__ out, int nrows,
@@ -597,21 +601,31 @@ __global__ void __launch_bounds__(256) k_fft_rows_r2c(const float* __restrict__ 
   float2* a = sm + L;
   float2* b = a + P * L;
   for (int t = threadIdx.x; t < L; t += blockDim.x) tw[t] = twg[t];
-  const int r0 = blockIdx.x * P;
+  const int r0 = blockIdx.x * 2 * P;
   for (int idx = threadIdx.x; idx < P * L; idx += blockDim.x) {
-    int p = idx / L, x = idx - p * L;
-    a[idx] = (r0 + p < nrows) ? make_float2(in[(size_t)(r0 + p) * L + x], 0.f)
-                              : make_float2(0.f, 0.f);
+    const int q = idx / L, x = idx - q * L;
+    const int ra = r0 + 2 * q, rb = ra + 1;
+    a[idx] = make_float2(ra < nrows ? in[(size_t)ra * L + x] : 0.f,
+                         rb < nrows ? in[(size_t)rb * L + x] : 0.f);
   }
   __syncthreads();
   float2* res = fft_any<N, -1>(a, b, L, P, pl, tw);
   for (int idx = threadIdx.x; idx < P * Kxh; idx += blockDim.x) {
-    int p = idx / Kxh, k = idx - p * Kxh;
-    if (r0 + p < nrows) out[(size_t)(r0 + p) * Kxh + k] = res[p * L + k];
+    const int q = idx / Kxh, k = idx - q * Kxh;
+    const float2 zk = res[q * L + k], zm = res[q * L + (k == 0 ? 0 : L - k)];
+    const int ra = r0 + 2 * q, rb = ra + 1;
+    if (ra < nrows)
+      out[(size_t)ra * Kxh + k] = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+    if (rb < nrows)
+      out[(size_t)rb * Kxh + k] = make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
   }
 }
 
 // x-direction inverse: half spectrum -> real rows (Hermitian completion).
+// Two rows per complex transform: pencil q holds Z = X_a + i X_b over the
+// full spectrum, each X completed by X(L-k) = conj X(k); the imaginary parts
+// of X(0) and X(L/2), which are zero for a real row, are set to zero, so the
+// real and imaginary parts of the inverse are the two rows.
 template <int N>
 __global__ void __launch_bounds__(256) k_fft_rows_c2r(const float2* __restrict__ in,
                                                       float* __restrict__ out, int nrows,
@@ -624,25 +638,34 @@ __global__ void __launch_bounds__(256) k_fft_rows_c2r(const float2* __restrict__
   float2* a = sm + L;
   float2* b = a + P * L;
   for (int t = threadIdx.x; t < L; t += blockDim.x) tw[t] = twg[t];
-  const int r0 = blockIdx.x * P;
+  const int r0 = blockIdx.x * 2 * P;
   for (int idx = threadIdx.x; idx < P * L; idx += blockDim.x) {
-    int p = idx / L, k = idx - p * L;
-    float2 v = make_float2(0.f, 0.f);
-    if (r0 + p < nrows) {
-      if (k < Kxh) {
-        v = in[(size_t)(r0 + p) * Kxh + k];
-      } else {
-        v = in[(size_t)(r0 + p) * Kxh + (L - k)];
-        v.y = -v.y;
-      }
+    const int q = idx / L, k = idx - q * L;
+    const int ra = r0 + 2 * q, rb = ra + 1;
+    const bool hi = k >= Kxh;
+    const int kk = hi ? L - k : k;
+    const bool self_conj = k == 0 || 2 * k == L;
+    float2 xa = make_float2(0.f, 0.f), xb = make_float2(0.f, 0.f);
+    if (ra < nrows) xa = in[(size_t)ra * Kxh + kk];
+    if (rb < nrows) xb = in[(size_t)rb * Kxh + kk];
+    if (hi) {
+      xa.y = -xa.y;
+      xb.y = -xb.y;
     }
-    a[idx] = v;
+    if (self_conj) {
+      xa.y = 0.f;
+      xb.y = 0.f;
+    }
+    a[idx] = make_float2(xa.x - xb.y, xa.y + xb.x);
   }
   __syncthreads();
   float2* res = fft_any<N, +1>(a, b, L, P, pl, tw);
   for (int idx = threadIdx.x; idx < P * L; idx += blockDim.x) {
-    int p = idx / L, x = idx - p * L;
-    if (r0 + p < nrows) out[(size_t)(r0 + p) * L + x] = res[idx].x;
+    const int q = idx / L, x = idx - q * L;
+    const int ra = r0 + 2 * q, rb = ra + 1;
+    const float2 z = res[idx];
+    if (ra < nrows) out[(size_t)ra * L + x] = z.x;
+    if (rb < nrows) out[(size_t)rb * L + x] = z.y;
   }
 }
 
@@ -941,9 +964,10 @@ hipError_t launch_pme_fft(Ctx& c, hipStream_t s, hipEvent_t done, bool virial) {
   const PmeParams pp = make_pme_params(c);
   FftPlan px = make_plan(g.K[0]), py = make_plan(g.K[1]), pz = make_plan(g.K[2]);
   const int rows = g.K[1] * g.K[2];
-  const int P = pencils_for(g.K[0]);
+  // row passes: P pencils of two rows each per block
+  const int P = std::max(1, pencils_for(g.K[0]) / 2);
   const size_t sh = (size_t)(g.K[0] + 2 * P * g.K[0]) * sizeof(float2);
-  const int rblocks = (rows + P - 1) / P;
+  const int rblocks = (rows + 2 * P - 1) / (2 * P);
   rows_r2c(g.K[0], rblocks, sh, s, c.grid_q, c.grid_c, rows, P, g.Kxh, px, c.tw[0]);
   const int Pc = pme_col_pencils(g.Kxh);
   const int ntile = (g.Kxh + Pc - 1) / Pc;
