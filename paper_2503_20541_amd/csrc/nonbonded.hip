@@ -128,7 +128,7 @@ struct HalfArgs {
 };
 
 // tiles whose keep flags a wave holds before writing them out (a power of two)
-constexpr int kKeepTiles = 2048;
+constexpr int kKeepTiles = 256;
 
 template <bool ENERGY, int COUL, bool SWITCH, bool HALF, bool VIR = false>
 __global__ void __launch_bounds__(256) k_pair(const float4* __restrict__ xs,

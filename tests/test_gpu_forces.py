@@ -215,6 +215,31 @@ def test_water96k_full_size_sampled_forces_and_energies():
     assert rel_rms(F_step, F_fresh) < 1e-6
 
 
+def test_pruned_list_written_in_chunks_keeps_every_pair():
+    # An LJ fluid with a long cutoff: about 450 tiles per cluster, so a walk
+    # that writes the pruned list does so in several chunks of 256 tiles.
+    # After steps that rebuild the list and write the pruned list again, the
+    # force the step leaves equals a fresh full-list evaluation.
+    import torch
+    s = synth.lj_fluid(n_side=20, density=0.8, r_cut=6.0, r_ghost=1.0, temperature=1.0,
+                       dt=0.002)
+    announce(f"pruned list in chunks: LJ N={s.n_atoms} r_c=6")
+    with gpu_context(s) as (mdx, ctx, t):
+        mdx.build_neighbors(ctx, t["pos"])
+        info = mdx.get_info(ctx)
+        assert info.n_list_tiles > 256 * (s.n_atoms // 4)
+        mdx.integrate_step(ctx, t["pos"], t["vel"], t["force"], 25, s.dt)
+        torch.cuda.synchronize()
+        F_step = t["force"].cpu().numpy().astype(np.float64)
+        f2 = torch.zeros_like(t["force"])
+        mdx.compute_nonbonded(ctx, t["pos"], f2)
+        torch.cuda.synchronize()
+        F_fresh = f2.cpu().numpy().astype(np.float64)
+        assert mdx.get_status(ctx) == 0
+        assert mdx.get_info(ctx).n_builds >= 3
+    assert rel_rms(F_step, F_fresh) < 1e-6
+
+
 def _off_equilibrium(s, seed=4):
     # water away from its rigid geometry, so bonds and angles carry force
     s = s.copy()
