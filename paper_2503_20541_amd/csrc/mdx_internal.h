@@ -261,6 +261,8 @@ struct Ctx {
   float2* tw[3] = {nullptr, nullptr, nullptr};  // twiddles exp(-2 pi i k/K_d)
   double* bmod[3] = {nullptr, nullptr, nullptr}; // |b_d(m)|^2
   double* mrec[3] = {nullptr, nullptr, nullptr}; // m'_d / L_d
+  double* pme_g = nullptr;     // [Ky][Kxh][Kz] influence function B(m) exp(-pi^2 m^2 / alpha^2)
+                               // / m^2 (0 at m = 0), without 1/(pi V); box and alpha are fixed
   double pme_energy_scale = 0.0;                 // 1 / (pi V)
   int* brick_cols = nullptr;   // per brick index along x, y: first column, count
   float* brick_z = nullptr;    // per brick index along z: z range [lo, hi) of atoms that reach it

@@ -683,6 +683,7 @@ __global__ void __launch_bounds__(256) k_fft_cols(float2* __restrict__ grid, Pme
                                                   const double* __restrict__ mx,
                                                   const double* __restrict__ my,
                                                   const double* __restrict__ mz,
+                                                  const double* __restrict__ gtab,
                                                   double* __restrict__ partials, int pstride) {
   fft_priority();
   extern __shared__ float2 sm[];
@@ -741,9 +742,16 @@ __global__ void __launch_bounds__(256) k_fft_cols(float2* __restrict__ grid, Pme
       float2 v = res[p * SP + kz];
       float g = 0.f;
       if (kx < Kxh) {
-        double msq = mx[kx] * mx[kx] + my[ky] * my[ky] + mz[kz] * mz[kz];
-        if (msq > 0.0) {
-          double gd = bmx[kx] * bmy[ky] * bmz[kz] * exp(-pp.exp_fac * msq) / msq;
+        // G from the context's table (the virial pass needs m^2 and forms it
+        // here); zero at m = 0
+        double msq = 0.0, gd = 0.0;
+        if (MODE == 3) {
+          msq = mx[kx] * mx[kx] + my[ky] * my[ky] + mz[kz] * mz[kz];
+          if (msq > 0.0) gd = bmx[kx] * bmy[ky] * bmz[kz] * exp(-pp.exp_fac * msq) / msq;
+        } else {
+          gd = gtab[((size_t)ky * Kxh + kx) * L + kz];
+        }
+        if (gd != 0.0) {
           int wgt = (kx == 0 || (2 * kx == pp.K[0])) ? 1 : 2;
           const double ew = (double)wgt * gd * ((double)v.x * v.x + (double)v.y * v.y);
           e += ew;
@@ -865,7 +873,7 @@ static void launch_cols(int blocks, size_t sh, hipStream_t s, Ctx& c, const PmeP
                         const FftPlan& pl, const float2* tw) {
   k_fft_cols<N, MODE><<<blocks, 256, sh, s>>>(c.grid_c, pp, P, pl, tw, c.bmod[0], c.bmod[1],
                                                c.bmod[2], c.mrec[0], c.mrec[1], c.mrec[2],
-                                               c.partials, c.max_blocks);
+                                               c.pme_g, c.partials, c.max_blocks);
 }
 
 static void rows_r2c(int N, int blocks, size_t sh, hipStream_t s, const float* in, float2* out,

@@ -269,6 +269,7 @@ int setup_pme(mdx_ctx* x, const mdx_system_desc* d) {
   if ((rc = dev_upload(x, &c.brick_z, bz)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.brick_zr, (size_t)g.nb[2] * c.cg.ncell)) != MDX_OK) return rc;
 
+  std::vector<double> bmh[3], mrh[3];
   for (int k = 0; k < 3; ++k) {
     const int K = g.K[k];
     std::vector<float2> tw(K);
@@ -288,6 +289,25 @@ int setup_pme(mdx_ctx* x, const mdx_system_desc* d) {
     if ((rc = dev_upload(x, &c.tw[k], tw)) != MDX_OK) return rc;
     if ((rc = dev_upload(x, &c.bmod[k], bm)) != MDX_OK) return rc;
     if ((rc = dev_upload(x, &c.mrec[k], mr)) != MDX_OK) return rc;
+    bmh[k] = bm;
+    mrh[k] = mr;
+  }
+  {
+    // the influence function on the half spectrum, in the z pass's order
+    // [ky][kx][kz]: G(m) = B(m) exp(-pi^2 m^2 / alpha^2) / m^2 (smooth PME,
+    // Sec. II.A.2)
+    const double exp_fac = M_PI * M_PI / (c.alpha * c.alpha);
+    std::vector<double> gt((size_t)g.K[1] * g.Kxh * g.K[2], 0.0);
+    for (int ky = 0; ky < g.K[1]; ++ky)
+      for (int kx = 0; kx < g.Kxh; ++kx)
+        for (int kz = 0; kz < g.K[2]; ++kz) {
+          const double msq =
+              mrh[0][kx] * mrh[0][kx] + mrh[1][ky] * mrh[1][ky] + mrh[2][kz] * mrh[2][kz];
+          if (msq > 0.0)
+            gt[((size_t)ky * g.Kxh + kx) * g.K[2] + kz] =
+                bmh[0][kx] * bmh[1][ky] * bmh[2][kz] * std::exp(-exp_fac * msq) / msq;
+        }
+    if ((rc = dev_upload(x, &c.pme_g, gt)) != MDX_OK) return rc;
   }
   c.pme_energy_scale = 1.0 / (M_PI * (double)c.box[0] * c.box[1] * c.box[2]);
   size_t ng = (size_t)g.K[0] * g.K[1] * g.K[2];
