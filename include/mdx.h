@@ -86,7 +86,9 @@ typedef struct mdx_batch mdx_batch;
 /*
  * System description (all pointers host, read during mdx_create only).
  *
- * Atoms: charge, mass, atom_type [n_atoms]; per-type LJ sigma/epsilon
+ * Atoms: charge, mass, atom_type [n_atoms] (n_atoms <= 100,000,000, more is
+ * MDX_E_UNSUPPORTED: kernels address per-atom arrays by 32-bit byte
+ * offsets); per-type LJ sigma/epsilon
  * [n_types] (Lorentz-Berthelot mixing, Eq. 5; n_types <= 32, more is
  * MDX_E_UNSUPPORTED). Topology index arrays use
  * the caller's atom order: exclusions [n_exclusions][2] (any order,

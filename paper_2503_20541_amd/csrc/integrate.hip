@@ -99,44 +99,73 @@ __device__ __forceinline__ void langevin_normals(unsigned long long seed, unsign
   z[2] = r2 * cosf(t2);
 }
 
-// The rest of the opening half once the three new coordinates of atom a
-// (slot s) are known: slot refresh and the two validity tests.
-__device__ __forceinline__ void open_tail(const OpenStep& o, int a, int s, const float x[3]) {
-  const int n = o.n;
+// What the opening half reads of atom a (slot s) besides its force and
+// velocity: position, build position, pruned-list position, charge, dt/2
+// scale and the Langevin noise amplitude. Read ahead of the kick, these loads
+// overlap the rest of the closing kernel's.
+struct OpenIn {
+  float x[3], b[3];
+  float4 p0;
+  float qa, acc, sig;
+};
+
+__device__ __forceinline__ void open_fetch(const OpenStep& o, int a, int s, OpenIn& in) {
+  const unsigned un = o.n, ua = a;
+  for (unsigned d = 0; d < 3; ++d) {
+    in.x[d] = ld32(o.pos_in, d * un + ua);
+    in.b[d] = ld32(o.x_build, d * un + ua);
+  }
+  in.p0 = ld32(o.xp, (unsigned)s);
+  in.qa = ld32(o.q, ua);
+  in.acc = ld32(o.acc_over_m, ua);
+  in.sig = o.lv_sig ? ld32(o.lv_sig, ua) : 0.f;
+}
+
+// The rest of the opening half once the three new coordinates x of an atom
+// in slot s are known (b: its build position, q0: its pruned-list position):
+// slot refresh and the two validity tests.
+__device__ __forceinline__ void open_tail_at(const OpenStep& o, int s, const float x[3],
+                                             const float b[3], float qa, float4 q0) {
   const CellGrid& cg = o.cg;
-  const float bx = o.x_build[a], by = o.x_build[n + a], bz = o.x_build[2 * n + a];
-  const float dx = min_image(bx, x[0], cg.L[0], cg.hL[0]);
-  const float dy = min_image(by, x[1], cg.L[1], cg.hL[1]);
-  const float dz = min_image(bz, x[2], cg.L[2], cg.hL[2]);
+  const float dx = min_image(b[0], x[0], cg.L[0], cg.hL[0]);
+  const float dy = min_image(b[1], x[1], cg.L[1], cg.hL[1]);
+  const float dz = min_image(b[2], x[2], cg.L[2], cg.hL[2]);
   // slot position continued from the build position (not wrapped between
   // builds), so the periodic image each list tile records stays valid
-  o.xs[s] = make_float4(bx + dx, by + dy, bz + dz, o.q[a]);
+  o.xs[s] = make_float4(b[0] + dx, b[1] + dy, b[2] + dz, qa);
   if (dist2(dx, dy, dz) > o.half_skin2) atomicOr(o.gate_now, 1);
   // pruned list: displacement since it was made (same slot order)
-  const float4 q0 = o.xp[s];
   const float px = min_image(q0.x, x[0], cg.L[0], cg.hL[0]);
   const float py = min_image(q0.y, x[1], cg.L[1], cg.hL[1]);
   const float pz = min_image(q0.z, x[2], cg.L[2], cg.hL[2]);
   if (dist2(px, py, pz) > o.prune_move2) atomicOr(o.pgate_now, 1);
 }
 
-__device__ __forceinline__ void open_step_atom(const OpenStep& o, const float* __restrict__ force,
+__device__ __forceinline__ void open_tail(const OpenStep& o, int a, int s, const float x[3]) {
+  const int n = o.n;
+  const float b[3] = {o.x_build[a], o.x_build[n + a], o.x_build[2 * n + a]};
+  open_tail_at(o, s, x, b, o.q[a], o.xp[s]);
+}
+
+// Opening half for atom a in slot s from its force f and velocity v.
+__device__ __forceinline__ void open_step_atom(const OpenStep& o, const OpenIn& in,
+                                               const float f[3], const float v[3],
                                                float* __restrict__ vel, int a, int s) {
   const int n = o.n;
   const CellGrid& cg = o.cg;
-  const float h = o.half_dt * o.acc_over_m[a];
+  const float h = o.half_dt * in.acc;
   float x[3];
   if (o.lv_sig) {
     // Langevin, BAOAB: kick, half drift, Ornstein-Uhlenbeck step, half drift
     float z[3];
     langevin_normals(o.lv_seed, o.lv_step, a, z);
-    const float sg = o.lv_sig[a];
+    const float sg = in.sig;
     const float hdt = 0.5f * o.dt;
     for (int d = 0; d < 3; ++d) {
       const size_t k = (size_t)d * n + a;
       int wraps;
-      const float v1 = vel[k] + h * force[k];
-      const float xh = o.pos_in[k] + hdt * v1;
+      const float v1 = v[d] + h * f[d];
+      const float xh = in.x[d] + hdt * v1;
       const float v2 = o.lv_c1 * v1 + o.lv_c2 * sg * z[d];
       vel[k] = v2;
       x[d] = wrap_box(xh + hdt * v2, cg.L[d], wraps);
@@ -149,20 +178,20 @@ __device__ __forceinline__ void open_step_atom(const OpenStep& o, const float* _
     int wraps;
     if (o.xc) {   // compensated sums (MDX_OPT_KAHAN_VV)
       float cv = o.vc[k], cx = o.xc[k];
-      const float v = kahan_add(vel[k], h * force[k], cv);
-      vel[k] = v;
-      x[d] = wrap_box(kahan_add(o.pos_in[k], o.dt * v, cx), cg.L[d], wraps);
+      const float vv = kahan_add(v[d], h * f[d], cv);
+      vel[k] = vv;
+      x[d] = wrap_box(kahan_add(in.x[d], o.dt * vv, cx), cg.L[d], wraps);
       o.vc[k] = cv;
       o.xc[k] = cx;
     } else {
-      const float v = vel[k] + h * force[k];
-      vel[k] = v;
-      x[d] = wrap_box(o.pos_in[k] + o.dt * v, cg.L[d], wraps);
+      const float vv = v[d] + h * f[d];
+      vel[k] = vv;
+      x[d] = wrap_box(in.x[d] + o.dt * vv, cg.L[d], wraps);
     }
     o.pos_out[k] = x[d];
     if (wraps) o.img[k] += wraps;
   }
-  open_tail(o, a, s, x);
+  open_tail_at(o, s, x, in.b, in.qa, in.p0);
 }
 
 // Stand-alone opening half for every slot (the first step of a call).
@@ -175,7 +204,12 @@ __global__ void __launch_bounds__(256) k_begin_step(OpenStep o, const float* __r
   if (s >= meta[0]) return;
   const int a = perm[s];
   if (a < 0) return;
-  open_step_atom(o, force, vel, a, s);
+  OpenIn in;
+  open_fetch(o, a, s, in);
+  const int n = o.n;
+  const float f[3] = {force[a], force[n + a], force[2 * n + a]};
+  const float v[3] = {vel[a], vel[n + a], vel[2 * n + a]};
+  open_step_atom(o, in, f, v, vel, a, s);
 }
 
 // Closing half of a step, four lanes per slot: lane q of the quad takes z
@@ -186,14 +220,20 @@ __global__ void __launch_bounds__(256) k_begin_step(OpenStep o, const float* __r
 // the total and applies v += (dt/2) a. FP64 energy
 // partials (exclusion, bond, angle, kinetic) per block. With `open`, lane 0
 // then opens the next step for its atom (open_step_atom, from the velocity
-// and force it has just stored): the same values as a separate opening
+// and force it has just computed): the same values as a separate opening
 // kernel, one launch fewer per step. The bonded terms read the positions of
 // other atoms from `pos`, so the new positions go to o.pos_out (another
 // buffer).
+//
+// The kernel is bound by the latency of its dependent loads, so every load
+// that does not need an earlier one's value is issued first: the slot's
+// position and the atom's list bounds, lane 0's kick and opening inputs, then
+// the PME plane and the first term of each kind (terms_fetch), and only then
+// the arithmetic, in the same order as a plain evaluation.
 constexpr int kFinishLanes = 4;
 
 template <bool ENERGY, bool COUL, bool PME>
-__global__ void __launch_bounds__(256) k_finish_step(
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_finish_step(
     const float4* __restrict__ xs, const int* __restrict__ perm, const int* __restrict__ meta,
     const float* __restrict__ phi, PmeParams pp, const float* __restrict__ pos, int n,
     BondedParams bp, Topology tp, float* __restrict__ fslot, int fstride,
@@ -209,12 +249,38 @@ __global__ void __launch_bounds__(256) k_finish_step(
   const int gt = lb * blockDim.x + threadIdx.x;
   const int s = gt / kFinishLanes, q = gt & (kFinishLanes - 1);
   double e_ex = 0.0, e_b = 0.0, e_a = 0.0, ke = 0.0;
-  const int a = lb >= 0 && s < meta[0] ? perm[s] : -1;
+  const bool live = lb >= 0 && s < meta[0];
+  const int a = live ? ld32(perm, (unsigned)s) : -1;
+  float4 p;
+  if (PME && live) p = ld32(xs, (unsigned)s);
   float fx = 0.f, fy = 0.f, fz = 0.f;
+  float fs[3], v[3], acc;
+  OpenIn in;
   if (a >= 0) {
-    if (PME) pme_gather_atom(xs[s], phi, pp, fx, fy, fz, q, kFinishLanes);
-    bonded_excl_atom<ENERGY, COUL>(a, pos, n, bp, tp, fx, fy, fz, e_ex, e_b, e_a, q,
-                                   kFinishLanes);
+    AtomTerms t;
+    terms_begin<COUL>(t, a, pos, n, tp, q);
+    // lane 0's inputs, read by all four lanes (one request per quad) so no
+    // branch holds the loads back
+    for (unsigned d = 0; d < 3; ++d) {
+      fs[d] = ld32(fslot, d * fstride + s);
+      v[d] = ld32(vel, d * n + a);
+    }
+    acc = ld32(acc_over_m, (unsigned)a);
+    if (open) open_fetch(o, a, s, in);
+    PmeStencil st;
+    float pv[16];
+    if (PME) {
+      pme_stencil(p, pp, st);
+      pme_plane_load(st, phi, pp, q, pv);
+    }
+    terms_fetch<COUL>(t, a, pos, n, tp);
+    if (PME) {
+      float gx = 0.f, gy = 0.f, gz = 0.f;
+      pme_plane_add(st, pv, pick4(st.th[2], q), pick4(st.dth[2], q), gx, gy, gz);
+      pme_force_add(p, pp, gx, gy, gz, fx, fy, fz);
+    }
+    terms_apply<ENERGY, COUL, false>(t, a, pos, n, bp, tp, fx, fy, fz, e_ex, e_b, e_a,
+                                     kFinishLanes, nullptr);
     if (jp.jpart) add_jparts(jp, s, q, kFinishLanes, fx, fy, fz);
   }
   // quad sum (all four lanes of a quad share the slot, so a is quad-uniform)
@@ -225,36 +291,39 @@ __global__ void __launch_bounds__(256) k_finish_step(
   fy += __shfl_xor(fy, 2, kWave);
   fz += __shfl_xor(fz, 2, kWave);
   if (a >= 0 && q == 0) {
-    fx += fslot[s];
-    fy += fslot[fstride + s];
-    fz += fslot[2 * fstride + s];
+    fx += fs[0];
+    fy += fs[1];
+    fz += fs[2];
     fslot[s] = 0.f;
     fslot[fstride + s] = 0.f;
     fslot[2 * fstride + s] = 0.f;
     force[a] = fx;
     force[n + a] = fy;
     force[2 * n + a] = fz;
-    const float h = half_dt * acc_over_m[a];
+    const float h = half_dt * acc;
     float v0, v1, v2;
     if (vc) {   // compensated sums (MDX_OPT_KAHAN_VV)
       float c0 = vc[a], c1 = vc[n + a], c2 = vc[2 * n + a];
-      v0 = kahan_add(vel[a], h * fx, c0);
-      v1 = kahan_add(vel[n + a], h * fy, c1);
-      v2 = kahan_add(vel[2 * n + a], h * fz, c2);
+      v0 = kahan_add(v[0], h * fx, c0);
+      v1 = kahan_add(v[1], h * fy, c1);
+      v2 = kahan_add(v[2], h * fz, c2);
       vc[a] = c0;
       vc[n + a] = c1;
       vc[2 * n + a] = c2;
     } else {
-      v0 = vel[a] + h * fx;
-      v1 = vel[n + a] + h * fy;
-      v2 = vel[2 * n + a] + h * fz;
+      v0 = v[0] + h * fx;
+      v1 = v[1] + h * fy;
+      v2 = v[2] + h * fz;
     }
     vel[a] = v0;
     vel[n + a] = v1;
     vel[2 * n + a] = v2;
     if (ENERGY)
       ke = (double)mass[a] * ((double)v0 * v0 + (double)v1 * v1 + (double)v2 * v2) * inv_2acc;
-    if (open) open_step_atom(o, force, vel, a, s);
+    if (open) {
+      const float f3[3] = {fx, fy, fz}, v3[3] = {v0, v1, v2};
+      open_step_atom(o, in, f3, v3, vel, a, s);
+    }
   }
   if (ENERGY) {
     double s1 = block_sum(e_ex, red);

@@ -29,6 +29,9 @@ __device__ __forceinline__ int xcd_block(int nwork) {
   const int i = (int)(blockIdx.x / kXcds);
   return i < per ? (int)(blockIdx.x % kXcds) * per + i : -1;
 }
+// Atoms per context: kernels address per-atom arrays ([3][n] floats at most)
+// and the slot arrays by 32-bit byte offsets (ld32).
+constexpr int kMaxAtoms = 100000000;
 constexpr int kMaxLjTypes = 32;   // LJ atom types (the pair kernel keeps the type-pair table in LDS)
 // PME spreading bricks: kBrickXY x kBrickXY x kBrickZ grid points (smaller
 // along a dimension with fewer grid points)
@@ -456,6 +459,16 @@ __device__ __forceinline__ float kahan_add(float s, float y, float& c) {
   const float t = s + yc;
   c = (t - s) - yc;
   return t;
+}
+
+// Element i of a device array, addressed as the array's (wave-uniform) base
+// plus a 32-bit byte offset: the load then takes a scalar base and one 32-bit
+// lane offset instead of 64-bit per-lane address arithmetic. The arrays read
+// this way stay below 4 GB (kMaxAtoms).
+template <typename T>
+__device__ __forceinline__ T ld32(const T* __restrict__ base, unsigned i) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) +
+                                     i * (unsigned)sizeof(T));
 }
 
 __device__ __forceinline__ float dist2(float dx, float dy, float dz) {

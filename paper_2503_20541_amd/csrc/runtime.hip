@@ -84,6 +84,15 @@ void dev_free(mdx_ctx* x, void* p) {
   (void)hipFree(p);
 }
 
+// v with zeros appended up to m entries. The closing kernel reads entry 0 of
+// each topology array (and members 0..2 of term 0) whether or not an atom
+// has terms of that kind, so these arrays are never empty.
+template <typename T>
+std::vector<T> padded(std::vector<T> v, size_t m) {
+  if (v.size() < m) v.resize(m, T(0));
+  return v;
+}
+
 // CSR of per-atom item lists from (atom, item) pairs.
 void build_csr(int n, const std::vector<std::pair<int, int>>& items, std::vector<int>& start,
                std::vector<int>& idx) {
@@ -320,7 +329,7 @@ int setup_pme(mdx_ctx* x, const mdx_system_desc* d) {
 int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
   Ctx& c = x->c;
   const int n = d->n_atoms;
-  if (d->n_types > mdx::kMaxLjTypes) return MDX_E_UNSUPPORTED;
+  if (d->n_types > mdx::kMaxLjTypes || n > mdx::kMaxAtoms) return MDX_E_UNSUPPORTED;
   if (n <= 0 || !d->charge || !d->mass || !d->atom_type || d->n_types <= 0 || !d->type_sigma ||
       !d->type_epsilon)
     return MDX_E_INVALID;
@@ -459,7 +468,7 @@ int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
   build_csr(n, items, st, ix);
   c.n_excl = (int)ex.size();
   if ((rc = dev_upload(x, &c.ex_start, st)) != MDX_OK) return rc;
-  if ((rc = dev_upload(x, &c.ex_idx, ix)) != MDX_OK) return rc;
+  if ((rc = dev_upload(x, &c.ex_idx, padded(ix, 1))) != MDX_OK) return rc;
 
   std::vector<int> bidx(2 * d->n_bonds);
   std::vector<float> bk(d->n_bonds), br(d->n_bonds);
@@ -476,11 +485,11 @@ int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
   }
   build_csr(n, items, st, ix);
   c.n_bonds = d->n_bonds;
-  if ((rc = dev_upload(x, &c.bonds, bidx)) != MDX_OK) return rc;
-  if ((rc = dev_upload(x, &c.bond_k, bk)) != MDX_OK) return rc;
-  if ((rc = dev_upload(x, &c.bond_r0, br)) != MDX_OK) return rc;
+  if ((rc = dev_upload(x, &c.bonds, padded(bidx, 2))) != MDX_OK) return rc;
+  if ((rc = dev_upload(x, &c.bond_k, padded(bk, 1))) != MDX_OK) return rc;
+  if ((rc = dev_upload(x, &c.bond_r0, padded(br, 1))) != MDX_OK) return rc;
   if ((rc = dev_upload(x, &c.bt_start, st)) != MDX_OK) return rc;
-  if ((rc = dev_upload(x, &c.bt_idx, ix)) != MDX_OK) return rc;
+  if ((rc = dev_upload(x, &c.bt_idx, padded(ix, 1))) != MDX_OK) return rc;
 
   std::vector<int> aidx(3 * d->n_angles);
   std::vector<float> ak(d->n_angles), at(d->n_angles);
@@ -500,11 +509,11 @@ int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
   }
   build_csr(n, items, st, ix);
   c.n_angles = d->n_angles;
-  if ((rc = dev_upload(x, &c.angles, aidx)) != MDX_OK) return rc;
-  if ((rc = dev_upload(x, &c.angle_k, ak)) != MDX_OK) return rc;
-  if ((rc = dev_upload(x, &c.angle_t0, at)) != MDX_OK) return rc;
+  if ((rc = dev_upload(x, &c.angles, padded(aidx, 3))) != MDX_OK) return rc;
+  if ((rc = dev_upload(x, &c.angle_k, padded(ak, 1))) != MDX_OK) return rc;
+  if ((rc = dev_upload(x, &c.angle_t0, padded(at, 1))) != MDX_OK) return rc;
   if ((rc = dev_upload(x, &c.at_start, st)) != MDX_OK) return rc;
-  if ((rc = dev_upload(x, &c.at_idx, ix)) != MDX_OK) return rc;
+  if ((rc = dev_upload(x, &c.at_idx, padded(ix, 1))) != MDX_OK) return rc;
 
   // ---- column sort, cluster slots and tile list storage ----
   const int ncol = g.ncell;
