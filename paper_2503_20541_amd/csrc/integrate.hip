@@ -212,10 +212,11 @@ __global__ void __launch_bounds__(256) k_begin_step(OpenStep o, const float* __r
   open_step_atom(o, in, f, v, vel, a, s);
 }
 
-// Closing half of a step, four lanes per slot: lane q of the quad takes z
-// plane q of the PME stencil and every fourth bonded / exclusion term of the
-// atom (and, with a half list, every fourth of the j partials naming its
-// cluster); the quad sums its parts in a fixed order, and lane 0 adds the
+// Closing half of a step, two lanes per slot: lane q of the pair takes z
+// planes q and q + 2 of the PME stencil and every second bonded / exclusion
+// term of the atom (and, with a half list, every second of the j partials
+// naming its cluster); the pair sums its parts in a fixed order, and lane 0
+// adds the
 // pair force the pair kernel stored in the slot array (clearing it), stores
 // the total and applies v += (dt/2) a. FP64 energy
 // partials (exclusion, bond, angle, kinetic) per block. With `open`, lane 0
@@ -230,10 +231,11 @@ __global__ void __launch_bounds__(256) k_begin_step(OpenStep o, const float* __r
 // position and the atom's list bounds, lane 0's kick and opening inputs, then
 // the PME plane and the first term of each kind (terms_fetch), and only then
 // the arithmetic, in the same order as a plain evaluation.
-constexpr int kFinishLanes = 4;
+constexpr int kFinishLanes = 2;
+constexpr int kFinishPlanes = 4 / kFinishLanes;   // PME z planes per lane
 
 template <bool ENERGY, bool COUL, bool PME>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_finish_step(
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_finish_step(
     const float4* __restrict__ xs, const int* __restrict__ perm, const int* __restrict__ meta,
     const float* __restrict__ phi, PmeParams pp, const float* __restrict__ pos, int n,
     BondedParams bp, Topology tp, float* __restrict__ fslot, int fstride,
@@ -259,7 +261,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
   if (a >= 0) {
     AtomTerms t;
     terms_begin<COUL>(t, a, pos, n, tp, q);
-    // lane 0's inputs, read by all four lanes (one request per quad) so no
+    // lane 0's inputs, read by both lanes (one request per pair) so no
     // branch holds the loads back
     for (unsigned d = 0; d < 3; ++d) {
       fs[d] = ld32(fslot, d * fstride + s);
@@ -268,28 +270,31 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     acc = ld32(acc_over_m, (unsigned)a);
     if (open) open_fetch(o, a, s, in);
     PmeStencil st;
-    float pv[16];
+    float pv[kFinishPlanes][16];
     if (PME) {
       pme_stencil(p, pp, st);
-      pme_plane_load(st, phi, pp, q, pv);
+      for (int k = 0; k < kFinishPlanes; ++k)
+        pme_plane_load(st, phi, pp, q + k * kFinishLanes, pv[k]);
     }
     terms_fetch<COUL>(t, a, pos, n, tp);
     if (PME) {
       float gx = 0.f, gy = 0.f, gz = 0.f;
-      pme_plane_add(st, pv, pick4(st.th[2], q), pick4(st.dth[2], q), gx, gy, gz);
+      for (int k = 0; k < kFinishPlanes; ++k) {
+        const int t3 = q + k * kFinishLanes;
+        pme_plane_add(st, pv[k], pick4(st.th[2], t3), pick4(st.dth[2], t3), gx, gy, gz);
+      }
       pme_force_add(p, pp, gx, gy, gz, fx, fy, fz);
     }
     terms_apply<ENERGY, COUL, false>(t, a, pos, n, bp, tp, fx, fy, fz, e_ex, e_b, e_a,
                                      kFinishLanes, nullptr);
     if (jp.jpart) add_jparts(jp, s, q, kFinishLanes, fx, fy, fz);
   }
-  // quad sum (all four lanes of a quad share the slot, so a is quad-uniform)
-  fx += __shfl_xor(fx, 1, kWave);
-  fy += __shfl_xor(fy, 1, kWave);
-  fz += __shfl_xor(fz, 1, kWave);
-  fx += __shfl_xor(fx, 2, kWave);
-  fy += __shfl_xor(fy, 2, kWave);
-  fz += __shfl_xor(fz, 2, kWave);
+  // sum over the slot's lanes (they share the slot, so a is uniform among them)
+  for (int o = 1; o < kFinishLanes; o <<= 1) {
+    fx += __shfl_xor(fx, o, kWave);
+    fy += __shfl_xor(fy, o, kWave);
+    fz += __shfl_xor(fz, o, kWave);
+  }
   if (a >= 0 && q == 0) {
     fx += fs[0];
     fy += fs[1];
