@@ -127,6 +127,13 @@ def test_error_codes():
     with pytest.raises(mdx.MdxError) as e:
         mdx.create(desc)
     assert e.value.code == mdx.MDX_E_UNSUPPORTED
+    # more atoms than the 32-bit byte offsets of the kernels allow (refused
+    # before any array is read)
+    desc, keep = mdx.desc_from_system(s)
+    desc.n_atoms = 100_000_001
+    with pytest.raises(mdx.MdxError) as e:
+        mdx.create(desc)
+    assert e.value.code == mdx.MDX_E_UNSUPPORTED
     desc, keep = mdx.desc_from_system(s)
     ctx = mdx.create(desc)
     try:
@@ -281,3 +288,39 @@ def test_half_list_stand_alone_call_between_steps():
         assert m.get_status(ctx) == 0
         F_fresh = fresh.cpu().numpy().astype(np.float64)
     assert np.linalg.norm(F_run - F_fresh) < 1e-6 * np.linalg.norm(F_fresh)
+
+
+@pytest.mark.parametrize("n_excl", [0, 1], ids=["no-exclusions", "exclusions"])
+def test_pme_steps_without_bonded_terms(n_excl):
+    # charged atoms with PME and no bonds or angles (first also no
+    # exclusions): the closing kernel reads entry 0 of each empty topology
+    # array, which the context pads, and must add nothing for it. After 12
+    # steps (energies on, so both kernel variants run) the force it leaves
+    # is the oracle's at the GPU's positions, and the positions follow the
+    # oracle's trajectory.
+    import torch
+    s = synth.random_box(96, [9.0, 9.0, 9.0], 3.5, 0.5, 4242, n_excl_per_atom=n_excl,
+                         pme_grid=(16, 16, 16), min_dist=0.9)
+    assert len(s.bonds) == 0 and len(s.angles) == 0
+    assert (len(s.exclusions) == 0) == (n_excl == 0)
+    n_steps, dt = 12, 0.001
+    announce(f"PME steps without bonded terms, exclusions per atom {n_excl}")
+    with gpu_context(s) as (mdx, ctx, t):
+        mdx.build_neighbors(ctx, t["pos"])
+        mdx.compute_nonbonded(ctx, t["pos"], t["force"])
+        mdx.compute_pme(ctx, t["pos"], t["force"])
+        en = torch.zeros((n_steps, mdx.MDX_N_ENERGY), dtype=torch.float64, device="cuda:0")
+        mdx.integrate_step(ctx, t["pos"], t["vel"], t["force"], n_steps, dt, en)
+        torch.cuda.synchronize()
+        assert mdx.get_status(ctx) == 0
+        x_gpu = t["pos"].cpu().numpy().astype(np.float64)
+        f_gpu = t["force"].cpu().numpy().astype(np.float64)
+        assert np.all(np.isfinite(en.cpu().numpy()))
+    f_orc = forcefield.total_forces_fp64(s, x_gpu)[1]
+    rel = np.linalg.norm(f_gpu - f_orc) / np.linalg.norm(f_orc)
+    assert rel < 1e-5, rel
+    F = lambda p: forcefield.total_forces_fp64(s, p)[1]
+    ref = integrate.velocity_verlet(s.pos, s.vel, s.mass, s.box, F, dt, n_steps, float(s.accel))
+    d = x_gpu - ref["pos"]
+    d -= s.box[:, None] * np.round(d / s.box[:, None])
+    assert np.abs(d).max() < 1e-4
