@@ -753,6 +753,12 @@ def main():
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(s)
     print(json.dumps(result), flush=True)
+    # a run that raised a status flag (list or cell overflow, stale list) or
+    # left non-finite coordinates measured something else: fail loudly
+    if result.get("status_flags", 0) != 0 or result.get("finite") is False:
+        print(f"bench: status flags {result.get('status_flags')}, finite "
+              f"{result.get('finite')}: the measurement is not valid", file=sys.stderr, flush=True)
+        sys.exit(3)
 
 
 if __name__ == "__main__":
