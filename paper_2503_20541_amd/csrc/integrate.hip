@@ -234,7 +234,7 @@ __global__ void __launch_bounds__(256) k_begin_step(OpenStep o, const float* __r
 constexpr int kFinishLanes = 2;
 constexpr int kFinishPlanes = 4 / kFinishLanes;   // PME z planes per lane
 
-template <bool ENERGY, bool COUL, bool PME>
+template <bool ENERGY, bool COUL, bool PME, bool SIDE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_finish_step(
     const float4* __restrict__ xs, const int* __restrict__ perm, const int* __restrict__ meta,
     const float* __restrict__ phi, PmeParams pp, const float* __restrict__ pos, int n,
@@ -242,7 +242,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     float* __restrict__ force, float* __restrict__ vel,
     const float* __restrict__ acc_over_m, const float* __restrict__ mass, float half_dt,
     double inv_2acc, double* __restrict__ partials, int pstride, float* __restrict__ vc,
-    OpenStep o, int open, JParts jp) {
+    OpenStep o, int open, JParts jp, const float* __restrict__ fside) {
   __shared__ double red[16];
   if (open && blockIdx.x == 0 && threadIdx.x == 0) open_step_flags(o);
   // neighbouring slots on one XCD: the PME potential they gather comes from
@@ -256,15 +256,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   float4 p;
   if (PME && live) p = ld32(xs, (unsigned)s);
   float fx = 0.f, fy = 0.f, fz = 0.f;
-  float fs[3], v[3], acc;
+  float fs[3], sd[3], v[3], acc;
   OpenIn in;
   if (a >= 0) {
     AtomTerms t;
-    terms_begin<COUL>(t, a, pos, n, tp, q);
+    if (!SIDE) terms_begin<COUL>(t, a, pos, n, tp, q);
     // lane 0's inputs, read by both lanes (one request per pair) so no
     // branch holds the loads back
     for (unsigned d = 0; d < 3; ++d) {
       fs[d] = ld32(fslot, d * fstride + s);
+      if (SIDE) sd[d] = ld32(fside, d * fstride + s);
       v[d] = ld32(vel, d * n + a);
     }
     acc = ld32(acc_over_m, (unsigned)a);
@@ -276,7 +277,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
       for (int k = 0; k < kFinishPlanes; ++k)
         pme_plane_load(st, phi, pp, q + k * kFinishLanes, pv[k]);
     }
-    terms_fetch<COUL>(t, a, pos, n, tp);
+    if (!SIDE) terms_fetch<COUL>(t, a, pos, n, tp);
     if (PME) {
       float gx = 0.f, gy = 0.f, gz = 0.f;
       for (int k = 0; k < kFinishPlanes; ++k) {
@@ -285,8 +286,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
       }
       pme_force_add(p, pp, gx, gy, gz, fx, fy, fz);
     }
-    terms_apply<ENERGY, COUL, false>(t, a, pos, n, bp, tp, fx, fy, fz, e_ex, e_b, e_a,
-                                     kFinishLanes, nullptr);
+    if (!SIDE)
+      terms_apply<ENERGY, COUL, false>(t, a, pos, n, bp, tp, fx, fy, fz, e_ex, e_b, e_a,
+                                       kFinishLanes, nullptr);
     if (jp.jpart) add_jparts(jp, s, q, kFinishLanes, fx, fy, fz);
   }
   // sum over the slot's lanes (they share the slot, so a is uniform among them)
@@ -299,6 +301,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     fx += fs[0];
     fy += fs[1];
     fz += fs[2];
+    if (SIDE) {
+      fx += sd[0];
+      fy += sd[1];
+      fz += sd[2];
+    }
     fslot[s] = 0.f;
     fslot[fstride + s] = 0.f;
     fslot[2 * fstride + s] = 0.f;
@@ -331,15 +338,65 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     }
   }
   if (ENERGY) {
+    if (!SIDE) {   // (with SIDE the side kernel wrote these rows)
+      double s1 = block_sum(e_ex, red);
+      double s2 = block_sum(e_b, red);
+      double s3 = block_sum(e_a, red);
+      if (threadIdx.x == 0) {
+        partials[kRowExcl * pstride + blockIdx.x] = s1;
+        partials[kRowBond * pstride + blockIdx.x] = s2;
+        partials[kRowAngle * pstride + blockIdx.x] = s3;
+      }
+    }
+    double s4 = block_sum(ke, red);
+    if (threadIdx.x == 0) partials[kRowKin * pstride + blockIdx.x] = s4;
+  }
+}
+
+// The closing half's bonded and exclusion terms on their own. They need only
+// this step's positions, so inside mdx_integrate_step (PME contexts) they run
+// on the second stream after the reciprocal-space passes, beside the end of
+// the pair kernel, and the closing kernel adds their sum by slot instead of
+// evaluating them. Same lanes, block order and grid as the closing kernel,
+// so its energy rows (exclusion, bond, angle) line up with its kinetic row.
+template <bool ENERGY, bool COUL>
+__global__ void __launch_bounds__(256) k_side_terms(
+    const int* __restrict__ perm, const int* __restrict__ meta, const float* __restrict__ pos,
+    int n, BondedParams bp, Topology tp, float* __restrict__ fside, int fstride,
+    double* __restrict__ partials, int pstride) {
+  __shared__ double red[16];
+  const int lb = xcd_block((meta[0] * kFinishLanes + 255) / 256);
+  const int gt = lb * blockDim.x + threadIdx.x;
+  const int s = gt / kFinishLanes, q = gt & (kFinishLanes - 1);
+  const bool live = lb >= 0 && s < meta[0];
+  const int a = live ? ld32(perm, (unsigned)s) : -1;
+  double e_ex = 0.0, e_b = 0.0, e_a = 0.0;
+  float fx = 0.f, fy = 0.f, fz = 0.f;
+  if (a >= 0) {
+    AtomTerms t;
+    terms_begin<COUL>(t, a, pos, n, tp, q);
+    terms_fetch<COUL>(t, a, pos, n, tp);
+    terms_apply<ENERGY, COUL, false>(t, a, pos, n, bp, tp, fx, fy, fz, e_ex, e_b, e_a,
+                                     kFinishLanes, nullptr);
+  }
+  for (int o = 1; o < kFinishLanes; o <<= 1) {
+    fx += __shfl_xor(fx, o, kWave);
+    fy += __shfl_xor(fy, o, kWave);
+    fz += __shfl_xor(fz, o, kWave);
+  }
+  if (a >= 0 && q == 0) {
+    fside[s] = fx;
+    fside[fstride + s] = fy;
+    fside[2 * fstride + s] = fz;
+  }
+  if (ENERGY) {
     double s1 = block_sum(e_ex, red);
     double s2 = block_sum(e_b, red);
     double s3 = block_sum(e_a, red);
-    double s4 = block_sum(ke, red);
     if (threadIdx.x == 0) {
       partials[kRowExcl * pstride + blockIdx.x] = s1;
       partials[kRowBond * pstride + blockIdx.x] = s2;
       partials[kRowAngle * pstride + blockIdx.x] = s3;
-      partials[kRowKin * pstride + blockIdx.x] = s4;
     }
   }
 }
@@ -687,9 +744,33 @@ hipError_t launch_begin_step(Ctx& c, float* pos, float* vel, const float* force,
   return hipGetLastError();
 }
 
+hipError_t launch_side_terms(Ctx& c, const float* pos, bool energy, hipStream_t s,
+                             hipEvent_t done) {
+  if (!c.fside) return hipErrorInvalidValue;
+  const int nb = xcd_grid((c.max_slots * kFinishLanes + 255) / 256);
+  BondedParams bp = make_bonded_params(c);
+  Topology tp = make_topology(c);
+  const int* perm = c.perm;
+  const int* meta = c.meta;
+  int n = c.n, fstride = c.max_slots, pstride = c.max_blocks;
+  float* fside = c.fside;
+  double* partials = c.partials;
+  const void* fn = energy ? (c.has_coulomb ? reinterpret_cast<const void*>(k_side_terms<true, true>)
+                                           : reinterpret_cast<const void*>(k_side_terms<true, false>))
+                          : (c.has_coulomb ? reinterpret_cast<const void*>(k_side_terms<false, true>)
+                                           : reinterpret_cast<const void*>(k_side_terms<false, false>));
+  void* args[] = {&perm, &meta, &pos, &n, &bp, &tp, &fside, &fstride, &partials, &pstride};
+  if (done && !c.capturing)
+    return hipExtLaunchKernel(fn, dim3(nb), dim3(256), args, 0, s, nullptr, done, 0);
+  hipError_t e = hipLaunchKernel(fn, dim3(nb), dim3(256), args, 0, s);
+  if (e == hipSuccess && done) e = hipEventRecord(done, s);
+  return e;
+}
+
 hipError_t launch_finish_step(Ctx& c, const float* pos, float* vel, float* force, float dt,
-                              bool energy, const StepGates* next, float* pos_next) {
+                              bool energy, const StepGates* next, float* pos_next, bool side) {
   if (next && (!pos_next || pos_next == pos)) return hipErrorInvalidValue;
+  if (side && (!c.fside || !c.has_pme || !c.has_coulomb)) return hipErrorInvalidValue;
   const StepGates none{c.gate, c.gate, c.gate, c.gate, false, 0};   // not used when !next
   const OpenStep o = make_open(c, pos, pos_next, dt, next ? *next : none);
   const int open = next ? 1 : 0;
@@ -699,21 +780,23 @@ hipError_t launch_finish_step(Ctx& c, const float* pos, float* vel, float* force
   const Topology tp = make_topology(c);
   const double inv_2acc = 0.5 / c.accel;
   c.finish_blocks = nb;
-#define MDX_FIN(E, C, P)                                                                      \
-  k_finish_step<E, C, P><<<nb, 256, 0, c.stream>>>(c.xs, c.perm, c.meta, c.grid_phi, pp, pos, \
-                                                    c.n, bp, tp, c.fslot, c.max_slots, force, \
-                                                    vel, c.hdt_scale, c.mass, 0.5f * dt,      \
-                                                    inv_2acc, c.partials, c.max_blocks, c.vc, \
-                                                    o, open, c.jparts())
+#define MDX_FIN(E, C, P, S)                                                                    \
+  k_finish_step<E, C, P, S><<<nb, 256, 0, c.stream>>>(c.xs, c.perm, c.meta, c.grid_phi, pp, pos, \
+                                                       c.n, bp, tp, c.fslot, c.max_slots, force, \
+                                                       vel, c.hdt_scale, c.mass, 0.5f * dt,      \
+                                                       inv_2acc, c.partials, c.max_blocks, c.vc, \
+                                                       o, open, c.jparts(), c.fside)
   const bool C = c.has_coulomb, P = c.has_pme;
   if (energy) {
-    if (C && P) MDX_FIN(true, true, true);
-    else if (C) MDX_FIN(true, true, false);
-    else MDX_FIN(true, false, false);
+    if (side) MDX_FIN(true, true, true, true);
+    else if (C && P) MDX_FIN(true, true, true, false);
+    else if (C) MDX_FIN(true, true, false, false);
+    else MDX_FIN(true, false, false, false);
   } else {
-    if (C && P) MDX_FIN(false, true, true);
-    else if (C) MDX_FIN(false, true, false);
-    else MDX_FIN(false, false, false);
+    if (side) MDX_FIN(false, true, true, true);
+    else if (C && P) MDX_FIN(false, true, true, false);
+    else if (C) MDX_FIN(false, true, false, false);
+    else MDX_FIN(false, false, false, false);
   }
 #undef MDX_FIN
   return hipGetLastError();

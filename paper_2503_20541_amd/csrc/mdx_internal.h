@@ -219,6 +219,8 @@ struct Ctx {
   float4* xs = nullptr;        // [max_slots] (x, y, z, q) at the current positions
   float* fslot = nullptr;      // [3][max_slots] pair forces by slot; all zero between
                                // a force evaluation's consumer and the next pair kernel
+  float* fside = nullptr;      // [3][max_slots] bonded + exclusion forces by slot, from
+                               // the second stream (PME contexts; mdx_integrate_step)
   int* ts = nullptr;           // [max_slots] LJ type
   float* zb = nullptr;         // [max_slots] z at the last build (sorted within a column)
   float4* box_lo = nullptr;    // [max_clusters] cluster box (w = real atoms)
@@ -341,9 +343,16 @@ hipError_t launch_begin_step(Ctx& c, float* pos, float* vel, const float* force,
 // opens the following step (gates *next) from the closing kick's velocities
 // and forces, reading pos and writing the new positions to pos_next (another
 // buffer: the bonded terms of other atoms still read pos).
+// With `side`, the bonded and exclusion terms are not evaluated: their sum
+// by slot is read from c.fside (launch_side_terms of the same step).
 hipError_t launch_finish_step(Ctx& c, const float* pos, float* vel, float* force, float dt,
                               bool energy, const StepGates* next = nullptr,
-                              float* pos_next = nullptr);
+                              float* pos_next = nullptr, bool side = false);
+// The closing half's bonded and exclusion terms at positions pos, summed by
+// slot into c.fside (and their energy rows of the closing kernel's partials)
+// on stream s; `done` (if given) is recorded by the kernel's own dispatch.
+hipError_t launch_side_terms(Ctx& c, const float* pos, bool energy, hipStream_t s,
+                             hipEvent_t done);
 // Rigid water: SHAKE after the drift (x_old: positions before it) with the
 // velocity correction, wrap, slot refresh and validity tests (x_old: positions
 // before the drift, y_in: after it, pos: output, which may be x_old or y_in);

@@ -539,6 +539,7 @@ int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
   if ((rc = dev_alloc(x, &c.zbin, (size_t)ncol * (g.nzb + 1))) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.fslot, (size_t)3 * c.max_slots)) != MDX_OK) return rc;
   MDX_TRY(hipMemset(c.fslot, 0, sizeof(float) * 3 * c.max_slots));
+  if (c.has_pme && (rc = dev_alloc(x, &c.fside, (size_t)3 * c.max_slots)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.ts, c.max_slots)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.zb, c.max_slots)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.box_lo, c.max_clusters)) != MDX_OK) return rc;
@@ -956,20 +957,22 @@ int integrate_eager(mdx_ctx* x, float* pos, float* vel, float* force, int32_t n_
     // The reciprocal-space potential only needs this step's slot positions
     // and the PME brick slot ranges: the spread and the FFT passes run on the
     // second stream, from the end of the list build on, concurrently with
-    // the pair kernel; the closing kernel (force interpolation) waits for
-    // them. The fork and join events are recorded by the tile search's and
-    // the last FFT pass's own dispatches (no marker packets between kernels).
+    // the pair kernel. The bonded and exclusion terms need only the
+    // positions: they follow on the second stream (side terms), beside the
+    // end of the pair kernel. The closing kernel (force interpolation, kick)
+    // waits for both. The fork and join events are recorded by the tile
+    // search's and the side kernel's own dispatches (no marker packets
+    // between kernels).
     if (c.has_pme) {
       MDX_TRY(hipStreamWaitEvent(x->aux, x->ev_fork, 0));
       std::pair<hipEvent_t, hipEvent_t>* tslot;
       MDX_TRY(timing_begin(x, MDX_TIMING_PME, x->aux, &tslot));
       MDX_TRY(mdx::launch_pme_spread(c, x->aux, nullptr));
-      // the join event is recorded by the last pass's dispatch, or (timing,
-      // graph capture) explicitly after it
-      const bool by_dispatch = !tslot && !c.capturing;
-      MDX_TRY(mdx::launch_pme_fft(c, x->aux, by_dispatch ? x->ev_join : nullptr));
+      MDX_TRY(mdx::launch_pme_fft(c, x->aux, nullptr));
       MDX_TRY(timing_end(tslot, x->aux));
-      if (!by_dispatch) MDX_TRY(hipEventRecord(x->ev_join, x->aux));
+      // the join event is recorded by the side kernel's dispatch, or (graph
+      // capture) explicitly after it
+      MDX_TRY(mdx::launch_side_terms(c, pos_cur, e, x->aux, x->ev_join));
     }
     {
       // timed by events that the pair kernel's dispatch records (marker
@@ -980,8 +983,9 @@ int integrate_eager(mdx_ctx* x, float* pos, float* vel, float* force, int32_t n_
                                     ps ? ps->first : nullptr, ps ? ps->second : nullptr));
     }
     if (c.has_pme) MDX_TRY(hipStreamWaitEvent(c.stream, x->ev_join, 0));
+    const bool side = c.has_pme;
     if (rigid) {
-      MDX_TRY(mdx::launch_finish_step(c, pos_cur, vel, force, dt, e));
+      MDX_TRY(mdx::launch_finish_step(c, pos_cur, vel, force, dt, e, nullptr, nullptr, side));
       MDX_TRY(mdx::launch_rigid_velocities(c, pos_cur, vel, e, &rigid_blocks));
       if (s + 1 < n_steps) {
         g = gates_of(c.steps_taken + 1);
@@ -989,11 +993,11 @@ int integrate_eager(mdx_ctx* x, float* pos, float* vel, float* force, int32_t n_
       }
     } else if (s + 1 < n_steps) {
       const mdx::StepGates next = gates_of(c.steps_taken + 1);
-      MDX_TRY(mdx::launch_finish_step(c, pos_cur, vel, force, dt, e, &next, pos_other));
+      MDX_TRY(mdx::launch_finish_step(c, pos_cur, vel, force, dt, e, &next, pos_other, side));
       std::swap(pos_cur, pos_other);
       g = next;
     } else {
-      MDX_TRY(mdx::launch_finish_step(c, pos_cur, vel, force, dt, e));
+      MDX_TRY(mdx::launch_finish_step(c, pos_cur, vel, force, dt, e, nullptr, nullptr, side));
     }
     if (e) {
       int rows[7] = {mdx::kRowLJ,    mdx::kRowDir, mdx::kRowExcl, mdx::kRowBond,
