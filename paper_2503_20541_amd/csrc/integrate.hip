@@ -254,7 +254,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   const bool live = lb >= 0 && s < meta[0];
   const int a = live ? ld32(perm, (unsigned)s) : -1;
   float4 p;
-  if (PME && live) p = ld32(xs, (unsigned)s);
+  if (PME && !SIDE && live) p = ld32(xs, (unsigned)s);
   float fx = 0.f, fy = 0.f, fz = 0.f;
   float fs[3], sd[3], v[3], acc;
   OpenIn in;
@@ -272,13 +272,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     if (open) open_fetch(o, a, s, in);
     PmeStencil st;
     float pv[kFinishPlanes][16];
-    if (PME) {
+    if (PME && !SIDE) {
       pme_stencil(p, pp, st);
       for (int k = 0; k < kFinishPlanes; ++k)
         pme_plane_load(st, phi, pp, q + k * kFinishLanes, pv[k]);
     }
     if (!SIDE) terms_fetch<COUL>(t, a, pos, n, tp);
-    if (PME) {
+    if (PME && !SIDE) {
       float gx = 0.f, gy = 0.f, gz = 0.f;
       for (int k = 0; k < kFinishPlanes; ++k) {
         const int t3 = q + k * kFinishLanes;
@@ -360,9 +360,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
 // evaluating them. Same lanes, block order and grid as the closing kernel,
 // so its energy rows (exclusion, bond, angle) line up with its kinetic row.
 template <bool ENERGY, bool COUL>
-__global__ void __launch_bounds__(256) k_side_terms(
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_side_terms(
     const int* __restrict__ perm, const int* __restrict__ meta, const float* __restrict__ pos,
-    int n, BondedParams bp, Topology tp, float* __restrict__ fside, int fstride,
+    int n, BondedParams bp, Topology tp, const float4* __restrict__ xs,
+    const float* __restrict__ phi, PmeParams pp, float* __restrict__ fside, int fstride,
     double* __restrict__ partials, int pstride) {
   __shared__ double red[16];
   const int lb = xcd_block((meta[0] * kFinishLanes + 255) / 256);
@@ -370,12 +371,27 @@ __global__ void __launch_bounds__(256) k_side_terms(
   const int s = gt / kFinishLanes, q = gt & (kFinishLanes - 1);
   const bool live = lb >= 0 && s < meta[0];
   const int a = live ? ld32(perm, (unsigned)s) : -1;
+  float4 p;
+  if (live) p = ld32(xs, (unsigned)s);
   double e_ex = 0.0, e_b = 0.0, e_a = 0.0;
   float fx = 0.f, fy = 0.f, fz = 0.f;
   if (a >= 0) {
     AtomTerms t;
     terms_begin<COUL>(t, a, pos, n, tp, q);
+    PmeStencil st;
+    float pv[kFinishPlanes][16];
+    pme_stencil(p, pp, st);
+    for (int k = 0; k < kFinishPlanes; ++k)
+      pme_plane_load(st, phi, pp, q + k * kFinishLanes, pv[k]);
     terms_fetch<COUL>(t, a, pos, n, tp);
+    {
+      float gx = 0.f, gy = 0.f, gz = 0.f;
+      for (int k = 0; k < kFinishPlanes; ++k) {
+        const int t3 = q + k * kFinishLanes;
+        pme_plane_add(st, pv[k], pick4(st.th[2], t3), pick4(st.dth[2], t3), gx, gy, gz);
+      }
+      pme_force_add(p, pp, gx, gy, gz, fx, fy, fz);
+    }
     terms_apply<ENERGY, COUL, false>(t, a, pos, n, bp, tp, fx, fy, fz, e_ex, e_b, e_a,
                                      kFinishLanes, nullptr);
   }
@@ -750,8 +766,11 @@ hipError_t launch_side_terms(Ctx& c, const float* pos, bool energy, hipStream_t 
   const int nb = xcd_grid((c.max_slots * kFinishLanes + 255) / 256);
   BondedParams bp = make_bonded_params(c);
   Topology tp = make_topology(c);
+  PmeParams pp = make_pme_params(c);
   const int* perm = c.perm;
   const int* meta = c.meta;
+  const float4* xs = c.xs;
+  const float* phi = c.grid_phi;
   int n = c.n, fstride = c.max_slots, pstride = c.max_blocks;
   float* fside = c.fside;
   double* partials = c.partials;
@@ -759,7 +778,8 @@ hipError_t launch_side_terms(Ctx& c, const float* pos, bool energy, hipStream_t 
                                            : reinterpret_cast<const void*>(k_side_terms<true, false>))
                           : (c.has_coulomb ? reinterpret_cast<const void*>(k_side_terms<false, true>)
                                            : reinterpret_cast<const void*>(k_side_terms<false, false>));
-  void* args[] = {&perm, &meta, &pos, &n, &bp, &tp, &fside, &fstride, &partials, &pstride};
+  void* args[] = {&perm, &meta, &pos, &n, &bp, &tp, &xs, &phi, &pp, &fside, &fstride, &partials,
+                  &pstride};
   if (done && !c.capturing)
     return hipExtLaunchKernel(fn, dim3(nb), dim3(256), args, 0, s, nullptr, done, 0);
   hipError_t e = hipLaunchKernel(fn, dim3(nb), dim3(256), args, 0, s);
