@@ -212,49 +212,45 @@ __global__ void __launch_bounds__(256) k_begin_step(OpenStep o, const float* __r
   open_step_atom(o, in, f, v, vel, a, s);
 }
 
-// Closing half of a step, two lanes per slot: lane q of the pair takes z
-// planes q and q + 2 of the PME stencil and every second bonded / exclusion
-// term of the atom (and, with a half list, every second of the j partials
-// naming its cluster); the pair sums its parts in a fixed order, and lane 0
-// adds the
+// Closing half of a step, two lanes per slot. Without SIDE, lane q of the
+// pair takes every second bonded / exclusion term of the atom (and, with a
+// half list, every second of the j partials naming its cluster). With SIDE
+// (PME contexts) those terms and the reciprocal-space force were summed by
+// slot into fside on the second stream (k_side_terms), and the kernel reads
+// that sum. The pair sums its parts in a fixed order, and lane 0 adds the
 // pair force the pair kernel stored in the slot array (clearing it), stores
-// the total and applies v += (dt/2) a. FP64 energy
-// partials (exclusion, bond, angle, kinetic) per block. With `open`, lane 0
-// then opens the next step for its atom (open_step_atom, from the velocity
-// and force it has just computed): the same values as a separate opening
-// kernel, one launch fewer per step. The bonded terms read the positions of
-// other atoms from `pos`, so the new positions go to o.pos_out (another
-// buffer).
+// the total and applies v += (dt/2) a. FP64 energy partials (exclusion,
+// bond, angle, kinetic) per block. With `open`, lane 0 then opens the next
+// step for its atom (open_step_atom, from the velocity and force it has just
+// computed): the same values as a separate opening kernel, one launch fewer
+// per step. The bonded terms read the positions of other atoms from `pos`,
+// so the new positions go to o.pos_out (another buffer).
 //
 // The kernel is bound by the latency of its dependent loads, so every load
-// that does not need an earlier one's value is issued first: the slot's
-// position and the atom's list bounds, lane 0's kick and opening inputs, then
-// the PME plane and the first term of each kind (terms_fetch), and only then
-// the arithmetic, in the same order as a plain evaluation.
+// that does not need an earlier one's value is issued first: the atom's list
+// bounds, lane 0's kick and opening inputs, then the first term of each kind
+// (terms_fetch), and only then the arithmetic, in the same order as a plain
+// evaluation.
 constexpr int kFinishLanes = 2;
-constexpr int kFinishPlanes = 4 / kFinishLanes;   // PME z planes per lane
+constexpr int kFinishPlanes = 4 / kFinishLanes;   // PME z planes per lane (k_side_terms)
 
-template <bool ENERGY, bool COUL, bool PME, bool SIDE>
+template <bool ENERGY, bool COUL, bool SIDE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_finish_step(
-    const float4* __restrict__ xs, const int* __restrict__ perm, const int* __restrict__ meta,
-    const float* __restrict__ phi, PmeParams pp, const float* __restrict__ pos, int n,
-    BondedParams bp, Topology tp, float* __restrict__ fslot, int fstride,
+    const int* __restrict__ perm, const int* __restrict__ meta, const float* __restrict__ pos,
+    int n, BondedParams bp, Topology tp, float* __restrict__ fslot, int fstride,
     float* __restrict__ force, float* __restrict__ vel,
     const float* __restrict__ acc_over_m, const float* __restrict__ mass, float half_dt,
     double inv_2acc, double* __restrict__ partials, int pstride, float* __restrict__ vc,
     OpenStep o, int open, JParts jp, const float* __restrict__ fside) {
   __shared__ double red[16];
   if (open && blockIdx.x == 0 && threadIdx.x == 0) open_step_flags(o);
-  // neighbouring slots on one XCD: the PME potential they gather comes from
-  // one part of the grid
+  // neighbouring slots on one XCD (the same order as k_side_terms)
   const int lb = xcd_block((meta[0] * kFinishLanes + 255) / 256);
   const int gt = lb * blockDim.x + threadIdx.x;
   const int s = gt / kFinishLanes, q = gt & (kFinishLanes - 1);
   double e_ex = 0.0, e_b = 0.0, e_a = 0.0, ke = 0.0;
   const bool live = lb >= 0 && s < meta[0];
   const int a = live ? ld32(perm, (unsigned)s) : -1;
-  float4 p;
-  if (PME && !SIDE && live) p = ld32(xs, (unsigned)s);
   float fx = 0.f, fy = 0.f, fz = 0.f;
   float fs[3], sd[3], v[3], acc;
   OpenIn in;
@@ -270,25 +266,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     }
     acc = ld32(acc_over_m, (unsigned)a);
     if (open) open_fetch(o, a, s, in);
-    PmeStencil st;
-    float pv[kFinishPlanes][16];
-    if (PME && !SIDE) {
-      pme_stencil(p, pp, st);
-      for (int k = 0; k < kFinishPlanes; ++k)
-        pme_plane_load(st, phi, pp, q + k * kFinishLanes, pv[k]);
-    }
-    if (!SIDE) terms_fetch<COUL>(t, a, pos, n, tp);
-    if (PME && !SIDE) {
-      float gx = 0.f, gy = 0.f, gz = 0.f;
-      for (int k = 0; k < kFinishPlanes; ++k) {
-        const int t3 = q + k * kFinishLanes;
-        pme_plane_add(st, pv[k], pick4(st.th[2], t3), pick4(st.dth[2], t3), gx, gy, gz);
-      }
-      pme_force_add(p, pp, gx, gy, gz, fx, fy, fz);
-    }
-    if (!SIDE)
+    if (!SIDE) {
+      terms_fetch<COUL>(t, a, pos, n, tp);
       terms_apply<ENERGY, COUL, false>(t, a, pos, n, bp, tp, fx, fy, fz, e_ex, e_b, e_a,
                                        kFinishLanes, nullptr);
+    }
     if (jp.jpart) add_jparts(jp, s, q, kFinishLanes, fx, fy, fz);
   }
   // sum over the slot's lanes (they share the slot, so a is uniform among them)
@@ -353,13 +335,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   }
 }
 
-// The closing half's bonded and exclusion terms on their own. They need only
-// this step's positions, so inside mdx_integrate_step (PME contexts) they run
-// on the second stream after the reciprocal-space passes, beside the end of
-// the pair kernel, and the closing kernel adds their sum by slot instead of
-// evaluating them. Same lanes, block order and grid as the closing kernel,
-// so its energy rows (exclusion, bond, angle) line up with its kinetic row.
-template <bool ENERGY, bool COUL>
+// The closing half's forces that do not need the pair kernel: the PME force
+// interpolation and the bonded and exclusion terms, summed by slot into
+// fside. Inside mdx_integrate_step they run on the second stream after the
+// last FFT pass (the potential is complete there), beside the end of the
+// pair kernel, and the closing kernel adds the sum. Lane q of the pair takes
+// z planes q and q + 2 of the PME stencil and every second term; every load
+// that does not need an earlier one's value is issued first. Same lanes,
+// block order and grid as the closing kernel, so its energy rows (exclusion,
+// bond, angle) line up with the closing kernel's kinetic row.
+template <bool ENERGY>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_side_terms(
     const int* __restrict__ perm, const int* __restrict__ meta, const float* __restrict__ pos,
     int n, BondedParams bp, Topology tp, const float4* __restrict__ xs,
@@ -377,13 +362,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   float fx = 0.f, fy = 0.f, fz = 0.f;
   if (a >= 0) {
     AtomTerms t;
-    terms_begin<COUL>(t, a, pos, n, tp, q);
+    terms_begin<true>(t, a, pos, n, tp, q);
     PmeStencil st;
     float pv[kFinishPlanes][16];
     pme_stencil(p, pp, st);
     for (int k = 0; k < kFinishPlanes; ++k)
       pme_plane_load(st, phi, pp, q + k * kFinishLanes, pv[k]);
-    terms_fetch<COUL>(t, a, pos, n, tp);
+    terms_fetch<true>(t, a, pos, n, tp);
     {
       float gx = 0.f, gy = 0.f, gz = 0.f;
       for (int k = 0; k < kFinishPlanes; ++k) {
@@ -392,7 +377,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
       }
       pme_force_add(p, pp, gx, gy, gz, fx, fy, fz);
     }
-    terms_apply<ENERGY, COUL, false>(t, a, pos, n, bp, tp, fx, fy, fz, e_ex, e_b, e_a,
+    terms_apply<ENERGY, true, false>(t, a, pos, n, bp, tp, fx, fy, fz, e_ex, e_b, e_a,
                                      kFinishLanes, nullptr);
   }
   for (int o = 1; o < kFinishLanes; o <<= 1) {
@@ -762,7 +747,7 @@ hipError_t launch_begin_step(Ctx& c, float* pos, float* vel, const float* force,
 
 hipError_t launch_side_terms(Ctx& c, const float* pos, bool energy, hipStream_t s,
                              hipEvent_t done) {
-  if (!c.fside) return hipErrorInvalidValue;
+  if (!c.fside || !c.has_pme) return hipErrorInvalidValue;
   const int nb = xcd_grid((c.max_slots * kFinishLanes + 255) / 256);
   BondedParams bp = make_bonded_params(c);
   Topology tp = make_topology(c);
@@ -774,10 +759,8 @@ hipError_t launch_side_terms(Ctx& c, const float* pos, bool energy, hipStream_t 
   int n = c.n, fstride = c.max_slots, pstride = c.max_blocks;
   float* fside = c.fside;
   double* partials = c.partials;
-  const void* fn = energy ? (c.has_coulomb ? reinterpret_cast<const void*>(k_side_terms<true, true>)
-                                           : reinterpret_cast<const void*>(k_side_terms<true, false>))
-                          : (c.has_coulomb ? reinterpret_cast<const void*>(k_side_terms<false, true>)
-                                           : reinterpret_cast<const void*>(k_side_terms<false, false>));
+  const void* fn = energy ? reinterpret_cast<const void*>(k_side_terms<true>)
+                          : reinterpret_cast<const void*>(k_side_terms<false>);
   void* args[] = {&perm, &meta, &pos, &n, &bp, &tp, &xs, &phi, &pp, &fside, &fstride, &partials,
                   &pstride};
   if (done && !c.capturing)
@@ -788,35 +771,35 @@ hipError_t launch_side_terms(Ctx& c, const float* pos, bool energy, hipStream_t 
 }
 
 hipError_t launch_finish_step(Ctx& c, const float* pos, float* vel, float* force, float dt,
-                              bool energy, const StepGates* next, float* pos_next, bool side) {
+                              bool energy, const StepGates* next, float* pos_next) {
   if (next && (!pos_next || pos_next == pos)) return hipErrorInvalidValue;
-  if (side && (!c.fside || !c.has_pme || !c.has_coulomb)) return hipErrorInvalidValue;
+  // PME contexts: the reciprocal-space, bonded and exclusion forces come from
+  // the side kernel of the same step
+  const bool side = c.has_pme;
+  if (side && (!c.fside || !c.has_coulomb)) return hipErrorInvalidValue;
   const StepGates none{c.gate, c.gate, c.gate, c.gate, false, 0};   // not used when !next
   const OpenStep o = make_open(c, pos, pos_next, dt, next ? *next : none);
   const int open = next ? 1 : 0;
   const int nb = xcd_grid((c.max_slots * kFinishLanes + 255) / 256);
-  const PmeParams pp = c.has_pme ? make_pme_params(c) : PmeParams{};
   const BondedParams bp = make_bonded_params(c);
   const Topology tp = make_topology(c);
   const double inv_2acc = 0.5 / c.accel;
   c.finish_blocks = nb;
-#define MDX_FIN(E, C, P, S)                                                                    \
-  k_finish_step<E, C, P, S><<<nb, 256, 0, c.stream>>>(c.xs, c.perm, c.meta, c.grid_phi, pp, pos, \
-                                                       c.n, bp, tp, c.fslot, c.max_slots, force, \
-                                                       vel, c.hdt_scale, c.mass, 0.5f * dt,      \
-                                                       inv_2acc, c.partials, c.max_blocks, c.vc, \
-                                                       o, open, c.jparts(), c.fside)
-  const bool C = c.has_coulomb, P = c.has_pme;
+#define MDX_FIN(E, C, S)                                                                     \
+  k_finish_step<E, C, S><<<nb, 256, 0, c.stream>>>(c.perm, c.meta, pos, c.n, bp, tp, c.fslot, \
+                                                    c.max_slots, force, vel, c.hdt_scale,      \
+                                                    c.mass, 0.5f * dt, inv_2acc, c.partials,   \
+                                                    c.max_blocks, c.vc, o, open, c.jparts(),   \
+                                                    c.fside)
+  const bool C = c.has_coulomb;
   if (energy) {
-    if (side) MDX_FIN(true, true, true, true);
-    else if (C && P) MDX_FIN(true, true, true, false);
-    else if (C) MDX_FIN(true, true, false, false);
-    else MDX_FIN(true, false, false, false);
+    if (side) MDX_FIN(true, true, true);
+    else if (C) MDX_FIN(true, true, false);
+    else MDX_FIN(true, false, false);
   } else {
-    if (side) MDX_FIN(false, true, true, true);
-    else if (C && P) MDX_FIN(false, true, true, false);
-    else if (C) MDX_FIN(false, true, false, false);
-    else MDX_FIN(false, false, false, false);
+    if (side) MDX_FIN(false, true, true);
+    else if (C) MDX_FIN(false, true, false);
+    else MDX_FIN(false, false, false);
   }
 #undef MDX_FIN
   return hipGetLastError();

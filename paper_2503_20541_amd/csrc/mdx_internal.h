@@ -343,14 +343,17 @@ hipError_t launch_begin_step(Ctx& c, float* pos, float* vel, const float* force,
 // opens the following step (gates *next) from the closing kick's velocities
 // and forces, reading pos and writing the new positions to pos_next (another
 // buffer: the bonded terms of other atoms still read pos).
-// With `side`, the bonded and exclusion terms are not evaluated: their sum
-// by slot is read from c.fside (launch_side_terms of the same step).
+// In PME contexts the PME, bonded and exclusion forces are not evaluated
+// here: their sum by slot is read from c.fside (launch_side_terms of the
+// same step, which must precede it).
 hipError_t launch_finish_step(Ctx& c, const float* pos, float* vel, float* force, float dt,
                               bool energy, const StepGates* next = nullptr,
-                              float* pos_next = nullptr, bool side = false);
-// The closing half's bonded and exclusion terms at positions pos, summed by
-// slot into c.fside (and their energy rows of the closing kernel's partials)
-// on stream s; `done` (if given) is recorded by the kernel's own dispatch.
+                              float* pos_next = nullptr);
+// PME contexts: the closing half's PME force interpolation and bonded and
+// exclusion terms at positions pos (slot positions c.xs), summed by slot into
+// c.fside (and their energy rows of the closing kernel's partials) on stream
+// s, after the FFT passes; `done` (if given) is recorded by the kernel's own
+// dispatch.
 hipError_t launch_side_terms(Ctx& c, const float* pos, bool energy, hipStream_t s,
                              hipEvent_t done);
 // Rigid water: SHAKE after the drift (x_old: positions before it) with the

@@ -957,12 +957,12 @@ int integrate_eager(mdx_ctx* x, float* pos, float* vel, float* force, int32_t n_
     // The reciprocal-space potential only needs this step's slot positions
     // and the PME brick slot ranges: the spread and the FFT passes run on the
     // second stream, from the end of the list build on, concurrently with
-    // the pair kernel. The bonded and exclusion terms need only the
-    // positions: they follow on the second stream (side terms), beside the
-    // end of the pair kernel. The closing kernel (force interpolation, kick)
-    // waits for both. The fork and join events are recorded by the tile
-    // search's and the side kernel's own dispatches (no marker packets
-    // between kernels).
+    // the pair kernel. The PME force interpolation and the bonded and
+    // exclusion terms do not need the pair forces either: they follow on the
+    // second stream (side terms), beside the end of the pair kernel. The
+    // closing kernel (pair-force add, kick, opening half) waits for them.
+    // The fork and join events are recorded by the tile search's and the
+    // side kernel's own dispatches (no marker packets between kernels).
     if (c.has_pme) {
       MDX_TRY(hipStreamWaitEvent(x->aux, x->ev_fork, 0));
       std::pair<hipEvent_t, hipEvent_t>* tslot;
@@ -983,9 +983,8 @@ int integrate_eager(mdx_ctx* x, float* pos, float* vel, float* force, int32_t n_
                                     ps ? ps->first : nullptr, ps ? ps->second : nullptr));
     }
     if (c.has_pme) MDX_TRY(hipStreamWaitEvent(c.stream, x->ev_join, 0));
-    const bool side = c.has_pme;
     if (rigid) {
-      MDX_TRY(mdx::launch_finish_step(c, pos_cur, vel, force, dt, e, nullptr, nullptr, side));
+      MDX_TRY(mdx::launch_finish_step(c, pos_cur, vel, force, dt, e));
       MDX_TRY(mdx::launch_rigid_velocities(c, pos_cur, vel, e, &rigid_blocks));
       if (s + 1 < n_steps) {
         g = gates_of(c.steps_taken + 1);
@@ -993,11 +992,11 @@ int integrate_eager(mdx_ctx* x, float* pos, float* vel, float* force, int32_t n_
       }
     } else if (s + 1 < n_steps) {
       const mdx::StepGates next = gates_of(c.steps_taken + 1);
-      MDX_TRY(mdx::launch_finish_step(c, pos_cur, vel, force, dt, e, &next, pos_other, side));
+      MDX_TRY(mdx::launch_finish_step(c, pos_cur, vel, force, dt, e, &next, pos_other));
       std::swap(pos_cur, pos_other);
       g = next;
     } else {
-      MDX_TRY(mdx::launch_finish_step(c, pos_cur, vel, force, dt, e, nullptr, nullptr, side));
+      MDX_TRY(mdx::launch_finish_step(c, pos_cur, vel, force, dt, e));
     }
     if (e) {
       int rows[7] = {mdx::kRowLJ,    mdx::kRowDir, mdx::kRowExcl, mdx::kRowBond,
