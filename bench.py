@@ -45,7 +45,7 @@ VALU_PEAK_T = 256 * 64 * 2.4e9 / 1e12
 # (profiles/pair_kernel_counters_water96k.md); set to None when the kernel
 # changes until the counters are taken again.
 PAIR_TRAFFIC_BYTES = 61.5e6
-PAIR_TRAFFIC_COMMIT = "50ae657"     # the commit whose k_pair the counters measured
+PAIR_TRAFFIC_COMMIT = "f9aef80"     # the commit whose k_pair the counters measured
 # Whole-step floors of the 96,000-atom water step (the method's compulsory
 # work per step: 199 MB of HBM traffic -- fused integrate 6.1 MB, pair kernel
 # per-atom I/O plus a 4-byte-per-pair Verlet list 118 MB, PME 56 MB, list
