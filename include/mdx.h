@@ -324,9 +324,11 @@ int mdx_ewald_direct_noalloc_bytes(int32_t n_atoms, int32_t n_max, int64_t* byte
  * also on any step where an atom has moved more than r_g/2 since the last
  * build (tested every step on the device; no host synchronisation). The
  * number of builds is reported by mdx_get_info. Inside a step the PME spread
- * and FFT passes run on a library-owned second stream, concurrently with the
- * pair kernel; they are forked from and joined back into the context's
- * stream, so the call is ordered on that stream like any other work.
+ * and FFT passes (and, from 40,000 atoms on, the PME force gather and the
+ * bonded and exclusion terms) run on a library-owned second stream,
+ * concurrently with the pair kernel; they are forked from and joined back
+ * into the context's stream, so the call is ordered on that stream like any
+ * other work.
  * energies, if not NULL, is dev double[n_steps][MDX_N_ENERGY]: all slots
  * after each step. After mdx_set_langevin with gamma > 0 each step opens with
  * the Langevin (BAOAB) half instead (kinetic energy from the closing kick's

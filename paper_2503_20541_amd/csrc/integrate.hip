@@ -213,11 +213,12 @@ __global__ void __launch_bounds__(256) k_begin_step(OpenStep o, const float* __r
 }
 
 // Closing half of a step, two lanes per slot. Without SIDE, lane q of the
-// pair takes every second bonded / exclusion term of the atom (and, with a
-// half list, every second of the j partials naming its cluster). With SIDE
-// (PME contexts) those terms and the reciprocal-space force were summed by
-// slot into fside on the second stream (k_side_terms), and the kernel reads
-// that sum. The pair sums its parts in a fixed order, and lane 0 adds the
+// pair takes z planes q and q + 2 of the PME stencil (PME) and every second
+// bonded / exclusion term of the atom (and, with a half list, every second
+// of the j partials naming its cluster). With SIDE (PME contexts of at least
+// kSideStreamMinAtoms atoms) those terms and the reciprocal-space force were
+// summed by slot into fside on the second stream (k_side_terms), and the
+// kernel reads that sum. The pair sums its parts in a fixed order, and lane 0 adds the
 // pair force the pair kernel stored in the slot array (clearing it), stores
 // the total and applies v += (dt/2) a. FP64 energy partials (exclusion,
 // bond, angle, kinetic) per block. With `open`, lane 0 then opens the next
@@ -227,15 +228,16 @@ __global__ void __launch_bounds__(256) k_begin_step(OpenStep o, const float* __r
 // so the new positions go to o.pos_out (another buffer).
 //
 // The kernel is bound by the latency of its dependent loads, so every load
-// that does not need an earlier one's value is issued first: the atom's list
-// bounds, lane 0's kick and opening inputs, then the first term of each kind
-// (terms_fetch), and only then the arithmetic, in the same order as a plain
-// evaluation.
+// that does not need an earlier one's value is issued first: the slot's
+// position and the atom's list bounds, lane 0's kick and opening inputs, then
+// the PME planes and the first term of each kind (terms_fetch), and only
+// then the arithmetic, in the same order as a plain evaluation.
 constexpr int kFinishLanes = 2;
-constexpr int kFinishPlanes = 4 / kFinishLanes;   // PME z planes per lane (k_side_terms)
+constexpr int kFinishPlanes = 4 / kFinishLanes;   // PME z planes per lane
 
-template <bool ENERGY, bool COUL, bool SIDE>
+template <bool ENERGY, bool COUL, bool PME, bool SIDE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_finish_step(
+    const float4* __restrict__ xs, const float* __restrict__ phi, PmeParams pp,
     const int* __restrict__ perm, const int* __restrict__ meta, const float* __restrict__ pos,
     int n, BondedParams bp, Topology tp, float* __restrict__ fslot, int fstride,
     float* __restrict__ force, float* __restrict__ vel,
@@ -251,6 +253,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   double e_ex = 0.0, e_b = 0.0, e_a = 0.0, ke = 0.0;
   const bool live = lb >= 0 && s < meta[0];
   const int a = live ? ld32(perm, (unsigned)s) : -1;
+  float4 p;
+  if (PME && !SIDE && live) p = ld32(xs, (unsigned)s);
   float fx = 0.f, fy = 0.f, fz = 0.f;
   float fs[3], sd[3], v[3], acc;
   OpenIn in;
@@ -267,7 +271,22 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     acc = ld32(acc_over_m, (unsigned)a);
     if (open) open_fetch(o, a, s, in);
     if (!SIDE) {
+      PmeStencil st;
+      float pv[kFinishPlanes][16];
+      if (PME) {
+        pme_stencil(p, pp, st);
+        for (int k = 0; k < kFinishPlanes; ++k)
+          pme_plane_load(st, phi, pp, q + k * kFinishLanes, pv[k]);
+      }
       terms_fetch<COUL>(t, a, pos, n, tp);
+      if (PME) {
+        float gx = 0.f, gy = 0.f, gz = 0.f;
+        for (int k = 0; k < kFinishPlanes; ++k) {
+          const int t3 = q + k * kFinishLanes;
+          pme_plane_add(st, pv[k], pick4(st.th[2], t3), pick4(st.dth[2], t3), gx, gy, gz);
+        }
+        pme_force_add(p, pp, gx, gy, gz, fx, fy, fz);
+      }
       terms_apply<ENERGY, COUL, false>(t, a, pos, n, bp, tp, fx, fy, fz, e_ex, e_b, e_a,
                                        kFinishLanes, nullptr);
     }
@@ -747,7 +766,7 @@ hipError_t launch_begin_step(Ctx& c, float* pos, float* vel, const float* force,
 
 hipError_t launch_side_terms(Ctx& c, const float* pos, bool energy, hipStream_t s,
                              hipEvent_t done) {
-  if (!c.fside || !c.has_pme) return hipErrorInvalidValue;
+  if (!c.fside || !side_terms_used(c)) return hipErrorInvalidValue;
   const int nb = xcd_grid((c.max_slots * kFinishLanes + 255) / 256);
   BondedParams bp = make_bonded_params(c);
   Topology tp = make_topology(c);
@@ -773,9 +792,9 @@ hipError_t launch_side_terms(Ctx& c, const float* pos, bool energy, hipStream_t 
 hipError_t launch_finish_step(Ctx& c, const float* pos, float* vel, float* force, float dt,
                               bool energy, const StepGates* next, float* pos_next) {
   if (next && (!pos_next || pos_next == pos)) return hipErrorInvalidValue;
-  // PME contexts: the reciprocal-space, bonded and exclusion forces come from
-  // the side kernel of the same step
-  const bool side = c.has_pme;
+  // PME contexts from kSideStreamMinAtoms atoms on: the reciprocal-space,
+  // bonded and exclusion forces come from the side kernel of the same step
+  const bool side = side_terms_used(c);
   if (side && (!c.fside || !c.has_coulomb)) return hipErrorInvalidValue;
   const StepGates none{c.gate, c.gate, c.gate, c.gate, false, 0};   // not used when !next
   const OpenStep o = make_open(c, pos, pos_next, dt, next ? *next : none);
@@ -785,21 +804,24 @@ hipError_t launch_finish_step(Ctx& c, const float* pos, float* vel, float* force
   const Topology tp = make_topology(c);
   const double inv_2acc = 0.5 / c.accel;
   c.finish_blocks = nb;
-#define MDX_FIN(E, C, S)                                                                     \
-  k_finish_step<E, C, S><<<nb, 256, 0, c.stream>>>(c.perm, c.meta, pos, c.n, bp, tp, c.fslot, \
-                                                    c.max_slots, force, vel, c.hdt_scale,      \
-                                                    c.mass, 0.5f * dt, inv_2acc, c.partials,   \
-                                                    c.max_blocks, c.vc, o, open, c.jparts(),   \
-                                                    c.fside)
-  const bool C = c.has_coulomb;
+  const PmeParams pp = c.has_pme ? make_pme_params(c) : PmeParams{};
+#define MDX_FIN(E, C, P, S)                                                                    \
+  k_finish_step<E, C, P, S><<<nb, 256, 0, c.stream>>>(c.xs, c.grid_phi, pp, c.perm, c.meta, pos, \
+                                                       c.n, bp, tp, c.fslot, c.max_slots, force, \
+                                                       vel, c.hdt_scale, c.mass, 0.5f * dt,      \
+                                                       inv_2acc, c.partials, c.max_blocks, c.vc, \
+                                                       o, open, c.jparts(), c.fside)
+  const bool C = c.has_coulomb, P = c.has_pme;
   if (energy) {
-    if (side) MDX_FIN(true, true, true);
-    else if (C) MDX_FIN(true, true, false);
-    else MDX_FIN(true, false, false);
+    if (side) MDX_FIN(true, true, true, true);
+    else if (C && P) MDX_FIN(true, true, true, false);
+    else if (C) MDX_FIN(true, true, false, false);
+    else MDX_FIN(true, false, false, false);
   } else {
-    if (side) MDX_FIN(false, true, true);
-    else if (C) MDX_FIN(false, true, false);
-    else MDX_FIN(false, false, false);
+    if (side) MDX_FIN(false, true, true, true);
+    else if (C && P) MDX_FIN(false, true, true, false);
+    else if (C) MDX_FIN(false, true, false, false);
+    else MDX_FIN(false, false, false, false);
   }
 #undef MDX_FIN
   return hipGetLastError();

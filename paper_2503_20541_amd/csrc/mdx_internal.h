@@ -32,6 +32,11 @@ __device__ __forceinline__ int xcd_block(int nwork) {
 // Atoms per context: kernels address per-atom arrays ([3][n] floats at most)
 // and the slot arrays by 32-bit byte offsets (ld32).
 constexpr int kMaxAtoms = 100000000;
+// Atoms from which mdx_integrate_step evaluates the PME force gather and the
+// bonded and exclusion terms in a side kernel on the second stream, beside
+// the pair kernel; in smaller systems the second stream is the longer one
+// already, and the closing kernel evaluates them.
+constexpr int kSideStreamMinAtoms = 40000;
 constexpr int kMaxLjTypes = 32;   // LJ atom types (the pair kernel keeps the type-pair table in LDS)
 // PME spreading bricks: kBrickXY x kBrickXY x kBrickZ grid points (smaller
 // along a dimension with fewer grid points)
@@ -343,13 +348,16 @@ hipError_t launch_begin_step(Ctx& c, float* pos, float* vel, const float* force,
 // opens the following step (gates *next) from the closing kick's velocities
 // and forces, reading pos and writing the new positions to pos_next (another
 // buffer: the bonded terms of other atoms still read pos).
-// In PME contexts the PME, bonded and exclusion forces are not evaluated
-// here: their sum by slot is read from c.fside (launch_side_terms of the
-// same step, which must precede it).
+// Whether the closing half's PME, bonded and exclusion forces come from the
+// side kernel (PME contexts of at least kSideStreamMinAtoms atoms).
+inline bool side_terms_used(const Ctx& c) { return c.has_pme && c.n >= kSideStreamMinAtoms; }
+// When side_terms_used, the PME, bonded and exclusion forces are not
+// evaluated here: their sum by slot is read from c.fside (launch_side_terms
+// of the same step, which must precede it).
 hipError_t launch_finish_step(Ctx& c, const float* pos, float* vel, float* force, float dt,
                               bool energy, const StepGates* next = nullptr,
                               float* pos_next = nullptr);
-// PME contexts: the closing half's PME force interpolation and bonded and
+// side_terms_used contexts: the closing half's PME force interpolation and bonded and
 // exclusion terms at positions pos (slot positions c.xs), summed by slot into
 // c.fside (and their energy rows of the closing kernel's partials) on stream
 // s, after the FFT passes; `done` (if given) is recorded by the kernel's own

@@ -539,7 +539,8 @@ int create_impl(mdx_ctx* x, const mdx_system_desc* d) {
   if ((rc = dev_alloc(x, &c.zbin, (size_t)ncol * (g.nzb + 1))) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.fslot, (size_t)3 * c.max_slots)) != MDX_OK) return rc;
   MDX_TRY(hipMemset(c.fslot, 0, sizeof(float) * 3 * c.max_slots));
-  if (c.has_pme && (rc = dev_alloc(x, &c.fside, (size_t)3 * c.max_slots)) != MDX_OK) return rc;
+  if (mdx::side_terms_used(c) && (rc = dev_alloc(x, &c.fside, (size_t)3 * c.max_slots)) != MDX_OK)
+    return rc;
   if ((rc = dev_alloc(x, &c.ts, c.max_slots)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.zb, c.max_slots)) != MDX_OK) return rc;
   if ((rc = dev_alloc(x, &c.box_lo, c.max_clusters)) != MDX_OK) return rc;
@@ -963,16 +964,21 @@ int integrate_eager(mdx_ctx* x, float* pos, float* vel, float* force, int32_t n_
     // closing kernel (pair-force add, kick, opening half) waits for them.
     // The fork and join events are recorded by the tile search's and the
     // side kernel's own dispatches (no marker packets between kernels).
+    // (Below kSideStreamMinAtoms the second stream is the longer one already,
+    // and the closing kernel evaluates those terms.)
     if (c.has_pme) {
+      const bool side = mdx::side_terms_used(c);
       MDX_TRY(hipStreamWaitEvent(x->aux, x->ev_fork, 0));
       std::pair<hipEvent_t, hipEvent_t>* tslot;
       MDX_TRY(timing_begin(x, MDX_TIMING_PME, x->aux, &tslot));
       MDX_TRY(mdx::launch_pme_spread(c, x->aux, nullptr));
-      MDX_TRY(mdx::launch_pme_fft(c, x->aux, nullptr));
+      // the join event is recorded by the last kernel's dispatch, or (timing
+      // of the FFT passes, graph capture) explicitly after it
+      const bool by_dispatch = !tslot && !c.capturing;
+      MDX_TRY(mdx::launch_pme_fft(c, x->aux, by_dispatch && !side ? x->ev_join : nullptr));
       MDX_TRY(timing_end(tslot, x->aux));
-      // the join event is recorded by the side kernel's dispatch, or (graph
-      // capture) explicitly after it
-      MDX_TRY(mdx::launch_side_terms(c, pos_cur, e, x->aux, x->ev_join));
+      if (side) MDX_TRY(mdx::launch_side_terms(c, pos_cur, e, x->aux, x->ev_join));
+      else if (!by_dispatch) MDX_TRY(hipEventRecord(x->ev_join, x->aux));
     }
     {
       // timed by events that the pair kernel's dispatch records (marker

@@ -297,3 +297,32 @@ def test_pme_virial_parity(name):
     scale = np.abs(np.diag(ref["W"])).max()
     assert np.abs(Wg - ref["W"]).max() <= W_TOL * scale, (Wg, ref["W"])
     assert np.array_equal(Wg, Wg.T)
+
+
+@pytest.mark.parametrize("n_mol", [12000, 14000], ids=["closing-kernel", "side-kernel"])
+def test_pme_step_force_matches_fresh_evaluation(n_mol):
+    # Water with PME on either side of the 40,000 atoms from which the PME
+    # force gather and the bonded and exclusion terms run as a side kernel on
+    # the second stream (below it the closing kernel evaluates them). After
+    # steps that include a list rebuild, the force the step leaves equals a
+    # fresh evaluation by the stand-alone kernels at the same positions.
+    import torch
+    L = (n_mol * 29.91) ** (1.0 / 3.0)
+    s = synth.water_box(n_mol, L, (75, 75, 75) if n_mol > 12000 else (72, 72, 72), 9.0, None,
+                        5e-4, 11, n_steps=100, name=f"water{3 * n_mol}")
+    announce(f"PME step against a fresh evaluation: water N={s.n_atoms}")
+    with gpu_context(s) as (mdx, ctx, t):
+        mdx.build_neighbors(ctx, t["pos"])
+        mdx.compute_nonbonded(ctx, t["pos"], t["force"])
+        mdx.compute_pme(ctx, t["pos"], t["force"])
+        mdx.integrate_step(ctx, t["pos"], t["vel"], t["force"], 12, float(s.dt))
+        torch.cuda.synchronize()
+        F_step = t["force"].cpu().numpy().astype(np.float64)
+        f2 = torch.zeros_like(t["force"])
+        mdx.compute_nonbonded(ctx, t["pos"], f2)
+        mdx.compute_pme(ctx, t["pos"], f2)
+        torch.cuda.synchronize()
+        F_fresh = f2.cpu().numpy().astype(np.float64)
+        assert mdx.get_status(ctx) == 0
+        assert mdx.get_info(ctx).n_builds >= 2
+    assert rel_rms(F_step, F_fresh) < 1e-6
