@@ -213,15 +213,16 @@ __global__ void __launch_bounds__(256) k_begin_step(OpenStep o, const float* __r
 }
 
 // Closing half of a step, two lanes per slot. Without SIDE, lane q of the
-// pair takes z planes q and q + 2 of the PME stencil (PME) and every second
-// bonded / exclusion term of the atom (and, with a half list, every second
-// of the j partials naming its cluster). With SIDE (PME contexts of at least
-// kSideStreamMinAtoms atoms) those terms and the reciprocal-space force were
-// summed by slot into fside on the second stream (k_side_terms), and the
-// kernel reads that sum. The pair sums its parts in a fixed order, and lane 0 adds the
-// pair force the pair kernel stored in the slot array (clearing it), stores
-// the total and applies v += (dt/2) a. FP64 energy partials (exclusion,
-// bond, angle, kinetic) per block. With `open`, lane 0 then opens the next
+// pair takes z planes q and q + 2 of the PME stencil (with PME) and every
+// second bonded / exclusion term of the atom; with a half list it also takes
+// every second of the j partials naming its cluster. With SIDE (PME
+// contexts of at least kSideStreamMinAtoms atoms) the reciprocal-space force
+// and those terms were summed by slot into fside on the second stream
+// (k_side_terms), and the kernel reads that sum. The pair of lanes sums its
+// parts in a fixed order, and lane 0 adds the pair force the pair kernel
+// stored in the slot array (clearing it), stores the total and applies
+// v += (dt/2) a. FP64 energy partials (exclusion, bond, angle, kinetic) per
+// block. With `open`, lane 0 then opens the next
 // step for its atom (open_step_atom, from the velocity and force it has just
 // computed): the same values as a separate opening kernel, one launch fewer
 // per step. The bonded terms read the positions of other atoms from `pos`,
@@ -246,7 +247,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     OpenStep o, int open, JParts jp, const float* __restrict__ fside) {
   __shared__ double red[16];
   if (open && blockIdx.x == 0 && threadIdx.x == 0) open_step_flags(o);
-  // neighbouring slots on one XCD (the same order as k_side_terms)
+  // neighbouring slots on one XCD (the same order as k_side_terms): the PME
+  // potential they gather comes from one part of the grid
   const int lb = xcd_block((meta[0] * kFinishLanes + 255) / 256);
   const int gt = lb * blockDim.x + threadIdx.x;
   const int s = gt / kFinishLanes, q = gt & (kFinishLanes - 1);
